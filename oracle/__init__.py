@@ -1,0 +1,247 @@
+"""FP64 CPU oracle for the narrow-band semi-Lagrangian level-set method of
+Preda & Semplice (arXiv:2410.22205).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library: the arithmetic lives in ``lsr_oracle.c`` (plain C,
+double precision, one node at a time) and is reached through ctypes; the exact
+distance field for large grids uses SciPy's k-d tree nearest-neighbour query
+(a library primitive) and is pinned against brute force in the tests.
+
+Every function takes plain NumPy arrays.  Grids are dicts
+``{"dim": 2|3, "n": (n0, n1[, n2]), "lo": (..), "h": h}`` and parameters are
+dicts with the keys of :data:`PARAM_KEYS` (see :func:`default_params`).
+Nodal arrays are C-ordered with shape ``n`` (axis 0 <-> x).
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
+                ("lo", ctypes.c_double * 3), ("h", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double), ("delta", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
+                ("grad_C", ctypes.c_double), ("grad_alpha", ctypes.c_double),
+                ("energy", ctypes.c_double),
+                ("reinit_every", ctypes.c_int32), ("reinit_iters", ctypes.c_int32),
+                ("reinit_dtau", ctypes.c_double), ("interface_floor", ctypes.c_double)]
+
+
+PARAM_KEYS = [f[0] for f in _Params._fields_]
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+_GP = ctypes.POINTER(_Grid)
+_PP = ctypes.POINTER(_Params)
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        sig = {
+            "orc_cutoff": (ctypes.c_double, [ctypes.c_double] * 3),
+            "orc_weno1d": (ctypes.c_double, [_D, ctypes.c_double, ctypes.c_double, _D]),
+            "orc_interp": (ctypes.c_double, [_D, _GP, ctypes.c_int, _D]),
+            "orc_gradient": (None, [_D, _GP, ctypes.c_int64, _D]),
+            "orc_sl_nodes": (None, [_D, _D, _GP, _PP, ctypes.c_double, ctypes.c_int, _I64,
+                                    ctypes.c_int64, _D, _I32]),
+            "orc_step": (None, [_D, _D, _GP, _PP, ctypes.c_double, ctypes.c_int, _D, _U8, _I64]),
+            "orc_reinit": (None, [_D, _U8, _GP, _PP, _I64]),
+            "orc_run": (None, [_D, _D, _GP, _PP, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                               ctypes.c_int32, _I64]),
+            "orc_init_phi": (None, [_D, _GP, ctypes.c_int, _D, ctypes.c_double]),
+            "orc_distance_brute": (None, [_D, ctypes.c_int64, _GP, _D]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a, t=_D):
+    return a.ctypes.data_as(t)
+
+
+def _grid(grid):
+    g = _Grid()
+    g.dim = int(grid["dim"])
+    n = list(grid["n"]) + [1] * (3 - len(grid["n"]))
+    lo = list(grid["lo"]) + [0.0] * (3 - len(grid["lo"]))
+    for a in range(3):
+        g.n[a] = int(n[a])
+        g.lo[a] = float(lo[a])
+    g.h = float(grid["h"])
+    return g
+
+
+def _params(prm):
+    p = _Params()
+    for k in PARAM_KEYS:
+        setattr(p, k, prm[k])
+    return p
+
+
+def shape(grid):
+    return tuple(int(v) for v in grid["n"][: grid["dim"]])
+
+
+def default_params(dim, h, **over):
+    """The paper's parameter values (Sections 3.1, 3.7, 3.8) plus the stated
+    readings: p = delta = 1, gamma = 4h / 6h and beta = 2h / 3h in 2D / 3D,
+    C = 1e-3, alpha = 1, pseudo-time step h/2 and ceil((gamma + h)/dtau)
+    iterations, reinitialisation after every step in 2D and every 10th in 3D."""
+    gamma = (4.0 if dim == 2 else 6.0) * h
+    prm = dict(p=1.0, delta=1.0, gamma=gamma, beta=gamma / 2.0, grad_C=1e-3, grad_alpha=1.0,
+               energy=1.0, reinit_every=1 if dim == 2 else 10, reinit_iters=0,
+               reinit_dtau=0.5 * h, interface_floor=1e-3)
+    prm.update(over)
+    if "reinit_iters" not in over:
+        prm["reinit_iters"] = int(math.ceil((prm["gamma"] + h) / prm["reinit_dtau"] - 1e-9))
+    return prm
+
+
+def cutoff(phi, beta, gamma):
+    return _lib().orc_cutoff(float(phi), float(beta), float(gamma))
+
+
+def weno1d(v, s, dx, parts=False):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(8)
+    r = _lib().orc_weno1d(_ptr(v), float(s), float(dx), _ptr(out))
+    if parts:
+        keys = ["PL", "PR", "CL", "CR", "IL", "IR", "wL", "wR"]
+        return r, dict(zip(keys, out.tolist()))
+    return r
+
+
+def interp(f, grid, x, kind):
+    """Interpolate nodal field f at the points x (m x dim); kind 'q1'|'weno'."""
+    lib = _lib()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = _grid(grid)
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    k = 0 if kind == "q1" else 1
+    out = np.empty(len(x))
+    for m in range(len(x)):
+        pt = np.zeros(3)
+        pt[: grid["dim"]] = x[m]
+        out[m] = lib.orc_interp(_ptr(f), ctypes.byref(g), k, _ptr(pt))
+    return out
+
+
+def gradient(f, grid, idx):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(3)
+    _lib().orc_gradient(_ptr(f), ctypes.byref(_grid(grid)), int(idx), _ptr(out))
+    return out[: grid["dim"]]
+
+
+def sl_nodes(phi, d, grid, prm, dt, kind, idx):
+    """Updated values (with the cut) at the flat node indices idx, no band test.
+    Returns (values, flags) with flag bit 1 = fallback, 2 = frame regularised."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(len(idx))
+    flags = np.empty(len(idx), dtype=np.int32)
+    _lib().orc_sl_nodes(_ptr(phi), _ptr(d), ctypes.byref(_grid(grid)), ctypes.byref(_params(prm)),
+                        float(dt), 0 if kind == "q1" else 1, _ptr(idx, _I64), len(idx), _ptr(out),
+                        _ptr(flags, _I32))
+    return out, flags
+
+
+def step(phi, d, grid, prm, dt, kind):
+    """One time step on the whole grid.  Returns (phi_new, band_mask, counts)
+    with counts = [band size, fallbacks, frame regularisations]."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.empty_like(phi)
+    band = np.empty(phi.shape, dtype=np.uint8)
+    counts = np.zeros(3, dtype=np.int64)
+    _lib().orc_step(_ptr(phi), _ptr(d), ctypes.byref(_grid(grid)), ctypes.byref(_params(prm)),
+                    float(dt), 0 if kind == "q1" else 1, _ptr(out), _ptr(band, _U8),
+                    _ptr(counts, _I64))
+    return out, band, counts
+
+
+def reinit(phi, band, grid, prm):
+    """Reinitialisation on the band plus its neighbours.  Returns
+    (phi_new, [|Gbar|, |I|])."""
+    phi = np.array(phi, dtype=np.float64, order="C", copy=True)
+    band = np.ascontiguousarray(band, dtype=np.uint8)
+    counts = np.zeros(2, dtype=np.int64)
+    _lib().orc_reinit(_ptr(phi), _ptr(band, _U8), ctypes.byref(_grid(grid)),
+                      ctypes.byref(_params(prm)), _ptr(counts, _I64))
+    return phi, counts
+
+
+def run(phi0, d, grid, prm, dt, kind, n_steps, step0=0):
+    """n_steps of Algorithm 1's loop (energy omitted, p = 1).  Returns
+    (phi, counts) with counts = [node updates, fallbacks, frame
+    regularisations, reinitialisations, sum |Gbar|, sum |I|]."""
+    phi = np.array(phi0, dtype=np.float64, order="C", copy=True)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    counts = np.zeros(6, dtype=np.int64)
+    _lib().orc_run(_ptr(phi), _ptr(d), ctypes.byref(_grid(grid)), ctypes.byref(_params(prm)),
+                   float(dt), 0 if kind == "q1" else 1, int(step0), int(n_steps),
+                   _ptr(counts, _I64))
+    return phi, counts
+
+
+def band_mask(phi, prm):
+    """Narrow band of eq. (subgrid), read as |phi| < gamma."""
+    return (np.abs(phi) < prm["gamma"]).astype(np.uint8)
+
+
+def init_phi(grid, kind, args, gamma):
+    """Closed-form SDF (kind 'sphere' or 'torus') cut to [-gamma, gamma]."""
+    phi = np.empty(shape(grid), dtype=np.float64)
+    a = np.zeros(8)
+    a[: len(args)] = args
+    _lib().orc_init_phi(_ptr(phi), ctypes.byref(_grid(grid)), 1 if kind == "sphere" else 2,
+                        _ptr(a), float(gamma))
+    return phi
+
+
+def node_coords(grid):
+    axes = [grid["lo"][a] + grid["h"] * np.arange(grid["n"][a]) for a in range(grid["dim"])]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return np.stack([m.ravel() for m in mesh], axis=1)
+
+
+def distance_brute(points, grid):
+    """d(x) = min_Q |x - Q| at every node by brute force (Section 2)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    d = np.empty(shape(grid), dtype=np.float64)
+    _lib().orc_distance_brute(_ptr(pts), len(pts), ctypes.byref(_grid(grid)), _ptr(d))
+    return d
+
+
+def distance(points, grid, x=None):
+    """Exact distance to the cloud at every node (or at the points x), through
+    SciPy's exact k-d tree nearest-neighbour query."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.asarray(points, dtype=np.float64))
+    if x is None:
+        dd, _ = tree.query(node_coords(grid), k=1, workers=-1)
+        return dd.reshape(shape(grid))
+    dd, _ = tree.query(np.asarray(x, dtype=np.float64), k=1, workers=-1)
+    return dd

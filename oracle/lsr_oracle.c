@@ -1,0 +1,533 @@
+/*
+ * FP64 CPU oracle for the narrow-band semi-Lagrangian level-set method of
+ * S. Preda and M. Semplice, "Surface reconstruction from point cloud using a
+ * semi-Lagrangian scheme with local interpolator" (arXiv:2410.22205).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU path is checked against.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header or
+ * constant with the HIP library: every formula below is written out from the
+ * paper's text, in double precision, one grid node at a time.
+ *
+ * Conventions (shared with the paper, Section 3):
+ *   - uniform Cartesian grid, node (i,j[,k]) at x = lo + (i,j[,k]) * h,
+ *     h the mesh width (the paper's Delta x);
+ *   - storage in C order: 2D index i*n1 + j, 3D index (i*n1 + j)*n2 + k,
+ *     axis 0 <-> x, axis 1 <-> y, axis 2 <-> z;
+ *   - "centred finite differences" (Section 3, before 3.1) for every
+ *     gradient, with first-order one-sided differences on the domain
+ *     boundary (the paper is silent there).
+ *
+ * The OpenMP pragmas only split independent per-node loops (every update in
+ * one time step reads the previous step only); they change no arithmetic.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  int32_t dim;    /* 2 or 3 */
+  int32_t n[3];   /* nodes per axis (n[2] ignored in 2D) */
+  double lo[3];   /* coordinates of node 0 */
+  double h;       /* mesh width */
+} orc_grid;
+
+typedef struct {
+  double p;            /* exponent of the energy, Section 2 (only p = 1 used) */
+  double delta;        /* weight of the curvature term, eq. (levelset:pde) */
+  double gamma;        /* narrow-band half width, eq. (subgrid) */
+  double beta;         /* inner radius of the cut-off, eq. (cutoff) */
+  double grad_C;       /* C of the degenerate-gradient test, Section 3.1 */
+  double grad_alpha;   /* alpha of the same test */
+  double energy;       /* E_p(phi^n) in C^n_j; unused when p == 1 */
+  int32_t reinit_every;  /* reinitialise after every K-th step */
+  int32_t reinit_iters;  /* forward-Euler pseudo-time iterations */
+  double reinit_dtau;    /* pseudo-time step */
+  double interface_floor;/* lower bound of |grad| in the interface fix */
+} orc_params;
+
+/* ------------------------------------------------------------------ grid */
+
+static int64_t orc_nodes(const orc_grid* g) {
+  int64_t t = (int64_t)g->n[0] * g->n[1];
+  return g->dim == 3 ? t * g->n[2] : t;
+}
+
+static int64_t orc_index(const orc_grid* g, const int c[3]) {
+  if (g->dim == 3) return ((int64_t)c[0] * g->n[1] + c[1]) * g->n[2] + c[2];
+  return (int64_t)c[0] * g->n[1] + c[1];
+}
+
+static void orc_coords(const orc_grid* g, int64_t idx, int c[3]) {
+  if (g->dim == 3) {
+    c[2] = (int)(idx % g->n[2]);
+    idx /= g->n[2];
+  } else {
+    c[2] = 0;
+  }
+  c[1] = (int)(idx % g->n[1]);
+  c[0] = (int)(idx / g->n[1]);
+}
+
+/* One component of the centred gradient of the nodal field f at node c. */
+static double orc_diff(const double* f, const orc_grid* g, const int c[3], int a) {
+  int cm[3] = {c[0], c[1], c[2]}, cp[3] = {c[0], c[1], c[2]};
+  int has_m = c[a] > 0, has_p = c[a] < g->n[a] - 1;
+  cm[a] -= 1;
+  cp[a] += 1;
+  if (has_m && has_p) return (f[orc_index(g, cp)] - f[orc_index(g, cm)]) / (2.0 * g->h);
+  if (has_p) return (f[orc_index(g, cp)] - f[orc_index(g, c)]) / g->h;
+  if (has_m) return (f[orc_index(g, c)] - f[orc_index(g, cm)]) / g->h;
+  return 0.0;
+}
+
+void orc_gradient(const double* f, const orc_grid* g, int64_t idx, double* out) {
+  int c[3];
+  orc_coords(g, idx, c);
+  for (int a = 0; a < 3; ++a) out[a] = a < g->dim ? orc_diff(f, g, c, a) : 0.0;
+}
+
+/* ---------------------------------------------------- cut-off, eq. (cutoff) */
+
+double orc_cutoff(double phi, double beta, double gamma) {
+  double a = fabs(phi);
+  if (a <= beta) return 1.0;
+  if (a <= gamma) {
+    double gb = gamma - beta;
+    return (a - gamma) * (a - gamma) * (2.0 * a + gamma - 3.0 * beta) / (gb * gb * gb);
+  }
+  return 0.0;
+}
+
+/* ------------------------------------------------------------ interpolation */
+
+/* Cell that contains coordinate x along axis a and the local coordinate
+ * theta = (x - x_i)/h in [0,1].  Points outside the grid are moved onto its
+ * boundary (the paper is silent; the grid is meant to contain every foot). */
+static void orc_locate(const orc_grid* g, int a, double x, int* i0, double* theta) {
+  double u = (x - g->lo[a]) / g->h;
+  double umax = (double)(g->n[a] - 1);
+  if (u < 0.0) u = 0.0;
+  if (u > umax) u = umax;
+  int i = (int)floor(u);
+  if (i > g->n[a] - 2) i = g->n[a] - 2;
+  *i0 = i;
+  *theta = u - (double)i;
+}
+
+/* Multilinear (Q1) interpolation, eq. (IQ1): the tensor-product degree-1
+ * shape functions of the cell containing x, 2^dim terms. */
+double orc_interp_q1(const double* f, const orc_grid* g, const double* x) {
+  int i0[3] = {0, 0, 0};
+  double t[3] = {0, 0, 0};
+  for (int a = 0; a < g->dim; ++a) orc_locate(g, a, x[a], &i0[a], &t[a]);
+  double sum = 0.0;
+  int corners = 1 << g->dim;
+  for (int m = 0; m < corners; ++m) {
+    int c[3] = {i0[0], i0[1], i0[2]};
+    double w = 1.0;
+    for (int a = 0; a < g->dim; ++a) {
+      int b = (m >> a) & 1;
+      c[a] += b;
+      w *= b ? t[a] : (1.0 - t[a]);
+    }
+    sum += w * f[orc_index(g, c)];
+  }
+  return sum;
+}
+
+/* One-dimensional third-order WENO interpolation on the cell [x_j, x_{j+1}]
+ * (Section 3.2, n = 2).  v = (v_{j-1}, v_j, v_{j+1}, v_{j+2}), s = (x-x_j)/dx.
+ *   P_L interpolates v on {x_{j-1}, x_j, x_{j+1}}, P_R on {x_j, x_{j+1}, x_{j+2}};
+ *   C_L(x) = (x_{j+2}-x)/(3dx), C_R(x) = (x-x_{j-1})/(3dx)  (eq. ckgamma);
+ *   I[P] = (1/dx^2) 4 a_2^2 with a_2 the coefficient of s^2 (eq. ind:1d);
+ *   alpha_k = C_k/(I_k + eps)^2, eps = dx^2;  w_k = alpha_k / sum alpha;
+ *   result = sum w_k P_k  (eq. IWENO).
+ * parts (if not NULL) receives P_L, P_R, C_L, C_R, I_L, I_R, w_L, w_R. */
+double orc_weno1d(const double* v, double s, double dx, double* parts) {
+  double PL = v[0] * s * (s - 1.0) / 2.0 + v[1] * (1.0 - s) * (1.0 + s) + v[2] * s * (s + 1.0) / 2.0;
+  double PR = v[1] * (s - 1.0) * (s - 2.0) / 2.0 + v[2] * s * (2.0 - s) + v[3] * s * (s - 1.0) / 2.0;
+  double CL = (2.0 - s) / 3.0;
+  double CR = (1.0 + s) / 3.0;
+  double a2L = (v[0] - 2.0 * v[1] + v[2]) / 2.0;
+  double a2R = (v[1] - 2.0 * v[2] + v[3]) / 2.0;
+  double IL = 4.0 * a2L * a2L / (dx * dx);
+  double IR = 4.0 * a2R * a2R / (dx * dx);
+  double eps = dx * dx;
+  double alL = CL / ((IL + eps) * (IL + eps));
+  double alR = CR / ((IR + eps) * (IR + eps));
+  double wL = alL / (alL + alR);
+  double wR = alR / (alL + alR);
+  if (parts) {
+    parts[0] = PL; parts[1] = PR; parts[2] = CL; parts[3] = CR;
+    parts[4] = IL; parts[5] = IR; parts[6] = wL; parts[7] = wR;
+  }
+  return wL * PL + wR * PR;
+}
+
+static int orc_clampi(int i, int n) { return i < 0 ? 0 : (i > n - 1 ? n - 1 : i); }
+
+/* Tensor WENO interpolation (Section 3.2, last paragraphs): one-dimensional
+ * WENO along the last axis first, then the previous one, then x.  Stencil
+ * indices outside the grid repeat the boundary node. */
+double orc_interp_weno(const double* f, const orc_grid* g, const double* x) {
+  int i0[3] = {0, 0, 0};
+  double t[3] = {0, 0, 0};
+  for (int a = 0; a < g->dim; ++a) orc_locate(g, a, x[a], &i0[a], &t[a]);
+  double h = g->h;
+  if (g->dim == 2) {
+    double wy[4];
+    for (int a = 0; a < 4; ++a) {
+      double v[4];
+      int c[3] = {orc_clampi(i0[0] - 1 + a, g->n[0]), 0, 0};
+      for (int b = 0; b < 4; ++b) {
+        c[1] = orc_clampi(i0[1] - 1 + b, g->n[1]);
+        v[b] = f[orc_index(g, c)];
+      }
+      wy[a] = orc_weno1d(v, t[1], h, NULL);
+    }
+    return orc_weno1d(wy, t[0], h, NULL);
+  }
+  double wx[4];
+  for (int a = 0; a < 4; ++a) {
+    double wy[4];
+    for (int b = 0; b < 4; ++b) {
+      double v[4];
+      int c[3] = {orc_clampi(i0[0] - 1 + a, g->n[0]), orc_clampi(i0[1] - 1 + b, g->n[1]), 0};
+      for (int e = 0; e < 4; ++e) {
+        c[2] = orc_clampi(i0[2] - 1 + e, g->n[2]);
+        v[e] = f[orc_index(g, c)];
+      }
+      wy[b] = orc_weno1d(v, t[2], h, NULL);
+    }
+    wx[a] = orc_weno1d(wy, t[1], h, NULL);
+  }
+  return orc_weno1d(wx, t[0], h, NULL);
+}
+
+double orc_interp(const double* f, const orc_grid* g, int kind, const double* x) {
+  return kind == 0 ? orc_interp_q1(f, g, x) : orc_interp_weno(f, g, x);
+}
+
+/* ------------------------------------------------ semi-Lagrangian update */
+
+/* Flags reported by orc_sl_node. */
+#define ORC_FALLBACK 1   /* |grad phi| below C dt^alpha, eq. (SL:2) used */
+#define ORC_FRAME0   2   /* 3D tangent frame regularised to (e1, e3) */
+
+/* New value at band node idx, eqs. (SL2d)/(SL3d) with the cut-off factor of
+ * Section 3.8 folded into C^n_j, followed by the cut of eq. (cut).
+ * kind 0 = Q1, 1 = WENO. */
+int orc_sl_node(const double* phi, const double* d, const orc_grid* g, const orc_params* P,
+                double dt, int kind, int64_t idx, double* out) {
+  int c[3];
+  orc_coords(g, idx, c);
+  double xj[3] = {0, 0, 0};
+  for (int a = 0; a < g->dim; ++a) xj[a] = g->lo[a] + c[a] * g->h;
+  double gp[3], gd[3];
+  orc_gradient(phi, g, idx, gp);
+  orc_gradient(d, g, idx, gd);
+  double norm = sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]);
+  int flags = 0;
+  double val;
+  if (norm < P->grad_C * pow(dt, P->grad_alpha)) {
+    /* eq. (SL:2): mean of the interpolant over the first (face) neighbours,
+     * which are grid nodes, so the interpolant returns the nodal values. */
+    double sum = 0.0;
+    int cnt = 0;
+    for (int a = 0; a < g->dim; ++a) {
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        int cn[3] = {c[0], c[1], c[2]};
+        cn[a] += sgn;
+        if (cn[a] < 0 || cn[a] > g->n[a] - 1) continue;
+        sum += phi[orc_index(g, cn)];
+        cnt += 1;
+      }
+    }
+    val = sum / cnt;
+    flags |= ORC_FALLBACK;
+  } else {
+    double C = orc_cutoff(phi[idx], P->beta, P->gamma);
+    if (P->p != 1.0) C *= pow(d[idx] / P->energy, P->p - 1.0);
+    double amp = sqrt(C * P->delta * d[idx] * dt / P->p);
+    double base[3];
+    for (int a = 0; a < 3; ++a) base[a] = xj[a] + C * dt * gd[a];
+    if (g->dim == 2) {
+      /* eq. (sigma2d): sigma = (d2 phi, -d1 phi)/|grad phi|, lambda = -1, +1 */
+      double sg[2] = {gp[1] / norm, -gp[0] / norm};
+      double sum = 0.0;
+      for (int l = -1; l <= 1; l += 2) {
+        double xs[3] = {base[0] + amp * sg[0] * l, base[1] + amp * sg[1] * l, 0.0};
+        sum += orc_interp(phi, g, kind, xs);
+      }
+      val = sum / 2.0;
+    } else {
+      /* eq. (sigma3d) and the regularisation above it */
+      double s = sqrt(gp[0] * gp[0] + gp[2] * gp[2]);
+      double nu1[3], nu2[3];
+      if (s != 0.0) {
+        nu1[0] = -gp[2] / s; nu1[1] = 0.0; nu1[2] = gp[0] / s;
+        nu2[0] = -gp[0] * gp[1] / s / norm;
+        nu2[1] = s / norm;
+        nu2[2] = -gp[1] * gp[2] / s / norm;
+      } else {
+        nu1[0] = 1.0; nu1[1] = 0.0; nu1[2] = 0.0;
+        nu2[0] = 0.0; nu2[1] = 0.0; nu2[2] = 1.0;
+        flags |= ORC_FRAME0;
+      }
+      double sum = 0.0;
+      for (int l1 = -1; l1 <= 1; l1 += 2) {
+        for (int l2 = -1; l2 <= 1; l2 += 2) {
+          double xs[3];
+          for (int a = 0; a < 3; ++a) xs[a] = base[a] + amp * (nu1[a] * l1 + nu2[a] * l2);
+          sum += orc_interp(phi, g, kind, xs);
+        }
+      }
+      val = sum / 4.0;
+    }
+  }
+  if (val > P->gamma) val = P->gamma;
+  if (val < -P->gamma) val = -P->gamma;
+  *out = val;
+  return flags;
+}
+
+/* Values at an arbitrary list of nodes (no band test). */
+void orc_sl_nodes(const double* phi, const double* d, const orc_grid* g, const orc_params* P,
+                  double dt, int kind, const int64_t* idx, int64_t m, double* out, int32_t* flags) {
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t e = 0; e < m; ++e) {
+    int f = orc_sl_node(phi, d, g, P, dt, kind, idx[e], &out[e]);
+    if (flags) flags[e] = f;
+  }
+}
+
+/* One time step on the whole grid: band of eq. (subgrid) read as
+ * |phi^n_j| < gamma, update inside it, every other node kept.
+ * counts[0] += band size, counts[1] += fallbacks, counts[2] += frame
+ * regularisations.  band (may be NULL) receives the 0/1 band mask. */
+void orc_step(const double* phi, const double* d, const orc_grid* g, const orc_params* P,
+              double dt, int kind, double* out, uint8_t* band, int64_t* counts) {
+  int64_t N = orc_nodes(g);
+  int64_t nb = 0, nf = 0, nr = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : nb, nf, nr)
+  for (int64_t j = 0; j < N; ++j) {
+    int in = fabs(phi[j]) < P->gamma;
+    if (band) band[j] = (uint8_t)in;
+    if (!in) {
+      out[j] = phi[j];
+      continue;
+    }
+    int f = orc_sl_node(phi, d, g, P, dt, kind, j, &out[j]);
+    nb += 1;
+    nf += (f & ORC_FALLBACK) ? 1 : 0;
+    nr += (f & ORC_FRAME0) ? 1 : 0;
+  }
+  if (counts) {
+    counts[0] += nb;
+    counts[1] += nf;
+    counts[2] += nr;
+  }
+}
+
+/* ----------------------------------------------------- reinitialisation */
+
+static double orc_sign(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
+
+/* Constrained reinitialisation of Section 3.7 on the band of Section 3.8.
+ * The paper gives the method only by reference; the reading used here:
+ *   Gbar = band plus its face neighbours;
+ *   interface set I = nodes of Gbar with a face neighbour of opposite (or
+ *     zero) sign in phi~;
+ *   one-step fix on I:  phi_j = phi~_j / max(|grad_c phi~_j|, floor);
+ *   then reinit_iters forward-Euler steps of phi_tau + sign(phi~)(|grad phi|-1)
+ *     = 0 on Gbar \ I with the first-order upwind (Godunov) gradient, I frozen;
+ *   finally the cut of eq. (cut).
+ * phi is overwritten.  counts[0] += |Gbar|, counts[1] += |I|. */
+void orc_reinit(double* phi, const uint8_t* band, const orc_grid* g, const orc_params* P,
+                int64_t* counts) {
+  int64_t N = orc_nodes(g);
+  uint8_t* gbar = (uint8_t*)calloc((size_t)N, 1);
+  uint8_t* itf = (uint8_t*)calloc((size_t)N, 1);
+  double* tilde = (double*)malloc((size_t)N * sizeof(double));
+  double* cur = (double*)malloc((size_t)N * sizeof(double));
+  double* nxt = (double*)malloc((size_t)N * sizeof(double));
+  memcpy(tilde, phi, (size_t)N * sizeof(double));
+  int64_t ng = 0, ni = 0;
+
+#pragma omp parallel for reduction(+ : ng)
+  for (int64_t j = 0; j < N; ++j) {
+    int c[3];
+    orc_coords(g, j, c);
+    int in = band[j] != 0;
+    for (int a = 0; a < g->dim && !in; ++a) {
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        int cn[3] = {c[0], c[1], c[2]};
+        cn[a] += sgn;
+        if (cn[a] < 0 || cn[a] > g->n[a] - 1) continue;
+        if (band[orc_index(g, cn)]) in = 1;
+      }
+    }
+    gbar[j] = (uint8_t)in;
+    ng += in;
+  }
+
+#pragma omp parallel for reduction(+ : ni)
+  for (int64_t j = 0; j < N; ++j) {
+    if (!gbar[j]) continue;
+    int c[3];
+    orc_coords(g, j, c);
+    int is_if = 0;
+    for (int a = 0; a < g->dim; ++a) {
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        int cn[3] = {c[0], c[1], c[2]};
+        cn[a] += sgn;
+        if (cn[a] < 0 || cn[a] > g->n[a] - 1) continue;
+        if (tilde[j] * tilde[orc_index(g, cn)] <= 0.0) is_if = 1;
+      }
+    }
+    itf[j] = (uint8_t)is_if;
+    ni += is_if;
+  }
+
+  memcpy(cur, tilde, (size_t)N * sizeof(double));
+#pragma omp parallel for
+  for (int64_t j = 0; j < N; ++j) {
+    if (!itf[j]) continue;
+    double gr[3];
+    orc_gradient(tilde, g, j, gr);
+    double nrm = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+    if (nrm < P->interface_floor) nrm = P->interface_floor;
+    cur[j] = tilde[j] / nrm;
+  }
+
+  for (int it = 0; it < P->reinit_iters; ++it) {
+    memcpy(nxt, cur, (size_t)N * sizeof(double));
+#pragma omp parallel for
+    for (int64_t j = 0; j < N; ++j) {
+      if (!gbar[j] || itf[j]) continue;
+      double S = orc_sign(tilde[j]);
+      if (S == 0.0) continue;
+      int c[3];
+      orc_coords(g, j, c);
+      double G2 = 0.0;
+      for (int a = 0; a < g->dim; ++a) {
+        int cm[3] = {c[0], c[1], c[2]}, cp[3] = {c[0], c[1], c[2]};
+        cm[a] -= 1;
+        cp[a] += 1;
+        double Dm = c[a] > 0 ? (cur[j] - cur[orc_index(g, cm)]) / g->h : 0.0;
+        double Dp = c[a] < g->n[a] - 1 ? (cur[orc_index(g, cp)] - cur[j]) / g->h : 0.0;
+        double t1, t2;
+        if (S > 0.0) {
+          t1 = Dm > 0.0 ? Dm * Dm : 0.0;
+          t2 = Dp < 0.0 ? Dp * Dp : 0.0;
+        } else {
+          t1 = Dm < 0.0 ? Dm * Dm : 0.0;
+          t2 = Dp > 0.0 ? Dp * Dp : 0.0;
+        }
+        G2 += t1 > t2 ? t1 : t2;
+      }
+      nxt[j] = cur[j] - P->reinit_dtau * S * (sqrt(G2) - 1.0);
+    }
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+
+#pragma omp parallel for
+  for (int64_t j = 0; j < N; ++j) {
+    if (!gbar[j]) continue;
+    double v = cur[j];
+    if (v > P->gamma) v = P->gamma;
+    if (v < -P->gamma) v = -P->gamma;
+    phi[j] = v;
+  }
+  if (counts) {
+    counts[0] += ng;
+    counts[1] += ni;
+  }
+  free(gbar);
+  free(itf);
+  free(tilde);
+  free(cur);
+  free(nxt);
+}
+
+/* ----------------------------------------------------- Algorithm 1 loop */
+
+/* n_steps passes of Algorithm 1, step 4, without the energy (p = 1):
+ * band (a), update (c), and every reinit_every-th step the reinitialisation
+ * on the band of that step and the cut (d).  step0 is the global index of the
+ * first step, so that the reinitialisation phase survives a restart.
+ * counts[0] = node updates, [1] fallbacks, [2] frame regularisations,
+ * [3] reinitialisations, [4] sum |Gbar|, [5] sum |I|. */
+void orc_run(double* phi, const double* d, const orc_grid* g, const orc_params* P, double dt,
+             int kind, int64_t step0, int32_t n_steps, int64_t* counts) {
+  int64_t N = orc_nodes(g);
+  double* nxt = (double*)malloc((size_t)N * sizeof(double));
+  uint8_t* band = (uint8_t*)malloc((size_t)N);
+  int64_t local[6] = {0, 0, 0, 0, 0, 0};
+  for (int32_t s = 0; s < n_steps; ++s) {
+    orc_step(phi, d, g, P, dt, kind, nxt, band, local);
+    if (P->reinit_every > 0 && (step0 + s + 1) % P->reinit_every == 0) {
+      orc_reinit(nxt, band, g, P, &local[4]);
+      local[3] += 1;
+    }
+    memcpy(phi, nxt, (size_t)N * sizeof(double));
+  }
+  if (counts) memcpy(counts, local, sizeof(local));
+  free(nxt);
+  free(band);
+}
+
+/* ------------------------------------------------------- initial data */
+
+/* Closed-form signed distances used as phi^0, then the cut of eq. (cut).
+ * kind 1: sphere (circle in 2D) centre args[0..2], radius args[3];
+ * kind 2: torus with axis z, centre args[0..2], radii R = args[3], r = args[4]. */
+void orc_init_phi(double* phi, const orc_grid* g, int kind, const double* args, double gamma) {
+  int64_t N = orc_nodes(g);
+#pragma omp parallel for
+  for (int64_t j = 0; j < N; ++j) {
+    int c[3];
+    orc_coords(g, j, c);
+    double x[3] = {0, 0, 0};
+    for (int a = 0; a < g->dim; ++a) x[a] = g->lo[a] + c[a] * g->h - args[a];
+    double v;
+    if (kind == 1) {
+      v = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) - args[3];
+    } else {
+      double rho = sqrt(x[0] * x[0] + x[1] * x[1]) - args[3];
+      v = sqrt(rho * rho + x[2] * x[2]) - args[4];
+    }
+    if (v > gamma) v = gamma;
+    if (v < -gamma) v = -gamma;
+    phi[j] = v;
+  }
+}
+
+/* ------------------------------------------------------ distance field */
+
+/* d(x) = min_Q |x - Q| (Section 2), by brute force over all cloud points, at
+ * every grid node.  pts is n_pts x dim, row major. */
+void orc_distance_brute(const double* pts, int64_t n_pts, const orc_grid* g, double* d) {
+  int64_t N = orc_nodes(g);
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < N; ++j) {
+    int c[3];
+    orc_coords(g, j, c);
+    double x[3] = {0, 0, 0};
+    for (int a = 0; a < g->dim; ++a) x[a] = g->lo[a] + c[a] * g->h;
+    double best = INFINITY;
+    for (int64_t q = 0; q < n_pts; ++q) {
+      double s = 0.0;
+      for (int a = 0; a < g->dim; ++a) {
+        double t = x[a] - pts[q * g->dim + a];
+        s += t * t;
+      }
+      if (s < best) best = s;
+    }
+    d[j] = sqrt(best);
+  }
+}
