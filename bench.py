@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the narrow-band semi-Lagrangian level-set solver on one MI355X.
+
+One bench step = one whole reconstruction of the 3D single-instance workload
+(128^3 grid on [-1,1]^3, 20k noisy torus points, WENO, dt = h/2, 300 steps,
+band 6h, reinitialisation every 10 steps): exact distance field from the
+cloud, initial data and first band, 300 time steps (update, band rebuild,
+reinitialisation and cut) and the copy-out of phi and the band.  The cloud is
+resident in HBM before the timed region.
+
+value = node updates (sum of band sizes over the steps) per second of wall
+time over the timed jobs.  The roofline object describes the dominant kernel
+(the 3D WENO step), timed with HIP events on the job's stream.  The
+cpu_baseline object times the FP64 oracle on a bounded sample of the same
+workload on the host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work of one node update of the step kernel (FMA = 2 flops):
+# 3D WENO: 84 one-dimensional WENO evaluations x 30 flops, 4 foot points x 42
+# flops of per-foot set-up, 60 flops of per-node set-up.
+FLOPS_PER_UPDATE = {(3, "weno"): 84 * 30 + 4 * 42 + 60, (3, "q1"): 4 * (7 * 3 + 18) + 60,
+                    (2, "weno"): 2 * (5 * 30 + 28) + 40, (2, "q1"): 2 * (3 * 3 + 12) + 40}
+# Compulsory HBM bytes of one node update: list entry in 4, phi^n_j 4,
+# (grad d, d) 16, phi^{n+1}_j 4, list entry out 4.
+BYTES_PER_UPDATE = 32
+PEAK_FP32_TFLOPS = 157.3  # MI355X published fp32 vector peak
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kernels.hip"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"sl_step_weno3_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, n_steps):
+    import numpy as np  # noqa: F401
+    import oracle
+    g = w["grid"]
+    prm = oracle.default_params(g["dim"], g["h"], gamma=w["gamma"], beta=w["beta"],
+                                reinit_every=w["reinit_every"])
+    d = oracle.distance(w["points"], g)
+    phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
+    oracle.run(phi0, d, g, prm, w["dt"], w["interp"], 1)  # load the library, touch memory
+    t0 = time.perf_counter()
+    _, counts = oracle.run(phi0, d, g, prm, w["dt"], w["interp"], n_steps)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": counts[0] / dt, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "sample": (f"first {n_steps} steps of the same run from phi0 ({int(counts[0])} node "
+                       f"updates, {int(counts[3])} reinitialisations), FP64, {dt:.1f} s wall; "
+                       f"distance field not timed")}
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE /
+    WRITE_SIZE readings (run under rocprofv3 --pmc)."""
+    import torch
+    n = 256 << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n, "copy_bytes_written_per_launch": n,
+                      "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed jobs")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="torus3d")
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2410_22205_amd import lsr, synth
+
+    torch.cuda.set_device(0)
+    w = synth.workload(args.workload)
+    g = w["grid"]
+    dim = g["dim"]
+    prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"])
+    job = lsr.Job(g, prm, max_points=len(w["points"]))
+    stream = job.stream
+    pts = torch.as_tensor(w["points"], dtype=torch.float64, device="cuda").contiguous()
+    phi_out = torch.empty(job.nodes, dtype=torch.float32, device="cuda")
+    band_out = torch.empty(job.nodes, dtype=torch.uint8, device="cuda")
+    kind = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}[w["phi0"][0]]
+    interp = lsr.interp_code(w["interp"])
+
+    def one_job():
+        lsr.lsr_load_cloud(job.handle, pts.data_ptr(), pts.shape[0])
+        lsr.lsr_init_phi(job.handle, None, kind, list(w["phi0"][1]), 0)
+        lsr.lsr_step(job.handle, w["steps"], w["dt"], interp)
+        lsr.lsr_extract(job.handle, phi_out.data_ptr(), band_out.data_ptr(), want_count=False)
+
+    for _ in range(args.warmup):
+        one_job()
+    stream.synchronize()
+    per_job = lsr.lsr_counters(job.handle)
+    updates_per_job = per_job["node_updates"]
+
+    lsr.lsr_profile_enable(job.handle, True, w["steps"] * args.steps + 8)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        one_job()
+        stream.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms, launches = lsr.lsr_profile_read(job.handle)
+    lsr.lsr_profile_enable(job.handle, False)
+    check = lsr.lsr_counters(job.handle)
+    assert check["node_updates"] == updates_per_job, "runs are not deterministic"
+
+    total_updates = updates_per_job * args.steps
+    value = total_updates / wall
+    kernel_s = kernel_ms / 1e3
+    flops = FLOPS_PER_UPDATE[(dim, w["interp"])]
+    achieved_tflops = flops * total_updates / kernel_s / 1e12
+    upd_per_launch = total_updates / launches
+    traffic = read_traffic(args.workload)
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic,
+                "kernel": f"k_sl_step<{dim},{w['interp']}>",
+                "flops_per_node_update": flops,
+                "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
+                "node_updates_per_launch": round(upd_per_launch, 1)}
+    hbm_gbs = BYTES_PER_UPDATE * total_updates / kernel_s / 1e9
+    lat_ms = sorted(1e3 * x for x in lat)
+    out = {
+        "metric": "narrow-band node-updates/s (3D WENO SL step) + jobs/s, p50/p99 latency",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": "x".join(str(v) for v in g["n"]),
+                   "points": len(w["points"]), "interp": w["interp"], "dt": "h/2" if dim == 3 else "h",
+                   "steps_per_job": w["steps"], "band": "6h", "reinit_every": w["reinit_every"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "hbm": {"algorithmic_bytes_per_update": BYTES_PER_UPDATE, "achieved_gbs": round(hbm_gbs, 1),
+                "peak_gbs": PEAK_HBM_GBS, "frac": round(hbm_gbs / PEAK_HBM_GBS, 4)},
+        "sl_kernel_node_updates_per_s": total_updates / kernel_s,
+        "sl_kernel_share_of_wall": kernel_s / wall,
+        "node_updates_per_job": updates_per_job,
+        "jobs_per_s": args.steps / wall,
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+    }
+    job.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * lsr.h - C ABI of the narrow-band semi-Lagrangian level-set solver for
+ * surface reconstruction from point clouds on AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Preda and M. Semplice, "Surface reconstruction from point cloud
+ * using a semi-Lagrangian scheme with local interpolator", arXiv:2410.22205.
+ * The library runs Algorithm 1's steps 2 and 4 (the energy step omitted, as
+ * it only matters for p > 1): the distance field to the cloud (Section 2 and
+ * 3.4, computed exactly), the narrow band (3.8), the semi-Lagrangian update
+ * with Q1 or tensor WENO interpolation (3.1, 3.2) and the reinitialisation
+ * plus cut (3.7, 3.8).
+ *
+ * General rules
+ *  - Every function returns an lsr_status; none throws.  On failure the job is
+ *    left as it was and lsr_last_error() describes the cause.
+ *  - Device memory is owned by the caller: lsr_create carves the caller's
+ *    workspace (size from lsr_workspace_bytes) and never allocates device
+ *    memory itself.  Pointers marked "device" are HIP device pointers.
+ *  - All device work is enqueued on the caller's HIP stream given to
+ *    lsr_create; only calls that return host-side values from the device
+ *    (lsr_load_cloud's input check, lsr_extract with n_band, lsr_counters)
+ *    synchronise that stream.
+ *  - Nodal arrays are in C order: 2D index i*n[1] + j, 3D index
+ *    (i*n[1] + j)*n[2] + k, axis 0 <-> x.  Node (i,j,k) sits at
+ *    lo + (i,j,k)*h.
+ *  - A job is used from one host thread at a time.
+ */
+#ifndef LSR_H
+#define LSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSR_OK = 0,
+  LSR_E_INVALID = -1,     /* bad argument (shape, parameter, non-finite input) */
+  LSR_E_NOMEM = -2,       /* workspace too small */
+  LSR_E_DEVICE = -3,      /* HIP error; text in lsr_last_error() */
+  LSR_E_STATE = -4,       /* call out of order (e.g. step before init_phi) */
+  LSR_E_UNSUPPORTED = -5  /* valid but not implemented (e.g. p != 1) */
+} lsr_status;
+
+/* Interpolation operator I[phi] of Section 3.2. */
+typedef enum { LSR_Q1 = 0, LSR_WENO = 1 } lsr_interp;
+
+/* Initial-data kinds for lsr_init_phi. */
+enum { LSR_PHI_ARRAY = 0, LSR_PHI_SPHERE = 1, LSR_PHI_TORUS = 2 };
+
+/* Uniform Cartesian grid (Section 3): dim 2 or 3, n[a] >= 4 nodes per axis
+ * (the WENO stencil spans 4 nodes), n[2] ignored in 2D, node spacing h > 0.
+ * Limits: total nodes < 2^32 and the per-axis index bit widths sum to <= 32. */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double lo[3];
+  double h;
+} lsr_grid;
+
+/* Parameters (see lsr_params_default for the values the paper uses). */
+typedef struct {
+  double p;          /* energy exponent of Section 2; only p = 1 is supported */
+  double delta;      /* curvature weight, eq. (levelset:pde); >= 0 */
+  double gamma;      /* narrow-band half width, eq. (subgrid); band |phi| < gamma */
+  double beta;       /* cut-off inner radius, eq. (cutoff); 0 < beta < gamma */
+  double grad_C;     /* degenerate-gradient threshold C dt^alpha, Section 3.1 */
+  double grad_alpha;
+  int32_t reinit_every;  /* reinitialise after every K-th step (0: never) */
+  int32_t reinit_iters;  /* forward-Euler pseudo-time iterations per reinit */
+  double reinit_dtau;    /* pseudo-time step, <= h/sqrt(dim) */
+  double interface_floor;/* lower bound on |grad phi| in the interface fix */
+} lsr_params;
+
+typedef struct lsr_job lsr_job;
+typedef struct lsr_batch lsr_batch;
+
+/* Device counters returned by lsr_counters (cumulative since init_phi). */
+enum {
+  LSR_CNT_NODE_UPDATES = 0, /* sum over steps of the band size |G~^n| */
+  LSR_CNT_FALLBACKS = 1,    /* updates through eq. (SL:2) */
+  LSR_CNT_FRAME0 = 2,       /* 3D updates with the regularised frame (e1, e3) */
+  LSR_CNT_REINITS = 3,      /* reinitialisations run */
+  LSR_CNT_GBAR = 4,         /* sum of |band + face neighbours| over reinits */
+  LSR_CNT_INTERFACE = 5,    /* sum of interface-set sizes over reinits */
+  LSR_CNT_STEPS = 6,        /* steps run */
+  LSR_CNT_COUNT = 7
+};
+
+/* Paper values for a grid of spacing h: p = delta = 1; gamma = 4h, beta = 2h
+ * in 2D and gamma = 6h, beta = 3h in 3D (Section 3.8); C = 1e-3, alpha = 1
+ * (Section 3.1); reinitialisation after every step in 2D and every 10th in
+ * 3D, pseudo-time step h/2, ceil((gamma + h)/dtau) iterations, floor 1e-3
+ * (Section 3.7 gives no values; these are this library's choice). */
+lsr_status lsr_params_default(int32_t dim, double h, lsr_params* out);
+
+/* Device workspace a job needs for this grid and at most max_points cloud
+ * points.  Independent of the parameters. */
+lsr_status lsr_workspace_bytes(const lsr_grid* grid, int64_t max_points, size_t* bytes);
+
+/* Create a job on the current HIP device.  dev_workspace: device memory of
+ * at least lsr_workspace_bytes bytes, 256-byte aligned, owned by the caller
+ * and untouched by other work while the job lives.  hip_stream: a
+ * hipStream_t (NULL = default stream).  Enqueues the clearing of the
+ * workspace.  LSR_E_INVALID on a bad grid or parameters, LSR_E_NOMEM if the
+ * workspace is too small, LSR_E_UNSUPPORTED for p != 1. */
+lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_workspace,
+                      size_t ws_bytes, void* hip_stream, lsr_job** out);
+
+/* Distance field of Section 2, d(x) = min_Q |x - Q|, computed exactly at
+ * every node from the cloud.  dev_xyz: device, n x dim doubles, row major;
+ * it is copied into the workspace and may be freed afterwards.  Every point
+ * must be finite and inside the grid's box (Algorithm 1, step 1: the grid
+ * encompasses the cloud); otherwise LSR_E_INVALID.  Synchronises the stream
+ * once to check the points.  The current phi and band are kept. */
+lsr_status lsr_load_cloud(lsr_job* job, const double* dev_xyz, int64_t n);
+
+/* Test and restart hook: use the given distance field instead of a cloud.
+ * dev_d: device, one double per node, C order, finite and >= 0 (not
+ * checked).  The current phi and band are kept. */
+lsr_status lsr_set_distance(lsr_job* job, const double* dev_d);
+
+/* Copy the distance field (as stored, float) to dev_out (device, one float
+ * per node, C order). */
+lsr_status lsr_get_distance(lsr_job* job, float* dev_out);
+
+/* Initial data phi^0 (Algorithm 1, step 3), cut to [-gamma, gamma] by
+ * eq. (cut), and the first band.  kind LSR_PHI_ARRAY: dev_phi0 (device, one
+ * float per node, C order) is copied; LSR_PHI_SPHERE: signed distance to the
+ * sphere (circle in 2D) with centre args[0..2] and radius args[3];
+ * LSR_PHI_TORUS (3D): torus with axis z, centre args[0..2], radii R = args[3],
+ * r = args[4].  args is host memory.  step0 is the global index of the next
+ * step, which fixes the reinitialisation phase after a restart. */
+lsr_status lsr_init_phi(lsr_job* job, const float* dev_phi0, int32_t kind, const double* args,
+                        int64_t step0);
+
+/* n_steps iterations of Algorithm 1's loop: band (eq. subgrid, read as
+ * |phi| < gamma), the update of eqs. (SL2d)/(SL3d) with the cut-off factor of
+ * Section 3.8 and the fallback of eq. (SL:2), the cut of eq. (cut) and, after
+ * every step whose global index s satisfies (s + 1) % reinit_every == 0, the
+ * reinitialisation on the pre-update band plus its face neighbours.  dt > 0.
+ * Enqueued on the stream; returns before the work finishes. */
+lsr_status lsr_step(lsr_job* job, int32_t n_steps, double dt, lsr_interp interp);
+
+/* One reinitialisation (Section 3.7) plus cut, on the current band and its
+ * face neighbours, outside the step loop. */
+lsr_status lsr_reinit(lsr_job* job);
+
+/* Copy out the current phi (dev_phi: device, one float per node) and the band
+ * mask (dev_band: device, one byte per node, 1 iff |phi| < gamma); either may
+ * be NULL.  If n_band is not NULL the stream is synchronised and the band
+ * size stored there; step_index (may be NULL) receives the global index of
+ * the next step. */
+lsr_status lsr_extract(lsr_job* job, float* dev_phi, uint8_t* dev_band, int64_t* n_band,
+                       int64_t* step_index);
+
+/* Read up to n cumulative counters (LSR_CNT_*) into host memory; syncs. */
+lsr_status lsr_counters(lsr_job* job, int64_t* out, int32_t n);
+
+/* Destroy the host-side job object.  Does not free the workspace; waits for
+ * the job's queued work to finish. */
+lsr_status lsr_destroy(lsr_job* job);
+
+/* Batched execution of independent jobs (same device, each job already
+ * through lsr_init_phi): one persistent launch per step covers every job's
+ * band; each job keeps its own dt, interpolator, reinitialisation phase and
+ * state, and its results are bitwise those of lsr_step on the job alone.
+ * Work goes to the first job's stream.  dt and interp per job. */
+lsr_status lsr_batch_create(lsr_job* const* jobs, int32_t n_jobs, const double* dt,
+                            const int32_t* interp, lsr_batch** out);
+lsr_status lsr_batch_step(lsr_batch* batch, int32_t n_steps);
+lsr_status lsr_batch_destroy(lsr_batch* batch);
+
+/* Measurement hook.  While enabled, every semi-Lagrangian step kernel the job
+ * launches is bracketed by a pair of HIP events recorded on the job's stream
+ * (at most max_launches pairs; later launches are not recorded).  Enabling
+ * clears earlier records.  lsr_profile_read synchronises the stream and
+ * returns the summed kernel time in milliseconds and the number of recorded
+ * launches. */
+lsr_status lsr_profile_enable(lsr_job* job, int32_t enable, int32_t max_launches);
+lsr_status lsr_profile_read(lsr_job* job, double* total_ms, int64_t* launches);
+
+/* Text of the last error on this host thread; valid until the next call. */
+const char* lsr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSR_H */

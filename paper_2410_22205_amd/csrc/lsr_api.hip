@@ -1,0 +1,618 @@
+// C-ABI layer of the narrow-band semi-Lagrangian level-set solver
+// (include/lsr.h): argument checks, workspace carving, job state and the
+// order of kernel launches for Algorithm 1's loop (Preda & Semplice,
+// arXiv:2410.22205).
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lsr.h"
+#include "lsr_internal.h"
+
+using namespace lsr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lsr_status fail(lsr_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define LSR_HIP(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(LSR_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+int bits_for(int n) {  // bits to hold indices 0..n-1
+  int b = 0;
+  while ((1LL << b) < (long long)n) ++b;
+  return b;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, stamp, cnt, stats;
+  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ;
+  size_t total;
+  int nb[3];
+  int64_t nbins;
+};
+
+int64_t node_count(const lsr_grid& g) {
+  int64_t N = (int64_t)g.n[0] * g.n[1];
+  return g.dim == 3 ? N * g.n[2] : N;
+}
+
+void bin_counts(const lsr_grid& g, int nb[3]) {
+  for (int a = 0; a < 3; ++a) nb[a] = a < g.dim ? (g.n[a] - 1) / BIN_W + 1 : 1;
+}
+
+Layout make_layout(const lsr_grid& g, int64_t max_points) {
+  Layout L;
+  const size_t N = (size_t)node_count(g);
+  const size_t P = (size_t)(max_points > 0 ? max_points : 1);
+  bin_counts(g, L.nb);
+  L.nbins = (int64_t)L.nb[0] * L.nb[1] * L.nb[2];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.phi0 = take(4 * N);
+  L.phi1 = take(4 * N);
+  L.dp = take(16 * N);
+  L.d64 = take(8 * N);
+  L.list0 = take(4 * N);
+  L.list1 = take(4 * N);
+  L.listM = take(4 * N);
+  L.mflags = take(N);
+  L.stamp = take(4 * N);
+  L.cnt = take(4 * 16);
+  L.stats = take(8 * 16);
+  L.pts_raw = take(8 * (size_t)g.dim * P);
+  L.pts = take(8 * (size_t)g.dim * P);
+  L.pt_bin = take(4 * P);
+  L.bin_count = take(4 * (size_t)L.nbins);
+  L.bin_start = take(4 * ((size_t)L.nbins + 1));
+  L.bin_fill = take(4 * (size_t)L.nbins);
+  L.occ = take(4 * (size_t)L.nbins);
+  L.total = off;
+  return L;
+}
+
+lsr_status check_grid(const lsr_grid* g) {
+  if (!g) return fail(LSR_E_INVALID, "grid is NULL");
+  if (g->dim != 2 && g->dim != 3) return fail(LSR_E_INVALID, "dim must be 2 or 3");
+  for (int a = 0; a < g->dim; ++a) {
+    if (g->n[a] < 4) return fail(LSR_E_INVALID, "every axis needs at least 4 nodes");
+    if (!isfinite(g->lo[a])) return fail(LSR_E_INVALID, "lo must be finite");
+  }
+  if (!(g->h > 0.0) || !isfinite(g->h)) return fail(LSR_E_INVALID, "h must be finite and > 0");
+  const int64_t N = node_count(*g);
+  if (N >= (int64_t)1 << 32) return fail(LSR_E_UNSUPPORTED, "grids of 2^32 nodes or more");
+  int bits = bits_for(g->n[0]) + bits_for(g->n[1]) + (g->dim == 3 ? bits_for(g->n[2]) : 0);
+  if (bits > 32) return fail(LSR_E_UNSUPPORTED, "packed node coordinates need more than 32 bits");
+  return LSR_OK;
+}
+
+lsr_status check_params(const lsr_grid* g, const lsr_params* p) {
+  if (!p) return fail(LSR_E_INVALID, "params is NULL");
+  if (!(p->p >= 1.0)) return fail(LSR_E_INVALID, "p must be >= 1");
+  if (p->p != 1.0) return fail(LSR_E_UNSUPPORTED, "p != 1 needs the energy functional");
+  if (!(p->delta >= 0.0) || !isfinite(p->delta)) return fail(LSR_E_INVALID, "delta must be >= 0");
+  if (!(p->beta > 0.0) || !(p->gamma > p->beta) || !isfinite(p->gamma))
+    return fail(LSR_E_INVALID, "need 0 < beta < gamma");
+  if (!(p->grad_C >= 0.0) || !isfinite(p->grad_C) || !isfinite(p->grad_alpha))
+    return fail(LSR_E_INVALID, "bad fallback threshold");
+  if (p->reinit_every < 0 || p->reinit_iters < 0)
+    return fail(LSR_E_INVALID, "reinit_every and reinit_iters must be >= 0");
+  if (!(p->reinit_dtau > 0.0) || p->reinit_dtau > g->h / sqrt((double)g->dim) * (1.0 + 1e-12))
+    return fail(LSR_E_INVALID, "reinit_dtau must be in (0, h/sqrt(dim)]");
+  if (!(p->interface_floor > 0.0)) return fail(LSR_E_INVALID, "interface_floor must be > 0");
+  return LSR_OK;
+}
+
+}  // namespace
+
+struct lsr_job {
+  lsr_grid grid;
+  lsr_params prm;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  Layout L;
+  int64_t max_points;
+  DevGrid dg;
+  BinGeom bg;
+  float* phi[2];
+  float4* dp;
+  double* d64;
+  uint32_t* list[2];
+  uint32_t* listM;
+  uint8_t* mflags;
+  uint32_t* stamp;
+  int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins
+  unsigned long long* stats;
+  double* pts_raw;
+  double* pts;
+  int32_t* pt_bin;
+  int32_t* bin_count;
+  int32_t* bin_start;
+  int32_t* bin_fill;
+  uint32_t* occ;
+  unsigned list_blocks;
+  int cur;       // phi buffer holding the current phi
+  int cur_list;  // list buffer holding the current band list
+  int ring;      // counter slot holding the current list length
+  uint32_t epoch;
+  int64_t step_index;
+  int64_t n_reinits, n_steps;
+  bool has_d, has_phi;
+  // measurement hook
+  bool prof_on;
+  int prof_used;
+  std::vector<hipEvent_t> prof_ev;
+};
+
+namespace {
+
+StepConst step_const(const lsr_job* j, double dt) {
+  StepConst c;
+  const double h = j->grid.h;
+  const lsr_params& p = j->prm;
+  c.gamma = (float)p.gamma;
+  c.beta = (float)p.beta;
+  const double gb = p.gamma - p.beta;
+  c.inv_gb3 = (float)(1.0 / (gb * gb * gb));
+  c.drift = (float)(dt / h);
+  c.diff2 = (float)(p.delta * dt / (p.p * h * h));
+  c.grad_thr = (float)(p.grad_C * pow(dt, p.grad_alpha));
+  c.weno_e = (float)(h * h * h * h);
+  c.half_inv_h = (float)(0.5 / h);
+  c.inv_h = (float)(1.0 / h);
+  return c;
+}
+
+int32_t* ring_slot(lsr_job* j, int k) { return j->cnt + ((j->ring + k) % 3); }
+
+lsr_status run_reinit(lsr_job* j) {
+  hipStream_t s = j->stream;
+  const int dim = j->grid.dim;
+  if (j->epoch == 0xFFFFFFFFu) {
+    LSR_HIP(launch_fill_u32(j->stamp, 0u, j->dg.N, s));
+    j->epoch = 0;
+  }
+  j->epoch += 1;
+  DilArgs da;
+  da.g = j->dg;
+  da.L = j->list[j->cur_list];
+  da.cnt_in = ring_slot(j, 0);
+  da.M = j->listM;
+  da.cnt_out = ring_slot(j, 1);
+  da.cnt_reset = ring_slot(j, 2);
+  da.stamp = j->stamp;
+  da.epoch = j->epoch;
+  LSR_HIP(launch_dilate(dim, da, j->list_blocks, s));
+  j->ring = (j->ring + 1) % 3;
+
+  RArgs ra;
+  ra.g = j->dg;
+  ra.c = step_const(j, j->grid.h);
+  ra.M = j->listM;
+  ra.cnt = ring_slot(j, 0);
+  ra.flags = j->mflags;
+  ra.dtau = (float)j->prm.reinit_dtau;
+  ra.floor_ = (float)j->prm.interface_floor;
+  ra.stats = j->stats;
+  ra.src = j->phi[j->cur];
+  ra.dst = j->phi[1 - j->cur];
+  LSR_HIP(launch_reinit_fix(dim, ra, j->list_blocks, s));
+  int w = 1 - j->cur;
+  for (int it = 0; it < j->prm.reinit_iters; ++it) {
+    ra.src = j->phi[w];
+    ra.dst = j->phi[1 - w];
+    LSR_HIP(launch_reinit_iter(dim, ra, j->list_blocks, s));
+    w = 1 - w;
+  }
+  FinArgs fa;
+  fa.g = j->dg;
+  fa.gamma = (float)j->prm.gamma;
+  fa.M = j->listM;
+  fa.cnt_in = ring_slot(j, 0);
+  fa.cur = j->phi[w];
+  fa.other = j->phi[1 - w];
+  fa.Lout = j->list[j->cur_list];
+  fa.cnt_out = ring_slot(j, 1);
+  fa.cnt_reset = ring_slot(j, 2);
+  LSR_HIP(launch_reinit_final(fa, j->list_blocks, s));
+  j->ring = (j->ring + 1) % 3;
+  j->cur = w;
+  j->n_reinits += 1;
+  return LSR_OK;
+}
+
+lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp) {
+  hipStream_t s = j->stream;
+  SLArgs a;
+  a.g = j->dg;
+  a.c = step_const(j, dt);
+  a.dp = j->dp;
+  a.stats = j->stats;
+  for (int32_t q = 0; q < n_steps; ++q) {
+    a.A = j->phi[j->cur];
+    a.B = j->phi[1 - j->cur];
+    a.Lin = j->list[j->cur_list];
+    a.Lout = j->list[1 - j->cur_list];
+    a.cnt_in = ring_slot(j, 0);
+    a.cnt_out = ring_slot(j, 1);
+    a.cnt_reset = ring_slot(j, 2);
+    const bool rec = j->prof_on && 2 * (size_t)j->prof_used + 1 < j->prof_ev.size();
+    if (rec) LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used], s));
+    LSR_HIP(launch_sl_step(j->grid.dim, interp, a, j->list_blocks, s));
+    if (rec) {
+      LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used + 1], s));
+      j->prof_used += 1;
+    }
+    j->cur = 1 - j->cur;
+    j->cur_list = 1 - j->cur_list;
+    j->ring = (j->ring + 1) % 3;
+    j->step_index += 1;
+    j->n_steps += 1;
+    if (j->prm.reinit_every > 0 && j->step_index % j->prm.reinit_every == 0) {
+      lsr_status st = run_reinit(j);
+      if (st != LSR_OK) return st;
+    }
+  }
+  return LSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lsr_last_error(void) { return g_last_error.c_str(); }
+
+lsr_status lsr_params_default(int32_t dim, double h, lsr_params* out) {
+  if (!out) return fail(LSR_E_INVALID, "out is NULL");
+  if (dim != 2 && dim != 3) return fail(LSR_E_INVALID, "dim must be 2 or 3");
+  if (!(h > 0.0) || !isfinite(h)) return fail(LSR_E_INVALID, "h must be > 0");
+  lsr_params p;
+  p.p = 1.0;
+  p.delta = 1.0;
+  p.gamma = (dim == 2 ? 4.0 : 6.0) * h;
+  p.beta = (dim == 2 ? 2.0 : 3.0) * h;
+  p.grad_C = 1e-3;
+  p.grad_alpha = 1.0;
+  p.reinit_every = dim == 2 ? 1 : 10;
+  p.reinit_dtau = 0.5 * h;
+  p.reinit_iters = (int32_t)ceil((p.gamma + h) / p.reinit_dtau - 1e-9);
+  p.interface_floor = 1e-3;
+  *out = p;
+  return LSR_OK;
+}
+
+lsr_status lsr_workspace_bytes(const lsr_grid* grid, int64_t max_points, size_t* bytes) {
+  lsr_status st = check_grid(grid);
+  if (st != LSR_OK) return st;
+  if (!bytes) return fail(LSR_E_INVALID, "bytes is NULL");
+  if (max_points < 0) return fail(LSR_E_INVALID, "max_points must be >= 0");
+  *bytes = make_layout(*grid, max_points).total;
+  return LSR_OK;
+}
+
+lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_workspace,
+                      size_t ws_bytes, void* hip_stream, lsr_job** out) {
+  lsr_status st = check_grid(grid);
+  if (st != LSR_OK) return st;
+  st = check_params(grid, params);
+  if (st != LSR_OK) return st;
+  if (!out) return fail(LSR_E_INVALID, "out is NULL");
+  if (!dev_workspace) return fail(LSR_E_INVALID, "workspace is NULL");
+  if (((uintptr_t)dev_workspace) & 255) return fail(LSR_E_INVALID, "workspace must be 256-byte aligned");
+  // the largest cloud the workspace holds
+  Layout L0 = make_layout(*grid, 1);
+  if (ws_bytes < L0.total) return fail(LSR_E_NOMEM, "workspace smaller than lsr_workspace_bytes");
+  const size_t per_point = 8 * 2 * (size_t)grid->dim + 4;
+  int64_t maxp = 1 + (int64_t)((ws_bytes - L0.total) / (per_point + 8));
+  while (maxp > 1 && make_layout(*grid, maxp).total > ws_bytes) maxp = maxp * 15 / 16;
+  Layout L = make_layout(*grid, maxp);
+  if (L.total > ws_bytes) return fail(LSR_E_NOMEM, "workspace too small");
+
+  int dev = 0, ncu = 0;
+  LSR_HIP(hipGetDevice(&dev));
+  LSR_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+
+  lsr_job* j = new (std::nothrow) lsr_job();
+  if (!j) return fail(LSR_E_NOMEM, "host allocation failed");
+  j->grid = *grid;
+  if (grid->dim == 2) {
+    j->grid.n[2] = 1;
+    j->grid.lo[2] = 0.0;
+  }
+  j->prm = *params;
+  j->stream = (hipStream_t)hip_stream;
+  j->ws = (char*)dev_workspace;
+  j->ws_bytes = ws_bytes;
+  j->L = L;
+  j->max_points = maxp;
+  const lsr_grid& g = j->grid;
+  DevGrid& d = j->dg;
+  d.n0 = g.n[0];
+  d.n1 = g.n[1];
+  d.n2 = g.dim == 3 ? g.n[2] : 1;
+  d.s1 = (uint32_t)d.n2;
+  d.s0 = (uint32_t)d.n1 * (uint32_t)d.n2;
+  d.N = (uint32_t)node_count(g);
+  d.bits_k = g.dim == 3 ? bits_for(d.n2) : 0;
+  d.bits_j = bits_for(d.n1);
+  d.h = (float)g.h;
+  d.inv_h = (float)(1.0 / g.h);
+  d.hd = g.h;
+  d.lo0 = g.lo[0];
+  d.lo1 = g.lo[1];
+  d.lo2 = g.lo[2];
+  BinGeom& b = j->bg;
+  for (int a = 0; a < 3; ++a) {
+    b.nb[a] = L.nb[a];
+    b.lo[a] = g.lo[a];
+    b.hi[a] = a < g.dim ? g.lo[a] + (g.n[a] - 1) * g.h : g.lo[a];
+  }
+  b.bw = BIN_W * g.h;
+  b.inv_bw = 1.0 / b.bw;
+
+  char* w = j->ws;
+  j->phi[0] = (float*)(w + L.phi0);
+  j->phi[1] = (float*)(w + L.phi1);
+  j->dp = (float4*)(w + L.dp);
+  j->d64 = (double*)(w + L.d64);
+  j->list[0] = (uint32_t*)(w + L.list0);
+  j->list[1] = (uint32_t*)(w + L.list1);
+  j->listM = (uint32_t*)(w + L.listM);
+  j->mflags = (uint8_t*)(w + L.mflags);
+  j->stamp = (uint32_t*)(w + L.stamp);
+  j->cnt = (int32_t*)(w + L.cnt);
+  j->stats = (unsigned long long*)(w + L.stats);
+  j->pts_raw = (double*)(w + L.pts_raw);
+  j->pts = (double*)(w + L.pts);
+  j->pt_bin = (int32_t*)(w + L.pt_bin);
+  j->bin_count = (int32_t*)(w + L.bin_count);
+  j->bin_start = (int32_t*)(w + L.bin_start);
+  j->bin_fill = (int32_t*)(w + L.bin_fill);
+  j->occ = (uint32_t*)(w + L.occ);
+  uint64_t want = ((uint64_t)d.N + 255) / 256;
+  uint64_t cap = (uint64_t)(ncu > 0 ? ncu : 256) * 8;
+  uint64_t lb = want < cap ? want : cap;
+  lb = ((lb + 7) / 8) * 8;
+  j->list_blocks = (unsigned)lb;
+  j->cur = 0;
+  j->cur_list = 0;
+  j->ring = 0;
+  j->epoch = 0;
+  j->step_index = 0;
+  j->n_reinits = 0;
+  j->n_steps = 0;
+  j->has_d = false;
+  j->has_phi = false;
+  j->prof_on = false;
+  j->prof_used = 0;
+
+  hipStream_t s = j->stream;
+  hipError_t e = launch_fill_u32(j->stamp, 0u, d.N, s);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->cnt, 0u, 16, s);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->stats, 0u, 32, s);
+  if (e != hipSuccess) {
+    delete j;
+    return fail(LSR_E_DEVICE, std::string("clearing the workspace: ") + hipGetErrorString(e));
+  }
+  *out = j;
+  return LSR_OK;
+}
+
+lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (!dev_xyz) return fail(LSR_E_INVALID, "points are NULL");
+  if (n < 1) return fail(LSR_E_INVALID, "the cloud needs at least one point");
+  if (n > j->max_points) return fail(LSR_E_NOMEM, "cloud larger than the workspace allows");
+  hipStream_t s = j->stream;
+  const int dim = j->grid.dim;
+  const int32_t nbins = (int32_t)j->L.nbins;
+  LSR_HIP(hipMemcpyAsync(j->pts_raw, dev_xyz, sizeof(double) * dim * (size_t)n,
+                         hipMemcpyDeviceToDevice, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)j->bin_count, 0u, (uint64_t)nbins, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)j->bin_fill, 0u, (uint64_t)nbins, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 5), 0u, 1, s));
+  LSR_HIP(launch_bin_points(dim, j->bg, j->pts_raw, n, j->bin_count, j->pt_bin, j->cnt + 3, s));
+  int32_t flag = 0;
+  LSR_HIP(hipMemcpyAsync(&flag, j->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LSR_HIP(hipStreamSynchronize(s));
+  if (flag) return fail(LSR_E_INVALID, "cloud has a non-finite point or one outside the grid box");
+  LSR_HIP(launch_scan_bins(j->bin_count, nbins, j->bin_start, s));
+  LSR_HIP(launch_occupied(j->bin_start, nbins, j->occ, j->cnt + 5, s));
+  LSR_HIP(launch_scatter_points(dim, j->pts_raw, n, j->pt_bin, j->bin_start, j->bin_fill, j->pts, s));
+  DistArgs da;
+  da.g = j->dg;
+  da.bg = j->bg;
+  da.pts = j->pts;
+  da.start = j->bin_start;
+  da.occ = j->occ;
+  da.occ_cnt = j->cnt + 5;
+  da.d64 = j->d64;
+  const int BS = dim == 3 ? 8 : 16;
+  unsigned bricks = (unsigned)(((j->dg.n0 + BS - 1) / BS) * ((j->dg.n1 + BS - 1) / BS) *
+                               (dim == 3 ? (j->dg.n2 + BS - 1) / BS : 1));
+  LSR_HIP(launch_distance(dim, da, bricks, s));
+  LSR_HIP(launch_dpack(dim, j->dg, j->d64, j->dp, s));
+  j->has_d = true;
+  return LSR_OK;
+}
+
+lsr_status lsr_set_distance(lsr_job* j, const double* dev_d) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (!dev_d) return fail(LSR_E_INVALID, "distance is NULL");
+  LSR_HIP(hipMemcpyAsync(j->d64, dev_d, sizeof(double) * j->dg.N, hipMemcpyDeviceToDevice,
+                         j->stream));
+  LSR_HIP(launch_dpack(j->grid.dim, j->dg, j->d64, j->dp, j->stream));
+  j->has_d = true;
+  return LSR_OK;
+}
+
+lsr_status lsr_get_distance(lsr_job* j, float* dev_out) {
+  if (!j || !dev_out) return fail(LSR_E_INVALID, "NULL argument");
+  if (!j->has_d) return fail(LSR_E_STATE, "no distance field yet");
+  LSR_HIP(hipMemcpy2DAsync(dev_out, sizeof(float), ((const char*)j->dp) + 12, sizeof(float4),
+                           sizeof(float), j->dg.N, hipMemcpyDeviceToDevice, j->stream));
+  return LSR_OK;
+}
+
+lsr_status lsr_init_phi(lsr_job* j, const float* dev_phi0, int32_t kind, const double* args,
+                        int64_t step0) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (kind < 0 || kind > 2) return fail(LSR_E_INVALID, "unknown kind");
+  if (kind == LSR_PHI_ARRAY && !dev_phi0) return fail(LSR_E_INVALID, "phi0 is NULL");
+  if (kind == LSR_PHI_TORUS && j->grid.dim != 3) return fail(LSR_E_INVALID, "torus needs 3D");
+  if (kind != LSR_PHI_ARRAY && !args) return fail(LSR_E_INVALID, "args is NULL");
+  if (step0 < 0) return fail(LSR_E_INVALID, "step0 must be >= 0");
+  double a[5] = {0, 0, 0, 0, 0};
+  if (kind != LSR_PHI_ARRAY) {
+    const int na = kind == LSR_PHI_SPHERE ? 4 : 5;
+    for (int q = 0; q < na; ++q) {
+      if (!isfinite(args[q])) return fail(LSR_E_INVALID, "args must be finite");
+      a[q] = args[q];
+    }
+    if (j->grid.dim == 2) a[2] = 0.0;
+  }
+  hipStream_t s = j->stream;
+  const int dim = j->grid.dim;
+  if (kind == LSR_PHI_ARRAY) {
+    // check the input before touching the state (no output buffers: check only)
+    LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s));
+    LSR_HIP(launch_init_phi(dim, j->dg, 0, a, (float)j->prm.gamma, dev_phi0, nullptr, nullptr,
+                            j->cnt + 3, s));
+    int32_t flag = 0;
+    LSR_HIP(hipMemcpyAsync(&flag, j->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSR_HIP(hipStreamSynchronize(s));
+    if (flag) return fail(LSR_E_INVALID, "phi0 has a non-finite value");
+  }
+  LSR_HIP(launch_init_phi(dim, j->dg, kind, a, (float)j->prm.gamma, dev_phi0, j->phi[0], j->phi[1],
+                          j->cnt + 3, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)j->cnt, 0u, 3, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)j->stats, 0u, 32, s));
+  LSR_HIP(launch_band_scan(dim, j->dg, (float)j->prm.gamma, j->phi[0], j->list[0], j->cnt, s));
+  j->cur = 0;
+  j->cur_list = 0;
+  j->ring = 0;
+  j->step_index = step0;
+  j->n_reinits = 0;
+  j->n_steps = 0;
+  j->has_phi = true;
+  return LSR_OK;
+}
+
+lsr_status lsr_step(lsr_job* j, int32_t n_steps, double dt, lsr_interp interp) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (n_steps < 0) return fail(LSR_E_INVALID, "n_steps must be >= 0");
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(LSR_E_INVALID, "dt must be > 0");
+  if (interp != LSR_Q1 && interp != LSR_WENO) return fail(LSR_E_INVALID, "unknown interpolator");
+  if (!j->has_d) return fail(LSR_E_STATE, "no distance field: call lsr_load_cloud first");
+  if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
+  return run_steps(j, n_steps, dt, (int)interp);
+}
+
+lsr_status lsr_reinit(lsr_job* j) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
+  return run_reinit(j);
+}
+
+lsr_status lsr_extract(lsr_job* j, float* dev_phi, uint8_t* dev_band, int64_t* n_band,
+                       int64_t* step_index) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
+  hipStream_t s = j->stream;
+  if (dev_phi)
+    LSR_HIP(hipMemcpyAsync(dev_phi, j->phi[j->cur], sizeof(float) * j->dg.N,
+                           hipMemcpyDeviceToDevice, s));
+  if (dev_band || n_band) {
+    if (dev_band) LSR_HIP(launch_fill_u8(dev_band, 0, j->dg.N, s));
+    LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 4), 0u, 1, s));
+    LSR_HIP(launch_band_mask(j->dg, (float)j->prm.gamma, j->phi[j->cur], j->list[j->cur_list],
+                             ring_slot(j, 0), dev_band, j->cnt + 4, j->list_blocks, s));
+  }
+  if (n_band) {
+    int32_t c = 0;
+    LSR_HIP(hipMemcpyAsync(&c, j->cnt + 4, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSR_HIP(hipStreamSynchronize(s));
+    *n_band = c;
+  }
+  if (step_index) *step_index = j->step_index;
+  return LSR_OK;
+}
+
+lsr_status lsr_counters(lsr_job* j, int64_t* out, int32_t n) {
+  if (!j || !out) return fail(LSR_E_INVALID, "NULL argument");
+  if (n < 0) return fail(LSR_E_INVALID, "n must be >= 0");
+  unsigned long long dev[16];
+  LSR_HIP(hipMemcpyAsync(dev, j->stats, sizeof(dev), hipMemcpyDeviceToHost, j->stream));
+  LSR_HIP(hipStreamSynchronize(j->stream));
+  int64_t all[LSR_CNT_COUNT];
+  all[LSR_CNT_NODE_UPDATES] = (int64_t)dev[0];
+  all[LSR_CNT_FALLBACKS] = (int64_t)dev[1];
+  all[LSR_CNT_FRAME0] = (int64_t)dev[2];
+  all[LSR_CNT_REINITS] = j->n_reinits;
+  all[LSR_CNT_GBAR] = (int64_t)dev[4];
+  all[LSR_CNT_INTERFACE] = (int64_t)dev[5];
+  all[LSR_CNT_STEPS] = j->n_steps;
+  for (int32_t q = 0; q < n && q < LSR_CNT_COUNT; ++q) out[q] = all[q];
+  return LSR_OK;
+}
+
+lsr_status lsr_profile_enable(lsr_job* j, int32_t enable, int32_t max_launches) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (enable && max_launches < 1) return fail(LSR_E_INVALID, "max_launches must be >= 1");
+  LSR_HIP(hipStreamSynchronize(j->stream));
+  for (hipEvent_t e : j->prof_ev) LSR_HIP(hipEventDestroy(e));
+  j->prof_ev.clear();
+  j->prof_used = 0;
+  j->prof_on = false;
+  if (!enable) return LSR_OK;
+  j->prof_ev.resize(2 * (size_t)max_launches, nullptr);
+  for (auto& e : j->prof_ev) LSR_HIP(hipEventCreate(&e));
+  j->prof_on = true;
+  return LSR_OK;
+}
+
+lsr_status lsr_profile_read(lsr_job* j, double* total_ms, int64_t* launches) {
+  if (!j || !total_ms || !launches) return fail(LSR_E_INVALID, "NULL argument");
+  LSR_HIP(hipStreamSynchronize(j->stream));
+  double tot = 0.0;
+  for (int q = 0; q < j->prof_used; ++q) {
+    float ms = 0.0f;
+    LSR_HIP(hipEventElapsedTime(&ms, j->prof_ev[2 * q], j->prof_ev[2 * q + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = j->prof_used;
+  return LSR_OK;
+}
+
+lsr_status lsr_destroy(lsr_job* j) {
+  if (!j) return LSR_OK;
+  hipError_t e = hipStreamSynchronize(j->stream);
+  for (hipEvent_t ev : j->prof_ev) (void)hipEventDestroy(ev);
+  delete j;
+  if (e != hipSuccess) return fail(LSR_E_DEVICE, hipGetErrorString(e));
+  return LSR_OK;
+}
+
+}  // extern "C"
+
+// Batched execution: filled in by lsr_batch.hip.

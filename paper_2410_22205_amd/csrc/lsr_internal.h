@@ -1,0 +1,107 @@
+// Internal interface between the C-ABI layer (lsr_api.hip) and the kernels
+// (lsr_kernels.hip).  Not installed; the public interface is include/lsr.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lsr_device.h"
+
+namespace lsr {
+
+// Cloud bins: cubes of BIN_W nodes per side.
+constexpr int BIN_W = 4;
+
+struct BinGeom {
+  int nb[3];        // bins per axis (nb[2] = 1 in 2D)
+  double lo[3];     // grid box
+  double hi[3];
+  double bw, inv_bw;
+};
+
+struct SLArgs {
+  DevGrid g;
+  StepConst c;
+  const float* A;   // phi^n (read only)
+  float* B;         // phi^{n+1} (written on the list)
+  const float4* dp; // (grad d, d)
+  const uint32_t* Lin;
+  uint32_t* Lout;
+  const int32_t* cnt_in;
+  int32_t* cnt_out;
+  int32_t* cnt_reset;
+  unsigned long long* stats;
+};
+
+struct DilArgs {
+  DevGrid g;
+  const uint32_t* L;
+  const int32_t* cnt_in;
+  uint32_t* M;
+  int32_t* cnt_out;
+  int32_t* cnt_reset;
+  uint32_t* stamp;
+  uint32_t epoch;
+};
+
+struct RArgs {
+  DevGrid g;
+  StepConst c;
+  const uint32_t* M;
+  const int32_t* cnt;
+  const float* src;
+  float* dst;
+  uint8_t* flags;
+  float dtau;
+  float floor_;
+  unsigned long long* stats;
+};
+
+struct FinArgs {
+  DevGrid g;
+  float gamma;
+  const uint32_t* M;
+  const int32_t* cnt_in;
+  float* cur;
+  float* other;
+  uint32_t* Lout;
+  int32_t* cnt_out;
+  int32_t* cnt_reset;
+};
+
+struct DistArgs {
+  DevGrid g;
+  BinGeom bg;
+  const double* pts;      // sorted by bin, dim doubles per point
+  const int32_t* start;   // bin start offsets, nbins + 1
+  const uint32_t* occ;    // occupied bin ids
+  const int32_t* occ_cnt;
+  double* d64;
+};
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s);
+hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* args, float gamma,
+                           const float* src, float* A, float* B, int32_t* flag, hipStream_t s);
+hipError_t launch_band_scan(int dim, const DevGrid& g, float gamma, const float* A, uint32_t* L,
+                            int32_t* cnt, hipStream_t s);
+hipError_t launch_band_mask(const DevGrid& g, float gamma, const float* A, const uint32_t* L,
+                            const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
+                            hipStream_t s);
+hipError_t launch_sl_step(int dim, int interp, const SLArgs& a, unsigned blocks, hipStream_t s);
+hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s);
+hipError_t launch_reinit_fix(int dim, const RArgs& a, unsigned blocks, hipStream_t s);
+hipError_t launch_reinit_iter(int dim, const RArgs& a, unsigned blocks, hipStream_t s);
+hipError_t launch_reinit_final(const FinArgs& a, unsigned blocks, hipStream_t s);
+hipError_t launch_bin_points(int dim, const BinGeom& bg, const double* pts, int64_t n,
+                             int32_t* bin_count, int32_t* pt_bin, int32_t* flag, hipStream_t s);
+hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start, hipStream_t s);
+hipError_t launch_occupied(const int32_t* start, int32_t nbins, uint32_t* occ, int32_t* cnt,
+                           hipStream_t s);
+hipError_t launch_scatter_points(int dim, const double* pts, int64_t n, const int32_t* pt_bin,
+                                 const int32_t* start, int32_t* fill, double* sorted,
+                                 hipStream_t s);
+hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s);
+hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, float4* dp, hipStream_t s);
+
+}  // namespace lsr

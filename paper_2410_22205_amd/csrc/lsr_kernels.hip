@@ -1,0 +1,790 @@
+// HIP kernels of the narrow-band semi-Lagrangian level-set solver for gfx950
+// (Preda & Semplice, arXiv:2410.22205) and their launchers.
+//
+// Every list kernel is a grid-stride loop over a device-resident list whose
+// length it reads from device memory, so launches have a fixed shape and need
+// no host round trip.  Blocks are remapped so that each of the 8 XCDs walks a
+// contiguous stretch of the list (its own L2 then sees neighbouring nodes).
+// Lists are compacted with a wave-wide ballot, a popcount and one atomic per
+// wave.
+#include "lsr_internal.h"
+
+namespace lsr {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+  // The dispatcher places workgroup b on XCD (b % 8); G is a multiple of 8.
+  return (b % 8u) * (G / 8u) + (b / 8u);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Append val for every lane with pred set; called by all 64 lanes of a wave.
+__device__ __forceinline__ void wave_append(bool pred, uint32_t val, uint32_t* __restrict__ out,
+                                            int32_t* __restrict__ counter) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return;
+  int base = 0;
+  if (lane_id() == 0) base = atomicAdd(counter, (int)__popcll(m));
+  base = __shfl(base, 0);
+  if (pred) out[base + (int)lanes_below(m)] = val;
+}
+
+__device__ __forceinline__ uint32_t wave_count(bool pred) { return (uint32_t)__popcll(__ballot(pred)); }
+
+__device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
+  if (v) atomicAdd(p, (unsigned long long)v);
+}
+
+// ------------------------------------------------------------------ fills
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, uint64_t n) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// ------------------------------------------------------------- init / band
+
+// Closed-form signed distance (computed in double, stored in float) or a
+// copy of the caller's array, cut to [-gamma, gamma]; written to both phi
+// buffers (A == NULL: only check the array).  flag[0] |= 1 for a non-finite
+// input value.
+template <int DIM>
+__global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2, double a3,
+                           double a4, float gamma, const float* __restrict__ src,
+                           float* __restrict__ A, float* __restrict__ B, int32_t* flag) {
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.N;
+       idx += gridDim.x * blockDim.x) {
+    float v;
+    if (kind == 0) {
+      v = src[idx];
+      if (!isfinite(v)) atomicOr(flag, 1);
+    } else {
+      uint32_t r = idx;
+      int k = 0;
+      if (DIM == 3) {
+        k = (int)(r % (uint32_t)g.n2);
+        r /= (uint32_t)g.n2;
+      }
+      int j = (int)(r % (uint32_t)g.n1);
+      int i = (int)(r / (uint32_t)g.n1);
+      double x = g.lo0 + i * g.hd - a0, y = g.lo1 + j * g.hd - a1;
+      double z = DIM == 3 ? g.lo2 + k * g.hd - a2 : 0.0;
+      double s;
+      if (kind == 1) {
+        s = sqrt(x * x + y * y + z * z) - a3;
+      } else {
+        double rho = sqrt(x * x + y * y) - a3;
+        s = sqrt(rho * rho + z * z) - a4;
+      }
+      v = (float)s;
+    }
+    if (!A) continue;  // check-only pass over the caller's array
+    v = fminf(fmaxf(v, -gamma), gamma);
+    A[idx] = v;
+    B[idx] = v;
+  }
+}
+
+// First band {|phi| < gamma} from a scan of the whole grid.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_band_scan(DevGrid g, float gamma,
+                                                   const float* __restrict__ A,
+                                                   uint32_t* __restrict__ L, int32_t* cnt) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < g.N; base += stride) {
+    const uint32_t idx = base + lane_id();
+    bool in = false;
+    uint32_t code = 0;
+    if (idx < g.N) {
+      in = fabsf(A[idx]) < gamma;
+      uint32_t r = idx;
+      int k = 0;
+      if (DIM == 3) {
+        k = (int)(r % (uint32_t)g.n2);
+        r /= (uint32_t)g.n2;
+      }
+      code = encode(g, (int)(r / (uint32_t)g.n1), (int)(r % (uint32_t)g.n1), k);
+    }
+    wave_append(in, code, L, cnt);
+  }
+}
+
+// Band mask of the current list: mask[idx] = 1 iff |phi| < gamma.
+__global__ __launch_bounds__(256) void k_band_mask(DevGrid g, float gamma,
+                                                   const float* __restrict__ A,
+                                                   const uint32_t* __restrict__ L,
+                                                   const int32_t* cnt, uint8_t* __restrict__ mask,
+                                                   int32_t* count) {
+  const int n = *cnt;
+  uint32_t tot = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < (uint32_t)n;
+       base += stride) {
+    const uint32_t e = base + lane_id();
+    bool in = false;
+    if (e < (uint32_t)n) {
+      int i, j, k;
+      decode(g, L[e], i, j, k);
+      const uint32_t idx = lin(g, i, j, k);
+      in = fabsf(A[idx]) < gamma;
+      if (in && mask) mask[idx] = 1;
+    }
+    tot += wave_count(in);
+  }
+  if (lane_id() == 0 && tot) atomicAdd(count, (int)tot);
+}
+
+// ---------------------------------------------------------- the SL step
+
+// One time step over the current list: entries with |phi^n| < gamma get the
+// update of eqs. (SL2d)/(SL3d) written to B; entries that left the band in
+// the previous step get their value copied, so that A and B agree off the
+// new list.  The new list is the set of entries updated here (the band of
+// this step).  cnt_reset is the list counter the next step will write.
+template <int DIM, int INTERP>
+__global__ __launch_bounds__(256) void k_sl_step(SLArgs a) {
+  const int n = *a.cnt_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  uint32_t nupd = 0, nfb = 0, nfr = 0;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
+    const uint32_t e = base + lane_id();
+    bool act = false;
+    int fl = 0;
+    uint32_t code = 0;
+    if (e < (uint32_t)n) {
+      code = a.Lin[e];
+      int i, j, k;
+      decode(a.g, code, i, j, k);
+      const uint32_t idx = lin(a.g, i, j, k);
+      const float v = a.A[idx];
+      float nv = v;
+      if (fabsf(v) < a.c.gamma) {
+        act = true;
+        nv = sl_update<DIM, INTERP>(a.A, a.g, a.c, i, j, k, idx, v, a.dp[idx], fl);
+      }
+      a.B[idx] = nv;
+    }
+    wave_append(act, code, a.Lout, a.cnt_out);
+    nupd += wave_count(act);
+    nfb += wave_count(fl & UPD_FALLBACK);
+    nfr += wave_count(fl & UPD_FRAME0);
+  }
+  if (lane_id() == 0) {
+    add_stat(&a.stats[0], nupd);
+    add_stat(&a.stats[1], nfb);
+    add_stat(&a.stats[2], nfr);
+  }
+}
+
+// ------------------------------------------------------- reinitialisation
+
+// Gbar = band + face neighbours, deduplicated through a per-node stamp.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
+  const int n = *a.cnt_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
+    const uint32_t e = base + lane_id();
+    const bool valid = e < (uint32_t)n;
+    int i = 0, j = 0, k = 0;
+    if (valid) decode(a.g, a.L[e], i, j, k);
+#pragma unroll
+    for (int q = 0; q < 1 + 2 * DIM; ++q) {
+      int ii = i + (q == 1 ? -1 : q == 2 ? 1 : 0);
+      int jj = j + (q == 3 ? -1 : q == 4 ? 1 : 0);
+      int kk = k + (q == 5 ? -1 : q == 6 ? 1 : 0);
+      bool ins = false;
+      uint32_t code = 0;
+      if (valid && ii >= 0 && ii < a.g.n0 && jj >= 0 && jj < a.g.n1 && kk >= 0 && kk < a.g.n2) {
+        const uint32_t old = atomicMax(&a.stamp[lin(a.g, ii, jj, kk)], a.epoch);
+        ins = old < a.epoch;
+        code = encode(a.g, ii, jj, kk);
+      }
+      wave_append(ins, code, a.M, a.cnt_out);
+    }
+  }
+}
+
+// Interface set and one-step fix on Gbar.  Reads phi~ from T, writes the
+// working copy W: W = phi~ / max(|grad_c phi~|, floor) on interface nodes
+// (a face neighbour of opposite or zero sign), W = phi~ elsewhere on Gbar.
+// flags: bit 7 interface, bits 0-1 sign of phi~ (1 positive, 2 negative).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_reinit_fix(RArgs a) {
+  const int n = *a.cnt;
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t stride = gridDim.x * 256u;
+  uint32_t nif = 0, ng = 0;
+  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
+    const uint32_t e = base + lane_id();
+    bool itf = false;
+    const bool valid = e < (uint32_t)n;
+    if (valid) {
+      int i, j, k;
+      decode(a.g, a.M[e], i, j, k);
+      const uint32_t idx = lin(a.g, i, j, k);
+      const float t = a.src[idx];
+      const float xm = i > 0 ? a.src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? a.src[idx + a.g.s0] : t;
+      const float ym = j > 0 ? a.src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? a.src[idx + a.g.s1] : t;
+      float zm = t, zp = t;
+      if (DIM == 3) {
+        zm = k > 0 ? a.src[idx - 1] : t;
+        zp = k < a.g.n2 - 1 ? a.src[idx + 1] : t;
+      }
+      itf = (i > 0 && t * xm <= 0.0f) || (i < a.g.n0 - 1 && t * xp <= 0.0f) ||
+            (j > 0 && t * ym <= 0.0f) || (j < a.g.n1 - 1 && t * yp <= 0.0f);
+      if (DIM == 3) itf = itf || (k > 0 && t * zm <= 0.0f) || (k < a.g.n2 - 1 && t * zp <= 0.0f);
+      float w = t;
+      if (itf) {
+        const float gx = cdiff(xm, t, xp, i, a.g.n0, a.c);
+        const float gy = cdiff(ym, t, yp, j, a.g.n1, a.c);
+        const float gz = DIM == 3 ? cdiff(zm, t, zp, k, a.g.n2, a.c) : 0.0f;
+        const float nr = fmaxf(sqrtf(gx * gx + gy * gy + gz * gz), a.floor_);
+        w = t / nr;
+      }
+      a.dst[idx] = w;
+      a.flags[e] = (uint8_t)((itf ? 0x80 : 0) | (t > 0.0f ? 1 : (t < 0.0f ? 2 : 0)));
+    }
+    nif += wave_count(itf);
+    ng += wave_count(valid);
+  }
+  if (lane_id() == 0) {
+    add_stat(&a.stats[4], ng);
+    add_stat(&a.stats[5], nif);
+  }
+}
+
+// One forward-Euler pseudo-time step of phi_tau + S (|grad phi| - 1) = 0 on
+// Gbar minus the interface set, first-order upwind (Godunov) gradient; a
+// missing neighbour contributes no difference.  src -> dst on Gbar.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_reinit_iter(RArgs a) {
+  const int n = *a.cnt;
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
+    const uint32_t e = base + lane_id();
+    if (e >= (uint32_t)n) continue;
+    int i, j, k;
+    decode(a.g, a.M[e], i, j, k);
+    const uint32_t idx = lin(a.g, i, j, k);
+    const uint8_t f = a.flags[e];
+    float v = a.src[idx];
+    if (!(f & 0x80) && (f & 3)) {
+      const bool pos = f & 1;
+      float G2 = 0.0f;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        const int ci = ax == 0 ? i : (ax == 1 ? j : k);
+        const int nn = ax == 0 ? a.g.n0 : (ax == 1 ? a.g.n1 : a.g.n2);
+        const uint32_t s = ax == 0 ? a.g.s0 : (ax == 1 ? a.g.s1 : 1u);
+        const float Dm = ci > 0 ? (v - a.src[idx - s]) * a.c.inv_h : 0.0f;
+        const float Dp = ci < nn - 1 ? (a.src[idx + s] - v) * a.c.inv_h : 0.0f;
+        float t1, t2;
+        if (pos) {
+          t1 = Dm > 0.0f ? Dm * Dm : 0.0f;
+          t2 = Dp < 0.0f ? Dp * Dp : 0.0f;
+        } else {
+          t1 = Dm < 0.0f ? Dm * Dm : 0.0f;
+          t2 = Dp > 0.0f ? Dp * Dp : 0.0f;
+        }
+        G2 += fmaxf(t1, t2);
+      }
+      const float S = pos ? 1.0f : -1.0f;
+      v = v - a.dtau * S * (sqrtf(G2) - 1.0f);
+    }
+    a.dst[idx] = v;
+  }
+}
+
+// Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
+__global__ __launch_bounds__(256) void k_reinit_final(FinArgs a) {
+  const int n = *a.cnt_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
+    const uint32_t e = base + lane_id();
+    bool in = false;
+    uint32_t code = 0;
+    if (e < (uint32_t)n) {
+      code = a.M[e];
+      int i, j, k;
+      decode(a.g, code, i, j, k);
+      const uint32_t idx = lin(a.g, i, j, k);
+      const float v = fminf(fmaxf(a.cur[idx], -a.gamma), a.gamma);
+      a.cur[idx] = v;
+      a.other[idx] = v;
+      in = fabsf(v) < a.gamma;
+    }
+    wave_append(in, code, a.Lout, a.cnt_out);
+  }
+}
+
+// ------------------------------------------------------------ distance
+
+// Validate and bin the cloud: bins are cubes of BIN_W nodes; flag |= 1 for a
+// non-finite point or one outside the grid's box.
+template <int DIM>
+__global__ void k_bin_points(BinGeom bg, const double* __restrict__ pts, int64_t n,
+                             int32_t* __restrict__ bin_count, int32_t* __restrict__ pt_bin,
+                             int32_t* flag) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    bool ok = true;
+    int b[3] = {0, 0, 0};
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const double x = pts[p * DIM + ax];
+      const double lo = bg.lo[ax], hi = bg.hi[ax];
+      if (!(x >= lo && x <= hi)) ok = false;  // also false for NaN
+      int q = ok ? (int)floor((x - lo) * bg.inv_bw) : 0;
+      b[ax] = q < 0 ? 0 : (q > bg.nb[ax] - 1 ? bg.nb[ax] - 1 : q);
+    }
+    if (!ok) {
+      atomicOr(flag, 1);
+      pt_bin[p] = -1;
+      continue;
+    }
+    const int id = (b[0] * bg.nb[1] + b[1]) * bg.nb[2] + b[2];
+    atomicAdd(&bin_count[id], 1);
+    pt_bin[p] = id;
+  }
+}
+
+// Exclusive scan of the bin counts (one block, 1024 threads, contiguous
+// segments per thread).  start has nbins + 1 entries.
+__global__ __launch_bounds__(1024) void k_scan_bins(const int32_t* __restrict__ count,
+                                                    int32_t nbins, int32_t* __restrict__ start) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int seg = (nbins + 1023) / 1024;
+  const int b0 = t * seg, b1 = min(b0 + seg, nbins);
+  int32_t s = 0;
+  for (int b = b0; b < b1; ++b) s += count[b];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - s;
+  for (int b = b0; b < b1; ++b) {
+    start[b] = run;
+    run += count[b];
+  }
+  if (t == 1023) start[nbins] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_occupied(const int32_t* __restrict__ start, int32_t nbins,
+                                                  uint32_t* __restrict__ occ, int32_t* cnt) {
+  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < (uint32_t)nbins;
+       base += gridDim.x * blockDim.x) {
+    const uint32_t b = base + lane_id();
+    const bool nz = b < (uint32_t)nbins && start[b + 1] > start[b];
+    wave_append(nz, b, occ, cnt);
+  }
+}
+
+template <int DIM>
+__global__ void k_scatter_points(const double* __restrict__ pts, int64_t n,
+                                 const int32_t* __restrict__ pt_bin,
+                                 const int32_t* __restrict__ start, int32_t* __restrict__ fill,
+                                 double* __restrict__ sorted) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int b = pt_bin[p];
+    if (b < 0) continue;
+    const int slot = start[b] + atomicAdd(&fill[b], 1);
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) sorted[(int64_t)slot * DIM + ax] = pts[p * DIM + ax];
+  }
+}
+
+__device__ __forceinline__ double block_min(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = fmin(r, red[q]);
+  return r;
+}
+
+template <int DIM>
+__device__ __forceinline__ void bin_box(const BinGeom& bg, uint32_t id, double lo[3], double hi[3]) {
+  int b2 = (int)(id % (uint32_t)bg.nb[2]);
+  uint32_t r = id / (uint32_t)bg.nb[2];
+  int b1 = (int)(r % (uint32_t)bg.nb[1]);
+  int b0 = (int)(r / (uint32_t)bg.nb[1]);
+  const int bb[3] = {b0, b1, b2};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    lo[ax] = bg.lo[ax] + bb[ax] * bg.bw;
+    hi[ax] = lo[ax] + bg.bw;
+  }
+}
+
+// Exact distance to the cloud at the nodes of one brick (8^3 nodes in 3D,
+// 16^2 in 2D) per workgroup.  With c the brick centre, rho its half diagonal
+// and U = d(c), every node's nearest point lies within U + 2 rho of c; U is
+// found exactly from the occupied bins whose box can hold a point closer
+// than the best far-corner bound, then the nodes scan all points of the
+// occupied bins whose box meets the ball of radius U + 2 rho.  All distance
+// arithmetic in double.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_distance(DistArgs a) {
+  constexpr int BS = DIM == 3 ? 8 : 16;
+  constexpr int NPT = DIM == 3 ? 2 : 1;
+  constexpr int CAP = 6144;
+  __shared__ double red[4];
+  __shared__ uint32_t cand[CAP];
+  __shared__ int ncand;
+  const DevGrid& g = a.g;
+  const int nbx = (g.n0 + BS - 1) / BS, nby = (g.n1 + BS - 1) / BS;
+  const int nbz = DIM == 3 ? (g.n2 + BS - 1) / BS : 1;
+  int b = blockIdx.x;
+  const int bz = b % nbz;
+  b /= nbz;
+  const int by = b % nby, bx = b / nby;
+  if (bx >= nbx) return;
+  const int f[3] = {bx * BS, by * BS, DIM == 3 ? bz * BS : 0};
+  const int l[3] = {min(f[0] + BS, g.n0) - 1, min(f[1] + BS, g.n1) - 1,
+                    DIM == 3 ? min(f[2] + BS, g.n2) - 1 : 0};
+  const double glo[3] = {g.lo0, g.lo1, g.lo2};
+  double c[3], rho2 = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    c[ax] = ax < DIM ? glo[ax] + g.hd * 0.5 * (f[ax] + l[ax]) : 0.0;
+    const double e = 0.5 * g.hd * (l[ax] - f[ax]);
+    rho2 += e * e;
+  }
+  const double rho = sqrt(rho2);
+  const int nocc = *a.occ_cnt;
+  const double slack = 1.0 + 1e-12;
+
+  // far-corner bound: every occupied box holds a point no farther than it
+  double ub2 = INFINITY;
+  for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
+    double lo[3], hi[3];
+    bin_box<DIM>(a.bg, a.occ[t], lo, hi);
+    double s = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const double q = fmax(fabs(c[ax] - lo[ax]), fabs(c[ax] - hi[ax]));
+      s += q * q;
+    }
+    ub2 = fmin(ub2, s);
+  }
+  ub2 = block_min(ub2, red) * slack;
+
+  // exact d(c)^2
+  double best = INFINITY;
+  for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
+    const uint32_t id = a.occ[t];
+    double lo[3], hi[3];
+    bin_box<DIM>(a.bg, id, lo, hi);
+    double s = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
+      s += q * q;
+    }
+    if (s > ub2) continue;
+    for (int q = a.start[id]; q < a.start[id + 1]; ++q) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        const double t2 = a.pts[(int64_t)q * DIM + ax] - c[ax];
+        s2 += t2 * t2;
+      }
+      best = fmin(best, s2);
+    }
+  }
+  best = block_min(best, red);
+  const double R = sqrt(best) + 2.0 * rho;
+  const double R2 = R * R * slack;
+
+  // occupied bins whose box meets the ball (c, R)
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
+    const uint32_t id = a.occ[t];
+    double lo[3], hi[3];
+    bin_box<DIM>(a.bg, id, lo, hi);
+    double s = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
+      s += q * q;
+    }
+    if (s <= R2) {
+      const int pos = atomicAdd(&ncand, 1);
+      if (pos < CAP) cand[pos] = id;
+    }
+  }
+  __syncthreads();
+  const int nc = ncand;
+
+  double x[NPT][3], bn[NPT];
+  bool valid[NPT];
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) {
+    const int t = threadIdx.x + u * 256;
+    int li, lj, lk;
+    if (DIM == 3) {
+      li = t >> 6; lj = (t >> 3) & 7; lk = t & 7;
+    } else {
+      li = t >> 4; lj = t & 15; lk = 0;
+    }
+    const int node[3] = {f[0] + li, f[1] + lj, f[2] + lk};
+    valid[u] = node[0] <= l[0] && node[1] <= l[1] && node[2] <= l[2];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) x[u][ax] = ax < DIM ? glo[ax] + node[ax] * g.hd : 0.0;
+    bn[u] = INFINITY;
+  }
+  const int nloop = nc <= CAP ? nc : nocc;
+  for (int q = 0; q < nloop; ++q) {
+    uint32_t id;
+    if (nc <= CAP) {
+      id = cand[q];
+    } else {
+      id = a.occ[q];
+      double lo[3], hi[3];
+      bin_box<DIM>(a.bg, id, lo, hi);
+      double s = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        const double w = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
+        s += w * w;
+      }
+      if (s > R2) continue;
+    }
+    const int p1 = a.start[id + 1];
+    for (int p = a.start[id]; p < p1; ++p) {
+      double Q[3];
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) Q[ax] = a.pts[(int64_t)p * DIM + ax];
+#pragma unroll
+      for (int u = 0; u < NPT; ++u) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+          const double t2 = x[u][ax] - Q[ax];
+          s2 = fma(t2, t2, s2);
+        }
+        bn[u] = fmin(bn[u], s2);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) {
+    if (!valid[u]) continue;
+    const int t = threadIdx.x + u * 256;
+    int li, lj, lk;
+    if (DIM == 3) {
+      li = t >> 6; lj = (t >> 3) & 7; lk = t & 7;
+    } else {
+      li = t >> 4; lj = t & 15; lk = 0;
+    }
+    a.d64[lin(g, f[0] + li, f[1] + lj, f[2] + lk)] = sqrt(bn[u]);
+  }
+}
+
+// Centred gradient of d (one-sided on the boundary), in double, packed with
+// d itself: dp = (d_x, d_y, d_z, d) as floats (d_z = 0 in 2D).
+template <int DIM>
+__global__ void k_dpack(DevGrid g, const double* __restrict__ d, float4* __restrict__ dp) {
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.N;
+       idx += gridDim.x * blockDim.x) {
+    uint32_t r = idx;
+    int k = 0;
+    if (DIM == 3) {
+      k = (int)(r % (uint32_t)g.n2);
+      r /= (uint32_t)g.n2;
+    }
+    const int j = (int)(r % (uint32_t)g.n1), i = (int)(r / (uint32_t)g.n1);
+    const int ci[3] = {i, j, k};
+    const int nn[3] = {g.n0, g.n1, g.n2};
+    const uint32_t st[3] = {g.s0, g.s1, 1u};
+    const double v = d[idx];
+    double gr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const bool hm = ci[ax] > 0, hp = ci[ax] < nn[ax] - 1;
+      if (hm && hp)
+        gr[ax] = (d[idx + st[ax]] - d[idx - st[ax]]) / (2.0 * g.hd);
+      else if (hp)
+        gr[ax] = (d[idx + st[ax]] - v) / g.hd;
+      else
+        gr[ax] = (v - d[idx - st[ax]]) / g.hd;
+    }
+    dp[idx] = make_float4((float)gr[0], (float)gr[1], (float)gr[2], (float)v);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
+  uint64_t b = (n + block - 1) / block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* args, float gamma,
+                           const float* src, float* A, float* B, int32_t* flag, hipStream_t s) {
+  dim3 gr(grid_for(g.N, 256, 8192)), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_init_phi<3>, gr, bl, 0, s, g, kind, args[0], args[1], args[2], args[3],
+                       args[4], gamma, src, A, B, flag);
+  else
+    hipLaunchKernelGGL(k_init_phi<2>, gr, bl, 0, s, g, kind, args[0], args[1], args[2], args[3],
+                       args[4], gamma, src, A, B, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_scan(int dim, const DevGrid& g, float gamma, const float* A, uint32_t* L,
+                            int32_t* cnt, hipStream_t s) {
+  dim3 gr(grid_for(g.N, 256, 8192)), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_band_scan<3>, gr, bl, 0, s, g, gamma, A, L, cnt);
+  else
+    hipLaunchKernelGGL(k_band_scan<2>, gr, bl, 0, s, g, gamma, A, L, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_mask(const DevGrid& g, float gamma, const float* A, const uint32_t* L,
+                            const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_band_mask, dim3(blocks), dim3(256), 0, s, g, gamma, A, L, cnt, mask, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_sl_step(int dim, int interp, const SLArgs& a, unsigned blocks, hipStream_t s) {
+  dim3 gr(blocks), bl(256);
+  if (dim == 3) {
+    if (interp == 0)
+      hipLaunchKernelGGL((k_sl_step<3, 0>), gr, bl, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_sl_step<3, 1>), gr, bl, 0, s, a);
+  } else {
+    if (interp == 0)
+      hipLaunchKernelGGL((k_sl_step<2, 0>), gr, bl, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_sl_step<2, 1>), gr, bl, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_dilate<3>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_dilate<2>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reinit_fix(int dim, const RArgs& a, unsigned blocks, hipStream_t s) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_reinit_fix<3>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_reinit_fix<2>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reinit_iter(int dim, const RArgs& a, unsigned blocks, hipStream_t s) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_reinit_iter<3>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_reinit_iter<2>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reinit_final(const FinArgs& a, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_reinit_final, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_points(int dim, const BinGeom& bg, const double* pts, int64_t n,
+                             int32_t* bin_count, int32_t* pt_bin, int32_t* flag, hipStream_t s) {
+  dim3 gr(grid_for((uint64_t)n, 256, 4096)), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_bin_points<3>, gr, bl, 0, s, bg, pts, n, bin_count, pt_bin, flag);
+  else
+    hipLaunchKernelGGL(k_bin_points<2>, gr, bl, 0, s, bg, pts, n, bin_count, pt_bin, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, count, nbins, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_occupied(const int32_t* start, int32_t nbins, uint32_t* occ, int32_t* cnt,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_occupied, dim3(grid_for((uint64_t)nbins, 256, 4096)), dim3(256), 0, s,
+                     start, nbins, occ, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_points(int dim, const double* pts, int64_t n, const int32_t* pt_bin,
+                                 const int32_t* start, int32_t* fill, double* sorted,
+                                 hipStream_t s) {
+  dim3 gr(grid_for((uint64_t)n, 256, 4096)), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_scatter_points<3>, gr, bl, 0, s, pts, n, pt_bin, start, fill, sorted);
+  else
+    hipLaunchKernelGGL(k_scatter_points<2>, gr, bl, 0, s, pts, n, pt_bin, start, fill, sorted);
+  return hipGetLastError();
+}
+
+hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_distance<3>, dim3(bricks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_distance<2>, dim3(bricks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, float4* dp, hipStream_t s) {
+  dim3 gr(grid_for(g.N, 256, 8192)), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_dpack<3>, gr, bl, 0, s, g, d, dp);
+  else
+    hipLaunchKernelGGL(k_dpack<2>, gr, bl, 0, s, g, d, dp);
+  return hipGetLastError();
+}
+
+}  // namespace lsr

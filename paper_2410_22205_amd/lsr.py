@@ -1,0 +1,297 @@
+"""ctypes binding of ``include/lsr.h`` (liblsr.so, the HIP library).
+
+The ``lsr_*`` functions mirror the C entry points one to one and only
+marshal arguments; every step of the solver runs in the library's kernels.
+:class:`Job` is a convenience owner of a job: it allocates the workspace as a
+torch uint8 tensor, passes torch's current HIP stream and converts inputs and
+outputs.  PyTorch is used for device memory and streams only.
+
+There is no CPU fallback: if the library is missing, importing the binding
+works but the first call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblsr.so")
+
+LSR_OK, LSR_E_INVALID, LSR_E_NOMEM, LSR_E_DEVICE, LSR_E_STATE, LSR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+LSR_Q1, LSR_WENO = 0, 1
+LSR_PHI_ARRAY, LSR_PHI_SPHERE, LSR_PHI_TORUS = 0, 1, 2
+COUNTER_NAMES = ["node_updates", "fallbacks", "frame0", "reinits", "gbar", "interface", "steps"]
+
+EXPORTED = [
+    "lsr_params_default", "lsr_workspace_bytes", "lsr_create", "lsr_load_cloud",
+    "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
+    "lsr_extract", "lsr_counters", "lsr_destroy", "lsr_batch_create", "lsr_batch_step",
+    "lsr_batch_destroy", "lsr_profile_enable", "lsr_profile_read", "lsr_last_error",
+]
+
+
+class LsrGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
+                ("lo", ctypes.c_double * 3), ("h", ctypes.c_double)]
+
+
+class LsrParams(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double), ("delta", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
+                ("grad_C", ctypes.c_double), ("grad_alpha", ctypes.c_double),
+                ("reinit_every", ctypes.c_int32), ("reinit_iters", ctypes.c_int32),
+                ("reinit_dtau", ctypes.c_double), ("interface_floor", ctypes.c_double)]
+
+
+class LsrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lsr status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def load():
+    """Open liblsr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        GP, PP = ctypes.POINTER(LsrGrid), ctypes.POINTER(LsrParams)
+        I64P = ctypes.POINTER(ctypes.c_int64)
+        sig = {
+            "lsr_params_default": [ctypes.c_int32, ctypes.c_double, PP],
+            "lsr_workspace_bytes": [GP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+            "lsr_create": [GP, PP, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+            "lsr_load_cloud": [_P, _P, ctypes.c_int64],
+            "lsr_set_distance": [_P, _P],
+            "lsr_get_distance": [_P, _P],
+            "lsr_init_phi": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int64],
+            "lsr_step": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int],
+            "lsr_reinit": [_P],
+            "lsr_extract": [_P, _P, _P, I64P, I64P],
+            "lsr_counters": [_P, I64P, ctypes.c_int32],
+            "lsr_destroy": [_P],
+            "lsr_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_P)],
+            "lsr_batch_step": [_P, ctypes.c_int32],
+            "lsr_profile_enable": [_P, ctypes.c_int32, ctypes.c_int32],
+            "lsr_profile_read": [_P, ctypes.POINTER(ctypes.c_double), I64P],
+            "lsr_batch_destroy": [_P],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.lsr_last_error.argtypes = []
+        lib.lsr_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def lsr_last_error():
+    return load().lsr_last_error().decode()
+
+
+def _check(status):
+    if status != LSR_OK:
+        raise LsrError(status, lsr_last_error())
+
+
+def make_grid(grid):
+    g = LsrGrid()
+    g.dim = int(grid["dim"])
+    n = list(grid["n"]) + [1] * (3 - len(grid["n"]))
+    lo = list(grid["lo"]) + [0.0] * (3 - len(grid["lo"]))
+    for a in range(3):
+        g.n[a] = int(n[a])
+        g.lo[a] = float(lo[a])
+    g.h = float(grid["h"])
+    return g
+
+
+# ------------------------------------------------------- C entry points
+
+def lsr_params_default(dim, h):
+    p = LsrParams()
+    _check(load().lsr_params_default(int(dim), float(h), ctypes.byref(p)))
+    return p
+
+
+def lsr_workspace_bytes(grid, max_points):
+    out = ctypes.c_size_t()
+    _check(load().lsr_workspace_bytes(ctypes.byref(grid), int(max_points), ctypes.byref(out)))
+    return out.value
+
+
+def lsr_create(grid, params, ws_ptr, ws_bytes, stream_ptr):
+    h = _P()
+    _check(load().lsr_create(ctypes.byref(grid), ctypes.byref(params), _P(ws_ptr), int(ws_bytes),
+                             _P(stream_ptr), ctypes.byref(h)))
+    return h
+
+
+def lsr_load_cloud(job, xyz_ptr, n):
+    _check(load().lsr_load_cloud(job, _P(xyz_ptr), int(n)))
+
+
+def lsr_set_distance(job, d_ptr):
+    _check(load().lsr_set_distance(job, _P(d_ptr)))
+
+
+def lsr_get_distance(job, out_ptr):
+    _check(load().lsr_get_distance(job, _P(out_ptr)))
+
+
+def lsr_init_phi(job, phi_ptr, kind, args, step0):
+    a = (ctypes.c_double * 8)(*([float(x) for x in (args or [])] + [0.0] * (8 - len(args or []))))
+    _check(load().lsr_init_phi(job, _P(phi_ptr) if phi_ptr else None, int(kind), a, int(step0)))
+
+
+def lsr_step(job, n_steps, dt, interp):
+    _check(load().lsr_step(job, int(n_steps), float(dt), int(interp)))
+
+
+def lsr_reinit(job):
+    _check(load().lsr_reinit(job))
+
+
+def lsr_extract(job, phi_ptr, band_ptr, want_count=True):
+    nb = ctypes.c_int64(-1)
+    si = ctypes.c_int64(-1)
+    _check(load().lsr_extract(job, _P(phi_ptr) if phi_ptr else None,
+                              _P(band_ptr) if band_ptr else None,
+                              ctypes.byref(nb) if want_count else None, ctypes.byref(si)))
+    return nb.value, si.value
+
+
+def lsr_counters(job):
+    out = (ctypes.c_int64 * len(COUNTER_NAMES))()
+    _check(load().lsr_counters(job, out, len(COUNTER_NAMES)))
+    return dict(zip(COUNTER_NAMES, list(out)))
+
+
+def lsr_destroy(job):
+    _check(load().lsr_destroy(job))
+
+
+def lsr_batch_create(jobs, dts, interps):
+    n = len(jobs)
+    arr = (_P * n)(*[j.value if isinstance(j, _P) else j for j in jobs])
+    dt = (ctypes.c_double * n)(*[float(x) for x in dts])
+    it = (ctypes.c_int32 * n)(*[int(x) for x in interps])
+    h = _P()
+    _check(load().lsr_batch_create(arr, n, dt, it, ctypes.byref(h)))
+    return h
+
+
+def lsr_batch_step(batch, n_steps):
+    _check(load().lsr_batch_step(batch, int(n_steps)))
+
+
+def lsr_batch_destroy(batch):
+    _check(load().lsr_batch_destroy(batch))
+
+
+def lsr_profile_enable(job, enable, max_launches=4096):
+    _check(load().lsr_profile_enable(job, int(bool(enable)), int(max_launches)))
+
+
+def lsr_profile_read(job):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().lsr_profile_read(job, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ------------------------------------------------------------ convenience
+
+def interp_code(name):
+    return {"q1": LSR_Q1, "weno": LSR_WENO}[name]
+
+
+class Job:
+    """One reconstruction on the current device.
+
+    grid: {"dim", "n", "lo", "h"}; params: overrides of lsr_params_default;
+    max_points: largest cloud to be loaded; stream: a torch.cuda.Stream
+    (default: the current stream)."""
+
+    def __init__(self, grid, params=None, max_points=0, stream=None):
+        import torch
+        self.torch = torch
+        self.grid_dict = dict(grid)
+        self.grid = make_grid(grid)
+        self.params = lsr_params_default(self.grid.dim, self.grid.h)
+        for k, v in (params or {}).items():
+            setattr(self.params, k, v)
+        self.shape = tuple(int(v) for v in grid["n"][: self.grid.dim])
+        self.nodes = int(np.prod(self.shape))
+        self.ws_bytes = lsr_workspace_bytes(self.grid, max_points)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.stream.device)
+        self.handle = lsr_create(self.grid, self.params, self.ws.data_ptr(), self.ws_bytes,
+                                 self.stream.cuda_stream)
+
+    def _dev(self, x, dtype):
+        t = self.torch.as_tensor(np.ascontiguousarray(x) if isinstance(x, np.ndarray) else x)
+        return t.to(device=self.stream.device, dtype=dtype).contiguous()
+
+    def load_cloud(self, points):
+        pts = self._dev(points, self.torch.float64)
+        with self.torch.cuda.stream(self.stream):
+            lsr_load_cloud(self.handle, pts.data_ptr(), pts.shape[0])
+
+    def set_distance(self, d):
+        dd = self._dev(d, self.torch.float64)
+        self._keep = dd
+        lsr_set_distance(self.handle, dd.data_ptr())
+
+    def distance(self):
+        out = self.torch.empty(self.nodes, dtype=self.torch.float32, device=self.stream.device)
+        lsr_get_distance(self.handle, out.data_ptr())
+        self.stream.synchronize()
+        return out.cpu().numpy().reshape(self.shape)
+
+    def init_phi(self, kind="sphere", args=(), phi0=None, step0=0):
+        if phi0 is not None:
+            t = self._dev(phi0, self.torch.float32)
+            self._keep = t
+            lsr_init_phi(self.handle, t.data_ptr(), LSR_PHI_ARRAY, [], step0)
+        else:
+            k = {"sphere": LSR_PHI_SPHERE, "torus": LSR_PHI_TORUS}[kind]
+            lsr_init_phi(self.handle, None, k, list(args), step0)
+
+    def step(self, n_steps, dt, interp):
+        lsr_step(self.handle, n_steps, dt, interp_code(interp) if isinstance(interp, str) else interp)
+
+    def reinit(self):
+        lsr_reinit(self.handle)
+
+    def extract_device(self):
+        phi = self.torch.empty(self.nodes, dtype=self.torch.float32, device=self.stream.device)
+        band = self.torch.empty(self.nodes, dtype=self.torch.uint8, device=self.stream.device)
+        nb, si = lsr_extract(self.handle, phi.data_ptr(), band.data_ptr(), want_count=True)
+        return phi.view(self.shape), band.view(self.shape), nb, si
+
+    def extract(self):
+        phi, band, nb, si = self.extract_device()
+        self.stream.synchronize()
+        return phi.cpu().numpy(), band.cpu().numpy(), nb, si
+
+    def counters(self):
+        return lsr_counters(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lsr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

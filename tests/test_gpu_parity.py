@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances: the distance field within one float ulp of the exact value;
+one step within 1e-5 h; whole runs within 1e-4 h (max |phi_gpu - phi_oracle|);
+band membership bit-exact except for nodes whose oracle value lies within
+1e-6 h of the band threshold gamma.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _lsr():
+    from paper_2410_22205_amd import lsr
+    return lsr
+
+
+def gpu_run(w, steps=None, d=None, step0=0, extra=None):
+    lsr = _lsr()
+    prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"])
+    prm.update(extra or {})
+    job = lsr.Job(w["grid"], prm, max_points=len(w["points"]))
+    if d is None:
+        job.load_cloud(w["points"])
+    else:
+        job.set_distance(d)
+    if w["phi0"][0] == "array":
+        job.init_phi(phi0=w["phi0"][1], step0=step0)
+    else:
+        job.init_phi(w["phi0"][0], w["phi0"][1], step0=step0)
+    n = w["steps"] if steps is None else steps
+    if n:
+        job.step(n, w["dt"], w["interp"])
+    phi, band, nb, si = job.extract()
+    cnt = job.counters()
+    dgpu = job.distance()
+    job.close()
+    return phi, band, nb, si, cnt, dgpu
+
+
+def oracle_params(w, extra=None):
+    g = w["grid"]
+    prm = oracle.default_params(g["dim"], g["h"], gamma=w["gamma"], beta=w["beta"],
+                                reinit_every=w["reinit_every"])
+    prm.update(extra or {})
+    return prm
+
+
+def oracle_run(w, steps=None, d=None, extra=None):
+    g = w["grid"]
+    prm = oracle_params(w, extra)
+    if d is None:
+        d = oracle.distance(w["points"], g)
+    if w["phi0"][0] == "array":
+        phi0 = np.clip(np.asarray(w["phi0"][1], np.float64), -prm["gamma"], prm["gamma"])
+    else:
+        phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
+    n = w["steps"] if steps is None else steps
+    phi, counts = oracle.run(phi0, d, g, prm, w["dt"], w["interp"], n)
+    return phi, counts, d, prm
+
+
+def check_phi(phi_gpu, phi_orc, h, tol):
+    err = np.abs(phi_gpu.astype(np.float64) - phi_orc)
+    worst = float(err.max())
+    where = np.unravel_index(int(err.argmax()), err.shape)
+    assert worst <= tol * h, f"max |dphi| = {worst / h:.3e} h at {where} (tol {tol:g} h)"
+    return worst / h
+
+
+def check_band(band_gpu, phi_gpu, phi_orc, gamma, h):
+    # the device's own band list is exactly {|phi_gpu| < gamma} in float
+    np.testing.assert_array_equal(band_gpu, (np.abs(phi_gpu) < np.float32(gamma)).astype(np.uint8))
+    want = np.abs(phi_orc) < gamma
+    sure = np.abs(np.abs(phi_orc) - gamma) > 1e-6 * h
+    bad = (band_gpu.astype(bool) != want) & sure
+    assert not bad.any(), f"{int(bad.sum())} band nodes differ away from the threshold"
+
+
+# ------------------------------------------------------------ distance
+
+@pytest.mark.parametrize("name,n", [("circle2d", 128), ("torus3d", 45), ("torus3d", 128)])
+def test_distance_field_matches_oracle(name, n):
+    w = synth.workload(name, n=n)
+    _, _, _, _, _, dgpu = gpu_run(w, steps=0)
+    dor = oracle.distance(w["points"], w["grid"])
+    ref = dor.astype(np.float32).astype(np.float64)
+    ulp = np.spacing(np.abs(dor).astype(np.float32)).astype(np.float64)
+    err = np.abs(dgpu.astype(np.float64) - ref)
+    assert (err <= ulp).all(), f"max err {err.max():.3e}"
+
+
+def test_distance_field_union_sampled():
+    """256^3, 200k points: sampled nodes against the oracle's exact query."""
+    w = synth.workload("union3d")
+    _, _, _, _, _, dgpu = gpu_run(w, steps=0)
+    g = w["grid"]
+    rng = np.random.default_rng(17)
+    idx = rng.choice(dgpu.size, size=400_000, replace=False)
+    X = np.stack(np.unravel_index(idx, dgpu.shape), 1) * g["h"] + np.array(g["lo"])
+    dor = oracle.distance(w["points"], g, x=X)
+    got = dgpu.ravel()[idx].astype(np.float64)
+    ulp = np.spacing(dor.astype(np.float32)).astype(np.float64)
+    assert (np.abs(got - dor.astype(np.float32)) <= ulp).all()
+
+
+# ------------------------------------------------------------ one step
+
+@pytest.mark.parametrize("name,n,interp", [
+    ("circle2d", 128, "q1"), ("circle2d", 128, "weno"), ("circle2d", 61, "weno"),
+    ("torus3d", 40, "q1"), ("torus3d", 40, "weno"), ("torus3d", 37, "weno"),
+])
+def test_one_step_matches_oracle(name, n, interp):
+    w = synth.workload(name, n=n)
+    w["interp"] = interp
+    w["reinit_every"] = 0
+    h = w["grid"]["h"]
+    phi, band, nb, si, cnt, _ = gpu_run(w, steps=1)
+    ophi, counts, _, prm = oracle_run(w, steps=1)
+    check_phi(phi, ophi, h, 1e-5)
+    check_band(band, phi, ophi, prm["gamma"], h)
+    assert si == 1 and cnt["node_updates"] == counts[0]
+
+
+def test_ragged_anisotropic_grid_one_step():
+    g = {"dim": 3, "n": (23, 41, 30), "lo": (-0.6, -1.0, -0.75), "h": 0.05}
+    pts = synth.torus_cloud(3000, 0.45, 0.18, 0.0, seed=9)
+    pts = pts[np.all(np.abs(pts) < [0.5, 0.9, 0.7], axis=1)]
+    w = dict(grid=g, points=pts, phi0=("sphere", (0.0, 0.05, 0.0, 0.5)), interp="weno",
+             dt=0.5 * g["h"], steps=3, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=2)
+    phi, band, nb, _, _, _ = gpu_run(w)
+    ophi, _, _, prm = oracle_run(w)
+    check_phi(phi, ophi, g["h"], 3e-5)
+    check_band(band, phi, ophi, prm["gamma"], g["h"])
+
+
+# ------------------------------------------------------------ whole runs
+
+def test_full_run_circle2d():
+    """The 2D workload as specified: 128^2, Q1, dt = h, 200 steps, reinit
+    after every step."""
+    w = synth.workload("circle2d")
+    h = w["grid"]["h"]
+    phi, band, nb, si, cnt, _ = gpu_run(w)
+    ophi, counts, _, prm = oracle_run(w)
+    e = check_phi(phi, ophi, h, 1e-4)
+    check_band(band, phi, ophi, prm["gamma"], h)
+    assert si == 200 and cnt["reinits"] == 200
+    print(f"circle2d: max |dphi| = {e:.2e} h, node updates {cnt['node_updates']} vs {counts[0]}")
+
+
+@pytest.mark.parametrize("interp", ["q1", "weno"])
+def test_full_run_torus3d_small(interp):
+    w = synth.workload("torus3d", n=48, steps=100)
+    w["interp"] = interp
+    h = w["grid"]["h"]
+    phi, band, nb, si, cnt, _ = gpu_run(w)
+    ophi, counts, _, prm = oracle_run(w)
+    check_phi(phi, ophi, h, 1e-4)
+    check_band(band, phi, ophi, prm["gamma"], h)
+    assert cnt["reinits"] == 10
+
+
+def test_full_run_torus3d_full_size():
+    """The 3D single-instance workload at full size: 128^3, 20k noisy torus
+    points, WENO, dt = h/2, 300 steps, reinit every 10 steps."""
+    w = synth.workload("torus3d")
+    h = w["grid"]["h"]
+    phi, band, nb, si, cnt, _ = gpu_run(w)
+    ophi, counts, _, prm = oracle_run(w)
+    e = check_phi(phi, ophi, h, 1e-4)
+    check_band(band, phi, ophi, prm["gamma"], h)
+    rel = abs(cnt["node_updates"] - counts[0]) / counts[0]
+    assert rel < 1e-4
+    print(f"torus3d 128^3: max |dphi| = {e:.2e} h, updates {cnt['node_updates']} vs {counts[0]}")
+
+
+def test_union3d_first_steps():
+    """The 256^3 non-uniform workload, first 30 steps (3 reinitialisations)."""
+    w = synth.workload("union3d", steps=30)
+    h = w["grid"]["h"]
+    phi, band, nb, si, cnt, _ = gpu_run(w)
+    ophi, counts, _, prm = oracle_run(w)
+    check_phi(phi, ophi, h, 1e-4)
+    check_band(band, phi, ophi, prm["gamma"], h)
+
+
+# ------------------------------------------------------- reinitialisation
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reinit_alone_matches_oracle(dim):
+    lsr = _lsr()
+    n = 64 if dim == 2 else 40
+    g = synth.cube_grid(dim, n)
+    h = g["h"]
+    X = oracle.node_coords(g)
+    r = np.linalg.norm(X - 0.03, axis=1)
+    phi0 = ((1.0 + 0.5 * X[:, 0]) * (r - 0.55)).reshape(g["n"])  # not a distance
+    prm = oracle.default_params(dim, h)
+    job = lsr.Job(g, dict(gamma=prm["gamma"], beta=prm["beta"]), max_points=1)
+    job.set_distance(np.zeros(g["n"]))
+    job.init_phi(phi0=phi0.astype(np.float32))
+    job.reinit()
+    phi, band, nb, _ = job.extract()
+    cnt = job.counters()
+    job.close()
+    pc = np.clip(phi0.astype(np.float32).astype(np.float64), -prm["gamma"], prm["gamma"])
+    ophi, oc = oracle.reinit(pc, oracle.band_mask(pc, prm), g, prm)
+    check_phi(phi, ophi, h, 1e-5)
+    assert cnt["gbar"] == oc[0] and cnt["interface"] == oc[1]
+
+
+# --------------------------------------------------------- edge cases
+
+def test_empty_band_is_a_no_op():
+    w = synth.workload("torus3d", n=24, steps=5)
+    w["phi0"] = ("sphere", (0.0, 0.0, 0.0, 5.0))  # every node far inside: phi = -gamma
+    phi, band, nb, si, cnt, _ = gpu_run(w)
+    assert nb == 0 and cnt["node_updates"] == 0 and si == 5
+    np.testing.assert_array_equal(phi, np.float32(-w["gamma"]))
+
+
+def test_minimal_grid_and_band_on_the_boundary():
+    """n = 4 per axis: every WENO stencil is clamped and every gradient at the
+    boundary is one-sided."""
+    g = synth.cube_grid(3, 6)
+    pts = np.array([[0.1, -0.2, 0.05], [-0.3, 0.2, 0.1], [0.5, 0.5, -0.5]])
+    for n in (4, 6):
+        g = synth.cube_grid(3, n)
+        w = dict(grid=g, points=pts, phi0=("sphere", (0.0, 0.0, 0.0, 0.6)), interp="weno",
+                 dt=0.5 * g["h"], steps=4, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=2)
+        phi, band, nb, _, _, _ = gpu_run(w)
+        ophi, _, _, prm = oracle_run(w)
+        check_phi(phi, ophi, g["h"], 1e-5)
+
+
+def test_torus_initial_data_and_ragged_2d():
+    g = {"dim": 2, "n": (50, 77), "lo": (-1.0, -1.5), "h": 2.0 / 49}
+    pts = synth.circle_cloud(300, 0.6, seed=4)
+    w = dict(grid=g, points=pts, phi0=("sphere", (0.1, -0.1, 0.0, 0.8)), interp="weno",
+             dt=g["h"], steps=20, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=1)
+    phi, band, nb, _, _, _ = gpu_run(w)
+    ophi, _, _, prm = oracle_run(w)
+    check_phi(phi, ophi, g["h"], 1e-4)
+    w3 = synth.workload("torus3d", n=33, steps=6)
+    w3["phi0"] = ("torus", (0.0, 0.0, 0.0, 0.5, 0.25))
+    phi, band, nb, _, _, _ = gpu_run(w3)
+    ophi, _, _, prm = oracle_run(w3)
+    check_phi(phi, ophi, w3["grid"]["h"], 1e-4)
+
+
+def test_fallback_and_array_initial_data():
+    """A flat plateau inside the band takes the degenerate-gradient branch."""
+    g = synth.cube_grid(3, 24)
+    h = g["h"]
+    X = oracle.node_coords(g)
+    phi0 = np.clip(np.linalg.norm(X, axis=1) - 0.5, -0.5 * h, 6 * h).reshape(g["n"])
+    w = dict(grid=g, points=synth.torus_cloud(2000, 0.5, 0.2, 0.0, seed=3),
+             phi0=("array", phi0.astype(np.float32)), interp="weno", dt=0.5 * h, steps=3,
+             gamma=6 * h, beta=3 * h, reinit_every=0)
+    phi, band, nb, _, cnt, _ = gpu_run(w)
+    ophi, counts, _, prm = oracle_run(w)
+    check_phi(phi, ophi, h, 1e-5)
+    assert cnt["fallbacks"] == counts[1] and counts[1] > 0
+
+
+def test_restart_is_bitwise_identical():
+    w = synth.workload("torus3d", n=40, steps=20)
+    full, _, _, _, _, _ = gpu_run(w)
+    half, _, _, _, _, _ = gpu_run(w, steps=7)
+    w2 = dict(w)
+    w2["phi0"] = ("array", half)
+    rest, _, _, si, _, _ = gpu_run(w2, steps=13, step0=7)
+    assert si == 20
+    np.testing.assert_array_equal(full, rest)
+
+
+def test_errors_leave_the_job_usable():
+    lsr = _lsr()
+    w = synth.workload("torus3d", n=24)
+    job = lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"]), max_points=len(w["points"]))
+    with pytest.raises(lsr.LsrError) as e:
+        job.step(1, w["dt"], "weno")
+    assert e.value.status == lsr.LSR_E_STATE
+    job.load_cloud(w["points"])
+    d1 = job.distance()
+    bad = w["points"].copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(lsr.LsrError) as e:
+        job.load_cloud(bad)
+    assert e.value.status == lsr.LSR_E_INVALID
+    bad = w["points"].copy()
+    bad[7, 0] = 1.5
+    with pytest.raises(lsr.LsrError):
+        job.load_cloud(bad)
+    np.testing.assert_array_equal(job.distance(), d1)
+    phi0 = np.zeros(w["grid"]["n"], np.float32)
+    phi0[1, 2, 3] = np.inf
+    with pytest.raises(lsr.LsrError):
+        job.init_phi(phi0=phi0)
+    job.init_phi("sphere", (0, 0, 0, 0.9))
+    job.step(2, w["dt"], "weno")
+    assert job.extract()[3] == 2
+    job.close()
