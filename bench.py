@@ -32,9 +32,9 @@ if ROOT not in sys.path:
 # flops of per-foot set-up, 60 flops of per-node set-up.
 FLOPS_PER_UPDATE = {(3, "weno"): 84 * 30 + 4 * 42 + 60, (3, "q1"): 4 * (7 * 3 + 18) + 60,
                     (2, "weno"): 2 * (5 * 30 + 28) + 40, (2, "q1"): 2 * (3 * 3 + 12) + 40}
-# Compulsory HBM bytes of one node update: list entry in 4, phi^n_j 4,
-# (grad d, d) 16, phi^{n+1}_j 4, list entry out 4.
-BYTES_PER_UPDATE = 32
+# Compulsory HBM bytes of one node update: list entry in 4, phi^n_j e,
+# (grad d, d) 4e, phi^{n+1}_j e, list entry out 4, with e the element size.
+BYTES_PER_UPDATE = {"fp32": 4 + 4 + 16 + 4 + 4, "fp64": 4 + 8 + 32 + 8 + 4}
 PEAK_FP32_TFLOPS = 157.3  # MI355X published fp32 vector peak
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kernels.hip"]
@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed jobs")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus3d")
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -130,11 +131,12 @@ def main():
     w = synth.workload(args.workload)
     g = w["grid"]
     dim = g["dim"]
-    prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"])
+    prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
+               precision=args.precision)
     job = lsr.Job(g, prm, max_points=len(w["points"]))
     stream = job.stream
     pts = torch.as_tensor(w["points"], dtype=torch.float64, device="cuda").contiguous()
-    phi_out = torch.empty(job.nodes, dtype=torch.float32, device="cuda")
+    phi_out = torch.empty(job.nodes, dtype=job.dtype, device="cuda")
     band_out = torch.empty(job.nodes, dtype=torch.uint8, device="cuda")
     kind = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}[w["phi0"][0]]
     interp = lsr.interp_code(w["interp"])
@@ -177,11 +179,11 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": f"k_sl_step<{dim},{w['interp']}>",
+                "kernel": f"k_sl_step<{dim},{w['interp']},{'double' if args.precision == 'fp64' else 'float'}>",
                 "flops_per_node_update": flops,
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
                 "node_updates_per_launch": round(upd_per_launch, 1)}
-    hbm_gbs = BYTES_PER_UPDATE * total_updates / kernel_s / 1e9
+    hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in lat)
     out = {
         "metric": "narrow-band node-updates/s (3D WENO SL step) + jobs/s, p50/p99 latency",
@@ -194,14 +196,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": "x".join(str(v) for v in g["n"]),
                    "points": len(w["points"]), "interp": w["interp"], "dt": "h/2" if dim == 3 else "h",
                    "steps_per_job": w["steps"], "band": "6h", "reinit_every": w["reinit_every"],
                    "parallelism": "single GPU"},
         "roofline": roofline,
-        "hbm": {"algorithmic_bytes_per_update": BYTES_PER_UPDATE, "achieved_gbs": round(hbm_gbs, 1),
+        "hbm": {"algorithmic_bytes_per_update": BYTES_PER_UPDATE[args.precision],
+                "achieved_gbs": round(hbm_gbs, 1),
                 "peak_gbs": PEAK_HBM_GBS, "frac": round(hbm_gbs / PEAK_HBM_GBS, 4)},
         "sl_kernel_node_updates_per_s": total_updates / kernel_s,
         "sl_kernel_share_of_wall": kernel_s / wall,

@@ -47,6 +47,11 @@ typedef enum {
 /* Interpolation operator I[phi] of Section 3.2. */
 typedef enum { LSR_Q1 = 0, LSR_WENO = 1 } lsr_interp;
 
+/* Precision of the state (phi, the packed distance gradient) and of the
+ * arithmetic of the step and reinitialisation kernels.  The distance field
+ * itself is always computed in double. */
+enum { LSR_FP32 = 0, LSR_FP64 = 1 };
+
 /* Initial-data kinds for lsr_init_phi. */
 enum { LSR_PHI_ARRAY = 0, LSR_PHI_SPHERE = 1, LSR_PHI_TORUS = 2 };
 
@@ -72,6 +77,7 @@ typedef struct {
   int32_t reinit_iters;  /* forward-Euler pseudo-time iterations per reinit */
   double reinit_dtau;    /* pseudo-time step, <= h/sqrt(dim) */
   double interface_floor;/* lower bound on |grad phi| in the interface fix */
+  int32_t precision;     /* LSR_FP32 or LSR_FP64 */
 } lsr_params;
 
 typedef struct lsr_job lsr_job;
@@ -93,12 +99,15 @@ enum {
  * in 2D and gamma = 6h, beta = 3h in 3D (Section 3.8); C = 1e-3, alpha = 1
  * (Section 3.1); reinitialisation after every step in 2D and every 10th in
  * 3D, pseudo-time step h/2, ceil((gamma + h)/dtau) iterations, floor 1e-3
- * (Section 3.7 gives no values; these are this library's choice). */
+ * (Section 3.7 gives no values; these are this library's choice);
+ * precision LSR_FP32. */
 lsr_status lsr_params_default(int32_t dim, double h, lsr_params* out);
 
-/* Device workspace a job needs for this grid and at most max_points cloud
- * points.  Independent of the parameters. */
-lsr_status lsr_workspace_bytes(const lsr_grid* grid, int64_t max_points, size_t* bytes);
+/* Device workspace a job needs for this grid, these parameters (only the
+ * precision matters; NULL means LSR_FP32) and at most max_points cloud
+ * points. */
+lsr_status lsr_workspace_bytes(const lsr_grid* grid, const lsr_params* params, int64_t max_points,
+                               size_t* bytes);
 
 /* Create a job on the current HIP device.  dev_workspace: device memory of
  * at least lsr_workspace_bytes bytes, 256-byte aligned, owned by the caller
@@ -122,18 +131,18 @@ lsr_status lsr_load_cloud(lsr_job* job, const double* dev_xyz, int64_t n);
  * checked).  The current phi and band are kept. */
 lsr_status lsr_set_distance(lsr_job* job, const double* dev_d);
 
-/* Copy the distance field (as stored, float) to dev_out (device, one float
- * per node, C order). */
-lsr_status lsr_get_distance(lsr_job* job, float* dev_out);
+/* Copy the distance field (double, as computed) to dev_out (device, one
+ * double per node, C order). */
+lsr_status lsr_get_distance(lsr_job* job, double* dev_out);
 
 /* Initial data phi^0 (Algorithm 1, step 3), cut to [-gamma, gamma] by
  * eq. (cut), and the first band.  kind LSR_PHI_ARRAY: dev_phi0 (device, one
- * float per node, C order) is copied; LSR_PHI_SPHERE: signed distance to the
+ * value per node in the job's precision, C order) is copied; LSR_PHI_SPHERE: signed distance to the
  * sphere (circle in 2D) with centre args[0..2] and radius args[3];
  * LSR_PHI_TORUS (3D): torus with axis z, centre args[0..2], radii R = args[3],
  * r = args[4].  args is host memory.  step0 is the global index of the next
  * step, which fixes the reinitialisation phase after a restart. */
-lsr_status lsr_init_phi(lsr_job* job, const float* dev_phi0, int32_t kind, const double* args,
+lsr_status lsr_init_phi(lsr_job* job, const void* dev_phi0, int32_t kind, const double* args,
                         int64_t step0);
 
 /* n_steps iterations of Algorithm 1's loop: band (eq. subgrid, read as
@@ -148,12 +157,13 @@ lsr_status lsr_step(lsr_job* job, int32_t n_steps, double dt, lsr_interp interp)
  * face neighbours, outside the step loop. */
 lsr_status lsr_reinit(lsr_job* job);
 
-/* Copy out the current phi (dev_phi: device, one float per node) and the band
+/* Copy out the current phi (dev_phi: device, one value per node in the job's
+ * precision) and the band
  * mask (dev_band: device, one byte per node, 1 iff |phi| < gamma); either may
  * be NULL.  If n_band is not NULL the stream is synchronised and the band
  * size stored there; step_index (may be NULL) receives the global index of
  * the next step. */
-lsr_status lsr_extract(lsr_job* job, float* dev_phi, uint8_t* dev_band, int64_t* n_band,
+lsr_status lsr_extract(lsr_job* job, void* dev_phi, uint8_t* dev_band, int64_t* n_band,
                        int64_t* step_index);
 
 /* Read up to n cumulative counters (LSR_CNT_*) into host memory; syncs. */

@@ -8,12 +8,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lsr.h"
-#include "lsr_internal.h"
+#include "lsr_job.h"
 
 using namespace lsr;
 
-namespace {
+namespace lsr {
 
 thread_local std::string g_last_error;
 
@@ -22,12 +21,9 @@ lsr_status fail(lsr_status st, const std::string& msg) {
   return st;
 }
 
-#define LSR_HIP(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(LSR_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
-  } while (0)
+}  // namespace lsr
+
+namespace {
 
 int bits_for(int n) {  // bits to hold indices 0..n-1
   int b = 0;
@@ -36,14 +32,6 @@ int bits_for(int n) {  // bits to hold indices 0..n-1
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-struct Layout {
-  size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, stamp, cnt, stats;
-  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ;
-  size_t total;
-  int nb[3];
-  int64_t nbins;
-};
 
 int64_t node_count(const lsr_grid& g) {
   int64_t N = (int64_t)g.n[0] * g.n[1];
@@ -54,10 +42,11 @@ void bin_counts(const lsr_grid& g, int nb[3]) {
   for (int a = 0; a < 3; ++a) nb[a] = a < g.dim ? (g.n[a] - 1) / BIN_W + 1 : 1;
 }
 
-Layout make_layout(const lsr_grid& g, int64_t max_points) {
+Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   Layout L;
   const size_t N = (size_t)node_count(g);
   const size_t P = (size_t)(max_points > 0 ? max_points : 1);
+  const size_t es = fp64 ? 8 : 4;
   bin_counts(g, L.nb);
   L.nbins = (int64_t)L.nb[0] * L.nb[1] * L.nb[2];
   size_t off = 0;
@@ -66,9 +55,9 @@ Layout make_layout(const lsr_grid& g, int64_t max_points) {
     off = align256(off + bytes);
     return o;
   };
-  L.phi0 = take(4 * N);
-  L.phi1 = take(4 * N);
-  L.dp = take(16 * N);
+  L.phi0 = take(es * N);
+  L.phi1 = take(es * N);
+  L.dp = take(4 * es * N);
   L.d64 = take(8 * N);
   L.list0 = take(4 * N);
   L.list1 = take(4 * N);
@@ -117,164 +106,88 @@ lsr_status check_params(const lsr_grid* g, const lsr_params* p) {
   if (!(p->reinit_dtau > 0.0) || p->reinit_dtau > g->h / sqrt((double)g->dim) * (1.0 + 1e-12))
     return fail(LSR_E_INVALID, "reinit_dtau must be in (0, h/sqrt(dim)]");
   if (!(p->interface_floor > 0.0)) return fail(LSR_E_INVALID, "interface_floor must be > 0");
+  if (p->precision != LSR_FP32 && p->precision != LSR_FP64)
+    return fail(LSR_E_INVALID, "precision must be LSR_FP32 or LSR_FP64");
   return LSR_OK;
 }
 
 }  // namespace
 
-struct lsr_job {
-  lsr_grid grid;
-  lsr_params prm;
-  hipStream_t stream;
-  char* ws;
-  size_t ws_bytes;
-  Layout L;
-  int64_t max_points;
-  DevGrid dg;
-  BinGeom bg;
-  float* phi[2];
-  float4* dp;
-  double* d64;
-  uint32_t* list[2];
-  uint32_t* listM;
-  uint8_t* mflags;
-  uint32_t* stamp;
-  int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins
-  unsigned long long* stats;
-  double* pts_raw;
-  double* pts;
-  int32_t* pt_bin;
-  int32_t* bin_count;
-  int32_t* bin_start;
-  int32_t* bin_fill;
-  uint32_t* occ;
-  unsigned list_blocks;
-  int cur;       // phi buffer holding the current phi
-  int cur_list;  // list buffer holding the current band list
-  int ring;      // counter slot holding the current list length
-  uint32_t epoch;
-  int64_t step_index;
-  int64_t n_reinits, n_steps;
-  bool has_d, has_phi;
-  // measurement hook
-  bool prof_on;
-  int prof_used;
-  std::vector<hipEvent_t> prof_ev;
-};
+namespace lsr {
 
-namespace {
-
-StepConst step_const(const lsr_job* j, double dt) {
-  StepConst c;
-  const double h = j->grid.h;
-  const lsr_params& p = j->prm;
-  c.gamma = (float)p.gamma;
-  c.beta = (float)p.beta;
-  const double gb = p.gamma - p.beta;
-  c.inv_gb3 = (float)(1.0 / (gb * gb * gb));
-  c.drift = (float)(dt / h);
-  c.diff2 = (float)(p.delta * dt / (p.p * h * h));
-  c.grad_thr = (float)(p.grad_C * pow(dt, p.grad_alpha));
-  c.weno_e = (float)(h * h * h * h);
-  c.half_inv_h = (float)(0.5 / h);
-  c.inv_h = (float)(1.0 / h);
-  return c;
-}
-
-int32_t* ring_slot(lsr_job* j, int k) { return j->cnt + ((j->ring + k) % 3); }
-
-lsr_status run_reinit(lsr_job* j) {
+template <typename T>
+static lsr_status launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
   hipStream_t s = j->stream;
   const int dim = j->grid.dim;
-  if (j->epoch == 0xFFFFFFFFu) {
-    LSR_HIP(launch_fill_u32(j->stamp, 0u, j->dg.N, s));
-    j->epoch = 0;
-  }
-  j->epoch += 1;
-  DilArgs da;
-  da.g = j->dg;
-  da.L = j->list[j->cur_list];
-  da.cnt_in = ring_slot(j, 0);
-  da.M = j->listM;
-  da.cnt_out = ring_slot(j, 1);
-  da.cnt_reset = ring_slot(j, 2);
-  da.stamp = j->stamp;
-  da.epoch = j->epoch;
-  LSR_HIP(launch_dilate(dim, da, j->list_blocks, s));
-  j->ring = (j->ring + 1) % 3;
-
-  RArgs ra;
-  ra.g = j->dg;
-  ra.c = step_const(j, j->grid.h);
-  ra.M = j->listM;
-  ra.cnt = ring_slot(j, 0);
-  ra.flags = j->mflags;
-  ra.dtau = (float)j->prm.reinit_dtau;
-  ra.floor_ = (float)j->prm.interface_floor;
-  ra.stats = j->stats;
-  ra.src = j->phi[j->cur];
-  ra.dst = j->phi[1 - j->cur];
-  LSR_HIP(launch_reinit_fix(dim, ra, j->list_blocks, s));
-  int w = 1 - j->cur;
-  for (int it = 0; it < j->prm.reinit_iters; ++it) {
-    ra.src = j->phi[w];
-    ra.dst = j->phi[1 - w];
-    LSR_HIP(launch_reinit_iter(dim, ra, j->list_blocks, s));
-    w = 1 - w;
-  }
-  FinArgs fa;
-  fa.g = j->dg;
-  fa.gamma = (float)j->prm.gamma;
-  fa.M = j->listM;
-  fa.cnt_in = ring_slot(j, 0);
-  fa.cur = j->phi[w];
-  fa.other = j->phi[1 - w];
-  fa.Lout = j->list[j->cur_list];
-  fa.cnt_out = ring_slot(j, 1);
-  fa.cnt_reset = ring_slot(j, 2);
-  LSR_HIP(launch_reinit_final(fa, j->list_blocks, s));
-  j->ring = (j->ring + 1) % 3;
-  j->cur = w;
-  j->n_reinits += 1;
+  LSR_HIP(launch_dilate(dim, r.dil, j->list_blocks, s));
+  LSR_HIP(launch_reinit_fix<T>(dim, r.fix, j->list_blocks, s));
+  for (int it = 0; it < r.iters; ++it)
+    LSR_HIP(launch_reinit_iter<T>(dim, r.iter[it % 2], j->list_blocks, s));
+  LSR_HIP(launch_reinit_final<T>(r.fin, j->list_blocks, s));
   return LSR_OK;
 }
 
-lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp) {
+template <typename T>
+static lsr_status run_reinit_t(lsr_job* j) {
+  if (stamp_needs_clear(j)) {
+    LSR_HIP(launch_fill_u32(j->stamp, 0u, j->dg.N, j->stream));
+    j->epoch = 0;
+  }
+  ReinitPlan<T> r = plan_reinit<T>(j);
+  return launch_reinit_plan<T>(j, r);
+}
+
+template <typename T>
+static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp) {
   hipStream_t s = j->stream;
-  SLArgs a;
-  a.g = j->dg;
-  a.c = step_const(j, dt);
-  a.dp = j->dp;
-  a.stats = j->stats;
+  const StepConst<T> c = step_const<T>(j, dt);
   for (int32_t q = 0; q < n_steps; ++q) {
-    a.A = j->phi[j->cur];
-    a.B = j->phi[1 - j->cur];
-    a.Lin = j->list[j->cur_list];
-    a.Lout = j->list[1 - j->cur_list];
-    a.cnt_in = ring_slot(j, 0);
-    a.cnt_out = ring_slot(j, 1);
-    a.cnt_reset = ring_slot(j, 2);
+    SLArgs<T> a = plan_step<T>(j, c);
     const bool rec = j->prof_on && 2 * (size_t)j->prof_used + 1 < j->prof_ev.size();
     if (rec) LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used], s));
-    LSR_HIP(launch_sl_step(j->grid.dim, interp, a, j->list_blocks, s));
+    LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, a, j->list_blocks, s));
     if (rec) {
       LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used + 1], s));
       j->prof_used += 1;
     }
-    j->cur = 1 - j->cur;
-    j->cur_list = 1 - j->cur_list;
-    j->ring = (j->ring + 1) % 3;
-    j->step_index += 1;
-    j->n_steps += 1;
-    if (j->prm.reinit_every > 0 && j->step_index % j->prm.reinit_every == 0) {
-      lsr_status st = run_reinit(j);
+    if (reinit_due(j)) {
+      lsr_status st = run_reinit_t<T>(j);
       if (st != LSR_OK) return st;
     }
   }
   return LSR_OK;
 }
 
-}  // namespace
+lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp) {
+  return j->fp64 ? run_steps_t<double>(j, n_steps, dt, interp)
+                 : run_steps_t<float>(j, n_steps, dt, interp);
+}
+
+lsr_status run_reinit(lsr_job* j) {
+  return j->fp64 ? run_reinit_t<double>(j) : run_reinit_t<float>(j);
+}
+
+hipError_t dpack(lsr_job* j) {
+  return j->fp64 ? launch_dpack<double>(j->grid.dim, j->dg, j->d64,
+                                        (typename Vec<double>::pack*)j->dp, j->stream)
+                 : launch_dpack<float>(j->grid.dim, j->dg, j->d64,
+                                       (typename Vec<float>::pack*)j->dp, j->stream);
+}
+
+// Initial data into both phi buffers, or (write = false) only the check of
+// the caller's array.
+hipError_t init_phi(lsr_job* j, int kind, const double* a, const void* src, bool write) {
+  const int dim = j->grid.dim;
+  if (j->fp64)
+    return launch_init_phi<double>(dim, j->dg, kind, a, j->prm.gamma, (const double*)src,
+                                   write ? phi_buf<double>(j, 0) : nullptr,
+                                   write ? phi_buf<double>(j, 1) : nullptr, j->cnt + 3, j->stream);
+  return launch_init_phi<float>(dim, j->dg, kind, a, (float)j->prm.gamma, (const float*)src,
+                                write ? phi_buf<float>(j, 0) : nullptr,
+                                write ? phi_buf<float>(j, 1) : nullptr, j->cnt + 3, j->stream);
+}
+
+}  // namespace lsr
 
 extern "C" {
 
@@ -295,16 +208,19 @@ lsr_status lsr_params_default(int32_t dim, double h, lsr_params* out) {
   p.reinit_dtau = 0.5 * h;
   p.reinit_iters = (int32_t)ceil((p.gamma + h) / p.reinit_dtau - 1e-9);
   p.interface_floor = 1e-3;
+  p.precision = LSR_FP32;
   *out = p;
   return LSR_OK;
 }
 
-lsr_status lsr_workspace_bytes(const lsr_grid* grid, int64_t max_points, size_t* bytes) {
+lsr_status lsr_workspace_bytes(const lsr_grid* grid, const lsr_params* params, int64_t max_points,
+                               size_t* bytes) {
   lsr_status st = check_grid(grid);
   if (st != LSR_OK) return st;
   if (!bytes) return fail(LSR_E_INVALID, "bytes is NULL");
   if (max_points < 0) return fail(LSR_E_INVALID, "max_points must be >= 0");
-  *bytes = make_layout(*grid, max_points).total;
+  const bool fp64 = params && params->precision == LSR_FP64;
+  *bytes = make_layout(*grid, max_points, fp64).total;
   return LSR_OK;
 }
 
@@ -318,12 +234,24 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   if (!dev_workspace) return fail(LSR_E_INVALID, "workspace is NULL");
   if (((uintptr_t)dev_workspace) & 255) return fail(LSR_E_INVALID, "workspace must be 256-byte aligned");
   // the largest cloud the workspace holds
-  Layout L0 = make_layout(*grid, 1);
+  const bool fp64 = params->precision == LSR_FP64;
+  Layout L0 = make_layout(*grid, 1, fp64);
   if (ws_bytes < L0.total) return fail(LSR_E_NOMEM, "workspace smaller than lsr_workspace_bytes");
-  const size_t per_point = 8 * 2 * (size_t)grid->dim + 4;
-  int64_t maxp = 1 + (int64_t)((ws_bytes - L0.total) / (per_point + 8));
-  while (maxp > 1 && make_layout(*grid, maxp).total > ws_bytes) maxp = maxp * 15 / 16;
-  Layout L = make_layout(*grid, maxp);
+  // largest cloud that fits: the layout grows monotonically with the cloud size
+  int64_t lo = 1, hi = 2;
+  while (make_layout(*grid, hi, fp64).total <= ws_bytes) {
+    lo = hi;
+    hi *= 2;
+  }
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (make_layout(*grid, mid, fp64).total <= ws_bytes)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int64_t maxp = lo;
+  Layout L = make_layout(*grid, maxp, fp64);
   if (L.total > ws_bytes) return fail(LSR_E_NOMEM, "workspace too small");
 
   int dev = 0, ncu = 0;
@@ -338,6 +266,8 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
     j->grid.lo[2] = 0.0;
   }
   j->prm = *params;
+  j->fp64 = fp64;
+  j->in_batch = false;
   j->stream = (hipStream_t)hip_stream;
   j->ws = (char*)dev_workspace;
   j->ws_bytes = ws_bytes;
@@ -353,8 +283,6 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   d.N = (uint32_t)node_count(g);
   d.bits_k = g.dim == 3 ? bits_for(d.n2) : 0;
   d.bits_j = bits_for(d.n1);
-  d.h = (float)g.h;
-  d.inv_h = (float)(1.0 / g.h);
   d.hd = g.h;
   d.lo0 = g.lo[0];
   d.lo1 = g.lo[1];
@@ -369,9 +297,9 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   b.inv_bw = 1.0 / b.bw;
 
   char* w = j->ws;
-  j->phi[0] = (float*)(w + L.phi0);
-  j->phi[1] = (float*)(w + L.phi1);
-  j->dp = (float4*)(w + L.dp);
+  j->phi[0] = (void*)(w + L.phi0);
+  j->phi[1] = (void*)(w + L.phi1);
+  j->dp = (void*)(w + L.dp);
   j->d64 = (double*)(w + L.d64);
   j->list[0] = (uint32_t*)(w + L.list0);
   j->list[1] = (uint32_t*)(w + L.list1);
@@ -450,7 +378,7 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   unsigned bricks = (unsigned)(((j->dg.n0 + BS - 1) / BS) * ((j->dg.n1 + BS - 1) / BS) *
                                (dim == 3 ? (j->dg.n2 + BS - 1) / BS : 1));
   LSR_HIP(launch_distance(dim, da, bricks, s));
-  LSR_HIP(launch_dpack(dim, j->dg, j->d64, j->dp, s));
+  LSR_HIP(dpack(j));
   j->has_d = true;
   return LSR_OK;
 }
@@ -460,22 +388,23 @@ lsr_status lsr_set_distance(lsr_job* j, const double* dev_d) {
   if (!dev_d) return fail(LSR_E_INVALID, "distance is NULL");
   LSR_HIP(hipMemcpyAsync(j->d64, dev_d, sizeof(double) * j->dg.N, hipMemcpyDeviceToDevice,
                          j->stream));
-  LSR_HIP(launch_dpack(j->grid.dim, j->dg, j->d64, j->dp, j->stream));
+  LSR_HIP(dpack(j));
   j->has_d = true;
   return LSR_OK;
 }
 
-lsr_status lsr_get_distance(lsr_job* j, float* dev_out) {
+lsr_status lsr_get_distance(lsr_job* j, double* dev_out) {
   if (!j || !dev_out) return fail(LSR_E_INVALID, "NULL argument");
   if (!j->has_d) return fail(LSR_E_STATE, "no distance field yet");
-  LSR_HIP(hipMemcpy2DAsync(dev_out, sizeof(float), ((const char*)j->dp) + 12, sizeof(float4),
-                           sizeof(float), j->dg.N, hipMemcpyDeviceToDevice, j->stream));
+  LSR_HIP(hipMemcpyAsync(dev_out, j->d64, sizeof(double) * j->dg.N, hipMemcpyDeviceToDevice,
+                         j->stream));
   return LSR_OK;
 }
 
-lsr_status lsr_init_phi(lsr_job* j, const float* dev_phi0, int32_t kind, const double* args,
+lsr_status lsr_init_phi(lsr_job* j, const void* dev_phi0, int32_t kind, const double* args,
                         int64_t step0) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   if (kind < 0 || kind > 2) return fail(LSR_E_INVALID, "unknown kind");
   if (kind == LSR_PHI_ARRAY && !dev_phi0) return fail(LSR_E_INVALID, "phi0 is NULL");
   if (kind == LSR_PHI_TORUS && j->grid.dim != 3) return fail(LSR_E_INVALID, "torus needs 3D");
@@ -495,18 +424,19 @@ lsr_status lsr_init_phi(lsr_job* j, const float* dev_phi0, int32_t kind, const d
   if (kind == LSR_PHI_ARRAY) {
     // check the input before touching the state (no output buffers: check only)
     LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s));
-    LSR_HIP(launch_init_phi(dim, j->dg, 0, a, (float)j->prm.gamma, dev_phi0, nullptr, nullptr,
-                            j->cnt + 3, s));
+    LSR_HIP(init_phi(j, 0, a, dev_phi0, false));
     int32_t flag = 0;
     LSR_HIP(hipMemcpyAsync(&flag, j->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LSR_HIP(hipStreamSynchronize(s));
     if (flag) return fail(LSR_E_INVALID, "phi0 has a non-finite value");
   }
-  LSR_HIP(launch_init_phi(dim, j->dg, kind, a, (float)j->prm.gamma, dev_phi0, j->phi[0], j->phi[1],
-                          j->cnt + 3, s));
+  LSR_HIP(init_phi(j, kind, a, dev_phi0, true));
   LSR_HIP(launch_fill_u32((uint32_t*)j->cnt, 0u, 3, s));
   LSR_HIP(launch_fill_u32((uint32_t*)j->stats, 0u, 32, s));
-  LSR_HIP(launch_band_scan(dim, j->dg, (float)j->prm.gamma, j->phi[0], j->list[0], j->cnt, s));
+  LSR_HIP(j->fp64 ? launch_band_scan<double>(dim, j->dg, j->prm.gamma, phi_buf<double>(j, 0),
+                                             j->list[0], j->cnt, s)
+                  : launch_band_scan<float>(dim, j->dg, (float)j->prm.gamma, phi_buf<float>(j, 0),
+                                            j->list[0], j->cnt, s));
   j->cur = 0;
   j->cur_list = 0;
   j->ring = 0;
@@ -524,28 +454,36 @@ lsr_status lsr_step(lsr_job* j, int32_t n_steps, double dt, lsr_interp interp) {
   if (interp != LSR_Q1 && interp != LSR_WENO) return fail(LSR_E_INVALID, "unknown interpolator");
   if (!j->has_d) return fail(LSR_E_STATE, "no distance field: call lsr_load_cloud first");
   if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   return run_steps(j, n_steps, dt, (int)interp);
 }
 
 lsr_status lsr_reinit(lsr_job* j) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
   if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   return run_reinit(j);
 }
 
-lsr_status lsr_extract(lsr_job* j, float* dev_phi, uint8_t* dev_band, int64_t* n_band,
+lsr_status lsr_extract(lsr_job* j, void* dev_phi, uint8_t* dev_band, int64_t* n_band,
                        int64_t* step_index) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
   if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
   hipStream_t s = j->stream;
   if (dev_phi)
-    LSR_HIP(hipMemcpyAsync(dev_phi, j->phi[j->cur], sizeof(float) * j->dg.N,
+    LSR_HIP(hipMemcpyAsync(dev_phi, j->phi[j->cur], (j->fp64 ? 8 : 4) * (size_t)j->dg.N,
                            hipMemcpyDeviceToDevice, s));
   if (dev_band || n_band) {
     if (dev_band) LSR_HIP(launch_fill_u8(dev_band, 0, j->dg.N, s));
     LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 4), 0u, 1, s));
-    LSR_HIP(launch_band_mask(j->dg, (float)j->prm.gamma, j->phi[j->cur], j->list[j->cur_list],
-                             ring_slot(j, 0), dev_band, j->cnt + 4, j->list_blocks, s));
+    if (j->fp64)
+      LSR_HIP(launch_band_mask<double>(j->dg, j->prm.gamma, phi_buf<double>(j, j->cur),
+                                       j->list[j->cur_list], ring_slot(j, 0), dev_band, j->cnt + 4,
+                                       j->list_blocks, s));
+    else
+      LSR_HIP(launch_band_mask<float>(j->dg, (float)j->prm.gamma, phi_buf<float>(j, j->cur),
+                                      j->list[j->cur_list], ring_slot(j, 0), dev_band, j->cnt + 4,
+                                      j->list_blocks, s));
   }
   if (n_band) {
     int32_t c = 0;

@@ -1,8 +1,8 @@
 // Device-side building blocks of the narrow-band semi-Lagrangian solver
 // (Preda & Semplice, arXiv:2410.22205): grid addressing, centred gradients,
 // the cut-off, the Q1 and tensor WENO interpolants of Section 3.2 and the
-// node update of Section 3.1.  Single precision throughout, except the
-// distance field, which is built in double (lsr_kernels.hip).
+// node update of Section 3.1.  Templated on the real type T of the state
+// (float or double); the distance field is always built in double.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,10 +22,24 @@
 
 namespace lsr {
 
-// Four consecutive floats loaded with one 16-byte access at any 4-byte
-// aligned address (global memory accepts dword-aligned multi-dword loads).
+// Consecutive values loaded with 16-byte accesses at any element-aligned
+// address (global memory accepts dword-aligned multi-dword loads).
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef double d4u __attribute__((ext_vector_type(4), aligned(8)));
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
+template <typename T> struct Vec;
+template <> struct Vec<float> {
+  typedef f4u v4;
+  typedef f2u v2;
+  typedef float4 pack;  // (d_x, d_y, d_z, d)
+};
+template <> struct Vec<double> {
+  typedef d4u v4;
+  typedef d2u v2;
+  typedef double4 pack;
+};
 
 // Grid geometry as the kernels see it.  Band lists hold packed node
 // coordinates: code = (i << (bits_j + bits_k)) | (j << bits_k) | k.
@@ -34,18 +48,18 @@ struct DevGrid {
   uint32_t s0, s1;       // strides of axes 0 and 1 (axis 2 has stride 1)
   uint32_t N;            // total nodes
   int bits_j, bits_k;    // bit widths of j and k in a packed code
-  float h, inv_h;
   double hd, lo0, lo1, lo2;
 };
 
 // Per-step constants of the update, derived on the host from the parameters.
+template <typename T>
 struct StepConst {
-  float gamma, beta, inv_gb3;  // band half width, cut-off radius, 1/(gamma-beta)^3
-  float drift;                 // dt / h: drift in cells per unit C and |grad d|
-  float diff2;                 // delta dt / (p h^2): squared diffusion reach in cells per unit C d
-  float grad_thr;              // C dt^alpha of the fallback test
-  float weno_e;                // h^4 (eps = h^2 with indicators scaled by h^2)
-  float half_inv_h, inv_h;
+  T gamma, beta, inv_gb3;  // band half width, cut-off radius, 1/(gamma-beta)^3
+  T drift;                 // dt / h: drift in cells per unit C and |grad d|
+  T diff2;                 // delta dt / (p h^2): squared diffusion reach in cells per unit C d
+  T grad_thr;              // C dt^alpha of the fallback test
+  T weno_e;                // h^4 (eps = h^2 with indicators scaled by h^2)
+  T half_inv_h, inv_h;
 };
 
 __device__ __forceinline__ void decode(const DevGrid& g, uint32_t code, int& i, int& j, int& k) {
@@ -62,19 +76,28 @@ __device__ __forceinline__ uint32_t lin(const DevGrid& g, int i, int j, int k) {
   return (uint32_t)i * g.s0 + (uint32_t)j * g.s1 + (uint32_t)k;
 }
 
+// Reciprocal: the hardware approximation in single precision (1 ulp); in
+// double, the approximation refined by one Newton step.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Cut-off of eq. (cutoff).
-__device__ __forceinline__ float cutoff(float phi, const StepConst& c) {
-  float a = fabsf(phi);
-  if (a <= c.beta) return 1.0f;
-  if (a > c.gamma) return 0.0f;
-  float t = a - c.gamma;
-  return t * t * (2.0f * a + c.gamma - 3.0f * c.beta) * c.inv_gb3;
+template <typename T>
+__device__ __forceinline__ T cutoff(T phi, const StepConst<T>& c) {
+  T a = fabs(phi);
+  if (a <= c.beta) return T(1);
+  if (a > c.gamma) return T(0);
+  T t = a - c.gamma;
+  return t * t * (T(2) * a + c.gamma - T(3) * c.beta) * c.inv_gb3;
 }
 
 // Centred difference along one axis from the node value and its two
 // neighbours; first-order one-sided on the domain boundary.
-__device__ __forceinline__ float cdiff(float vm, float v, float vp, int idx, int n,
-                                       const StepConst& c) {
+template <typename T>
+__device__ __forceinline__ T cdiff(T vm, T v, T vp, int idx, int n, const StepConst<T>& c) {
   if (idx > 0 && idx < n - 1) return (vp - vm) * c.half_inv_h;
   if (idx == 0) return (vp - v) * c.inv_h;
   return (v - vm) * c.inv_h;
@@ -82,22 +105,24 @@ __device__ __forceinline__ float cdiff(float vm, float v, float vp, int idx, int
 
 // Cell and local coordinate of a foot point given as node index + offset in
 // cells, the point being moved onto the grid if it left it.
+template <typename T>
 struct Loc {
   int i0;
-  float t;
+  T t;
 };
 
-__device__ __forceinline__ Loc locate(int i, float off, int n) {
-  float fl = floorf(off);
-  Loc r;
+template <typename T>
+__device__ __forceinline__ Loc<T> locate(int i, T off, int n) {
+  T fl = floor(off);
+  Loc<T> r;
   r.i0 = i + (int)fl;
   r.t = off - fl;
   if (r.i0 < 0) {
     r.i0 = 0;
-    r.t = 0.0f;
+    r.t = T(0);
   } else if (r.i0 >= n - 1) {
     r.i0 = n - 2;
-    r.t = 1.0f;
+    r.t = T(1);
   }
   return r;
 }
@@ -105,18 +130,20 @@ __device__ __forceinline__ Loc locate(int i, float off, int n) {
 __device__ __forceinline__ int clampi(int i, int n) { return i < 0 ? 0 : (i > n - 1 ? n - 1 : i); }
 
 // Per-axis constants of the one-dimensional WENO interpolant at s = t.
+template <typename T>
 struct WC {
-  float t, ht, ht2, tr, cL, cR;
+  T t, ht, ht2, tr, cL, cR;
 };
 
-__device__ __forceinline__ WC wcoef(float t) {
-  WC c;
+template <typename T>
+__device__ __forceinline__ WC<T> wcoef(T t) {
+  WC<T> c;
   c.t = t;
-  c.ht = 0.5f * t;
-  c.ht2 = 0.5f * t * t;
+  c.ht = T(0.5) * t;
+  c.ht2 = T(0.5) * t * t;
   c.tr = c.ht2 - c.ht;
-  c.cL = (2.0f - t) * (1.0f / 3.0f);
-  c.cR = (1.0f + t) * (1.0f / 3.0f);
+  c.cL = (T(2) - t) * (T(1) / T(3));
+  c.cR = (T(1) + t) * (T(1) / T(3));
   return c;
 }
 
@@ -126,25 +153,28 @@ __device__ __forceinline__ WC wcoef(float t) {
 // are the two quadratic interpolants, the indicators are D^2/h^2 and eps = h^2,
 // so with s_k = D_k^2 + h^4 the weights are w_L = C_L s_R^2 / (C_L s_R^2 + C_R s_L^2)
 // (the common factor h^4 of alpha_L and alpha_R cancels).
-__device__ __forceinline__ float weno1(float v0, float v1, float v2, float v3, const WC& c,
-                                       float e) {
-  float dL = fmaf(-2.0f, v1, v0 + v2);
-  float dR = fmaf(-2.0f, v2, v1 + v3);
-  float pL = fmaf(c.ht2, dL, fmaf(c.ht, v2 - v0, v1));
-  float pR = fmaf(c.tr, dR, fmaf(c.t, v2 - v1, v1));
-  float sL = fmaf(dL, dL, e);
-  float sR = fmaf(dR, dR, e);
-  float aL = c.cL * (sR * sR);
-  float aR = c.cR * (sL * sL);
-  float w = aL * __builtin_amdgcn_rcpf(aL + aR);
-  return fmaf(w, pL - pR, pR);
+template <typename T>
+__device__ __forceinline__ T weno1(T v0, T v1, T v2, T v3, const WC<T>& c, T e) {
+  T dL = fma(T(-2), v1, v0 + v2);
+  T dR = fma(T(-2), v2, v1 + v3);
+  T pL = fma(c.ht2, dL, fma(c.ht, v2 - v0, v1));
+  T pR = fma(c.tr, dR, fma(c.t, v2 - v1, v1));
+  T sL = fma(dL, dL, e);
+  T sR = fma(dR, dR, e);
+  T aL = c.cL * (sR * sR);
+  T aR = c.cR * (sL * sL);
+  T w = aL * rcp(aL + aR);
+  return fma(w, pL - pR, pR);
 }
 
 // Four values along the last axis at k0-1 .. k0+2 (indices clamped to the
 // grid, i.e. the boundary node repeated) of the row starting at `row`.
-__device__ __forceinline__ f4u row4(const float* __restrict__ A, uint32_t row, int k0, int n) {
-  if (k0 >= 1 && k0 + 2 <= n - 1) return *(const f4u*)(A + row + (uint32_t)(k0 - 1));
-  f4u r;
+template <typename T>
+__device__ __forceinline__ typename Vec<T>::v4 row4(const T* __restrict__ A, uint32_t row, int k0,
+                                                   int n) {
+  typedef typename Vec<T>::v4 V;
+  if (k0 >= 1 && k0 + 2 <= n - 1) return *(const V*)(A + row + (uint32_t)(k0 - 1));
+  V r;
   r.x = A[row + clampi(k0 - 1, n)];
   r.y = A[row + clampi(k0, n)];
   r.z = A[row + clampi(k0 + 1, n)];
@@ -154,19 +184,20 @@ __device__ __forceinline__ f4u row4(const float* __restrict__ A, uint32_t row, i
 
 // Tensor WENO (Section 3.2): one-dimensional WENO along the last axis
 // first, then along the previous axes, x last.
-__device__ __forceinline__ float interp_weno3(const float* __restrict__ A, const DevGrid& g,
-                                              const Loc& lx, const Loc& ly, const Loc& lz,
-                                              float e) {
-  const WC cx = wcoef(lx.t), cy = wcoef(ly.t), cz = wcoef(lz.t);
-  float wx[4];
-LSR_UNROLL(LSR_WENO_X_UNROLL)
+template <typename T>
+__device__ __forceinline__ T interp_weno3(const T* __restrict__ A, const DevGrid& g,
+                                          const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz,
+                                          T e) {
+  const WC<T> cx = wcoef(lx.t), cy = wcoef(ly.t), cz = wcoef(lz.t);
+  T wx[4];
+  LSR_UNROLL(LSR_WENO_X_UNROLL)
   for (int a = 0; a < 4; ++a) {
     const uint32_t ra = (uint32_t)clampi(lx.i0 - 1 + a, g.n0) * g.s0;
-    float wy[4];
+    T wy[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const uint32_t row = ra + (uint32_t)clampi(ly.i0 - 1 + b, g.n1) * g.s1;
-      f4u r = row4(A, row, lz.i0, g.n2);
+      typename Vec<T>::v4 r = row4(A, row, lz.i0, g.n2);
       wy[b] = weno1(r.x, r.y, r.z, r.w, cz, e);
     }
     wx[a] = weno1(wy[0], wy[1], wy[2], wy[3], cy, e);
@@ -174,132 +205,135 @@ LSR_UNROLL(LSR_WENO_X_UNROLL)
   return weno1(wx[0], wx[1], wx[2], wx[3], cx, e);
 }
 
-__device__ __forceinline__ float interp_weno2(const float* __restrict__ A, const DevGrid& g,
-                                              const Loc& lx, const Loc& ly, float e) {
-  const WC cx = wcoef(lx.t), cy = wcoef(ly.t);
-  float wx[4];
+template <typename T>
+__device__ __forceinline__ T interp_weno2(const T* __restrict__ A, const DevGrid& g,
+                                          const Loc<T>& lx, const Loc<T>& ly, T e) {
+  const WC<T> cx = wcoef(lx.t), cy = wcoef(ly.t);
+  T wx[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const uint32_t row = (uint32_t)clampi(lx.i0 - 1 + a, g.n0) * g.s0;
-    f4u r = row4(A, row, ly.i0, g.n1);
+    typename Vec<T>::v4 r = row4(A, row, ly.i0, g.n1);
     wx[a] = weno1(r.x, r.y, r.z, r.w, cy, e);
   }
   return weno1(wx[0], wx[1], wx[2], wx[3], cx, e);
 }
 
 // Multilinear interpolation, eq. (IQ1).
-__device__ __forceinline__ float interp_q1_3(const float* __restrict__ A, const DevGrid& g,
-                                             const Loc& lx, const Loc& ly, const Loc& lz) {
+template <typename T>
+__device__ __forceinline__ T interp_q1_3(const T* __restrict__ A, const DevGrid& g,
+                                         const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) {
+  typedef typename Vec<T>::v2 V2;
   const uint32_t r00 = (uint32_t)lx.i0 * g.s0 + (uint32_t)ly.i0 * g.s1 + (uint32_t)lz.i0;
-  f2u a00 = *(const f2u*)(A + r00);
-  f2u a01 = *(const f2u*)(A + r00 + g.s1);
-  f2u a10 = *(const f2u*)(A + r00 + g.s0);
-  f2u a11 = *(const f2u*)(A + r00 + g.s0 + g.s1);
-  float tz = lz.t, ty = ly.t, tx = lx.t;
-  float b00 = fmaf(tz, a00.y - a00.x, a00.x);
-  float b01 = fmaf(tz, a01.y - a01.x, a01.x);
-  float b10 = fmaf(tz, a10.y - a10.x, a10.x);
-  float b11 = fmaf(tz, a11.y - a11.x, a11.x);
-  float c0 = fmaf(ty, b01 - b00, b00);
-  float c1 = fmaf(ty, b11 - b10, b10);
-  return fmaf(tx, c1 - c0, c0);
+  V2 a00 = *(const V2*)(A + r00);
+  V2 a01 = *(const V2*)(A + r00 + g.s1);
+  V2 a10 = *(const V2*)(A + r00 + g.s0);
+  V2 a11 = *(const V2*)(A + r00 + g.s0 + g.s1);
+  T tz = lz.t, ty = ly.t, tx = lx.t;
+  T b00 = fma(tz, a00.y - a00.x, a00.x);
+  T b01 = fma(tz, a01.y - a01.x, a01.x);
+  T b10 = fma(tz, a10.y - a10.x, a10.x);
+  T b11 = fma(tz, a11.y - a11.x, a11.x);
+  T c0 = fma(ty, b01 - b00, b00);
+  T c1 = fma(ty, b11 - b10, b10);
+  return fma(tx, c1 - c0, c0);
 }
 
-__device__ __forceinline__ float interp_q1_2(const float* __restrict__ A, const DevGrid& g,
-                                             const Loc& lx, const Loc& ly) {
+template <typename T>
+__device__ __forceinline__ T interp_q1_2(const T* __restrict__ A, const DevGrid& g,
+                                         const Loc<T>& lx, const Loc<T>& ly) {
+  typedef typename Vec<T>::v2 V2;
   const uint32_t r0 = (uint32_t)lx.i0 * g.s0 + (uint32_t)ly.i0;
-  f2u a0 = *(const f2u*)(A + r0);
-  f2u a1 = *(const f2u*)(A + r0 + g.s0);
-  float b0 = fmaf(ly.t, a0.y - a0.x, a0.x);
-  float b1 = fmaf(ly.t, a1.y - a1.x, a1.x);
-  return fmaf(lx.t, b1 - b0, b0);
+  V2 a0 = *(const V2*)(A + r0);
+  V2 a1 = *(const V2*)(A + r0 + g.s0);
+  T b0 = fma(ly.t, a0.y - a0.x, a0.x);
+  T b1 = fma(ly.t, a1.y - a1.x, a1.x);
+  return fma(lx.t, b1 - b0, b0);
 }
 
 enum { UPD_FALLBACK = 1, UPD_FRAME0 = 2 };
-
 
 // New value of band node (i,j,k) from phi^n = A: eqs. (SL2d)/(SL3d) with
 // C = c(phi^n_j) (p = 1), the fallback of eq. (SL:2) and the cut of eq. (cut).
 // dp = (d_x, d_y, d_z, d) with the centred gradient of d precomputed.
 // Foot points are carried as node index + offset in cells.
-template <int DIM, int INTERP>
-__device__ __forceinline__ float sl_update(const float* __restrict__ A, const DevGrid& g,
-                                           const StepConst& c, int i, int j, int k, uint32_t idx,
-                                           float v, float4 dp, int& flags) {
-  float gx, gy, gz = 0.0f;
-  float xm = i > 0 ? A[idx - g.s0] : v, xp = i < g.n0 - 1 ? A[idx + g.s0] : v;
-  float ym = j > 0 ? A[idx - g.s1] : v, yp = j < g.n1 - 1 ? A[idx + g.s1] : v;
+template <int DIM, int INTERP, typename T>
+__device__ __forceinline__ T sl_update(const T* __restrict__ A, const DevGrid& g,
+                                       const StepConst<T>& c, int i, int j, int k, uint32_t idx,
+                                       T v, typename Vec<T>::pack dp, int& flags) {
+  T gx, gy, gz = T(0);
+  T xm = i > 0 ? A[idx - g.s0] : v, xp = i < g.n0 - 1 ? A[idx + g.s0] : v;
+  T ym = j > 0 ? A[idx - g.s1] : v, yp = j < g.n1 - 1 ? A[idx + g.s1] : v;
   gx = cdiff(xm, v, xp, i, g.n0, c);
   gy = cdiff(ym, v, yp, j, g.n1, c);
-  float zm = v, zp = v;
+  T zm = v, zp = v;
   if (DIM == 3) {
     zm = k > 0 ? A[idx - 1] : v;
     zp = k < g.n2 - 1 ? A[idx + 1] : v;
     gz = cdiff(zm, v, zp, k, g.n2, c);
   }
-  float nrm2 = gx * gx + gy * gy + gz * gz;
-  float nrm = sqrtf(nrm2);
-  float out;
+  T nrm = sqrt(gx * gx + gy * gy + gz * gz);
+  T out;
   if (nrm < c.grad_thr) {
-    float sum = 0.0f, cnt = 0.0f;
-    if (i > 0) { sum += xm; cnt += 1.0f; }
-    if (i < g.n0 - 1) { sum += xp; cnt += 1.0f; }
-    if (j > 0) { sum += ym; cnt += 1.0f; }
-    if (j < g.n1 - 1) { sum += yp; cnt += 1.0f; }
+    T sum = T(0), cnt = T(0);
+    if (i > 0) { sum += xm; cnt += T(1); }
+    if (i < g.n0 - 1) { sum += xp; cnt += T(1); }
+    if (j > 0) { sum += ym; cnt += T(1); }
+    if (j < g.n1 - 1) { sum += yp; cnt += T(1); }
     if (DIM == 3) {
-      if (k > 0) { sum += zm; cnt += 1.0f; }
-      if (k < g.n2 - 1) { sum += zp; cnt += 1.0f; }
+      if (k > 0) { sum += zm; cnt += T(1); }
+      if (k < g.n2 - 1) { sum += zp; cnt += T(1); }
     }
     out = sum / cnt;
     flags |= UPD_FALLBACK;
   } else {
-    const float C = cutoff(v, c);
-    const float dd = dp.w;
-    const float amp = sqrtf(C * dd * c.diff2);  // diffusion reach in cells
-    const float cd = C * c.drift;
-    const float bx = cd * dp.x, by = cd * dp.y;
+    const T C = cutoff(v, c);
+    const T dd = dp.w;
+    const T amp = sqrt(C * dd * c.diff2);  // diffusion reach in cells
+    const T cd = C * c.drift;
+    const T bx = cd * dp.x, by = cd * dp.y;
     if (DIM == 2) {
-      const float inv = 1.0f / nrm;
-      const float sx = gy * inv * amp, sy = -gx * inv * amp;  // eq. (sigma2d), scaled
-      float acc = 0.0f;
+      const T inv = T(1) / nrm;
+      const T sx = gy * inv * amp, sy = -gx * inv * amp;  // eq. (sigma2d), scaled
+      T acc = T(0);
 #pragma unroll
       for (int l = -1; l <= 1; l += 2) {
-        Loc lx = locate(i, bx + sx * (float)l, g.n0);
-        Loc ly = locate(j, by + sy * (float)l, g.n1);
+        Loc<T> lx = locate(i, bx + sx * T(l), g.n0);
+        Loc<T> ly = locate(j, by + sy * T(l), g.n1);
         acc += INTERP == 0 ? interp_q1_2(A, g, lx, ly) : interp_weno2(A, g, lx, ly, c.weno_e);
       }
-      out = 0.5f * acc;
+      out = T(0.5) * acc;
     } else {
-      const float bz = cd * dp.z;
-      float n1x, n1y, n1z, n2x, n2y, n2z;
-      const float s2 = gx * gx + gz * gz;
-      if (s2 != 0.0f) {  // eq. (sigma3d)
-        const float s = sqrtf(s2);
-        const float is = 1.0f / s;
-        const float isn = is / nrm;
-        n1x = -gz * is; n1y = 0.0f; n1z = gx * is;
+      const T bz = cd * dp.z;
+      T n1x, n1y, n1z, n2x, n2y, n2z;
+      const T s2 = gx * gx + gz * gz;
+      if (s2 != T(0)) {  // eq. (sigma3d)
+        const T s = sqrt(s2);
+        const T is = T(1) / s;
+        const T isn = is / nrm;
+        n1x = -gz * is; n1y = T(0); n1z = gx * is;
         n2x = -gx * gy * isn; n2y = s / nrm; n2z = -gy * gz * isn;
       } else {
-        n1x = 1.0f; n1y = 0.0f; n1z = 0.0f;
-        n2x = 0.0f; n2y = 0.0f; n2z = 1.0f;
+        n1x = T(1); n1y = T(0); n1z = T(0);
+        n2x = T(0); n2y = T(0); n2z = T(1);
         flags |= UPD_FRAME0;
       }
       n1x *= amp; n1y *= amp; n1z *= amp;
       n2x *= amp; n2y *= amp; n2z *= amp;
-      float acc = 0.0f;
-LSR_UNROLL(LSR_FOOT_UNROLL)
+      T acc = T(0);
+      LSR_UNROLL(LSR_FOOT_UNROLL)
       for (int q = 0; q < 4; ++q) {
-        const float f1 = (q & 2) ? 1.0f : -1.0f, f2 = (q & 1) ? 1.0f : -1.0f;
-        Loc lx = locate(i, bx + f1 * n1x + f2 * n2x, g.n0);
-        Loc ly = locate(j, by + f1 * n1y + f2 * n2y, g.n1);
-        Loc lz = locate(k, bz + f1 * n1z + f2 * n2z, g.n2);
+        const T f1 = (q & 2) ? T(1) : T(-1), f2 = (q & 1) ? T(1) : T(-1);
+        Loc<T> lx = locate(i, bx + f1 * n1x + f2 * n2x, g.n0);
+        Loc<T> ly = locate(j, by + f1 * n1y + f2 * n2y, g.n1);
+        Loc<T> lz = locate(k, bz + f1 * n1z + f2 * n2z, g.n2);
         acc += INTERP == 0 ? interp_q1_3(A, g, lx, ly, lz)
                            : interp_weno3(A, g, lx, ly, lz, c.weno_e);
       }
-      out = 0.25f * acc;
+      out = T(0.25) * acc;
     }
   }
-  return fminf(fmaxf(out, -c.gamma), c.gamma);
+  return fmin(fmax(out, -c.gamma), c.gamma);
 }
 
 }  // namespace lsr

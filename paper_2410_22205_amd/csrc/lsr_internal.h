@@ -1,5 +1,6 @@
-// Internal interface between the C-ABI layer (lsr_api.hip) and the kernels
-// (lsr_kernels.hip).  Not installed; the public interface is include/lsr.h.
+// Internal interface between the C-ABI layer (lsr_api.hip, lsr_batch.hip)
+// and the kernels (lsr_kernels.hip).  Not installed; the public interface is
+// include/lsr.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,12 +20,13 @@ struct BinGeom {
   double bw, inv_bw;
 };
 
+template <typename T>
 struct SLArgs {
   DevGrid g;
-  StepConst c;
-  const float* A;   // phi^n (read only)
-  float* B;         // phi^{n+1} (written on the list)
-  const float4* dp; // (grad d, d)
+  StepConst<T> c;
+  const T* A;                       // phi^n (read only)
+  T* B;                             // phi^{n+1} (written on the list)
+  const typename Vec<T>::pack* dp;  // (grad d, d)
   const uint32_t* Lin;
   uint32_t* Lout;
   const int32_t* cnt_in;
@@ -44,26 +46,28 @@ struct DilArgs {
   uint32_t epoch;
 };
 
+template <typename T>
 struct RArgs {
   DevGrid g;
-  StepConst c;
+  StepConst<T> c;
   const uint32_t* M;
   const int32_t* cnt;
-  const float* src;
-  float* dst;
+  const T* src;
+  T* dst;
   uint8_t* flags;
-  float dtau;
-  float floor_;
+  T dtau;
+  T floor_;
   unsigned long long* stats;
 };
 
+template <typename T>
 struct FinArgs {
   DevGrid g;
-  float gamma;
+  T gamma;
   const uint32_t* M;
   const int32_t* cnt_in;
-  float* cur;
-  float* other;
+  T* cur;
+  T* other;
   uint32_t* Lout;
   int32_t* cnt_out;
   int32_t* cnt_reset;
@@ -81,18 +85,25 @@ struct DistArgs {
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s);
-hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* args, float gamma,
-                           const float* src, float* A, float* B, int32_t* flag, hipStream_t s);
-hipError_t launch_band_scan(int dim, const DevGrid& g, float gamma, const float* A, uint32_t* L,
+template <typename T>
+hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* args, T gamma,
+                           const T* src, T* A, T* B, int32_t* flag, hipStream_t s);
+template <typename T>
+hipError_t launch_band_scan(int dim, const DevGrid& g, T gamma, const T* A, uint32_t* L,
                             int32_t* cnt, hipStream_t s);
-hipError_t launch_band_mask(const DevGrid& g, float gamma, const float* A, const uint32_t* L,
+template <typename T>
+hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_t* L,
                             const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
                             hipStream_t s);
-hipError_t launch_sl_step(int dim, int interp, const SLArgs& a, unsigned blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_sl_step(int dim, int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s);
 hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s);
-hipError_t launch_reinit_fix(int dim, const RArgs& a, unsigned blocks, hipStream_t s);
-hipError_t launch_reinit_iter(int dim, const RArgs& a, unsigned blocks, hipStream_t s);
-hipError_t launch_reinit_final(const FinArgs& a, unsigned blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_reinit_iter(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_reinit_final(const FinArgs<T>& a, unsigned blocks, hipStream_t s);
 hipError_t launch_bin_points(int dim, const BinGeom& bg, const double* pts, int64_t n,
                              int32_t* bin_count, int32_t* pt_bin, int32_t* flag, hipStream_t s);
 hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start, hipStream_t s);
@@ -102,6 +113,8 @@ hipError_t launch_scatter_points(int dim, const double* pts, int64_t n, const in
                                  const int32_t* start, int32_t* fill, double* sorted,
                                  hipStream_t s);
 hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s);
-hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, float4* dp, hipStream_t s);
+template <typename T>
+hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,
+                        hipStream_t s);
 
 }  // namespace lsr

@@ -1,0 +1,200 @@
+// Host-side job state shared by the single-job entry points (lsr_api.hip) and
+// the batched ones (lsr_batch.hip).  The plan_* functions fill the kernel
+// arguments of the next launch from the job state and advance that state
+// without launching anything, so a single job and a batch of jobs drive the
+// same kernels through the same sequence of buffers and counters.
+#pragma once
+
+#include <math.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lsr.h"
+#include "lsr_internal.h"
+
+namespace lsr {
+
+lsr_status fail(lsr_status st, const std::string& msg);
+
+#define LSR_HIP(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return ::lsr::fail(LSR_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+struct Layout {
+  size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, stamp, cnt, stats;
+  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ;
+  size_t total;
+  int nb[3];
+  int64_t nbins;
+};
+
+}  // namespace lsr
+
+struct lsr_job {
+  lsr_grid grid;
+  lsr_params prm;
+  bool fp64;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  lsr::Layout L;
+  int64_t max_points;
+  lsr::DevGrid dg;
+  lsr::BinGeom bg;
+  void* phi[2];
+  void* dp;
+  double* d64;
+  uint32_t* list[2];
+  uint32_t* listM;
+  uint8_t* mflags;
+  uint32_t* stamp;
+  int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins
+  unsigned long long* stats;
+  double* pts_raw;
+  double* pts;
+  int32_t* pt_bin;
+  int32_t* bin_count;
+  int32_t* bin_start;
+  int32_t* bin_fill;
+  uint32_t* occ;
+  unsigned list_blocks;
+  int cur;       // phi buffer holding the current phi
+  int cur_list;  // list buffer holding the current band list
+  int ring;      // counter slot holding the current list length
+  uint32_t epoch;
+  int64_t step_index;
+  int64_t n_reinits, n_steps;
+  bool has_d, has_phi;
+  bool in_batch;
+  // measurement hook
+  bool prof_on;
+  int prof_used;
+  std::vector<hipEvent_t> prof_ev;
+};
+
+namespace lsr {
+
+template <typename T>
+StepConst<T> step_const(const lsr_job* j, double dt) {
+  StepConst<T> c;
+  const double h = j->grid.h;
+  const lsr_params& p = j->prm;
+  c.gamma = (T)p.gamma;
+  c.beta = (T)p.beta;
+  const double gb = p.gamma - p.beta;
+  c.inv_gb3 = (T)(1.0 / (gb * gb * gb));
+  c.drift = (T)(dt / h);
+  c.diff2 = (T)(p.delta * dt / (p.p * h * h));
+  c.grad_thr = (T)(p.grad_C * pow(dt, p.grad_alpha));
+  c.weno_e = (T)(h * h * h * h);
+  c.half_inv_h = (T)(0.5 / h);
+  c.inv_h = (T)(1.0 / h);
+  return c;
+}
+
+inline int32_t* ring_slot(lsr_job* j, int k) { return j->cnt + ((j->ring + k) % 3); }
+
+template <typename T>
+inline T* phi_buf(lsr_job* j, int b) {
+  return (T*)j->phi[b];
+}
+
+inline bool reinit_due(const lsr_job* j) {
+  return j->prm.reinit_every > 0 && j->step_index % j->prm.reinit_every == 0;
+}
+
+// Arguments of the next step kernel; advances buffers, list, ring, step index.
+template <typename T>
+SLArgs<T> plan_step(lsr_job* j, const StepConst<T>& c) {
+  SLArgs<T> a;
+  a.g = j->dg;
+  a.c = c;
+  a.dp = (const typename Vec<T>::pack*)j->dp;
+  a.stats = j->stats;
+  a.A = phi_buf<T>(j, j->cur);
+  a.B = phi_buf<T>(j, 1 - j->cur);
+  a.Lin = j->list[j->cur_list];
+  a.Lout = j->list[1 - j->cur_list];
+  a.cnt_in = ring_slot(j, 0);
+  a.cnt_out = ring_slot(j, 1);
+  a.cnt_reset = ring_slot(j, 2);
+  j->cur = 1 - j->cur;
+  j->cur_list = 1 - j->cur_list;
+  j->ring = (j->ring + 1) % 3;
+  j->step_index += 1;
+  j->n_steps += 1;
+  return a;
+}
+
+// Arguments of one reinitialisation: dilation, interface fix, iterations
+// (iter[it % 2] is the it-th), final cut and compaction.
+template <typename T>
+struct ReinitPlan {
+  DilArgs dil;
+  RArgs<T> fix;
+  RArgs<T> iter[2];
+  FinArgs<T> fin;
+  int iters;
+};
+
+// The stamp epoch must be bumped before planning; a wrap needs a stamp clear.
+inline bool stamp_needs_clear(const lsr_job* j) { return j->epoch == 0xFFFFFFFFu; }
+
+template <typename T>
+ReinitPlan<T> plan_reinit(lsr_job* j) {
+  ReinitPlan<T> r;
+  j->epoch += 1;
+  r.dil.g = j->dg;
+  r.dil.L = j->list[j->cur_list];
+  r.dil.cnt_in = ring_slot(j, 0);
+  r.dil.M = j->listM;
+  r.dil.cnt_out = ring_slot(j, 1);
+  r.dil.cnt_reset = ring_slot(j, 2);
+  r.dil.stamp = j->stamp;
+  r.dil.epoch = j->epoch;
+  j->ring = (j->ring + 1) % 3;
+
+  RArgs<T> ra;
+  ra.g = j->dg;
+  ra.c = step_const<T>(j, j->grid.h);
+  ra.M = j->listM;
+  ra.cnt = ring_slot(j, 0);
+  ra.flags = j->mflags;
+  ra.dtau = (T)j->prm.reinit_dtau;
+  ra.floor_ = (T)j->prm.interface_floor;
+  ra.stats = j->stats;
+  ra.src = phi_buf<T>(j, j->cur);
+  ra.dst = phi_buf<T>(j, 1 - j->cur);
+  r.fix = ra;
+  int w = 1 - j->cur;
+  for (int q = 0; q < 2; ++q) {
+    r.iter[q] = ra;
+    r.iter[q].src = phi_buf<T>(j, w);
+    r.iter[q].dst = phi_buf<T>(j, 1 - w);
+    w = 1 - w;
+  }
+  r.iters = j->prm.reinit_iters;
+  const int wf = (r.iters % 2 == 0) ? 1 - j->cur : j->cur;
+  r.fin.g = j->dg;
+  r.fin.gamma = (T)j->prm.gamma;
+  r.fin.M = j->listM;
+  r.fin.cnt_in = ring_slot(j, 0);
+  r.fin.cur = phi_buf<T>(j, wf);
+  r.fin.other = phi_buf<T>(j, 1 - wf);
+  r.fin.Lout = j->list[j->cur_list];
+  r.fin.cnt_out = ring_slot(j, 1);
+  r.fin.cnt_reset = ring_slot(j, 2);
+  j->ring = (j->ring + 1) % 3;
+  j->cur = wf;
+  j->n_reinits += 1;
+  return r;
+}
+
+lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp);
+lsr_status run_reinit(lsr_job* j);
+
+}  // namespace lsr

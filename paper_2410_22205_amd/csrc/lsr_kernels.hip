@@ -61,13 +61,13 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, uint64_t n) {
 // copy of the caller's array, cut to [-gamma, gamma]; written to both phi
 // buffers (A == NULL: only check the array).  flag[0] |= 1 for a non-finite
 // input value.
-template <int DIM>
+template <int DIM, typename T>
 __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2, double a3,
-                           double a4, float gamma, const float* __restrict__ src,
-                           float* __restrict__ A, float* __restrict__ B, int32_t* flag) {
+                           double a4, T gamma, const T* __restrict__ src, T* __restrict__ A,
+                           T* __restrict__ B, int32_t* flag) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.N;
        idx += gridDim.x * blockDim.x) {
-    float v;
+    T v;
     if (kind == 0) {
       v = src[idx];
       if (!isfinite(v)) atomicOr(flag, 1);
@@ -89,19 +89,18 @@ __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2,
         double rho = sqrt(x * x + y * y) - a3;
         s = sqrt(rho * rho + z * z) - a4;
       }
-      v = (float)s;
+      v = (T)s;
     }
     if (!A) continue;  // check-only pass over the caller's array
-    v = fminf(fmaxf(v, -gamma), gamma);
+    v = fmin(fmax(v, -gamma), gamma);
     A[idx] = v;
     B[idx] = v;
   }
 }
 
 // First band {|phi| < gamma} from a scan of the whole grid.
-template <int DIM>
-__global__ __launch_bounds__(256) void k_band_scan(DevGrid g, float gamma,
-                                                   const float* __restrict__ A,
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_band_scan(DevGrid g, T gamma, const T* __restrict__ A,
                                                    uint32_t* __restrict__ L, int32_t* cnt) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < g.N; base += stride) {
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(256) void k_band_scan(DevGrid g, float gamma,
     bool in = false;
     uint32_t code = 0;
     if (idx < g.N) {
-      in = fabsf(A[idx]) < gamma;
+      in = fabs(A[idx]) < gamma;
       uint32_t r = idx;
       int k = 0;
       if (DIM == 3) {
@@ -123,8 +122,8 @@ __global__ __launch_bounds__(256) void k_band_scan(DevGrid g, float gamma,
 }
 
 // Band mask of the current list: mask[idx] = 1 iff |phi| < gamma.
-__global__ __launch_bounds__(256) void k_band_mask(DevGrid g, float gamma,
-                                                   const float* __restrict__ A,
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* __restrict__ A,
                                                    const uint32_t* __restrict__ L,
                                                    const int32_t* cnt, uint8_t* __restrict__ mask,
                                                    int32_t* count) {
@@ -139,7 +138,7 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, float gamma,
       int i, j, k;
       decode(g, L[e], i, j, k);
       const uint32_t idx = lin(g, i, j, k);
-      in = fabsf(A[idx]) < gamma;
+      in = fabs(A[idx]) < gamma;
       if (in && mask) mask[idx] = 1;
     }
     tot += wave_count(in);
@@ -154,8 +153,8 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, float gamma,
 // the previous step get their value copied, so that A and B agree off the
 // new list.  The new list is the set of entries updated here (the band of
 // this step).  cnt_reset is the list counter the next step will write.
-template <int DIM, int INTERP>
-__global__ __launch_bounds__(256) void k_sl_step(SLArgs a) {
+template <int DIM, int INTERP, typename T>
+__global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -171,11 +170,11 @@ __global__ __launch_bounds__(256) void k_sl_step(SLArgs a) {
       int i, j, k;
       decode(a.g, code, i, j, k);
       const uint32_t idx = lin(a.g, i, j, k);
-      const float v = a.A[idx];
-      float nv = v;
-      if (fabsf(v) < a.c.gamma) {
+      const T v = a.A[idx];
+      T nv = v;
+      if (fabs(v) < a.c.gamma) {
         act = true;
-        nv = sl_update<DIM, INTERP>(a.A, a.g, a.c, i, j, k, idx, v, a.dp[idx], fl);
+        nv = sl_update<DIM, INTERP, T>(a.A, a.g, a.c, i, j, k, idx, v, a.dp[idx], fl);
       }
       a.B[idx] = nv;
     }
@@ -226,8 +225,8 @@ __global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
 // working copy W: W = phi~ / max(|grad_c phi~|, floor) on interface nodes
 // (a face neighbour of opposite or zero sign), W = phi~ elsewhere on Gbar.
 // flags: bit 7 interface, bits 0-1 sign of phi~ (1 positive, 2 negative).
-template <int DIM>
-__global__ __launch_bounds__(256) void k_reinit_fix(RArgs a) {
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
   const int n = *a.cnt;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t stride = gridDim.x * 256u;
@@ -240,27 +239,28 @@ __global__ __launch_bounds__(256) void k_reinit_fix(RArgs a) {
       int i, j, k;
       decode(a.g, a.M[e], i, j, k);
       const uint32_t idx = lin(a.g, i, j, k);
-      const float t = a.src[idx];
-      const float xm = i > 0 ? a.src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? a.src[idx + a.g.s0] : t;
-      const float ym = j > 0 ? a.src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? a.src[idx + a.g.s1] : t;
-      float zm = t, zp = t;
+      const T t = a.src[idx];
+      const T xm = i > 0 ? a.src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? a.src[idx + a.g.s0] : t;
+      const T ym = j > 0 ? a.src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? a.src[idx + a.g.s1] : t;
+      T zm = t, zp = t;
       if (DIM == 3) {
         zm = k > 0 ? a.src[idx - 1] : t;
         zp = k < a.g.n2 - 1 ? a.src[idx + 1] : t;
       }
-      itf = (i > 0 && t * xm <= 0.0f) || (i < a.g.n0 - 1 && t * xp <= 0.0f) ||
-            (j > 0 && t * ym <= 0.0f) || (j < a.g.n1 - 1 && t * yp <= 0.0f);
-      if (DIM == 3) itf = itf || (k > 0 && t * zm <= 0.0f) || (k < a.g.n2 - 1 && t * zp <= 0.0f);
-      float w = t;
+      const T z0 = T(0);
+      itf = (i > 0 && t * xm <= z0) || (i < a.g.n0 - 1 && t * xp <= z0) ||
+            (j > 0 && t * ym <= z0) || (j < a.g.n1 - 1 && t * yp <= z0);
+      if (DIM == 3) itf = itf || (k > 0 && t * zm <= z0) || (k < a.g.n2 - 1 && t * zp <= z0);
+      T w = t;
       if (itf) {
-        const float gx = cdiff(xm, t, xp, i, a.g.n0, a.c);
-        const float gy = cdiff(ym, t, yp, j, a.g.n1, a.c);
-        const float gz = DIM == 3 ? cdiff(zm, t, zp, k, a.g.n2, a.c) : 0.0f;
-        const float nr = fmaxf(sqrtf(gx * gx + gy * gy + gz * gz), a.floor_);
+        const T gx = cdiff(xm, t, xp, i, a.g.n0, a.c);
+        const T gy = cdiff(ym, t, yp, j, a.g.n1, a.c);
+        const T gz = DIM == 3 ? cdiff(zm, t, zp, k, a.g.n2, a.c) : z0;
+        const T nr = fmax(sqrt(gx * gx + gy * gy + gz * gz), a.floor_);
         w = t / nr;
       }
       a.dst[idx] = w;
-      a.flags[e] = (uint8_t)((itf ? 0x80 : 0) | (t > 0.0f ? 1 : (t < 0.0f ? 2 : 0)));
+      a.flags[e] = (uint8_t)((itf ? 0x80 : 0) | (t > z0 ? 1 : (t < z0 ? 2 : 0)));
     }
     nif += wave_count(itf);
     ng += wave_count(valid);
@@ -274,8 +274,8 @@ __global__ __launch_bounds__(256) void k_reinit_fix(RArgs a) {
 // One forward-Euler pseudo-time step of phi_tau + S (|grad phi| - 1) = 0 on
 // Gbar minus the interface set, first-order upwind (Godunov) gradient; a
 // missing neighbour contributes no difference.  src -> dst on Gbar.
-template <int DIM>
-__global__ __launch_bounds__(256) void k_reinit_iter(RArgs a) {
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
   const int n = *a.cnt;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t stride = gridDim.x * 256u;
@@ -286,36 +286,38 @@ __global__ __launch_bounds__(256) void k_reinit_iter(RArgs a) {
     decode(a.g, a.M[e], i, j, k);
     const uint32_t idx = lin(a.g, i, j, k);
     const uint8_t f = a.flags[e];
-    float v = a.src[idx];
+    T v = a.src[idx];
     if (!(f & 0x80) && (f & 3)) {
       const bool pos = f & 1;
-      float G2 = 0.0f;
+      const T z0 = T(0);
+      T G2 = z0;
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) {
         const int ci = ax == 0 ? i : (ax == 1 ? j : k);
         const int nn = ax == 0 ? a.g.n0 : (ax == 1 ? a.g.n1 : a.g.n2);
         const uint32_t s = ax == 0 ? a.g.s0 : (ax == 1 ? a.g.s1 : 1u);
-        const float Dm = ci > 0 ? (v - a.src[idx - s]) * a.c.inv_h : 0.0f;
-        const float Dp = ci < nn - 1 ? (a.src[idx + s] - v) * a.c.inv_h : 0.0f;
-        float t1, t2;
+        const T Dm = ci > 0 ? (v - a.src[idx - s]) * a.c.inv_h : z0;
+        const T Dp = ci < nn - 1 ? (a.src[idx + s] - v) * a.c.inv_h : z0;
+        T t1, t2;
         if (pos) {
-          t1 = Dm > 0.0f ? Dm * Dm : 0.0f;
-          t2 = Dp < 0.0f ? Dp * Dp : 0.0f;
+          t1 = Dm > z0 ? Dm * Dm : z0;
+          t2 = Dp < z0 ? Dp * Dp : z0;
         } else {
-          t1 = Dm < 0.0f ? Dm * Dm : 0.0f;
-          t2 = Dp > 0.0f ? Dp * Dp : 0.0f;
+          t1 = Dm < z0 ? Dm * Dm : z0;
+          t2 = Dp > z0 ? Dp * Dp : z0;
         }
-        G2 += fmaxf(t1, t2);
+        G2 += fmax(t1, t2);
       }
-      const float S = pos ? 1.0f : -1.0f;
-      v = v - a.dtau * S * (sqrtf(G2) - 1.0f);
+      const T S = pos ? T(1) : T(-1);
+      v = v - a.dtau * S * (sqrt(G2) - T(1));
     }
     a.dst[idx] = v;
   }
 }
 
 // Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
-__global__ __launch_bounds__(256) void k_reinit_final(FinArgs a) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -329,10 +331,10 @@ __global__ __launch_bounds__(256) void k_reinit_final(FinArgs a) {
       int i, j, k;
       decode(a.g, code, i, j, k);
       const uint32_t idx = lin(a.g, i, j, k);
-      const float v = fminf(fmaxf(a.cur[idx], -a.gamma), a.gamma);
+      const T v = fmin(fmax(a.cur[idx], -a.gamma), a.gamma);
       a.cur[idx] = v;
       a.other[idx] = v;
-      in = fabsf(v) < a.gamma;
+      in = fabs(v) < a.gamma;
     }
     wave_append(in, code, a.Lout, a.cnt_out);
   }
@@ -613,9 +615,9 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
 }
 
 // Centred gradient of d (one-sided on the boundary), in double, packed with
-// d itself: dp = (d_x, d_y, d_z, d) as floats (d_z = 0 in 2D).
-template <int DIM>
-__global__ void k_dpack(DevGrid g, const double* __restrict__ d, float4* __restrict__ dp) {
+// d itself: dp = (d_x, d_y, d_z, d) in the state's precision (d_z = 0 in 2D).
+template <int DIM, typename P>
+__global__ void k_dpack(DevGrid g, const double* __restrict__ d, P* __restrict__ dp) {
   for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.N;
        idx += gridDim.x * blockDim.x) {
     uint32_t r = idx;
@@ -640,7 +642,13 @@ __global__ void k_dpack(DevGrid g, const double* __restrict__ d, float4* __restr
       else
         gr[ax] = (v - d[idx - st[ax]]) / g.hd;
     }
-    dp[idx] = make_float4((float)gr[0], (float)gr[1], (float)gr[2], (float)v);
+    typedef decltype(dp->x) E;
+    P out;
+    out.x = (E)gr[0];
+    out.y = (E)gr[1];
+    out.z = (E)gr[2];
+    out.w = (E)v;
+    dp[idx] = out;
   }
 }
 
@@ -663,47 +671,52 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* args, float gamma,
-                           const float* src, float* A, float* B, int32_t* flag, hipStream_t s) {
+template <typename T>
+hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* args, T gamma,
+                           const T* src, T* A, T* B, int32_t* flag, hipStream_t s) {
   dim3 gr(grid_for(g.N, 256, 8192)), bl(256);
   if (dim == 3)
-    hipLaunchKernelGGL(k_init_phi<3>, gr, bl, 0, s, g, kind, args[0], args[1], args[2], args[3],
-                       args[4], gamma, src, A, B, flag);
+    hipLaunchKernelGGL((k_init_phi<3, T>), gr, bl, 0, s, g, kind, args[0], args[1], args[2],
+                       args[3], args[4], gamma, src, A, B, flag);
   else
-    hipLaunchKernelGGL(k_init_phi<2>, gr, bl, 0, s, g, kind, args[0], args[1], args[2], args[3],
-                       args[4], gamma, src, A, B, flag);
+    hipLaunchKernelGGL((k_init_phi<2, T>), gr, bl, 0, s, g, kind, args[0], args[1], args[2],
+                       args[3], args[4], gamma, src, A, B, flag);
   return hipGetLastError();
 }
 
-hipError_t launch_band_scan(int dim, const DevGrid& g, float gamma, const float* A, uint32_t* L,
+template <typename T>
+hipError_t launch_band_scan(int dim, const DevGrid& g, T gamma, const T* A, uint32_t* L,
                             int32_t* cnt, hipStream_t s) {
   dim3 gr(grid_for(g.N, 256, 8192)), bl(256);
   if (dim == 3)
-    hipLaunchKernelGGL(k_band_scan<3>, gr, bl, 0, s, g, gamma, A, L, cnt);
+    hipLaunchKernelGGL((k_band_scan<3, T>), gr, bl, 0, s, g, gamma, A, L, cnt);
   else
-    hipLaunchKernelGGL(k_band_scan<2>, gr, bl, 0, s, g, gamma, A, L, cnt);
+    hipLaunchKernelGGL((k_band_scan<2, T>), gr, bl, 0, s, g, gamma, A, L, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_band_mask(const DevGrid& g, float gamma, const float* A, const uint32_t* L,
+template <typename T>
+hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_t* L,
                             const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_band_mask, dim3(blocks), dim3(256), 0, s, g, gamma, A, L, cnt, mask, count);
+  hipLaunchKernelGGL((k_band_mask<T>), dim3(blocks), dim3(256), 0, s, g, gamma, A, L, cnt, mask,
+                     count);
   return hipGetLastError();
 }
 
-hipError_t launch_sl_step(int dim, int interp, const SLArgs& a, unsigned blocks, hipStream_t s) {
+template <typename T>
+hipError_t launch_sl_step(int dim, int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s) {
   dim3 gr(blocks), bl(256);
   if (dim == 3) {
     if (interp == 0)
-      hipLaunchKernelGGL((k_sl_step<3, 0>), gr, bl, 0, s, a);
+      hipLaunchKernelGGL((k_sl_step<3, 0, T>), gr, bl, 0, s, a);
     else
-      hipLaunchKernelGGL((k_sl_step<3, 1>), gr, bl, 0, s, a);
+      hipLaunchKernelGGL((k_sl_step<3, 1, T>), gr, bl, 0, s, a);
   } else {
     if (interp == 0)
-      hipLaunchKernelGGL((k_sl_step<2, 0>), gr, bl, 0, s, a);
+      hipLaunchKernelGGL((k_sl_step<2, 0, T>), gr, bl, 0, s, a);
     else
-      hipLaunchKernelGGL((k_sl_step<2, 1>), gr, bl, 0, s, a);
+      hipLaunchKernelGGL((k_sl_step<2, 1, T>), gr, bl, 0, s, a);
   }
   return hipGetLastError();
 }
@@ -716,24 +729,27 @@ hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_reinit_fix(int dim, const RArgs& a, unsigned blocks, hipStream_t s) {
+template <typename T>
+hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s) {
   if (dim == 3)
-    hipLaunchKernelGGL(k_reinit_fix<3>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_reinit_fix<3, T>), dim3(blocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(k_reinit_fix<2>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_reinit_fix<2, T>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_reinit_iter(int dim, const RArgs& a, unsigned blocks, hipStream_t s) {
+template <typename T>
+hipError_t launch_reinit_iter(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s) {
   if (dim == 3)
-    hipLaunchKernelGGL(k_reinit_iter<3>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_reinit_iter<3, T>), dim3(blocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(k_reinit_iter<2>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_reinit_iter<2, T>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_reinit_final(const FinArgs& a, unsigned blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_reinit_final, dim3(blocks), dim3(256), 0, s, a);
+template <typename T>
+hipError_t launch_reinit_final(const FinArgs<T>& a, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_reinit_final<T>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -778,13 +794,34 @@ hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, float4* dp, hipStream_t s) {
+template <typename T>
+hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,
+                        hipStream_t s) {
+  typedef typename Vec<T>::pack P;
   dim3 gr(grid_for(g.N, 256, 8192)), bl(256);
   if (dim == 3)
-    hipLaunchKernelGGL(k_dpack<3>, gr, bl, 0, s, g, d, dp);
+    hipLaunchKernelGGL((k_dpack<3, P>), gr, bl, 0, s, g, d, dp);
   else
-    hipLaunchKernelGGL(k_dpack<2>, gr, bl, 0, s, g, d, dp);
+    hipLaunchKernelGGL((k_dpack<2, P>), gr, bl, 0, s, g, d, dp);
   return hipGetLastError();
 }
+
+#define LSR_INSTANTIATE(T)                                                                        \
+  template hipError_t launch_init_phi<T>(int, const DevGrid&, int, const double*, T, const T*, T*, \
+                                         T*, int32_t*, hipStream_t);                              \
+  template hipError_t launch_band_scan<T>(int, const DevGrid&, T, const T*, uint32_t*, int32_t*,   \
+                                          hipStream_t);                                           \
+  template hipError_t launch_band_mask<T>(const DevGrid&, T, const T*, const uint32_t*,           \
+                                          const int32_t*, uint8_t*, int32_t*, unsigned,           \
+                                          hipStream_t);                                           \
+  template hipError_t launch_sl_step<T>(int, int, const SLArgs<T>&, unsigned, hipStream_t);       \
+  template hipError_t launch_reinit_fix<T>(int, const RArgs<T>&, unsigned, hipStream_t);          \
+  template hipError_t launch_reinit_iter<T>(int, const RArgs<T>&, unsigned, hipStream_t);         \
+  template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \
+  template hipError_t launch_dpack<T>(int, const DevGrid&, const double*, typename Vec<T>::pack*, \
+                                      hipStream_t);
+
+LSR_INSTANTIATE(float)
+LSR_INSTANTIATE(double)
 
 }  // namespace lsr

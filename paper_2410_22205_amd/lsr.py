@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "liblsr.so")
 LSR_OK, LSR_E_INVALID, LSR_E_NOMEM, LSR_E_DEVICE, LSR_E_STATE, LSR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 LSR_Q1, LSR_WENO = 0, 1
 LSR_PHI_ARRAY, LSR_PHI_SPHERE, LSR_PHI_TORUS = 0, 1, 2
+LSR_FP32, LSR_FP64 = 0, 1
 COUNTER_NAMES = ["node_updates", "fallbacks", "frame0", "reinits", "gbar", "interface", "steps"]
 
 EXPORTED = [
@@ -40,7 +41,8 @@ class LsrParams(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
                 ("grad_C", ctypes.c_double), ("grad_alpha", ctypes.c_double),
                 ("reinit_every", ctypes.c_int32), ("reinit_iters", ctypes.c_int32),
-                ("reinit_dtau", ctypes.c_double), ("interface_floor", ctypes.c_double)]
+                ("reinit_dtau", ctypes.c_double), ("interface_floor", ctypes.c_double),
+                ("precision", ctypes.c_int32)]
 
 
 class LsrError(RuntimeError):
@@ -64,7 +66,7 @@ def load():
         I64P = ctypes.POINTER(ctypes.c_int64)
         sig = {
             "lsr_params_default": [ctypes.c_int32, ctypes.c_double, PP],
-            "lsr_workspace_bytes": [GP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+            "lsr_workspace_bytes": [GP, PP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
             "lsr_create": [GP, PP, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
             "lsr_load_cloud": [_P, _P, ctypes.c_int64],
             "lsr_set_distance": [_P, _P],
@@ -121,9 +123,10 @@ def lsr_params_default(dim, h):
     return p
 
 
-def lsr_workspace_bytes(grid, max_points):
+def lsr_workspace_bytes(grid, params, max_points):
     out = ctypes.c_size_t()
-    _check(load().lsr_workspace_bytes(ctypes.byref(grid), int(max_points), ctypes.byref(out)))
+    _check(load().lsr_workspace_bytes(ctypes.byref(grid), ctypes.byref(params) if params else None,
+                                      int(max_points), ctypes.byref(out)))
     return out.value
 
 
@@ -216,9 +219,10 @@ def interp_code(name):
 class Job:
     """One reconstruction on the current device.
 
-    grid: {"dim", "n", "lo", "h"}; params: overrides of lsr_params_default;
-    max_points: largest cloud to be loaded; stream: a torch.cuda.Stream
-    (default: the current stream)."""
+    grid: {"dim", "n", "lo", "h"}; params: overrides of lsr_params_default
+    (``precision``: "fp32" or "fp64" also accepted); max_points: largest
+    cloud to be loaded; stream: a torch.cuda.Stream (default: the current
+    stream)."""
 
     def __init__(self, grid, params=None, max_points=0, stream=None):
         import torch
@@ -226,11 +230,20 @@ class Job:
         self.grid_dict = dict(grid)
         self.grid = make_grid(grid)
         self.params = lsr_params_default(self.grid.dim, self.grid.h)
-        for k, v in (params or {}).items():
+        params = dict(params or {})
+        if isinstance(params.get("precision"), str):
+            params["precision"] = {"fp32": LSR_FP32, "fp64": LSR_FP64}[params["precision"]]
+        for k, v in params.items():
             setattr(self.params, k, v)
+        if "reinit_iters" not in params and ("gamma" in params or "reinit_dtau" in params):
+            # the default iteration count follows the band width: ceil((gamma + h)/dtau)
+            p = self.params
+            p.reinit_iters = int(np.ceil((p.gamma + self.grid.h) / p.reinit_dtau - 1e-9))
         self.shape = tuple(int(v) for v in grid["n"][: self.grid.dim])
         self.nodes = int(np.prod(self.shape))
-        self.ws_bytes = lsr_workspace_bytes(self.grid, max_points)
+        self.fp64 = self.params.precision == LSR_FP64
+        self.dtype = torch.float64 if self.fp64 else torch.float32
+        self.ws_bytes = lsr_workspace_bytes(self.grid, self.params, max_points)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.stream.device)
         self.handle = lsr_create(self.grid, self.params, self.ws.data_ptr(), self.ws_bytes,
@@ -251,14 +264,14 @@ class Job:
         lsr_set_distance(self.handle, dd.data_ptr())
 
     def distance(self):
-        out = self.torch.empty(self.nodes, dtype=self.torch.float32, device=self.stream.device)
+        out = self.torch.empty(self.nodes, dtype=self.torch.float64, device=self.stream.device)
         lsr_get_distance(self.handle, out.data_ptr())
         self.stream.synchronize()
         return out.cpu().numpy().reshape(self.shape)
 
     def init_phi(self, kind="sphere", args=(), phi0=None, step0=0):
         if phi0 is not None:
-            t = self._dev(phi0, self.torch.float32)
+            t = self._dev(phi0, self.dtype)
             self._keep = t
             lsr_init_phi(self.handle, t.data_ptr(), LSR_PHI_ARRAY, [], step0)
         else:
@@ -272,7 +285,7 @@ class Job:
         lsr_reinit(self.handle)
 
     def extract_device(self):
-        phi = self.torch.empty(self.nodes, dtype=self.torch.float32, device=self.stream.device)
+        phi = self.torch.empty(self.nodes, dtype=self.dtype, device=self.stream.device)
         band = self.torch.empty(self.nodes, dtype=self.torch.uint8, device=self.stream.device)
         nb, si = lsr_extract(self.handle, phi.data_ptr(), band.data_ptr(), want_count=True)
         return phi.view(self.shape), band.view(self.shape), nb, si

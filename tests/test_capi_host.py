@@ -38,11 +38,14 @@ def test_params_default_follow_the_paper():
 
 def test_workspace_bytes_scale_with_grid_and_cloud():
     g = lsr.make_grid({"dim": 3, "n": (64, 64, 64), "lo": (-1, -1, -1), "h": 2 / 63})
-    a = lsr.lsr_workspace_bytes(g, 1000)
-    b = lsr.lsr_workspace_bytes(g, 100000)
+    a = lsr.lsr_workspace_bytes(g, None, 1000)
+    b = lsr.lsr_workspace_bytes(g, None, 100000)
     assert b > a > 64 ** 3 * 40
     g2 = lsr.make_grid({"dim": 3, "n": (128, 64, 64), "lo": (-1, -1, -1), "h": 2 / 63})
-    assert lsr.lsr_workspace_bytes(g2, 1000) > 1.9 * a
+    assert lsr.lsr_workspace_bytes(g2, None, 1000) > 1.9 * a
+    p64 = lsr.lsr_params_default(3, 2 / 63)
+    p64.precision = lsr.LSR_FP64
+    assert lsr.lsr_workspace_bytes(g, p64, 1000) > a + 64 ** 3 * 20
 
 
 @pytest.mark.parametrize("grid,code", [
@@ -54,7 +57,7 @@ def test_workspace_bytes_scale_with_grid_and_cloud():
 ])
 def test_invalid_grids_are_rejected(grid, code):
     with pytest.raises(lsr.LsrError) as e:
-        lsr.lsr_workspace_bytes(lsr.make_grid(grid), 10)
+        lsr.lsr_workspace_bytes(lsr.make_grid(grid), None, 10)
     assert e.value.status == code
     assert lsr.lsr_last_error()
 
@@ -75,6 +78,7 @@ def _create(params_over):
     ({"p": 0.5}, lsr.LSR_E_INVALID),
     ({"reinit_dtau": 0.1}, lsr.LSR_E_INVALID),   # beyond h/sqrt(3)
     ({"reinit_every": -1}, lsr.LSR_E_INVALID),
+    ({"precision": 7}, lsr.LSR_E_INVALID),
 ])
 def test_invalid_params_are_rejected(over, code):
     with pytest.raises(lsr.LsrError) as e:
