@@ -35,7 +35,7 @@ FLOPS_PER_UPDATE = {(3, "weno"): 84 * 30 + 4 * 42 + 60, (3, "q1"): 4 * (7 * 3 + 
 # Compulsory HBM bytes of one node update: list entry in 4, phi^n_j e,
 # (grad d, d) 4e, phi^{n+1}_j e, list entry out 4, with e the element size.
 BYTES_PER_UPDATE = {"fp32": 4 + 4 + 16 + 4 + 4, "fp64": 4 + 8 + 32 + 8 + 4}
-PEAK_FP32_TFLOPS = 157.3  # MI355X published fp32 vector peak
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kernels.hip"]
 
@@ -176,8 +176,9 @@ def main():
     achieved_tflops = flops * total_updates / kernel_s / 1e12
     upd_per_launch = total_updates / launches
     traffic = read_traffic(args.workload)
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / peak, 4),
                 "traffic": traffic,
                 "kernel": f"k_sl_step<{dim},{w['interp']},{'double' if args.precision == 'fp64' else 'float'}>",
                 "flops_per_node_update": flops,

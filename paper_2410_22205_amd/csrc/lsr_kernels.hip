@@ -72,6 +72,10 @@ __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2,
       v = src[idx];
       if (!isfinite(v)) atomicOr(flag, 1);
     } else {
+      // no FMA contraction: nodes placed symmetrically about the centre get
+      // bitwise symmetric values (the 3D tangent frame of the update switches
+      // on an exact zero of two gradient components)
+#pragma clang fp contract(off)
       uint32_t r = idx;
       int k = 0;
       if (DIM == 3) {
