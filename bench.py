@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus3d")
     ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64"])
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per band node (0: library default)")
+    ap.add_argument("--blocks-per-cu", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -134,6 +136,8 @@ def main():
     prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
                precision=args.precision)
     job = lsr.Job(g, prm, max_points=len(w["points"]))
+    if args.lanes or args.blocks_per_cu != 8:
+        lsr.lsr_set_launch(job.handle, args.lanes or (4 if dim == 3 else 2), args.blocks_per_cu)
     stream = job.stream
     pts = torch.as_tensor(w["points"], dtype=torch.float64, device="cuda").contiguous()
     phi_out = torch.empty(job.nodes, dtype=job.dtype, device="cuda")
@@ -183,7 +187,8 @@ def main():
                 "kernel": f"k_sl_step<{dim},{w['interp']},{'double' if args.precision == 'fp64' else 'float'}>",
                 "flops_per_node_update": flops,
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
-                "node_updates_per_launch": round(upd_per_launch, 1)}
+                "node_updates_per_launch": round(upd_per_launch, 1),
+                "lanes": args.lanes or (4 if dim == 3 else 2), "blocks_per_cu": args.blocks_per_cu}
     hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in lat)
     out = {

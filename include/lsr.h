@@ -183,6 +183,12 @@ lsr_status lsr_batch_create(lsr_job* const* jobs, int32_t n_jobs, const double* 
 lsr_status lsr_batch_step(lsr_batch* batch, int32_t n_steps);
 lsr_status lsr_batch_destroy(lsr_batch* batch);
 
+/* Launch shape of the list kernels (results are bitwise the same for every
+ * shape): lanes = 1 (one lane per band node) or the number of foot points
+ * per node (2 in 2D, 4 in 3D: one lane per foot point); blocks_per_cu in
+ * 1..64 sets the persistent grid.  Defaults: foot points per node, 8. */
+lsr_status lsr_set_launch(lsr_job* job, int32_t lanes, int32_t blocks_per_cu);
+
 /* Measurement hook.  While enabled, every semi-Lagrangian step kernel the job
  * launches is bracketed by a pair of HIP events recorded on the job's stream
  * (at most max_launches pairs; later launches are not recorded).  Enabling

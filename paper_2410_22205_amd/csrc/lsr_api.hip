@@ -145,7 +145,7 @@ static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp
     SLArgs<T> a = plan_step<T>(j, c);
     const bool rec = j->prof_on && 2 * (size_t)j->prof_used + 1 < j->prof_ev.size();
     if (rec) LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used], s));
-    LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, a, j->list_blocks, s));
+    LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s));
     if (rec) {
       LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used + 1], s));
       j->prof_used += 1;
@@ -165,6 +165,16 @@ lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp) {
 
 lsr_status run_reinit(lsr_job* j) {
   return j->fp64 ? run_reinit_t<double>(j) : run_reinit_t<float>(j);
+}
+
+// Persistent grid of the list kernels: blocks_per_cu blocks per CU, fewer
+// for small grids, always a multiple of 8 (one share per XCD).
+void set_list_blocks(lsr_job* j) {
+  uint64_t want = ((uint64_t)j->dg.N + 255) / 256;
+  uint64_t cap = (uint64_t)j->ncu * (uint64_t)j->blocks_per_cu;
+  uint64_t lb = want < cap ? want : cap;
+  lb = ((lb + 7) / 8) * 8;
+  j->list_blocks = (unsigned)lb;
 }
 
 hipError_t dpack(lsr_job* j) {
@@ -315,11 +325,10 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->bin_start = (int32_t*)(w + L.bin_start);
   j->bin_fill = (int32_t*)(w + L.bin_fill);
   j->occ = (uint32_t*)(w + L.occ);
-  uint64_t want = ((uint64_t)d.N + 255) / 256;
-  uint64_t cap = (uint64_t)(ncu > 0 ? ncu : 256) * 8;
-  uint64_t lb = want < cap ? want : cap;
-  lb = ((lb + 7) / 8) * 8;
-  j->list_blocks = (unsigned)lb;
+  j->ncu = ncu > 0 ? ncu : 256;
+  j->lanes = g.dim == 3 ? 4 : 2;
+  j->blocks_per_cu = 8;
+  set_list_blocks(j);
   j->cur = 0;
   j->cur_list = 0;
   j->ring = 0;
@@ -510,6 +519,17 @@ lsr_status lsr_counters(lsr_job* j, int64_t* out, int32_t n) {
   all[LSR_CNT_INTERFACE] = (int64_t)dev[5];
   all[LSR_CNT_STEPS] = j->n_steps;
   for (int32_t q = 0; q < n && q < LSR_CNT_COUNT; ++q) out[q] = all[q];
+  return LSR_OK;
+}
+
+lsr_status lsr_set_launch(lsr_job* j, int32_t lanes, int32_t blocks_per_cu) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  const int fp = j->grid.dim == 3 ? 4 : 2;
+  if (lanes != 1 && lanes != fp) return fail(LSR_E_INVALID, "lanes must be 1 or the foot points per node");
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LSR_E_INVALID, "blocks_per_cu must be in 1..64");
+  j->lanes = lanes;
+  j->blocks_per_cu = blocks_per_cu;
+  set_list_blocks(j);
   return LSR_OK;
 }
 

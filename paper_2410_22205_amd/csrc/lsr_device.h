@@ -257,10 +257,34 @@ enum { UPD_FALLBACK = 1, UPD_FRAME0 = 2 };
 // C = c(phi^n_j) (p = 1), the fallback of eq. (SL:2) and the cut of eq. (cut).
 // dp = (d_x, d_y, d_z, d) with the centred gradient of d precomputed.
 // Foot points are carried as node index + offset in cells.
+//
+// LANES = 1: one lane interpolates all foot points of the node.  LANES = 2
+// (2D) or 4 (3D): the node is handled by a group of LANES consecutive lanes,
+// lane `sub` interpolating foot point `sub`, and the group sums its values
+// with two cross-lane exchanges.  Both ways add the foot values as
+// (v0 + v1) + (v2 + v3), so they give bitwise identical results.
 template <int DIM, int INTERP, typename T>
+__device__ __forceinline__ T foot_value(const T* __restrict__ A, const DevGrid& g,
+                                        const StepConst<T>& c, int i, int j, int k, int q, T bx,
+                                        T by, T bz, T n1x, T n1y, T n1z, T n2x, T n2y, T n2z) {
+  if (DIM == 2) {
+    const T l = (q & 1) ? T(1) : T(-1);
+    Loc<T> lx = locate(i, bx + n1x * l, g.n0);
+    Loc<T> ly = locate(j, by + n1y * l, g.n1);
+    return INTERP == 0 ? interp_q1_2(A, g, lx, ly) : interp_weno2(A, g, lx, ly, c.weno_e);
+  }
+  const T f1 = (q & 2) ? T(1) : T(-1), f2 = (q & 1) ? T(1) : T(-1);
+  Loc<T> lx = locate(i, bx + f1 * n1x + f2 * n2x, g.n0);
+  Loc<T> ly = locate(j, by + f1 * n1y + f2 * n2y, g.n1);
+  Loc<T> lz = locate(k, bz + f1 * n1z + f2 * n2z, g.n2);
+  return INTERP == 0 ? interp_q1_3(A, g, lx, ly, lz) : interp_weno3(A, g, lx, ly, lz, c.weno_e);
+}
+
+template <int DIM, int INTERP, typename T, int LANES>
 __device__ __forceinline__ T sl_update(const T* __restrict__ A, const DevGrid& g,
                                        const StepConst<T>& c, int i, int j, int k, uint32_t idx,
-                                       T v, typename Vec<T>::pack dp, int& flags) {
+                                       T v, typename Vec<T>::pack dp, int sub, int& flags) {
+  constexpr int FP = DIM == 3 ? 4 : 2;  // foot points per node
   T gx, gy, gz = T(0);
   T xm = i > 0 ? A[idx - g.s0] : v, xp = i < g.n0 - 1 ? A[idx + g.s0] : v;
   T ym = j > 0 ? A[idx - g.s1] : v, yp = j < g.n1 - 1 ? A[idx + g.s1] : v;
@@ -288,24 +312,15 @@ __device__ __forceinline__ T sl_update(const T* __restrict__ A, const DevGrid& g
     flags |= UPD_FALLBACK;
   } else {
     const T C = cutoff(v, c);
-    const T dd = dp.w;
-    const T amp = sqrt(C * dd * c.diff2);  // diffusion reach in cells
+    const T amp = sqrt(C * dp.w * c.diff2);  // diffusion reach in cells
     const T cd = C * c.drift;
-    const T bx = cd * dp.x, by = cd * dp.y;
+    const T bx = cd * dp.x, by = cd * dp.y, bz = DIM == 3 ? cd * dp.z : T(0);
+    T n1x, n1y, n1z = T(0), n2x = T(0), n2y = T(0), n2z = T(0);
     if (DIM == 2) {
       const T inv = T(1) / nrm;
-      const T sx = gy * inv * amp, sy = -gx * inv * amp;  // eq. (sigma2d), scaled
-      T acc = T(0);
-#pragma unroll
-      for (int l = -1; l <= 1; l += 2) {
-        Loc<T> lx = locate(i, bx + sx * T(l), g.n0);
-        Loc<T> ly = locate(j, by + sy * T(l), g.n1);
-        acc += INTERP == 0 ? interp_q1_2(A, g, lx, ly) : interp_weno2(A, g, lx, ly, c.weno_e);
-      }
-      out = T(0.5) * acc;
+      n1x = gy * inv * amp;  // eq. (sigma2d), scaled
+      n1y = -gx * inv * amp;
     } else {
-      const T bz = cd * dp.z;
-      T n1x, n1y, n1z, n2x, n2y, n2z;
       const T s2 = gx * gx + gz * gz;
       if (s2 != T(0)) {  // eq. (sigma3d)
         const T s = sqrt(s2);
@@ -320,18 +335,29 @@ __device__ __forceinline__ T sl_update(const T* __restrict__ A, const DevGrid& g
       }
       n1x *= amp; n1y *= amp; n1z *= amp;
       n2x *= amp; n2y *= amp; n2z *= amp;
-      T acc = T(0);
-      LSR_UNROLL(LSR_FOOT_UNROLL)
-      for (int q = 0; q < 4; ++q) {
-        const T f1 = (q & 2) ? T(1) : T(-1), f2 = (q & 1) ? T(1) : T(-1);
-        Loc<T> lx = locate(i, bx + f1 * n1x + f2 * n2x, g.n0);
-        Loc<T> ly = locate(j, by + f1 * n1y + f2 * n2y, g.n1);
-        Loc<T> lz = locate(k, bz + f1 * n1z + f2 * n2z, g.n2);
-        acc += INTERP == 0 ? interp_q1_3(A, g, lx, ly, lz)
-                           : interp_weno3(A, g, lx, ly, lz, c.weno_e);
-      }
-      out = T(0.25) * acc;
     }
+    T acc;
+    if (LANES == 1) {
+      T prev = T(0), s01 = T(0), s23 = T(0);
+      LSR_UNROLL(LSR_FOOT_UNROLL)
+      for (int q = 0; q < FP; ++q) {
+        const T vq = foot_value<DIM, INTERP, T>(A, g, c, i, j, k, q, bx, by, bz, n1x, n1y, n1z, n2x,
+                                                n2y, n2z);
+        if (q & 1) {
+          if (q == 1) s01 = prev + vq;
+          else s23 = prev + vq;
+        } else {
+          prev = vq;
+        }
+      }
+      acc = FP == 4 ? s01 + s23 : s01;
+    } else {
+      const T vq = foot_value<DIM, INTERP, T>(A, g, c, i, j, k, sub, bx, by, bz, n1x, n1y, n1z,
+                                              n2x, n2y, n2z);
+      acc = vq + __shfl_xor(vq, 1, LANES);
+      if (FP == 4) acc = acc + __shfl_xor(acc, 2, LANES);
+    }
+    out = acc * (T(1) / T(FP));
   }
   return fmin(fmax(out, -c.gamma), c.gamma);
 }

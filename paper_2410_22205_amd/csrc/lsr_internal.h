@@ -95,8 +95,10 @@ template <typename T>
 hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_t* L,
                             const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
                             hipStream_t s);
+// lanes: 1, or the number of foot points per node (2 in 2D, 4 in 3D).
 template <typename T>
-hipError_t launch_sl_step(int dim, int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s);
+hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
+                          hipStream_t s);
 hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s);

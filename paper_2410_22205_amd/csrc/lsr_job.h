@@ -62,6 +62,9 @@ struct lsr_job {
   int32_t* bin_fill;
   uint32_t* occ;
   unsigned list_blocks;
+  int lanes;         // lanes per band node in the step kernel (1 or foot points per node)
+  int blocks_per_cu; // persistent grid of the list kernels: blocks_per_cu x CUs (multiple of 8)
+  int ncu;
   int cur;       // phi buffer holding the current phi
   int cur_list;  // list buffer holding the current band list
   int ring;      // counter slot holding the current list length

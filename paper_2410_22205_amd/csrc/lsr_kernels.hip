@@ -13,9 +13,15 @@ namespace lsr {
 
 // ------------------------------------------------------------------ helpers
 
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
-  // The dispatcher places workgroup b on XCD (b % 8); G is a multiple of 8.
-  return (b % 8u) * (G / 8u) + (b / 8u);
+// Work distribution over a persistent grid (a multiple of 8 blocks): a list
+// is cut into chunks; chunk c is handled on XCD (c / STRIPE) % 8, where the
+// dispatcher places workgroup b on XCD b % 8, and the blocks of one XCD take
+// that XCD's chunks in turn.  Neighbouring chunks (neighbouring nodes) share
+// an L2, and every XCD gets work whatever the list length.
+constexpr uint32_t STRIPE = 4;
+
+__device__ __forceinline__ uint32_t chunk_of(uint32_t q, uint32_t xcd) {
+  return ((q / STRIPE) * 8u + xcd) * STRIPE + (q % STRIPE);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -24,21 +30,72 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Append val for every lane with pred set; called by all 64 lanes of a wave.
-__device__ __forceinline__ void wave_append(bool pred, uint32_t val, uint32_t* __restrict__ out,
-                                            int32_t* __restrict__ counter) {
-  const uint64_t m = __ballot(pred);
-  if (m == 0) return;
-  int base = 0;
-  if (lane_id() == 0) base = atomicAdd(counter, (int)__popcll(m));
-  base = __shfl(base, 0);
-  if (pred) out[base + (int)lanes_below(m)] = val;
-}
-
 __device__ __forceinline__ uint32_t wave_count(bool pred) { return (uint32_t)__popcll(__ballot(pred)); }
 
-__device__ __forceinline__ void add_stat(unsigned long long* p, uint32_t v) {
-  if (v) atomicAdd(p, (unsigned long long)v);
+// Block-wide append (256 threads, called by all of them): the values of the
+// lanes with pred set go to out[] in lane order within the block, behind one
+// atomic on the list counter per block.  lds holds at least 5 ints.
+template <int K>
+__device__ __forceinline__ void block_append(const bool (&pred)[K], const uint32_t (&val)[K],
+                                             uint32_t* __restrict__ out, int32_t* counter,
+                                             int* lds) {
+  uint64_t m[K];
+  int tot = 0;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    m[q] = __ballot(pred[q]);
+    tot += (int)__popcll(m[q]);
+  }
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) lds[w] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int cq = lds[q];
+      lds[q] = run;
+      run += cq;
+    }
+    lds[4] = run ? atomicAdd(counter, run) : 0;
+  }
+  __syncthreads();
+  int off = lds[4] + lds[w];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    if (pred[q]) out[off + (int)lanes_below(m[q])] = val[q];
+    off += (int)__popcll(m[q]);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void block_append1(bool pred, uint32_t val, uint32_t* __restrict__ out,
+                                              int32_t* counter, int* lds) {
+  const bool p[1] = {pred};
+  const uint32_t v[1] = {val};
+  block_append<1>(p, v, out, counter, lds);
+}
+
+// Block-wide sum of up to three wave-uniform counts, one atomic per nonzero
+// total.  lds holds at least 12 uints.
+__device__ __forceinline__ void block_add3(uint32_t a, uint32_t b, uint32_t c,
+                                           unsigned long long* pa, unsigned long long* pb,
+                                           unsigned long long* pc, uint32_t* lds) {
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane_id() == 0) {
+    lds[3 * w] = a;
+    lds[3 * w + 1] = b;
+    lds[3 * w + 2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t[3] = {0, 0, 0};
+    for (int q = 0; q < 4; ++q)
+      for (int r = 0; r < 3; ++r) t[r] += lds[3 * q + r];
+    if (t[0] && pa) atomicAdd(pa, (unsigned long long)t[0]);
+    if (t[1] && pb) atomicAdd(pb, (unsigned long long)t[1]);
+    if (t[2] && pc) atomicAdd(pc, (unsigned long long)t[2]);
+  }
 }
 
 // ------------------------------------------------------------------ fills
@@ -106,9 +163,12 @@ __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2,
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_band_scan(DevGrid g, T gamma, const T* __restrict__ A,
                                                    uint32_t* __restrict__ L, int32_t* cnt) {
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < g.N; base += stride) {
-    const uint32_t idx = base + lane_id();
+  __shared__ int lds[8];
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * 256u;
+    if (base >= g.N) break;
+    const uint32_t idx = base + threadIdx.x;
     bool in = false;
     uint32_t code = 0;
     if (idx < g.N) {
@@ -121,7 +181,7 @@ __global__ __launch_bounds__(256) void k_band_scan(DevGrid g, T gamma, const T* 
       }
       code = encode(g, (int)(r / (uint32_t)g.n1), (int)(r % (uint32_t)g.n1), k);
     }
-    wave_append(in, code, L, cnt);
+    block_append1(in, code, L, cnt, lds);
   }
 }
 
@@ -131,12 +191,14 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
                                                    const uint32_t* __restrict__ L,
                                                    const int32_t* cnt, uint8_t* __restrict__ mask,
                                                    int32_t* count) {
+  __shared__ uint32_t lds[12];
   const int n = *cnt;
   uint32_t tot = 0;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < (uint32_t)n;
-       base += stride) {
-    const uint32_t e = base + lane_id();
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * 256u;
+    if (base >= (uint32_t)n) break;
+    const uint32_t e = base + threadIdx.x;
     bool in = false;
     if (e < (uint32_t)n) {
       int i, j, k;
@@ -147,7 +209,13 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
     }
     tot += wave_count(in);
   }
-  if (lane_id() == 0 && tot) atomicAdd(count, (int)tot);
+  __syncthreads();
+  if (lane_id() == 0) lds[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = lds[0] + lds[1] + lds[2] + lds[3];
+    if (t) atomicAdd(count, (int)t);
+  }
 }
 
 // ---------------------------------------------------------- the SL step
@@ -157,15 +225,22 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
 // the previous step get their value copied, so that A and B agree off the
 // new list.  The new list is the set of entries updated here (the band of
 // this step).  cnt_reset is the list counter the next step will write.
-template <int DIM, int INTERP, typename T>
+// LANES lanes share one entry (see sl_update).
+template <int DIM, int INTERP, typename T, int LANES>
 __global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
+  __shared__ int lds_app[8];
+  __shared__ uint32_t lds_st[12];
+  constexpr uint32_t CH = 256 / LANES;  // entries per block and chunk
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  const int sub = (int)(threadIdx.x % LANES);
+  const uint32_t slot = threadIdx.x / LANES;
   uint32_t nupd = 0, nfb = 0, nfr = 0;
-  const uint32_t stride = gridDim.x * 256u;
-  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
-    const uint32_t e = base + lane_id();
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * CH;
+    if (base >= (uint32_t)n) break;
+    const uint32_t e = base + slot;
     bool act = false;
     int fl = 0;
     uint32_t code = 0;
@@ -178,20 +253,17 @@ __global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
       T nv = v;
       if (fabs(v) < a.c.gamma) {
         act = true;
-        nv = sl_update<DIM, INTERP, T>(a.A, a.g, a.c, i, j, k, idx, v, a.dp[idx], fl);
+        nv = sl_update<DIM, INTERP, T, LANES>(a.A, a.g, a.c, i, j, k, idx, v, a.dp[idx], sub, fl);
       }
-      a.B[idx] = nv;
+      if (sub == 0) a.B[idx] = nv;
     }
-    wave_append(act, code, a.Lout, a.cnt_out);
-    nupd += wave_count(act);
-    nfb += wave_count(fl & UPD_FALLBACK);
-    nfr += wave_count(fl & UPD_FRAME0);
+    const bool lead = act && sub == 0;
+    block_append1(lead, code, a.Lout, a.cnt_out, lds_app);
+    nupd += wave_count(lead);
+    nfb += wave_count(sub == 0 && (fl & UPD_FALLBACK));
+    nfr += wave_count(sub == 0 && (fl & UPD_FRAME0));
   }
-  if (lane_id() == 0) {
-    add_stat(&a.stats[0], nupd);
-    add_stat(&a.stats[1], nfb);
-    add_stat(&a.stats[2], nfr);
-  }
+  block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
 }
 
 // ------------------------------------------------------- reinitialisation
@@ -199,44 +271,51 @@ __global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
 // Gbar = band + face neighbours, deduplicated through a per-node stamp.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
+  __shared__ int lds[8];
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t stride = gridDim.x * 256u;
-  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
-    const uint32_t e = base + lane_id();
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  constexpr int K = 1 + 2 * DIM;
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * 256u;
+    if (base >= (uint32_t)n) break;
+    const uint32_t e = base + threadIdx.x;
     const bool valid = e < (uint32_t)n;
     int i = 0, j = 0, k = 0;
     if (valid) decode(a.g, a.L[e], i, j, k);
+    bool ins[K];
+    uint32_t code[K];
 #pragma unroll
-    for (int q = 0; q < 1 + 2 * DIM; ++q) {
-      int ii = i + (q == 1 ? -1 : q == 2 ? 1 : 0);
-      int jj = j + (q == 3 ? -1 : q == 4 ? 1 : 0);
-      int kk = k + (q == 5 ? -1 : q == 6 ? 1 : 0);
-      bool ins = false;
-      uint32_t code = 0;
+    for (int c = 0; c < K; ++c) {
+      const int ii = i + (c == 1 ? -1 : c == 2 ? 1 : 0);
+      const int jj = j + (c == 3 ? -1 : c == 4 ? 1 : 0);
+      const int kk = k + (c == 5 ? -1 : c == 6 ? 1 : 0);
+      ins[c] = false;
+      code[c] = 0;
       if (valid && ii >= 0 && ii < a.g.n0 && jj >= 0 && jj < a.g.n1 && kk >= 0 && kk < a.g.n2) {
         const uint32_t old = atomicMax(&a.stamp[lin(a.g, ii, jj, kk)], a.epoch);
-        ins = old < a.epoch;
-        code = encode(a.g, ii, jj, kk);
+        ins[c] = old < a.epoch;
+        code[c] = encode(a.g, ii, jj, kk);
       }
-      wave_append(ins, code, a.M, a.cnt_out);
     }
+    block_append<K>(ins, code, a.M, a.cnt_out, lds);
   }
 }
 
-// Interface set and one-step fix on Gbar.  Reads phi~ from T, writes the
-// working copy W: W = phi~ / max(|grad_c phi~|, floor) on interface nodes
-// (a face neighbour of opposite or zero sign), W = phi~ elsewhere on Gbar.
+// Interface set and one-step fix on Gbar.  Reads phi~ from src, writes the
+// working copy dst: dst = phi~ / max(|grad_c phi~|, floor) on interface nodes
+// (a face neighbour of opposite or zero sign), dst = phi~ elsewhere on Gbar.
 // flags: bit 7 interface, bits 0-1 sign of phi~ (1 positive, 2 negative).
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
+  __shared__ uint32_t lds_st[12];
   const int n = *a.cnt;
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t stride = gridDim.x * 256u;
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   uint32_t nif = 0, ng = 0;
-  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
-    const uint32_t e = base + lane_id();
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * 256u;
+    if (base >= (uint32_t)n) break;
+    const uint32_t e = base + threadIdx.x;
     bool itf = false;
     const bool valid = e < (uint32_t)n;
     if (valid) {
@@ -269,10 +348,7 @@ __global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
     nif += wave_count(itf);
     ng += wave_count(valid);
   }
-  if (lane_id() == 0) {
-    add_stat(&a.stats[4], ng);
-    add_stat(&a.stats[5], nif);
-  }
+  block_add3(ng, nif, 0, &a.stats[4], &a.stats[5], nullptr, lds_st);
 }
 
 // One forward-Euler pseudo-time step of phi_tau + S (|grad phi| - 1) = 0 on
@@ -281,10 +357,11 @@ __global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
   const int n = *a.cnt;
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t stride = gridDim.x * 256u;
-  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
-    const uint32_t e = base + lane_id();
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * 256u;
+    if (base >= (uint32_t)n) break;
+    const uint32_t e = base + threadIdx.x;
     if (e >= (uint32_t)n) continue;
     int i, j, k;
     decode(a.g, a.M[e], i, j, k);
@@ -322,12 +399,14 @@ __global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
 // Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
 template <typename T>
 __global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
+  __shared__ int lds[8];
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t stride = gridDim.x * 256u;
-  for (uint32_t base = lb * 256u + (threadIdx.x & ~63u); base < (uint32_t)n; base += stride) {
-    const uint32_t e = base + lane_id();
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * 256u;
+    if (base >= (uint32_t)n) break;
+    const uint32_t e = base + threadIdx.x;
     bool in = false;
     uint32_t code = 0;
     if (e < (uint32_t)n) {
@@ -340,7 +419,7 @@ __global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
       a.other[idx] = v;
       in = fabs(v) < a.gamma;
     }
-    wave_append(in, code, a.Lout, a.cnt_out);
+    block_append1(in, code, a.Lout, a.cnt_out, lds);
   }
 }
 
@@ -403,11 +482,11 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const int32_t* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_occupied(const int32_t* __restrict__ start, int32_t nbins,
                                                   uint32_t* __restrict__ occ, int32_t* cnt) {
-  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < (uint32_t)nbins;
-       base += gridDim.x * blockDim.x) {
-    const uint32_t b = base + lane_id();
+  __shared__ int lds[8];
+  for (uint32_t base = blockIdx.x * 256u; base < (uint32_t)nbins; base += gridDim.x * 256u) {
+    const uint32_t b = base + threadIdx.x;
     const bool nz = b < (uint32_t)nbins && start[b + 1] > start[b];
-    wave_append(nz, b, occ, cnt);
+    block_append1(nz, b, occ, cnt, lds);
   }
 }
 
@@ -461,6 +540,9 @@ __device__ __forceinline__ void bin_box(const BinGeom& bg, uint32_t id, double l
 // arithmetic in double.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
+  // no FMA contraction: node coordinates lo + i h and the sums of squares are
+  // rounded exactly as the plain definition states them
+#pragma clang fp contract(off)
   constexpr int BS = DIM == 3 ? 8 : 16;
   constexpr int NPT = DIM == 3 ? 2 : 1;
   constexpr int CAP = 6144;
@@ -598,7 +680,7 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
 #pragma unroll
         for (int ax = 0; ax < DIM; ++ax) {
           const double t2 = x[u][ax] - Q[ax];
-          s2 = fma(t2, t2, s2);
+          s2 += t2 * t2;
         }
         bn[u] = fmin(bn[u], s2);
       }
@@ -691,7 +773,8 @@ hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* ar
 template <typename T>
 hipError_t launch_band_scan(int dim, const DevGrid& g, T gamma, const T* A, uint32_t* L,
                             int32_t* cnt, hipStream_t s) {
-  dim3 gr(grid_for(g.N, 256, 8192)), bl(256);
+  // the chunk loop needs a multiple of 8 blocks (equal shares per XCD)
+  dim3 gr((grid_for(g.N, 256, 8192) + 7) / 8 * 8), bl(256);
   if (dim == 3)
     hipLaunchKernelGGL((k_band_scan<3, T>), gr, bl, 0, s, g, gamma, A, L, cnt);
   else
@@ -703,29 +786,47 @@ template <typename T>
 hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_t* L,
                             const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
                             hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_band_mask<T>), dim3(blocks), dim3(256), 0, s, g, gamma, A, L, cnt, mask,
                      count);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sl_step(int dim, int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s) {
+hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
+                          hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
   dim3 gr(blocks), bl(256);
   if (dim == 3) {
-    if (interp == 0)
-      hipLaunchKernelGGL((k_sl_step<3, 0, T>), gr, bl, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_sl_step<3, 1, T>), gr, bl, 0, s, a);
+    if (lanes == 1) {
+      if (interp == 0)
+        hipLaunchKernelGGL((k_sl_step<3, 0, T, 1>), gr, bl, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_sl_step<3, 1, T, 1>), gr, bl, 0, s, a);
+    } else {
+      if (interp == 0)
+        hipLaunchKernelGGL((k_sl_step<3, 0, T, 4>), gr, bl, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_sl_step<3, 1, T, 4>), gr, bl, 0, s, a);
+    }
   } else {
-    if (interp == 0)
-      hipLaunchKernelGGL((k_sl_step<2, 0, T>), gr, bl, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_sl_step<2, 1, T>), gr, bl, 0, s, a);
+    if (lanes == 1) {
+      if (interp == 0)
+        hipLaunchKernelGGL((k_sl_step<2, 0, T, 1>), gr, bl, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_sl_step<2, 1, T, 1>), gr, bl, 0, s, a);
+    } else {
+      if (interp == 0)
+        hipLaunchKernelGGL((k_sl_step<2, 0, T, 2>), gr, bl, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_sl_step<2, 1, T, 2>), gr, bl, 0, s, a);
+    }
   }
   return hipGetLastError();
 }
 
 hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
   if (dim == 3)
     hipLaunchKernelGGL(k_dilate<3>, dim3(blocks), dim3(256), 0, s, a);
   else
@@ -735,6 +836,7 @@ hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t
 
 template <typename T>
 hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
   if (dim == 3)
     hipLaunchKernelGGL((k_reinit_fix<3, T>), dim3(blocks), dim3(256), 0, s, a);
   else
@@ -744,6 +846,7 @@ hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStr
 
 template <typename T>
 hipError_t launch_reinit_iter(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
   if (dim == 3)
     hipLaunchKernelGGL((k_reinit_iter<3, T>), dim3(blocks), dim3(256), 0, s, a);
   else
@@ -753,6 +856,7 @@ hipError_t launch_reinit_iter(int dim, const RArgs<T>& a, unsigned blocks, hipSt
 
 template <typename T>
 hipError_t launch_reinit_final(const FinArgs<T>& a, unsigned blocks, hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_reinit_final<T>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -818,7 +922,7 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
   template hipError_t launch_band_mask<T>(const DevGrid&, T, const T*, const uint32_t*,           \
                                           const int32_t*, uint8_t*, int32_t*, unsigned,           \
                                           hipStream_t);                                           \
-  template hipError_t launch_sl_step<T>(int, int, const SLArgs<T>&, unsigned, hipStream_t);       \
+  template hipError_t launch_sl_step<T>(int, int, int, const SLArgs<T>&, unsigned, hipStream_t);  \
   template hipError_t launch_reinit_fix<T>(int, const RArgs<T>&, unsigned, hipStream_t);          \
   template hipError_t launch_reinit_iter<T>(int, const RArgs<T>&, unsigned, hipStream_t);         \
   template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \

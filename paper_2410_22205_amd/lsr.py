@@ -27,7 +27,8 @@ EXPORTED = [
     "lsr_params_default", "lsr_workspace_bytes", "lsr_create", "lsr_load_cloud",
     "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
     "lsr_extract", "lsr_counters", "lsr_destroy", "lsr_batch_create", "lsr_batch_step",
-    "lsr_batch_destroy", "lsr_profile_enable", "lsr_profile_read", "lsr_last_error",
+    "lsr_batch_destroy", "lsr_set_launch", "lsr_profile_enable", "lsr_profile_read",
+    "lsr_last_error",
 ]
 
 
@@ -81,6 +82,7 @@ def load():
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_P)],
             "lsr_batch_step": [_P, ctypes.c_int32],
             "lsr_profile_enable": [_P, ctypes.c_int32, ctypes.c_int32],
+            "lsr_set_launch": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_profile_read": [_P, ctypes.POINTER(ctypes.c_double), I64P],
             "lsr_batch_destroy": [_P],
         }
@@ -197,6 +199,10 @@ def lsr_batch_step(batch, n_steps):
 
 def lsr_batch_destroy(batch):
     _check(load().lsr_batch_destroy(batch))
+
+
+def lsr_set_launch(job, lanes, blocks_per_cu):
+    _check(load().lsr_set_launch(job, int(lanes), int(blocks_per_cu)))
 
 
 def lsr_profile_enable(job, enable, max_launches=4096):
