@@ -173,14 +173,41 @@ lsr_status lsr_counters(lsr_job* job, int64_t* out, int32_t n);
  * the job's queued work to finish. */
 lsr_status lsr_destroy(lsr_job* job);
 
-/* Batched execution of independent jobs (same device, each job already
- * through lsr_init_phi): one persistent launch per step covers every job's
- * band; each job keeps its own dt, interpolator, reinitialisation phase and
- * state, and its results are bitwise those of lsr_step on the job alone.
- * Work goes to the first job's stream.  dt and interp per job. */
-lsr_status lsr_batch_create(lsr_job* const* jobs, int32_t n_jobs, const double* dt,
-                            const int32_t* interp, lsr_batch** out);
+/* Batched execution of independent jobs on one device (one dimension and one
+ * precision per batch).  A batch step launches each kernel of the step once
+ * for all member jobs (per-job arguments from packed tables in the batch's
+ * workspace); every job keeps its own dt, interpolator, reinitialisation
+ * phase and state, and its results are bitwise those of lsr_step on the job
+ * alone with the same launch shape.  All work of a batch, including calls on
+ * member jobs (lsr_extract, lsr_counters, ...), goes to the batch's stream.
+ *
+ * lsr_batch_workspace_bytes: device workspace for up to max_jobs members,
+ * tables for group_steps steps per upload, members with at most
+ * max_reinit_iters reinitialisation iterations.
+ * lsr_batch_create: dev_workspace (device, caller-owned, 256-byte aligned),
+ * hip_stream (NULL = default stream).  Host staging is pinned memory.
+ * lsr_batch_add: the job joins at the next batch step, after the work
+ * already queued on its own stream (no host synchronisation); a job in a
+ * batch refuses lsr_step, lsr_reinit, lsr_init_phi, lsr_load_cloud,
+ * lsr_set_distance, lsr_set_launch and lsr_destroy.
+ * lsr_batch_remove: the job leaves at the current step boundary; its own
+ * stream is ordered after the batch's queued work.
+ * lsr_batch_step: n_steps steps of every member (uploads one table per group).
+ * lsr_batch_set_launch: launch shape as in lsr_set_launch.
+ * lsr_batch_tune: times the next step under each candidate launch shape
+ * (lanes per node, blocks per CU) without changing the jobs, keeps the
+ * fastest and returns it with its time in ms (synchronises).
+ * lsr_batch_destroy: removes the members, waits for the stream. */
+lsr_status lsr_batch_workspace_bytes(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
+                                     size_t* bytes);
+lsr_status lsr_batch_create(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
+                            void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                            lsr_batch** out);
+lsr_status lsr_batch_add(lsr_batch* batch, lsr_job* job, double dt, lsr_interp interp);
+lsr_status lsr_batch_remove(lsr_batch* batch, lsr_job* job);
 lsr_status lsr_batch_step(lsr_batch* batch, int32_t n_steps);
+lsr_status lsr_batch_set_launch(lsr_batch* batch, int32_t lanes, int32_t blocks_per_cu);
+lsr_status lsr_batch_tune(lsr_batch* batch, int32_t* lanes, int32_t* blocks_per_cu, double* ms);
 lsr_status lsr_batch_destroy(lsr_batch* batch);
 
 /* Launch shape of the list kernels (results are bitwise the same for every

@@ -278,6 +278,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->prm = *params;
   j->fp64 = fp64;
   j->in_batch = false;
+  j->own_stream = (hipStream_t)hip_stream;
   j->stream = (hipStream_t)hip_stream;
   j->ws = (char*)dev_workspace;
   j->ws_bytes = ws_bytes;
@@ -355,6 +356,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
 
 lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   if (!dev_xyz) return fail(LSR_E_INVALID, "points are NULL");
   if (n < 1) return fail(LSR_E_INVALID, "the cloud needs at least one point");
   if (n > j->max_points) return fail(LSR_E_NOMEM, "cloud larger than the workspace allows");
@@ -394,6 +396,7 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
 
 lsr_status lsr_set_distance(lsr_job* j, const double* dev_d) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   if (!dev_d) return fail(LSR_E_INVALID, "distance is NULL");
   LSR_HIP(hipMemcpyAsync(j->d64, dev_d, sizeof(double) * j->dg.N, hipMemcpyDeviceToDevice,
                          j->stream));
@@ -524,6 +527,7 @@ lsr_status lsr_counters(lsr_job* j, int64_t* out, int32_t n) {
 
 lsr_status lsr_set_launch(lsr_job* j, int32_t lanes, int32_t blocks_per_cu) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   const int fp = j->grid.dim == 3 ? 4 : 2;
   if (lanes != 1 && lanes != fp) return fail(LSR_E_INVALID, "lanes must be 1 or the foot points per node");
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LSR_E_INVALID, "blocks_per_cu must be in 1..64");
@@ -564,6 +568,7 @@ lsr_status lsr_profile_read(lsr_job* j, double* total_ms, int64_t* launches) {
 
 lsr_status lsr_destroy(lsr_job* j) {
   if (!j) return LSR_OK;
+  if (j->in_batch) return fail(LSR_E_STATE, "remove the job from its batch first");
   hipError_t e = hipStreamSynchronize(j->stream);
   for (hipEvent_t ev : j->prof_ev) (void)hipEventDestroy(ev);
   delete j;

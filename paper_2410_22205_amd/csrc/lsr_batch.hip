@@ -1,12 +1,441 @@
-// Batched execution of independent jobs (include/lsr.h, lsr_batch_*).
-#include "../../include/lsr.h"
+// Batched execution of independent jobs (include/lsr.h, lsr_batch_*) and the
+// launch-shape autotuner.
+//
+// A batch step launches each kernel of the step once for all jobs: the
+// per-job arguments come from packed tables that the host fills with the
+// same plan_* functions the single-job path uses (lsr_job.h), so every job
+// goes through the same buffers, counters and per-node arithmetic as it would
+// alone.  Tables for a group of steps are written to pinned host memory and
+// copied to the caller's device workspace with one transfer per group.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "lsr_job.h"
+
+using namespace lsr;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Launch {
+  int kind;  // 0 step, 1 dilate, 2 fix, 3 iteration, 4 final, 5 stamp clear
+  size_t off;
+  int n;
+  lsr_job* job;  // kind 5 only
+};
+
+}  // namespace
+
+struct lsr_batch {
+  std::vector<lsr_job*> jobs;
+  std::vector<double> dt;
+  std::vector<int32_t> interp;
+  int max_jobs, max_iters;
+  hipStream_t stream;
+  int dim;                           // 0 until the first job joins
+  bool fp64;
+  char* ws;
+  size_t ws_bytes;
+  int32_t* scratch_cnt;              // 2 ints per job for dry runs
+  unsigned long long* scratch_stats;
+  size_t table_off, table_bytes;
+  int group_steps;
+  char* host;
+  size_t host_bytes;
+  hipEvent_t copy_done;
+  bool copy_pending;
+  int lanes, bpc, ncu;
+  unsigned blocks;
+};
+
+namespace {
+
+// Upper bound of the tables of one group: per step a step table and its
+// interpolator codes, and at most one reinitialisation per job (dilation,
+// fix, max_iters iteration tables, final), each table 256-byte aligned; the
+// double-precision argument structs bound the single-precision ones.
+size_t group_table_bytes(int n_jobs, int group_steps, int max_iters) {
+  const size_t n = (size_t)n_jobs, a = 255;
+  const size_t per_step = n * sizeof(SLArgs<double>) + a + 4 * n + a + n * sizeof(DilArgs) + a +
+                          n * sizeof(RArgs<double>) + a +
+                          (size_t)max_iters * (n * sizeof(RArgs<double>) + a) +
+                          n * sizeof(FinArgs<double>) + a;
+  return per_step * (size_t)group_steps + a;
+}
+
+unsigned batch_blocks(int ncu, int bpc) {
+  unsigned b = (unsigned)(ncu * bpc);
+  return (b + 7) / 8 * 8;
+}
+
+template <typename T>
+struct Builder {
+  lsr_batch* b;
+  size_t off = 0;
+  std::vector<Launch> launches;
+  template <typename A>
+  A* take(int n) {
+    off = align256(off);
+    A* p = (A*)(b->host + off);
+    off += sizeof(A) * (size_t)n;
+    return p;
+  }
+};
+
+template <typename T>
+lsr_status build_group(lsr_batch* b, int steps, Builder<T>& B) {
+  const int nj = (int)b->jobs.size();
+  for (int s = 0; s < steps; ++s) {
+    size_t o = align256(B.off);
+    SLArgs<T>* tab = B.template take<SLArgs<T>>(nj);
+    int32_t* itp = B.template take<int32_t>(nj);
+    for (int q = 0; q < nj; ++q) {
+      lsr_job* j = b->jobs[q];
+      tab[q] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
+      itp[q] = b->interp[q];
+    }
+    B.launches.push_back({0, o, nj, nullptr});
+    std::vector<int> due;
+    for (int q = 0; q < nj; ++q)
+      if (reinit_due(b->jobs[q])) due.push_back(q);
+    if (due.empty()) continue;
+    const int nd = (int)due.size();
+    std::vector<ReinitPlan<T>> plans;
+    int max_it = 0;
+    for (int q : due) {
+      lsr_job* j = b->jobs[q];
+      if (stamp_needs_clear(j)) {
+        B.launches.push_back({5, 0, 0, j});
+        j->epoch = 0;
+      }
+      plans.push_back(plan_reinit<T>(j));
+      max_it = std::max(max_it, plans.back().iters);
+    }
+    size_t od = align256(B.off);
+    DilArgs* dil = B.template take<DilArgs>(nd);
+    for (int q = 0; q < nd; ++q) dil[q] = plans[q].dil;
+    B.launches.push_back({1, od, nd, nullptr});
+    size_t of = align256(B.off);
+    RArgs<T>* fix = B.template take<RArgs<T>>(nd);
+    for (int q = 0; q < nd; ++q) fix[q] = plans[q].fix;
+    B.launches.push_back({2, of, nd, nullptr});
+    for (int it = 0; it < max_it; ++it) {
+      size_t oi = align256(B.off);
+      RArgs<T>* itab = B.template take<RArgs<T>>(nd);
+      int m = 0;
+      for (int q = 0; q < nd; ++q)
+        if (it < plans[q].iters) itab[m++] = plans[q].iter[it % 2];
+      B.launches.push_back({3, oi, m, nullptr});
+    }
+    size_t on = align256(B.off);
+    FinArgs<T>* fin = B.template take<FinArgs<T>>(nd);
+    for (int q = 0; q < nd; ++q) fin[q] = plans[q].fin;
+    B.launches.push_back({4, on, nd, nullptr});
+  }
+  if (B.off > b->table_bytes) return fail(LSR_E_NOMEM, "batch table workspace too small");
+  return LSR_OK;
+}
+
+template <typename T>
+lsr_status issue(lsr_batch* b, const Builder<T>& B) {
+  hipStream_t s = b->stream;
+  char* dev = b->ws + b->table_off;
+  for (const Launch& L : B.launches) {
+    switch (L.kind) {
+      case 0: {
+        const size_t io = align256(L.off + sizeof(SLArgs<T>) * (size_t)L.n);
+        LSR_HIP(launch_sl_step_batch<T>(b->dim, b->lanes, (const SLArgs<T>*)(dev + L.off),
+                                        (const int32_t*)(dev + io), L.n, b->blocks, s));
+        break;
+      }
+      case 1:
+        LSR_HIP(launch_dilate_batch(b->dim, (const DilArgs*)(dev + L.off), L.n, b->blocks, s));
+        break;
+      case 2:
+        LSR_HIP(launch_reinit_fix_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n, b->blocks, s));
+        break;
+      case 3:
+        if (L.n > 0)
+          LSR_HIP(launch_reinit_iter_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n,
+                                              b->blocks, s));
+        break;
+      case 4:
+        LSR_HIP(launch_reinit_final_batch<T>((const FinArgs<T>*)(dev + L.off), L.n, b->blocks, s));
+        break;
+      case 5:
+        LSR_HIP(launch_fill_u32(L.job->stamp, 0u, L.job->dg.N, s));
+        break;
+    }
+  }
+  return LSR_OK;
+}
+
+// Tables must be in place before the launches: wait until the previous
+// group's copy has left the pinned buffer, fill it, copy, launch.
+template <typename T>
+lsr_status run_group(lsr_batch* b, int steps) {
+  if (b->jobs.empty()) return LSR_OK;
+  if (b->copy_pending) {
+    LSR_HIP(hipEventSynchronize(b->copy_done));
+    b->copy_pending = false;
+  }
+  Builder<T> B;
+  B.b = b;
+  lsr_status st = build_group<T>(b, steps, B);
+  if (st != LSR_OK) return st;
+  LSR_HIP(hipMemcpyAsync(b->ws + b->table_off, b->host, B.off, hipMemcpyHostToDevice, b->stream));
+  LSR_HIP(hipEventRecord(b->copy_done, b->stream));
+  b->copy_pending = true;
+  return issue<T>(b, B);
+}
+
+struct SavedState {
+  int cur, cur_list, ring;
+  int64_t step_index, n_steps;
+};
+
+SavedState save(const lsr_job* j) {
+  return {j->cur, j->cur_list, j->ring, j->step_index, j->n_steps};
+}
+
+void restore(lsr_job* j, const SavedState& s) {
+  j->cur = s.cur;
+  j->cur_list = s.cur_list;
+  j->ring = s.ring;
+  j->step_index = s.step_index;
+  j->n_steps = s.n_steps;
+}
+
+// Time the next step kernel under each candidate launch shape without
+// changing the jobs: a dry step writes where the real one will (B, the next
+// list), its list counters and statistics go to scratch.
+template <typename T>
+lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
+  const int nj = (int)b->jobs.size();
+  if (b->copy_pending) {
+    LSR_HIP(hipEventSynchronize(b->copy_done));
+    b->copy_pending = false;
+  }
+  SLArgs<T>* tab = (SLArgs<T>*)b->host;
+  const size_t io = align256(sizeof(SLArgs<T>) * (size_t)nj);
+  int32_t* itp = (int32_t*)(b->host + io);
+  for (int q = 0; q < nj; ++q) {
+    itp[q] = b->interp[q];
+    lsr_job* j = b->jobs[q];
+    SavedState sv = save(j);
+    tab[q] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
+    restore(j, sv);
+    tab[q].cnt_out = b->scratch_cnt + 2 * q;
+    tab[q].cnt_reset = b->scratch_cnt + 2 * q + 1;
+    tab[q].stats = b->scratch_stats;
+  }
+  hipStream_t s = b->stream;
+  char* dev = b->ws + b->table_off;
+  LSR_HIP(hipMemcpyAsync(dev, b->host, io + 4 * (size_t)nj, hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  LSR_HIP(hipEventCreate(&e0));
+  LSR_HIP(hipEventCreate(&e1));
+  const int fp = b->dim == 3 ? 4 : 2;
+  const int lanes_c[2] = {1, fp};
+  const int bpc_c[4] = {4, 8, 16, 32};
+  double best = 1e30;
+  for (int li = 0; li < 2; ++li) {
+    for (int bi = 0; bi < 4; ++bi) {
+      const unsigned blocks = batch_blocks(b->ncu, bpc_c[bi]);
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 4; ++rep) {
+        LSR_HIP(launch_fill_u32((uint32_t*)b->scratch_cnt, 0u, 2 * (uint64_t)nj, s));
+        LSR_HIP(hipEventRecord(e0, s));
+        LSR_HIP(launch_sl_step_batch<T>(b->dim, lanes_c[li], (const SLArgs<T>*)dev,
+                                        (const int32_t*)(dev + io), nj, blocks, s));
+        LSR_HIP(hipEventRecord(e1, s));
+        LSR_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        LSR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tmin = std::min(tmin, ms);  // first run warms up
+      }
+      if (tmin < best) {
+        best = tmin;
+        *best_lanes = lanes_c[li];
+        *best_bpc = bpc_c[bi];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *best_ms = best;
+  return LSR_OK;
+}
+
+}  // namespace
+
+// Make `waiter` wait for the work queued on `signaller` so far (no host sync).
+hipError_t order_after(hipStream_t waiter, hipStream_t signaller) {
+  if (waiter == signaller) return hipSuccess;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev, signaller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(waiter, ev, 0);
+  hipError_t e2 = hipEventDestroy(ev);
+  return e != hipSuccess ? e : e2;
+}
 
 extern "C" {
 
-lsr_status lsr_batch_create(lsr_job* const*, int32_t, const double*, const int32_t*, lsr_batch**) {
-  return LSR_E_UNSUPPORTED;
+lsr_status lsr_batch_workspace_bytes(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
+                                     size_t* bytes) {
+  if (max_jobs < 1 || group_steps < 1 || max_reinit_iters < 0 || !bytes)
+    return fail(LSR_E_INVALID, "need max_jobs >= 1, group_steps >= 1, max_reinit_iters >= 0");
+  size_t tot = align256(8 * (size_t)max_jobs) + align256(8 * 16);
+  tot += group_table_bytes(max_jobs, group_steps, max_reinit_iters);
+  *bytes = tot;
+  return LSR_OK;
 }
-lsr_status lsr_batch_step(lsr_batch*, int32_t) { return LSR_E_UNSUPPORTED; }
-lsr_status lsr_batch_destroy(lsr_batch*) { return LSR_E_UNSUPPORTED; }
+
+lsr_status lsr_batch_create(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
+                            void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                            lsr_batch** out) {
+  if (!out || !dev_workspace) return fail(LSR_E_INVALID, "NULL argument");
+  if (((uintptr_t)dev_workspace) & 255) return fail(LSR_E_INVALID, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  lsr_status st = lsr_batch_workspace_bytes(max_jobs, group_steps, max_reinit_iters, &need);
+  if (st != LSR_OK) return st;
+  if (ws_bytes < need) return fail(LSR_E_NOMEM, "batch workspace too small");
+  int dev = 0, ncu = 0;
+  LSR_HIP(hipGetDevice(&dev));
+  LSR_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  lsr_batch* b = new (std::nothrow) lsr_batch();
+  if (!b) return fail(LSR_E_NOMEM, "host allocation failed");
+  b->max_jobs = max_jobs;
+  b->max_iters = max_reinit_iters;
+  b->stream = (hipStream_t)hip_stream;
+  b->dim = 0;
+  b->fp64 = false;
+  b->ws = (char*)dev_workspace;
+  b->ws_bytes = ws_bytes;
+  size_t off = 0;
+  b->scratch_cnt = (int32_t*)(b->ws + off);
+  off = align256(off + 8 * (size_t)max_jobs);
+  b->scratch_stats = (unsigned long long*)(b->ws + off);
+  off = align256(off + 8 * 16);
+  b->table_off = off;
+  b->table_bytes = ws_bytes - off;
+  b->group_steps = group_steps;
+  b->host_bytes = group_table_bytes(max_jobs, group_steps, max_reinit_iters);
+  b->copy_pending = false;
+  b->ncu = ncu > 0 ? ncu : 256;
+  b->lanes = 0;
+  b->bpc = 8;
+  b->blocks = batch_blocks(b->ncu, b->bpc);
+  hipError_t e = hipHostMalloc((void**)&b->host, b->host_bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(LSR_E_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  e = hipEventCreateWithFlags(&b->copy_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipHostFree(b->host);
+    delete b;
+    return fail(LSR_E_DEVICE, hipGetErrorString(e));
+  }
+  *out = b;
+  return LSR_OK;
+}
+
+lsr_status lsr_batch_add(lsr_batch* b, lsr_job* j, double dt, lsr_interp interp) {
+  if (!b || !j) return fail(LSR_E_INVALID, "NULL argument");
+  if (!j->has_d || !j->has_phi) return fail(LSR_E_STATE, "the job needs a distance field and phi");
+  if (j->in_batch) return fail(LSR_E_STATE, "the job is already in a batch");
+  if ((int)b->jobs.size() >= b->max_jobs) return fail(LSR_E_NOMEM, "the batch is full");
+  if (j->prm.reinit_iters > b->max_iters) return fail(LSR_E_NOMEM, "reinit_iters above the batch's maximum");
+  if (b->dim && (j->grid.dim != b->dim || j->fp64 != b->fp64))
+    return fail(LSR_E_UNSUPPORTED, "a batch needs one dimension and one precision");
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(LSR_E_INVALID, "dt must be > 0");
+  if (interp != LSR_Q1 && interp != LSR_WENO) return fail(LSR_E_INVALID, "unknown interpolator");
+  LSR_HIP(order_after(b->stream, j->stream));
+  if (!b->dim) {
+    b->dim = j->grid.dim;
+    b->fp64 = j->fp64;
+    if (!b->lanes) b->lanes = j->lanes;
+  }
+  j->in_batch = true;
+  j->own_stream = j->stream;
+  j->stream = b->stream;
+  b->jobs.push_back(j);
+  b->dt.push_back(dt);
+  b->interp.push_back((int32_t)interp);
+  return LSR_OK;
+}
+
+lsr_status lsr_batch_remove(lsr_batch* b, lsr_job* j) {
+  if (!b || !j) return fail(LSR_E_INVALID, "NULL argument");
+  auto it = std::find(b->jobs.begin(), b->jobs.end(), j);
+  if (it == b->jobs.end()) return fail(LSR_E_INVALID, "the job is not in this batch");
+  const size_t q = (size_t)(it - b->jobs.begin());
+  LSR_HIP(order_after(j->own_stream, b->stream));
+  j->stream = j->own_stream;
+  j->in_batch = false;
+  b->jobs.erase(b->jobs.begin() + q);
+  b->dt.erase(b->dt.begin() + q);
+  b->interp.erase(b->interp.begin() + q);
+  return LSR_OK;
+}
+
+lsr_status lsr_batch_step(lsr_batch* b, int32_t n_steps) {
+  if (!b) return fail(LSR_E_INVALID, "batch is NULL");
+  if (n_steps < 0) return fail(LSR_E_INVALID, "n_steps must be >= 0");
+  while (n_steps > 0) {
+    const int g = std::min<int>(n_steps, b->group_steps);
+    lsr_status st = b->fp64 ? run_group<double>(b, g) : run_group<float>(b, g);
+    if (st != LSR_OK) return st;
+    n_steps -= g;
+  }
+  return LSR_OK;
+}
+
+lsr_status lsr_batch_set_launch(lsr_batch* b, int32_t lanes, int32_t blocks_per_cu) {
+  if (!b) return fail(LSR_E_INVALID, "batch is NULL");
+  if (!b->dim) return fail(LSR_E_STATE, "the batch has no job yet");
+  const int fp = b->dim == 3 ? 4 : 2;
+  if (lanes != 1 && lanes != fp) return fail(LSR_E_INVALID, "lanes must be 1 or the foot points per node");
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LSR_E_INVALID, "blocks_per_cu must be in 1..64");
+  b->lanes = lanes;
+  b->bpc = blocks_per_cu;
+  b->blocks = batch_blocks(b->ncu, b->bpc);
+  return LSR_OK;
+}
+
+lsr_status lsr_batch_tune(lsr_batch* b, int32_t* lanes, int32_t* blocks_per_cu, double* ms) {
+  if (!b) return fail(LSR_E_INVALID, "batch is NULL");
+  if (b->jobs.empty()) return fail(LSR_E_STATE, "the batch has no job");
+  int bl = b->lanes, bb = b->bpc;
+  double t = 0.0;
+  lsr_status st = b->fp64 ? tune<double>(b, &bl, &bb, &t) : tune<float>(b, &bl, &bb, &t);
+  if (st != LSR_OK) return st;
+  st = lsr_batch_set_launch(b, bl, bb);
+  if (st != LSR_OK) return st;
+  if (lanes) *lanes = bl;
+  if (blocks_per_cu) *blocks_per_cu = bb;
+  if (ms) *ms = t;
+  return LSR_OK;
+}
+
+lsr_status lsr_batch_destroy(lsr_batch* b) {
+  if (!b) return LSR_OK;
+  while (!b->jobs.empty()) {
+    lsr_status st = lsr_batch_remove(b, b->jobs.back());
+    if (st != LSR_OK) return st;
+  }
+  hipError_t e = hipStreamSynchronize(b->stream);
+  (void)hipEventDestroy(b->copy_done);
+  (void)hipHostFree(b->host);
+  delete b;
+  if (e != hipSuccess) return fail(LSR_E_DEVICE, hipGetErrorString(e));
+  return LSR_OK;
+}
 
 }  // extern "C"

@@ -119,4 +119,18 @@ template <typename T>
 hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,
                         hipStream_t s);
 
+// Batched forms: one launch over a packed table of per-job arguments.
+template <typename T>
+hipError_t launch_sl_step_batch(int dim, int lanes, const SLArgs<T>* tab, const int32_t* interp,
+                                int n, unsigned blocks, hipStream_t s);
+hipError_t launch_dilate_batch(int dim, const DilArgs* tab, int n, unsigned blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_reinit_fix_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
+                                   hipStream_t s);
+template <typename T>
+hipError_t launch_reinit_iter_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
+                                    hipStream_t s);
+template <typename T>
+hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned blocks, hipStream_t s);
+
 }  // namespace lsr

@@ -72,7 +72,8 @@ struct lsr_job {
   int64_t step_index;
   int64_t n_reinits, n_steps;
   bool has_d, has_phi;
-  bool in_batch;
+  bool in_batch;            // while in a batch, stream is the batch's stream
+  hipStream_t own_stream;   // the job's stream, saved while it is in a batch
   // measurement hook
   bool prof_on;
   int prof_used;

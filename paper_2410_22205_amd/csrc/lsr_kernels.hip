@@ -227,9 +227,7 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
 // this step).  cnt_reset is the list counter the next step will write.
 // LANES lanes share one entry (see sl_update).
 template <int DIM, int INTERP, typename T, int LANES>
-__global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
-  __shared__ int lds_app[8];
-  __shared__ uint32_t lds_st[12];
+__device__ __forceinline__ void sl_step_body(const SLArgs<T>& a, int* lds_app, uint32_t* lds_st) {
   constexpr uint32_t CH = 256 / LANES;  // entries per block and chunk
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
@@ -266,12 +264,36 @@ __global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
   block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
 }
 
+template <int DIM, int INTERP, typename T, int LANES>
+__global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
+  __shared__ int lds_app[8];
+  __shared__ uint32_t lds_st[12];
+  sl_step_body<DIM, INTERP, T, LANES>(a, lds_app, lds_st);
+}
+
+// The same step for a batch of independent jobs in one launch: every block
+// takes part in every job's list in turn (per-job arguments from a packed
+// table, interpolator per job).  Per-node arithmetic is that of k_sl_step.
+template <int DIM, typename T, int LANES>
+__global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab,
+                                                       const int32_t* __restrict__ interp, int n) {
+  __shared__ int lds_app[8];
+  __shared__ uint32_t lds_st[12];
+  for (int jb = 0; jb < n; ++jb) {
+    const SLArgs<T> a = tab[jb];
+    if (interp[jb] == 0)
+      sl_step_body<DIM, 0, T, LANES>(a, lds_app, lds_st);
+    else
+      sl_step_body<DIM, 1, T, LANES>(a, lds_app, lds_st);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------- reinitialisation
 
 // Gbar = band + face neighbours, deduplicated through a per-node stamp.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
-  __shared__ int lds[8];
+__device__ __forceinline__ void dilate_body(const DilArgs& a, int* lds) {
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
@@ -302,13 +324,28 @@ __global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
   }
 }
 
+template <int DIM>
+__global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
+  __shared__ int lds[8];
+  dilate_body<DIM>(a, lds);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_dilate_batch(const DilArgs* __restrict__ tab, int n) {
+  __shared__ int lds[8];
+  for (int jb = 0; jb < n; ++jb) {
+    const DilArgs a = tab[jb];
+    dilate_body<DIM>(a, lds);
+    __syncthreads();
+  }
+}
+
 // Interface set and one-step fix on Gbar.  Reads phi~ from src, writes the
 // working copy dst: dst = phi~ / max(|grad_c phi~|, floor) on interface nodes
 // (a face neighbour of opposite or zero sign), dst = phi~ elsewhere on Gbar.
 // flags: bit 7 interface, bits 0-1 sign of phi~ (1 positive, 2 negative).
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
-  __shared__ uint32_t lds_st[12];
+__device__ __forceinline__ void reinit_fix_body(const RArgs<T>& a, uint32_t* lds_st) {
   const int n = *a.cnt;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   uint32_t nif = 0, ng = 0;
@@ -351,11 +388,27 @@ __global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
   block_add3(ng, nif, 0, &a.stats[4], &a.stats[5], nullptr, lds_st);
 }
 
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
+  __shared__ uint32_t lds_st[12];
+  reinit_fix_body<DIM, T>(a, lds_st);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_fix_batch(const RArgs<T>* __restrict__ tab, int n) {
+  __shared__ uint32_t lds_st[12];
+  for (int jb = 0; jb < n; ++jb) {
+    const RArgs<T> a = tab[jb];
+    reinit_fix_body<DIM, T>(a, lds_st);
+    __syncthreads();
+  }
+}
+
 // One forward-Euler pseudo-time step of phi_tau + S (|grad phi| - 1) = 0 on
 // Gbar minus the interface set, first-order upwind (Godunov) gradient; a
 // missing neighbour contributes no difference.  src -> dst on Gbar.
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
+__device__ __forceinline__ void reinit_iter_body(const RArgs<T>& a) {
   const int n = *a.cnt;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
@@ -396,10 +449,22 @@ __global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
   }
 }
 
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
+  reinit_iter_body<DIM, T>(a);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_iter_batch(const RArgs<T>* __restrict__ tab, int n) {
+  for (int jb = 0; jb < n; ++jb) {
+    const RArgs<T> a = tab[jb];
+    reinit_iter_body<DIM, T>(a);
+  }
+}
+
 // Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
 template <typename T>
-__global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
-  __shared__ int lds[8];
+__device__ __forceinline__ void reinit_final_body(const FinArgs<T>& a, int* lds) {
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
@@ -420,6 +485,23 @@ __global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
       in = fabs(v) < a.gamma;
     }
     block_append1(in, code, a.Lout, a.cnt_out, lds);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
+  __shared__ int lds[8];
+  reinit_final_body<T>(a, lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_reinit_final_batch(const FinArgs<T>* __restrict__ tab,
+                                                            int n) {
+  __shared__ int lds[8];
+  for (int jb = 0; jb < n; ++jb) {
+    const FinArgs<T> a = tab[jb];
+    reinit_final_body<T>(a, lds);
+    __syncthreads();
   }
 }
 
@@ -914,6 +996,63 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_sl_step_batch(int dim, int lanes, const SLArgs<T>* tab, const int32_t* interp,
+                                int n, unsigned blocks, hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
+  dim3 gr(blocks), bl(256);
+  if (dim == 3) {
+    if (lanes == 1)
+      hipLaunchKernelGGL((k_sl_step_batch<3, T, 1>), gr, bl, 0, s, tab, interp, n);
+    else
+      hipLaunchKernelGGL((k_sl_step_batch<3, T, 4>), gr, bl, 0, s, tab, interp, n);
+  } else {
+    if (lanes == 1)
+      hipLaunchKernelGGL((k_sl_step_batch<2, T, 1>), gr, bl, 0, s, tab, interp, n);
+    else
+      hipLaunchKernelGGL((k_sl_step_batch<2, T, 2>), gr, bl, 0, s, tab, interp, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dilate_batch(int dim, const DilArgs* tab, int n, unsigned blocks, hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_dilate_batch<3>, dim3(blocks), dim3(256), 0, s, tab, n);
+  else
+    hipLaunchKernelGGL(k_dilate_batch<2>, dim3(blocks), dim3(256), 0, s, tab, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reinit_fix_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
+                                   hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
+  if (dim == 3)
+    hipLaunchKernelGGL((k_reinit_fix_batch<3, T>), dim3(blocks), dim3(256), 0, s, tab, n);
+  else
+    hipLaunchKernelGGL((k_reinit_fix_batch<2, T>), dim3(blocks), dim3(256), 0, s, tab, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reinit_iter_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
+                                    hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
+  if (dim == 3)
+    hipLaunchKernelGGL((k_reinit_iter_batch<3, T>), dim3(blocks), dim3(256), 0, s, tab, n);
+  else
+    hipLaunchKernelGGL((k_reinit_iter_batch<2, T>), dim3(blocks), dim3(256), 0, s, tab, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned blocks, hipStream_t s) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_reinit_final_batch<T>), dim3(blocks), dim3(256), 0, s, tab, n);
+  return hipGetLastError();
+}
+
 #define LSR_INSTANTIATE(T)                                                                        \
   template hipError_t launch_init_phi<T>(int, const DevGrid&, int, const double*, T, const T*, T*, \
                                          T*, int32_t*, hipStream_t);                              \
@@ -927,7 +1066,13 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
   template hipError_t launch_reinit_iter<T>(int, const RArgs<T>&, unsigned, hipStream_t);         \
   template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \
   template hipError_t launch_dpack<T>(int, const DevGrid&, const double*, typename Vec<T>::pack*, \
-                                      hipStream_t);
+                                      hipStream_t);                                               \
+  template hipError_t launch_sl_step_batch<T>(int, int, const SLArgs<T>*, const int32_t*, int,     \
+                                              unsigned, hipStream_t);                             \
+  template hipError_t launch_reinit_fix_batch<T>(int, const RArgs<T>*, int, unsigned, hipStream_t);\
+  template hipError_t launch_reinit_iter_batch<T>(int, const RArgs<T>*, int, unsigned,             \
+                                                  hipStream_t);                                   \
+  template hipError_t launch_reinit_final_batch<T>(const FinArgs<T>*, int, unsigned, hipStream_t);
 
 LSR_INSTANTIATE(float)
 LSR_INSTANTIATE(double)

@@ -26,9 +26,10 @@ COUNTER_NAMES = ["node_updates", "fallbacks", "frame0", "reinits", "gbar", "inte
 EXPORTED = [
     "lsr_params_default", "lsr_workspace_bytes", "lsr_create", "lsr_load_cloud",
     "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
-    "lsr_extract", "lsr_counters", "lsr_destroy", "lsr_batch_create", "lsr_batch_step",
-    "lsr_batch_destroy", "lsr_set_launch", "lsr_profile_enable", "lsr_profile_read",
-    "lsr_last_error",
+    "lsr_extract", "lsr_counters", "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
+    "lsr_batch_add", "lsr_batch_remove", "lsr_batch_step", "lsr_batch_set_launch",
+    "lsr_batch_tune", "lsr_batch_destroy", "lsr_set_launch", "lsr_profile_enable",
+    "lsr_profile_read", "lsr_last_error",
 ]
 
 
@@ -78,13 +79,20 @@ def load():
             "lsr_extract": [_P, _P, _P, I64P, I64P],
             "lsr_counters": [_P, I64P, ctypes.c_int32],
             "lsr_destroy": [_P],
-            "lsr_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
-                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_P)],
+            "lsr_batch_workspace_bytes": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_size_t)],
+            "lsr_batch_create": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t,
+                                 _P, ctypes.POINTER(_P)],
+            "lsr_batch_add": [_P, _P, ctypes.c_double, ctypes.c_int],
+            "lsr_batch_remove": [_P, _P],
             "lsr_batch_step": [_P, ctypes.c_int32],
+            "lsr_batch_set_launch": [_P, ctypes.c_int32, ctypes.c_int32],
+            "lsr_batch_tune": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_double)],
+            "lsr_batch_destroy": [_P],
             "lsr_profile_enable": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_set_launch": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_profile_read": [_P, ctypes.POINTER(ctypes.c_double), I64P],
-            "lsr_batch_destroy": [_P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -183,18 +191,40 @@ def lsr_destroy(job):
     _check(load().lsr_destroy(job))
 
 
-def lsr_batch_create(jobs, dts, interps):
-    n = len(jobs)
-    arr = (_P * n)(*[j.value if isinstance(j, _P) else j for j in jobs])
-    dt = (ctypes.c_double * n)(*[float(x) for x in dts])
-    it = (ctypes.c_int32 * n)(*[int(x) for x in interps])
+def lsr_batch_workspace_bytes(max_jobs, group_steps, max_reinit_iters):
+    out = ctypes.c_size_t()
+    _check(load().lsr_batch_workspace_bytes(int(max_jobs), int(group_steps), int(max_reinit_iters),
+                                            ctypes.byref(out)))
+    return out.value
+
+
+def lsr_batch_create(max_jobs, group_steps, max_reinit_iters, ws_ptr, ws_bytes, stream_ptr):
     h = _P()
-    _check(load().lsr_batch_create(arr, n, dt, it, ctypes.byref(h)))
+    _check(load().lsr_batch_create(int(max_jobs), int(group_steps), int(max_reinit_iters),
+                                   _P(ws_ptr), int(ws_bytes), _P(stream_ptr), ctypes.byref(h)))
     return h
+
+
+def lsr_batch_add(batch, job, dt, interp):
+    _check(load().lsr_batch_add(batch, job, float(dt), int(interp)))
+
+
+def lsr_batch_remove(batch, job):
+    _check(load().lsr_batch_remove(batch, job))
 
 
 def lsr_batch_step(batch, n_steps):
     _check(load().lsr_batch_step(batch, int(n_steps)))
+
+
+def lsr_batch_set_launch(batch, lanes, blocks_per_cu):
+    _check(load().lsr_batch_set_launch(batch, int(lanes), int(blocks_per_cu)))
+
+
+def lsr_batch_tune(batch):
+    lanes, bpc, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load().lsr_batch_tune(batch, ctypes.byref(lanes), ctypes.byref(bpc), ctypes.byref(ms)))
+    return lanes.value, bpc.value, ms.value
 
 
 def lsr_batch_destroy(batch):
@@ -304,9 +334,59 @@ class Job:
     def counters(self):
         return lsr_counters(self.handle)
 
+    def set_launch(self, lanes, blocks_per_cu=8):
+        lsr_set_launch(self.handle, lanes, blocks_per_cu)
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             lsr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched stepping of Jobs on one stream (see lsr_batch_* in lsr.h)."""
+
+    def __init__(self, max_jobs, group_steps=64, max_reinit_iters=32, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ws_bytes = lsr_batch_workspace_bytes(max_jobs, group_steps, max_reinit_iters)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.stream.device)
+        self.handle = lsr_batch_create(max_jobs, group_steps, max_reinit_iters, self.ws.data_ptr(),
+                                       self.ws_bytes, self.stream.cuda_stream)
+        self.members = []
+
+    def add(self, job, dt, interp):
+        lsr_batch_add(self.handle, job.handle, dt,
+                      interp_code(interp) if isinstance(interp, str) else interp)
+        job.stream_saved = job.stream
+        job.stream = self.stream
+        self.members.append(job)
+
+    def remove(self, job):
+        lsr_batch_remove(self.handle, job.handle)
+        job.stream = job.stream_saved
+        self.members.remove(job)
+
+    def step(self, n_steps):
+        lsr_batch_step(self.handle, n_steps)
+
+    def set_launch(self, lanes, blocks_per_cu):
+        lsr_batch_set_launch(self.handle, lanes, blocks_per_cu)
+
+    def tune(self):
+        return lsr_batch_tune(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            for job in list(self.members):
+                self.remove(job)
+            lsr_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,168 @@
+"""Batched execution: several independent jobs stepped by one launch per
+kernel give bitwise the results of each job run alone (same launch shape),
+whatever the mix of grids, interpolators and reinitialisation phases, and
+when jobs join or leave between steps.  The solo runs are themselves checked
+against the oracle by test_gpu_parity.py; one batched job is checked against
+the oracle here as well."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _lsr():
+    from paper_2410_22205_amd import lsr
+    return lsr
+
+
+def _jobs(precision, n=5, seed=4000, small=True):
+    """Uneven grids, Q1/WENO alternating, random shape unions."""
+    out = []
+    for w in synth.batch_jobs(n_jobs=n, seed=seed, n_range=(40, 72) if small else (64, 192),
+                              pts_range=(2000, 20000), steps=12):
+        w["precision"] = precision
+        out.append(w)
+    return out
+
+
+def _make(lsr, w, step0=0, lanes=None):
+    h = w["grid"]["h"]
+    prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
+               precision=w["precision"])
+    job = lsr.Job(w["grid"], prm, max_points=len(w["points"]))
+    if lanes:
+        job.set_launch(lanes)
+    job.load_cloud(w["points"])
+    job.init_phi(w["phi0"][0], w["phi0"][1], step0=step0)
+    return job
+
+
+def _solo(w, steps, step0=0, lanes=None):
+    lsr = _lsr()
+    job = _make(lsr, w, step0, lanes)
+    job.step(steps, w["dt"], w["interp"])
+    phi, band, nb, si = job.extract()
+    cnt = job.counters()
+    job.close()
+    return phi, band, nb, si, cnt
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_equals_solo_bitwise(precision):
+    lsr = _lsr()
+    ws = _jobs(precision)
+    steps = 23  # crosses two reinitialisations
+    solo = [_solo(w, steps) for w in ws]
+    batch = lsr.Batch(max_jobs=len(ws), group_steps=8)
+    jobs = [_make(lsr, w) for w in ws]
+    for w, j in zip(ws, jobs):
+        batch.add(j, w["dt"], w["interp"])
+    batch.step(steps)
+    for (phi0, band0, nb0, si0, cnt0), j in zip(solo, jobs):
+        phi, band, nb, si = j.extract()
+        np.testing.assert_array_equal(phi, phi0)
+        np.testing.assert_array_equal(band, band0)
+        assert nb == nb0 and si == si0 == steps
+        assert j.counters() == cnt0
+    batch.close()
+    for j in jobs:
+        j.close()
+
+
+def test_batch_with_mixed_phases_and_membership():
+    lsr = _lsr()
+    ws = _jobs("fp32", n=4, seed=4100)
+    # job k starts at global step k (its own reinitialisation phase)
+    solo = [_solo(w, 17, step0=k) for k, w in enumerate(ws)]
+    batch = lsr.Batch(max_jobs=4, group_steps=5)
+    jobs = [_make(lsr, w, step0=k) for k, w in enumerate(ws)]
+    # jobs 0, 1 from the start; job 2 joins after 4 steps (having stepped 4
+    # alone); job 3 steps 6 in the batch, leaves and finishes alone
+    batch.add(jobs[0], ws[0]["dt"], ws[0]["interp"])
+    batch.add(jobs[1], ws[1]["dt"], ws[1]["interp"])
+    batch.add(jobs[3], ws[3]["dt"], ws[3]["interp"])
+    jobs[2].step(4, ws[2]["dt"], ws[2]["interp"])
+    batch.step(4)
+    batch.add(jobs[2], ws[2]["dt"], ws[2]["interp"])
+    batch.step(2)
+    batch.remove(jobs[3])
+    jobs[3].step(11, ws[3]["dt"], ws[3]["interp"])
+    batch.step(11)
+    batch.remove(jobs[2])
+    jobs[2].step(6, ws[2]["dt"], ws[2]["interp"])
+    batch.close()
+    for k, j in enumerate(jobs):
+        phi, band, nb, si = j.extract()
+        np.testing.assert_array_equal(phi, solo[k][0])
+        assert si == 17 + k
+        j.close()
+
+
+def test_tuning_changes_speed_not_results():
+    lsr = _lsr()
+    ws = _jobs("fp32", n=3, seed=4200)
+    solo = [_solo(w, 11, lanes=1) for w in ws]
+    batch = lsr.Batch(max_jobs=3, group_steps=16)
+    jobs = [_make(lsr, w) for w in ws]
+    for w, j in zip(ws, jobs):
+        batch.add(j, w["dt"], w["interp"])
+    lanes, bpc, ms = batch.tune()
+    assert lanes in (1, 4) and bpc in (4, 8, 16, 32) and ms > 0
+    batch.step(11)
+    for (phi0, *_), j in zip(solo, jobs):
+        np.testing.assert_array_equal(j.extract()[0], phi0)
+    batch.close()
+    for j in jobs:
+        j.close()
+
+
+def test_batched_job_matches_oracle():
+    lsr = _lsr()
+    ws = _jobs("fp64", n=2, seed=4300)
+    batch = lsr.Batch(max_jobs=2, group_steps=32)
+    jobs = [_make(lsr, w) for w in ws]
+    for w, j in zip(ws, jobs):
+        batch.add(j, w["dt"], w["interp"])
+    batch.step(12)
+    for w, j in zip(ws, jobs):
+        g = w["grid"]
+        prm = oracle.default_params(3, g["h"], gamma=w["gamma"], beta=w["beta"],
+                                    reinit_every=w["reinit_every"])
+        d = oracle.distance(w["points"], g)
+        phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
+        ophi, _ = oracle.run(phi0, d, g, prm, w["dt"], w["interp"], 12)
+        phi = j.extract()[0]
+        assert np.abs(phi - ophi).max() <= 1e-4 * g["h"]
+    batch.close()
+    for j in jobs:
+        j.close()
+
+
+def test_batch_rules():
+    lsr = _lsr()
+    w3 = _jobs("fp32", n=1, seed=4400)[0]
+    w2 = synth.workload("circle2d", n=40, steps=3)
+    w2["precision"] = "fp32"
+    batch = lsr.Batch(max_jobs=2, group_steps=4)
+    j3 = _make(lsr, w3)
+    j2 = _make(lsr, w2)
+    batch.add(j3, w3["dt"], w3["interp"])
+    with pytest.raises(lsr.LsrError) as e:
+        batch.add(j2, w2["dt"], w2["interp"])
+    assert e.value.status == lsr.LSR_E_UNSUPPORTED
+    with pytest.raises(lsr.LsrError) as e:
+        j3.step(1, w3["dt"], w3["interp"])
+    assert e.value.status == lsr.LSR_E_STATE
+    with pytest.raises(lsr.LsrError) as e:
+        batch.add(j3, w3["dt"], w3["interp"])
+    assert e.value.status == lsr.LSR_E_STATE
+    batch.step(2)
+    assert j3.extract()[3] == 2
+    batch.close()
+    j3.step(1, w3["dt"], w3["interp"])
+    assert j3.extract()[3] == 3
+    j3.close()
+    j2.close()
