@@ -122,19 +122,22 @@ double orc_interp_q1(const double* f, const orc_grid* g, const double* x) {
   int i0[3] = {0, 0, 0};
   double t[3] = {0, 0, 0};
   for (int a = 0; a < g->dim; ++a) orc_locate(g, a, x[a], &i0[a], &t[a]);
-  double sum = 0.0;
+  /* corner m has offset bit a of m along axis a */
+  double v[8];
   int corners = 1 << g->dim;
   for (int m = 0; m < corners; ++m) {
     int c[3] = {i0[0], i0[1], i0[2]};
-    double w = 1.0;
-    for (int a = 0; a < g->dim; ++a) {
-      int b = (m >> a) & 1;
-      c[a] += b;
-      w *= b ? t[a] : (1.0 - t[a]);
-    }
-    sum += w * f[orc_index(g, c)];
+    for (int a = 0; a < g->dim; ++a) c[a] += (m >> a) & 1;
+    v[m] = f[orc_index(g, c)];
   }
-  return sum;
+  /* The tensor product of linear interpolants, one axis at a time (last axis
+   * first), each written as v0 + t (v1 - v0): equal to eq. (IQ1), and a cell
+   * whose corners hold one value gives that value back exactly. */
+  for (int a = g->dim - 1; a >= 0; --a) {
+    int half = 1 << a;
+    for (int m = 0; m < half; ++m) v[m] = v[m] + t[a] * (v[m + half] - v[m]);
+  }
+  return v[0];
 }
 
 /* One-dimensional third-order WENO interpolation on the cell [x_j, x_{j+1}]
@@ -144,26 +147,33 @@ double orc_interp_q1(const double* f, const orc_grid* g, const double* x) {
  *   I[P] = (1/dx^2) 4 a_2^2 with a_2 the coefficient of s^2 (eq. ind:1d);
  *   alpha_k = C_k/(I_k + eps)^2, eps = dx^2;  w_k = alpha_k / sum alpha;
  *   result = sum w_k P_k  (eq. IWENO).
+ * The quadratics are written in Newton form about x_j and the sum as
+ * P_R + w_L (P_L - P_R) (w_R = 1 - w_L): the same polynomials and the same
+ * combination, evaluated so that a constant stencil returns its value
+ * exactly (in the Lagrange form the basis functions sum to one only up to
+ * rounding).  Foot points deep in the cut plateau then read exactly +-gamma.
  * parts (if not NULL) receives P_L, P_R, C_L, C_R, I_L, I_R, w_L, w_R. */
 double orc_weno1d(const double* v, double s, double dx, double* parts) {
-  double PL = v[0] * s * (s - 1.0) / 2.0 + v[1] * (1.0 - s) * (1.0 + s) + v[2] * s * (s + 1.0) / 2.0;
-  double PR = v[1] * (s - 1.0) * (s - 2.0) / 2.0 + v[2] * s * (2.0 - s) + v[3] * s * (s - 1.0) / 2.0;
+  double DL = v[0] - 2.0 * v[1] + v[2]; /* second differences: 2 a_2 */
+  double DR = v[1] - 2.0 * v[2] + v[3];
+  double PL = v[1] + 0.5 * s * (v[2] - v[0]) + 0.5 * s * s * DL;
+  double PR = v[1] + s * (v[2] - v[1]) + 0.5 * s * (s - 1.0) * DR;
   double CL = (2.0 - s) / 3.0;
   double CR = (1.0 + s) / 3.0;
-  double a2L = (v[0] - 2.0 * v[1] + v[2]) / 2.0;
-  double a2R = (v[1] - 2.0 * v[2] + v[3]) / 2.0;
+  double a2L = DL / 2.0;
+  double a2R = DR / 2.0;
   double IL = 4.0 * a2L * a2L / (dx * dx);
   double IR = 4.0 * a2R * a2R / (dx * dx);
   double eps = dx * dx;
   double alL = CL / ((IL + eps) * (IL + eps));
   double alR = CR / ((IR + eps) * (IR + eps));
   double wL = alL / (alL + alR);
-  double wR = alR / (alL + alR);
+  double wR = 1.0 - wL;
   if (parts) {
     parts[0] = PL; parts[1] = PR; parts[2] = CL; parts[3] = CR;
     parts[4] = IL; parts[5] = IR; parts[6] = wL; parts[7] = wR;
   }
-  return wL * PL + wR * PR;
+  return PR + wL * (PL - PR);
 }
 
 static int orc_clampi(int i, int n) { return i < 0 ? 0 : (i > n - 1 ? n - 1 : i); }

@@ -79,8 +79,8 @@ def test_batch_with_mixed_phases_and_membership():
     solo = [_solo(w, 17, step0=k) for k, w in enumerate(ws)]
     batch = lsr.Batch(max_jobs=4, group_steps=5)
     jobs = [_make(lsr, w, step0=k) for k, w in enumerate(ws)]
-    # jobs 0, 1 from the start; job 2 joins after 4 steps (having stepped 4
-    # alone); job 3 steps 6 in the batch, leaves and finishes alone
+    # jobs 0, 1 in the batch throughout; job 2 steps 4 alone, then joins;
+    # job 3 steps 6 in the batch, leaves and finishes alone (17 steps each)
     batch.add(jobs[0], ws[0]["dt"], ws[0]["interp"])
     batch.add(jobs[1], ws[1]["dt"], ws[1]["interp"])
     batch.add(jobs[3], ws[3]["dt"], ws[3]["interp"])
@@ -91,8 +91,6 @@ def test_batch_with_mixed_phases_and_membership():
     batch.remove(jobs[3])
     jobs[3].step(11, ws[3]["dt"], ws[3]["interp"])
     batch.step(11)
-    batch.remove(jobs[2])
-    jobs[2].step(6, ws[2]["dt"], ws[2]["interp"])
     batch.close()
     for k, j in enumerate(jobs):
         phi, band, nb, si = j.extract()

@@ -7,19 +7,25 @@ one step within 1e-5 h; whole runs within 1e-4 h (max |phi_gpu - phi_oracle|);
 band membership bit-exact except for nodes whose oracle value lies within
 1e-6 h of the band threshold gamma.
 
-On the 128^3 torus workload the scheme itself is unstable to rounding: the
-front reaches the torus axis, where d has a cone point (every point of the
-inner ring is equidistant), and perturbations grow 3-5x per step there; the
-FP64 oracle started from phi0 perturbed by one ulp differs from itself by
-O(h) after 35 steps (pinned by tests/test_oracle_sensitivity.py).  No
-implementation that does not repeat the oracle's exact operation order can
-then stay within 1e-4 h over the whole run.  Whole runs on that workload are
-therefore held to 1e-4 h over the horizon before the divergence (25 steps in
-FP64, 5 in FP32), and at the end of the run to the oracle's own envelope: the
-GPU result may differ from the oracle no more than the oracle perturbed by one
-ulp does, and both reconstructions attach to the cloud alike.  Workloads
-without the instability (the 2D circle, the torus at 48^3) are held to
-1e-4 h over the whole run.
+On the 128^3 torus and the 256^3 union workloads the scheme itself is
+unstable to rounding: on the torus the front reaches the torus axis, where d
+has a cone point; on the union the e2-based tangent frame of eq. (sigma3d) is
+ill-conditioned near the poles of the initial sphere (sqrt(d1 phi^2 +
+d3 phi^2) small, so a rounding change turns the frame).  The FP64 oracle
+started from phi0 perturbed by one ulp differs from itself by O(h) after ~35
+steps on the torus and by 0.4 h after 20 on the union (pinned, at 128^3
+and at 96^3, by tests/test_oracle_sensitivity.py).  No implementation that does not repeat
+the oracle's exact operation order can stay within 1e-4 h over such runs.
+They are therefore held to:
+  * 1e-4 h from phi0 over the horizon before the divergence;
+  * stepwise parity over the whole run: after every step the device's state
+    equals the oracle's single step (band, update, reinitialisation and cut)
+    taken from the device's previous state, within 1e-10 h in FP64 (about
+    1e5 ulps of gamma; every discrete disagreement seen so far, a band or
+    interface decision or a frame branch, moves a node by 1e-3 h or more);
+  * the same attachment to the cloud at the end of the run.
+Workloads without the instability (the 2D circle, the torus at 48^3) are
+held to 1e-4 h over the whole run.
 """
 import numpy as np
 import pytest
@@ -146,17 +152,40 @@ def test_one_step_matches_oracle(name, n, interp, precision):
     assert si == 1 and cnt["node_updates"] == counts[0]
 
 
-@pytest.mark.parametrize("precision", PRECISIONS)
-def test_ragged_anisotropic_grid(precision):
+def _ragged_case(centre):
     g = {"dim": 3, "n": (23, 41, 30), "lo": (-0.6, -1.0, -0.75), "h": 0.05}
     pts = synth.torus_cloud(3000, 0.45, 0.18, 0.0, seed=9)
     pts = pts[np.all(np.abs(pts) < [0.5, 0.9, 0.7], axis=1)]
-    w = dict(grid=g, points=pts, phi0=("sphere", (0.0, 0.05, 0.0, 0.5)), interp="weno",
-             dt=0.5 * g["h"], steps=3, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=2)
-    phi, band, nb, _, _, _ = gpu_run(w, precision=precision)
-    ophi, _, _, prm = oracle_run(w)
-    check_phi(phi, ophi, g["h"], 1e-4)
-    check_band(band, phi, ophi, prm["gamma"], g["h"])
+    return dict(grid=g, points=pts, phi0=("sphere", tuple(centre) + (0.5,)), interp="weno",
+                dt=0.5 * g["h"], steps=3, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=2)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ragged_anisotropic_grid(precision):
+    """Uneven extents (none a multiple of a tile), a box not centred on the
+    origin, a reinitialisation inside the run.  The sphere's centre is off
+    every grid line, so no node has a gradient along an axis (the frame test
+    of eq. (sigma3d) has no ties)."""
+    w = _ragged_case((0.0123, 0.0571, -0.0087))
+    phi, band, nb, _, cnt, _ = gpu_run(w, precision=precision)
+    ophi, counts, _, prm = oracle_run(w)
+    check_phi(phi, ophi, w["grid"]["h"], 1e-4)
+    check_band(band, phi, ophi, prm["gamma"], w["grid"]["h"])
+    assert counts[2] == 0
+
+
+def test_frame_regularisation_on_a_symmetry_axis():
+    """A sphere centred on grid lines: nodes on its axes have a gradient along
+    e2 and take the regularised frame (e1, e3).  Whether such a node ties is
+    decided by the last bit of phi0 (x = lo + i h is not exact in binary), so
+    the branch taken is compared with an FP64 state, where both sides see
+    bitwise the same initial data."""
+    w = _ragged_case((0.0, 0.05, 0.0))
+    phi, band, nb, _, cnt, _ = gpu_run(w, precision="fp64")
+    ophi, counts, _, prm = oracle_run(w)
+    check_phi(phi, ophi, w["grid"]["h"], 1e-4)
+    check_band(band, phi, ophi, prm["gamma"], w["grid"]["h"])
+    assert cnt["frame0"] == counts[2] > 0
 
 
 # ------------------------------------------------------------ whole runs
@@ -193,24 +222,59 @@ def test_full_run_torus3d_small(interp):
     assert cnt["reinits"] == 10
 
 
-def _perturbed_oracle(w, d, steps):
-    """The oracle from phi0 with every band value moved by one ulp."""
+def _perturbed_oracle(w, d, steps, rel=2.0 ** -52):
+    """The oracle from phi0 with every band value moved by a relative rel
+    (default one FP64 ulp; 2^-24 for the resolution of an FP32 state)."""
     g = w["grid"]
     prm = oracle_params(w)
     phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
     rng = np.random.default_rng(1)
     band = np.abs(phi0) < prm["gamma"]
-    phi0 = np.where(band, phi0 * (1 + rng.choice([-1.0, 1.0], phi0.shape) * 2.0 ** -52), phi0)
+    phi0 = np.where(band, phi0 * (1 + rng.choice([-1.0, 1.0], phi0.shape) * rel), phi0)
     phi, _ = oracle.run(phi0, d, g, prm, w["dt"], w["interp"], steps)
     return phi
+
+
+def stepwise_errors(w, steps, d, precision="fp64"):
+    """Run the device `steps` steps from phi0 with the distance field d,
+    reading the state back after every step; return the largest difference
+    (in h) between the device's state n+1 and the oracle's one step from the
+    device's state n, over the steps, and where it was.  The band is checked
+    at every step."""
+    lsr = _lsr()
+    g = w["grid"]
+    h = g["h"]
+    oprm = oracle_params(w)
+    prm = {k: oprm[k] for k in ("gamma", "beta", "reinit_every", "reinit_iters", "reinit_dtau")}
+    prm["precision"] = precision
+    job = lsr.Job(g, prm)
+    job.set_distance(d)
+    job.init_phi(w["phi0"][0], w["phi0"][1])
+    prev = job.extract()[0].astype(np.float64)
+    worst, where = 0.0, None
+    for s in range(steps):
+        ref, _ = oracle.run(prev, d, g, oprm, w["dt"], w["interp"], 1, step0=s)
+        job.step(1, w["dt"], w["interp"])
+        cur, band, nb, si = job.extract()
+        err = np.abs(cur.astype(np.float64) - ref)
+        assert si == s + 1
+        check_band(band, cur, ref, oprm["gamma"], h)
+        if err.max() / h > worst:
+            worst = float(err.max()) / h
+            where = (s + 1, np.unravel_index(int(err.argmax()), err.shape))
+        prev = cur.astype(np.float64)
+    job.close()
+    return worst, where
 
 
 def test_full_run_torus3d_full_size_fp64():
     """The 3D single-instance workload at full size (128^3, 20k noisy torus
     points, WENO, dt = h/2, reinit every 10 steps), FP64 state: within 1e-4 h
-    (and band-exact) over the first 25 steps; after the 300 steps no farther
-    from the oracle, in max and mean over the band, than the oracle perturbed
-    by one ulp, with the same attachment to the cloud."""
+    (and band-exact) from phi0 over the first 25 steps; each of the 300 steps
+    within 1e-10 h of the oracle's step from the device's state; after the
+    300 steps the mean difference from the oracle's run over the band no
+    more than twice what a one-ulp perturbation of phi0 makes it, with the
+    same attachment to the cloud."""
     w = synth.workload("torus3d", steps=25)
     h = w["grid"]["h"]
     d = oracle.distance(w["points"], w["grid"])
@@ -220,32 +284,38 @@ def test_full_run_torus3d_full_size_fp64():
     check_band(band, phi, ophi, prm["gamma"], h)
     assert cnt["node_updates"] == counts[0]
     w = synth.workload("torus3d")
+    step_err, where = stepwise_errors(w, w["steps"], d)
+    assert step_err <= 1e-10, (step_err, where)
     phi, band, nb, si, cnt, _ = gpu_run(w, precision="fp64")
     ophi, counts, _, prm = oracle_run(w, d=d)
     pphi = _perturbed_oracle(w, d, w["steps"])
     sel = (np.abs(ophi) < prm["gamma"]) | (np.abs(phi) < prm["gamma"])
-    gpu_max, gpu_mean = np.abs(phi - ophi).max(), np.abs(phi - ophi)[sel].mean()
-    env_max, env_mean = np.abs(pphi - ophi).max(), np.abs(pphi - ophi)[sel].mean()
-    assert env_max > 1e-4 * h  # the instability is there
-    assert gpu_max <= 2 * env_max and gpu_mean <= 2 * env_mean, (gpu_max / h, env_max / h,
-                                                                   gpu_mean / h, env_mean / h)
+    gpu_mean = np.abs(phi - ophi)[sel].mean()
+    env_mean = np.abs(pphi - ophi)[sel].mean()
+    assert np.abs(pphi - ophi).max() > 1e-4 * h  # the instability is there
+    assert gpu_mean <= 2 * env_mean, (gpu_mean / h, env_mean / h)
     eg = _err_cloud(phi, w["grid"], w["points"])
     eo = _err_cloud(ophi, w["grid"], w["points"])
     assert abs(eg - eo) < 0.02 * h
-    print(f"torus3d fp64: 25 steps max |dphi| {e:.2e} h; 300 steps max {gpu_max / h:.2f} h "
-          f"mean {gpu_mean / h:.2e} h vs oracle envelope max {env_max / h:.2f} h "
-          f"mean {env_mean / h:.2e} h; Err_S {eg / h:.4f} h vs {eo / h:.4f} h")
+    print(f"torus3d fp64: 25 steps max |dphi| {e:.2e} h; stepwise max {step_err:.2e} h; "
+          f"300 steps mean {gpu_mean / h:.2e} h vs oracle envelope mean {env_mean / h:.2e} h; "
+          f"Err_S {eg / h:.4f} h vs {eo / h:.4f} h")
 
 
 def test_union3d_first_steps():
-    """The 256^3 non-uniform workload, first 20 steps (2 reinitialisations),
-    FP64 state."""
-    w = synth.workload("union3d", steps=20)
+    """The 256^3 non-uniform workload, FP64 state: within 1e-4 h from phi0
+    over the first 12 steps (one reinitialisation); each of the first 20
+    steps (two reinitialisations) within 1e-10 h of the oracle's step from
+    the device's state."""
+    w = synth.workload("union3d", steps=12)
     h = w["grid"]["h"]
-    phi, band, nb, si, cnt, _ = gpu_run(w, precision="fp64")
-    ophi, counts, _, prm = oracle_run(w)
+    d = oracle.distance(w["points"], w["grid"])
+    phi, band, nb, si, cnt, _ = gpu_run(w, d=d, precision="fp64")
+    ophi, counts, _, prm = oracle_run(w, d=d)
     check_phi(phi, ophi, h, 1e-4)
     check_band(band, phi, ophi, prm["gamma"], h)
+    step_err, where = stepwise_errors(w, 20, d)
+    assert step_err <= 1e-10, (step_err, where)
 
 
 def test_fp32_torus3d_full_size():
@@ -331,11 +401,21 @@ def test_torus_initial_data_and_ragged_2d(precision):
     phi, band, nb, _, _, _ = gpu_run(w, precision=precision)
     ophi, _, _, prm = oracle_run(w)
     check_phi(phi, ophi, g["h"], 1e-4)
+    # Torus phi0 on a grid with a node at its centre: the nodes of its axis
+    # and of its plane of symmetry sit on frame ties and on the cone points of
+    # phi0 and d.  FP64 state: 1e-4 h.  FP32 state: the oracle itself moves by
+    # ~3e-2 h when phi0 is perturbed at FP32 resolution, so the bar is twice
+    # that envelope (floored at 1e-4 h).
     w3 = synth.workload("torus3d", n=33, steps=6)
     w3["phi0"] = ("torus", (0.0, 0.0, 0.0, 0.5, 0.25))
+    h3 = w3["grid"]["h"]
     phi, band, nb, _, _, _ = gpu_run(w3, precision=precision)
-    ophi, _, _, prm = oracle_run(w3)
-    check_phi(phi, ophi, w3["grid"]["h"], 1e-4)
+    ophi, _, d3, prm = oracle_run(w3)
+    if precision == "fp64":
+        check_phi(phi, ophi, h3, 1e-4)
+    else:
+        env = np.abs(_perturbed_oracle(w3, d3, w3["steps"], rel=2.0 ** -24) - ophi).max()
+        check_phi(phi, ophi, h3, max(1e-4, 2 * env / h3))
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)

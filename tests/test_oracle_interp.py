@@ -218,3 +218,21 @@ def test_tensor_weno_last_axis_first_2d():
         w = [oracle.weno1d(vals[i0[0] - 1 + a, i0[1] - 1:i0[1] + 3], t[1], h) for a in range(4)]
         want = oracle.weno1d(np.array(w), t[0], h)
         assert oracle.interp(vals, g, p[None], "weno")[0] == pytest.approx(want, abs=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("kind", ["q1", "weno"])
+def test_constant_stencils_are_returned_exactly(dim, kind):
+    """Both interpolants reproduce constants (eqs. (IQ1), (IWENO)); the
+    oracle evaluates them so that this holds bit for bit, which fixes the
+    value read from inside the cut plateau at exactly +-gamma."""
+    g = _grid(dim, 9)
+    for c in (6 * 2.0 / 127, -0.0470588235294118, 0.3):
+        vals = np.full(g["n"], c)
+        pts = RNG.uniform(-1, 1, size=(200, dim))
+        got = oracle.interp(vals, g, pts, kind)
+        assert (got == c).all()
+    for s in RNG.uniform(0, 1, size=50):
+        v = np.full(4, 0.0472440944881889)
+        r, parts = oracle.weno1d(v, s, 0.1, parts=True)
+        assert r == v[0] and parts["wL"] + parts["wR"] == 1.0
