@@ -29,17 +29,31 @@ typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
 typedef double d4u __attribute__((ext_vector_type(4), aligned(8)));
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
+typedef float f4a __attribute__((ext_vector_type(4)));   // naturally aligned
+typedef double d4a __attribute__((ext_vector_type(4)));
+
 template <typename T> struct Vec;
 template <> struct Vec<float> {
   typedef f4u v4;
   typedef f2u v2;
-  typedef float4 pack;  // (d_x, d_y, d_z, d)
+  typedef float4 pack;  // (d_x, d_y, d_z, d) as stored
+  typedef f4a p4;       // the same, as the step kernel reads it
 };
 template <> struct Vec<double> {
   typedef d4u v4;
   typedef d2u v2;
   typedef double4 pack;
+  typedef d4a p4;
 };
+
+// Pointers into device memory with the address space in the type.  Loads
+// and stores through them compile to global-memory instructions even when the
+// pointer itself was read from a table in memory (the batched kernels), where
+// the compiler cannot infer the address space and would use flat ones.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+using gwptr = __attribute__((address_space(1))) T*;
 
 // Grid geometry as the kernels see it.  Band lists hold packed node
 // coordinates: code = (i << (bits_j + bits_k)) | (j << bits_k) | k.
@@ -170,10 +184,10 @@ __device__ __forceinline__ T weno1(T v0, T v1, T v2, T v3, const WC<T>& c, T e) 
 // Four values along the last axis at k0-1 .. k0+2 (indices clamped to the
 // grid, i.e. the boundary node repeated) of the row starting at `row`.
 template <typename T>
-__device__ __forceinline__ typename Vec<T>::v4 row4(const T* __restrict__ A, uint32_t row, int k0,
+__device__ __forceinline__ typename Vec<T>::v4 row4(gptr<T> A, uint32_t row, int k0,
                                                    int n) {
   typedef typename Vec<T>::v4 V;
-  if (k0 >= 1 && k0 + 2 <= n - 1) return *(const V*)(A + row + (uint32_t)(k0 - 1));
+  if (k0 >= 1 && k0 + 2 <= n - 1) return *(gptr<V>)(A + row + (uint32_t)(k0 - 1));
   V r;
   r.x = A[row + clampi(k0 - 1, n)];
   r.y = A[row + clampi(k0, n)];
@@ -185,7 +199,7 @@ __device__ __forceinline__ typename Vec<T>::v4 row4(const T* __restrict__ A, uin
 // Tensor WENO (Section 3.2): one-dimensional WENO along the last axis
 // first, then along the previous axes, x last.
 template <typename T>
-__device__ __forceinline__ T interp_weno3(const T* __restrict__ A, const DevGrid& g,
+__device__ __forceinline__ T interp_weno3(gptr<T> A, const DevGrid& g,
                                           const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz,
                                           T e) {
   const WC<T> cx = wcoef(lx.t), cy = wcoef(ly.t), cz = wcoef(lz.t);
@@ -206,7 +220,7 @@ __device__ __forceinline__ T interp_weno3(const T* __restrict__ A, const DevGrid
 }
 
 template <typename T>
-__device__ __forceinline__ T interp_weno2(const T* __restrict__ A, const DevGrid& g,
+__device__ __forceinline__ T interp_weno2(gptr<T> A, const DevGrid& g,
                                           const Loc<T>& lx, const Loc<T>& ly, T e) {
   const WC<T> cx = wcoef(lx.t), cy = wcoef(ly.t);
   T wx[4];
@@ -221,14 +235,14 @@ __device__ __forceinline__ T interp_weno2(const T* __restrict__ A, const DevGrid
 
 // Multilinear interpolation, eq. (IQ1).
 template <typename T>
-__device__ __forceinline__ T interp_q1_3(const T* __restrict__ A, const DevGrid& g,
+__device__ __forceinline__ T interp_q1_3(gptr<T> A, const DevGrid& g,
                                          const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) {
   typedef typename Vec<T>::v2 V2;
   const uint32_t r00 = (uint32_t)lx.i0 * g.s0 + (uint32_t)ly.i0 * g.s1 + (uint32_t)lz.i0;
-  V2 a00 = *(const V2*)(A + r00);
-  V2 a01 = *(const V2*)(A + r00 + g.s1);
-  V2 a10 = *(const V2*)(A + r00 + g.s0);
-  V2 a11 = *(const V2*)(A + r00 + g.s0 + g.s1);
+  V2 a00 = *(gptr<V2>)(A + r00);
+  V2 a01 = *(gptr<V2>)(A + r00 + g.s1);
+  V2 a10 = *(gptr<V2>)(A + r00 + g.s0);
+  V2 a11 = *(gptr<V2>)(A + r00 + g.s0 + g.s1);
   T tz = lz.t, ty = ly.t, tx = lx.t;
   T b00 = fma(tz, a00.y - a00.x, a00.x);
   T b01 = fma(tz, a01.y - a01.x, a01.x);
@@ -240,12 +254,12 @@ __device__ __forceinline__ T interp_q1_3(const T* __restrict__ A, const DevGrid&
 }
 
 template <typename T>
-__device__ __forceinline__ T interp_q1_2(const T* __restrict__ A, const DevGrid& g,
+__device__ __forceinline__ T interp_q1_2(gptr<T> A, const DevGrid& g,
                                          const Loc<T>& lx, const Loc<T>& ly) {
   typedef typename Vec<T>::v2 V2;
   const uint32_t r0 = (uint32_t)lx.i0 * g.s0 + (uint32_t)ly.i0;
-  V2 a0 = *(const V2*)(A + r0);
-  V2 a1 = *(const V2*)(A + r0 + g.s0);
+  V2 a0 = *(gptr<V2>)(A + r0);
+  V2 a1 = *(gptr<V2>)(A + r0 + g.s0);
   T b0 = fma(ly.t, a0.y - a0.x, a0.x);
   T b1 = fma(ly.t, a1.y - a1.x, a1.x);
   return fma(lx.t, b1 - b0, b0);
@@ -264,7 +278,7 @@ enum { UPD_FALLBACK = 1, UPD_FRAME0 = 2 };
 // with two cross-lane exchanges.  Both ways add the foot values as
 // (v0 + v1) + (v2 + v3), so they give bitwise identical results.
 template <int DIM, int INTERP, typename T>
-__device__ __forceinline__ T foot_value(const T* __restrict__ A, const DevGrid& g,
+__device__ __forceinline__ T foot_value(gptr<T> A, const DevGrid& g,
                                         const StepConst<T>& c, int i, int j, int k, int q, T bx,
                                         T by, T bz, T n1x, T n1y, T n1z, T n2x, T n2y, T n2z) {
   if (DIM == 2) {
@@ -281,9 +295,9 @@ __device__ __forceinline__ T foot_value(const T* __restrict__ A, const DevGrid& 
 }
 
 template <int DIM, int INTERP, typename T, int LANES>
-__device__ __forceinline__ T sl_update(const T* __restrict__ A, const DevGrid& g,
+__device__ __forceinline__ T sl_update(gptr<T> A, const DevGrid& g,
                                        const StepConst<T>& c, int i, int j, int k, uint32_t idx,
-                                       T v, typename Vec<T>::pack dp, int sub, int& flags) {
+                                       T v, typename Vec<T>::p4 dp, int sub, int& flags) {
   constexpr int FP = DIM == 3 ? 4 : 2;  // foot points per node
   T gx, gy, gz = T(0);
   T xm = i > 0 ? A[idx - g.s0] : v, xp = i < g.n0 - 1 ? A[idx + g.s0] : v;

@@ -37,8 +37,7 @@ __device__ __forceinline__ uint32_t wave_count(bool pred) { return (uint32_t)__p
 // atomic on the list counter per block.  lds holds at least 5 ints.
 template <int K>
 __device__ __forceinline__ void block_append(const bool (&pred)[K], const uint32_t (&val)[K],
-                                             uint32_t* __restrict__ out, int32_t* counter,
-                                             int* lds) {
+                                             gwptr<uint32_t> out, int32_t* counter, int* lds) {
   uint64_t m[K];
   int tot = 0;
 #pragma unroll
@@ -68,7 +67,7 @@ __device__ __forceinline__ void block_append(const bool (&pred)[K], const uint32
   __syncthreads();
 }
 
-__device__ __forceinline__ void block_append1(bool pred, uint32_t val, uint32_t* __restrict__ out,
+__device__ __forceinline__ void block_append1(bool pred, uint32_t val, gwptr<uint32_t> out,
                                               int32_t* counter, int* lds) {
   const bool p[1] = {pred};
   const uint32_t v[1] = {val};
@@ -181,7 +180,7 @@ __global__ __launch_bounds__(256) void k_band_scan(DevGrid g, T gamma, const T* 
       }
       code = encode(g, (int)(r / (uint32_t)g.n1), (int)(r % (uint32_t)g.n1), k);
     }
-    block_append1(in, code, L, cnt, lds);
+    block_append1(in, code, (gwptr<uint32_t>)L, cnt, lds);
   }
 }
 
@@ -229,6 +228,10 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
 template <int DIM, int INTERP, typename T, int LANES>
 __device__ __forceinline__ void sl_step_body(const SLArgs<T>& a, int* lds_app, uint32_t* lds_st) {
   constexpr uint32_t CH = 256 / LANES;  // entries per block and chunk
+  const gptr<T> A = (gptr<T>)a.A;
+  const gwptr<T> B = (gwptr<T>)a.B;
+  const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
+  const gptr<uint32_t> Lin = (gptr<uint32_t>)a.Lin;
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
@@ -243,20 +246,20 @@ __device__ __forceinline__ void sl_step_body(const SLArgs<T>& a, int* lds_app, u
     int fl = 0;
     uint32_t code = 0;
     if (e < (uint32_t)n) {
-      code = a.Lin[e];
+      code = Lin[e];
       int i, j, k;
       decode(a.g, code, i, j, k);
       const uint32_t idx = lin(a.g, i, j, k);
-      const T v = a.A[idx];
+      const T v = A[idx];
       T nv = v;
       if (fabs(v) < a.c.gamma) {
         act = true;
-        nv = sl_update<DIM, INTERP, T, LANES>(a.A, a.g, a.c, i, j, k, idx, v, a.dp[idx], sub, fl);
+        nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, a.c, i, j, k, idx, v, DP[idx], sub, fl);
       }
-      if (sub == 0) a.B[idx] = nv;
+      if (sub == 0) B[idx] = nv;
     }
     const bool lead = act && sub == 0;
-    block_append1(lead, code, a.Lout, a.cnt_out, lds_app);
+    block_append1(lead, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds_app);
     nupd += wave_count(lead);
     nfb += wave_count(sub == 0 && (fl & UPD_FALLBACK));
     nfr += wave_count(sub == 0 && (fl & UPD_FRAME0));
@@ -304,7 +307,7 @@ __device__ __forceinline__ void dilate_body(const DilArgs& a, int* lds) {
     const uint32_t e = base + threadIdx.x;
     const bool valid = e < (uint32_t)n;
     int i = 0, j = 0, k = 0;
-    if (valid) decode(a.g, a.L[e], i, j, k);
+    if (valid) decode(a.g, ((gptr<uint32_t>)a.L)[e], i, j, k);
     bool ins[K];
     uint32_t code[K];
 #pragma unroll
@@ -320,7 +323,7 @@ __device__ __forceinline__ void dilate_body(const DilArgs& a, int* lds) {
         code[c] = encode(a.g, ii, jj, kk);
       }
     }
-    block_append<K>(ins, code, a.M, a.cnt_out, lds);
+    block_append<K>(ins, code, (gwptr<uint32_t>)a.M, a.cnt_out, lds);
   }
 }
 
@@ -346,6 +349,10 @@ __global__ __launch_bounds__(256) void k_dilate_batch(const DilArgs* __restrict_
 // flags: bit 7 interface, bits 0-1 sign of phi~ (1 positive, 2 negative).
 template <int DIM, typename T>
 __device__ __forceinline__ void reinit_fix_body(const RArgs<T>& a, uint32_t* lds_st) {
+  const gptr<T> src = (gptr<T>)a.src;
+  const gwptr<T> dst = (gwptr<T>)a.dst;
+  const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
+  const gwptr<uint8_t> flags = (gwptr<uint8_t>)a.flags;
   const int n = *a.cnt;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   uint32_t nif = 0, ng = 0;
@@ -357,15 +364,15 @@ __device__ __forceinline__ void reinit_fix_body(const RArgs<T>& a, uint32_t* lds
     const bool valid = e < (uint32_t)n;
     if (valid) {
       int i, j, k;
-      decode(a.g, a.M[e], i, j, k);
+      decode(a.g, M[e], i, j, k);
       const uint32_t idx = lin(a.g, i, j, k);
-      const T t = a.src[idx];
-      const T xm = i > 0 ? a.src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? a.src[idx + a.g.s0] : t;
-      const T ym = j > 0 ? a.src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? a.src[idx + a.g.s1] : t;
+      const T t = src[idx];
+      const T xm = i > 0 ? src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? src[idx + a.g.s0] : t;
+      const T ym = j > 0 ? src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? src[idx + a.g.s1] : t;
       T zm = t, zp = t;
       if (DIM == 3) {
-        zm = k > 0 ? a.src[idx - 1] : t;
-        zp = k < a.g.n2 - 1 ? a.src[idx + 1] : t;
+        zm = k > 0 ? src[idx - 1] : t;
+        zp = k < a.g.n2 - 1 ? src[idx + 1] : t;
       }
       const T z0 = T(0);
       itf = (i > 0 && t * xm <= z0) || (i < a.g.n0 - 1 && t * xp <= z0) ||
@@ -379,8 +386,8 @@ __device__ __forceinline__ void reinit_fix_body(const RArgs<T>& a, uint32_t* lds
         const T nr = fmax(sqrt(gx * gx + gy * gy + gz * gz), a.floor_);
         w = t / nr;
       }
-      a.dst[idx] = w;
-      a.flags[e] = (uint8_t)((itf ? 0x80 : 0) | (t > z0 ? 1 : (t < z0 ? 2 : 0)));
+      dst[idx] = w;
+      flags[e] = (uint8_t)((itf ? 0x80 : 0) | (t > z0 ? 1 : (t < z0 ? 2 : 0)));
     }
     nif += wave_count(itf);
     ng += wave_count(valid);
@@ -409,6 +416,10 @@ __global__ __launch_bounds__(256) void k_reinit_fix_batch(const RArgs<T>* __rest
 // missing neighbour contributes no difference.  src -> dst on Gbar.
 template <int DIM, typename T>
 __device__ __forceinline__ void reinit_iter_body(const RArgs<T>& a) {
+  const gptr<T> src = (gptr<T>)a.src;
+  const gwptr<T> dst = (gwptr<T>)a.dst;
+  const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
+  const gptr<uint8_t> flags = (gptr<uint8_t>)a.flags;
   const int n = *a.cnt;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
@@ -417,10 +428,10 @@ __device__ __forceinline__ void reinit_iter_body(const RArgs<T>& a) {
     const uint32_t e = base + threadIdx.x;
     if (e >= (uint32_t)n) continue;
     int i, j, k;
-    decode(a.g, a.M[e], i, j, k);
+    decode(a.g, M[e], i, j, k);
     const uint32_t idx = lin(a.g, i, j, k);
-    const uint8_t f = a.flags[e];
-    T v = a.src[idx];
+    const uint8_t f = flags[e];
+    T v = src[idx];
     if (!(f & 0x80) && (f & 3)) {
       const bool pos = f & 1;
       const T z0 = T(0);
@@ -430,8 +441,8 @@ __device__ __forceinline__ void reinit_iter_body(const RArgs<T>& a) {
         const int ci = ax == 0 ? i : (ax == 1 ? j : k);
         const int nn = ax == 0 ? a.g.n0 : (ax == 1 ? a.g.n1 : a.g.n2);
         const uint32_t s = ax == 0 ? a.g.s0 : (ax == 1 ? a.g.s1 : 1u);
-        const T Dm = ci > 0 ? (v - a.src[idx - s]) * a.c.inv_h : z0;
-        const T Dp = ci < nn - 1 ? (a.src[idx + s] - v) * a.c.inv_h : z0;
+        const T Dm = ci > 0 ? (v - src[idx - s]) * a.c.inv_h : z0;
+        const T Dp = ci < nn - 1 ? (src[idx + s] - v) * a.c.inv_h : z0;
         T t1, t2;
         if (pos) {
           t1 = Dm > z0 ? Dm * Dm : z0;
@@ -445,7 +456,7 @@ __device__ __forceinline__ void reinit_iter_body(const RArgs<T>& a) {
       const T S = pos ? T(1) : T(-1);
       v = v - a.dtau * S * (sqrt(G2) - T(1));
     }
-    a.dst[idx] = v;
+    dst[idx] = v;
   }
 }
 
@@ -465,6 +476,9 @@ __global__ __launch_bounds__(256) void k_reinit_iter_batch(const RArgs<T>* __res
 // Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
 template <typename T>
 __device__ __forceinline__ void reinit_final_body(const FinArgs<T>& a, int* lds) {
+  const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
+  const gwptr<T> cur = (gwptr<T>)a.cur;
+  const gwptr<T> other = (gwptr<T>)a.other;
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
@@ -475,16 +489,16 @@ __device__ __forceinline__ void reinit_final_body(const FinArgs<T>& a, int* lds)
     bool in = false;
     uint32_t code = 0;
     if (e < (uint32_t)n) {
-      code = a.M[e];
+      code = M[e];
       int i, j, k;
       decode(a.g, code, i, j, k);
       const uint32_t idx = lin(a.g, i, j, k);
-      const T v = fmin(fmax(a.cur[idx], -a.gamma), a.gamma);
-      a.cur[idx] = v;
-      a.other[idx] = v;
+      const T v = fmin(fmax(cur[idx], -a.gamma), a.gamma);
+      cur[idx] = v;
+      other[idx] = v;
       in = fabs(v) < a.gamma;
     }
-    block_append1(in, code, a.Lout, a.cnt_out, lds);
+    block_append1(in, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds);
   }
 }
 
@@ -568,7 +582,7 @@ __global__ __launch_bounds__(256) void k_occupied(const int32_t* __restrict__ st
   for (uint32_t base = blockIdx.x * 256u; base < (uint32_t)nbins; base += gridDim.x * 256u) {
     const uint32_t b = base + threadIdx.x;
     const bool nz = b < (uint32_t)nbins && start[b + 1] > start[b];
-    block_append1(nz, b, occ, cnt, lds);
+    block_append1(nz, b, (gwptr<uint32_t>)occ, cnt, lds);
   }
 }
 

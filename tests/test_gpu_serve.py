@@ -1,0 +1,58 @@
+"""Served execution on the GPU: jobs arriving over time and running in one
+continuously re-formed batch give bitwise the result each gives alone."""
+import numpy as np
+import pytest
+
+from paper_2410_22205_amd import serve, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(n, seed, steps_range=(20, 37)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, w in enumerate(synth.batch_jobs(n_jobs=n, seed=seed, n_range=(40, 64),
+                                           pts_range=(2000, 8000))):
+        w = dict(w)
+        w["steps"] = int(rng.integers(*steps_range))
+        w["arrival"] = 0.0005 * k
+        w["interp"] = "weno"
+        out.append(w)
+    return out
+
+
+def _alone(req, precision):
+    from paper_2410_22205_amd import lsr
+    job = lsr.Job(req["grid"], serve.job_params(req, precision), max_points=len(req["points"]))
+    job.load_cloud(req["points"])
+    job.init_phi(req["phi0"][0], req["phi0"][1])
+    job.step(req["steps"], req["dt"], req["interp"])
+    phi, band, _, si = job.extract()
+    job.close()
+    assert si == req["steps"]
+    return phi.ravel(), band.ravel()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_served_results_equal_alone(precision):
+    reqs = _requests(6, 4500)
+    srv = serve.Server(max_active=8, group_steps=7, precision=precision)
+    out = srv.run(reqs, keep_results=True)
+    assert out["jobs"] == len(reqs) and not out["rejected"]
+    assert out["max_batch"] >= 2  # the jobs did share the batch
+    for i, req in enumerate(reqs):
+        phi, band = _alone(req, precision)
+        np.testing.assert_array_equal(out["results"][i][0], phi)
+        np.testing.assert_array_equal(out["results"][i][1], band)
+
+
+def test_budget_bounds_the_mix_and_sequential_replay_agrees():
+    reqs = _requests(5, 4600)
+    one = max(serve.footprint_bytes(r, "fp32") for r in reqs)
+    srv = serve.Server(budget_bytes=2 * one, max_active=8, group_steps=5, precision="fp32")
+    out = srv.run(reqs, keep_results=True)
+    assert out["jobs"] == 5 and out["max_batch"] <= 2
+    seq = serve.run_sequential(reqs, precision="fp32", keep_results=True)
+    for i in range(len(reqs)):
+        np.testing.assert_array_equal(out["results"][i][0], seq["results"][i][0])
+    assert out["latency_ms"]["p99"] >= out["latency_ms"]["p50"] > 0
