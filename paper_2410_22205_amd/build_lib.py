@@ -15,6 +15,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a multiply and an add only within one source expression: the same
+    # source then rounds the same way in every kernel that inlines it (the
+    # single-job and batched kernels give bitwise equal results)
+    "-ffp-contract=on",
     "-fno-gpu-rdc", "-Wall", "-Wno-unused-result",
 ]
 

@@ -7,6 +7,9 @@
 // contiguous stretch of the list (its own L2 then sees neighbouring nodes).
 // Lists are compacted with a wave-wide ballot, a popcount and one atomic per
 // wave.
+#include <mutex>
+#include <unordered_map>
+
 #include "lsr_internal.h"
 
 namespace lsr {
@@ -225,70 +228,135 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
 // new list.  The new list is the set of entries updated here (the band of
 // this step).  cnt_reset is the list counter the next step will write.
 // LANES lanes share one entry (see sl_update).
+//
+// Each kernel below is a per-chunk body (one block, CH consecutive list
+// entries) driven either over one job's list or, in the batched kernels, over
+// the chunks of all jobs of the table numbered one after the other: every
+// block takes global chunk numbers in increasing order, XCD-striped as in the
+// single-job kernels, and follows them from job to job, so that blocks start
+// on different jobs and no block idles while another works through the jobs.
+
 template <int DIM, int INTERP, typename T, int LANES>
-__device__ __forceinline__ void sl_step_body(const SLArgs<T>& a, int* lds_app, uint32_t* lds_st) {
-  constexpr uint32_t CH = 256 / LANES;  // entries per block and chunk
+__device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t base, int n, int* lds_app,
+                                         uint32_t& nupd, uint32_t& nfb, uint32_t& nfr) {
   const gptr<T> A = (gptr<T>)a.A;
   const gwptr<T> B = (gwptr<T>)a.B;
   const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
   const gptr<uint32_t> Lin = (gptr<uint32_t>)a.Lin;
-  const int n = *a.cnt_in;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   const int sub = (int)(threadIdx.x % LANES);
-  const uint32_t slot = threadIdx.x / LANES;
-  uint32_t nupd = 0, nfb = 0, nfr = 0;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * CH;
-    if (base >= (uint32_t)n) break;
-    const uint32_t e = base + slot;
-    bool act = false;
-    int fl = 0;
-    uint32_t code = 0;
-    if (e < (uint32_t)n) {
-      code = Lin[e];
-      int i, j, k;
-      decode(a.g, code, i, j, k);
-      const uint32_t idx = lin(a.g, i, j, k);
-      const T v = A[idx];
-      T nv = v;
-      if (fabs(v) < a.c.gamma) {
-        act = true;
-        nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, a.c, i, j, k, idx, v, DP[idx], sub, fl);
-      }
-      if (sub == 0) B[idx] = nv;
+  const uint32_t e = base + threadIdx.x / LANES;
+  bool act = false;
+  int fl = 0;
+  uint32_t code = 0;
+  if (e < (uint32_t)n) {
+    code = Lin[e];
+    int i, j, k;
+    decode(a.g, code, i, j, k);
+    const uint32_t idx = lin(a.g, i, j, k);
+    const T v = A[idx];
+    T nv = v;
+    if (fabs(v) < a.c.gamma) {
+      act = true;
+      nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, a.c, i, j, k, idx, v, DP[idx], sub, fl);
     }
-    const bool lead = act && sub == 0;
-    block_append1(lead, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds_app);
-    nupd += wave_count(lead);
-    nfb += wave_count(sub == 0 && (fl & UPD_FALLBACK));
-    nfr += wave_count(sub == 0 && (fl & UPD_FRAME0));
+    if (sub == 0) B[idx] = nv;
   }
-  block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
+  const bool lead = act && sub == 0;
+  block_append1(lead, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds_app);
+  nupd += wave_count(lead);
+  nfb += wave_count(sub == 0 && (fl & UPD_FALLBACK));
+  nfr += wave_count(sub == 0 && (fl & UPD_FRAME0));
 }
 
 template <int DIM, int INTERP, typename T, int LANES>
 __global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
+  constexpr uint32_t CH = 256 / LANES;  // entries per block and chunk
   __shared__ int lds_app[8];
   __shared__ uint32_t lds_st[12];
-  sl_step_body<DIM, INTERP, T, LANES>(a, lds_app, lds_st);
+  const int n = *a.cnt_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  uint32_t nupd = 0, nfb = 0, nfr = 0;
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * CH;
+    if (base >= (uint32_t)n) break;
+    sl_chunk<DIM, INTERP, T, LANES>(a, base, n, lds_app, nupd, nfb, nfr);
+  }
+  block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
 }
 
-// The same step for a batch of independent jobs in one launch: every block
-// takes part in every job's list in turn (per-job arguments from a packed
-// table, interpolator per job).  Per-node arithmetic is that of k_sl_step.
+// A table entry read with scalar loads into scalar registers, as kernel
+// arguments are: the table is read through the constant address space (the
+// host writes it before the launch and nothing writes it during one) at a
+// wave-uniform index, so the per-job arguments neither cost vector memory
+// instructions nor occupy vector registers.
+template <typename A>
+__device__ __forceinline__ A uniform_load(const A* tab, int index) {
+  static_assert(sizeof(A) % 4 == 0, "table entries are whole words");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  const int q = __builtin_amdgcn_readfirstlane(index);
+  cword* src = (cword*)(tab + q);
+  A out;
+  uint32_t* dst = (uint32_t*)&out;
+#pragma unroll
+  for (unsigned w = 0; w < sizeof(A) / 4; ++w) dst[w] = src[w];
+  return out;
+}
+
+// Cursor of a block over the jobs of a batched launch: job jb holds the
+// global chunks [beg, end) and nl list entries.  advance() moves to the job
+// holding chunk gch and returns false once gch lies past the last job; on
+// every job change it calls leave(jb) for the job being left (uniform across
+// the block).  Only these integers are carried from chunk to chunk; the
+// job's arguments are read again for every chunk (into scalar registers).
+struct JobCursor {
+  int n, jb = -1, nl = 0;
+  uint32_t beg = 0, end = 0;
+  template <typename A, typename Leave>
+  __device__ __forceinline__ bool advance(const A* tab, uint32_t gch, uint32_t ch, Leave leave) {
+    while (gch >= end) {
+      if (jb >= 0) leave(jb);
+      if (++jb >= n) return false;
+      nl = __builtin_amdgcn_readfirstlane(*count(uniform_load(tab, jb)));
+      beg = end;
+      end = beg + ((uint32_t)nl + ch - 1) / ch;
+    }
+    return true;
+  }
+  static __device__ __forceinline__ const int32_t* count(const SLArgs<float>& x) { return x.cnt_in; }
+  static __device__ __forceinline__ const int32_t* count(const SLArgs<double>& x) { return x.cnt_in; }
+  static __device__ __forceinline__ const int32_t* count(const DilArgs& x) { return x.cnt_in; }
+  static __device__ __forceinline__ const int32_t* count(const RArgs<float>& x) { return x.cnt; }
+  static __device__ __forceinline__ const int32_t* count(const RArgs<double>& x) { return x.cnt; }
+  static __device__ __forceinline__ const int32_t* count(const FinArgs<float>& x) { return x.cnt_in; }
+  static __device__ __forceinline__ const int32_t* count(const FinArgs<double>& x) { return x.cnt_in; }
+};
+
 template <int DIM, typename T, int LANES>
 __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab,
                                                        const int32_t* __restrict__ interp, int n) {
+  constexpr uint32_t CH = 256 / LANES;
   __shared__ int lds_app[8];
   __shared__ uint32_t lds_st[12];
-  for (int jb = 0; jb < n; ++jb) {
-    const SLArgs<T> a = tab[jb];
-    if (interp[jb] == 0)
-      sl_step_body<DIM, 0, T, LANES>(a, lds_app, lds_st);
+  if (blockIdx.x == 0)
+    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_reset = 0;
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  uint32_t nupd = 0, nfb = 0, nfr = 0;
+  JobCursor cur{n};
+  auto leave = [&](int jb) {
+    const SLArgs<T> a = uniform_load(tab, jb);
+    block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
+    nupd = nfb = nfr = 0;
+  };
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t gch = chunk_of(q, xcd);
+    if (!cur.advance(tab, gch, CH, leave)) break;
+    const SLArgs<T> a = uniform_load(tab, cur.jb);
+    const uint32_t base = (gch - cur.beg) * CH;
+    if (((const __attribute__((address_space(4))) int32_t*)interp)[cur.jb] == 0)
+      sl_chunk<DIM, 0, T, LANES>(a, base, cur.nl, lds_app, nupd, nfb, nfr);
     else
-      sl_step_body<DIM, 1, T, LANES>(a, lds_app, lds_st);
-    __syncthreads();
+      sl_chunk<DIM, 1, T, LANES>(a, base, cur.nl, lds_app, nupd, nfb, nfr);
   }
 }
 
@@ -296,50 +364,55 @@ __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restri
 
 // Gbar = band + face neighbours, deduplicated through a per-node stamp.
 template <int DIM>
-__device__ __forceinline__ void dilate_body(const DilArgs& a, int* lds) {
-  const int n = *a.cnt_in;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+__device__ __forceinline__ void dilate_chunk(const DilArgs& a, uint32_t base, int n, int* lds) {
   constexpr int K = 1 + 2 * DIM;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * 256u;
-    if (base >= (uint32_t)n) break;
-    const uint32_t e = base + threadIdx.x;
-    const bool valid = e < (uint32_t)n;
-    int i = 0, j = 0, k = 0;
-    if (valid) decode(a.g, ((gptr<uint32_t>)a.L)[e], i, j, k);
-    bool ins[K];
-    uint32_t code[K];
+  const uint32_t e = base + threadIdx.x;
+  const bool valid = e < (uint32_t)n;
+  int i = 0, j = 0, k = 0;
+  if (valid) decode(a.g, ((gptr<uint32_t>)a.L)[e], i, j, k);
+  bool ins[K];
+  uint32_t code[K];
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
-      const int ii = i + (c == 1 ? -1 : c == 2 ? 1 : 0);
-      const int jj = j + (c == 3 ? -1 : c == 4 ? 1 : 0);
-      const int kk = k + (c == 5 ? -1 : c == 6 ? 1 : 0);
-      ins[c] = false;
-      code[c] = 0;
-      if (valid && ii >= 0 && ii < a.g.n0 && jj >= 0 && jj < a.g.n1 && kk >= 0 && kk < a.g.n2) {
-        const uint32_t old = atomicMax(&a.stamp[lin(a.g, ii, jj, kk)], a.epoch);
-        ins[c] = old < a.epoch;
-        code[c] = encode(a.g, ii, jj, kk);
-      }
+  for (int c = 0; c < K; ++c) {
+    const int ii = i + (c == 1 ? -1 : c == 2 ? 1 : 0);
+    const int jj = j + (c == 3 ? -1 : c == 4 ? 1 : 0);
+    const int kk = k + (c == 5 ? -1 : c == 6 ? 1 : 0);
+    ins[c] = false;
+    code[c] = 0;
+    if (valid && ii >= 0 && ii < a.g.n0 && jj >= 0 && jj < a.g.n1 && kk >= 0 && kk < a.g.n2) {
+      const uint32_t old = atomicMax(&a.stamp[lin(a.g, ii, jj, kk)], a.epoch);
+      ins[c] = old < a.epoch;
+      code[c] = encode(a.g, ii, jj, kk);
     }
-    block_append<K>(ins, code, (gwptr<uint32_t>)a.M, a.cnt_out, lds);
   }
+  block_append<K>(ins, code, (gwptr<uint32_t>)a.M, a.cnt_out, lds);
 }
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
   __shared__ int lds[8];
-  dilate_body<DIM>(a, lds);
+  const int n = *a.cnt_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t base = chunk_of(q, xcd) * 256u;
+    if (base >= (uint32_t)n) break;
+    dilate_chunk<DIM>(a, base, n, lds);
+  }
 }
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_dilate_batch(const DilArgs* __restrict__ tab, int n) {
   __shared__ int lds[8];
-  for (int jb = 0; jb < n; ++jb) {
-    const DilArgs a = tab[jb];
-    dilate_body<DIM>(a, lds);
-    __syncthreads();
+  if (blockIdx.x == 0)
+    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_reset = 0;
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  JobCursor cur{n};
+  auto leave = [](int) {};
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t gch = chunk_of(q, xcd);
+    if (!cur.advance(tab, gch, 256u, leave)) break;
+    dilate_chunk<DIM>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl, lds);
   }
 }
 
@@ -348,66 +421,75 @@ __global__ __launch_bounds__(256) void k_dilate_batch(const DilArgs* __restrict_
 // (a face neighbour of opposite or zero sign), dst = phi~ elsewhere on Gbar.
 // flags: bit 7 interface, bits 0-1 sign of phi~ (1 positive, 2 negative).
 template <int DIM, typename T>
-__device__ __forceinline__ void reinit_fix_body(const RArgs<T>& a, uint32_t* lds_st) {
+__device__ __forceinline__ void fix_chunk(const RArgs<T>& a, uint32_t base, int n, uint32_t& ng,
+                                          uint32_t& nif) {
   const gptr<T> src = (gptr<T>)a.src;
   const gwptr<T> dst = (gwptr<T>)a.dst;
   const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
   const gwptr<uint8_t> flags = (gwptr<uint8_t>)a.flags;
+  const uint32_t e = base + threadIdx.x;
+  bool itf = false;
+  const bool valid = e < (uint32_t)n;
+  if (valid) {
+    int i, j, k;
+    decode(a.g, M[e], i, j, k);
+    const uint32_t idx = lin(a.g, i, j, k);
+    const T t = src[idx];
+    const T xm = i > 0 ? src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? src[idx + a.g.s0] : t;
+    const T ym = j > 0 ? src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? src[idx + a.g.s1] : t;
+    T zm = t, zp = t;
+    if (DIM == 3) {
+      zm = k > 0 ? src[idx - 1] : t;
+      zp = k < a.g.n2 - 1 ? src[idx + 1] : t;
+    }
+    const T z0 = T(0);
+    itf = (i > 0 && t * xm <= z0) || (i < a.g.n0 - 1 && t * xp <= z0) ||
+          (j > 0 && t * ym <= z0) || (j < a.g.n1 - 1 && t * yp <= z0);
+    if (DIM == 3) itf = itf || (k > 0 && t * zm <= z0) || (k < a.g.n2 - 1 && t * zp <= z0);
+    T w = t;
+    if (itf) {
+      const T gx = cdiff(xm, t, xp, i, a.g.n0, a.c);
+      const T gy = cdiff(ym, t, yp, j, a.g.n1, a.c);
+      const T gz = DIM == 3 ? cdiff(zm, t, zp, k, a.g.n2, a.c) : z0;
+      const T nr = fmax(sqrt(gx * gx + gy * gy + gz * gz), a.floor_);
+      w = t / nr;
+    }
+    dst[idx] = w;
+    flags[e] = (uint8_t)((itf ? 0x80 : 0) | (t > z0 ? 1 : (t < z0 ? 2 : 0)));
+  }
+  nif += wave_count(itf);
+  ng += wave_count(valid);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
+  __shared__ uint32_t lds_st[12];
   const int n = *a.cnt;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   uint32_t nif = 0, ng = 0;
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
     const uint32_t base = chunk_of(q, xcd) * 256u;
     if (base >= (uint32_t)n) break;
-    const uint32_t e = base + threadIdx.x;
-    bool itf = false;
-    const bool valid = e < (uint32_t)n;
-    if (valid) {
-      int i, j, k;
-      decode(a.g, M[e], i, j, k);
-      const uint32_t idx = lin(a.g, i, j, k);
-      const T t = src[idx];
-      const T xm = i > 0 ? src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? src[idx + a.g.s0] : t;
-      const T ym = j > 0 ? src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? src[idx + a.g.s1] : t;
-      T zm = t, zp = t;
-      if (DIM == 3) {
-        zm = k > 0 ? src[idx - 1] : t;
-        zp = k < a.g.n2 - 1 ? src[idx + 1] : t;
-      }
-      const T z0 = T(0);
-      itf = (i > 0 && t * xm <= z0) || (i < a.g.n0 - 1 && t * xp <= z0) ||
-            (j > 0 && t * ym <= z0) || (j < a.g.n1 - 1 && t * yp <= z0);
-      if (DIM == 3) itf = itf || (k > 0 && t * zm <= z0) || (k < a.g.n2 - 1 && t * zp <= z0);
-      T w = t;
-      if (itf) {
-        const T gx = cdiff(xm, t, xp, i, a.g.n0, a.c);
-        const T gy = cdiff(ym, t, yp, j, a.g.n1, a.c);
-        const T gz = DIM == 3 ? cdiff(zm, t, zp, k, a.g.n2, a.c) : z0;
-        const T nr = fmax(sqrt(gx * gx + gy * gy + gz * gz), a.floor_);
-        w = t / nr;
-      }
-      dst[idx] = w;
-      flags[e] = (uint8_t)((itf ? 0x80 : 0) | (t > z0 ? 1 : (t < z0 ? 2 : 0)));
-    }
-    nif += wave_count(itf);
-    ng += wave_count(valid);
+    fix_chunk<DIM, T>(a, base, n, ng, nif);
   }
   block_add3(ng, nif, 0, &a.stats[4], &a.stats[5], nullptr, lds_st);
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
-  __shared__ uint32_t lds_st[12];
-  reinit_fix_body<DIM, T>(a, lds_st);
-}
-
-template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_fix_batch(const RArgs<T>* __restrict__ tab, int n) {
   __shared__ uint32_t lds_st[12];
-  for (int jb = 0; jb < n; ++jb) {
-    const RArgs<T> a = tab[jb];
-    reinit_fix_body<DIM, T>(a, lds_st);
-    __syncthreads();
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  uint32_t nif = 0, ng = 0;
+  JobCursor cur{n};
+  auto leave = [&](int jb) {
+    const RArgs<T> a = uniform_load(tab, jb);
+    block_add3(ng, nif, 0, &a.stats[4], &a.stats[5], nullptr, lds_st);
+    ng = nif = 0;
+  };
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t gch = chunk_of(q, xcd);
+    if (!cur.advance(tab, gch, 256u, leave)) break;
+    fix_chunk<DIM, T>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl, ng, nif);
   }
 }
 
@@ -415,107 +497,116 @@ __global__ __launch_bounds__(256) void k_reinit_fix_batch(const RArgs<T>* __rest
 // Gbar minus the interface set, first-order upwind (Godunov) gradient; a
 // missing neighbour contributes no difference.  src -> dst on Gbar.
 template <int DIM, typename T>
-__device__ __forceinline__ void reinit_iter_body(const RArgs<T>& a) {
+__device__ __forceinline__ void iter_chunk(const RArgs<T>& a, uint32_t base, int n) {
   const gptr<T> src = (gptr<T>)a.src;
   const gwptr<T> dst = (gwptr<T>)a.dst;
   const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
   const gptr<uint8_t> flags = (gptr<uint8_t>)a.flags;
+  const uint32_t e = base + threadIdx.x;
+  if (e >= (uint32_t)n) return;
+  int i, j, k;
+  decode(a.g, M[e], i, j, k);
+  const uint32_t idx = lin(a.g, i, j, k);
+  const uint8_t f = flags[e];
+  T v = src[idx];
+  if (!(f & 0x80) && (f & 3)) {
+    const bool pos = f & 1;
+    const T z0 = T(0);
+    T G2 = z0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const int ci = ax == 0 ? i : (ax == 1 ? j : k);
+      const int nn = ax == 0 ? a.g.n0 : (ax == 1 ? a.g.n1 : a.g.n2);
+      const uint32_t s = ax == 0 ? a.g.s0 : (ax == 1 ? a.g.s1 : 1u);
+      const T Dm = ci > 0 ? (v - src[idx - s]) * a.c.inv_h : z0;
+      const T Dp = ci < nn - 1 ? (src[idx + s] - v) * a.c.inv_h : z0;
+      T t1, t2;
+      if (pos) {
+        t1 = Dm > z0 ? Dm * Dm : z0;
+        t2 = Dp < z0 ? Dp * Dp : z0;
+      } else {
+        t1 = Dm < z0 ? Dm * Dm : z0;
+        t2 = Dp > z0 ? Dp * Dp : z0;
+      }
+      G2 += fmax(t1, t2);
+    }
+    const T S = pos ? T(1) : T(-1);
+    v = v - a.dtau * S * (sqrt(G2) - T(1));
+  }
+  dst[idx] = v;
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
   const int n = *a.cnt;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
     const uint32_t base = chunk_of(q, xcd) * 256u;
     if (base >= (uint32_t)n) break;
-    const uint32_t e = base + threadIdx.x;
-    if (e >= (uint32_t)n) continue;
-    int i, j, k;
-    decode(a.g, M[e], i, j, k);
-    const uint32_t idx = lin(a.g, i, j, k);
-    const uint8_t f = flags[e];
-    T v = src[idx];
-    if (!(f & 0x80) && (f & 3)) {
-      const bool pos = f & 1;
-      const T z0 = T(0);
-      T G2 = z0;
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) {
-        const int ci = ax == 0 ? i : (ax == 1 ? j : k);
-        const int nn = ax == 0 ? a.g.n0 : (ax == 1 ? a.g.n1 : a.g.n2);
-        const uint32_t s = ax == 0 ? a.g.s0 : (ax == 1 ? a.g.s1 : 1u);
-        const T Dm = ci > 0 ? (v - src[idx - s]) * a.c.inv_h : z0;
-        const T Dp = ci < nn - 1 ? (src[idx + s] - v) * a.c.inv_h : z0;
-        T t1, t2;
-        if (pos) {
-          t1 = Dm > z0 ? Dm * Dm : z0;
-          t2 = Dp < z0 ? Dp * Dp : z0;
-        } else {
-          t1 = Dm < z0 ? Dm * Dm : z0;
-          t2 = Dp > z0 ? Dp * Dp : z0;
-        }
-        G2 += fmax(t1, t2);
-      }
-      const T S = pos ? T(1) : T(-1);
-      v = v - a.dtau * S * (sqrt(G2) - T(1));
-    }
-    dst[idx] = v;
+    iter_chunk<DIM, T>(a, base, n);
   }
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
-  reinit_iter_body<DIM, T>(a);
-}
-
-template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_iter_batch(const RArgs<T>* __restrict__ tab, int n) {
-  for (int jb = 0; jb < n; ++jb) {
-    const RArgs<T> a = tab[jb];
-    reinit_iter_body<DIM, T>(a);
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  JobCursor cur{n};
+  auto leave = [](int) {};
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t gch = chunk_of(q, xcd);
+    if (!cur.advance(tab, gch, 256u, leave)) break;
+    iter_chunk<DIM, T>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl);
   }
 }
 
 // Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
 template <typename T>
-__device__ __forceinline__ void reinit_final_body(const FinArgs<T>& a, int* lds) {
+__device__ __forceinline__ void final_chunk(const FinArgs<T>& a, uint32_t base, int n, int* lds) {
   const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
   const gwptr<T> cur = (gwptr<T>)a.cur;
   const gwptr<T> other = (gwptr<T>)a.other;
+  const uint32_t e = base + threadIdx.x;
+  bool in = false;
+  uint32_t code = 0;
+  if (e < (uint32_t)n) {
+    code = M[e];
+    int i, j, k;
+    decode(a.g, code, i, j, k);
+    const uint32_t idx = lin(a.g, i, j, k);
+    const T v = fmin(fmax(cur[idx], -a.gamma), a.gamma);
+    cur[idx] = v;
+    other[idx] = v;
+    in = fabs(v) < a.gamma;
+  }
+  block_append1(in, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
+  __shared__ int lds[8];
   const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
     const uint32_t base = chunk_of(q, xcd) * 256u;
     if (base >= (uint32_t)n) break;
-    const uint32_t e = base + threadIdx.x;
-    bool in = false;
-    uint32_t code = 0;
-    if (e < (uint32_t)n) {
-      code = M[e];
-      int i, j, k;
-      decode(a.g, code, i, j, k);
-      const uint32_t idx = lin(a.g, i, j, k);
-      const T v = fmin(fmax(cur[idx], -a.gamma), a.gamma);
-      cur[idx] = v;
-      other[idx] = v;
-      in = fabs(v) < a.gamma;
-    }
-    block_append1(in, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds);
+    final_chunk<T>(a, base, n, lds);
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
-  __shared__ int lds[8];
-  reinit_final_body<T>(a, lds);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_reinit_final_batch(const FinArgs<T>* __restrict__ tab,
                                                             int n) {
   __shared__ int lds[8];
-  for (int jb = 0; jb < n; ++jb) {
-    const FinArgs<T> a = tab[jb];
-    reinit_final_body<T>(a, lds);
-    __syncthreads();
+  if (blockIdx.x == 0)
+    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_reset = 0;
+  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  JobCursor cur{n};
+  auto leave = [](int) {};
+  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
+    const uint32_t gch = chunk_of(q, xcd);
+    if (!cur.advance(tab, gch, 256u, leave)) break;
+    final_chunk<T>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl, lds);
   }
 }
 
@@ -836,6 +927,38 @@ __global__ void k_dpack(DevGrid g, const double* __restrict__ d, P* __restrict__
 
 // ------------------------------------------------------------ launchers
 
+// Blocks of a persistent launch: `blocks` (a multiple of 8) is an upper
+// bound, and the launch takes no more blocks than fit on the device at once
+// (this kernel's occupancy at 256 threads times the CU count), rounded down
+// to a multiple of 8.  The chunks of a list are striped over the blocks up
+// front, so a block that had to wait for a second round would finish its
+// share late and hold up the whole launch.  Computed once per kernel (one
+// device type per process).
+static unsigned resident_blocks(const void* kern) {
+  static std::mutex m;
+  static std::unordered_map<const void*, unsigned> cache;
+  std::lock_guard<std::mutex> lock(m);
+  auto it = cache.find(kern);
+  if (it != cache.end()) return it->second;
+  int dev = 0, ncu = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess)
+    return 1u << 30;  // unknown: no clamp
+  unsigned r = (unsigned)(ncu * (nb > 0 ? nb : 1)) / 8u * 8u;
+  if (r < 8) r = 8;
+  cache[kern] = r;
+  return r;
+}
+
+template <typename... P, typename... A>
+static hipError_t persistent_launch(void (*kern)(P...), unsigned blocks, hipStream_t s, A... args) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
+  const unsigned b = std::min(blocks, resident_blocks((const void*)kern));
+  hipLaunchKernelGGL(kern, dim3(b), dim3(256), 0, s, args...);
+  return hipGetLastError();
+}
+
 static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
   uint64_t b = (n + block - 1) / block;
   if (b < 1) b = 1;
@@ -882,79 +1005,39 @@ template <typename T>
 hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_t* L,
                             const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
                             hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_band_mask<T>), dim3(blocks), dim3(256), 0, s, g, gamma, A, L, cnt, mask,
-                     count);
-  return hipGetLastError();
+  return persistent_launch(k_band_mask<T>, blocks, s, g, gamma, A, L, cnt, mask, count);
 }
 
 template <typename T>
 hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
                           hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  dim3 gr(blocks), bl(256);
-  if (dim == 3) {
-    if (lanes == 1) {
-      if (interp == 0)
-        hipLaunchKernelGGL((k_sl_step<3, 0, T, 1>), gr, bl, 0, s, a);
-      else
-        hipLaunchKernelGGL((k_sl_step<3, 1, T, 1>), gr, bl, 0, s, a);
-    } else {
-      if (interp == 0)
-        hipLaunchKernelGGL((k_sl_step<3, 0, T, 4>), gr, bl, 0, s, a);
-      else
-        hipLaunchKernelGGL((k_sl_step<3, 1, T, 4>), gr, bl, 0, s, a);
-    }
-  } else {
-    if (lanes == 1) {
-      if (interp == 0)
-        hipLaunchKernelGGL((k_sl_step<2, 0, T, 1>), gr, bl, 0, s, a);
-      else
-        hipLaunchKernelGGL((k_sl_step<2, 1, T, 1>), gr, bl, 0, s, a);
-    } else {
-      if (interp == 0)
-        hipLaunchKernelGGL((k_sl_step<2, 0, T, 2>), gr, bl, 0, s, a);
-      else
-        hipLaunchKernelGGL((k_sl_step<2, 1, T, 2>), gr, bl, 0, s, a);
-    }
-  }
-  return hipGetLastError();
+  void (*k)(SLArgs<T>);
+  if (dim == 3)
+    k = lanes == 1 ? (interp == 0 ? k_sl_step<3, 0, T, 1> : k_sl_step<3, 1, T, 1>)
+                   : (interp == 0 ? k_sl_step<3, 0, T, 4> : k_sl_step<3, 1, T, 4>);
+  else
+    k = lanes == 1 ? (interp == 0 ? k_sl_step<2, 0, T, 1> : k_sl_step<2, 1, T, 1>)
+                   : (interp == 0 ? k_sl_step<2, 0, T, 2> : k_sl_step<2, 1, T, 2>);
+  return persistent_launch(k, blocks, s, a);
 }
 
 hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  if (dim == 3)
-    hipLaunchKernelGGL(k_dilate<3>, dim3(blocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_dilate<2>, dim3(blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return persistent_launch(dim == 3 ? k_dilate<3> : k_dilate<2>, blocks, s, a);
 }
 
 template <typename T>
 hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  if (dim == 3)
-    hipLaunchKernelGGL((k_reinit_fix<3, T>), dim3(blocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_reinit_fix<2, T>), dim3(blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return persistent_launch(dim == 3 ? k_reinit_fix<3, T> : k_reinit_fix<2, T>, blocks, s, a);
 }
 
 template <typename T>
 hipError_t launch_reinit_iter(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  if (dim == 3)
-    hipLaunchKernelGGL((k_reinit_iter<3, T>), dim3(blocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_reinit_iter<2, T>), dim3(blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return persistent_launch(dim == 3 ? k_reinit_iter<3, T> : k_reinit_iter<2, T>, blocks, s, a);
 }
 
 template <typename T>
 hipError_t launch_reinit_final(const FinArgs<T>& a, unsigned blocks, hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_reinit_final<T>), dim3(blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return persistent_launch(k_reinit_final<T>, blocks, s, a);
 }
 
 hipError_t launch_bin_points(int dim, const BinGeom& bg, const double* pts, int64_t n,
@@ -1013,58 +1096,35 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
 template <typename T>
 hipError_t launch_sl_step_batch(int dim, int lanes, const SLArgs<T>* tab, const int32_t* interp,
                                 int n, unsigned blocks, hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  dim3 gr(blocks), bl(256);
-  if (dim == 3) {
-    if (lanes == 1)
-      hipLaunchKernelGGL((k_sl_step_batch<3, T, 1>), gr, bl, 0, s, tab, interp, n);
-    else
-      hipLaunchKernelGGL((k_sl_step_batch<3, T, 4>), gr, bl, 0, s, tab, interp, n);
-  } else {
-    if (lanes == 1)
-      hipLaunchKernelGGL((k_sl_step_batch<2, T, 1>), gr, bl, 0, s, tab, interp, n);
-    else
-      hipLaunchKernelGGL((k_sl_step_batch<2, T, 2>), gr, bl, 0, s, tab, interp, n);
-  }
-  return hipGetLastError();
+  void (*k)(const SLArgs<T>*, const int32_t*, int);
+  if (dim == 3)
+    k = lanes == 1 ? k_sl_step_batch<3, T, 1> : k_sl_step_batch<3, T, 4>;
+  else
+    k = lanes == 1 ? k_sl_step_batch<2, T, 1> : k_sl_step_batch<2, T, 2>;
+  return persistent_launch(k, blocks, s, tab, interp, n);
 }
 
 hipError_t launch_dilate_batch(int dim, const DilArgs* tab, int n, unsigned blocks, hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  if (dim == 3)
-    hipLaunchKernelGGL(k_dilate_batch<3>, dim3(blocks), dim3(256), 0, s, tab, n);
-  else
-    hipLaunchKernelGGL(k_dilate_batch<2>, dim3(blocks), dim3(256), 0, s, tab, n);
-  return hipGetLastError();
+  return persistent_launch(dim == 3 ? k_dilate_batch<3> : k_dilate_batch<2>, blocks, s, tab, n);
 }
 
 template <typename T>
 hipError_t launch_reinit_fix_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
                                    hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  if (dim == 3)
-    hipLaunchKernelGGL((k_reinit_fix_batch<3, T>), dim3(blocks), dim3(256), 0, s, tab, n);
-  else
-    hipLaunchKernelGGL((k_reinit_fix_batch<2, T>), dim3(blocks), dim3(256), 0, s, tab, n);
-  return hipGetLastError();
+  return persistent_launch(dim == 3 ? k_reinit_fix_batch<3, T> : k_reinit_fix_batch<2, T>, blocks, s,
+                           tab, n);
 }
 
 template <typename T>
 hipError_t launch_reinit_iter_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
                                     hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  if (dim == 3)
-    hipLaunchKernelGGL((k_reinit_iter_batch<3, T>), dim3(blocks), dim3(256), 0, s, tab, n);
-  else
-    hipLaunchKernelGGL((k_reinit_iter_batch<2, T>), dim3(blocks), dim3(256), 0, s, tab, n);
-  return hipGetLastError();
+  return persistent_launch(dim == 3 ? k_reinit_iter_batch<3, T> : k_reinit_iter_batch<2, T>, blocks,
+                           s, tab, n);
 }
 
 template <typename T>
 hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned blocks, hipStream_t s) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_reinit_final_batch<T>), dim3(blocks), dim3(256), 0, s, tab, n);
-  return hipGetLastError();
+  return persistent_launch(k_reinit_final_batch<T>, blocks, s, tab, n);
 }
 
 #define LSR_INSTANTIATE(T)                                                                        \
