@@ -12,7 +12,10 @@ value = node updates (sum of band sizes over the steps) per second of wall
 time over the timed jobs.  The roofline object describes the dominant kernel
 (the 3D WENO step), timed with HIP events on the job's stream.  The
 cpu_baseline object times the FP64 oracle on a bounded sample of the same
-workload on the host's cores.
+workload on the host's cores.  Two more objects report the multi-job forms:
+"batched" (many independent jobs in one batch against the same jobs run one
+after the other) and "served" (a Poisson request stream with continuous
+batching against the same stream served by plain solves).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -91,6 +94,95 @@ def cpu_baseline(w, n_steps):
                        f"distance field not timed")}
 
 
+def run_batched(n_jobs, steps, precision):
+    """The batched workload: independent jobs with uneven grids (64^3-192^3),
+    clouds of 5k-150k points, Q1 and WENO alternating, `steps` steps each;
+    one after the other as plain solves, then all in one batch (autotuned
+    launch shape).  Wall time from the first cloud load to the last extract;
+    the clouds are resident in HBM before either timed region."""
+    import numpy as np
+    import torch
+    from paper_2410_22205_amd import lsr, synth
+    jobs = synth.batch_jobs(n_jobs=n_jobs, steps=steps)
+    pts = [torch.as_tensor(w["points"], dtype=torch.float64, device="cuda").contiguous()
+           for w in jobs]
+    kinds = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}
+
+    def make(w):
+        return lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"],
+                                       reinit_every=w["reinit_every"], precision=precision),
+                       max_points=len(w["points"]))
+
+    def load(job, w, p):
+        lsr.lsr_load_cloud(job.handle, p.data_ptr(), p.shape[0])
+        lsr.lsr_init_phi(job.handle, None, kinds[w["phi0"][0]], list(w["phi0"][1]), 0)
+
+    def extract(job):
+        phi = torch.empty(job.nodes, dtype=job.dtype, device="cuda")
+        band = torch.empty(job.nodes, dtype=torch.uint8, device="cuda")
+        lsr.lsr_extract(job.handle, phi.data_ptr(), band.data_ptr(), want_count=False)
+        return phi, band
+
+    # one after the other
+    upd = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w, p in zip(jobs, pts):
+        job = make(w)
+        load(job, w, p)
+        lsr.lsr_step(job.handle, w["steps"], w["dt"], lsr.interp_code(w["interp"]))
+        extract(job)
+        upd += lsr.lsr_counters(job.handle)["node_updates"]
+        job.close()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    # all in one batch
+    handles = [make(w) for w in jobs]
+    batch = lsr.Batch(max_jobs=n_jobs, group_steps=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for job, w, p in zip(handles, jobs, pts):
+        load(job, w, p)
+        batch.add(job, w["dt"], w["interp"])
+    lanes, bpc, _ = batch.tune()
+    batch.step(steps)
+    for job in list(handles):
+        batch.remove(job)
+        extract(job)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    upd_b = sum(lsr.lsr_counters(j.handle)["node_updates"] for j in handles)
+    assert upd_b == upd, "batched and sequential runs did different work"
+    batch.close()
+    for j in handles:
+        j.close()
+    return {"workload": f"{n_jobs} jobs, grids 64^3-192^3, 5k-150k points, Q1/WENO alternating, "
+                        f"{steps} steps each, dt = h/2, reinit every 10",
+            "jobs_per_s": n_jobs / t_bat, "sequential_jobs_per_s": n_jobs / t_seq,
+            "speedup": t_seq / t_bat, "node_updates_per_s": upd / t_bat,
+            "sequential_node_updates_per_s": upd / t_seq, "tuned": {"lanes": lanes,
+                                                                    "blocks_per_cu": bpc}}
+
+
+def run_served(n_jobs, precision):
+    """The served workload: a Poisson stream at 20 requests/s of jobs with
+    grids 64^3-320^3, 5k-1M points, 200-400 WENO steps, served with
+    continuous batching; then the same stream as plain solves one at a time.
+    Latency = completion - arrival."""
+    from paper_2410_22205_amd import serve, synth
+    reqs = serve.materialise(synth.served_jobs(n_jobs=n_jobs))
+    srv = serve.Server(precision=precision)
+    warm = serve.materialise(synth.served_jobs(n_jobs=2, seed=77))
+    srv.run([dict(r, arrival=0.0) for r in warm])
+    out = srv.run(reqs)
+    seq = serve.run_sequential(reqs, precision=precision)
+    return {"workload": f"{n_jobs} requests, Poisson 20/s, grids 64^3-320^3, 5k-1M points, "
+                        "WENO, 200-400 steps",
+            "jobs_per_s": out["jobs_per_s"], "latency_ms": out["latency_ms"],
+            "max_batch": out["max_batch"], "rejected": len(out["rejected"]),
+            "sequential": {"jobs_per_s": seq["jobs_per_s"], "latency_ms": seq["latency_ms"]}}
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE /
     WRITE_SIZE readings (run under rocprofv3 --pmc)."""
@@ -119,6 +211,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batch-jobs", type=int, default=64, help="batched section (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--served-jobs", type=int, default=60, help="served section (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -141,7 +236,7 @@ def main():
                precision=args.precision)
     job = lsr.Job(g, prm, max_points=len(w["points"]))
     if args.lanes or args.blocks_per_cu != 8:
-        lsr.lsr_set_launch(job.handle, args.lanes or (4 if dim == 3 else 2), args.blocks_per_cu)
+        lsr.lsr_set_launch(job.handle, args.lanes or 1, args.blocks_per_cu)
     stream = job.stream
     pts = torch.as_tensor(w["points"], dtype=torch.float64, device="cuda").contiguous()
     phi_out = torch.empty(job.nodes, dtype=job.dtype, device="cuda")
@@ -192,7 +287,7 @@ def main():
                 "flops_per_node_update": flops,
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
                 "node_updates_per_launch": round(upd_per_launch, 1),
-                "lanes": args.lanes or (4 if dim == 3 else 2), "blocks_per_cu": args.blocks_per_cu}
+                "lanes": args.lanes or 1, "blocks_per_cu": args.blocks_per_cu}
     hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in lat)
     out = {
@@ -223,6 +318,10 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
     }
     job.close()
+    if args.batch_jobs:
+        out["batched"] = run_batched(args.batch_jobs, args.batch_steps, args.precision)
+    if args.served_jobs:
+        out["served"] = run_served(args.served_jobs, args.precision)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

@@ -213,7 +213,8 @@ lsr_status lsr_batch_destroy(lsr_batch* batch);
 /* Launch shape of the list kernels (results are bitwise the same for every
  * shape): lanes = 1 (one lane per band node) or the number of foot points
  * per node (2 in 2D, 4 in 3D: one lane per foot point); blocks_per_cu in
- * 1..64 sets the persistent grid.  Defaults: foot points per node, 8. */
+ * 1..64 bounds the persistent grid, which never exceeds the blocks of the
+ * kernel that fit on the device at once.  Defaults: 1 lane, 8. */
 lsr_status lsr_set_launch(lsr_job* job, int32_t lanes, int32_t blocks_per_cu);
 
 /* Measurement hook.  While enabled, every semi-Lagrangian step kernel the job

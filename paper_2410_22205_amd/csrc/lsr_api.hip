@@ -327,7 +327,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->bin_fill = (int32_t*)(w + L.bin_fill);
   j->occ = (uint32_t*)(w + L.occ);
   j->ncu = ncu > 0 ? ncu : 256;
-  j->lanes = g.dim == 3 ? 4 : 2;
+  j->lanes = 1;
   j->blocks_per_cu = 8;
   set_list_blocks(j);
   j->cur = 0;

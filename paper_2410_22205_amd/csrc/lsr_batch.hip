@@ -25,6 +25,7 @@ struct Launch {
   size_t off;
   int n;
   lsr_job* job;  // kind 5 only
+  int interp;    // kind 0 only
 };
 
 }  // namespace
@@ -57,14 +58,30 @@ namespace {
 // interpolator codes, and at most one reinitialisation per job (dilation,
 // fix, max_iters iteration tables, final), each table 256-byte aligned; the
 // double-precision argument structs bound the single-precision ones.
+// The members are stepped in cache groups (see cache_groups), each with its
+// own tables, so the alignment padding is counted once per table per job.
 size_t group_table_bytes(int n_jobs, int group_steps, int max_iters) {
   const size_t n = (size_t)n_jobs, a = 255;
-  const size_t per_step = n * sizeof(SLArgs<double>) + a + 4 * n + a + n * sizeof(DilArgs) + a +
-                          n * sizeof(RArgs<double>) + a +
-                          (size_t)max_iters * (n * sizeof(RArgs<double>) + a) +
-                          n * sizeof(FinArgs<double>) + a;
+  const size_t per_step = n * (sizeof(SLArgs<double>) + sizeof(DilArgs) +
+                               (size_t)(max_iters + 1) * sizeof(RArgs<double>) +
+                               sizeof(FinArgs<double>)) +
+                          n * (size_t)(2 + 3 + max_iters) * a;
   return per_step * (size_t)group_steps + a;
 }
+
+// Jobs whose state is stepped together in one launch should fit the device's
+// last-level cache (256 MB Infinity Cache on MI355X) with room to spare: a
+// step then finds the group's phi and (grad d, d) where the previous step left
+// them.  Larger launches lose that reuse and run up to 1.5x slower per node.
+constexpr size_t kCacheGroupBytes = (size_t)192 << 20;
+
+size_t step_footprint(const lsr_job* j) {
+  return (size_t)j->dg.N * 6u * (j->fp64 ? 8u : 4u);  // phi A, B and (grad d, d)
+}
+
+// Consecutive members packed greedily into groups of at most
+// kCacheGroupBytes (a larger job forms a group of its own).
+std::vector<std::pair<int, int>> cache_groups(const lsr_batch* b);
 
 unsigned batch_blocks(int ncu, int bpc) {
   unsigned b = (unsigned)(ncu * bpc);
@@ -85,21 +102,27 @@ struct Builder {
   }
 };
 
+// Tables and launches of `steps` steps of the members q0 .. q1-1.
 template <typename T>
-lsr_status build_group(lsr_batch* b, int steps, Builder<T>& B) {
-  const int nj = (int)b->jobs.size();
+lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
   for (int s = 0; s < steps; ++s) {
-    size_t o = align256(B.off);
-    SLArgs<T>* tab = B.template take<SLArgs<T>>(nj);
-    int32_t* itp = B.template take<int32_t>(nj);
-    for (int q = 0; q < nj; ++q) {
-      lsr_job* j = b->jobs[q];
-      tab[q] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
-      itp[q] = b->interp[q];
+    // one step table and launch per interpolator
+    for (int itp = 0; itp < 2; ++itp) {
+      int m = 0;
+      for (int q = q0; q < q1; ++q) m += b->interp[q] == itp;
+      if (!m) continue;
+      size_t o = align256(B.off);
+      SLArgs<T>* tab = B.template take<SLArgs<T>>(m);
+      m = 0;
+      for (int q = q0; q < q1; ++q) {
+        if (b->interp[q] != itp) continue;
+        lsr_job* j = b->jobs[q];
+        tab[m++] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
+      }
+      B.launches.push_back({0, o, m, nullptr, itp});
     }
-    B.launches.push_back({0, o, nj, nullptr});
     std::vector<int> due;
-    for (int q = 0; q < nj; ++q)
+    for (int q = q0; q < q1; ++q)
       if (reinit_due(b->jobs[q])) due.push_back(q);
     if (due.empty()) continue;
     const int nd = (int)due.size();
@@ -108,7 +131,7 @@ lsr_status build_group(lsr_batch* b, int steps, Builder<T>& B) {
     for (int q : due) {
       lsr_job* j = b->jobs[q];
       if (stamp_needs_clear(j)) {
-        B.launches.push_back({5, 0, 0, j});
+        B.launches.push_back({5, 0, 0, j, 0});
         j->epoch = 0;
       }
       plans.push_back(plan_reinit<T>(j));
@@ -117,23 +140,23 @@ lsr_status build_group(lsr_batch* b, int steps, Builder<T>& B) {
     size_t od = align256(B.off);
     DilArgs* dil = B.template take<DilArgs>(nd);
     for (int q = 0; q < nd; ++q) dil[q] = plans[q].dil;
-    B.launches.push_back({1, od, nd, nullptr});
+    B.launches.push_back({1, od, nd, nullptr, 0});
     size_t of = align256(B.off);
     RArgs<T>* fix = B.template take<RArgs<T>>(nd);
     for (int q = 0; q < nd; ++q) fix[q] = plans[q].fix;
-    B.launches.push_back({2, of, nd, nullptr});
+    B.launches.push_back({2, of, nd, nullptr, 0});
     for (int it = 0; it < max_it; ++it) {
       size_t oi = align256(B.off);
       RArgs<T>* itab = B.template take<RArgs<T>>(nd);
       int m = 0;
       for (int q = 0; q < nd; ++q)
         if (it < plans[q].iters) itab[m++] = plans[q].iter[it % 2];
-      B.launches.push_back({3, oi, m, nullptr});
+      B.launches.push_back({3, oi, m, nullptr, 0});
     }
     size_t on = align256(B.off);
     FinArgs<T>* fin = B.template take<FinArgs<T>>(nd);
     for (int q = 0; q < nd; ++q) fin[q] = plans[q].fin;
-    B.launches.push_back({4, on, nd, nullptr});
+    B.launches.push_back({4, on, nd, nullptr, 0});
   }
   if (B.off > b->table_bytes) return fail(LSR_E_NOMEM, "batch table workspace too small");
   return LSR_OK;
@@ -145,12 +168,10 @@ lsr_status issue(lsr_batch* b, const Builder<T>& B) {
   char* dev = b->ws + b->table_off;
   for (const Launch& L : B.launches) {
     switch (L.kind) {
-      case 0: {
-        const size_t io = align256(L.off + sizeof(SLArgs<T>) * (size_t)L.n);
-        LSR_HIP(launch_sl_step_batch<T>(b->dim, b->lanes, (const SLArgs<T>*)(dev + L.off),
-                                        (const int32_t*)(dev + io), L.n, b->blocks, s));
+      case 0:
+        LSR_HIP(launch_sl_step_batch<T>(b->dim, L.interp, b->lanes, (const SLArgs<T>*)(dev + L.off),
+                                        L.n, b->blocks, s));
         break;
-      }
       case 1:
         LSR_HIP(launch_dilate_batch(b->dim, (const DilArgs*)(dev + L.off), L.n, b->blocks, s));
         break;
@@ -173,6 +194,24 @@ lsr_status issue(lsr_batch* b, const Builder<T>& B) {
   return LSR_OK;
 }
 
+std::vector<std::pair<int, int>> cache_groups(const lsr_batch* b) {
+  std::vector<std::pair<int, int>> out;
+  const int nj = (int)b->jobs.size();
+  int q0 = 0;
+  size_t bytes = 0;
+  for (int q = 0; q < nj; ++q) {
+    const size_t f = step_footprint(b->jobs[q]);
+    if (q > q0 && bytes + f > kCacheGroupBytes) {
+      out.push_back({q0, q});
+      q0 = q;
+      bytes = 0;
+    }
+    bytes += f;
+  }
+  if (nj > q0) out.push_back({q0, nj});
+  return out;
+}
+
 // Tables must be in place before the launches: wait until the previous
 // group's copy has left the pinned buffer, fill it, copy, launch.
 template <typename T>
@@ -184,8 +223,10 @@ lsr_status run_group(lsr_batch* b, int steps) {
   }
   Builder<T> B;
   B.b = b;
-  lsr_status st = build_group<T>(b, steps, B);
-  if (st != LSR_OK) return st;
+  for (const auto& g : cache_groups(b)) {
+    lsr_status st = build_group<T>(b, g.first, g.second, steps, B);
+    if (st != LSR_OK) return st;
+  }
   LSR_HIP(hipMemcpyAsync(b->ws + b->table_off, b->host, B.off, hipMemcpyHostToDevice, b->stream));
   LSR_HIP(hipEventRecord(b->copy_done, b->stream));
   b->copy_pending = true;
@@ -219,22 +260,38 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
     LSR_HIP(hipEventSynchronize(b->copy_done));
     b->copy_pending = false;
   }
-  SLArgs<T>* tab = (SLArgs<T>*)b->host;
-  const size_t io = align256(sizeof(SLArgs<T>) * (size_t)nj);
-  int32_t* itp = (int32_t*)(b->host + io);
-  for (int q = 0; q < nj; ++q) {
-    itp[q] = b->interp[q];
-    lsr_job* j = b->jobs[q];
-    SavedState sv = save(j);
-    tab[q] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
-    restore(j, sv);
-    tab[q].cnt_out = b->scratch_cnt + 2 * q;
-    tab[q].cnt_reset = b->scratch_cnt + 2 * q + 1;
-    tab[q].stats = b->scratch_stats;
+  // the next step's tables, one per cache group and interpolator (as the
+  // step launches them), with list counters and statistics redirected to
+  // scratch
+  struct Tab {
+    size_t off;
+    int n, interp;
+  };
+  std::vector<Tab> tabs;
+  size_t top = 0;
+  for (const auto& g : cache_groups(b)) {
+    for (int itp = 0; itp < 2; ++itp) {
+      top = align256(top);
+      SLArgs<T>* tab = (SLArgs<T>*)(b->host + top);
+      int m = 0;
+      for (int q = g.first; q < g.second; ++q) {
+        if (b->interp[q] != itp) continue;
+        lsr_job* j = b->jobs[q];
+        SavedState sv = save(j);
+        SLArgs<T> a = plan_step<T>(j, step_const<T>(j, b->dt[q]));
+        restore(j, sv);
+        a.cnt_out = b->scratch_cnt + 2 * q;
+        a.cnt_reset = b->scratch_cnt + 2 * q + 1;
+        a.stats = b->scratch_stats;
+        tab[m++] = a;
+      }
+      if (m) tabs.push_back({top, m, itp});
+      top += sizeof(SLArgs<T>) * (size_t)m;
+    }
   }
   hipStream_t s = b->stream;
   char* dev = b->ws + b->table_off;
-  LSR_HIP(hipMemcpyAsync(dev, b->host, io + 4 * (size_t)nj, hipMemcpyHostToDevice, s));
+  LSR_HIP(hipMemcpyAsync(dev, b->host, top, hipMemcpyHostToDevice, s));
   hipEvent_t e0, e1;
   LSR_HIP(hipEventCreate(&e0));
   LSR_HIP(hipEventCreate(&e1));
@@ -249,8 +306,9 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
       for (int rep = 0; rep < 4; ++rep) {
         LSR_HIP(launch_fill_u32((uint32_t*)b->scratch_cnt, 0u, 2 * (uint64_t)nj, s));
         LSR_HIP(hipEventRecord(e0, s));
-        LSR_HIP(launch_sl_step_batch<T>(b->dim, lanes_c[li], (const SLArgs<T>*)dev,
-                                        (const int32_t*)(dev + io), nj, blocks, s));
+        for (const Tab& t : tabs)
+          LSR_HIP(launch_sl_step_batch<T>(b->dim, t.interp, lanes_c[li],
+                                          (const SLArgs<T>*)(dev + t.off), t.n, blocks, s));
         LSR_HIP(hipEventRecord(e1, s));
         LSR_HIP(hipEventSynchronize(e1));
         float ms = 0.0f;

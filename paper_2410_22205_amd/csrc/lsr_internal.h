@@ -121,8 +121,8 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
 
 // Batched forms: one launch over a packed table of per-job arguments.
 template <typename T>
-hipError_t launch_sl_step_batch(int dim, int lanes, const SLArgs<T>* tab, const int32_t* interp,
-                                int n, unsigned blocks, hipStream_t s);
+hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>* tab, int n,
+                                unsigned blocks, hipStream_t s);
 hipError_t launch_dilate_batch(int dim, const DilArgs* tab, int n, unsigned blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_fix_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,

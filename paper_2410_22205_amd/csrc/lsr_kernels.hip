@@ -332,9 +332,10 @@ struct JobCursor {
   static __device__ __forceinline__ const int32_t* count(const FinArgs<double>& x) { return x.cnt_in; }
 };
 
-template <int DIM, typename T, int LANES>
-__global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab,
-                                                       const int32_t* __restrict__ interp, int n) {
+// Batched step for the jobs of one interpolator (one launch per interpolator,
+// so that each kernel keeps its own register count and resident grid).
+template <int DIM, int INTERP, typename T, int LANES>
+__global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab, int n) {
   constexpr uint32_t CH = 256 / LANES;
   __shared__ int lds_app[8];
   __shared__ uint32_t lds_st[12];
@@ -351,12 +352,8 @@ __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restri
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
     const uint32_t gch = chunk_of(q, xcd);
     if (!cur.advance(tab, gch, CH, leave)) break;
-    const SLArgs<T> a = uniform_load(tab, cur.jb);
-    const uint32_t base = (gch - cur.beg) * CH;
-    if (((const __attribute__((address_space(4))) int32_t*)interp)[cur.jb] == 0)
-      sl_chunk<DIM, 0, T, LANES>(a, base, cur.nl, lds_app, nupd, nfb, nfr);
-    else
-      sl_chunk<DIM, 1, T, LANES>(a, base, cur.nl, lds_app, nupd, nfb, nfr);
+    sl_chunk<DIM, INTERP, T, LANES>(uniform_load(tab, cur.jb), (gch - cur.beg) * CH, cur.nl,
+                                    lds_app, nupd, nfb, nfr);
   }
 }
 
@@ -1094,14 +1091,16 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
 }
 
 template <typename T>
-hipError_t launch_sl_step_batch(int dim, int lanes, const SLArgs<T>* tab, const int32_t* interp,
-                                int n, unsigned blocks, hipStream_t s) {
-  void (*k)(const SLArgs<T>*, const int32_t*, int);
+hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>* tab, int n,
+                                unsigned blocks, hipStream_t s) {
+  void (*k)(const SLArgs<T>*, int);
   if (dim == 3)
-    k = lanes == 1 ? k_sl_step_batch<3, T, 1> : k_sl_step_batch<3, T, 4>;
+    k = lanes == 1 ? (interp == 0 ? k_sl_step_batch<3, 0, T, 1> : k_sl_step_batch<3, 1, T, 1>)
+                   : (interp == 0 ? k_sl_step_batch<3, 0, T, 4> : k_sl_step_batch<3, 1, T, 4>);
   else
-    k = lanes == 1 ? k_sl_step_batch<2, T, 1> : k_sl_step_batch<2, T, 2>;
-  return persistent_launch(k, blocks, s, tab, interp, n);
+    k = lanes == 1 ? (interp == 0 ? k_sl_step_batch<2, 0, T, 1> : k_sl_step_batch<2, 1, T, 1>)
+                   : (interp == 0 ? k_sl_step_batch<2, 0, T, 2> : k_sl_step_batch<2, 1, T, 2>);
+  return persistent_launch(k, blocks, s, tab, n);
 }
 
 hipError_t launch_dilate_batch(int dim, const DilArgs* tab, int n, unsigned blocks, hipStream_t s) {
@@ -1141,7 +1140,7 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \
   template hipError_t launch_dpack<T>(int, const DevGrid&, const double*, typename Vec<T>::pack*, \
                                       hipStream_t);                                               \
-  template hipError_t launch_sl_step_batch<T>(int, int, const SLArgs<T>*, const int32_t*, int,     \
+  template hipError_t launch_sl_step_batch<T>(int, int, int, const SLArgs<T>*, int,               \
                                               unsigned, hipStream_t);                             \
   template hipError_t launch_reinit_fix_batch<T>(int, const RArgs<T>*, int, unsigned, hipStream_t);\
   template hipError_t launch_reinit_iter_batch<T>(int, const RArgs<T>*, int, unsigned,             \

@@ -482,3 +482,29 @@ def test_errors_leave_the_job_usable():
     job.step(2, w["dt"], "weno")
     assert job.extract()[3] == 2
     job.close()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("name,interp", [("torus3d", "weno"), ("torus3d", "q1"),
+                                         ("circle2d", "weno")])
+def test_launch_shape_does_not_change_results(name, interp, precision):
+    """One lane per node and one lane per foot point add the foot values in
+    the same order: bitwise equal results, whatever the persistent grid."""
+    lsr = _lsr()
+    w = synth.workload(name, n=40 if name == "torus3d" else 96, steps=12)
+    w["interp"] = interp
+    fp = 4 if w["grid"]["dim"] == 3 else 2
+    out = []
+    for lanes, bpc in [(1, 8), (fp, 8), (1, 2)]:
+        oprm = oracle_params(w)
+        prm = {k: oprm[k] for k in ("gamma", "beta", "reinit_every", "reinit_iters")}
+        prm["precision"] = precision
+        job = lsr.Job(w["grid"], prm, max_points=len(w["points"]))
+        job.set_launch(lanes, bpc)
+        job.load_cloud(w["points"])
+        job.init_phi(w["phi0"][0], w["phi0"][1])
+        job.step(w["steps"], w["dt"], interp)
+        out.append(job.extract()[0])
+        job.close()
+    np.testing.assert_array_equal(out[0], out[1])
+    np.testing.assert_array_equal(out[0], out[2])
