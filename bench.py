@@ -40,6 +40,7 @@ FLOPS_PER_UPDATE = {(3, "weno"): 84 * 30 + 4 * 42 + 60, (3, "q1"): 4 * (7 * 3 + 
 BYTES_PER_UPDATE = {"fp32": 4 + 4 + 16 + 4 + 4, "fp64": 4 + 8 + 32 + 8 + 4}
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
+DEFAULT_LANES = {2: 1, 3: 1}  # the library's default launch shape (lsr_create)
 KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kernels.hip"]
 
 
@@ -97,9 +98,10 @@ def cpu_baseline(w, n_steps):
 def run_batched(n_jobs, steps, precision):
     """The batched workload: independent jobs with uneven grids (64^3-192^3),
     clouds of 5k-150k points, Q1 and WENO alternating, `steps` steps each;
-    one after the other as plain solves, then all in one batch (autotuned
-    launch shape).  Wall time from the first cloud load to the last extract;
-    the clouds are resident in HBM before either timed region."""
+    one after the other as plain solves, then all in one batch (loads on
+    side streams, autotuned launch shape).  Wall time from the first cloud
+    load to the last extract; the clouds are resident in HBM before either
+    timed region."""
     import numpy as np
     import torch
     from paper_2410_22205_amd import lsr, synth
@@ -136,13 +138,22 @@ def run_batched(n_jobs, steps, precision):
         job.close()
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    # all in one batch
-    handles = [make(w) for w in jobs]
+    # all in one batch; the jobs load (distance field, phi0) on four side
+    # streams so that the loads of small jobs overlap
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    handles = []
+    for k, w in enumerate(jobs):
+        with torch.cuda.stream(streams[k % 4]):
+            handles.append(lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"],
+                                                   reinit_every=w["reinit_every"],
+                                                   precision=precision),
+                                   max_points=len(w["points"]), stream=streams[k % 4]))
     batch = lsr.Batch(max_jobs=n_jobs, group_steps=10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for job, w, p in zip(handles, jobs, pts):
         load(job, w, p)
+    for job, w in zip(handles, jobs):
         batch.add(job, w["dt"], w["interp"])
     lanes, bpc, _ = batch.tune()
     batch.step(steps)
@@ -206,7 +217,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus3d")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per band node (0: library default)")
+    ap.add_argument("--lanes", type=int, default=-1,
+                    help="step kernel: 0 brick-staged (3D), 1 one lane per node, 4 (2 in 2D) one "
+                         "lane per foot point; -1 the library default")
     ap.add_argument("--blocks-per-cu", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -235,8 +248,10 @@ def main():
     prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
                precision=args.precision)
     job = lsr.Job(g, prm, max_points=len(w["points"]))
-    if args.lanes or args.blocks_per_cu != 8:
-        lsr.lsr_set_launch(job.handle, args.lanes or 1, args.blocks_per_cu)
+    if args.lanes >= 0 or args.blocks_per_cu != 8:
+        lsr.lsr_set_launch(job.handle, args.lanes if args.lanes >= 0 else DEFAULT_LANES[dim],
+                           args.blocks_per_cu)
+    lanes = args.lanes if args.lanes >= 0 else DEFAULT_LANES[dim]
     stream = job.stream
     pts = torch.as_tensor(w["points"], dtype=torch.float64, device="cuda").contiguous()
     phi_out = torch.empty(job.nodes, dtype=job.dtype, device="cuda")
@@ -283,11 +298,11 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / peak, 4),
                 "traffic": traffic,
-                "kernel": f"k_sl_step<{dim},{w['interp']},{'double' if args.precision == 'fp64' else 'float'}>",
+                "kernel": f"k_sl_step{'_staged' if lanes == 0 else ''}<{dim},{w['interp']},{'double' if args.precision == 'fp64' else 'float'}>",
                 "flops_per_node_update": flops,
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
                 "node_updates_per_launch": round(upd_per_launch, 1),
-                "lanes": args.lanes or 1, "blocks_per_cu": args.blocks_per_cu}
+                "lanes": lanes, "staged": lanes == 0, "blocks_per_cu": args.blocks_per_cu}
     hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in lat)
     out = {

@@ -64,6 +64,13 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.listM = take(4 * N);
   L.mflags = take(N);
   L.stamp = take(4 * N);
+  // bricks of the staged 3D step: 4 x 8 x 8 nodes
+  L.nbricks = g.dim == 3 ? (int64_t)((g.n[0] + BRICK_I - 1) / BRICK_I) *
+                               ((g.n[1] + BRICK_J - 1) / BRICK_J) * ((g.n[2] + BRICK_K - 1) / BRICK_K)
+                         : 1;
+  L.blist0 = take(4 * (size_t)L.nbricks);
+  L.blist1 = take(4 * (size_t)L.nbricks);
+  L.bstamp = take(4 * (size_t)L.nbricks);
   L.cnt = take(4 * 16);
   L.stats = take(8 * 16);
   L.pts_raw = take(8 * (size_t)g.dim * P);
@@ -134,18 +141,45 @@ static lsr_status run_reinit_t(lsr_job* j) {
     j->epoch = 0;
   }
   ReinitPlan<T> r = plan_reinit<T>(j);
+  j->bricks_valid = false;
   return launch_reinit_plan<T>(j, r);
+}
+
+// Brick list of the current node list (before a staged step that follows a
+// step of another kind, the initial data or a reinitialisation).
+static lsr_status rebuild_bricks(lsr_job* j) {
+  hipStream_t s = j->stream;
+  if (j->bepoch == 0xFFFFFFFFu) {
+    LSR_HIP(launch_fill_u32(j->bstamp, 0u, (uint64_t)j->L.nbricks, s));
+    j->bepoch = 0;
+  }
+  j->bepoch += 1;
+  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 8), 0u, 3, s));
+  LSR_HIP(launch_nodes_to_bricks(j->dg, j->list[j->cur_list], ring_slot(j, 0), j->bstamp, j->bepoch,
+                                 j->blist[j->cur_blist], bring_slot(j, 0), j->list_blocks, s));
+  j->bricks_valid = true;
+  return LSR_OK;
 }
 
 template <typename T>
 static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp) {
   hipStream_t s = j->stream;
   const StepConst<T> c = step_const<T>(j, dt);
+  const bool staged = j->lanes == 0;
   for (int32_t q = 0; q < n_steps; ++q) {
+    if (staged && !j->bricks_valid) {
+      lsr_status st = rebuild_bricks(j);
+      if (st != LSR_OK) return st;
+    }
     SLArgs<T> a = plan_step<T>(j, c);
     const bool rec = j->prof_on && 2 * (size_t)j->prof_used + 1 < j->prof_ev.size();
     if (rec) LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used], s));
-    LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s));
+    if (staged) {
+      LSR_HIP(launch_sl_step_staged<T>(interp, a, j->list_blocks, s));
+    } else {
+      LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s));
+      j->bricks_valid = false;
+    }
     if (rec) {
       LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used + 1], s));
       j->prof_used += 1;
@@ -317,6 +351,12 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->listM = (uint32_t*)(w + L.listM);
   j->mflags = (uint8_t*)(w + L.mflags);
   j->stamp = (uint32_t*)(w + L.stamp);
+  j->blist[0] = (uint32_t*)(w + L.blist0);
+  j->blist[1] = (uint32_t*)(w + L.blist1);
+  j->bstamp = (uint32_t*)(w + L.bstamp);
+  j->cur_blist = 0;
+  j->bepoch = 0;
+  j->bricks_valid = false;
   j->cnt = (int32_t*)(w + L.cnt);
   j->stats = (unsigned long long*)(w + L.stats);
   j->pts_raw = (double*)(w + L.pts_raw);
@@ -344,6 +384,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
 
   hipStream_t s = j->stream;
   hipError_t e = launch_fill_u32(j->stamp, 0u, d.N, s);
+  if (e == hipSuccess) e = launch_fill_u32(j->bstamp, 0u, (uint64_t)L.nbricks, s);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->cnt, 0u, 16, s);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->stats, 0u, 32, s);
   if (e != hipSuccess) {
@@ -456,6 +497,7 @@ lsr_status lsr_init_phi(lsr_job* j, const void* dev_phi0, int32_t kind, const do
   j->n_reinits = 0;
   j->n_steps = 0;
   j->has_phi = true;
+  j->bricks_valid = false;
   return LSR_OK;
 }
 
@@ -529,7 +571,8 @@ lsr_status lsr_set_launch(lsr_job* j, int32_t lanes, int32_t blocks_per_cu) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
   if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   const int fp = j->grid.dim == 3 ? 4 : 2;
-  if (lanes != 1 && lanes != fp) return fail(LSR_E_INVALID, "lanes must be 1 or the foot points per node");
+  if (lanes != 1 && lanes != fp && !(lanes == 0 && j->grid.dim == 3))
+    return fail(LSR_E_INVALID, "lanes must be 1, the foot points per node, or 0 (staged, 3D)");
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LSR_E_INVALID, "blocks_per_cu must be in 1..64");
   j->lanes = lanes;
   j->blocks_per_cu = blocks_per_cu;

@@ -117,6 +117,7 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
       for (int q = q0; q < q1; ++q) {
         if (b->interp[q] != itp) continue;
         lsr_job* j = b->jobs[q];
+        j->bricks_valid = false;  // stepped here through the node list
         tab[m++] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
       }
       B.launches.push_back({0, o, m, nullptr, itp});
@@ -297,10 +298,10 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
   LSR_HIP(hipEventCreate(&e1));
   const int fp = b->dim == 3 ? 4 : 2;
   const int lanes_c[2] = {1, fp};
-  const int bpc_c[4] = {4, 8, 16, 32};
+  const int bpc_c[3] = {2, 4, 8};  // 8 and more: every block resident
   double best = 1e30;
   for (int li = 0; li < 2; ++li) {
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < 3; ++bi) {
       const unsigned blocks = batch_blocks(b->ncu, bpc_c[bi]);
       float tmin = 1e30f;
       for (int rep = 0; rep < 4; ++rep) {
@@ -418,7 +419,7 @@ lsr_status lsr_batch_add(lsr_batch* b, lsr_job* j, double dt, lsr_interp interp)
   if (!b->dim) {
     b->dim = j->grid.dim;
     b->fp64 = j->fp64;
-    if (!b->lanes) b->lanes = j->lanes;
+    if (!b->lanes) b->lanes = j->lanes ? j->lanes : 1;  // batches step through node lists
   }
   j->in_batch = true;
   j->own_stream = j->stream;

@@ -197,21 +197,20 @@ __device__ __forceinline__ typename Vec<T>::v4 row4(gptr<T> A, uint32_t row, int
 }
 
 // Tensor WENO (Section 3.2): one-dimensional WENO along the last axis
-// first, then along the previous axes, x last.
-template <typename T>
-__device__ __forceinline__ T interp_weno3(gptr<T> A, const DevGrid& g,
-                                          const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz,
-                                          T e) {
+// first, then along the previous axes, x last.  R supplies the rows of four
+// values along z (stencil indices clamped to the grid): from device memory or
+// from a staged copy in LDS; the arithmetic is the same either way.
+template <typename T, typename R>
+__device__ __forceinline__ T interp_weno3(const R& rows, const Loc<T>& lx, const Loc<T>& ly,
+                                          const Loc<T>& lz, T e) {
   const WC<T> cx = wcoef(lx.t), cy = wcoef(ly.t), cz = wcoef(lz.t);
   T wx[4];
   LSR_UNROLL(LSR_WENO_X_UNROLL)
   for (int a = 0; a < 4; ++a) {
-    const uint32_t ra = (uint32_t)clampi(lx.i0 - 1 + a, g.n0) * g.s0;
     T wy[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const uint32_t row = ra + (uint32_t)clampi(ly.i0 - 1 + b, g.n1) * g.s1;
-      typename Vec<T>::v4 r = row4(A, row, lz.i0, g.n2);
+      typename Vec<T>::v4 r = rows.w4(lx.i0 - 1 + a, ly.i0 - 1 + b, lz.i0);
       wy[b] = weno1(r.x, r.y, r.z, r.w, cz, e);
     }
     wx[a] = weno1(wy[0], wy[1], wy[2], wy[3], cy, e);
@@ -234,15 +233,14 @@ __device__ __forceinline__ T interp_weno2(gptr<T> A, const DevGrid& g,
 }
 
 // Multilinear interpolation, eq. (IQ1).
-template <typename T>
-__device__ __forceinline__ T interp_q1_3(gptr<T> A, const DevGrid& g,
-                                         const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) {
+template <typename T, typename R>
+__device__ __forceinline__ T interp_q1_3(const R& rows, const Loc<T>& lx, const Loc<T>& ly,
+                                         const Loc<T>& lz) {
   typedef typename Vec<T>::v2 V2;
-  const uint32_t r00 = (uint32_t)lx.i0 * g.s0 + (uint32_t)ly.i0 * g.s1 + (uint32_t)lz.i0;
-  V2 a00 = *(gptr<V2>)(A + r00);
-  V2 a01 = *(gptr<V2>)(A + r00 + g.s1);
-  V2 a10 = *(gptr<V2>)(A + r00 + g.s0);
-  V2 a11 = *(gptr<V2>)(A + r00 + g.s0 + g.s1);
+  V2 a00 = rows.w2(lx.i0, ly.i0, lz.i0);
+  V2 a01 = rows.w2(lx.i0, ly.i0 + 1, lz.i0);
+  V2 a10 = rows.w2(lx.i0 + 1, ly.i0, lz.i0);
+  V2 a11 = rows.w2(lx.i0 + 1, ly.i0 + 1, lz.i0);
   T tz = lz.t, ty = ly.t, tx = lx.t;
   T b00 = fma(tz, a00.y - a00.x, a00.x);
   T b01 = fma(tz, a01.y - a01.x, a01.x);
@@ -267,47 +265,81 @@ __device__ __forceinline__ T interp_q1_2(gptr<T> A, const DevGrid& g,
 
 enum { UPD_FALLBACK = 1, UPD_FRAME0 = 2 };
 
-// New value of band node (i,j,k) from phi^n = A: eqs. (SL2d)/(SL3d) with
-// C = c(phi^n_j) (p = 1), the fallback of eq. (SL:2) and the cut of eq. (cut).
-// dp = (d_x, d_y, d_z, d) with the centred gradient of d precomputed.
-// Foot points are carried as node index + offset in cells.
+// Rows of phi^n read from device memory (3D): four values along z at
+// k0-1 .. k0+2 of row (ii, jj), or two at k0, k0+1; indices clamped.
+template <typename T>
+struct GlobalRows {
+  gptr<T> A;
+  int n0, n1, n2;
+  uint32_t s0, s1;
+  __device__ __forceinline__ typename Vec<T>::v4 w4(int ii, int jj, int k0) const {
+    return row4(A, (uint32_t)clampi(ii, n0) * s0 + (uint32_t)clampi(jj, n1) * s1, k0, n2);
+  }
+  __device__ __forceinline__ typename Vec<T>::v2 w2(int ii, int jj, int k0) const {
+    return *(gptr<typename Vec<T>::v2>)(A + (uint32_t)ii * s0 + (uint32_t)jj * s1 + (uint32_t)k0);
+  }
+};
+
+// phi^n as the node update reads it, from device memory: neighbours of the
+// node, and the interpolant at a located foot point.
+template <int DIM, int INTERP, typename T>
+struct GlobalSrc {
+  gptr<T> A;
+  const DevGrid& g;
+  T e;
+  __device__ __forceinline__ T nb(uint32_t idx, int di, int dj, int dk) const {
+    return A[idx + (uint32_t)(di * (int)g.s0 + dj * (int)g.s1 + dk)];
+  }
+  __device__ __forceinline__ T foot3(const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) const {
+    const GlobalRows<T> r{A, g.n0, g.n1, g.n2, g.s0, g.s1};
+    return INTERP == 0 ? interp_q1_3(r, lx, ly, lz) : interp_weno3(r, lx, ly, lz, e);
+  }
+  __device__ __forceinline__ T foot2(const Loc<T>& lx, const Loc<T>& ly) const {
+    return INTERP == 0 ? interp_q1_2(A, g, lx, ly) : interp_weno2(A, g, lx, ly, e);
+  }
+};
+
+// New value of band node (i,j,k) from phi^n (read through S): eqs.
+// (SL2d)/(SL3d) with C = c(phi^n_j) (p = 1), the fallback of eq. (SL:2) and
+// the cut of eq. (cut).  dp = (d_x, d_y, d_z, d) with the centred gradient of
+// d precomputed.  Foot points are carried as node index + offset in cells.
 //
 // LANES = 1: one lane interpolates all foot points of the node.  LANES = 2
 // (2D) or 4 (3D): the node is handled by a group of LANES consecutive lanes,
 // lane `sub` interpolating foot point `sub`, and the group sums its values
 // with two cross-lane exchanges.  Both ways add the foot values as
 // (v0 + v1) + (v2 + v3), so they give bitwise identical results.
-template <int DIM, int INTERP, typename T>
-__device__ __forceinline__ T foot_value(gptr<T> A, const DevGrid& g,
-                                        const StepConst<T>& c, int i, int j, int k, int q, T bx,
-                                        T by, T bz, T n1x, T n1y, T n1z, T n2x, T n2y, T n2z) {
+template <int DIM, typename T, typename S>
+__device__ __forceinline__ T foot_value(const S& src, const DevGrid& g, int i, int j, int k, int q,
+                                        T bx, T by, T bz, T n1x, T n1y, T n1z, T n2x, T n2y,
+                                        T n2z) {
   if (DIM == 2) {
     const T l = (q & 1) ? T(1) : T(-1);
     Loc<T> lx = locate(i, bx + n1x * l, g.n0);
     Loc<T> ly = locate(j, by + n1y * l, g.n1);
-    return INTERP == 0 ? interp_q1_2(A, g, lx, ly) : interp_weno2(A, g, lx, ly, c.weno_e);
+    return src.foot2(lx, ly);
   }
   const T f1 = (q & 2) ? T(1) : T(-1), f2 = (q & 1) ? T(1) : T(-1);
   Loc<T> lx = locate(i, bx + f1 * n1x + f2 * n2x, g.n0);
   Loc<T> ly = locate(j, by + f1 * n1y + f2 * n2y, g.n1);
   Loc<T> lz = locate(k, bz + f1 * n1z + f2 * n2z, g.n2);
-  return INTERP == 0 ? interp_q1_3(A, g, lx, ly, lz) : interp_weno3(A, g, lx, ly, lz, c.weno_e);
+  return src.foot3(lx, ly, lz);
 }
 
-template <int DIM, int INTERP, typename T, int LANES>
-__device__ __forceinline__ T sl_update(gptr<T> A, const DevGrid& g,
-                                       const StepConst<T>& c, int i, int j, int k, uint32_t idx,
-                                       T v, typename Vec<T>::p4 dp, int sub, int& flags) {
+template <int DIM, typename T, int LANES, typename S>
+__device__ __forceinline__ T sl_update_src(const S& src, const DevGrid& g, const StepConst<T>& c,
+                                           int i, int j, int k, uint32_t idx, T v,
+                                           typename Vec<T>::p4 dp, int sub, int& flags) {
   constexpr int FP = DIM == 3 ? 4 : 2;  // foot points per node
   T gx, gy, gz = T(0);
-  T xm = i > 0 ? A[idx - g.s0] : v, xp = i < g.n0 - 1 ? A[idx + g.s0] : v;
-  T ym = j > 0 ? A[idx - g.s1] : v, yp = j < g.n1 - 1 ? A[idx + g.s1] : v;
+  T xm = i > 0 ? src.nb(idx, -1, 0, 0) : v, xp = i < g.n0 - 1 ? src.nb(idx, 1, 0, 0) : v;
+  T ym = j > 0 ? src.nb(idx, 0, -1, 0) : v, yp = j < g.n1 - 1 ? src.nb(idx, 0, 1, 0) : v;
   gx = cdiff(xm, v, xp, i, g.n0, c);
   gy = cdiff(ym, v, yp, j, g.n1, c);
   T zm = v, zp = v;
   if (DIM == 3) {
-    zm = k > 0 ? A[idx - 1] : v;
-    zp = k < g.n2 - 1 ? A[idx + 1] : v;
+    zm = k > 0 ? src.nb(idx, 0, 0, -1) : v;
+    zp = k < g.n2 - 1 ? src.nb(idx, 0, 0, 1) : v;
     gz = cdiff(zm, v, zp, k, g.n2, c);
   }
   T nrm = sqrt(gx * gx + gy * gy + gz * gz);
@@ -355,8 +387,8 @@ __device__ __forceinline__ T sl_update(gptr<T> A, const DevGrid& g,
       T prev = T(0), s01 = T(0), s23 = T(0);
       LSR_UNROLL(LSR_FOOT_UNROLL)
       for (int q = 0; q < FP; ++q) {
-        const T vq = foot_value<DIM, INTERP, T>(A, g, c, i, j, k, q, bx, by, bz, n1x, n1y, n1z, n2x,
-                                                n2y, n2z);
+        const T vq = foot_value<DIM, T>(src, g, i, j, k, q, bx, by, bz, n1x, n1y, n1z, n2x, n2y,
+                                        n2z);
         if (q & 1) {
           if (q == 1) s01 = prev + vq;
           else s23 = prev + vq;
@@ -366,14 +398,23 @@ __device__ __forceinline__ T sl_update(gptr<T> A, const DevGrid& g,
       }
       acc = FP == 4 ? s01 + s23 : s01;
     } else {
-      const T vq = foot_value<DIM, INTERP, T>(A, g, c, i, j, k, sub, bx, by, bz, n1x, n1y, n1z,
-                                              n2x, n2y, n2z);
+      const T vq = foot_value<DIM, T>(src, g, i, j, k, sub, bx, by, bz, n1x, n1y, n1z, n2x, n2y,
+                                      n2z);
       acc = vq + __shfl_xor(vq, 1, LANES);
       if (FP == 4) acc = acc + __shfl_xor(acc, 2, LANES);
     }
     out = acc * (T(1) / T(FP));
   }
   return fmin(fmax(out, -c.gamma), c.gamma);
+}
+
+// The update reading phi^n from device memory.
+template <int DIM, int INTERP, typename T, int LANES>
+__device__ __forceinline__ T sl_update(gptr<T> A, const DevGrid& g, const StepConst<T>& c, int i,
+                                       int j, int k, uint32_t idx, T v, typename Vec<T>::p4 dp,
+                                       int sub, int& flags) {
+  const GlobalSrc<DIM, INTERP, T> src{A, g, c.weno_e};
+  return sl_update_src<DIM, T, LANES>(src, g, c, i, j, k, idx, v, dp, sub, flags);
 }
 
 }  // namespace lsr

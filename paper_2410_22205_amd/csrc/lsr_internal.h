@@ -33,7 +33,17 @@ struct SLArgs {
   int32_t* cnt_out;
   int32_t* cnt_reset;
   unsigned long long* stats;
+  // brick lists of the staged 3D step (bricks of 4 x 8 x 8 nodes): the input
+  // list covers every node of Lin, the output list the bricks of Lout
+  const uint32_t* BLin;
+  uint32_t* BLout;
+  const int32_t* bcnt_in;
+  int32_t* bcnt_out;
+  int32_t* bcnt_reset;
 };
+
+// Bricks of the staged 3D step.
+constexpr int BRICK_I = 4, BRICK_J = 8, BRICK_K = 8;
 
 struct DilArgs {
   DevGrid g;
@@ -99,6 +109,15 @@ hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_
 template <typename T>
 hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
                           hipStream_t s);
+// The 3D step over a brick list with phi staged in LDS (same results as
+// launch_sl_step).
+template <typename T>
+hipError_t launch_sl_step_staged(int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s);
+// Brick list (bricks holding a node of L, deduplicated through per-brick
+// stamps at `epoch`) appended to BL / bcnt.
+hipError_t launch_nodes_to_bricks(const DevGrid& g, const uint32_t* L, const int32_t* cnt,
+                                  uint32_t* bstamp, uint32_t epoch, uint32_t* BL, int32_t* bcnt,
+                                  unsigned blocks, hipStream_t s);
 hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s);

@@ -26,6 +26,8 @@ lsr_status fail(lsr_status st, const std::string& msg);
 
 struct Layout {
   size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, stamp, cnt, stats;
+  size_t blist0, blist1, bstamp;  // brick lists and stamps of the staged 3D step
+  int64_t nbricks;
   size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ;
   size_t total;
   int nb[3];
@@ -52,7 +54,8 @@ struct lsr_job {
   uint32_t* listM;
   uint8_t* mflags;
   uint32_t* stamp;
-  int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins
+  int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins,
+                 // [8..10] brick-count ring (staged 3D step)
   unsigned long long* stats;
   double* pts_raw;
   double* pts;
@@ -61,8 +64,13 @@ struct lsr_job {
   int32_t* bin_start;
   int32_t* bin_fill;
   uint32_t* occ;
+  uint32_t* blist[2];
+  uint32_t* bstamp;
+  int cur_blist;       // brick list buffer holding the current brick list
+  uint32_t bepoch;     // stamp epoch of the last brick-list rebuild
+  bool bricks_valid;   // the current brick list covers the current node list
   unsigned list_blocks;
-  int lanes;         // lanes per band node in the step kernel (1 or foot points per node)
+  int lanes;         // step kernel: 0 staged bricks (3D), 1 one lane per node, or foot points
   int blocks_per_cu; // persistent grid of the list kernels: blocks_per_cu x CUs (multiple of 8)
   int ncu;
   int cur;       // phi buffer holding the current phi
@@ -101,6 +109,7 @@ StepConst<T> step_const(const lsr_job* j, double dt) {
 }
 
 inline int32_t* ring_slot(lsr_job* j, int k) { return j->cnt + ((j->ring + k) % 3); }
+inline int32_t* bring_slot(lsr_job* j, int k) { return j->cnt + 8 + ((j->ring + k) % 3); }
 
 template <typename T>
 inline T* phi_buf(lsr_job* j, int b) {
@@ -126,8 +135,14 @@ SLArgs<T> plan_step(lsr_job* j, const StepConst<T>& c) {
   a.cnt_in = ring_slot(j, 0);
   a.cnt_out = ring_slot(j, 1);
   a.cnt_reset = ring_slot(j, 2);
+  a.BLin = j->blist[j->cur_blist];
+  a.BLout = j->blist[1 - j->cur_blist];
+  a.bcnt_in = bring_slot(j, 0);
+  a.bcnt_out = bring_slot(j, 1);
+  a.bcnt_reset = bring_slot(j, 2);
   j->cur = 1 - j->cur;
   j->cur_list = 1 - j->cur_list;
+  j->cur_blist = 1 - j->cur_blist;
   j->ring = (j->ring + 1) % 3;
   j->step_index += 1;
   j->n_steps += 1;

@@ -303,6 +303,187 @@ __device__ __forceinline__ A uniform_load(const A* tab, int index) {
   return out;
 }
 
+// ---------------------------------------------- the staged 3D step (bricks)
+
+#ifndef LSR_STAGE_HALO_F32
+#define LSR_STAGE_HALO_F32 6
+#endif
+#ifndef LSR_STAGE_HALO_F64
+#define LSR_STAGE_HALO_F64 5
+#endif
+
+// Rows of phi^n from a tile staged in LDS: the box of virtual node indices
+// [oi, oi + RI) x [oj, oj + RJ) x [ok, ok + RK), each entry holding phi at the
+// index clamped to the grid (the boundary node repeated), so reading the tile
+// gives exactly what the clamped reads of device memory give.
+template <typename T, int RJ, int RK>
+struct TileRows {
+  const T* tile;
+  int oi, oj, ok;
+  __device__ __forceinline__ typename Vec<T>::v4 w4(int ii, int jj, int k0) const {
+    const T* p = tile + ((ii - oi) * RJ + (jj - oj)) * RK + (k0 - 1 - ok);
+    typename Vec<T>::v4 r;
+    r.x = p[0];
+    r.y = p[1];
+    r.z = p[2];
+    r.w = p[3];
+    return r;
+  }
+  __device__ __forceinline__ typename Vec<T>::v2 w2(int ii, int jj, int k0) const {
+    const T* p = tile + ((ii - oi) * RJ + (jj - oj)) * RK + (k0 - ok);
+    typename Vec<T>::v2 r;
+    r.x = p[0];
+    r.y = p[1];
+    return r;
+  }
+};
+
+// phi^n for the node update of one node of a staged brick: neighbours from
+// the tile; a foot point whose whole stencil lies in the tile is interpolated
+// from it, any other from device memory.
+template <int INTERP, typename T, int H>
+struct StagedSrc {
+  static constexpr int RI = BRICK_I + 2 * H, RJ = BRICK_J + 2 * H, RK = BRICK_K + 2 * H;
+  const T* tile;
+  int oi, oj, ok;
+  int tn;  // tile index of the node
+  GlobalSrc<3, INTERP, T> glob;
+  __device__ __forceinline__ T nb(uint32_t, int di, int dj, int dk) const {
+    return tile[tn + (di * RJ + dj) * RK + dk];
+  }
+  __device__ __forceinline__ T foot3(const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) const {
+    constexpr int lo = INTERP == 0 ? 0 : 1, hi = INTERP == 0 ? 1 : 2;  // stencil reach
+    const bool in = lx.i0 - lo >= oi && lx.i0 + hi < oi + RI && ly.i0 - lo >= oj &&
+                    ly.i0 + hi < oj + RJ && lz.i0 - lo >= ok && lz.i0 + hi < ok + RK;
+    if (in) {
+      const TileRows<T, RJ, RK> r{tile, oi, oj, ok};
+      return INTERP == 0 ? interp_q1_3(r, lx, ly, lz) : interp_weno3(r, lx, ly, lz, glob.e);
+    }
+    return glob.foot3(lx, ly, lz);
+  }
+  __device__ __forceinline__ T foot2(const Loc<T>& lx, const Loc<T>& ly) const {
+    return glob.foot2(lx, ly);
+  }
+};
+
+// One time step over a list of bricks (4 x 8 x 8 nodes, one thread per node):
+// phi^n on the brick and a halo of H nodes is staged in LDS with coalesced
+// reads, then every node of the brick with |phi^n| < gamma gets the update of
+// k_sl_step (the same arithmetic on the same values) and every other node of
+// the brick is copied to B.  The next node list holds the updated nodes, the
+// next brick list the bricks that had one.
+template <int INTERP, typename T, int H>
+__global__ __launch_bounds__(256) void k_sl_step_staged(SLArgs<T> a) {
+  constexpr int RI = BRICK_I + 2 * H, RJ = BRICK_J + 2 * H, RK = BRICK_K + 2 * H;
+  constexpr int RJK = RJ * RK, RN = RI * RJK;
+  // index steps of the staging loop (r += 256)
+  constexpr int DI = 256 / RJK, DJ = (256 % RJK) / RK, DK = 256 % RK;
+  __shared__ T tile[RN];
+  __shared__ int lds_app[8];
+  __shared__ uint32_t lds_st[12];
+  __shared__ int wave_act[4];
+  __shared__ uint16_t act_ids[256];
+  const DevGrid& g = a.g;
+  const gptr<T> A = (gptr<T>)a.A;
+  const gwptr<T> B = (gwptr<T>)a.B;
+  const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
+  const gptr<uint32_t> BLin = (gptr<uint32_t>)a.BLin;
+  const int nbr = *a.bcnt_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *a.cnt_reset = 0;
+    *a.bcnt_reset = 0;
+  }
+  const uint32_t nbj = ((uint32_t)g.n1 + BRICK_J - 1) / BRICK_J;
+  const uint32_t nbk = ((uint32_t)g.n2 + BRICK_K - 1) / BRICK_K;
+  const int t = (int)threadIdx.x, w = t >> 6;
+  const int ri0 = t / RJK, rj0 = (t % RJK) / RK, rk0 = t % RK;
+  uint32_t nupd = 0, nfb = 0, nfr = 0;
+  for (int q = blockIdx.x; q < nbr; q += gridDim.x) {
+    const uint32_t br = BLin[q];
+    const int bi = (int)(br / (nbj * nbk)), bj = (int)((br / nbk) % nbj), bk = (int)(br % nbk);
+    const int oi = bi * BRICK_I - H, oj = bj * BRICK_J - H, ok = bk * BRICK_K - H;
+    __syncthreads();  // the previous brick's tile and ids are no longer read
+    {
+      int ri = ri0, rj = rj0, rk = rk0;
+      for (int r = t; r < RN; r += 256) {
+        tile[r] = A[lin(g, clampi(oi + ri, g.n0), clampi(oj + rj, g.n1), clampi(ok + rk, g.n2))];
+        rk += DK;
+        const int ck = rk >= RK;
+        rk -= ck * RK;
+        rj += DJ + ck;
+        const int cj = rj >= RJ;
+        rj -= cj * RJ;
+        ri += DI + cj;
+      }
+    }
+    __syncthreads();
+    // the brick's node t: copied to B unless it is in the band; band nodes
+    // are packed into the first lanes of the block for the update
+    const int li = t / (BRICK_J * BRICK_K), lj = (t / BRICK_K) % BRICK_J, lk = t % BRICK_K;
+    const int i = bi * BRICK_I + li, j = bj * BRICK_J + lj, k = bk * BRICK_K + lk;
+    const bool valid = i < g.n0 && j < g.n1 && k < g.n2;
+    const int tn = ((i - oi) * RJ + (j - oj)) * RK + (k - ok);
+    const T v = valid ? tile[tn] : T(0);
+    const bool band = valid && fabs(v) < a.c.gamma;
+    if (valid && !band) B[lin(g, i, j, k)] = v;
+    const uint64_t m = __ballot(band);
+    if ((t & 63) == 0) wave_act[w] = (int)__popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      off += u < w ? wave_act[u] : 0;
+      tot += wave_act[u];
+    }
+    if (band) act_ids[off + (int)lanes_below(m)] = (uint16_t)t;
+    __syncthreads();
+    bool act = false;
+    int fl = 0;
+    uint32_t code = 0;
+    if (t < tot) {
+      const int u = act_ids[t];
+      const int ui = u / (BRICK_J * BRICK_K), uj = (u / BRICK_K) % BRICK_J, uk = u % BRICK_K;
+      const int i2 = bi * BRICK_I + ui, j2 = bj * BRICK_J + uj, k2 = bk * BRICK_K + uk;
+      const int tn2 = ((i2 - oi) * RJ + (j2 - oj)) * RK + (k2 - ok);
+      const uint32_t idx = lin(g, i2, j2, k2);
+      act = true;
+      code = encode(g, i2, j2, k2);
+      const StagedSrc<INTERP, T, H> src{tile, oi, oj, ok, tn2,
+                                        GlobalSrc<3, INTERP, T>{A, g, a.c.weno_e}};
+      B[idx] = sl_update_src<3, T, 1>(src, g, a.c, i2, j2, k2, idx, tile[tn2], DP[idx], 0, fl);
+    }
+    block_append1(act, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds_app);
+    if (t == 0 && tot > 0) a.BLout[atomicAdd(a.bcnt_out, 1)] = br;
+    nupd += wave_count(act);
+    nfb += wave_count(fl & UPD_FALLBACK);
+    nfr += wave_count(fl & UPD_FRAME0);
+  }
+  block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
+}
+
+// Bricks holding a node of the list L (each once: per-brick stamps).
+__global__ __launch_bounds__(256) void k_nodes_to_bricks(DevGrid g, const uint32_t* __restrict__ L,
+                                                         const int32_t* cnt, uint32_t* bstamp,
+                                                         uint32_t epoch, uint32_t* BL,
+                                                         int32_t* bcnt) {
+  __shared__ int lds[8];
+  const int n = *cnt;
+  const uint32_t nbj = ((uint32_t)g.n1 + BRICK_J - 1) / BRICK_J;
+  const uint32_t nbk = ((uint32_t)g.n2 + BRICK_K - 1) / BRICK_K;
+  for (uint32_t base = blockIdx.x * 256u; base < (uint32_t)n; base += gridDim.x * 256u) {
+    const uint32_t e = base + threadIdx.x;
+    bool fresh = false;
+    uint32_t br = 0;
+    if (e < (uint32_t)n) {
+      int i, j, k;
+      decode(g, L[e], i, j, k);
+      br = ((uint32_t)(i / BRICK_I) * nbj + (uint32_t)(j / BRICK_J)) * nbk + (uint32_t)(k / BRICK_K);
+      fresh = atomicMax(&bstamp[br], epoch) < epoch;
+    }
+    block_append1(fresh, br, (gwptr<uint32_t>)BL, bcnt, lds);
+  }
+}
+
 // Cursor of a block over the jobs of a batched launch: job jb holds the
 // global chunks [beg, end) and nl list entries.  advance() moves to the job
 // holding chunk gch and returns false once gch lies past the last job; on
@@ -1018,6 +1199,20 @@ hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, un
   return persistent_launch(k, blocks, s, a);
 }
 
+template <typename T>
+hipError_t launch_sl_step_staged(int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s) {
+  // halo of the staged tile (nodes): LSR_STAGE_HALO_F32 / _F64
+  constexpr int H = sizeof(T) == 4 ? LSR_STAGE_HALO_F32 : LSR_STAGE_HALO_F64;
+  return persistent_launch(interp == 0 ? k_sl_step_staged<0, T, H> : k_sl_step_staged<1, T, H>,
+                           blocks, s, a);
+}
+
+hipError_t launch_nodes_to_bricks(const DevGrid& g, const uint32_t* L, const int32_t* cnt,
+                                  uint32_t* bstamp, uint32_t epoch, uint32_t* BL, int32_t* bcnt,
+                                  unsigned blocks, hipStream_t s) {
+  return persistent_launch(k_nodes_to_bricks, blocks, s, g, L, cnt, bstamp, epoch, BL, bcnt);
+}
+
 hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s) {
   return persistent_launch(dim == 3 ? k_dilate<3> : k_dilate<2>, blocks, s, a);
 }
@@ -1140,6 +1335,7 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \
   template hipError_t launch_dpack<T>(int, const DevGrid&, const double*, typename Vec<T>::pack*, \
                                       hipStream_t);                                               \
+  template hipError_t launch_sl_step_staged<T>(int, const SLArgs<T>&, unsigned, hipStream_t);     \
   template hipError_t launch_sl_step_batch<T>(int, int, int, const SLArgs<T>*, int,               \
                                               unsigned, hipStream_t);                             \
   template hipError_t launch_reinit_fix_batch<T>(int, const RArgs<T>*, int, unsigned, hipStream_t);\
