@@ -63,7 +63,6 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.list1 = take(4 * N);
   L.listM = take(4 * N);
   L.mflags = take(N);
-  L.stamp = take(4 * N);
   // bricks of the staged 3D step: 4 x 8 x 8 nodes
   L.nbricks = g.dim == 3 ? (int64_t)((g.n[0] + BRICK_I - 1) / BRICK_I) *
                                ((g.n[1] + BRICK_J - 1) / BRICK_J) * ((g.n[2] + BRICK_K - 1) / BRICK_K)
@@ -126,7 +125,7 @@ template <typename T>
 static lsr_status launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
   hipStream_t s = j->stream;
   const int dim = j->grid.dim;
-  LSR_HIP(launch_dilate(dim, r.dil, j->list_blocks, s));
+  LSR_HIP(launch_gbar_scan<T>(dim, r.gb, j->list_blocks, s));
   LSR_HIP(launch_reinit_fix<T>(dim, r.fix, j->list_blocks, s));
   for (int it = 0; it < r.iters; ++it)
     LSR_HIP(launch_reinit_iter<T>(dim, r.iter[it % 2], j->list_blocks, s));
@@ -136,10 +135,6 @@ static lsr_status launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
 
 template <typename T>
 static lsr_status run_reinit_t(lsr_job* j) {
-  if (stamp_needs_clear(j)) {
-    LSR_HIP(launch_fill_u32(j->stamp, 0u, j->dg.N, j->stream));
-    j->epoch = 0;
-  }
   ReinitPlan<T> r = plan_reinit<T>(j);
   j->bricks_valid = false;
   return launch_reinit_plan<T>(j, r);
@@ -350,7 +345,6 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->list[1] = (uint32_t*)(w + L.list1);
   j->listM = (uint32_t*)(w + L.listM);
   j->mflags = (uint8_t*)(w + L.mflags);
-  j->stamp = (uint32_t*)(w + L.stamp);
   j->blist[0] = (uint32_t*)(w + L.blist0);
   j->blist[1] = (uint32_t*)(w + L.blist1);
   j->bstamp = (uint32_t*)(w + L.bstamp);
@@ -373,7 +367,6 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->cur = 0;
   j->cur_list = 0;
   j->ring = 0;
-  j->epoch = 0;
   j->step_index = 0;
   j->n_reinits = 0;
   j->n_steps = 0;
@@ -383,8 +376,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->prof_used = 0;
 
   hipStream_t s = j->stream;
-  hipError_t e = launch_fill_u32(j->stamp, 0u, d.N, s);
-  if (e == hipSuccess) e = launch_fill_u32(j->bstamp, 0u, (uint64_t)L.nbricks, s);
+  hipError_t e = launch_fill_u32(j->bstamp, 0u, (uint64_t)L.nbricks, s);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->cnt, 0u, 16, s);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->stats, 0u, 32, s);
   if (e != hipSuccess) {

@@ -21,10 +21,9 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Launch {
-  int kind;  // 0 step, 1 dilate, 2 fix, 3 iteration, 4 final, 5 stamp clear
+  int kind;  // 0 step, 1 Gbar scan, 2 fix, 3 iteration, 4 final
   size_t off;
   int n;
-  lsr_job* job;  // kind 5 only
   int interp;    // kind 0 only
 };
 
@@ -62,7 +61,7 @@ namespace {
 // own tables, so the alignment padding is counted once per table per job.
 size_t group_table_bytes(int n_jobs, int group_steps, int max_iters) {
   const size_t n = (size_t)n_jobs, a = 255;
-  const size_t per_step = n * (sizeof(SLArgs<double>) + sizeof(DilArgs) +
+  const size_t per_step = n * (sizeof(SLArgs<double>) + sizeof(GbarArgs<double>) +
                                (size_t)(max_iters + 1) * sizeof(RArgs<double>) +
                                sizeof(FinArgs<double>)) +
                           n * (size_t)(2 + 3 + max_iters) * a;
@@ -120,7 +119,7 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
         j->bricks_valid = false;  // stepped here through the node list
         tab[m++] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
       }
-      B.launches.push_back({0, o, m, nullptr, itp});
+      B.launches.push_back({0, o, m, itp});
     }
     std::vector<int> due;
     for (int q = q0; q < q1; ++q)
@@ -131,33 +130,29 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
     int max_it = 0;
     for (int q : due) {
       lsr_job* j = b->jobs[q];
-      if (stamp_needs_clear(j)) {
-        B.launches.push_back({5, 0, 0, j, 0});
-        j->epoch = 0;
-      }
       plans.push_back(plan_reinit<T>(j));
       max_it = std::max(max_it, plans.back().iters);
     }
     size_t od = align256(B.off);
-    DilArgs* dil = B.template take<DilArgs>(nd);
-    for (int q = 0; q < nd; ++q) dil[q] = plans[q].dil;
-    B.launches.push_back({1, od, nd, nullptr, 0});
+    GbarArgs<T>* gb = B.template take<GbarArgs<T>>(nd);
+    for (int q = 0; q < nd; ++q) gb[q] = plans[q].gb;
+    B.launches.push_back({1, od, nd, 0});
     size_t of = align256(B.off);
     RArgs<T>* fix = B.template take<RArgs<T>>(nd);
     for (int q = 0; q < nd; ++q) fix[q] = plans[q].fix;
-    B.launches.push_back({2, of, nd, nullptr, 0});
+    B.launches.push_back({2, of, nd, 0});
     for (int it = 0; it < max_it; ++it) {
       size_t oi = align256(B.off);
       RArgs<T>* itab = B.template take<RArgs<T>>(nd);
       int m = 0;
       for (int q = 0; q < nd; ++q)
         if (it < plans[q].iters) itab[m++] = plans[q].iter[it % 2];
-      B.launches.push_back({3, oi, m, nullptr, 0});
+      B.launches.push_back({3, oi, m, 0});
     }
     size_t on = align256(B.off);
     FinArgs<T>* fin = B.template take<FinArgs<T>>(nd);
     for (int q = 0; q < nd; ++q) fin[q] = plans[q].fin;
-    B.launches.push_back({4, on, nd, nullptr, 0});
+    B.launches.push_back({4, on, nd, 0});
   }
   if (B.off > b->table_bytes) return fail(LSR_E_NOMEM, "batch table workspace too small");
   return LSR_OK;
@@ -174,7 +169,8 @@ lsr_status issue(lsr_batch* b, const Builder<T>& B) {
                                         L.n, b->blocks, s));
         break;
       case 1:
-        LSR_HIP(launch_dilate_batch(b->dim, (const DilArgs*)(dev + L.off), L.n, b->blocks, s));
+        LSR_HIP(launch_gbar_scan_batch<T>(b->dim, (const GbarArgs<T>*)(dev + L.off), L.n, b->blocks,
+                                          s));
         break;
       case 2:
         LSR_HIP(launch_reinit_fix_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n, b->blocks, s));
@@ -186,9 +182,6 @@ lsr_status issue(lsr_batch* b, const Builder<T>& B) {
         break;
       case 4:
         LSR_HIP(launch_reinit_final_batch<T>((const FinArgs<T>*)(dev + L.off), L.n, b->blocks, s));
-        break;
-      case 5:
-        LSR_HIP(launch_fill_u32(L.job->stamp, 0u, L.job->dg.N, s));
         break;
     }
   }

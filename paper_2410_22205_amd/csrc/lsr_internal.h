@@ -45,15 +45,17 @@ struct SLArgs {
 // Bricks of the staged 3D step.
 constexpr int BRICK_I = 4, BRICK_J = 8, BRICK_K = 8;
 
-struct DilArgs {
+// Gbar (the band of the step and its face neighbours) found by a scan of
+// the grid: node x belongs to it iff |P| < gamma at x or at a face neighbour,
+// with P = phi^n, the field whose band the step updated.
+template <typename T>
+struct GbarArgs {
   DevGrid g;
-  const uint32_t* L;
-  const int32_t* cnt_in;
+  T gamma;
+  const T* P;
   uint32_t* M;
   int32_t* cnt_out;
   int32_t* cnt_reset;
-  uint32_t* stamp;
-  uint32_t epoch;
 };
 
 template <typename T>
@@ -118,7 +120,8 @@ hipError_t launch_sl_step_staged(int interp, const SLArgs<T>& a, unsigned blocks
 hipError_t launch_nodes_to_bricks(const DevGrid& g, const uint32_t* L, const int32_t* cnt,
                                   uint32_t* bstamp, uint32_t epoch, uint32_t* BL, int32_t* bcnt,
                                   unsigned blocks, hipStream_t s);
-hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_gbar_scan(int dim, const GbarArgs<T>& a, unsigned blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s);
 template <typename T>
@@ -142,7 +145,9 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
 template <typename T>
 hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>* tab, int n,
                                 unsigned blocks, hipStream_t s);
-hipError_t launch_dilate_batch(int dim, const DilArgs* tab, int n, unsigned blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_gbar_scan_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
+                                  hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_fix_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
                                    hipStream_t s);

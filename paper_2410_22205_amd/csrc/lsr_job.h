@@ -25,7 +25,7 @@ lsr_status fail(lsr_status st, const std::string& msg);
   } while (0)
 
 struct Layout {
-  size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, stamp, cnt, stats;
+  size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, cnt, stats;
   size_t blist0, blist1, bstamp;  // brick lists and stamps of the staged 3D step
   int64_t nbricks;
   size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ;
@@ -53,7 +53,6 @@ struct lsr_job {
   uint32_t* list[2];
   uint32_t* listM;
   uint8_t* mflags;
-  uint32_t* stamp;
   int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins,
                  // [8..10] brick-count ring (staged 3D step)
   unsigned long long* stats;
@@ -76,7 +75,6 @@ struct lsr_job {
   int cur;       // phi buffer holding the current phi
   int cur_list;  // list buffer holding the current band list
   int ring;      // counter slot holding the current list length
-  uint32_t epoch;
   int64_t step_index;
   int64_t n_reinits, n_steps;
   bool has_d, has_phi;
@@ -149,32 +147,26 @@ SLArgs<T> plan_step(lsr_job* j, const StepConst<T>& c) {
   return a;
 }
 
-// Arguments of one reinitialisation: dilation, interface fix, iterations
+// Arguments of one reinitialisation: Gbar scan, interface fix, iterations
 // (iter[it % 2] is the it-th), final cut and compaction.
 template <typename T>
 struct ReinitPlan {
-  DilArgs dil;
+  GbarArgs<T> gb;
   RArgs<T> fix;
   RArgs<T> iter[2];
   FinArgs<T> fin;
   int iters;
 };
 
-// The stamp epoch must be bumped before planning; a wrap needs a stamp clear.
-inline bool stamp_needs_clear(const lsr_job* j) { return j->epoch == 0xFFFFFFFFu; }
-
 template <typename T>
 ReinitPlan<T> plan_reinit(lsr_job* j) {
   ReinitPlan<T> r;
-  j->epoch += 1;
-  r.dil.g = j->dg;
-  r.dil.L = j->list[j->cur_list];
-  r.dil.cnt_in = ring_slot(j, 0);
-  r.dil.M = j->listM;
-  r.dil.cnt_out = ring_slot(j, 1);
-  r.dil.cnt_reset = ring_slot(j, 2);
-  r.dil.stamp = j->stamp;
-  r.dil.epoch = j->epoch;
+  r.gb.g = j->dg;
+  r.gb.gamma = (T)j->prm.gamma;
+  r.gb.P = phi_buf<T>(j, 1 - j->cur);  // phi^n: the step just taken read it
+  r.gb.M = j->listM;
+  r.gb.cnt_out = ring_slot(j, 1);
+  r.gb.cnt_reset = ring_slot(j, 2);
   j->ring = (j->ring + 1) % 3;
 
   RArgs<T> ra;

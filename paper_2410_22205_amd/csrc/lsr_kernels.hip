@@ -305,6 +305,9 @@ __device__ __forceinline__ A uniform_load(const A* tab, int index) {
 
 // ---------------------------------------------- the staged 3D step (bricks)
 
+#ifndef LSR_GBAR_BRICK_ORDER
+#define LSR_GBAR_BRICK_ORDER 1
+#endif
 #ifndef LSR_STAGE_HALO_F32
 #define LSR_STAGE_HALO_F32 6
 #endif
@@ -484,6 +487,17 @@ __global__ __launch_bounds__(256) void k_nodes_to_bricks(DevGrid g, const uint32
   }
 }
 
+// Grid nodes covered by the chunks of the Gbar scan.
+template <int DIM>
+__device__ __forceinline__ uint32_t gbar_extent(const DevGrid& g) {
+#if LSR_GBAR_BRICK_ORDER
+  if (DIM == 3)
+    return ((uint32_t)g.n0 + 3u) / 4u * (((uint32_t)g.n1 + 7u) / 8u) * (((uint32_t)g.n2 + 7u) / 8u) *
+           256u;
+#endif
+  return g.N;
+}
+
 // Cursor of a block over the jobs of a batched launch: job jb holds the
 // global chunks [beg, end) and nl list entries.  advance() moves to the job
 // holding chunk gch and returns false once gch lies past the last job; on
@@ -498,19 +512,25 @@ struct JobCursor {
     while (gch >= end) {
       if (jb >= 0) leave(jb);
       if (++jb >= n) return false;
-      nl = __builtin_amdgcn_readfirstlane(*count(uniform_load(tab, jb)));
+      nl = __builtin_amdgcn_readfirstlane(count(uniform_load(tab, jb)));
       beg = end;
       end = beg + ((uint32_t)nl + ch - 1) / ch;
     }
     return true;
   }
-  static __device__ __forceinline__ const int32_t* count(const SLArgs<float>& x) { return x.cnt_in; }
-  static __device__ __forceinline__ const int32_t* count(const SLArgs<double>& x) { return x.cnt_in; }
-  static __device__ __forceinline__ const int32_t* count(const DilArgs& x) { return x.cnt_in; }
-  static __device__ __forceinline__ const int32_t* count(const RArgs<float>& x) { return x.cnt; }
-  static __device__ __forceinline__ const int32_t* count(const RArgs<double>& x) { return x.cnt; }
-  static __device__ __forceinline__ const int32_t* count(const FinArgs<float>& x) { return x.cnt_in; }
-  static __device__ __forceinline__ const int32_t* count(const FinArgs<double>& x) { return x.cnt_in; }
+  // list entries of a job, or grid nodes for the Gbar scan
+  static __device__ __forceinline__ int count(const SLArgs<float>& x) { return *x.cnt_in; }
+  static __device__ __forceinline__ int count(const SLArgs<double>& x) { return *x.cnt_in; }
+  static __device__ __forceinline__ int count(const GbarArgs<float>& x) {
+    return (int)(x.g.n2 > 1 ? gbar_extent<3>(x.g) : gbar_extent<2>(x.g));
+  }
+  static __device__ __forceinline__ int count(const GbarArgs<double>& x) {
+    return (int)(x.g.n2 > 1 ? gbar_extent<3>(x.g) : gbar_extent<2>(x.g));
+  }
+  static __device__ __forceinline__ int count(const RArgs<float>& x) { return *x.cnt; }
+  static __device__ __forceinline__ int count(const RArgs<double>& x) { return *x.cnt; }
+  static __device__ __forceinline__ int count(const FinArgs<float>& x) { return *x.cnt_in; }
+  static __device__ __forceinline__ int count(const FinArgs<double>& x) { return *x.cnt_in; }
 };
 
 // Batched step for the jobs of one interpolator (one launch per interpolator,
@@ -540,47 +560,80 @@ __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restri
 
 // ------------------------------------------------------- reinitialisation
 
-// Gbar = band + face neighbours, deduplicated through a per-node stamp.
+// Gbar = band + face neighbours, by a scan of 256 consecutive grid nodes per
+// chunk (the band of the step is {|phi^n| < gamma}).
+// One chunk of the Gbar scan: 4 sub-chunks of 256 nodes (in 3D, 4 bricks of
+// 4 x 8 x 8 nodes in local order), one node of each per thread, the values
+// read together and the members appended in node order with one atomic.
+constexpr uint32_t GBAR_SUB = 4, GBAR_CHUNK = 256 * GBAR_SUB;
+
 template <int DIM>
-__device__ __forceinline__ void dilate_chunk(const DilArgs& a, uint32_t base, int n, int* lds) {
-  constexpr int K = 1 + 2 * DIM;
-  const uint32_t e = base + threadIdx.x;
-  const bool valid = e < (uint32_t)n;
-  int i = 0, j = 0, k = 0;
-  if (valid) decode(a.g, ((gptr<uint32_t>)a.L)[e], i, j, k);
-  bool ins[K];
-  uint32_t code[K];
+__device__ __forceinline__ bool gbar_node(const DevGrid& g, uint32_t sub, int& i, int& j, int& k) {
+#if LSR_GBAR_BRICK_ORDER
+  if (DIM == 3) {
+    const uint32_t nbj = ((uint32_t)g.n1 + 7u) / 8u, nbk = ((uint32_t)g.n2 + 7u) / 8u;
+    i = (int)((sub / (nbj * nbk)) * 4u + threadIdx.x / 64u);
+    j = (int)(((sub / nbk) % nbj) * 8u + (threadIdx.x / 8u) % 8u);
+    k = (int)((sub % nbk) * 8u + threadIdx.x % 8u);
+    return i < g.n0 && j < g.n1 && k < g.n2;
+  }
+#endif
+  const uint32_t idx = sub * 256u + threadIdx.x;
+  uint32_t r = idx;
+  k = 0;
+  if (DIM == 3) {
+    k = (int)(r % (uint32_t)g.n2);
+    r /= (uint32_t)g.n2;
+  }
+  i = (int)(r / (uint32_t)g.n1);
+  j = (int)(r % (uint32_t)g.n1);
+  return idx < g.N;
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void gbar_chunk(const GbarArgs<T>& a, uint32_t base, int* lds) {
+  const gptr<T> P = (gptr<T>)a.P;
+  bool in[GBAR_SUB];
+  uint32_t code[GBAR_SUB];
 #pragma unroll
-  for (int c = 0; c < K; ++c) {
-    const int ii = i + (c == 1 ? -1 : c == 2 ? 1 : 0);
-    const int jj = j + (c == 3 ? -1 : c == 4 ? 1 : 0);
-    const int kk = k + (c == 5 ? -1 : c == 6 ? 1 : 0);
-    ins[c] = false;
-    code[c] = 0;
-    if (valid && ii >= 0 && ii < a.g.n0 && jj >= 0 && jj < a.g.n1 && kk >= 0 && kk < a.g.n2) {
-      const uint32_t old = atomicMax(&a.stamp[lin(a.g, ii, jj, kk)], a.epoch);
-      ins[c] = old < a.epoch;
-      code[c] = encode(a.g, ii, jj, kk);
+  for (uint32_t u = 0; u < GBAR_SUB; ++u) {
+    int i, j, k;
+    in[u] = false;
+    code[u] = 0;
+    if (gbar_node<DIM>(a.g, base / 256u + u, i, j, k)) {
+      const uint32_t idx = lin(a.g, i, j, k);
+      // all seven values (a neighbour off the grid reads the node itself)
+      const T v0 = P[idx];
+      const T xm = P[i > 0 ? idx - a.g.s0 : idx], xp = P[i < a.g.n0 - 1 ? idx + a.g.s0 : idx];
+      const T ym = P[j > 0 ? idx - a.g.s1 : idx], yp = P[j < a.g.n1 - 1 ? idx + a.g.s1 : idx];
+      T m = fmin(fmin(fabs(v0), fmin(fabs(xm), fabs(xp))), fmin(fabs(ym), fabs(yp)));
+      if (DIM == 3) {
+        const T zm = P[k > 0 ? idx - 1 : idx], zp = P[k < a.g.n2 - 1 ? idx + 1 : idx];
+        m = fmin(m, fmin(fabs(zm), fabs(zp)));
+      }
+      in[u] = m < a.gamma;
+      code[u] = encode(a.g, i, j, k);
     }
   }
-  block_append<K>(ins, code, (gwptr<uint32_t>)a.M, a.cnt_out, lds);
+  block_append<GBAR_SUB>(in, code, (gwptr<uint32_t>)a.M, a.cnt_out, lds);
 }
 
-template <int DIM>
-__global__ __launch_bounds__(256) void k_dilate(DilArgs a) {
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_gbar_scan(GbarArgs<T> a) {
   __shared__ int lds[8];
-  const int n = *a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  const uint32_t ext = gbar_extent<DIM>(a.g);
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * 256u;
-    if (base >= (uint32_t)n) break;
-    dilate_chunk<DIM>(a, base, n, lds);
+    const uint32_t base = chunk_of(q, xcd) * GBAR_CHUNK;
+    if (base >= ext) break;
+    gbar_chunk<DIM, T>(a, base, lds);
   }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(256) void k_dilate_batch(const DilArgs* __restrict__ tab, int n) {
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_gbar_scan_batch(const GbarArgs<T>* __restrict__ tab,
+                                                         int n) {
   __shared__ int lds[8];
   if (blockIdx.x == 0)
     for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_reset = 0;
@@ -589,8 +642,8 @@ __global__ __launch_bounds__(256) void k_dilate_batch(const DilArgs* __restrict_
   auto leave = [](int) {};
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
     const uint32_t gch = chunk_of(q, xcd);
-    if (!cur.advance(tab, gch, 256u, leave)) break;
-    dilate_chunk<DIM>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl, lds);
+    if (!cur.advance(tab, gch, GBAR_CHUNK, leave)) break;
+    gbar_chunk<DIM, T>(uniform_load(tab, cur.jb), (gch - cur.beg) * GBAR_CHUNK, lds);
   }
 }
 
@@ -1213,8 +1266,9 @@ hipError_t launch_nodes_to_bricks(const DevGrid& g, const uint32_t* L, const int
   return persistent_launch(k_nodes_to_bricks, blocks, s, g, L, cnt, bstamp, epoch, BL, bcnt);
 }
 
-hipError_t launch_dilate(int dim, const DilArgs& a, unsigned blocks, hipStream_t s) {
-  return persistent_launch(dim == 3 ? k_dilate<3> : k_dilate<2>, blocks, s, a);
+template <typename T>
+hipError_t launch_gbar_scan(int dim, const GbarArgs<T>& a, unsigned blocks, hipStream_t s) {
+  return persistent_launch(dim == 3 ? k_gbar_scan<3, T> : k_gbar_scan<2, T>, blocks, s, a);
 }
 
 template <typename T>
@@ -1298,8 +1352,11 @@ hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>*
   return persistent_launch(k, blocks, s, tab, n);
 }
 
-hipError_t launch_dilate_batch(int dim, const DilArgs* tab, int n, unsigned blocks, hipStream_t s) {
-  return persistent_launch(dim == 3 ? k_dilate_batch<3> : k_dilate_batch<2>, blocks, s, tab, n);
+template <typename T>
+hipError_t launch_gbar_scan_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
+                                  hipStream_t s) {
+  return persistent_launch(dim == 3 ? k_gbar_scan_batch<3, T> : k_gbar_scan_batch<2, T>, blocks, s,
+                           tab, n);
 }
 
 template <typename T>
@@ -1336,6 +1393,9 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_dpack<T>(int, const DevGrid&, const double*, typename Vec<T>::pack*, \
                                       hipStream_t);                                               \
   template hipError_t launch_sl_step_staged<T>(int, const SLArgs<T>&, unsigned, hipStream_t);     \
+  template hipError_t launch_gbar_scan<T>(int, const GbarArgs<T>&, unsigned, hipStream_t);        \
+  template hipError_t launch_gbar_scan_batch<T>(int, const GbarArgs<T>*, int, unsigned,           \
+                                                hipStream_t);                                     \
   template hipError_t launch_sl_step_batch<T>(int, int, int, const SLArgs<T>*, int,               \
                                               unsigned, hipStream_t);                             \
   template hipError_t launch_reinit_fix_batch<T>(int, const RArgs<T>*, int, unsigned, hipStream_t);\
