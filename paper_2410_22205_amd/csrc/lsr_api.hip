@@ -71,7 +71,7 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.blist1 = take(4 * (size_t)L.nbricks);
   L.bstamp = take(4 * (size_t)L.nbricks);
   L.cnt = take(4 * 16);
-  L.stats = take(8 * 16);
+  L.stats = take(8 * STAT_WORDS);
   L.pts_raw = take(8 * (size_t)g.dim * P);
   L.pts = take(8 * (size_t)g.dim * P);
   L.pt_bin = take(4 * P);
@@ -378,7 +378,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   hipStream_t s = j->stream;
   hipError_t e = launch_fill_u32(j->bstamp, 0u, (uint64_t)L.nbricks, s);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->cnt, 0u, 16, s);
-  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->stats, 0u, 32, s);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->stats, 0u, 2 * STAT_WORDS, s);
   if (e != hipSuccess) {
     delete j;
     return fail(LSR_E_DEVICE, std::string("clearing the workspace: ") + hipGetErrorString(e));
@@ -477,7 +477,7 @@ lsr_status lsr_init_phi(lsr_job* j, const void* dev_phi0, int32_t kind, const do
   }
   LSR_HIP(init_phi(j, kind, a, dev_phi0, true));
   LSR_HIP(launch_fill_u32((uint32_t*)j->cnt, 0u, 3, s));
-  LSR_HIP(launch_fill_u32((uint32_t*)j->stats, 0u, 32, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)j->stats, 0u, 2 * STAT_WORDS, s));
   LSR_HIP(j->fp64 ? launch_band_scan<double>(dim, j->dg, j->prm.gamma, phi_buf<double>(j, 0),
                                              j->list[0], j->cnt, s)
                   : launch_band_scan<float>(dim, j->dg, (float)j->prm.gamma, phi_buf<float>(j, 0),
@@ -544,9 +544,13 @@ lsr_status lsr_extract(lsr_job* j, void* dev_phi, uint8_t* dev_band, int64_t* n_
 lsr_status lsr_counters(lsr_job* j, int64_t* out, int32_t n) {
   if (!j || !out) return fail(LSR_E_INVALID, "NULL argument");
   if (n < 0) return fail(LSR_E_INVALID, "n must be >= 0");
-  unsigned long long dev[16];
-  LSR_HIP(hipMemcpyAsync(dev, j->stats, sizeof(dev), hipMemcpyDeviceToHost, j->stream));
+  std::vector<unsigned long long> raw(STAT_WORDS);
+  LSR_HIP(hipMemcpyAsync(raw.data(), j->stats, sizeof(unsigned long long) * STAT_WORDS,
+                         hipMemcpyDeviceToHost, j->stream));
   LSR_HIP(hipStreamSynchronize(j->stream));
+  unsigned long long dev[STAT_COUNTERS] = {};
+  for (int c = 0; c < STAT_COUNTERS; ++c)
+    for (int q = 0; q < STAT_SLOTS; ++q) dev[c] += raw[stat_index(c, q)];
   int64_t all[LSR_CNT_COUNT];
   all[LSR_CNT_NODE_UPDATES] = (int64_t)dev[0];
   all[LSR_CNT_FALLBACKS] = (int64_t)dev[1];

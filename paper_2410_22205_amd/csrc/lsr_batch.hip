@@ -342,7 +342,7 @@ lsr_status lsr_batch_workspace_bytes(int32_t max_jobs, int32_t group_steps, int3
                                      size_t* bytes) {
   if (max_jobs < 1 || group_steps < 1 || max_reinit_iters < 0 || !bytes)
     return fail(LSR_E_INVALID, "need max_jobs >= 1, group_steps >= 1, max_reinit_iters >= 0");
-  size_t tot = align256(8 * (size_t)max_jobs) + align256(8 * 16);
+  size_t tot = align256(8 * (size_t)max_jobs) + align256(8 * STAT_WORDS);
   tot += group_table_bytes(max_jobs, group_steps, max_reinit_iters);
   *bytes = tot;
   return LSR_OK;
@@ -373,7 +373,7 @@ lsr_status lsr_batch_create(int32_t max_jobs, int32_t group_steps, int32_t max_r
   b->scratch_cnt = (int32_t*)(b->ws + off);
   off = align256(off + 8 * (size_t)max_jobs);
   b->scratch_stats = (unsigned long long*)(b->ws + off);
-  off = align256(off + 8 * 16);
+  off = align256(off + 8 * STAT_WORDS);
   b->table_off = off;
   b->table_bytes = ws_bytes - off;
   b->group_steps = group_steps;

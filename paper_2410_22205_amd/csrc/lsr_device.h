@@ -287,8 +287,9 @@ struct GlobalSrc {
   gptr<T> A;
   const DevGrid& g;
   T e;
-  __device__ __forceinline__ T nb(uint32_t idx, int di, int dj, int dk) const {
-    return A[idx + (uint32_t)(di * (int)g.s0 + dj * (int)g.s1 + dk)];
+  // neighbour (di, dj, dk) of node idx if `inside` (on the grid), else the node
+  __device__ __forceinline__ T nb(uint32_t idx, bool inside, int di, int dj, int dk) const {
+    return A[inside ? idx + (uint32_t)(di * (int)g.s0 + dj * (int)g.s1 + dk) : idx];
   }
   __device__ __forceinline__ T foot3(const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) const {
     const GlobalRows<T> r{A, g.n0, g.n1, g.n2, g.s0, g.s1};
@@ -332,16 +333,17 @@ __device__ __forceinline__ T sl_update_src(const S& src, const DevGrid& g, const
                                            typename Vec<T>::p4 dp, int sub, int& flags) {
   constexpr int FP = DIM == 3 ? 4 : 2;  // foot points per node
   T gx, gy, gz = T(0);
-  T xm = i > 0 ? src.nb(idx, -1, 0, 0) : v, xp = i < g.n0 - 1 ? src.nb(idx, 1, 0, 0) : v;
-  T ym = j > 0 ? src.nb(idx, 0, -1, 0) : v, yp = j < g.n1 - 1 ? src.nb(idx, 0, 1, 0) : v;
-  gx = cdiff(xm, v, xp, i, g.n0, c);
-  gy = cdiff(ym, v, yp, j, g.n1, c);
+  // neighbours off the grid read the node itself (the value v)
+  T xm = src.nb(idx, i > 0, -1, 0, 0), xp = src.nb(idx, i < g.n0 - 1, 1, 0, 0);
+  T ym = src.nb(idx, j > 0, 0, -1, 0), yp = src.nb(idx, j < g.n1 - 1, 0, 1, 0);
   T zm = v, zp = v;
   if (DIM == 3) {
-    zm = k > 0 ? src.nb(idx, 0, 0, -1) : v;
-    zp = k < g.n2 - 1 ? src.nb(idx, 0, 0, 1) : v;
-    gz = cdiff(zm, v, zp, k, g.n2, c);
+    zm = src.nb(idx, k > 0, 0, 0, -1);
+    zp = src.nb(idx, k < g.n2 - 1, 0, 0, 1);
   }
+  gx = cdiff(xm, v, xp, i, g.n0, c);
+  gy = cdiff(ym, v, yp, j, g.n1, c);
+  if (DIM == 3) gz = cdiff(zm, v, zp, k, g.n2, c);
   T nrm = sqrt(gx * gx + gy * gy + gz * gz);
   T out;
   if (nrm < c.grad_thr) {

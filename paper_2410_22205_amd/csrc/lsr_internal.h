@@ -10,6 +10,15 @@
 
 namespace lsr {
 
+// Work statistics: each counter is spread over STAT_SLOTS slots a cache line
+// apart (a block adds to slot blockIdx % STAT_SLOTS), so that the blocks of a
+// launch do not all meet at one address; readers sum the slots.
+constexpr int STAT_COUNTERS = 8, STAT_SLOTS = 64, STAT_STRIDE = 16;  // stride in 8-byte words
+constexpr size_t STAT_WORDS = (size_t)STAT_COUNTERS * STAT_SLOTS * STAT_STRIDE;
+__host__ __device__ inline size_t stat_index(int counter, int slot) {
+  return ((size_t)counter * STAT_SLOTS + (size_t)slot) * STAT_STRIDE;
+}
+
 // Cloud bins: cubes of BIN_W nodes per side.
 constexpr int BIN_W = 4;
 

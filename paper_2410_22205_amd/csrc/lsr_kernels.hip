@@ -77,11 +77,12 @@ __device__ __forceinline__ void block_append1(bool pred, uint32_t val, gwptr<uin
   block_append<1>(p, v, out, counter, lds);
 }
 
-// Block-wide sum of up to three wave-uniform counts, one atomic per nonzero
-// total.  lds holds at least 12 uints.
+// Block-wide sum of up to three wave-uniform counts added to work counters
+// ca, cb, cc (-1: none) of the statistics array, one atomic per nonzero total,
+// in this block's slot.  lds holds at least 12 uints.
 __device__ __forceinline__ void block_add3(uint32_t a, uint32_t b, uint32_t c,
-                                           unsigned long long* pa, unsigned long long* pb,
-                                           unsigned long long* pc, uint32_t* lds) {
+                                           unsigned long long* stats, int ca, int cb, int cc,
+                                           uint32_t* lds) {
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if (lane_id() == 0) {
@@ -94,9 +95,10 @@ __device__ __forceinline__ void block_add3(uint32_t a, uint32_t b, uint32_t c,
     uint32_t t[3] = {0, 0, 0};
     for (int q = 0; q < 4; ++q)
       for (int r = 0; r < 3; ++r) t[r] += lds[3 * q + r];
-    if (t[0] && pa) atomicAdd(pa, (unsigned long long)t[0]);
-    if (t[1] && pb) atomicAdd(pb, (unsigned long long)t[1]);
-    if (t[2] && pc) atomicAdd(pc, (unsigned long long)t[2]);
+    const int slot = (int)(blockIdx.x % STAT_SLOTS);
+    const int cs[3] = {ca, cb, cc};
+    for (int r = 0; r < 3; ++r)
+      if (t[r] && cs[r] >= 0) atomicAdd(&stats[stat_index(cs[r], slot)], (unsigned long long)t[r]);
   }
 }
 
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
     if (base >= (uint32_t)n) break;
     sl_chunk<DIM, INTERP, T, LANES>(a, base, n, lds_app, nupd, nfb, nfr);
   }
-  block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
+  block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
 }
 
 // A table entry read with scalar loads into scalar registers, as kernel
@@ -351,7 +353,8 @@ struct StagedSrc {
   int oi, oj, ok;
   int tn;  // tile index of the node
   GlobalSrc<3, INTERP, T> glob;
-  __device__ __forceinline__ T nb(uint32_t, int di, int dj, int dk) const {
+  // the tile holds the clamped values: off the grid it reads the node itself
+  __device__ __forceinline__ T nb(uint32_t, bool, int di, int dj, int dk) const {
     return tile[tn + (di * RJ + dj) * RK + dk];
   }
   __device__ __forceinline__ T foot3(const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) const {
@@ -461,7 +464,7 @@ __global__ __launch_bounds__(256) void k_sl_step_staged(SLArgs<T> a) {
     nfb += wave_count(fl & UPD_FALLBACK);
     nfr += wave_count(fl & UPD_FRAME0);
   }
-  block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
+  block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
 }
 
 // Bricks holding a node of the list L (each once: per-brick stamps).
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restri
   JobCursor cur{n};
   auto leave = [&](int jb) {
     const SLArgs<T> a = uniform_load(tab, jb);
-    block_add3(nupd, nfb, nfr, &a.stats[0], &a.stats[1], &a.stats[2], lds_st);
+    block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
     nupd = nfb = nfr = 0;
   };
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
@@ -665,13 +668,14 @@ __device__ __forceinline__ void fix_chunk(const RArgs<T>& a, uint32_t base, int 
     int i, j, k;
     decode(a.g, M[e], i, j, k);
     const uint32_t idx = lin(a.g, i, j, k);
+    // neighbours off the grid read the node itself
     const T t = src[idx];
-    const T xm = i > 0 ? src[idx - a.g.s0] : t, xp = i < a.g.n0 - 1 ? src[idx + a.g.s0] : t;
-    const T ym = j > 0 ? src[idx - a.g.s1] : t, yp = j < a.g.n1 - 1 ? src[idx + a.g.s1] : t;
+    const T xm = src[i > 0 ? idx - a.g.s0 : idx], xp = src[i < a.g.n0 - 1 ? idx + a.g.s0 : idx];
+    const T ym = src[j > 0 ? idx - a.g.s1 : idx], yp = src[j < a.g.n1 - 1 ? idx + a.g.s1 : idx];
     T zm = t, zp = t;
     if (DIM == 3) {
-      zm = k > 0 ? src[idx - 1] : t;
-      zp = k < a.g.n2 - 1 ? src[idx + 1] : t;
+      zm = src[k > 0 ? idx - 1 : idx];
+      zp = src[k < a.g.n2 - 1 ? idx + 1 : idx];
     }
     const T z0 = T(0);
     itf = (i > 0 && t * xm <= z0) || (i < a.g.n0 - 1 && t * xp <= z0) ||
@@ -703,7 +707,7 @@ __global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
     if (base >= (uint32_t)n) break;
     fix_chunk<DIM, T>(a, base, n, ng, nif);
   }
-  block_add3(ng, nif, 0, &a.stats[4], &a.stats[5], nullptr, lds_st);
+  block_add3(ng, nif, 0, a.stats, 4, 5, -1, lds_st);
 }
 
 template <int DIM, typename T>
@@ -714,7 +718,7 @@ __global__ __launch_bounds__(256) void k_reinit_fix_batch(const RArgs<T>* __rest
   JobCursor cur{n};
   auto leave = [&](int jb) {
     const RArgs<T> a = uniform_load(tab, jb);
-    block_add3(ng, nif, 0, &a.stats[4], &a.stats[5], nullptr, lds_st);
+    block_add3(ng, nif, 0, a.stats, 4, 5, -1, lds_st);
     ng = nif = 0;
   };
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
@@ -749,8 +753,10 @@ __device__ __forceinline__ void iter_chunk(const RArgs<T>& a, uint32_t base, int
       const int ci = ax == 0 ? i : (ax == 1 ? j : k);
       const int nn = ax == 0 ? a.g.n0 : (ax == 1 ? a.g.n1 : a.g.n2);
       const uint32_t s = ax == 0 ? a.g.s0 : (ax == 1 ? a.g.s1 : 1u);
-      const T Dm = ci > 0 ? (v - src[idx - s]) * a.c.inv_h : z0;
-      const T Dp = ci < nn - 1 ? (src[idx + s] - v) * a.c.inv_h : z0;
+      // a neighbour off the grid reads the node: zero difference
+      const T vm = src[ci > 0 ? idx - s : idx], vp = src[ci < nn - 1 ? idx + s : idx];
+      const T Dm = (v - vm) * a.c.inv_h;
+      const T Dp = (vp - v) * a.c.inv_h;
       T t1, t2;
       if (pos) {
         t1 = Dm > z0 ? Dm * Dm : z0;
