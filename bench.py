@@ -76,26 +76,34 @@ def read_traffic(workload, precision):
         return None
 
 
-def cpu_baseline(w, n_steps):
-    import numpy as np  # noqa: F401
+def cpu_baseline(w, min_seconds=10.0):
+    """The oracle on the same workload: whole jobs (distance field, phi0, all
+    steps), repeated until at least min_seconds have passed."""
     import oracle
     g = w["grid"]
     prm = oracle.default_params(g["dim"], g["h"], gamma=w["gamma"], beta=w["beta"],
                                 reinit_every=w["reinit_every"])
-    d = oracle.distance(w["points"], g)
-    phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
-    oracle.run(phi0, d, g, prm, w["dt"], w["interp"], 1)  # load the library, touch memory
+    oracle.run(oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"]),
+               oracle.distance(w["points"], g), g, prm, w["dt"], w["interp"], 1)  # warm-up
+    jobs, updates = 0, 0
     t0 = time.perf_counter()
-    _, counts = oracle.run(phi0, d, g, prm, w["dt"], w["interp"], n_steps)
-    dt = time.perf_counter() - t0
+    while True:
+        d = oracle.distance(w["points"], g)
+        phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
+        _, counts = oracle.run(phi0, d, g, prm, w["dt"], w["interp"], w["steps"])
+        jobs += 1
+        updates += int(counts[0])
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    return {"value": counts[0] / dt, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
-            "sample": (f"first {n_steps} steps of the same run from phi0 ({int(counts[0])} node "
-                       f"updates, {int(counts[3])} reinitialisations), FP64, {dt:.1f} s wall; "
-                       f"distance field not timed")}
+    return {"value": updates / dt, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "jobs_per_s": jobs / dt,
+            "sample": (f"{jobs} whole job(s) of the same workload (distance field, phi0, "
+                       f"{w['steps']} steps; {updates} node updates), FP64, {dt:.1f} s wall")}
 
 
-def run_batched(n_jobs, steps, precision):
+def run_batched(n_jobs, steps, precision, graphs=True):
     """The batched workload: independent jobs with uneven grids (64^3-192^3),
     clouds of 5k-150k points, Q1 and WENO alternating, `steps` steps each;
     one after the other as plain solves, then all in one batch (loads on
@@ -110,10 +118,14 @@ def run_batched(n_jobs, steps, precision):
            for w in jobs]
     kinds = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}
 
+    seq_stream = torch.cuda.Stream()  # streams of their own: step loops run as graphs
+
     def make(w):
-        return lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"],
-                                       reinit_every=w["reinit_every"], precision=precision),
-                       max_points=len(w["points"]))
+        job = lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"],
+                                      reinit_every=w["reinit_every"], precision=precision),
+                      max_points=len(w["points"]), stream=seq_stream)
+        job.set_graphs(graphs)
+        return job
 
     def load(job, w, p):
         lsr.lsr_load_cloud(job.handle, p.data_ptr(), p.shape[0])
@@ -129,13 +141,14 @@ def run_batched(n_jobs, steps, precision):
     upd = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for w, p in zip(jobs, pts):
-        job = make(w)
-        load(job, w, p)
-        lsr.lsr_step(job.handle, w["steps"], w["dt"], lsr.interp_code(w["interp"]))
-        extract(job)
-        upd += lsr.lsr_counters(job.handle)["node_updates"]
-        job.close()
+    with torch.cuda.stream(seq_stream):
+        for w, p in zip(jobs, pts):
+            job = make(w)
+            load(job, w, p)
+            lsr.lsr_step(job.handle, w["steps"], w["dt"], lsr.interp_code(w["interp"]))
+            extract(job)
+            upd += lsr.lsr_counters(job.handle)["node_updates"]
+            job.close()
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     # all in one batch; the jobs load (distance field, phi0) on four side
@@ -148,7 +161,8 @@ def run_batched(n_jobs, steps, precision):
                                                    reinit_every=w["reinit_every"],
                                                    precision=precision),
                                    max_points=len(w["points"]), stream=streams[k % 4]))
-    batch = lsr.Batch(max_jobs=n_jobs, group_steps=10)
+    batch = lsr.Batch(max_jobs=n_jobs, group_steps=10, stream=torch.cuda.Stream())
+    batch.set_graphs(graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for job, w, p in zip(handles, jobs, pts):
@@ -157,6 +171,7 @@ def run_batched(n_jobs, steps, precision):
         batch.add(job, w["dt"], w["interp"])
     lanes, bpc, _ = batch.tune()
     batch.step(steps)
+    graphs = batch.graph_counts()
     for job in list(handles):
         batch.remove(job)
         extract(job)
@@ -171,22 +186,23 @@ def run_batched(n_jobs, steps, precision):
                         f"{steps} steps each, dt = h/2, reinit every 10",
             "jobs_per_s": n_jobs / t_bat, "sequential_jobs_per_s": n_jobs / t_seq,
             "speedup": t_seq / t_bat, "node_updates_per_s": upd / t_bat,
-            "sequential_node_updates_per_s": upd / t_seq, "tuned": {"lanes": lanes,
-                                                                    "blocks_per_cu": bpc}}
+            "sequential_node_updates_per_s": upd / t_seq,
+            "tuned": {"lanes": lanes, "blocks_per_cu": bpc},
+            "group_graphs": dict(zip(("recorded", "replays"), graphs))}
 
 
-def run_served(n_jobs, precision):
+def run_served(n_jobs, precision, graphs=True):
     """The served workload: a Poisson stream at 20 requests/s of jobs with
     grids 64^3-320^3, 5k-1M points, 200-400 WENO steps, served with
     continuous batching; then the same stream as plain solves one at a time.
     Latency = completion - arrival."""
     from paper_2410_22205_amd import serve, synth
     reqs = serve.materialise(synth.served_jobs(n_jobs=n_jobs))
-    srv = serve.Server(precision=precision)
+    srv = serve.Server(precision=precision, graphs=graphs)
     warm = serve.materialise(synth.served_jobs(n_jobs=2, seed=77))
     srv.run([dict(r, arrival=0.0) for r in warm])
     out = srv.run(reqs)
-    seq = serve.run_sequential(reqs, precision=precision)
+    seq = serve.run_sequential(reqs, precision=precision, graphs=graphs)
     return {"workload": f"{n_jobs} requests, Poisson 20/s, grids 64^3-320^3, 5k-1M points, "
                         "WENO, 200-400 steps",
             "jobs_per_s": out["jobs_per_s"], "latency_ms": out["latency_ms"],
@@ -221,8 +237,10 @@ def main():
                     help="step kernel: 0 brick-staged (3D), 1 one lane per node, 4 (2 in 2D) one "
                          "lane per foot point; -1 the library default")
     ap.add_argument("--blocks-per-cu", type=int, default=8)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="least wall time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch-jobs", type=int, default=64, help="batched section (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -247,17 +265,21 @@ def main():
     dim = g["dim"]
     prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
                precision=args.precision)
-    job = lsr.Job(g, prm, max_points=len(w["points"]))
+    # a stream of its own: step loops on the null stream cannot run as graphs
+    job = lsr.Job(g, prm, max_points=len(w["points"]), stream=torch.cuda.Stream())
     if args.lanes >= 0 or args.blocks_per_cu != 8:
         lsr.lsr_set_launch(job.handle, args.lanes if args.lanes >= 0 else DEFAULT_LANES[dim],
                            args.blocks_per_cu)
     lanes = args.lanes if args.lanes >= 0 else DEFAULT_LANES[dim]
+    if args.no_graphs:
+        job.set_graphs(False)
     stream = job.stream
     pts = torch.as_tensor(w["points"], dtype=torch.float64, device="cuda").contiguous()
     phi_out = torch.empty(job.nodes, dtype=job.dtype, device="cuda")
     band_out = torch.empty(job.nodes, dtype=torch.uint8, device="cuda")
     kind = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}[w["phi0"][0]]
     interp = lsr.interp_code(w["interp"])
+    torch.cuda.synchronize()  # inputs uploaded on torch's stream before the job's stream reads them
 
     def one_job():
         lsr.lsr_load_cloud(job.handle, pts.data_ptr(), pts.shape[0])
@@ -265,6 +287,9 @@ def main():
         lsr.lsr_step(job.handle, w["steps"], w["dt"], interp)
         lsr.lsr_extract(job.handle, phi_out.data_ptr(), band_out.data_ptr(), want_count=False)
 
+    # timing on during warm-up too, so that the step graphs recorded there are
+    # the timed ones the measured jobs replay; re-enabling clears the records
+    lsr.lsr_profile_enable(job.handle, True, w["steps"] * args.steps + 8)
     for _ in range(args.warmup):
         one_job()
     stream.synchronize()
@@ -302,7 +327,8 @@ def main():
                 "flops_per_node_update": flops,
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
                 "node_updates_per_launch": round(upd_per_launch, 1),
-                "lanes": lanes, "staged": lanes == 0, "blocks_per_cu": args.blocks_per_cu}
+                "lanes": lanes, "staged": lanes == 0, "blocks_per_cu": args.blocks_per_cu,
+                "step_graphs": dict(zip(("recorded", "replays"), job.graph_counts()))}
     hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in lat)
     out = {
@@ -334,11 +360,12 @@ def main():
     }
     job.close()
     if args.batch_jobs:
-        out["batched"] = run_batched(args.batch_jobs, args.batch_steps, args.precision)
+        out["batched"] = run_batched(args.batch_jobs, args.batch_steps, args.precision,
+                                     graphs=not args.no_graphs)
     if args.served_jobs:
-        out["served"] = run_served(args.served_jobs, args.precision)
+        out["served"] = run_served(args.served_jobs, args.precision, graphs=not args.no_graphs)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
     print(json.dumps(out))
 

@@ -194,6 +194,10 @@ lsr_status lsr_destroy(lsr_job* job);
  * stream is ordered after the batch's queued work.
  * lsr_batch_step: n_steps steps of every member (uploads one table per group).
  * lsr_batch_set_launch: launch shape as in lsr_set_launch.
+ * lsr_batch_set_graphs: 1 (default) records a group of steps whose launch
+ * sequence was seen before (same members, phases and launch shape) as a HIP
+ * graph and replays it for later such groups; 0 launches every kernel
+ * directly.  Results are the same either way.  Synchronises the stream.
  * lsr_batch_tune: times the next step under each candidate launch shape
  * (lanes per node, blocks per CU) without changing the jobs, keeps the
  * fastest and returns it with its time in ms (synchronises).
@@ -207,20 +211,40 @@ lsr_status lsr_batch_add(lsr_batch* batch, lsr_job* job, double dt, lsr_interp i
 lsr_status lsr_batch_remove(lsr_batch* batch, lsr_job* job);
 lsr_status lsr_batch_step(lsr_batch* batch, int32_t n_steps);
 lsr_status lsr_batch_set_launch(lsr_batch* batch, int32_t lanes, int32_t blocks_per_cu);
+lsr_status lsr_batch_set_graphs(lsr_batch* batch, int32_t enable);
 lsr_status lsr_batch_tune(lsr_batch* batch, int32_t* lanes, int32_t* blocks_per_cu, double* ms);
 lsr_status lsr_batch_destroy(lsr_batch* batch);
 
 /* Launch shape of the list kernels (results are bitwise the same for every
- * shape): lanes = 1 (one lane per band node) or the number of foot points
- * per node (2 in 2D, 4 in 3D: one lane per foot point); blocks_per_cu in
- * 1..64 bounds the persistent grid, which never exceeds the blocks of the
- * kernel that fit on the device at once.  Defaults: 1 lane, 8. */
+ * shape): lanes = 1 (one lane per band node), the number of foot points per
+ * node (2 in 2D, 4 in 3D: one lane per foot point), or, in 3D only, 0: the
+ * step kernel works brick by brick (4 x 8 x 8 nodes) with the brick and a
+ * halo of phi staged in LDS, and falls back to device-memory reads for foot
+ * points beyond the halo.  blocks_per_cu in 1..64 bounds the persistent grid,
+ * which never exceeds the blocks of the kernel that fit on the device at
+ * once.  Defaults: 1 lane, 8. */
 lsr_status lsr_set_launch(lsr_job* job, int32_t lanes, int32_t blocks_per_cu);
+
+/* Step loops as HIP graphs.  With enable = 1 (the default) lsr_step runs
+ * whole chunks of 2 * reinit_every steps (16 without reinitialisation)
+ * through recorded graphs: a chunk is recorded the second time the job
+ * starts one in the same state (buffer roles, counter slots, phase in the
+ * reinitialisation period, dt, interpolator, launch shape) and replayed after
+ * that; the remaining steps, the staged kernel (lanes = 0) and jobs on the
+ * null stream launch directly.  Results are the same either way.
+ * Synchronises the stream and drops the recorded graphs. */
+lsr_status lsr_set_graphs(lsr_job* job, int32_t enable);
+
+/* Graphs recorded and replayed so far by a job's lsr_step or a batch's
+ * lsr_batch_step (exactly one of job, batch non-NULL), into host memory. */
+lsr_status lsr_graph_counts(lsr_job* job, lsr_batch* batch, int64_t* captured, int64_t* replayed);
 
 /* Measurement hook.  While enabled, every semi-Lagrangian step kernel the job
  * launches is bracketed by a pair of HIP events recorded on the job's stream
- * (at most max_launches pairs; later launches are not recorded).  Enabling
- * clears earlier records.  lsr_profile_read synchronises the stream and
+ * (at most max_launches pairs for direct launches, later ones are not
+ * recorded; in a step graph the pairs are event-record nodes of the graph,
+ * all of them recorded; graphs recorded while timing is on are kept for later
+ * timed runs).  Enabling or disabling clears earlier records.  lsr_profile_read synchronises the stream and
  * returns the summed kernel time in milliseconds and the number of recorded
  * launches. */
 lsr_status lsr_profile_enable(lsr_job* job, int32_t enable, int32_t max_launches);

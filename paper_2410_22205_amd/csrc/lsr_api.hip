@@ -122,22 +122,23 @@ lsr_status check_params(const lsr_grid* g, const lsr_params* p) {
 namespace lsr {
 
 template <typename T>
-static lsr_status launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
+static hipError_t launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
   hipStream_t s = j->stream;
   const int dim = j->grid.dim;
-  LSR_HIP(launch_gbar_scan<T>(dim, r.gb, j->list_blocks, s));
-  LSR_HIP(launch_reinit_fix<T>(dim, r.fix, j->list_blocks, s));
-  for (int it = 0; it < r.iters; ++it)
-    LSR_HIP(launch_reinit_iter<T>(dim, r.iter[it % 2], j->list_blocks, s));
-  LSR_HIP(launch_reinit_final<T>(r.fin, j->list_blocks, s));
-  return LSR_OK;
+  hipError_t e = launch_gbar_scan<T>(dim, r.gb, j->list_blocks, s);
+  if (e == hipSuccess) e = launch_reinit_fix<T>(dim, r.fix, j->list_blocks, s);
+  for (int it = 0; it < r.iters && e == hipSuccess; ++it)
+    e = launch_reinit_iter<T>(dim, r.iter[it % 2], j->list_blocks, s);
+  if (e == hipSuccess) e = launch_reinit_final<T>(r.fin, j->list_blocks, s);
+  return e;
 }
 
 template <typename T>
 static lsr_status run_reinit_t(lsr_job* j) {
   ReinitPlan<T> r = plan_reinit<T>(j);
   j->bricks_valid = false;
-  return launch_reinit_plan<T>(j, r);
+  LSR_HIP(launch_reinit_plan<T>(j, r));
+  return LSR_OK;
 }
 
 // Brick list of the current node list (before a staged step that follows a
@@ -156,10 +157,76 @@ static lsr_status rebuild_bricks(lsr_job* j) {
   return LSR_OK;
 }
 
+// n steps of the node-list kernel, each followed by the reinitialisation
+// when due, from the current plan state, which they advance.  With launch
+// false nothing is launched (the state of a replayed graph); `timed` holds
+// one start/stop event pair per step, recorded as record_timed's `mode`.
 template <typename T>
-static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp) {
+static hipError_t issue_steps(lsr_job* j, int32_t n, const StepConst<T>& c, int interp,
+                              bool launch, std::vector<hipEvent_t>* timed, int mode) {
   hipStream_t s = j->stream;
-  const StepConst<T> c = step_const<T>(j, dt);
+  hipError_t e = hipSuccess;
+  for (int32_t q = 0; q < n && e == hipSuccess; ++q) {
+    SLArgs<T> a = plan_step<T>(j, c);
+    if (launch) {
+      if (timed) e = record_timed((*timed)[2 * q], s, mode);
+      if (e == hipSuccess) e = launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s);
+      if (timed && e == hipSuccess) e = record_timed((*timed)[2 * q + 1], s, mode);
+    }
+    if (reinit_due(j)) {
+      ReinitPlan<T> r = plan_reinit<T>(j);
+      if (launch && e == hipSuccess) e = launch_reinit_plan<T>(j, r);
+    }
+  }
+  j->bricks_valid = false;
+  return e;
+}
+
+struct PlanState {
+  int cur, cur_list, cur_blist, ring;
+  int64_t step_index, n_reinits, n_steps;
+  bool bricks_valid;
+};
+
+static PlanState save_plan(const lsr_job* j) {
+  return {j->cur, j->cur_list, j->cur_blist, j->ring, j->step_index, j->n_reinits, j->n_steps,
+          j->bricks_valid};
+}
+
+static void restore_plan(lsr_job* j, const PlanState& p) {
+  j->cur = p.cur;
+  j->cur_list = p.cur_list;
+  j->cur_blist = p.cur_blist;
+  j->ring = p.ring;
+  j->step_index = p.step_index;
+  j->n_reinits = p.n_reinits;
+  j->n_steps = p.n_steps;
+  j->bricks_valid = p.bricks_valid;
+}
+
+// Steps between two graph keys: twice the reinitialisation period, after
+// which buffers, lists and counter slots are back in their roles (a step
+// swaps phi and the lists and moves the counter ring by one; a
+// reinitialisation moves the ring by two and swaps phi when its iteration
+// count is even).
+static int32_t graph_chunk(const lsr_job* j) {
+  return j->prm.reinit_every > 0 ? 2 * j->prm.reinit_every : 16;
+}
+
+template <typename T>
+static std::vector<int64_t> graph_key(const lsr_job* j, int32_t n, double dt, int interp) {
+  int64_t dtb;
+  memcpy(&dtb, &dt, sizeof dtb);
+  const int64_t K = j->prm.reinit_every;
+  return {(int64_t)sizeof(T), j->cur, j->cur_list, j->cur_blist, j->ring,
+          K > 0 ? j->step_index % K : 0, n, dtb, interp, j->lanes, (int64_t)j->list_blocks,
+          j->prof_on ? 1 : 0};
+}
+
+// Steps launched one by one (timed through the job's own events).
+template <typename T>
+static lsr_status direct_steps(lsr_job* j, int32_t n_steps, const StepConst<T>& c, int interp) {
+  hipStream_t s = j->stream;
   const bool staged = j->lanes == 0;
   for (int32_t q = 0; q < n_steps; ++q) {
     if (staged && !j->bricks_valid) {
@@ -185,6 +252,58 @@ static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp
     }
   }
   return LSR_OK;
+}
+
+template <typename T>
+static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp) {
+  hipStream_t s = j->stream;
+  const StepConst<T> c = step_const<T>(j, dt);
+  // whole chunks through recorded graphs (node-list kernel only; never on the
+  // null stream, which cannot be captured)
+  const int32_t chunk = graph_chunk(j);
+  GraphCache& G = j->graphs;
+  while (j->lanes != 0 && G.enabled && s != nullptr && n_steps >= chunk &&
+         !(j->prof_on && G.event_mode == 0)) {
+    const std::vector<int64_t> key = graph_key<T>(j, chunk, dt, interp);
+    GraphCache::Entry* g = G.find(key);
+    bool direct = false;
+    if (g) {
+      (void)issue_steps<T>(j, chunk, c, interp, false, nullptr, 0);
+      LSR_HIP(G.replay(*g, s));
+    } else if (G.seen_before(key)) {
+      const PlanState p0 = save_plan(j);
+      const bool timed = j->prof_on;
+      bool launched = false;
+      hipError_t e = G.capture_and_launch(
+          s, key, timed ? chunk : 0,
+          [&](std::vector<hipEvent_t>& ev) {
+            return issue_steps<T>(j, chunk, c, interp, true, timed ? &ev : nullptr,
+                                  G.event_mode);
+          },
+          &launched);
+      if (e != hipSuccess && launched) LSR_HIP(e);
+      if (e != hipSuccess) {
+        // nothing ran: this chunk launches directly; a capture with timing
+        // tries the next way of timing, one without gives up graphs
+        (void)hipGetLastError();
+        restore_plan(j, p0);
+        if (timed)
+          G.event_mode -= 1;
+        else
+          G.enabled = false;
+        (void)fail(LSR_OK, "step graph not recorded (" + G.failure + "); launching directly");
+        direct = true;
+      }
+    } else {
+      direct = true;  // first sight of this key
+    }
+    if (direct) {
+      lsr_status st = direct_steps<T>(j, chunk, c, interp);
+      if (st != LSR_OK) return st;
+    }
+    n_steps -= chunk;
+  }
+  return direct_steps<T>(j, n_steps, c, interp);
 }
 
 lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp) {
@@ -484,6 +603,7 @@ lsr_status lsr_init_phi(lsr_job* j, const void* dev_phi0, int32_t kind, const do
                                             j->list[0], j->cnt, s));
   j->cur = 0;
   j->cur_list = 0;
+  j->cur_blist = 0;
   j->ring = 0;
   j->step_index = step0;
   j->n_reinits = 0;
@@ -576,6 +696,19 @@ lsr_status lsr_set_launch(lsr_job* j, int32_t lanes, int32_t blocks_per_cu) {
   return LSR_OK;
 }
 
+lsr_status lsr_set_graphs(lsr_job* j, int32_t enable) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  LSR_HIP(hipStreamSynchronize(j->stream));
+  LSR_HIP(j->graphs.collect_all());
+  const double ms = j->graphs.timed_ms;
+  const int64_t n = j->graphs.timed_n;
+  j->graphs.clear();
+  j->graphs.timed_ms = ms;  // timed launches so far still count
+  j->graphs.timed_n = n;
+  j->graphs.enabled = enable != 0;
+  return LSR_OK;
+}
+
 lsr_status lsr_profile_enable(lsr_job* j, int32_t enable, int32_t max_launches) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
   if (enable && max_launches < 1) return fail(LSR_E_INVALID, "max_launches must be >= 1");
@@ -584,6 +717,7 @@ lsr_status lsr_profile_enable(lsr_job* j, int32_t enable, int32_t max_launches) 
   j->prof_ev.clear();
   j->prof_used = 0;
   j->prof_on = false;
+  j->graphs.reset_timed();
   if (!enable) return LSR_OK;
   j->prof_ev.resize(2 * (size_t)max_launches, nullptr);
   for (auto& e : j->prof_ev) LSR_HIP(hipEventCreate(&e));
@@ -594,14 +728,15 @@ lsr_status lsr_profile_enable(lsr_job* j, int32_t enable, int32_t max_launches) 
 lsr_status lsr_profile_read(lsr_job* j, double* total_ms, int64_t* launches) {
   if (!j || !total_ms || !launches) return fail(LSR_E_INVALID, "NULL argument");
   LSR_HIP(hipStreamSynchronize(j->stream));
-  double tot = 0.0;
+  LSR_HIP(j->graphs.collect_all());
+  double tot = j->graphs.timed_ms;
   for (int q = 0; q < j->prof_used; ++q) {
     float ms = 0.0f;
     LSR_HIP(hipEventElapsedTime(&ms, j->prof_ev[2 * q], j->prof_ev[2 * q + 1]));
     tot += ms;
   }
   *total_ms = tot;
-  *launches = j->prof_used;
+  *launches = j->prof_used + j->graphs.timed_n;
   return LSR_OK;
 }
 
@@ -610,6 +745,7 @@ lsr_status lsr_destroy(lsr_job* j) {
   if (j->in_batch) return fail(LSR_E_STATE, "remove the job from its batch first");
   hipError_t e = hipStreamSynchronize(j->stream);
   for (hipEvent_t ev : j->prof_ev) (void)hipEventDestroy(ev);
+  j->graphs.clear();
   delete j;
   if (e != hipSuccess) return fail(LSR_E_DEVICE, hipGetErrorString(e));
   return LSR_OK;

@@ -49,16 +49,17 @@ struct lsr_batch {
   bool copy_pending;
   int lanes, bpc, ncu;
   unsigned blocks;
+  lsr::GraphCache graphs;  // recorded group launch sequences
 };
 
 namespace {
 
-// Upper bound of the tables of one group: per step a step table and its
-// interpolator codes, and at most one reinitialisation per job (dilation,
-// fix, max_iters iteration tables, final), each table 256-byte aligned; the
-// double-precision argument structs bound the single-precision ones.
-// The members are stepped in cache groups (see cache_groups), each with its
-// own tables, so the alignment padding is counted once per table per job.
+// Upper bound of the tables of one group: per step and cache group two step
+// tables (one per interpolator) and at most one reinitialisation per job
+// (Gbar scan, fix, max_iters iteration tables, final), each table 256-byte
+// aligned; the double-precision argument structs bound the single-precision
+// ones.  There are at most as many cache groups (see cache_groups) as jobs,
+// so the alignment padding is counted per job.
 size_t group_table_bytes(int n_jobs, int group_steps, int max_iters) {
   const size_t n = (size_t)n_jobs, a = 255;
   const size_t per_step = n * (sizeof(SLArgs<double>) + sizeof(GbarArgs<double>) +
@@ -159,32 +160,74 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
 }
 
 template <typename T>
-lsr_status issue(lsr_batch* b, const Builder<T>& B) {
+hipError_t issue(lsr_batch* b, const Builder<T>& B) {
   hipStream_t s = b->stream;
   char* dev = b->ws + b->table_off;
+  hipError_t e = hipSuccess;
   for (const Launch& L : B.launches) {
+    if (e != hipSuccess) break;
     switch (L.kind) {
       case 0:
-        LSR_HIP(launch_sl_step_batch<T>(b->dim, L.interp, b->lanes, (const SLArgs<T>*)(dev + L.off),
-                                        L.n, b->blocks, s));
+        e = launch_sl_step_batch<T>(b->dim, L.interp, b->lanes, (const SLArgs<T>*)(dev + L.off), L.n,
+                                    b->blocks, s);
         break;
       case 1:
-        LSR_HIP(launch_gbar_scan_batch<T>(b->dim, (const GbarArgs<T>*)(dev + L.off), L.n, b->blocks,
-                                          s));
+        e = launch_gbar_scan_batch<T>(b->dim, (const GbarArgs<T>*)(dev + L.off), L.n, b->blocks, s);
         break;
       case 2:
-        LSR_HIP(launch_reinit_fix_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n, b->blocks, s));
+        e = launch_reinit_fix_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n, b->blocks, s);
         break;
       case 3:
         if (L.n > 0)
-          LSR_HIP(launch_reinit_iter_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n,
-                                              b->blocks, s));
+          e = launch_reinit_iter_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n, b->blocks, s);
         break;
       case 4:
-        LSR_HIP(launch_reinit_final_batch<T>((const FinArgs<T>*)(dev + L.off), L.n, b->blocks, s));
+        e = launch_reinit_final_batch<T>((const FinArgs<T>*)(dev + L.off), L.n, b->blocks, s);
         break;
     }
   }
+  return e;
+}
+
+// A group's launches read their arguments from the tables at fixed offsets
+// of the workspace, so the launch sequence is fixed by the kinds, offsets and
+// job counts of its launches and the launch shape: groups with the same
+// sequence replay one recorded graph after their tables are copied.
+template <typename T>
+std::vector<int64_t> group_key(const lsr_batch* b, const Builder<T>& B) {
+  std::vector<int64_t> k = {(int64_t)sizeof(T), b->dim, b->lanes, (int64_t)b->blocks};
+  k.reserve(4 + 4 * B.launches.size());
+  for (const Launch& L : B.launches) {
+    k.push_back(L.kind);
+    k.push_back((int64_t)L.off);
+    k.push_back(L.n);
+    k.push_back(L.interp);
+  }
+  return k;
+}
+
+template <typename T>
+lsr_status launch_group(lsr_batch* b, const Builder<T>& B) {
+  hipStream_t s = b->stream;
+  if (b->graphs.enabled && s != nullptr) {
+    const std::vector<int64_t> key = group_key<T>(b, B);
+    GraphCache::Entry* g = b->graphs.find(key);
+    if (g) {
+      LSR_HIP(b->graphs.replay(*g, s));
+      return LSR_OK;
+    }
+    if (b->graphs.seen_before(key)) {
+      bool launched = false;
+      hipError_t e = b->graphs.capture_and_launch(
+          s, key, 0, [&](std::vector<hipEvent_t>&) { return issue<T>(b, B); }, &launched);
+      if (e == hipSuccess) return LSR_OK;
+      if (launched) LSR_HIP(e);
+      (void)hipGetLastError();
+      (void)fail(LSR_OK, "batch graph not recorded (" + b->graphs.failure + "); launching directly");
+      b->graphs.enabled = false;  // the stream cannot be captured: launch directly
+    }
+  }
+  LSR_HIP(issue<T>(b, B));
   return LSR_OK;
 }
 
@@ -224,7 +267,7 @@ lsr_status run_group(lsr_batch* b, int steps) {
   LSR_HIP(hipMemcpyAsync(b->ws + b->table_off, b->host, B.off, hipMemcpyHostToDevice, b->stream));
   LSR_HIP(hipEventRecord(b->copy_done, b->stream));
   b->copy_pending = true;
-  return issue<T>(b, B);
+  return launch_group<T>(b, B);
 }
 
 struct SavedState {
@@ -461,6 +504,23 @@ lsr_status lsr_batch_set_launch(lsr_batch* b, int32_t lanes, int32_t blocks_per_
   return LSR_OK;
 }
 
+lsr_status lsr_batch_set_graphs(lsr_batch* b, int32_t enable) {
+  if (!b) return fail(LSR_E_INVALID, "batch is NULL");
+  LSR_HIP(hipStreamSynchronize(b->stream));
+  b->graphs.clear();
+  b->graphs.enabled = enable != 0;
+  return LSR_OK;
+}
+
+lsr_status lsr_graph_counts(lsr_job* j, lsr_batch* b, int64_t* captured, int64_t* replayed) {
+  if ((j == nullptr) == (b == nullptr)) return fail(LSR_E_INVALID, "pass exactly one of job, batch");
+  if (!captured || !replayed) return fail(LSR_E_INVALID, "NULL argument");
+  const GraphCache& g = j ? j->graphs : b->graphs;
+  *captured = g.n_captured;
+  *replayed = g.n_replayed;
+  return LSR_OK;
+}
+
 lsr_status lsr_batch_tune(lsr_batch* b, int32_t* lanes, int32_t* blocks_per_cu, double* ms) {
   if (!b) return fail(LSR_E_INVALID, "batch is NULL");
   if (b->jobs.empty()) return fail(LSR_E_STATE, "the batch has no job");
@@ -483,6 +543,7 @@ lsr_status lsr_batch_destroy(lsr_batch* b) {
     if (st != LSR_OK) return st;
   }
   hipError_t e = hipStreamSynchronize(b->stream);
+  b->graphs.clear();
   (void)hipEventDestroy(b->copy_done);
   (void)hipHostFree(b->host);
   delete b;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/lsr.h"
+#include "lsr_graph.h"
 #include "lsr_internal.h"
 
 namespace lsr {
@@ -84,6 +85,7 @@ struct lsr_job {
   bool prof_on;
   int prof_used;
   std::vector<hipEvent_t> prof_ev;
+  lsr::GraphCache graphs;  // recorded step sequences (lsr_step)
 };
 
 namespace lsr {

@@ -28,7 +28,8 @@ EXPORTED = [
     "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
     "lsr_extract", "lsr_counters", "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
     "lsr_batch_add", "lsr_batch_remove", "lsr_batch_step", "lsr_batch_set_launch",
-    "lsr_batch_tune", "lsr_batch_destroy", "lsr_set_launch", "lsr_profile_enable",
+    "lsr_batch_tune", "lsr_batch_destroy", "lsr_batch_set_graphs", "lsr_set_launch",
+    "lsr_set_graphs", "lsr_graph_counts", "lsr_profile_enable",
     "lsr_profile_read", "lsr_last_error",
 ]
 
@@ -92,6 +93,9 @@ def load():
             "lsr_batch_destroy": [_P],
             "lsr_profile_enable": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_set_launch": [_P, ctypes.c_int32, ctypes.c_int32],
+            "lsr_set_graphs": [_P, ctypes.c_int32],
+            "lsr_batch_set_graphs": [_P, ctypes.c_int32],
+            "lsr_graph_counts": [_P, _P, I64P, I64P],
             "lsr_profile_read": [_P, ctypes.POINTER(ctypes.c_double), I64P],
         }
         for name, args in sig.items():
@@ -235,6 +239,21 @@ def lsr_set_launch(job, lanes, blocks_per_cu):
     _check(load().lsr_set_launch(job, int(lanes), int(blocks_per_cu)))
 
 
+def lsr_set_graphs(job, enable):
+    _check(load().lsr_set_graphs(job, int(bool(enable))))
+
+
+def lsr_batch_set_graphs(batch, enable):
+    _check(load().lsr_batch_set_graphs(batch, int(bool(enable))))
+
+
+def lsr_graph_counts(job=None, batch=None):
+    """(graphs recorded, graph replays) of a job's or a batch's step loop."""
+    c, r = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().lsr_graph_counts(job, batch, ctypes.byref(c), ctypes.byref(r)))
+    return c.value, r.value
+
+
 def lsr_profile_enable(job, enable, max_launches=4096):
     _check(load().lsr_profile_enable(job, int(bool(enable)), int(max_launches)))
 
@@ -337,6 +356,12 @@ class Job:
     def set_launch(self, lanes, blocks_per_cu=8):
         lsr_set_launch(self.handle, lanes, blocks_per_cu)
 
+    def set_graphs(self, enable):
+        lsr_set_graphs(self.handle, enable)
+
+    def graph_counts(self):
+        return lsr_graph_counts(job=self.handle)
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             lsr_destroy(self.handle)
@@ -378,6 +403,12 @@ class Batch:
 
     def set_launch(self, lanes, blocks_per_cu):
         lsr_batch_set_launch(self.handle, lanes, blocks_per_cu)
+
+    def set_graphs(self, enable):
+        lsr_batch_set_graphs(self.handle, enable)
+
+    def graph_counts(self):
+        return lsr_graph_counts(batch=self.handle)
 
     def tune(self):
         return lsr_batch_tune(self.handle)

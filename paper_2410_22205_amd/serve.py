@@ -128,13 +128,16 @@ class Server:
     work_budget: band nodes per step that the running jobs may add up to (a
     job joins when it fits, or when nothing is running); prefetch: jobs that
     may be loading or loaded ahead of joining;
-    precision: "fp32" | "fp64" (one per server: a batch has one precision)."""
+    precision: "fp32" | "fp64" (one per server: a batch has one precision);
+    graphs: replay recorded HIP graphs for repeated groups of batch steps."""
 
     def __init__(self, budget_bytes=None, max_active=64, group_steps=10, precision="fp32",
-                 load_streams=2, max_reinit_iters=32, work_budget=3_000_000, prefetch=3):
+                 load_streams=2, max_reinit_iters=32, work_budget=3_000_000, prefetch=3,
+                 graphs=True):
         import torch
         self.torch = torch
         self.precision = precision
+        self.graphs = graphs
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = int(0.8 * free)
@@ -190,6 +193,7 @@ class Server:
         adm = Admission(self.budget_bytes, self.max_active)
         batch = lsr.Batch(max_jobs=self.max_active, group_steps=self.group_steps,
                           max_reinit_iters=self.max_reinit_iters, stream=self.batch_stream)
+        batch.set_graphs(self.graphs)
         lives = {}
         pending = collections.deque(order)
         running = []
@@ -297,7 +301,7 @@ class Server:
         return out
 
 
-def run_sequential(requests, precision="fp32", time_scale=1.0, keep_results=False):
+def run_sequential(requests, precision="fp32", time_scale=1.0, keep_results=False, graphs=True):
     """The same stream served one plain solve at a time (no batching, no
     overlap): the reference the served form is compared with."""
     import torch
@@ -305,7 +309,7 @@ def run_sequential(requests, precision="fp32", time_scale=1.0, keep_results=Fals
     t0 = time.perf_counter()
     latency, results, done_at = {}, {}, {}
     first = None
-    s = torch.cuda.current_stream()
+    s = torch.cuda.Stream()  # not the null stream: step loops run as graphs
     for i in order:
         req = requests[i]
         arr = req["arrival"] * time_scale
@@ -313,17 +317,20 @@ def run_sequential(requests, precision="fp32", time_scale=1.0, keep_results=Fals
         wait = arr - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
-        job = lsr.Job(req["grid"], job_params(req, precision), max_points=len(req["points"]),
-                      stream=s)
-        pts = torch.as_tensor(np.ascontiguousarray(req["points"], dtype=np.float64),
-                              device=s.device)
-        lsr.lsr_load_cloud(job.handle, pts.data_ptr(), pts.shape[0])
-        kind = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}[req["phi0"][0]]
-        lsr.lsr_init_phi(job.handle, None, kind, list(req["phi0"][1]), 0)
-        lsr.lsr_step(job.handle, int(req["steps"]), req["dt"], lsr.interp_code(req["interp"]))
-        phi = torch.empty(job.nodes, dtype=job.dtype, device=s.device)
-        band = torch.empty(job.nodes, dtype=torch.uint8, device=s.device)
-        lsr.lsr_extract(job.handle, phi.data_ptr(), band.data_ptr(), want_count=False)
+        with torch.cuda.stream(s):
+            job = lsr.Job(req["grid"], job_params(req, precision),
+                          max_points=len(req["points"]), stream=s)
+            job.set_graphs(graphs)
+            pts = torch.as_tensor(np.ascontiguousarray(req["points"], dtype=np.float64),
+                                  device=s.device)
+            lsr.lsr_load_cloud(job.handle, pts.data_ptr(), pts.shape[0])
+            kind = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}[req["phi0"][0]]
+            lsr.lsr_init_phi(job.handle, None, kind, list(req["phi0"][1]), 0)
+            lsr.lsr_step(job.handle, int(req["steps"]), req["dt"],
+                         lsr.interp_code(req["interp"]))
+            phi = torch.empty(job.nodes, dtype=job.dtype, device=s.device)
+            band = torch.empty(job.nodes, dtype=torch.uint8, device=s.device)
+            lsr.lsr_extract(job.handle, phi.data_ptr(), band.data_ptr(), want_count=False)
         s.synchronize()
         done_at[i] = time.perf_counter() - t0
         latency[i] = done_at[i] - arr
