@@ -959,9 +959,12 @@ __device__ __forceinline__ void bin_box(const BinGeom& bg, uint32_t id, double l
 // 16^2 in 2D) per workgroup.  With c the brick centre, rho its half diagonal
 // and U = d(c), every node's nearest point lies within U + 2 rho of c; U is
 // found exactly from the occupied bins whose box can hold a point closer
-// than the best far-corner bound, then the nodes scan all points of the
-// occupied bins whose box meets the ball of radius U + 2 rho.  All distance
-// arithmetic in double.
+// than the best far-corner bound.  The occupied bins whose box meets the
+// ball of radius U + 2 rho are then visited nearest first, and a wave scans
+// a bin's points only if one of its nodes could still find a closer point
+// there.  The minimum is taken over exactly the pairs that can attain it,
+// so the result does not depend on the order.  All distance arithmetic in
+// double.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   // no FMA contraction: node coordinates lo + i h and the sums of squares are
@@ -1011,8 +1014,9 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   }
   ub2 = block_min(ub2, red) * slack;
 
-  // exact d(c)^2
+  // exact d(c)^2 and a point that attains it (the smallest index among ties)
   double best = INFINITY;
+  int bidx = -1;
   for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
     const uint32_t id = a.occ[t];
     double lo[3], hi[3];
@@ -1031,32 +1035,66 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
         const double t2 = a.pts[(int64_t)q * DIM + ax] - c[ax];
         s2 += t2 * t2;
       }
-      best = fmin(best, s2);
+      if (s2 < best) {
+        best = s2;
+        bidx = q;
+      }
     }
   }
-  best = block_min(best, red);
+  __shared__ int pstar;
+  if (threadIdx.x == 0) pstar = INT_MAX;
+  const double bmin = block_min(best, red);  // synchronises the block
+  if (bidx >= 0 && best == bmin) atomicMin(&pstar, bidx);
+  best = bmin;
   const double R = sqrt(best) + 2.0 * rho;
   const double R2 = R * R * slack;
 
-  // occupied bins whose box meets the ball (c, R)
+  // occupied bins whose box meets the ball (c, R), ordered by the box's
+  // distance from c in NSH shells (counting sort), so that the nodes meet
+  // close points first and can pass over the bins beyond their best
+  constexpr int NSH = 32;
+  __shared__ int shell_n[NSH], shell_at[NSH];
+  if (threadIdx.x < NSH) shell_n[threadIdx.x] = 0;
   if (threadIdx.x == 0) ncand = 0;
   __syncthreads();
-  for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
-    const uint32_t id = a.occ[t];
-    double lo[3], hi[3];
-    bin_box<DIM>(a.bg, id, lo, hi);
-    double s = 0.0;
+  // every occupied box lies at least d(c) - (box diagonal) from c
+  const double s0 = fmax(sqrt(best) - a.bg.bw * sqrt((double)DIM), 0.0);
+  const double shell_scale = NSH / fmax(R - s0, 1e-300);
+  auto shell_of = [&](double mind2) {
+    const int k = (int)((sqrt(mind2) - s0) * shell_scale);
+    return k < 0 ? 0 : (k > NSH - 1 ? NSH - 1 : k);
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
+      const uint32_t id = a.occ[t];
+      double lo[3], hi[3];
+      bin_box<DIM>(a.bg, id, lo, hi);
+      double s = 0.0;
 #pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) {
-      const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
-      s += q * q;
+      for (int ax = 0; ax < DIM; ++ax) {
+        const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
+        s += q * q;
+      }
+      if (s > R2) continue;
+      const int sh = shell_of(s);
+      if (pass == 0) {
+        atomicAdd(&shell_n[sh], 1);
+        atomicAdd(&ncand, 1);
+      } else {
+        const int pos = atomicAdd(&shell_at[sh], 1);
+        if (pos < CAP) cand[pos] = id;
+      }
     }
-    if (s <= R2) {
-      const int pos = atomicAdd(&ncand, 1);
-      if (pos < CAP) cand[pos] = id;
+    __syncthreads();
+    if (pass == 0 && threadIdx.x == 0) {
+      int run = 0;
+      for (int q = 0; q < NSH; ++q) {
+        shell_at[q] = run;
+        run += shell_n[q];
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   const int nc = ncand;
 
   double x[NPT][3], bn[NPT];
@@ -1074,17 +1112,30 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
     valid[u] = node[0] <= l[0] && node[1] <= l[1] && node[2] <= l[2];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) x[u][ax] = ax < DIM ? glo[ax] + node[ax] * g.hd : 0.0;
+    // start from the distance to the centre's nearest point, one of the
+    // pairs the minimum runs over
     bn[u] = INFINITY;
+    if (pstar != INT_MAX) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        const double t2 = x[u][ax] - a.pts[(int64_t)pstar * DIM + ax];
+        s2 += t2 * t2;
+      }
+      bn[u] = s2;
+    }
   }
+  // A wave passes over a bin when none of its nodes can find a closer point
+  // in it: the box, widened by a margin that covers the rounding of the
+  // binning, lies farther than every node's best so far.
+  const double margin = 1e-12 * a.bg.bw;
   const int nloop = nc <= CAP ? nc : nocc;
   for (int q = 0; q < nloop; ++q) {
-    uint32_t id;
-    if (nc <= CAP) {
-      id = cand[q];
-    } else {
-      id = a.occ[q];
-      double lo[3], hi[3];
-      bin_box<DIM>(a.bg, id, lo, hi);
+    // the same bin for the whole block: decoded on the scalar unit
+    const uint32_t id = __builtin_amdgcn_readfirstlane(nc <= CAP ? cand[q] : a.occ[q]);
+    double lo[3], hi[3];
+    bin_box<DIM>(a.bg, id, lo, hi);
+    if (nc > CAP) {
       double s = 0.0;
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) {
@@ -1093,6 +1144,18 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
       }
       if (s > R2) continue;
     }
+    bool need = false;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      double s = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        const double w = fmax(fmax(lo[ax] - margin - x[u][ax], x[u][ax] - hi[ax] - margin), 0.0);
+        s += w * w;
+      }
+      need = need || (valid[u] && s <= bn[u] * slack);
+    }
+    if (!__any(need)) continue;
     const int p1 = a.start[id + 1];
     for (int p = a.start[id]; p < p1; ++p) {
       double Q[3];

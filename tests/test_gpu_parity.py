@@ -133,6 +133,29 @@ def test_distance_field_union_sampled():
     assert (np.abs(got - dor) <= 4 * np.spacing(dor)).all()
 
 
+@pytest.mark.parametrize("case", ["dense", "corner", "corner2d"])
+def test_distance_field_dense_and_far_clouds(case):
+    """Many points per bin (80k points on a small torus at 72^3) and nodes up
+    to the far corner of the grid from a cloud in one corner: the bins are
+    visited nearest first and skipped wave by wave, and every node still
+    gets its exact nearest distance."""
+    if case == "dense":
+        g = synth.cube_grid(3, 72)
+        pts = synth.torus_cloud(80_000, 0.3, 0.1, 0.0, seed=21)
+    elif case == "corner":
+        g = synth.cube_grid(3, 96)
+        pts = synth.torus_cloud(4_000, 0.15, 0.05, 0.0, seed=22) + np.array([-0.75, -0.7, -0.72])
+    else:
+        g = synth.cube_grid(2, 200)
+        pts = synth.circle_cloud(3_000, 0.15, seed=23, centre=(-0.78, -0.74))
+    w = dict(grid=g, points=pts, phi0=("sphere", (0.0, 0.0, 0.0, 0.9)), interp="weno",
+             dt=0.5 * g["h"], steps=0, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=0)
+    _, _, _, _, _, dgpu = gpu_run(w, steps=0)
+    dor = oracle.distance(w["points"], g)
+    err = np.abs(dgpu - dor)
+    assert (err <= 4 * np.spacing(dor)).all(), f"max err {err.max():.3e}"
+
+
 # ------------------------------------------------------------ one step
 
 @pytest.mark.parametrize("precision", PRECISIONS)
