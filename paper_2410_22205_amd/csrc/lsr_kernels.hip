@@ -955,6 +955,24 @@ __device__ __forceinline__ void bin_box(const BinGeom& bg, uint32_t id, double l
   }
 }
 
+// Node (li, lj, lk) of the brick that thread threadIdx.x takes as its u-th
+// node.  3D: 512 nodes, two per thread, a wave's 128 nodes forming a
+// 4 x 4 x 8 box (nodes that are close together agree on the bins they can
+// skip); 2D: 16^2 nodes, one per thread.
+template <int DIM>
+__device__ __forceinline__ void dist_node(int u, int& li, int& lj, int& lk) {
+  if (DIM == 3) {
+    const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    li = 4 * (w >> 1) + 2 * u + (l >> 5);
+    lj = 4 * (w & 1) + ((l >> 3) & 3);
+    lk = l & 7;
+  } else {
+    li = (int)threadIdx.x >> 4;
+    lj = (int)threadIdx.x & 15;
+    lk = 0;
+  }
+}
+
 // Exact distance to the cloud at the nodes of one brick (8^3 nodes in 3D,
 // 16^2 in 2D) per workgroup.  With c the brick centre, rho its half diagonal
 // and U = d(c), every node's nearest point lies within U + 2 rho of c; U is
@@ -1101,13 +1119,8 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   bool valid[NPT];
 #pragma unroll
   for (int u = 0; u < NPT; ++u) {
-    const int t = threadIdx.x + u * 256;
     int li, lj, lk;
-    if (DIM == 3) {
-      li = t >> 6; lj = (t >> 3) & 7; lk = t & 7;
-    } else {
-      li = t >> 4; lj = t & 15; lk = 0;
-    }
+    dist_node<DIM>(u, li, lj, lk);
     const int node[3] = {f[0] + li, f[1] + lj, f[2] + lk};
     valid[u] = node[0] <= l[0] && node[1] <= l[1] && node[2] <= l[2];
 #pragma unroll
@@ -1176,13 +1189,8 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
 #pragma unroll
   for (int u = 0; u < NPT; ++u) {
     if (!valid[u]) continue;
-    const int t = threadIdx.x + u * 256;
     int li, lj, lk;
-    if (DIM == 3) {
-      li = t >> 6; lj = (t >> 3) & 7; lk = t & 7;
-    } else {
-      li = t >> 4; lj = t & 15; lk = 0;
-    }
+    dist_node<DIM>(u, li, lj, lk);
     a.d64[lin(g, f[0] + li, f[1] + lj, f[2] + lk)] = sqrt(bn[u]);
   }
 }
