@@ -181,18 +181,31 @@ __device__ __forceinline__ T weno1(T v0, T v1, T v2, T v3, const WC<T>& c, T e) 
   return fma(w, pL - pR, pR);
 }
 
+// v[m] for m in 0..3, by selects (no indexed register access).
+template <typename V, typename T>
+__device__ __forceinline__ T pick4(const V& v, int m) {
+  return m == 0 ? v.x : (m == 1 ? v.y : (m == 2 ? v.z : v.w));
+}
+
 // Four values along the last axis at k0-1 .. k0+2 (indices clamped to the
-// grid, i.e. the boundary node repeated) of the row starting at `row`.
+// grid, i.e. the boundary node repeated) of the row starting at `row`.  One
+// four-wide load from a start clamped into the row (every axis has at least
+// four nodes) serves every lane; lanes within one node of the row's ends
+// then take the clamped indices from it.  The load is issued the same way on
+// every lane, so the loads of consecutive rows stay in flight together.
 template <typename T>
 __device__ __forceinline__ typename Vec<T>::v4 row4(gptr<T> A, uint32_t row, int k0,
                                                    int n) {
   typedef typename Vec<T>::v4 V;
-  if (k0 >= 1 && k0 + 2 <= n - 1) return *(gptr<V>)(A + row + (uint32_t)(k0 - 1));
-  V r;
-  r.x = A[row + clampi(k0 - 1, n)];
-  r.y = A[row + clampi(k0, n)];
-  r.z = A[row + clampi(k0 + 1, n)];
-  r.w = A[row + clampi(k0 + 2, n)];
+  const int kb = k0 - 1 < 0 ? 0 : (k0 - 1 > n - 4 ? n - 4 : k0 - 1);
+  V r = *(gptr<V>)(A + row + (uint32_t)kb);
+  if (kb != k0 - 1) {
+    const V v = r;
+    r.x = pick4<V, T>(v, clampi(k0 - 1, n) - kb);
+    r.y = pick4<V, T>(v, clampi(k0, n) - kb);
+    r.z = pick4<V, T>(v, clampi(k0 + 1, n) - kb);
+    r.w = pick4<V, T>(v, clampi(k0 + 2, n) - kb);
+  }
   return r;
 }
 
