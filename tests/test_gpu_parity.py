@@ -423,6 +423,27 @@ def test_minimal_grid_and_band_on_the_boundary(precision):
         check_phi(phi, ophi, g["h"], 1e-5)
 
 
+@pytest.mark.parametrize("steps", [6, 16])
+@pytest.mark.parametrize("dim,interp", [(3, "weno"), (3, "q1"), (2, "weno")])
+def test_single_point_cloud(dim, interp, steps):
+    """A cloud of one point off the grid's nodes: d is the distance to it
+    (a cone with its tip between nodes).  The front shrinks toward the point,
+    reinitialising on the way (6 steps), and vanishes: by 16 steps the band
+    is empty and phi is +gamma everywhere."""
+    g = synth.cube_grid(dim, 33)
+    pts = np.array([[0.113, -0.071, 0.052][:dim]])
+    w = dict(grid=g, points=pts, phi0=("sphere", (0.0, 0.0, 0.0, 0.35)), interp=interp,
+             dt=0.5 * g["h"], steps=steps, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=4)
+    phi, band, nb, si, cnt, dgpu = gpu_run(w)
+    ophi, counts, dor, prm = oracle_run(w)
+    assert (np.abs(dgpu - dor) <= 4 * np.spacing(dor)).all()
+    check_phi(phi, ophi, g["h"], 1e-5)
+    check_band(band, phi, ophi, prm["gamma"], g["h"])
+    assert si == steps and cnt["node_updates"] == counts[0]
+    if steps == 16:
+        assert nb == 0
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_torus_initial_data_and_ragged_2d(precision):
     g = {"dim": 2, "n": (50, 77), "lo": (-1.0, -1.5), "h": 2.0 / 49}
