@@ -200,7 +200,11 @@ lsr_status lsr_destroy(lsr_job* job);
  * directly.  Results are the same either way.  Synchronises the stream.
  * lsr_batch_tune: times the next step under each candidate launch shape
  * (lanes per node, blocks per CU) without changing the jobs, keeps the
- * fastest and returns it with its time in ms (synchronises).
+ * fastest and returns it with its time in ms (synchronises).  The choice is
+ * kept for the process under the batch's signature (dimension, precision,
+ * jobs per interpolator, total grid nodes rounded up to a power of two); a
+ * later call with the same signature applies it without timing and returns
+ * the time measured then.
  * lsr_batch_destroy: removes the members, waits for the stream. */
 lsr_status lsr_batch_workspace_bytes(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
                                      size_t* bytes);

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "lsr_job.h"
@@ -365,6 +366,33 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
   return LSR_OK;
 }
 
+// Tuned launch shapes, kept for the process: a batch whose signature (dimension,
+// precision, jobs per interpolator, total grid nodes to the next power of
+// two) was tuned before reuses the shape without timing again.
+struct TuneEntry {
+  int64_t key[5];
+  int lanes, bpc;
+  double ms;
+};
+
+std::mutex g_tune_mutex;
+std::vector<TuneEntry> g_tune_cache;
+
+void tune_key(const lsr_batch* b, int64_t key[5]) {
+  int64_t nq = 0, nw = 0, nodes = 0;
+  for (size_t q = 0; q < b->jobs.size(); ++q) {
+    (b->interp[q] == LSR_Q1 ? nq : nw) += 1;
+    nodes += (int64_t)b->jobs[q]->dg.N;
+  }
+  int64_t p2 = 1;
+  while (p2 < nodes) p2 <<= 1;
+  key[0] = b->dim;
+  key[1] = b->fp64 ? 1 : 0;
+  key[2] = nq;
+  key[3] = nw;
+  key[4] = p2;
+}
+
 }  // namespace
 
 // Make `waiter` wait for the work queued on `signaller` so far (no host sync).
@@ -526,9 +554,32 @@ lsr_status lsr_batch_tune(lsr_batch* b, int32_t* lanes, int32_t* blocks_per_cu, 
   if (b->jobs.empty()) return fail(LSR_E_STATE, "the batch has no job");
   int bl = b->lanes, bb = b->bpc;
   double t = 0.0;
-  lsr_status st = b->fp64 ? tune<double>(b, &bl, &bb, &t) : tune<float>(b, &bl, &bb, &t);
-  if (st != LSR_OK) return st;
-  st = lsr_batch_set_launch(b, bl, bb);
+  int64_t key[5];
+  tune_key(b, key);
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    for (const TuneEntry& e : g_tune_cache)
+      if (std::equal(key, key + 5, e.key)) {
+        bl = e.lanes;
+        bb = e.bpc;
+        t = e.ms;
+        cached = true;
+        break;
+      }
+  }
+  if (!cached) {
+    lsr_status st = b->fp64 ? tune<double>(b, &bl, &bb, &t) : tune<float>(b, &bl, &bb, &t);
+    if (st != LSR_OK) return st;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    TuneEntry e;
+    std::copy(key, key + 5, e.key);
+    e.lanes = bl;
+    e.bpc = bb;
+    e.ms = t;
+    g_tune_cache.push_back(e);
+  }
+  lsr_status st = lsr_batch_set_launch(b, bl, bb);
   if (st != LSR_OK) return st;
   if (lanes) *lanes = bl;
   if (blocks_per_cu) *blocks_per_cu = bb;

@@ -183,3 +183,22 @@ def test_staged_job_through_a_batch():
     np.testing.assert_array_equal(job.extract()[0], ref)
     batch.close()
     job.close()
+
+
+def test_tuned_shape_is_kept_for_the_same_signature():
+    """A second batch of the same dimension, precision, interpolator mix and
+    size gets the first one's tuned shape without timing again (the same
+    time comes back)."""
+    lsr = _lsr()
+    ws = _jobs("fp32", n=2, seed=4800)
+    out = []
+    for _ in range(2):
+        batch = lsr.Batch(max_jobs=2, group_steps=4)
+        jobs = [_make(lsr, w) for w in ws]
+        for w, j in zip(ws, jobs):
+            batch.add(j, w["dt"], w["interp"])
+        out.append(batch.tune())
+        batch.close()
+        for j in jobs:
+            j.close()
+    assert out[0] == out[1] and out[0][2] > 0
