@@ -265,7 +265,7 @@ def main():
     dim = g["dim"]
     prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
                precision=args.precision)
-    # a stream of its own: step loops on the null stream cannot run as graphs
+    # a stream of its own (the null stream cannot be captured into graphs)
     job = lsr.Job(g, prm, max_points=len(w["points"]), stream=torch.cuda.Stream())
     if args.lanes >= 0 or args.blocks_per_cu != 8:
         lsr.lsr_set_launch(job.handle, args.lanes if args.lanes >= 0 else DEFAULT_LANES[dim],
@@ -287,9 +287,6 @@ def main():
         lsr.lsr_step(job.handle, w["steps"], w["dt"], interp)
         lsr.lsr_extract(job.handle, phi_out.data_ptr(), band_out.data_ptr(), want_count=False)
 
-    # timing on during warm-up too, so that the step graphs recorded there are
-    # the timed ones the measured jobs replay; re-enabling clears the records
-    lsr.lsr_profile_enable(job.handle, True, w["steps"] * args.steps + 8)
     for _ in range(args.warmup):
         one_job()
     stream.synchronize()
@@ -327,8 +324,7 @@ def main():
                 "flops_per_node_update": flops,
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
                 "node_updates_per_launch": round(upd_per_launch, 1),
-                "lanes": lanes, "staged": lanes == 0, "blocks_per_cu": args.blocks_per_cu,
-                "step_graphs": dict(zip(("recorded", "replays"), job.graph_counts()))}
+                "lanes": lanes, "staged": lanes == 0, "blocks_per_cu": args.blocks_per_cu}
     hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in lat)
     out = {

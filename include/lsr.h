@@ -234,8 +234,9 @@ lsr_status lsr_set_launch(lsr_job* job, int32_t lanes, int32_t blocks_per_cu);
  * through recorded graphs: a chunk is recorded the second time the job
  * starts one in the same state (buffer roles, counter slots, phase in the
  * reinitialisation period, dt, interpolator, launch shape) and replayed after
- * that; the remaining steps, the staged kernel (lanes = 0) and jobs on the
- * null stream launch directly.  Results are the same either way.
+ * that; the remaining steps, the staged kernel (lanes = 0), jobs on the null
+ * stream and step loops while kernel timing is on (lsr_profile_enable)
+ * launch directly.  Results are the same either way.
  * Synchronises the stream and drops the recorded graphs. */
 lsr_status lsr_set_graphs(lsr_job* job, int32_t enable);
 
@@ -243,14 +244,14 @@ lsr_status lsr_set_graphs(lsr_job* job, int32_t enable);
  * lsr_batch_step (exactly one of job, batch non-NULL), into host memory. */
 lsr_status lsr_graph_counts(lsr_job* job, lsr_batch* batch, int64_t* captured, int64_t* replayed);
 
-/* Measurement hook.  While enabled, every semi-Lagrangian step kernel the job
- * launches is bracketed by a pair of HIP events recorded on the job's stream
- * (at most max_launches pairs for direct launches, later ones are not
- * recorded; in a step graph the pairs are event-record nodes of the graph,
- * all of them recorded; graphs recorded while timing is on are kept for later
- * timed runs).  Enabling or disabling clears earlier records.  lsr_profile_read synchronises the stream and
- * returns the summed kernel time in milliseconds and the number of recorded
- * launches. */
+/* Measurement hook.  While enabled, lsr_step launches directly and every
+ * semi-Lagrangian step kernel of the job carries a pair of HIP events tied
+ * to its dispatch (hipExtLaunchKernel), whose elapsed time is the kernel's
+ * execution time (the staged kernel, lanes = 0: events recorded on the
+ * stream around the launch); at most max_launches pairs, later launches are
+ * not timed.  Enabling or disabling clears earlier records.
+ * lsr_profile_read synchronises the stream and returns the summed kernel
+ * time in milliseconds and the number of timed launches. */
 lsr_status lsr_profile_enable(lsr_job* job, int32_t enable, int32_t max_launches);
 lsr_status lsr_profile_read(lsr_job* job, double* total_ms, int64_t* launches);
 

@@ -159,20 +159,15 @@ static lsr_status rebuild_bricks(lsr_job* j) {
 
 // n steps of the node-list kernel, each followed by the reinitialisation
 // when due, from the current plan state, which they advance.  With launch
-// false nothing is launched (the state of a replayed graph); `timed` holds
-// one start/stop event pair per step, recorded as record_timed's `mode`.
+// false nothing is launched (the state of a replayed graph).
 template <typename T>
 static hipError_t issue_steps(lsr_job* j, int32_t n, const StepConst<T>& c, int interp,
-                              bool launch, std::vector<hipEvent_t>* timed, int mode) {
+                              bool launch) {
   hipStream_t s = j->stream;
   hipError_t e = hipSuccess;
   for (int32_t q = 0; q < n && e == hipSuccess; ++q) {
     SLArgs<T> a = plan_step<T>(j, c);
-    if (launch) {
-      if (timed) e = record_timed((*timed)[2 * q], s, mode);
-      if (e == hipSuccess) e = launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s);
-      if (timed && e == hipSuccess) e = record_timed((*timed)[2 * q + 1], s, mode);
-    }
+    if (launch) e = launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s);
     if (reinit_due(j)) {
       ReinitPlan<T> r = plan_reinit<T>(j);
       if (launch && e == hipSuccess) e = launch_reinit_plan<T>(j, r);
@@ -219,11 +214,11 @@ static std::vector<int64_t> graph_key(const lsr_job* j, int32_t n, double dt, in
   memcpy(&dtb, &dt, sizeof dtb);
   const int64_t K = j->prm.reinit_every;
   return {(int64_t)sizeof(T), j->cur, j->cur_list, j->cur_blist, j->ring,
-          K > 0 ? j->step_index % K : 0, n, dtb, interp, j->lanes, (int64_t)j->list_blocks,
-          j->prof_on ? 1 : 0};
+          K > 0 ? j->step_index % K : 0, n, dtb, interp, j->lanes, (int64_t)j->list_blocks};
 }
 
-// Steps launched one by one (timed through the job's own events).
+// Steps launched one by one; while kernel timing is on, each step kernel
+// carries start and stop events tied to its dispatch.
 template <typename T>
 static lsr_status direct_steps(lsr_job* j, int32_t n_steps, const StepConst<T>& c, int interp) {
   hipStream_t s = j->stream;
@@ -235,17 +230,17 @@ static lsr_status direct_steps(lsr_job* j, int32_t n_steps, const StepConst<T>& 
     }
     SLArgs<T> a = plan_step<T>(j, c);
     const bool rec = j->prof_on && 2 * (size_t)j->prof_used + 1 < j->prof_ev.size();
-    if (rec) LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used], s));
+    hipEvent_t e0 = rec ? j->prof_ev[2 * j->prof_used] : nullptr;
+    hipEvent_t e1 = rec ? j->prof_ev[2 * j->prof_used + 1] : nullptr;
     if (staged) {
+      if (rec) LSR_HIP(hipEventRecord(e0, s));
       LSR_HIP(launch_sl_step_staged<T>(interp, a, j->list_blocks, s));
+      if (rec) LSR_HIP(hipEventRecord(e1, s));
     } else {
-      LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s));
+      LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s, e0, e1));
       j->bricks_valid = false;
     }
-    if (rec) {
-      LSR_HIP(hipEventRecord(j->prof_ev[2 * j->prof_used + 1], s));
-      j->prof_used += 1;
-    }
+    if (rec) j->prof_used += 1;
     if (reinit_due(j)) {
       lsr_status st = run_reinit_t<T>(j);
       if (st != LSR_OK) return st;
@@ -258,39 +253,29 @@ template <typename T>
 static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp) {
   hipStream_t s = j->stream;
   const StepConst<T> c = step_const<T>(j, dt);
-  // whole chunks through recorded graphs (node-list kernel only; never on the
-  // null stream, which cannot be captured)
+  // whole chunks through recorded graphs (node-list kernel only, not while
+  // kernel timing is on, never on the null stream, which cannot be captured)
   const int32_t chunk = graph_chunk(j);
   GraphCache& G = j->graphs;
-  while (j->lanes != 0 && G.enabled && s != nullptr && n_steps >= chunk &&
-         !(j->prof_on && G.event_mode == 0)) {
+  while (j->lanes != 0 && !j->prof_on && G.enabled && s != nullptr && n_steps >= chunk) {
     const std::vector<int64_t> key = graph_key<T>(j, chunk, dt, interp);
     GraphCache::Entry* g = G.find(key);
     bool direct = false;
     if (g) {
-      (void)issue_steps<T>(j, chunk, c, interp, false, nullptr, 0);
+      (void)issue_steps<T>(j, chunk, c, interp, false);
       LSR_HIP(G.replay(*g, s));
     } else if (G.seen_before(key)) {
       const PlanState p0 = save_plan(j);
-      const bool timed = j->prof_on;
       bool launched = false;
       hipError_t e = G.capture_and_launch(
-          s, key, timed ? chunk : 0,
-          [&](std::vector<hipEvent_t>& ev) {
-            return issue_steps<T>(j, chunk, c, interp, true, timed ? &ev : nullptr,
-                                  G.event_mode);
-          },
-          &launched);
+          s, key, [&]() { return issue_steps<T>(j, chunk, c, interp, true); }, &launched);
       if (e != hipSuccess && launched) LSR_HIP(e);
       if (e != hipSuccess) {
-        // nothing ran: this chunk launches directly; a capture with timing
-        // tries the next way of timing, one without gives up graphs
+        // nothing ran and the stream cannot be captured: this chunk and
+        // all later ones launch directly
         (void)hipGetLastError();
         restore_plan(j, p0);
-        if (timed)
-          G.event_mode -= 1;
-        else
-          G.enabled = false;
+        G.enabled = false;
         (void)fail(LSR_OK, "step graph not recorded (" + G.failure + "); launching directly");
         direct = true;
       }
@@ -699,12 +684,7 @@ lsr_status lsr_set_launch(lsr_job* j, int32_t lanes, int32_t blocks_per_cu) {
 lsr_status lsr_set_graphs(lsr_job* j, int32_t enable) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
   LSR_HIP(hipStreamSynchronize(j->stream));
-  LSR_HIP(j->graphs.collect_all());
-  const double ms = j->graphs.timed_ms;
-  const int64_t n = j->graphs.timed_n;
   j->graphs.clear();
-  j->graphs.timed_ms = ms;  // timed launches so far still count
-  j->graphs.timed_n = n;
   j->graphs.enabled = enable != 0;
   return LSR_OK;
 }
@@ -717,7 +697,6 @@ lsr_status lsr_profile_enable(lsr_job* j, int32_t enable, int32_t max_launches) 
   j->prof_ev.clear();
   j->prof_used = 0;
   j->prof_on = false;
-  j->graphs.reset_timed();
   if (!enable) return LSR_OK;
   j->prof_ev.resize(2 * (size_t)max_launches, nullptr);
   for (auto& e : j->prof_ev) LSR_HIP(hipEventCreate(&e));
@@ -728,15 +707,14 @@ lsr_status lsr_profile_enable(lsr_job* j, int32_t enable, int32_t max_launches) 
 lsr_status lsr_profile_read(lsr_job* j, double* total_ms, int64_t* launches) {
   if (!j || !total_ms || !launches) return fail(LSR_E_INVALID, "NULL argument");
   LSR_HIP(hipStreamSynchronize(j->stream));
-  LSR_HIP(j->graphs.collect_all());
-  double tot = j->graphs.timed_ms;
+  double tot = 0.0;
   for (int q = 0; q < j->prof_used; ++q) {
     float ms = 0.0f;
     LSR_HIP(hipEventElapsedTime(&ms, j->prof_ev[2 * q], j->prof_ev[2 * q + 1]));
     tot += ms;
   }
   *total_ms = tot;
-  *launches = j->prof_used + j->graphs.timed_n;
+  *launches = j->prof_used;
   return LSR_OK;
 }
 

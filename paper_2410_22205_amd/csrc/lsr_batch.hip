@@ -219,8 +219,8 @@ lsr_status launch_group(lsr_batch* b, const Builder<T>& B) {
     }
     if (b->graphs.seen_before(key)) {
       bool launched = false;
-      hipError_t e = b->graphs.capture_and_launch(
-          s, key, 0, [&](std::vector<hipEvent_t>&) { return issue<T>(b, B); }, &launched);
+      hipError_t e =
+          b->graphs.capture_and_launch(s, key, [&]() { return issue<T>(b, B); }, &launched);
       if (e == hipSuccess) return LSR_OK;
       if (launched) LSR_HIP(e);
       (void)hipGetLastError();

@@ -119,7 +119,7 @@ hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_
 // lanes: 1, or the number of foot points per node (2 in 2D, 4 in 3D).
 template <typename T>
 hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
-                          hipStream_t s);
+                          hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // The 3D step over a brick list with phi staged in LDS (same results as
 // launch_sl_step).
 template <typename T>

@@ -7,6 +7,8 @@
 // contiguous stretch of the list (its own L2 then sees neighbouring nodes).
 // Lists are compacted with a wave-wide ballot, a popcount and one atomic per
 // wave.
+#include <hip/hip_ext.h>
+
 #include <mutex>
 #include <unordered_map>
 
@@ -1267,6 +1269,17 @@ static hipError_t persistent_launch(void (*kern)(P...), unsigned blocks, hipStre
   return hipGetLastError();
 }
 
+// The same launch with start and stop events tied to the dispatch itself, so
+// that their elapsed time is the kernel's execution time.
+template <typename... P, typename... A>
+static hipError_t persistent_launch_timed(void (*kern)(P...), unsigned blocks, hipStream_t s,
+                                          hipEvent_t start, hipEvent_t stop, A... args) {
+  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
+  const unsigned b = std::min(blocks, resident_blocks((const void*)kern));
+  hipExtLaunchKernelGGL(kern, dim3(b), dim3(256), 0, s, start, stop, 0, args...);
+  return hipGetLastError();
+}
+
 static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
   uint64_t b = (n + block - 1) / block;
   if (b < 1) b = 1;
@@ -1318,7 +1331,7 @@ hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_
 
 template <typename T>
 hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
-                          hipStream_t s) {
+                          hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   void (*k)(SLArgs<T>);
   if (dim == 3)
     k = lanes == 1 ? (interp == 0 ? k_sl_step<3, 0, T, 1> : k_sl_step<3, 1, T, 1>)
@@ -1326,6 +1339,7 @@ hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, un
   else
     k = lanes == 1 ? (interp == 0 ? k_sl_step<2, 0, T, 1> : k_sl_step<2, 1, T, 1>)
                    : (interp == 0 ? k_sl_step<2, 0, T, 2> : k_sl_step<2, 1, T, 2>);
+  if (start) return persistent_launch_timed(k, blocks, s, start, stop, a);
   return persistent_launch(k, blocks, s, a);
 }
 
@@ -1463,7 +1477,8 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_band_mask<T>(const DevGrid&, T, const T*, const uint32_t*,           \
                                           const int32_t*, uint8_t*, int32_t*, unsigned,           \
                                           hipStream_t);                                           \
-  template hipError_t launch_sl_step<T>(int, int, int, const SLArgs<T>&, unsigned, hipStream_t);  \
+  template hipError_t launch_sl_step<T>(int, int, int, const SLArgs<T>&, unsigned, hipStream_t,    \
+                                        hipEvent_t, hipEvent_t);                                  \
   template hipError_t launch_reinit_fix<T>(int, const RArgs<T>&, unsigned, hipStream_t);          \
   template hipError_t launch_reinit_iter<T>(int, const RArgs<T>&, unsigned, hipStream_t);         \
   template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \
