@@ -103,7 +103,7 @@ def cpu_baseline(w, min_seconds=10.0):
                        f"{w['steps']} steps; {updates} node updates), FP64, {dt:.1f} s wall")}
 
 
-def run_batched(n_jobs, steps, precision, graphs=True):
+def run_batched(n_jobs, steps, precision, graphs=True, batch_streams=2):
     """The batched workload: independent jobs with uneven grids (64^3-192^3),
     clouds of 5k-150k points, Q1 and WENO alternating, `steps` steps each;
     one after the other as plain solves, then all in one batch (loads on
@@ -163,6 +163,7 @@ def run_batched(n_jobs, steps, precision, graphs=True):
                                    max_points=len(w["points"]), stream=streams[k % 4]))
     batch = lsr.Batch(max_jobs=n_jobs, group_steps=10, stream=torch.cuda.Stream())
     batch.set_graphs(graphs)
+    batch.set_streams(batch_streams)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for job, w, p in zip(handles, jobs, pts):
@@ -191,14 +192,14 @@ def run_batched(n_jobs, steps, precision, graphs=True):
             "group_graphs": dict(zip(("recorded", "replays"), graphs))}
 
 
-def run_served(n_jobs, precision, graphs=True):
+def run_served(n_jobs, precision, graphs=True, streams=2):
     """The served workload: a Poisson stream at 20 requests/s of jobs with
     grids 64^3-320^3, 5k-1M points, 200-400 WENO steps, served with
     continuous batching; then the same stream as plain solves one at a time.
     Latency = completion - arrival."""
     from paper_2410_22205_amd import serve, synth
     reqs = serve.materialise(synth.served_jobs(n_jobs=n_jobs))
-    srv = serve.Server(precision=precision, graphs=graphs)
+    srv = serve.Server(precision=precision, graphs=graphs, batch_streams=streams)
     warm = serve.materialise(synth.served_jobs(n_jobs=2, seed=77))
     srv.run([dict(r, arrival=0.0) for r in warm])
     out = srv.run(reqs)
@@ -241,6 +242,8 @@ def main():
                     help="least wall time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
+    ap.add_argument("--batch-streams", type=int, default=2, choices=[1, 2],
+                    help="streams a batch runs its cache groups on")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--batch-jobs", type=int, default=64, help="batched section (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -357,9 +360,11 @@ def main():
     job.close()
     if args.batch_jobs:
         out["batched"] = run_batched(args.batch_jobs, args.batch_steps, args.precision,
-                                     graphs=not args.no_graphs)
+                                     graphs=not args.no_graphs,
+                                     batch_streams=args.batch_streams)
     if args.served_jobs:
-        out["served"] = run_served(args.served_jobs, args.precision, graphs=not args.no_graphs)
+        out["served"] = run_served(args.served_jobs, args.precision, graphs=not args.no_graphs,
+                                   streams=args.batch_streams)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

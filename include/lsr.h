@@ -194,6 +194,12 @@ lsr_status lsr_destroy(lsr_job* job);
  * stream is ordered after the batch's queued work.
  * lsr_batch_step: n_steps steps of every member (uploads one table per group).
  * lsr_batch_set_launch: launch shape as in lsr_set_launch.
+ * lsr_batch_set_streams: members whose state does not fit the device's
+ * last-level cache together are stepped in cache groups, each with its own
+ * launches; with 2 streams (the default) every other group runs on a second
+ * stream that the batch creates, forked from and joined back into the
+ * batch's stream within each lsr_batch_step, so that groups overlap; 1 runs
+ * all groups on the batch's stream.  Results are the same either way.
  * lsr_batch_set_graphs: 1 (default) records a group of steps whose launch
  * sequence was seen before (same members, phases and launch shape) as a HIP
  * graph and replays it for later such groups; 0 launches every kernel
@@ -215,6 +221,7 @@ lsr_status lsr_batch_add(lsr_batch* batch, lsr_job* job, double dt, lsr_interp i
 lsr_status lsr_batch_remove(lsr_batch* batch, lsr_job* job);
 lsr_status lsr_batch_step(lsr_batch* batch, int32_t n_steps);
 lsr_status lsr_batch_set_launch(lsr_batch* batch, int32_t lanes, int32_t blocks_per_cu);
+lsr_status lsr_batch_set_streams(lsr_batch* batch, int32_t n_streams);
 lsr_status lsr_batch_set_graphs(lsr_batch* batch, int32_t enable);
 lsr_status lsr_batch_tune(lsr_batch* batch, int32_t* lanes, int32_t* blocks_per_cu, double* ms);
 lsr_status lsr_batch_destroy(lsr_batch* batch);

@@ -26,6 +26,7 @@ struct Launch {
   size_t off;
   int n;
   int interp;    // kind 0 only
+  int group;     // cache group (see cache_groups)
 };
 
 }  // namespace
@@ -51,6 +52,12 @@ struct lsr_batch {
   int lanes, bpc, ncu;
   unsigned blocks;
   lsr::GraphCache graphs;  // recorded group launch sequences
+  // streams of the cache groups besides the batch's own (group g runs on
+  // stream g % n_streams, 0 the batch's), forked and joined back per call
+  static constexpr int kMaxStreams = 2;
+  hipStream_t side[kMaxStreams - 1];
+  hipEvent_t fork_ev, join_ev[kMaxStreams - 1];
+  int n_streams;
 };
 
 namespace {
@@ -93,6 +100,7 @@ template <typename T>
 struct Builder {
   lsr_batch* b;
   size_t off = 0;
+  int group = 0;
   std::vector<Launch> launches;
   template <typename A>
   A* take(int n) {
@@ -121,7 +129,7 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
         j->bricks_valid = false;  // stepped here through the node list
         tab[m++] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
       }
-      B.launches.push_back({0, o, m, itp});
+      B.launches.push_back({0, o, m, itp, B.group});
     }
     std::vector<int> due;
     for (int q = q0; q < q1; ++q)
@@ -138,35 +146,43 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
     size_t od = align256(B.off);
     GbarArgs<T>* gb = B.template take<GbarArgs<T>>(nd);
     for (int q = 0; q < nd; ++q) gb[q] = plans[q].gb;
-    B.launches.push_back({1, od, nd, 0});
+    B.launches.push_back({1, od, nd, 0, B.group});
     size_t of = align256(B.off);
     RArgs<T>* fix = B.template take<RArgs<T>>(nd);
     for (int q = 0; q < nd; ++q) fix[q] = plans[q].fix;
-    B.launches.push_back({2, of, nd, 0});
+    B.launches.push_back({2, of, nd, 0, B.group});
     for (int it = 0; it < max_it; ++it) {
       size_t oi = align256(B.off);
       RArgs<T>* itab = B.template take<RArgs<T>>(nd);
       int m = 0;
       for (int q = 0; q < nd; ++q)
         if (it < plans[q].iters) itab[m++] = plans[q].iter[it % 2];
-      B.launches.push_back({3, oi, m, 0});
+      B.launches.push_back({3, oi, m, 0, B.group});
     }
     size_t on = align256(B.off);
     FinArgs<T>* fin = B.template take<FinArgs<T>>(nd);
     for (int q = 0; q < nd; ++q) fin[q] = plans[q].fin;
-    B.launches.push_back({4, on, nd, 0});
+    B.launches.push_back({4, on, nd, 0, B.group});
   }
   if (B.off > b->table_bytes) return fail(LSR_E_NOMEM, "batch table workspace too small");
   return LSR_OK;
 }
 
+// The cache groups hold different jobs, so their launches are independent:
+// group g runs on stream g % n (stream 0 the batch's own, the others forked
+// from it and joined back into it), so that one group's kernels fill the
+// gaps between another's.
 template <typename T>
 hipError_t issue(lsr_batch* b, const Builder<T>& B) {
-  hipStream_t s = b->stream;
   char* dev = b->ws + b->table_off;
   hipError_t e = hipSuccess;
+  const int ns = std::min(b->n_streams, B.group);
+  if (ns > 1) e = hipEventRecord(b->fork_ev, b->stream);
+  for (int q = 1; q < ns && e == hipSuccess; ++q) e = hipStreamWaitEvent(b->side[q - 1], b->fork_ev, 0);
   for (const Launch& L : B.launches) {
     if (e != hipSuccess) break;
+    const int sq = ns > 1 ? L.group % ns : 0;
+    hipStream_t s = sq ? b->side[sq - 1] : b->stream;
     switch (L.kind) {
       case 0:
         e = launch_sl_step_batch<T>(b->dim, L.interp, b->lanes, (const SLArgs<T>*)(dev + L.off), L.n,
@@ -187,6 +203,11 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
         break;
     }
   }
+  for (int q = 1; q < ns; ++q) {
+    hipError_t r = hipEventRecord(b->join_ev[q - 1], b->side[q - 1]);
+    if (r == hipSuccess) r = hipStreamWaitEvent(b->stream, b->join_ev[q - 1], 0);
+    if (e == hipSuccess) e = r;
+  }
   return e;
 }
 
@@ -196,13 +217,15 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
 // sequence replay one recorded graph after their tables are copied.
 template <typename T>
 std::vector<int64_t> group_key(const lsr_batch* b, const Builder<T>& B) {
-  std::vector<int64_t> k = {(int64_t)sizeof(T), b->dim, b->lanes, (int64_t)b->blocks};
-  k.reserve(4 + 4 * B.launches.size());
+  std::vector<int64_t> k = {(int64_t)sizeof(T), b->dim, b->lanes, (int64_t)b->blocks,
+                            b->n_streams};
+  k.reserve(5 + 5 * B.launches.size());
   for (const Launch& L : B.launches) {
     k.push_back(L.kind);
     k.push_back((int64_t)L.off);
     k.push_back(L.n);
     k.push_back(L.interp);
+    k.push_back(L.group);
   }
   return k;
 }
@@ -264,6 +287,7 @@ lsr_status run_group(lsr_batch* b, int steps) {
   for (const auto& g : cache_groups(b)) {
     lsr_status st = build_group<T>(b, g.first, g.second, steps, B);
     if (st != LSR_OK) return st;
+    B.group += 1;
   }
   LSR_HIP(hipMemcpyAsync(b->ws + b->table_off, b->host, B.off, hipMemcpyHostToDevice, b->stream));
   LSR_HIP(hipEventRecord(b->copy_done, b->stream));
@@ -459,8 +483,25 @@ lsr_status lsr_batch_create(int32_t max_jobs, int32_t group_steps, int32_t max_r
     delete b;
     return fail(LSR_E_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
   }
+  b->fork_ev = b->copy_done = nullptr;
+  for (int q = 0; q < lsr_batch::kMaxStreams - 1; ++q) {
+    b->side[q] = nullptr;
+    b->join_ev[q] = nullptr;
+  }
+  b->n_streams = 2;
   e = hipEventCreateWithFlags(&b->copy_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+  for (int q = 0; q < lsr_batch::kMaxStreams - 1 && e == hipSuccess; ++q) {
+    e = hipEventCreateWithFlags(&b->join_ev[q], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking);
+  }
   if (e != hipSuccess) {
+    for (int q = 0; q < lsr_batch::kMaxStreams - 1; ++q) {
+      if (b->side[q]) (void)hipStreamDestroy(b->side[q]);
+      if (b->join_ev[q]) (void)hipEventDestroy(b->join_ev[q]);
+    }
+    for (hipEvent_t ev : {b->copy_done, b->fork_ev})
+      if (ev) (void)hipEventDestroy(ev);
     (void)hipHostFree(b->host);
     delete b;
     return fail(LSR_E_DEVICE, hipGetErrorString(e));
@@ -532,6 +573,15 @@ lsr_status lsr_batch_set_launch(lsr_batch* b, int32_t lanes, int32_t blocks_per_
   return LSR_OK;
 }
 
+lsr_status lsr_batch_set_streams(lsr_batch* b, int32_t n_streams) {
+  if (!b) return fail(LSR_E_INVALID, "batch is NULL");
+  if (n_streams < 1 || n_streams > lsr_batch::kMaxStreams)
+    return fail(LSR_E_INVALID, "n_streams must be 1 or 2");
+  LSR_HIP(hipStreamSynchronize(b->stream));
+  b->n_streams = n_streams;
+  return LSR_OK;
+}
+
 lsr_status lsr_batch_set_graphs(lsr_batch* b, int32_t enable) {
   if (!b) return fail(LSR_E_INVALID, "batch is NULL");
   LSR_HIP(hipStreamSynchronize(b->stream));
@@ -595,6 +645,11 @@ lsr_status lsr_batch_destroy(lsr_batch* b) {
   }
   hipError_t e = hipStreamSynchronize(b->stream);
   b->graphs.clear();
+  for (int q = 0; q < lsr_batch::kMaxStreams - 1; ++q) {
+    (void)hipStreamDestroy(b->side[q]);
+    (void)hipEventDestroy(b->join_ev[q]);
+  }
+  (void)hipEventDestroy(b->fork_ev);
   (void)hipEventDestroy(b->copy_done);
   (void)hipHostFree(b->host);
   delete b;

@@ -181,10 +181,11 @@ __device__ __forceinline__ T weno1(T v0, T v1, T v2, T v3, const WC<T>& c, T e) 
   return fma(w, pL - pR, pR);
 }
 
-// v[m] for m in 0..3, by selects (no indexed register access).
-template <typename V, typename T>
-__device__ __forceinline__ T pick4(const V& v, int m) {
-  return m == 0 ? v.x : (m == 1 ? v.y : (m == 2 ? v.z : v.w));
+// The m-th of (x, y, z, w), m in 0..3, by selects (no indexed register
+// access).
+template <typename T>
+__device__ __forceinline__ T pick4(T x, T y, T z, T w, int m) {
+  return m == 0 ? x : (m == 1 ? y : (m == 2 ? z : w));
 }
 
 // Four values along the last axis at k0-1 .. k0+2 (indices clamped to the
@@ -200,11 +201,11 @@ __device__ __forceinline__ typename Vec<T>::v4 row4(gptr<T> A, uint32_t row, int
   const int kb = k0 - 1 < 0 ? 0 : (k0 - 1 > n - 4 ? n - 4 : k0 - 1);
   V r = *(gptr<V>)(A + row + (uint32_t)kb);
   if (kb != k0 - 1) {
-    const V v = r;
-    r.x = pick4<V, T>(v, clampi(k0 - 1, n) - kb);
-    r.y = pick4<V, T>(v, clampi(k0, n) - kb);
-    r.z = pick4<V, T>(v, clampi(k0 + 1, n) - kb);
-    r.w = pick4<V, T>(v, clampi(k0 + 2, n) - kb);
+    const T x = r.x, y = r.y, z = r.z, w = r.w;
+    r.x = pick4<T>(x, y, z, w, clampi(k0 - 1, n) - kb);
+    r.y = pick4<T>(x, y, z, w, clampi(k0, n) - kb);
+    r.z = pick4<T>(x, y, z, w, clampi(k0 + 1, n) - kb);
+    r.w = pick4<T>(x, y, z, w, clampi(k0 + 2, n) - kb);
   }
   return r;
 }

@@ -28,7 +28,8 @@ EXPORTED = [
     "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
     "lsr_extract", "lsr_counters", "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
     "lsr_batch_add", "lsr_batch_remove", "lsr_batch_step", "lsr_batch_set_launch",
-    "lsr_batch_tune", "lsr_batch_destroy", "lsr_batch_set_graphs", "lsr_set_launch",
+    "lsr_batch_tune", "lsr_batch_destroy", "lsr_batch_set_graphs", "lsr_batch_set_streams",
+    "lsr_set_launch",
     "lsr_set_graphs", "lsr_graph_counts", "lsr_profile_enable",
     "lsr_profile_read", "lsr_last_error",
 ]
@@ -95,6 +96,7 @@ def load():
             "lsr_set_launch": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_set_graphs": [_P, ctypes.c_int32],
             "lsr_batch_set_graphs": [_P, ctypes.c_int32],
+            "lsr_batch_set_streams": [_P, ctypes.c_int32],
             "lsr_graph_counts": [_P, _P, I64P, I64P],
             "lsr_profile_read": [_P, ctypes.POINTER(ctypes.c_double), I64P],
         }
@@ -245,6 +247,10 @@ def lsr_set_graphs(job, enable):
 
 def lsr_batch_set_graphs(batch, enable):
     _check(load().lsr_batch_set_graphs(batch, int(bool(enable))))
+
+
+def lsr_batch_set_streams(batch, n_streams):
+    _check(load().lsr_batch_set_streams(batch, int(n_streams)))
 
 
 def lsr_graph_counts(job=None, batch=None):
@@ -406,6 +412,9 @@ class Batch:
 
     def set_graphs(self, enable):
         lsr_batch_set_graphs(self.handle, enable)
+
+    def set_streams(self, n_streams):
+        lsr_batch_set_streams(self.handle, n_streams)
 
     def graph_counts(self):
         return lsr_graph_counts(batch=self.handle)

@@ -129,15 +129,17 @@ class Server:
     job joins when it fits, or when nothing is running); prefetch: jobs that
     may be loading or loaded ahead of joining;
     precision: "fp32" | "fp64" (one per server: a batch has one precision);
-    graphs: replay recorded HIP graphs for repeated groups of batch steps."""
+    graphs: replay recorded HIP graphs for repeated groups of batch steps;
+    batch_streams: streams the batch runs its cache groups on (1 or 2)."""
 
     def __init__(self, budget_bytes=None, max_active=64, group_steps=10, precision="fp32",
                  load_streams=2, max_reinit_iters=32, work_budget=3_000_000, prefetch=3,
-                 graphs=True):
+                 graphs=True, batch_streams=2):
         import torch
         self.torch = torch
         self.precision = precision
         self.graphs = graphs
+        self.batch_streams = batch_streams
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = int(0.8 * free)
@@ -194,6 +196,7 @@ class Server:
         batch = lsr.Batch(max_jobs=self.max_active, group_steps=self.group_steps,
                           max_reinit_iters=self.max_reinit_iters, stream=self.batch_stream)
         batch.set_graphs(self.graphs)
+        batch.set_streams(self.batch_streams)
         lives = {}
         pending = collections.deque(order)
         running = []

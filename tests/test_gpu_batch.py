@@ -202,3 +202,28 @@ def test_tuned_shape_is_kept_for_the_same_signature():
         for j in jobs:
             j.close()
     assert out[0] == out[1] and out[0][2] > 0
+
+
+@pytest.mark.parametrize("streams", [2, 1])
+def test_cache_groups_on_two_streams(streams):
+    """Jobs too large to share the device's last-level cache are stepped in
+    separate cache groups; on two streams the groups overlap.  Every job
+    still ends bitwise where it ends alone."""
+    lsr = _lsr()
+    ws = []
+    for w in synth.batch_jobs(n_jobs=3, seed=4900, n_range=(168, 176), pts_range=(5000, 9000),
+                              steps=12):
+        w["precision"] = "fp32"
+        ws.append(w)
+    solo = [_solo(w, 12)[0] for w in ws]
+    batch = lsr.Batch(max_jobs=3, group_steps=6)
+    batch.set_streams(streams)
+    jobs = [_make(lsr, w) for w in ws]
+    for w, j in zip(ws, jobs):
+        batch.add(j, w["dt"], w["interp"])
+    batch.step(12)
+    for k, j in enumerate(jobs):
+        np.testing.assert_array_equal(j.extract()[0], solo[k])
+    batch.close()
+    for j in jobs:
+        j.close()
