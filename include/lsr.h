@@ -13,13 +13,21 @@
  * General rules
  *  - Every function returns an lsr_status; none throws.  On failure the job is
  *    left as it was and lsr_last_error() describes the cause.
- *  - Device memory is owned by the caller: lsr_create carves the caller's
- *    workspace (size from lsr_workspace_bytes) and never allocates device
- *    memory itself.  Pointers marked "device" are HIP device pointers.
+ *  - Device memory for data is owned by the caller: lsr_create and
+ *    lsr_batch_create carve the caller's workspace (sizes from
+ *    lsr_workspace_bytes, lsr_batch_workspace_bytes) and never allocate
+ *    device memory for data themselves.  The library creates only HIP
+ *    objects: events, a second stream per batch (lsr_batch_set_streams)
+ *    and instantiated graphs of step loops (lsr_set_graphs), whose memory
+ *    the HIP runtime manages.  Pointers marked "device" are HIP device
+ *    pointers.
  *  - All device work is enqueued on the caller's HIP stream given to
- *    lsr_create; only calls that return host-side values from the device
- *    (lsr_load_cloud's input check, lsr_extract with n_band, lsr_counters)
- *    synchronise that stream.
+ *    lsr_create (a batch's on its own stream, with its second stream
+ *    joined back into it within every call); only calls that return
+ *    host-side values from the device (lsr_load_cloud's input check,
+ *    lsr_extract with n_band, lsr_counters, lsr_profile_read,
+ *    lsr_batch_tune) and the switches of the graph, stream and timing
+ *    hooks synchronise that stream.
  *  - Nodal arrays are in C order: 2D index i*n[1] + j, 3D index
  *    (i*n[1] + j)*n[2] + k, axis 0 <-> x.  Node (i,j,k) sits at
  *    lo + (i,j,k)*h.
@@ -200,10 +208,13 @@ lsr_status lsr_destroy(lsr_job* job);
  * stream that the batch creates, forked from and joined back into the
  * batch's stream within each lsr_batch_step, so that groups overlap; 1 runs
  * all groups on the batch's stream.  Results are the same either way.
+ * Synchronises the stream; other values give LSR_E_INVALID.
  * lsr_batch_set_graphs: 1 (default) records a group of steps whose launch
- * sequence was seen before (same members, phases and launch shape) as a HIP
- * graph and replays it for later such groups; 0 launches every kernel
- * directly.  Results are the same either way.  Synchronises the stream.
+ * sequence was seen before (the same kernels, table offsets and job counts
+ * per launch, and the same launch shape and stream count) as a HIP graph
+ * and replays it for later such groups, whose tables are copied anew
+ * before the replay; 0 launches every kernel directly.  Results are the
+ * same either way.  Synchronises the stream.
  * lsr_batch_tune: times the next step under each candidate launch shape
  * (lanes per node, blocks per CU) without changing the jobs, keeps the
  * fastest and returns it with its time in ms (synchronises).  The choice is
@@ -211,7 +222,8 @@ lsr_status lsr_destroy(lsr_job* job);
  * jobs per interpolator, total grid nodes rounded up to a power of two); a
  * later call with the same signature applies it without timing and returns
  * the time measured then.
- * lsr_batch_destroy: removes the members, waits for the stream. */
+ * lsr_batch_destroy: removes the members, waits for the stream and
+ * releases the batch's graphs, second stream and events. */
 lsr_status lsr_batch_workspace_bytes(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
                                      size_t* bytes);
 lsr_status lsr_batch_create(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
