@@ -570,7 +570,10 @@ __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restri
 // One chunk of the Gbar scan: 4 sub-chunks of 256 nodes (in 3D, 4 bricks of
 // 4 x 8 x 8 nodes in local order), one node of each per thread, the values
 // read together and the members appended in node order with one atomic.
-constexpr uint32_t GBAR_SUB = 4, GBAR_CHUNK = 256 * GBAR_SUB;
+#ifndef LSR_GBAR_SUB
+#define LSR_GBAR_SUB 8
+#endif
+constexpr uint32_t GBAR_SUB = LSR_GBAR_SUB, GBAR_CHUNK = 256 * GBAR_SUB;
 
 template <int DIM>
 __device__ __forceinline__ bool gbar_node(const DevGrid& g, uint32_t sub, int& i, int& j, int& k) {
@@ -799,25 +802,38 @@ __global__ __launch_bounds__(256) void k_reinit_iter_batch(const RArgs<T>* __res
 }
 
 // Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
+// A block takes FIN_SUB sub-chunks of 256 entries per list append: this
+// kernel is short and its blocks finish together, so one atomic on the list
+// counter per 256 entries would queue up at the end of the launch.
+#ifndef LSR_FIN_SUB
+#define LSR_FIN_SUB 4
+#endif
+constexpr uint32_t FIN_SUB = LSR_FIN_SUB, FIN_CHUNK = 256 * FIN_SUB;
+
 template <typename T>
 __device__ __forceinline__ void final_chunk(const FinArgs<T>& a, uint32_t base, int n, int* lds) {
   const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
   const gwptr<T> cur = (gwptr<T>)a.cur;
   const gwptr<T> other = (gwptr<T>)a.other;
-  const uint32_t e = base + threadIdx.x;
-  bool in = false;
-  uint32_t code = 0;
-  if (e < (uint32_t)n) {
-    code = M[e];
-    int i, j, k;
-    decode(a.g, code, i, j, k);
-    const uint32_t idx = lin(a.g, i, j, k);
-    const T v = fmin(fmax(cur[idx], -a.gamma), a.gamma);
-    cur[idx] = v;
-    other[idx] = v;
-    in = fabs(v) < a.gamma;
+  bool in[FIN_SUB];
+  uint32_t code[FIN_SUB];
+#pragma unroll
+  for (uint32_t u = 0; u < FIN_SUB; ++u) {
+    const uint32_t e = base + u * 256u + threadIdx.x;
+    in[u] = false;
+    code[u] = 0;
+    if (e < (uint32_t)n) {
+      code[u] = M[e];
+      int i, j, k;
+      decode(a.g, code[u], i, j, k);
+      const uint32_t idx = lin(a.g, i, j, k);
+      const T v = fmin(fmax(cur[idx], -a.gamma), a.gamma);
+      cur[idx] = v;
+      other[idx] = v;
+      in[u] = fabs(v) < a.gamma;
+    }
   }
-  block_append1(in, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds);
+  block_append<FIN_SUB>(in, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds);
 }
 
 template <typename T>
@@ -827,7 +843,7 @@ __global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
   const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * 256u;
+    const uint32_t base = chunk_of(q, xcd) * FIN_CHUNK;
     if (base >= (uint32_t)n) break;
     final_chunk<T>(a, base, n, lds);
   }
@@ -844,8 +860,8 @@ __global__ __launch_bounds__(256) void k_reinit_final_batch(const FinArgs<T>* __
   auto leave = [](int) {};
   for (uint32_t q = blockIdx.x / 8u;; q += nper) {
     const uint32_t gch = chunk_of(q, xcd);
-    if (!cur.advance(tab, gch, 256u, leave)) break;
-    final_chunk<T>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl, lds);
+    if (!cur.advance(tab, gch, FIN_CHUNK, leave)) break;
+    final_chunk<T>(uniform_load(tab, cur.jb), (gch - cur.beg) * FIN_CHUNK, cur.nl, lds);
   }
 }
 
