@@ -38,8 +38,8 @@ int64_t node_count(const lsr_grid& g) {
   return g.dim == 3 ? N * g.n[2] : N;
 }
 
-void bin_counts(const lsr_grid& g, int nb[3]) {
-  for (int a = 0; a < 3; ++a) nb[a] = a < g.dim ? (g.n[a] - 1) / BIN_W + 1 : 1;
+void bin_counts(const lsr_grid& g, int width, int nb[3]) {
+  for (int a = 0; a < 3; ++a) nb[a] = a < g.dim ? (g.n[a] - 1) / width + 1 : 1;
 }
 
 Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
@@ -47,7 +47,7 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   const size_t N = (size_t)node_count(g);
   const size_t P = (size_t)(max_points > 0 ? max_points : 1);
   const size_t es = fp64 ? 8 : 4;
-  bin_counts(g, L.nb);
+  bin_counts(g, BIN_W_FINE, L.nb);  // room for the bins of either width
   L.nbins = (int64_t)L.nb[0] * L.nb[1] * L.nb[2];
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -79,6 +79,7 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.bin_start = take(4 * ((size_t)L.nbins + 1));
   L.bin_fill = take(4 * (size_t)L.nbins);
   L.occ = take(4 * (size_t)L.nbins);
+  L.scan_tmp = take(4 * (2 * (size_t)SCAN_TILES + 1));
   L.total = off;
   return L;
 }
@@ -431,14 +432,17 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   d.lo0 = g.lo[0];
   d.lo1 = g.lo[1];
   d.lo2 = g.lo[2];
-  BinGeom& b = j->bg;
-  for (int a = 0; a < 3; ++a) {
-    b.nb[a] = L.nb[a];
-    b.lo[a] = g.lo[a];
-    b.hi[a] = a < g.dim ? g.lo[a] + (g.n[a] - 1) * g.h : g.lo[a];
+  for (int q = 0; q < 2; ++q) {
+    const int width = q == 0 ? BIN_W : BIN_W_FINE;
+    BinGeom& b = q == 0 ? j->bg : j->bg_fine;
+    bin_counts(g, width, b.nb);
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = g.lo[a];
+      b.hi[a] = a < g.dim ? g.lo[a] + (g.n[a] - 1) * g.h : g.lo[a];
+    }
+    b.bw = width * g.h;
+    b.inv_bw = 1.0 / b.bw;
   }
-  b.bw = BIN_W * g.h;
-  b.inv_bw = 1.0 / b.bw;
 
   char* w = j->ws;
   j->phi[0] = (void*)(w + L.phi0);
@@ -464,6 +468,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->bin_start = (int32_t*)(w + L.bin_start);
   j->bin_fill = (int32_t*)(w + L.bin_fill);
   j->occ = (uint32_t*)(w + L.occ);
+  j->scan_tmp = (int32_t*)(w + L.scan_tmp);
   j->ncu = ncu > 0 ? ncu : 256;
   j->lanes = 1;
   j->blocks_per_cu = 8;
@@ -499,24 +504,38 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   if (n > j->max_points) return fail(LSR_E_NOMEM, "cloud larger than the workspace allows");
   hipStream_t s = j->stream;
   const int dim = j->grid.dim;
-  const int32_t nbins = (int32_t)j->L.nbins;
   LSR_HIP(hipMemcpyAsync(j->pts_raw, dev_xyz, sizeof(double) * dim * (size_t)n,
                          hipMemcpyDeviceToDevice, s));
-  LSR_HIP(launch_fill_u32((uint32_t*)j->bin_count, 0u, (uint64_t)nbins, s));
-  LSR_HIP(launch_fill_u32((uint32_t*)j->bin_fill, 0u, (uint64_t)nbins, s));
-  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s));
-  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 5), 0u, 1, s));
-  LSR_HIP(launch_bin_points(dim, j->bg, j->pts_raw, n, j->bin_count, j->pt_bin, j->cnt + 3, s));
-  int32_t flag = 0;
-  LSR_HIP(hipMemcpyAsync(&flag, j->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // bin at the standard width; validate the points and count occupied bins
+  auto bin = [&](const BinGeom& bg) -> hipError_t {
+    const int32_t nb = bg.nb[0] * bg.nb[1] * bg.nb[2];
+    hipError_t e = launch_fill_u32((uint32_t*)j->bin_count, 0u, (uint64_t)nb, s);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)(j->cnt + 6), 0u, 1, s);
+    if (e == hipSuccess)
+      e = launch_bin_points(dim, bg, j->pts_raw, n, j->bin_count, j->pt_bin, j->cnt + 3,
+                            j->cnt + 6, s);
+    return e;
+  };
+  LSR_HIP(bin(j->bg));
+  int32_t got[4] = {0, 0, 0, 0};  // flag, -, -, occupied bins
+  LSR_HIP(hipMemcpyAsync(got, j->cnt + 3, sizeof(got), hipMemcpyDeviceToHost, s));
   LSR_HIP(hipStreamSynchronize(s));
-  if (flag) return fail(LSR_E_INVALID, "cloud has a non-finite point or one outside the grid box");
-  LSR_HIP(launch_scan_bins(j->bin_count, nbins, j->bin_start, s));
+  if (got[0]) return fail(LSR_E_INVALID, "cloud has a non-finite point or one outside the grid box");
+  // a dense cloud (many points per occupied bin) gets the finer bins: the
+  // nodes of a brick then scan fewer points per bin they cannot rule out
+  const bool fine = got[3] > 0 && n > (int64_t)DENSE_BIN * got[3];
+  const BinGeom& bg = fine ? j->bg_fine : j->bg;
+  if (fine) LSR_HIP(bin(bg));
+  const int32_t nbins = bg.nb[0] * bg.nb[1] * bg.nb[2];
+  LSR_HIP(launch_fill_u32((uint32_t*)j->bin_fill, 0u, (uint64_t)nbins, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 5), 0u, 1, s));
+  LSR_HIP(launch_scan_bins(j->bin_count, nbins, j->bin_start, j->scan_tmp, s));
   LSR_HIP(launch_occupied(j->bin_start, nbins, j->occ, j->cnt + 5, s));
   LSR_HIP(launch_scatter_points(dim, j->pts_raw, n, j->pt_bin, j->bin_start, j->bin_fill, j->pts, s));
   DistArgs da;
   da.g = j->dg;
-  da.bg = j->bg;
+  da.bg = bg;
   da.pts = j->pts;
   da.start = j->bin_start;
   da.occ = j->occ;

@@ -19,8 +19,13 @@ __host__ __device__ inline size_t stat_index(int counter, int slot) {
   return ((size_t)counter * STAT_SLOTS + (size_t)slot) * STAT_STRIDE;
 }
 
-// Cloud bins: cubes of BIN_W nodes per side.
-constexpr int BIN_W = 4;
+// Cloud bins: cubes of BIN_W nodes per side, or of BIN_W_FINE nodes for
+// dense clouds (more than DENSE_BIN points per occupied BIN_W bin); the
+// workspace holds the bins of the finer width.
+constexpr int BIN_W = 4, BIN_W_FINE = 2, DENSE_BIN = 100;
+// Bin-count scans: one block up to SCAN_ONE_BLOCK bins, else at most
+// SCAN_TILES tiles (scratch of 2 * SCAN_TILES + 1 ints).
+constexpr int32_t SCAN_ONE_BLOCK = 65536, SCAN_TILES = 1024;
 
 struct BinGeom {
   int nb[3];        // bins per axis (nb[2] = 1 in 2D)
@@ -137,9 +142,15 @@ template <typename T>
 hipError_t launch_reinit_iter(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_final(const FinArgs<T>& a, unsigned blocks, hipStream_t s);
+// bin_count[] counts the points per bin, *occupied the bins it makes
+// non-empty; *flag |= 1 for a non-finite point or one outside the box.
 hipError_t launch_bin_points(int dim, const BinGeom& bg, const double* pts, int64_t n,
-                             int32_t* bin_count, int32_t* pt_bin, int32_t* flag, hipStream_t s);
-hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start, hipStream_t s);
+                             int32_t* bin_count, int32_t* pt_bin, int32_t* flag,
+                             int32_t* occupied, hipStream_t s);
+// Exclusive scan of nbins counts into start[0 .. nbins] (tmp: scratch of
+// 2 * SCAN_TILES + 1 ints).
+hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start, int32_t* tmp,
+                            hipStream_t s);
 hipError_t launch_occupied(const int32_t* start, int32_t nbins, uint32_t* occ, int32_t* cnt,
                            hipStream_t s);
 hipError_t launch_scatter_points(int dim, const double* pts, int64_t n, const int32_t* pt_bin,

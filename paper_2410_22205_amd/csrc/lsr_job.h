@@ -29,7 +29,7 @@ struct Layout {
   size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, cnt, stats;
   size_t blist0, blist1, bstamp;  // brick lists and stamps of the staged 3D step
   int64_t nbricks;
-  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ;
+  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp;
   size_t total;
   int nb[3];
   int64_t nbins;
@@ -47,7 +47,7 @@ struct lsr_job {
   lsr::Layout L;
   int64_t max_points;
   lsr::DevGrid dg;
-  lsr::BinGeom bg;
+  lsr::BinGeom bg, bg_fine;  // cloud bins of the standard and the finer width
   void* phi[2];
   void* dp;
   double* d64;
@@ -55,7 +55,8 @@ struct lsr_job {
   uint32_t* listM;
   uint8_t* mflags;
   int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins,
-                 // [8..10] brick-count ring (staged 3D step)
+                 // [6] bins a cloud's points occupy (density check), [8..10] brick-count
+                 // ring (staged 3D step)
   unsigned long long* stats;
   double* pts_raw;
   double* pts;
@@ -64,6 +65,7 @@ struct lsr_job {
   int32_t* bin_start;
   int32_t* bin_fill;
   uint32_t* occ;
+  int32_t* scan_tmp;
   uint32_t* blist[2];
   uint32_t* bstamp;
   int cur_blist;       // brick list buffer holding the current brick list

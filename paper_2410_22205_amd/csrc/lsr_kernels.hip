@@ -872,7 +872,7 @@ __global__ __launch_bounds__(256) void k_reinit_final_batch(const FinArgs<T>* __
 template <int DIM>
 __global__ void k_bin_points(BinGeom bg, const double* __restrict__ pts, int64_t n,
                              int32_t* __restrict__ bin_count, int32_t* __restrict__ pt_bin,
-                             int32_t* flag) {
+                             int32_t* flag, int32_t* occupied) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     bool ok = true;
@@ -891,7 +891,7 @@ __global__ void k_bin_points(BinGeom bg, const double* __restrict__ pts, int64_t
       continue;
     }
     const int id = (b[0] * bg.nb[1] + b[1]) * bg.nb[2] + b[2];
-    atomicAdd(&bin_count[id], 1);
+    if (atomicAdd(&bin_count[id], 1) == 0) atomicAdd(occupied, 1);  // the bin's first point
     pt_bin[p] = id;
   }
 }
@@ -920,6 +920,52 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const int32_t* __restrict__ 
     run += count[b];
   }
   if (t == 1023) start[nbins] = part[1023];
+}
+
+// The same exclusive scan for many bins, coalesced, in three launches:
+// k_scan_tiles sums tiles of `tile` counts, k_scan_bins scans the tile sums,
+// k_scan_apply scans each tile in passes of 256 from its tile's offset.
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* __restrict__ count,
+                                                    int32_t nbins, int32_t tile,
+                                                    int32_t* __restrict__ sums) {
+  __shared__ int32_t ws[4];
+  const int64_t b0 = (int64_t)blockIdx.x * tile, b1 = min(b0 + (int64_t)tile, (int64_t)nbins);
+  int32_t v = 0;
+  for (int64_t q = b0 + threadIdx.x; q < b1; q += 256) v += count[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane_id() == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ count,
+                                                    int32_t nbins, int32_t tile,
+                                                    const int32_t* __restrict__ offs,
+                                                    int32_t* __restrict__ start) {
+  __shared__ int32_t ws[4];
+  const int64_t b0 = (int64_t)blockIdx.x * tile, b1 = min(b0 + (int64_t)tile, (int64_t)nbins);
+  const int w = (int)(threadIdx.x >> 6), l = (int)lane_id();
+  int32_t run = offs[blockIdx.x];
+  for (int64_t base = b0; base < b1; base += 256) {
+    const int64_t q = base + threadIdx.x;
+    const int32_t v = q < b1 ? count[q] : 0;
+    int32_t x = v;  // inclusive scan within the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(x, off);
+      if (l >= off) x += y;
+    }
+    if (l == 63) ws[w] = x;
+    __syncthreads();
+    int32_t wo = 0;
+    for (int q2 = 0; q2 < w; ++q2) wo += ws[q2];
+    const int32_t total = ws[0] + ws[1] + ws[2] + ws[3];
+    if (q < b1) start[q] = run + wo + x - v;
+    __syncthreads();
+    run += total;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) start[nbins] = run;
 }
 
 __global__ __launch_bounds__(256) void k_occupied(const int32_t* __restrict__ start, int32_t nbins,
@@ -1394,17 +1440,33 @@ hipError_t launch_reinit_final(const FinArgs<T>& a, unsigned blocks, hipStream_t
 }
 
 hipError_t launch_bin_points(int dim, const BinGeom& bg, const double* pts, int64_t n,
-                             int32_t* bin_count, int32_t* pt_bin, int32_t* flag, hipStream_t s) {
+                             int32_t* bin_count, int32_t* pt_bin, int32_t* flag,
+                             int32_t* occupied, hipStream_t s) {
   dim3 gr(grid_for((uint64_t)n, 256, 4096)), bl(256);
   if (dim == 3)
-    hipLaunchKernelGGL(k_bin_points<3>, gr, bl, 0, s, bg, pts, n, bin_count, pt_bin, flag);
+    hipLaunchKernelGGL(k_bin_points<3>, gr, bl, 0, s, bg, pts, n, bin_count, pt_bin, flag,
+                       occupied);
   else
-    hipLaunchKernelGGL(k_bin_points<2>, gr, bl, 0, s, bg, pts, n, bin_count, pt_bin, flag);
+    hipLaunchKernelGGL(k_bin_points<2>, gr, bl, 0, s, bg, pts, n, bin_count, pt_bin, flag,
+                       occupied);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, count, nbins, start);
+hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start, int32_t* tmp,
+                            hipStream_t s) {
+  if (nbins <= SCAN_ONE_BLOCK) {
+    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, count, nbins, start);
+    return hipGetLastError();
+  }
+  // at most SCAN_TILES tiles of a multiple of 256 counts
+  const int64_t per = ((int64_t)nbins + SCAN_TILES - 1) / SCAN_TILES;
+  const int32_t tile = (int32_t)std::max<int64_t>(4096, (per + 255) / 256 * 256);
+  const int32_t ntiles = (int32_t)(((int64_t)nbins + tile - 1) / tile);
+  int32_t* sums = tmp;
+  int32_t* offs = tmp + SCAN_TILES;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, count, nbins, tile, sums);
+  hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, sums, ntiles, offs);
+  hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(256), 0, s, count, nbins, tile, offs, start);
   return hipGetLastError();
 }
 
