@@ -5,6 +5,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -80,6 +82,9 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.bin_fill = take(4 * (size_t)L.nbins);
   L.occ = take(4 * (size_t)L.nbins);
   L.scan_tmp = take(4 * (2 * (size_t)SCAN_TILES + 1));
+  // bin frames: at most one per point and one per bin
+  L.max_occ = (int64_t)std::min((size_t)L.nbins, P);
+  L.geo = take(8 * (size_t)GEO * (size_t)L.max_occ);
   L.total = off;
   return L;
 }
@@ -469,6 +474,8 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->bin_fill = (int32_t*)(w + L.bin_fill);
   j->occ = (uint32_t*)(w + L.occ);
   j->scan_tmp = (int32_t*)(w + L.scan_tmp);
+  j->geo = (double*)(w + L.geo);
+  j->max_occ = L.max_occ;
   j->ncu = ncu > 0 ? ncu : 256;
   j->lanes = 1;
   j->blocks_per_cu = 8;
@@ -533,6 +540,8 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   LSR_HIP(launch_scan_bins(j->bin_count, nbins, j->bin_start, j->scan_tmp, s));
   LSR_HIP(launch_occupied(j->bin_start, nbins, j->occ, j->cnt + 5, s));
   LSR_HIP(launch_scatter_points(dim, j->pts_raw, n, j->pt_bin, j->bin_start, j->bin_fill, j->pts, s));
+  LSR_HIP(launch_bin_geo(dim, j->pts, j->bin_start, j->occ, j->cnt + 5, j->geo,
+                         std::min(j->max_occ, (int64_t)nbins), s));
   DistArgs da;
   da.g = j->dg;
   da.bg = bg;
@@ -540,6 +549,16 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   da.start = j->bin_start;
   da.occ = j->occ;
   da.occ_cnt = j->cnt + 5;
+  da.geo = j->geo;
+  {
+    // margins that cover the rounding of the frame bounds: every coordinate
+    // lies in the grid's box
+    double diag2 = 0.0;
+    for (int ax = 0; ax < dim; ++ax) diag2 += (bg.hi[ax] - bg.lo[ax]) * (bg.hi[ax] - bg.lo[ax]);
+    const double diag = std::max(std::sqrt(diag2), j->grid.h);
+    da.mu = 1e-12 * diag;
+    da.mu2 = 1e-12 * diag * diag;
+  }
   da.d64 = j->d64;
   const int BS = dim == 3 ? 8 : 16;
   unsigned bricks = (unsigned)(((j->dg.n0 + BS - 1) / BS) * ((j->dg.n1 + BS - 1) / BS) *

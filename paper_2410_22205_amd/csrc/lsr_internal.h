@@ -99,6 +99,21 @@ struct FinArgs {
   int32_t* cnt_reset;
 };
 
+// Bounding frame of the points of one occupied bin, GEO doubles per bin at
+// the bin's place t in the occupied list:
+//   [0..2]  m, the mean of the points
+//   [3..5]  nv, a unit vector along which the points spread least (any unit
+//           vector keeps the bounds valid; this one makes them tight)
+//   [6..8]  E, the largest |p_k - m_k| per axis
+//   [9, 10] tmin, tmax, the range of nv . (p - m)
+//   [11]    rt, the largest distance of p - m from the line along nv
+//   [12]    rf, the largest |p - m|
+//   [13]    the bin's point range, two int32 (begin, end)
+// For any x, with a = nv . (x - m) and tau the distance of x - m from that
+// line, every point p of the bin has
+//   |x - p|^2 >= gap(a, [tmin, tmax])^2 + max(tau - rt, 0)^2.
+constexpr int GEO = 16;
+
 struct DistArgs {
   DevGrid g;
   BinGeom bg;
@@ -106,6 +121,9 @@ struct DistArgs {
   const int32_t* start;   // bin start offsets, nbins + 1
   const uint32_t* occ;    // occupied bin ids
   const int32_t* occ_cnt;
+  const double* geo;      // GEO doubles per occupied bin
+  double mu;              // distance margin that covers rounding (1e-12 x box diagonal)
+  double mu2;             // the same for squared distances (1e-12 x diagonal^2)
   double* d64;
 };
 
@@ -156,6 +174,9 @@ hipError_t launch_occupied(const int32_t* start, int32_t nbins, uint32_t* occ, i
 hipError_t launch_scatter_points(int dim, const double* pts, int64_t n, const int32_t* pt_bin,
                                  const int32_t* start, int32_t* fill, double* sorted,
                                  hipStream_t s);
+// Bounding frames of the occupied bins (GEO doubles each, at most max_occ bins).
+hipError_t launch_bin_geo(int dim, const double* pts, const int32_t* start, const uint32_t* occ,
+                          const int32_t* occ_cnt, double* geo, int64_t max_occ, hipStream_t s);
 hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s);
 template <typename T>
 hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,

@@ -29,7 +29,8 @@ struct Layout {
   size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, cnt, stats;
   size_t blist0, blist1, bstamp;  // brick lists and stamps of the staged 3D step
   int64_t nbricks;
-  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp;
+  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo;
+  int64_t max_occ;
   size_t total;
   int nb[3];
   int64_t nbins;
@@ -66,6 +67,8 @@ struct lsr_job {
   int32_t* bin_fill;
   uint32_t* occ;
   int32_t* scan_tmp;
+  double* geo;      // bin frames, GEO doubles per occupied bin
+  int64_t max_occ;  // room for frames
   uint32_t* blist[2];
   uint32_t* bstamp;
   int cur_blist;       // brick list buffer holding the current brick list

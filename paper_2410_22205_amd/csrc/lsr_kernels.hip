@@ -1005,6 +1005,203 @@ __device__ __forceinline__ double block_min(double v, double* red) {
   return r;
 }
 
+// One bin's frame as a whole (see GEO).
+struct Frame {
+  double w[GEO];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// A unit vector along which points with (unnormalised) covariance C spread
+// least: the eigenvector of the smallest eigenvalue, found from the closed
+// form of the eigenvalues of a symmetric 2 x 2 or 3 x 3 matrix.  Degenerate
+// spreads (a single point, a line, an isotropic cloud) fall back to the axis
+// of least variance; the bounds that use it hold for any unit vector.
+template <int DIM>
+__device__ void least_spread(const double C[3][3], double nv[3]) {
+  double v[3] = {0.0, 0.0, 0.0};
+  if (DIM == 2) {
+    const double a = C[0][0], b = C[0][1], c = C[1][1];
+    const double lam = 0.5 * (a + c) - sqrt(0.25 * (a - c) * (a - c) + b * b);
+    const double n1 = b * b + (lam - a) * (lam - a), n2 = (lam - c) * (lam - c) + b * b;
+    if (n1 >= n2) {
+      v[0] = b;
+      v[1] = lam - a;
+    } else {
+      v[0] = lam - c;
+      v[1] = b;
+    }
+  } else {
+    const double p1 = C[0][1] * C[0][1] + C[0][2] * C[0][2] + C[1][2] * C[1][2];
+    const double q = (C[0][0] + C[1][1] + C[2][2]) / 3.0;
+    const double b0 = C[0][0] - q, b1 = C[1][1] - q, b2 = C[2][2] - q;
+    const double p2 = b0 * b0 + b1 * b1 + b2 * b2 + 2.0 * p1;
+    double lam = q;
+    if (p2 > 0.0) {
+      const double pp = sqrt(p2 / 6.0);
+      const double det = b0 * (b1 * b2 - C[1][2] * C[1][2]) -
+                         C[0][1] * (C[0][1] * b2 - C[1][2] * C[0][2]) +
+                         C[0][2] * (C[0][1] * C[1][2] - b1 * C[0][2]);
+      const double r = fmin(fmax(det / (2.0 * pp * pp * pp), -1.0), 1.0);
+      lam = q + 2.0 * pp * cos(acos(r) / 3.0 + 2.0943951023931957);  // + 2 pi / 3
+    }
+    const double M[3][3] = {{C[0][0] - lam, C[0][1], C[0][2]},
+                            {C[0][1], C[1][1] - lam, C[1][2]},
+                            {C[0][2], C[1][2], C[2][2] - lam}};
+    double best = -1.0;
+#pragma unroll
+    for (int q0 = 0; q0 < 3; ++q0) {
+      const int ra = q0 == 2 ? 1 : 0, rb = q0 == 0 ? 1 : 2;
+      const double x[3] = {M[ra][1] * M[rb][2] - M[ra][2] * M[rb][1],
+                           M[ra][2] * M[rb][0] - M[ra][0] * M[rb][2],
+                           M[ra][0] * M[rb][1] - M[ra][1] * M[rb][0]};
+      const double n2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      if (n2 > best) {
+        best = n2;
+        v[0] = x[0];
+        v[1] = x[1];
+        v[2] = x[2];
+      }
+    }
+  }
+  double n2 = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) n2 += v[ax] * v[ax];
+  if (!(n2 > 0.0) || !isfinite(n2)) {
+    int k = 0;
+#pragma unroll
+    for (int ax = 1; ax < DIM; ++ax)
+      if (C[ax][ax] < C[k][k]) k = ax;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) v[ax] = ax == k ? 1.0 : 0.0;
+    n2 = 1.0;
+  }
+  const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) nv[ax] = ax < DIM ? v[ax] * inv : 0.0;
+}
+
+// Bounding frame (see GEO) of each occupied bin's points, one wave per bin.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_bin_geo(const double* __restrict__ pts,
+                                                 const int32_t* __restrict__ start,
+                                                 const uint32_t* __restrict__ occ,
+                                                 const int32_t* __restrict__ occ_cnt,
+                                                 double* __restrict__ geo) {
+  const int nocc = *occ_cnt;
+  const int l = (int)lane_id();
+  const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+  for (int t = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < nocc; t += nw) {
+    const uint32_t id = occ[t];
+    const int p0 = start[id], p1 = start[id + 1];
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int p = p0 + l; p < p1; p += 64)
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) m[ax] += pts[(int64_t)p * DIM + ax];
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) m[ax] = wave_sum(m[ax]) / (double)(p1 - p0);
+    double C[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int p = p0 + l; p < p1; p += 64) {
+      double v[3];
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) v[ax] = pts[(int64_t)p * DIM + ax] - m[ax];
+#pragma unroll
+      for (int r = 0; r < DIM; ++r)
+#pragma unroll
+        for (int c = r; c < DIM; ++c) C[r][c] += v[r] * v[c];
+    }
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+      for (int c = r; c < DIM; ++c) {
+        C[r][c] = wave_sum(C[r][c]);
+        C[c][r] = C[r][c];
+      }
+    double nv[3];
+    least_spread<DIM>(C, nv);
+    double tmin = INFINITY, tmax = -INFINITY, rt2 = 0.0, rf2 = 0.0, E[3] = {0.0, 0.0, 0.0};
+    for (int p = p0 + l; p < p1; p += 64) {
+      double v[3], a = 0.0, r2 = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        v[ax] = pts[(int64_t)p * DIM + ax] - m[ax];
+        a += nv[ax] * v[ax];
+        r2 += v[ax] * v[ax];
+        E[ax] = fmax(E[ax], fabs(v[ax]));
+      }
+      double w2 = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        const double w = v[ax] - a * nv[ax];
+        w2 += w * w;
+      }
+      tmin = fmin(tmin, a);
+      tmax = fmax(tmax, a);
+      rt2 = fmax(rt2, w2);
+      rf2 = fmax(rf2, r2);
+    }
+    tmin = wave_min(tmin);
+    tmax = wave_max(tmax);
+    rt2 = wave_max(rt2);
+    rf2 = wave_max(rf2);
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) E[ax] = wave_max(E[ax]);
+    if (l == 0) {
+      double* G = geo + (size_t)t * GEO;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        G[ax] = ax < DIM ? m[ax] : 0.0;
+        G[3 + ax] = nv[ax];
+        G[6 + ax] = ax < DIM ? E[ax] : 0.0;
+      }
+      G[9] = tmin;
+      G[10] = tmax;
+      G[11] = sqrt(rt2);
+      G[12] = sqrt(rf2);
+      int32_t* r = (int32_t*)(G + 13);
+      r[0] = p0;
+      r[1] = p1;
+    }
+  }
+}
+
+// Lower bound of |x - p|^2 over the points p of a bin with frame G (see
+// GEO), each of its two parts lowered by mu, which covers the rounding of
+// the frame and of this evaluation.
+template <int DIM>
+__device__ __forceinline__ double frame_lb2(const double* G, const double x[3], double mu) {
+  double v[3], a = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) {
+    v[ax] = x[ax] - G[ax];
+    a += G[3 + ax] * v[ax];
+  }
+  double w2 = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) {
+    const double w = v[ax] - a * G[3 + ax];
+    w2 += w * w;
+  }
+  const double gn = fmax(fmax(G[9] - a, a - G[10]), 0.0) - mu;
+  const double gt = sqrt(w2) - G[11] - mu;
+  const double un = fmax(gn, 0.0), ut = fmax(gt, 0.0);
+  return un * un + ut * ut;
+}
+
 template <int DIM>
 __device__ __forceinline__ void bin_box(const BinGeom& bg, uint32_t id, double lo[3], double hi[3]) {
   int b2 = (int)(id % (uint32_t)bg.nb[2]);
@@ -1038,15 +1235,23 @@ __device__ __forceinline__ void dist_node(int u, int& li, int& lj, int& lk) {
 }
 
 // Exact distance to the cloud at the nodes of one brick (8^3 nodes in 3D,
-// 16^2 in 2D) per workgroup.  With c the brick centre, rho its half diagonal
-// and U = d(c), every node's nearest point lies within U + 2 rho of c; U is
-// found exactly from the occupied bins whose box can hold a point closer
-// than the best far-corner bound.  The occupied bins whose box meets the
-// ball of radius U + 2 rho are then visited nearest first, and a wave scans
-// a bin's points only if one of its nodes could still find a closer point
-// there.  The minimum is taken over exactly the pairs that can attain it,
-// so the result does not depend on the order.  All distance arithmetic in
-// double.
+// 16^2 in 2D) per workgroup.  With c the brick centre, e its half extents
+// and rho its half diagonal:
+//  1. d(c) and a point p* that attains it are found exactly, from the
+//     occupied bins whose box and frame can hold a point closer than the
+//     best far-corner bound;
+//  2. a bin can hold a point closer to a node x of the brick than p* only
+//     if its box meets the ball (c, d(c) + 2 rho), and only if
+//     |c - y|^2 - |c - p*|^2 <= 2 sum_k e_k |y_k - p*_k| for some y in it
+//     (|x - y|^2 - |x - p*|^2 is linear in x, so its least value over the
+//     brick's box is attained at a corner); the bins that pass both, the
+//     candidates, are ordered by their frame's distance from c in NSH
+//     shells (counting sort), so that nodes meet close points first;
+//  3. every node starts from |x - p*|, and a wave scans a candidate's points
+//     only if one of its nodes could still find a closer point there by the
+//     frame bound.
+// The minimum is taken over all pairs that can attain it, so the result
+// does not depend on the order.  All distance arithmetic in double.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   // no FMA contraction: node coordinates lo + i h and the sums of squares are
@@ -1070,16 +1275,17 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   const int l[3] = {min(f[0] + BS, g.n0) - 1, min(f[1] + BS, g.n1) - 1,
                     DIM == 3 ? min(f[2] + BS, g.n2) - 1 : 0};
   const double glo[3] = {g.lo0, g.lo1, g.lo2};
-  double c[3], rho2 = 0.0;
+  double c[3], e[3], rho2 = 0.0;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     c[ax] = ax < DIM ? glo[ax] + g.hd * 0.5 * (f[ax] + l[ax]) : 0.0;
-    const double e = 0.5 * g.hd * (l[ax] - f[ax]);
-    rho2 += e * e;
+    e[ax] = 0.5 * g.hd * (l[ax] - f[ax]);
+    rho2 += e[ax] * e[ax];
   }
   const double rho = sqrt(rho2);
   const int nocc = *a.occ_cnt;
   const double slack = 1.0 + 1e-12;
+  const double mu = a.mu;
 
   // far-corner bound: every occupied box holds a point no farther than it
   double ub2 = INFINITY;
@@ -1100,9 +1306,8 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   double best = INFINITY;
   int bidx = -1;
   for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
-    const uint32_t id = a.occ[t];
     double lo[3], hi[3];
-    bin_box<DIM>(a.bg, id, lo, hi);
+    bin_box<DIM>(a.bg, a.occ[t], lo, hi);
     double s = 0.0;
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) {
@@ -1110,7 +1315,10 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
       s += q * q;
     }
     if (s > ub2) continue;
-    for (int q = a.start[id]; q < a.start[id + 1]; ++q) {
+    const double* G = a.geo + (size_t)t * GEO;
+    if (frame_lb2<DIM>(G, c, mu) > ub2) continue;
+    const int2 rng = *(const int2*)(G + 13);
+    for (int q = rng.x; q < rng.y; ++q) {
       double s2 = 0.0;
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) {
@@ -1131,40 +1339,54 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   const double R = sqrt(best) + 2.0 * rho;
   const double R2 = R * R * slack;
 
-  // occupied bins whose box meets the ball (c, R), ordered by the box's
-  // distance from c in NSH shells (counting sort), so that the nodes meet
-  // close points first and can pass over the bins beyond their best
+  // candidate bins (step 2), ordered by the box's distance from c in NSH
+  // shells (counting sort)
   constexpr int NSH = 32;
   __shared__ int shell_n[NSH], shell_at[NSH];
   if (threadIdx.x < NSH) shell_n[threadIdx.x] = 0;
   if (threadIdx.x == 0) ncand = 0;
   __syncthreads();
-  // every occupied box lies at least d(c) - (box diagonal) from c
+  const bool havep = pstar != INT_MAX;
+  double P[3] = {0.0, 0.0, 0.0};
+  if (havep)
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) P[ax] = a.pts[(int64_t)pstar * DIM + ax];
+  // every candidate frame lies at least d(c) - (box diagonal) from c
   const double s0 = fmax(sqrt(best) - a.bg.bw * sqrt((double)DIM), 0.0);
   const double shell_scale = NSH / fmax(R - s0, 1e-300);
-  auto shell_of = [&](double mind2) {
-    const int k = (int)((sqrt(mind2) - s0) * shell_scale);
-    return k < 0 ? 0 : (k > NSH - 1 ? NSH - 1 : k);
+  auto candidate = [&](int t, int* shell) -> bool {
+    double lo[3], hi[3];
+    bin_box<DIM>(a.bg, a.occ[t], lo, hi);
+    double s = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
+      s += q * q;
+    }
+    if (s > R2) return false;
+    const double* G = a.geo + (size_t)t * GEO;
+    const double lb2 = frame_lb2<DIM>(G, c, mu);
+    if (havep) {
+      // sum_k e_k max_y |y_k - p*_k| over the bin's points y
+      double w = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) w += e[ax] * (fabs(G[ax] - P[ax]) + G[6 + ax] + mu);
+      if (lb2 - best - 2.0 * w > a.mu2) return false;
+    }
+    const int k = (int)((sqrt(lb2) - s0) * shell_scale);
+    *shell = k < 0 ? 0 : (k > NSH - 1 ? NSH - 1 : k);
+    return true;
   };
   for (int pass = 0; pass < 2; ++pass) {
     for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
-      const uint32_t id = a.occ[t];
-      double lo[3], hi[3];
-      bin_box<DIM>(a.bg, id, lo, hi);
-      double s = 0.0;
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) {
-        const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
-        s += q * q;
-      }
-      if (s > R2) continue;
-      const int sh = shell_of(s);
+      int sh;
+      if (!candidate(t, &sh)) continue;
       if (pass == 0) {
         atomicAdd(&shell_n[sh], 1);
         atomicAdd(&ncand, 1);
       } else {
         const int pos = atomicAdd(&shell_at[sh], 1);
-        if (pos < CAP) cand[pos] = id;
+        if (pos < CAP) cand[pos] = (uint32_t)t;
       }
     }
     __syncthreads();
@@ -1192,49 +1414,37 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
     // start from the distance to the centre's nearest point, one of the
     // pairs the minimum runs over
     bn[u] = INFINITY;
-    if (pstar != INT_MAX) {
+    if (havep) {
       double s2 = 0.0;
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) {
-        const double t2 = x[u][ax] - a.pts[(int64_t)pstar * DIM + ax];
+        const double t2 = x[u][ax] - P[ax];
         s2 += t2 * t2;
       }
       bn[u] = s2;
     }
   }
-  // A wave passes over a bin when none of its nodes can find a closer point
-  // in it: the box, widened by a margin that covers the rounding of the
-  // binning, lies farther than every node's best so far.
-  const double margin = 1e-12 * a.bg.bw;
+  // A wave passes over a candidate when none of its nodes can find a closer
+  // point in it by the frame bound.  Beyond CAP candidates the occupied
+  // list is walked with the same candidate test.
   const int nloop = nc <= CAP ? nc : nocc;
   for (int q = 0; q < nloop; ++q) {
-    // the same bin for the whole block: decoded on the scalar unit
-    const uint32_t id = __builtin_amdgcn_readfirstlane(nc <= CAP ? cand[q] : a.occ[q]);
-    double lo[3], hi[3];
-    bin_box<DIM>(a.bg, id, lo, hi);
-    if (nc > CAP) {
-      double s = 0.0;
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) {
-        const double w = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
-        s += w * w;
-      }
-      if (s > R2) continue;
+    int t = q;
+    if (nc <= CAP) {
+      t = __builtin_amdgcn_readfirstlane(cand[q]);
+    } else {
+      int sh;
+      if (!candidate(q, &sh)) continue;
     }
+    // the same frame for the whole block: loaded through the scalar unit
+    const Frame F = uniform_load((const Frame*)a.geo, t);
     bool need = false;
 #pragma unroll
-    for (int u = 0; u < NPT; ++u) {
-      double s = 0.0;
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) {
-        const double w = fmax(fmax(lo[ax] - margin - x[u][ax], x[u][ax] - hi[ax] - margin), 0.0);
-        s += w * w;
-      }
-      need = need || (valid[u] && s <= bn[u] * slack);
-    }
+    for (int u = 0; u < NPT; ++u)
+      need = need || (valid[u] && frame_lb2<DIM>(F.w, x[u], mu) <= bn[u] * slack);
     if (!__any(need)) continue;
-    const int p1 = a.start[id + 1];
-    for (int p = a.start[id]; p < p1; ++p) {
+    const int2 rng = *(const int2*)(F.w + 13);
+    for (int p = rng.x; p < rng.y; ++p) {
       double Q[3];
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) Q[ax] = a.pts[(int64_t)p * DIM + ax];
@@ -1485,6 +1695,17 @@ hipError_t launch_scatter_points(int dim, const double* pts, int64_t n, const in
     hipLaunchKernelGGL(k_scatter_points<3>, gr, bl, 0, s, pts, n, pt_bin, start, fill, sorted);
   else
     hipLaunchKernelGGL(k_scatter_points<2>, gr, bl, 0, s, pts, n, pt_bin, start, fill, sorted);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_geo(int dim, const double* pts, const int32_t* start, const uint32_t* occ,
+                          const int32_t* occ_cnt, double* geo, int64_t max_occ, hipStream_t s) {
+  // one wave per bin, four per block, the grid walking the list if longer
+  dim3 gr(grid_for((uint64_t)max_occ, 4, 4096)), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_bin_geo<3>, gr, bl, 0, s, pts, start, occ, occ_cnt, geo);
+  else
+    hipLaunchKernelGGL(k_bin_geo<2>, gr, bl, 0, s, pts, start, occ, occ_cnt, geo);
   return hipGetLastError();
 }
 
