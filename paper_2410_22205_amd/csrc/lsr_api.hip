@@ -40,8 +40,21 @@ int64_t node_count(const lsr_grid& g) {
   return g.dim == 3 ? N * g.n[2] : N;
 }
 
-void bin_counts(const lsr_grid& g, int width, int nb[3]) {
-  for (int a = 0; a < 3; ++a) nb[a] = a < g.dim ? (g.n[a] - 1) / width + 1 : 1;
+// Cloud bins of `width` nodes per side over the grid's box, grouped in
+// super-bins (see SUP).
+BinGeom bin_geom(const lsr_grid& g, int width) {
+  BinGeom b;
+  for (int a = 0; a < 3; ++a) {
+    b.nb[a] = a < g.dim ? (g.n[a] - 1) / width + 1 : 1;
+    b.ns[a] = a < g.dim ? (b.nb[a] + SUP - 1) / SUP : 1;
+    b.lo[a] = g.lo[a];
+    b.hi[a] = a < g.dim ? g.lo[a] + (g.n[a] - 1) * g.h : g.lo[a];
+  }
+  b.kz = g.dim == 3 ? SUP : 1;
+  b.ksup = SUP * SUP * b.kz;
+  b.bw = width * g.h;
+  b.inv_bw = 1.0 / b.bw;
+  return b;
 }
 
 Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
@@ -49,8 +62,9 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   const size_t N = (size_t)node_count(g);
   const size_t P = (size_t)(max_points > 0 ? max_points : 1);
   const size_t es = fp64 ? 8 : 4;
-  bin_counts(g, BIN_W_FINE, L.nb);  // room for the bins of either width
-  L.nbins = (int64_t)L.nb[0] * L.nb[1] * L.nb[2];
+  const BinGeom fine = bin_geom(g, BIN_W_FINE);  // room for the bins of either width
+  L.nbins = bin_ids(fine);
+  const int64_t nsup = (int64_t)fine.ns[0] * fine.ns[1] * fine.ns[2];
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -85,6 +99,9 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   // bin frames: at most one per point and one per bin
   L.max_occ = (int64_t)std::min((size_t)L.nbins, P);
   L.geo = take(8 * (size_t)GEO * (size_t)L.max_occ);
+  L.max_sup = (int64_t)std::min((size_t)nsup, P);
+  L.sup = take(8 * (size_t)L.max_sup);
+  L.sgeo = take(8 * (size_t)GEO * (size_t)L.max_sup);
   L.total = off;
   return L;
 }
@@ -437,17 +454,8 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   d.lo0 = g.lo[0];
   d.lo1 = g.lo[1];
   d.lo2 = g.lo[2];
-  for (int q = 0; q < 2; ++q) {
-    const int width = q == 0 ? BIN_W : BIN_W_FINE;
-    BinGeom& b = q == 0 ? j->bg : j->bg_fine;
-    bin_counts(g, width, b.nb);
-    for (int a = 0; a < 3; ++a) {
-      b.lo[a] = g.lo[a];
-      b.hi[a] = a < g.dim ? g.lo[a] + (g.n[a] - 1) * g.h : g.lo[a];
-    }
-    b.bw = width * g.h;
-    b.inv_bw = 1.0 / b.bw;
-  }
+  j->bg = bin_geom(g, BIN_W);
+  j->bg_fine = bin_geom(g, BIN_W_FINE);
 
   char* w = j->ws;
   j->phi[0] = (void*)(w + L.phi0);
@@ -476,6 +484,9 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->scan_tmp = (int32_t*)(w + L.scan_tmp);
   j->geo = (double*)(w + L.geo);
   j->max_occ = L.max_occ;
+  j->sup = (int2*)(w + L.sup);
+  j->sgeo = (double*)(w + L.sgeo);
+  j->max_sup = L.max_sup;
   j->ncu = ncu > 0 ? ncu : 256;
   j->lanes = 1;
   j->blocks_per_cu = 8;
@@ -515,8 +526,7 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
                          hipMemcpyDeviceToDevice, s));
   // bin at the standard width; validate the points and count occupied bins
   auto bin = [&](const BinGeom& bg) -> hipError_t {
-    const int32_t nb = bg.nb[0] * bg.nb[1] * bg.nb[2];
-    hipError_t e = launch_fill_u32((uint32_t*)j->bin_count, 0u, (uint64_t)nb, s);
+    hipError_t e = launch_fill_u32((uint32_t*)j->bin_count, 0u, (uint64_t)bin_ids(bg), s);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)(j->cnt + 6), 0u, 1, s);
     if (e == hipSuccess)
@@ -534,14 +544,20 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   const bool fine = got[3] > 0 && n > (int64_t)DENSE_BIN * got[3];
   const BinGeom& bg = fine ? j->bg_fine : j->bg;
   if (fine) LSR_HIP(bin(bg));
-  const int32_t nbins = bg.nb[0] * bg.nb[1] * bg.nb[2];
+  const int32_t nbins = bin_ids(bg);
+  const int64_t max_occ = std::min(j->max_occ, (int64_t)nbins);
+  const int64_t max_sup =
+      std::min(j->max_sup, (int64_t)bg.ns[0] * bg.ns[1] * bg.ns[2]);
   LSR_HIP(launch_fill_u32((uint32_t*)j->bin_fill, 0u, (uint64_t)nbins, s));
   LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 5), 0u, 1, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 7), 0u, 1, s));
   LSR_HIP(launch_scan_bins(j->bin_count, nbins, j->bin_start, j->scan_tmp, s));
   LSR_HIP(launch_occupied(j->bin_start, nbins, j->occ, j->cnt + 5, s));
+  LSR_HIP(launch_super_list(bg, j->occ, j->cnt + 5, j->sup, j->cnt + 7, max_occ, s));
   LSR_HIP(launch_scatter_points(dim, j->pts_raw, n, j->pt_bin, j->bin_start, j->bin_fill, j->pts, s));
-  LSR_HIP(launch_bin_geo(dim, j->pts, j->bin_start, j->occ, j->cnt + 5, j->geo,
-                         std::min(j->max_occ, (int64_t)nbins), s));
+  LSR_HIP(launch_bin_geo(dim, j->pts, j->bin_start, j->occ, j->cnt + 5, j->geo, max_occ, s));
+  LSR_HIP(launch_super_geo(dim, j->pts, j->bin_start, j->occ, j->sup, j->cnt + 7, j->sgeo, max_sup,
+                           s));
   DistArgs da;
   da.g = j->dg;
   da.bg = bg;
@@ -550,6 +566,8 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   da.occ = j->occ;
   da.occ_cnt = j->cnt + 5;
   da.geo = j->geo;
+  da.sgeo = j->sgeo;
+  da.sup_cnt = j->cnt + 7;
   {
     // margins that cover the rounding of the frame bounds: every coordinate
     // lies in the grid's box

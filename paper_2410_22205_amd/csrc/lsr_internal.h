@@ -27,12 +27,31 @@ constexpr int BIN_W = 4, BIN_W_FINE = 2, DENSE_BIN = 100;
 // SCAN_TILES tiles (scratch of 2 * SCAN_TILES + 1 ints).
 constexpr int32_t SCAN_ONE_BLOCK = 65536, SCAN_TILES = 1024;
 
+// Bins are grouped in super-bins of SUP bins per axis (SUP^3 in 3D, SUP^2 in
+// 2D), numbered so that the bins of one super-bin have consecutive ids:
+// id = S * ksup + local, with S the super-bin's row-major index over ns[] and
+// local the bin's row-major index inside it.  Sorting the points by bin id
+// then also groups them by super-bin.
+constexpr int SUP = 4;
+
 struct BinGeom {
   int nb[3];        // bins per axis (nb[2] = 1 in 2D)
+  int ns[3];        // super-bins per axis, ceil(nb / SUP) (ns[2] = 1 in 2D)
+  int kz;           // SUP in 3D, 1 in 2D
+  int ksup;         // bins per super-bin: SUP * SUP * kz
   double lo[3];     // grid box
   double hi[3];
   double bw, inv_bw;
 };
+
+// Bin id of bin coordinates b (see SUP).
+__host__ __device__ inline int bin_id(const BinGeom& bg, const int b[3]) {
+  const int S = ((b[0] / SUP) * bg.ns[1] + b[1] / SUP) * bg.ns[2] + b[2] / SUP;
+  const int l = ((b[0] % SUP) * SUP + b[1] % SUP) * bg.kz + b[2] % SUP;
+  return S * bg.ksup + l;
+}
+// Number of bin ids, super-bin padding included.
+inline int32_t bin_ids(const BinGeom& bg) { return bg.ns[0] * bg.ns[1] * bg.ns[2] * bg.ksup; }
 
 template <typename T>
 struct SLArgs {
@@ -109,6 +128,8 @@ struct FinArgs {
 //   [11]    rt, the largest distance of p - m from the line along nv
 //   [12]    rf, the largest |p - m|
 //   [13]    the bin's point range, two int32 (begin, end)
+//   [14]    super-bins only: the range of their bins in the occupied list,
+//           two int32 (begin, end)
 // For any x, with a = nv . (x - m) and tau the distance of x - m from that
 // line, every point p of the bin has
 //   |x - p|^2 >= gap(a, [tmin, tmax])^2 + max(tau - rt, 0)^2.
@@ -122,6 +143,8 @@ struct DistArgs {
   const uint32_t* occ;    // occupied bin ids
   const int32_t* occ_cnt;
   const double* geo;      // GEO doubles per occupied bin
+  const double* sgeo;     // GEO doubles per occupied super-bin
+  const int32_t* sup_cnt; // occupied super-bins
   double mu;              // distance margin that covers rounding (1e-12 x box diagonal)
   double mu2;             // the same for squared distances (1e-12 x diagonal^2)
   double* d64;
@@ -174,9 +197,17 @@ hipError_t launch_occupied(const int32_t* start, int32_t nbins, uint32_t* occ, i
 hipError_t launch_scatter_points(int dim, const double* pts, int64_t n, const int32_t* pt_bin,
                                  const int32_t* start, int32_t* fill, double* sorted,
                                  hipStream_t s);
-// Bounding frames of the occupied bins (GEO doubles each, at most max_occ bins).
+// Occupied super-bins: the runs of one super-bin's bins in the occupied
+// list, appended to sup[] as (begin, end) with *sup_cnt counting them.
+hipError_t launch_super_list(const BinGeom& bg, const uint32_t* occ, const int32_t* occ_cnt,
+                             int2* sup, int32_t* sup_cnt, int64_t max_occ, hipStream_t s);
+// Bounding frames (GEO doubles each) of the occupied bins, at most max_occ,
+// and of the occupied super-bins, at most max_sup.
 hipError_t launch_bin_geo(int dim, const double* pts, const int32_t* start, const uint32_t* occ,
                           const int32_t* occ_cnt, double* geo, int64_t max_occ, hipStream_t s);
+hipError_t launch_super_geo(int dim, const double* pts, const int32_t* start,
+                            const uint32_t* occ, const int2* sup, const int32_t* sup_cnt,
+                            double* sgeo, int64_t max_sup, hipStream_t s);
 hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s);
 template <typename T>
 hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,

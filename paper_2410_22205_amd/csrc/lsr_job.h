@@ -29,11 +29,10 @@ struct Layout {
   size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, cnt, stats;
   size_t blist0, blist1, bstamp;  // brick lists and stamps of the staged 3D step
   int64_t nbricks;
-  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo;
-  int64_t max_occ;
+  size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo, sup, sgeo;
+  int64_t max_occ, max_sup;
   size_t total;
-  int nb[3];
-  int64_t nbins;
+  int64_t nbins;  // bin ids at the finer width, super-bin padding included
 };
 
 }  // namespace lsr
@@ -56,7 +55,8 @@ struct lsr_job {
   uint32_t* listM;
   uint8_t* mflags;
   int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins,
-                 // [6] bins a cloud's points occupy (density check), [8..10] brick-count
+                 // [6] bins a cloud's points occupy (density check), [7] occupied
+                 // super-bins, [8..10] brick-count
                  // ring (staged 3D step)
   unsigned long long* stats;
   double* pts_raw;
@@ -68,7 +68,10 @@ struct lsr_job {
   uint32_t* occ;
   int32_t* scan_tmp;
   double* geo;      // bin frames, GEO doubles per occupied bin
-  int64_t max_occ;  // room for frames
+  int64_t max_occ;  // room for bin frames
+  int2* sup;        // occupied super-bins: their runs in the occupied list
+  double* sgeo;     // super-bin frames
+  int64_t max_sup;  // room for super-bins
   uint32_t* blist[2];
   uint32_t* bstamp;
   int cur_blist;       // brick list buffer holding the current brick list

@@ -867,8 +867,8 @@ __global__ __launch_bounds__(256) void k_reinit_final_batch(const FinArgs<T>* __
 
 // ------------------------------------------------------------ distance
 
-// Validate and bin the cloud: bins are cubes of BIN_W nodes; flag |= 1 for a
-// non-finite point or one outside the grid's box.
+// Validate and bin the cloud (bin ids grouped by super-bin, see SUP); flag
+// |= 1 for a non-finite point or one outside the grid's box.
 template <int DIM>
 __global__ void k_bin_points(BinGeom bg, const double* __restrict__ pts, int64_t n,
                              int32_t* __restrict__ bin_count, int32_t* __restrict__ pt_bin,
@@ -890,7 +890,7 @@ __global__ void k_bin_points(BinGeom bg, const double* __restrict__ pts, int64_t
       pt_bin[p] = -1;
       continue;
     }
-    const int id = (b[0] * bg.nb[1] + b[1]) * bg.nb[2] + b[2];
+    const int id = bin_id(bg, b);
     if (atomicAdd(&bin_count[id], 1) == 0) atomicAdd(occupied, 1);  // the bin's first point
     pt_bin[p] = id;
   }
@@ -1095,7 +1095,81 @@ __device__ void least_spread(const double C[3][3], double nv[3]) {
   for (int ax = 0; ax < 3; ++ax) nv[ax] = ax < DIM ? v[ax] * inv : 0.0;
 }
 
-// Bounding frame (see GEO) of each occupied bin's points, one wave per bin.
+// Bounding frame (see GEO, slots 0 to 13) of the points p0 .. p1 - 1, by one
+// wave; lane 0 writes it to G.
+template <int DIM>
+__device__ void wave_frame(const double* __restrict__ pts, int p0, int p1, double* G) {
+  const int l = (int)lane_id();
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int p = p0 + l; p < p1; p += 64)
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) m[ax] += pts[(int64_t)p * DIM + ax];
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) m[ax] = wave_sum(m[ax]) / (double)(p1 - p0);
+  double C[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  for (int p = p0 + l; p < p1; p += 64) {
+    double v[3];
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) v[ax] = pts[(int64_t)p * DIM + ax] - m[ax];
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+      for (int c = r; c < DIM; ++c) C[r][c] += v[r] * v[c];
+  }
+#pragma unroll
+  for (int r = 0; r < DIM; ++r)
+#pragma unroll
+    for (int c = r; c < DIM; ++c) {
+      C[r][c] = wave_sum(C[r][c]);
+      C[c][r] = C[r][c];
+    }
+  double nv[3];
+  least_spread<DIM>(C, nv);
+  double tmin = INFINITY, tmax = -INFINITY, rt2 = 0.0, rf2 = 0.0, E[3] = {0.0, 0.0, 0.0};
+  for (int p = p0 + l; p < p1; p += 64) {
+    double v[3], a = 0.0, r2 = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      v[ax] = pts[(int64_t)p * DIM + ax] - m[ax];
+      a += nv[ax] * v[ax];
+      r2 += v[ax] * v[ax];
+      E[ax] = fmax(E[ax], fabs(v[ax]));
+    }
+    double w2 = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+      const double w = v[ax] - a * nv[ax];
+      w2 += w * w;
+    }
+    tmin = fmin(tmin, a);
+    tmax = fmax(tmax, a);
+    rt2 = fmax(rt2, w2);
+    rf2 = fmax(rf2, r2);
+  }
+  tmin = wave_min(tmin);
+  tmax = wave_max(tmax);
+  rt2 = wave_max(rt2);
+  rf2 = wave_max(rf2);
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) E[ax] = wave_max(E[ax]);
+  if (l == 0) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      G[ax] = ax < DIM ? m[ax] : 0.0;
+      G[3 + ax] = nv[ax];
+      G[6 + ax] = ax < DIM ? E[ax] : 0.0;
+    }
+    G[9] = tmin;
+    G[10] = tmax;
+    G[11] = sqrt(rt2);
+    G[12] = sqrt(rf2);
+    int32_t* r = (int32_t*)(G + 13);
+    r[0] = p0;
+    r[1] = p1;
+  }
+}
+
+// Frames of the occupied bins, one wave per bin.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_bin_geo(const double* __restrict__ pts,
                                                  const int32_t* __restrict__ start,
@@ -1103,79 +1177,46 @@ __global__ __launch_bounds__(256) void k_bin_geo(const double* __restrict__ pts,
                                                  const int32_t* __restrict__ occ_cnt,
                                                  double* __restrict__ geo) {
   const int nocc = *occ_cnt;
-  const int l = (int)lane_id();
   const int nw = (int)(gridDim.x * (blockDim.x >> 6));
   for (int t = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < nocc; t += nw) {
     const uint32_t id = occ[t];
-    const int p0 = start[id], p1 = start[id + 1];
-    double m[3] = {0.0, 0.0, 0.0};
-    for (int p = p0 + l; p < p1; p += 64)
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) m[ax] += pts[(int64_t)p * DIM + ax];
-#pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) m[ax] = wave_sum(m[ax]) / (double)(p1 - p0);
-    double C[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    for (int p = p0 + l; p < p1; p += 64) {
-      double v[3];
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) v[ax] = pts[(int64_t)p * DIM + ax] - m[ax];
-#pragma unroll
-      for (int r = 0; r < DIM; ++r)
-#pragma unroll
-        for (int c = r; c < DIM; ++c) C[r][c] += v[r] * v[c];
-    }
-#pragma unroll
-    for (int r = 0; r < DIM; ++r)
-#pragma unroll
-      for (int c = r; c < DIM; ++c) {
-        C[r][c] = wave_sum(C[r][c]);
-        C[c][r] = C[r][c];
-      }
-    double nv[3];
-    least_spread<DIM>(C, nv);
-    double tmin = INFINITY, tmax = -INFINITY, rt2 = 0.0, rf2 = 0.0, E[3] = {0.0, 0.0, 0.0};
-    for (int p = p0 + l; p < p1; p += 64) {
-      double v[3], a = 0.0, r2 = 0.0;
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) {
-        v[ax] = pts[(int64_t)p * DIM + ax] - m[ax];
-        a += nv[ax] * v[ax];
-        r2 += v[ax] * v[ax];
-        E[ax] = fmax(E[ax], fabs(v[ax]));
-      }
-      double w2 = 0.0;
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) {
-        const double w = v[ax] - a * nv[ax];
-        w2 += w * w;
-      }
-      tmin = fmin(tmin, a);
-      tmax = fmax(tmax, a);
-      rt2 = fmax(rt2, w2);
-      rf2 = fmax(rf2, r2);
-    }
-    tmin = wave_min(tmin);
-    tmax = wave_max(tmax);
-    rt2 = wave_max(rt2);
-    rf2 = wave_max(rf2);
-#pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) E[ax] = wave_max(E[ax]);
-    if (l == 0) {
-      double* G = geo + (size_t)t * GEO;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        G[ax] = ax < DIM ? m[ax] : 0.0;
-        G[3 + ax] = nv[ax];
-        G[6 + ax] = ax < DIM ? E[ax] : 0.0;
-      }
-      G[9] = tmin;
-      G[10] = tmax;
-      G[11] = sqrt(rt2);
-      G[12] = sqrt(rf2);
-      int32_t* r = (int32_t*)(G + 13);
-      r[0] = p0;
-      r[1] = p1;
-    }
+    wave_frame<DIM>(pts, start[id], start[id + 1], geo + (size_t)t * GEO);
+  }
+}
+
+// Occupied super-bins.  The occupied list holds a super-bin's bins as one
+// run (ids of a super-bin are consecutive and k_occupied keeps the order of
+// ids within each aligned chunk of 256, a multiple of ksup); the thread at
+// the head of a run appends (head, end).
+__global__ __launch_bounds__(256) void k_super_list(int ksup, const uint32_t* __restrict__ occ,
+                                                    const int32_t* __restrict__ occ_cnt,
+                                                    int2* __restrict__ sup, int32_t* sup_cnt) {
+  const int nocc = *occ_cnt;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nocc; t += gridDim.x * blockDim.x) {
+    const uint32_t S = occ[t] / (uint32_t)ksup;
+    if (t > 0 && occ[t - 1] / (uint32_t)ksup == S) continue;
+    int t1 = t + 1;
+    while (t1 < nocc && occ[t1] / (uint32_t)ksup == S) ++t1;
+    sup[atomicAdd(sup_cnt, 1)] = make_int2(t, t1);
+  }
+}
+
+// Frames of the occupied super-bins, one wave per super-bin: its points are
+// those of its bins, which are contiguous in the sorted cloud.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_super_geo(const double* __restrict__ pts,
+                                                   const int32_t* __restrict__ start,
+                                                   const uint32_t* __restrict__ occ,
+                                                   const int2* __restrict__ sup,
+                                                   const int32_t* __restrict__ sup_cnt,
+                                                   double* __restrict__ sgeo) {
+  const int nsup = *sup_cnt;
+  const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+  for (int u = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); u < nsup; u += nw) {
+    const int2 r = sup[u];
+    double* G = sgeo + (size_t)u * GEO;
+    wave_frame<DIM>(pts, start[occ[r.x]], start[occ[r.y - 1] + 1], G);
+    if (lane_id() == 0) *(int2*)(G + 14) = r;
   }
 }
 
@@ -1202,20 +1243,6 @@ __device__ __forceinline__ double frame_lb2(const double* G, const double x[3], 
   return un * un + ut * ut;
 }
 
-template <int DIM>
-__device__ __forceinline__ void bin_box(const BinGeom& bg, uint32_t id, double lo[3], double hi[3]) {
-  int b2 = (int)(id % (uint32_t)bg.nb[2]);
-  uint32_t r = id / (uint32_t)bg.nb[2];
-  int b1 = (int)(r % (uint32_t)bg.nb[1]);
-  int b0 = (int)(r / (uint32_t)bg.nb[1]);
-  const int bb[3] = {b0, b1, b2};
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    lo[ax] = bg.lo[ax] + bb[ax] * bg.bw;
-    hi[ax] = lo[ax] + bg.bw;
-  }
-}
-
 // Node (li, lj, lk) of the brick that thread threadIdx.x takes as its u-th
 // node.  3D: 512 nodes, two per thread, a wave's 128 nodes forming a
 // 4 x 4 x 8 box (nodes that are close together agree on the bins they can
@@ -1237,16 +1264,19 @@ __device__ __forceinline__ void dist_node(int u, int& li, int& lj, int& lk) {
 // Exact distance to the cloud at the nodes of one brick (8^3 nodes in 3D,
 // 16^2 in 2D) per workgroup.  With c the brick centre, e its half extents
 // and rho its half diagonal:
-//  1. d(c) and a point p* that attains it are found exactly, from the
-//     occupied bins whose box and frame can hold a point closer than the
-//     best far-corner bound;
-//  2. a bin can hold a point closer to a node x of the brick than p* only
-//     if its box meets the ball (c, d(c) + 2 rho), and only if
-//     |c - y|^2 - |c - p*|^2 <= 2 sum_k e_k |y_k - p*_k| for some y in it
-//     (|x - y|^2 - |x - p*|^2 is linear in x, so its least value over the
-//     brick's box is attained at a corner); the bins that pass both, the
-//     candidates, are ordered by their frame's distance from c in NSH
-//     shells (counting sort), so that nodes meet close points first;
+//  1. d(c) and a point p* that attains it are found exactly: the points of
+//     the bin whose frame comes closest to c, within the super-bin whose
+//     frame does, give an upper bound; then the points of every bin whose
+//     frame bound does not exceed it, within a super-bin whose frame bound
+//     does not either, are scanned;
+//  2. a bin can hold a point y closer to a node x of the brick than p* only
+//     if its frame meets the ball (c, d(c) + 2 rho), and only if
+//     |c - y|^2 - |c - p*|^2 <= 2 sum_k e_k |y_k - p*_k| (|x - y|^2 -
+//     |x - p*|^2 is linear in x, so its least value over the brick's box is
+//     attained at a corner).  Super-bins are tested first and the bins of
+//     those that pass next; the bins that pass, the candidates, are ordered
+//     by their frame's distance from c in NSH shells (counting sort), so
+//     that nodes meet close points first;
 //  3. every node starts from |x - p*|, and a wave scans a candidate's points
 //     only if one of its nodes could still find a closer point there by the
 //     frame bound.
@@ -1259,10 +1289,13 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
 #pragma clang fp contract(off)
   constexpr int BS = DIM == 3 ? 8 : 16;
   constexpr int NPT = DIM == 3 ? 2 : 1;
-  constexpr int CAP = 6144;
+  // LDS: CAP + SCAP ints and a few words, within a sixth of a CU's LDS
+  constexpr int CAP = 6144, SCAP = 512, NSH = 32;
   __shared__ double red[4];
   __shared__ uint32_t cand[CAP];
-  __shared__ int ncand;
+  __shared__ int slist[SCAP];
+  __shared__ int ncand, nsl, ndc, pstar, ubest;
+  __shared__ int shell_n[NSH], shell_at[NSH];
   const DevGrid& g = a.g;
   const int nbx = (g.n0 + BS - 1) / BS, nby = (g.n1 + BS - 1) / BS;
   const int nbz = DIM == 3 ? (g.n2 + BS - 1) / BS : 1;
@@ -1283,42 +1316,37 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
     rho2 += e[ax] * e[ax];
   }
   const double rho = sqrt(rho2);
-  const int nocc = *a.occ_cnt;
+  const int nocc = *a.occ_cnt, nsup = *a.sup_cnt;
   const double slack = 1.0 + 1e-12;
   const double mu = a.mu;
+  const int tid = (int)threadIdx.x, wv = tid >> 6, ln = (int)lane_id();
 
-  // far-corner bound: every occupied box holds a point no farther than it
-  double ub2 = INFINITY;
-  for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
-    double lo[3], hi[3];
-    bin_box<DIM>(a.bg, a.occ[t], lo, hi);
-    double s = 0.0;
-#pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) {
-      const double q = fmax(fabs(c[ax] - lo[ax]), fabs(c[ax] - hi[ax]));
-      s += q * q;
+  // 1. the super-bin whose frame bound from c is least (smallest index on
+  // ties) ...
+  double lmin = INFINITY;
+  int umin = INT_MAX;
+  for (int u = tid; u < nsup; u += blockDim.x) {
+    const double v = frame_lb2<DIM>(a.sgeo + (size_t)u * GEO, c, mu);
+    if (v < lmin) {
+      lmin = v;
+      umin = u;
     }
-    ub2 = fmin(ub2, s);
   }
-  ub2 = block_min(ub2, red) * slack;
-
-  // exact d(c)^2 and a point that attains it (the smallest index among ties)
+  if (tid == 0) {
+    ubest = INT_MAX;
+    pstar = INT_MAX;
+    nsl = 0;
+    ndc = 0;
+  }
+  const double lbest = block_min(lmin, red);  // synchronises the block
+  if (umin != INT_MAX && lmin == lbest) atomicMin(&ubest, umin);
+  __syncthreads();
+  // ... and its bin whose frame bound is least, whose points bound d(c)
+  // from above (a lane per bin of the super-bin: ksup <= 64)
   double best = INFINITY;
   int bidx = -1;
-  for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
-    double lo[3], hi[3];
-    bin_box<DIM>(a.bg, a.occ[t], lo, hi);
-    double s = 0.0;
-#pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) {
-      const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
-      s += q * q;
-    }
-    if (s > ub2) continue;
-    const double* G = a.geo + (size_t)t * GEO;
-    if (frame_lb2<DIM>(G, c, mu) > ub2) continue;
-    const int2 rng = *(const int2*)(G + 13);
-    for (int q = rng.x; q < rng.y; ++q) {
+  auto scan_c = [&](int p0, int p1, int first, int step) {
+    for (int q = p0 + first; q < p1; q += step) {
       double s2 = 0.0;
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) {
@@ -1330,75 +1358,129 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
         bidx = q;
       }
     }
+  };
+  if (ubest != INT_MAX && wv == 0) {
+    const int2 r = *(const int2*)(a.sgeo + (size_t)ubest * GEO + 14);
+    const int t = r.x + ln;
+    double v = INFINITY;
+    if (t < r.y) v = frame_lb2<DIM>(a.geo + (size_t)t * GEO, c, mu);
+    const double vmin = wave_min(v);
+    const uint64_t m = __ballot(t < r.y && v == vmin);
+    const int tb = r.x + (m ? (int)__builtin_ctzll(m) : 0);
+    const int2 rb = *(const int2*)(a.geo + (size_t)tb * GEO + 13);
+    scan_c(rb.x, rb.y, ln, 64);
   }
-  __shared__ int pstar;
-  if (threadIdx.x == 0) pstar = INT_MAX;
+  const double ub2 = block_min(best, red) * slack;
+  // every other super-bin whose frame bound does not exceed that ...
+  for (int u = tid; u < nsup; u += blockDim.x) {
+    if (frame_lb2<DIM>(a.sgeo + (size_t)u * GEO, c, mu) > ub2) continue;
+    const int pos = atomicAdd(&nsl, 1);
+    if (pos < SCAP) slist[pos] = u;
+  }
+  __syncthreads();
+  const int ns_dc = nsl;
+  if (ns_dc <= SCAP) {
+    // ... and of those, the bins whose frame bound does not (a wave per
+    // super-bin, a lane per bin of it: ksup <= 64)
+    for (int q = wv; q < ns_dc; q += (int)(blockDim.x >> 6)) {
+      const int2 r = *(const int2*)(a.sgeo + (size_t)slist[q] * GEO + 14);
+      const int t = r.x + ln;
+      if (t >= r.y || frame_lb2<DIM>(a.geo + (size_t)t * GEO, c, mu) > ub2) continue;
+      const int pos = atomicAdd(&ndc, 1);
+      if (pos < CAP) cand[pos] = (uint32_t)t;
+    }
+    __syncthreads();
+  }
+  const int nd = ndc;
+  if (ns_dc <= SCAP && nd <= CAP) {
+    // a wave per listed bin, its lanes over the bin's points
+    for (int q = wv; q < nd; q += (int)(blockDim.x >> 6)) {
+      const int2 r = *(const int2*)(a.geo + (size_t)cand[q] * GEO + 13);
+      scan_c(r.x, r.y, ln, 64);
+    }
+  } else {
+    for (int u = tid; u < nsup; u += blockDim.x) {
+      if (frame_lb2<DIM>(a.sgeo + (size_t)u * GEO, c, mu) > ub2) continue;
+      const int2 r = *(const int2*)(a.sgeo + (size_t)u * GEO + 13);
+      scan_c(r.x, r.y, 0, 1);
+    }
+  }
   const double bmin = block_min(best, red);  // synchronises the block
   if (bidx >= 0 && best == bmin) atomicMin(&pstar, bidx);
   best = bmin;
   const double R = sqrt(best) + 2.0 * rho;
   const double R2 = R * R * slack;
-
-  // candidate bins (step 2), ordered by the box's distance from c in NSH
-  // shells (counting sort)
-  constexpr int NSH = 32;
-  __shared__ int shell_n[NSH], shell_at[NSH];
-  if (threadIdx.x < NSH) shell_n[threadIdx.x] = 0;
-  if (threadIdx.x == 0) ncand = 0;
+  if (tid < NSH) shell_n[tid] = 0;
+  if (tid == 0) {
+    ncand = 0;
+    nsl = 0;
+  }
   __syncthreads();
+
+  // 2. candidates
   const bool havep = pstar != INT_MAX;
   double P[3] = {0.0, 0.0, 0.0};
   if (havep)
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) P[ax] = a.pts[(int64_t)pstar * DIM + ax];
-  // every candidate frame lies at least d(c) - (box diagonal) from c
+  // every candidate frame lies at least d(c) - (bin diagonal) from c
   const double s0 = fmax(sqrt(best) - a.bg.bw * sqrt((double)DIM), 0.0);
   const double shell_scale = NSH / fmax(R - s0, 1e-300);
-  auto candidate = [&](int t, int* shell) -> bool {
-    double lo[3], hi[3];
-    bin_box<DIM>(a.bg, a.occ[t], lo, hi);
-    double s = 0.0;
-#pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) {
-      const double q = fmax(fmax(lo[ax] - c[ax], c[ax] - hi[ax]), 0.0);
-      s += q * q;
-    }
-    if (s > R2) return false;
-    const double* G = a.geo + (size_t)t * GEO;
+  // the test of step 2 for a frame G; *lbc = its bound from c
+  auto passes = [&](const double* G, double* lbc) -> bool {
     const double lb2 = frame_lb2<DIM>(G, c, mu);
-    if (havep) {
-      // sum_k e_k max_y |y_k - p*_k| over the bin's points y
-      double w = 0.0;
+    *lbc = lb2;
+    if (lb2 > R2) return false;
+    if (!havep) return true;
+    // sum_k e_k max_y |y_k - p*_k| over the frame's points y
+    double w = 0.0;
 #pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) w += e[ax] * (fabs(G[ax] - P[ax]) + G[6 + ax] + mu);
-      if (lb2 - best - 2.0 * w > a.mu2) return false;
-    }
-    const int k = (int)((sqrt(lb2) - s0) * shell_scale);
-    *shell = k < 0 ? 0 : (k > NSH - 1 ? NSH - 1 : k);
-    return true;
+    for (int ax = 0; ax < DIM; ++ax) w += e[ax] * (fabs(G[ax] - P[ax]) + G[6 + ax] + mu);
+    return !(lb2 - best - 2.0 * w > a.mu2);
   };
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int t = threadIdx.x; t < nocc; t += blockDim.x) {
-      int sh;
-      if (!candidate(t, &sh)) continue;
-      if (pass == 0) {
-        atomicAdd(&shell_n[sh], 1);
-        atomicAdd(&ncand, 1);
-      } else {
-        const int pos = atomicAdd(&shell_at[sh], 1);
-        if (pos < CAP) cand[pos] = (uint32_t)t;
-      }
-    }
-    __syncthreads();
-    if (pass == 0 && threadIdx.x == 0) {
-      int run = 0;
-      for (int q = 0; q < NSH; ++q) {
-        shell_at[q] = run;
-        run += shell_n[q];
-      }
-    }
-    __syncthreads();
+  auto shell_of = [&](double lb2) {
+    const int k = (int)((sqrt(lb2) - s0) * shell_scale);
+    return k < 0 ? 0 : (k > NSH - 1 ? NSH - 1 : k);
+  };
+  for (int u = tid; u < nsup; u += blockDim.x) {
+    double lb2;
+    if (!passes(a.sgeo + (size_t)u * GEO, &lb2)) continue;
+    const int pos = atomicAdd(&nsl, 1);
+    if (pos < SCAP) slist[pos] = u;
   }
+  __syncthreads();
+  const int ns_pass = nsl;
+  if (ns_pass <= SCAP) {
+    // a wave per passing super-bin, a lane per bin of it (ksup <= 64)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = wv; q < ns_pass; q += (int)(blockDim.x >> 6)) {
+        const int2 r = *(const int2*)(a.sgeo + (size_t)slist[q] * GEO + 14);
+        const int t = r.x + ln;
+        double lb2;
+        if (t >= r.y || !passes(a.geo + (size_t)t * GEO, &lb2)) continue;
+        const int sh = shell_of(lb2);
+        if (pass == 0) {
+          atomicAdd(&shell_n[sh], 1);
+          atomicAdd(&ncand, 1);
+        } else {
+          const int pos = atomicAdd(&shell_at[sh], 1);
+          if (pos < CAP) cand[pos] = (uint32_t)t;
+        }
+      }
+      __syncthreads();
+      if (pass == 0 && tid == 0) {
+        int run = 0;
+        for (int q = 0; q < NSH; ++q) {
+          shell_at[q] = run;
+          run += shell_n[q];
+        }
+      }
+      __syncthreads();
+    }
+  } else if (tid == 0) {
+    ncand = CAP + 1;  // too many super-bins to list: walk every bin below
+  }
+  __syncthreads();
   const int nc = ncand;
 
   double x[NPT][3], bn[NPT];
@@ -1424,17 +1506,17 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
       bn[u] = s2;
     }
   }
-  // A wave passes over a candidate when none of its nodes can find a closer
-  // point in it by the frame bound.  Beyond CAP candidates the occupied
-  // list is walked with the same candidate test.
+  // 3. A wave passes over a candidate when none of its nodes can find a
+  // closer point in it by the frame bound.  Beyond CAP candidates every
+  // occupied bin is walked with the test of step 2.
   const int nloop = nc <= CAP ? nc : nocc;
   for (int q = 0; q < nloop; ++q) {
     int t = q;
     if (nc <= CAP) {
       t = __builtin_amdgcn_readfirstlane(cand[q]);
     } else {
-      int sh;
-      if (!candidate(q, &sh)) continue;
+      double lb2;
+      if (!passes(a.geo + (size_t)q * GEO, &lb2)) continue;
     }
     // the same frame for the whole block: loaded through the scalar unit
     const Frame F = uniform_load((const Frame*)a.geo, t);
@@ -1444,10 +1526,11 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
       need = need || (valid[u] && frame_lb2<DIM>(F.w, x[u], mu) <= bn[u] * slack);
     if (!__any(need)) continue;
     const int2 rng = *(const int2*)(F.w + 13);
-    for (int p = rng.x; p < rng.y; ++p) {
-      double Q[3];
-#pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) Q[ax] = a.pts[(int64_t)p * DIM + ax];
+    // the same point for the whole block: read through the scalar unit
+    typedef const __attribute__((address_space(4))) double cdouble;
+    cdouble* pts4 = (cdouble*)a.pts;
+    // two points per trip: both loads are in flight before either is used
+    auto fold = [&](const double* Q) {
 #pragma unroll
       for (int u = 0; u < NPT; ++u) {
         double s2 = 0.0;
@@ -1458,6 +1541,23 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
         }
         bn[u] = fmin(bn[u], s2);
       }
+    };
+    int p = rng.x;
+    for (; p + 1 < rng.y; p += 2) {
+      double Q0[3], Q1[3];
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) {
+        Q0[ax] = pts4[(int64_t)p * DIM + ax];
+        Q1[ax] = pts4[(int64_t)(p + 1) * DIM + ax];
+      }
+      fold(Q0);
+      fold(Q1);
+    }
+    if (p < rng.y) {
+      double Q0[3];
+#pragma unroll
+      for (int ax = 0; ax < DIM; ++ax) Q0[ax] = pts4[(int64_t)p * DIM + ax];
+      fold(Q0);
     }
   }
 #pragma unroll
@@ -1706,6 +1806,24 @@ hipError_t launch_bin_geo(int dim, const double* pts, const int32_t* start, cons
     hipLaunchKernelGGL(k_bin_geo<3>, gr, bl, 0, s, pts, start, occ, occ_cnt, geo);
   else
     hipLaunchKernelGGL(k_bin_geo<2>, gr, bl, 0, s, pts, start, occ, occ_cnt, geo);
+  return hipGetLastError();
+}
+
+hipError_t launch_super_list(const BinGeom& bg, const uint32_t* occ, const int32_t* occ_cnt,
+                             int2* sup, int32_t* sup_cnt, int64_t max_occ, hipStream_t s) {
+  hipLaunchKernelGGL(k_super_list, dim3(grid_for((uint64_t)max_occ, 256, 4096)), dim3(256), 0, s,
+                     bg.ksup, occ, occ_cnt, sup, sup_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_super_geo(int dim, const double* pts, const int32_t* start,
+                            const uint32_t* occ, const int2* sup, const int32_t* sup_cnt,
+                            double* sgeo, int64_t max_sup, hipStream_t s) {
+  dim3 gr(grid_for((uint64_t)max_sup, 4, 4096)), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_super_geo<3>, gr, bl, 0, s, pts, start, occ, sup, sup_cnt, sgeo);
+  else
+    hipLaunchKernelGGL(k_super_geo<2>, gr, bl, 0, s, pts, start, occ, sup, sup_cnt, sgeo);
   return hipGetLastError();
 }
 
