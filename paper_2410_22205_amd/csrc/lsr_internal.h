@@ -22,7 +22,7 @@ __host__ __device__ inline size_t stat_index(int counter, int slot) {
 // Cloud bins: cubes of BIN_W nodes per side, or of BIN_W_FINE nodes for
 // dense clouds (more than DENSE_BIN points per occupied BIN_W bin); the
 // workspace holds the bins of the finer width.
-constexpr int BIN_W = 4, BIN_W_FINE = 2, DENSE_BIN = 100;
+constexpr int BIN_W = 4, BIN_W_FINE = 2, DENSE_BIN = 40;
 // Bin-count scans: one block up to SCAN_ONE_BLOCK bins, else at most
 // SCAN_TILES tiles (scratch of 2 * SCAN_TILES + 1 ints).
 constexpr int32_t SCAN_ONE_BLOCK = 65536, SCAN_TILES = 1024;
