@@ -25,7 +25,7 @@ __host__ __device__ inline size_t stat_index(int counter, int slot) {
 constexpr int BIN_W = 4, BIN_W_FINE = 2, DENSE_BIN = 40;
 // Bin-count scans: one block up to SCAN_ONE_BLOCK bins, else at most
 // SCAN_TILES tiles (scratch of 2 * SCAN_TILES + 1 ints).
-constexpr int32_t SCAN_ONE_BLOCK = 65536, SCAN_TILES = 1024;
+constexpr int32_t SCAN_ONE_BLOCK = 4096, SCAN_TILES = 1024;
 
 // Bins are grouped in super-bins of SUP bins per axis (SUP^3 in 3D, SUP^2 in
 // 2D), numbered so that the bins of one super-bin have consecutive ids:

@@ -1289,8 +1289,9 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
 #pragma clang fp contract(off)
   constexpr int BS = DIM == 3 ? 8 : 16;
   constexpr int NPT = DIM == 3 ? 2 : 1;
-  // LDS: CAP + SCAP ints and a few words, within a sixth of a CU's LDS
-  constexpr int CAP = 6144, SCAP = 512, NSH = 32;
+  // LDS: CAP + SCAP ints and a few words, about 21 KB (7 blocks of 4 waves
+  // per CU, as many as the registers allow)
+  constexpr int CAP = 4608, SCAP = 512, NSH = 32;
   __shared__ double red[4];
   __shared__ uint32_t cand[CAP];
   __shared__ int slist[SCAP];
@@ -1398,6 +1399,12 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
       const int2 r = *(const int2*)(a.geo + (size_t)cand[q] * GEO + 13);
       scan_c(r.x, r.y, ln, 64);
     }
+  } else if (ns_dc <= SCAP) {
+    // too many bins to list: every point of the listed super-bins
+    for (int q = 0; q < ns_dc; ++q) {
+      const int2 r = *(const int2*)(a.sgeo + (size_t)slist[q] * GEO + 13);
+      scan_c(r.x, r.y, tid, blockDim.x);
+    }
   } else {
     for (int u = tid; u < nsup; u += blockDim.x) {
       if (frame_lb2<DIM>(a.sgeo + (size_t)u * GEO, c, mu) > ub2) continue;
@@ -1478,7 +1485,7 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
       __syncthreads();
     }
   } else if (tid == 0) {
-    ncand = CAP + 1;  // too many super-bins to list: walk every bin below
+    ncand = CAP + 1;  // too many super-bins to list: step 3 walks every bin
   }
   __syncthreads();
   const int nc = ncand;
@@ -1507,29 +1514,18 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
     }
   }
   // 3. A wave passes over a candidate when none of its nodes can find a
-  // closer point in it by the frame bound.  Beyond CAP candidates every
-  // occupied bin is walked with the test of step 2.
-  const int nloop = nc <= CAP ? nc : nocc;
-  for (int q = 0; q < nloop; ++q) {
-    int t = q;
-    if (nc <= CAP) {
-      t = __builtin_amdgcn_readfirstlane(cand[q]);
-    } else {
-      double lb2;
-      if (!passes(a.geo + (size_t)q * GEO, &lb2)) continue;
-    }
-    // the same frame for the whole block: loaded through the scalar unit
-    const Frame F = uniform_load((const Frame*)a.geo, t);
+  // closer point in it by the frame bound.
+  typedef const __attribute__((address_space(4))) double cdouble;
+  cdouble* pts4 = (cdouble*)a.pts;
+  auto visit = [&](const Frame& F) {
     bool need = false;
 #pragma unroll
     for (int u = 0; u < NPT; ++u)
       need = need || (valid[u] && frame_lb2<DIM>(F.w, x[u], mu) <= bn[u] * slack);
-    if (!__any(need)) continue;
+    if (!__any(need)) return;
     const int2 rng = *(const int2*)(F.w + 13);
-    // the same point for the whole block: read through the scalar unit
-    typedef const __attribute__((address_space(4))) double cdouble;
-    cdouble* pts4 = (cdouble*)a.pts;
-    // two points per trip: both loads are in flight before either is used
+    // the same point for the whole block, read through the scalar unit; two
+    // points per trip, both loads in flight before either is used
     auto fold = [&](const double* Q) {
 #pragma unroll
       for (int u = 0; u < NPT; ++u) {
@@ -1558,6 +1554,36 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) Q0[ax] = pts4[(int64_t)p * DIM + ax];
       fold(Q0);
+    }
+  };
+  const Frame* frames = (const Frame*)a.geo;
+  if (nc <= CAP) {
+    // the sorted candidates; each frame is the same for the whole block and
+    // read through the scalar unit, the next one while this one is used
+    if (nc > 0) {
+      Frame F = uniform_load(frames, (int)__builtin_amdgcn_readfirstlane(cand[0]));
+      for (int q = 0; q < nc; ++q) {
+        Frame Fn;
+        if (q + 1 < nc) Fn = uniform_load(frames, (int)__builtin_amdgcn_readfirstlane(cand[q + 1]));
+        visit(F);
+        F = Fn;
+      }
+    }
+  } else if (ns_pass <= SCAP) {
+    // too many candidates to list: the bins of the super-bins that passed,
+    // with the test of step 2, unsorted
+    for (int q = 0; q < ns_pass; ++q) {
+      const int2 r = *(const int2*)(a.sgeo + (size_t)slist[q] * GEO + 14);
+      for (int t = r.x; t < r.y; ++t) {
+        double lb2;
+        if (passes(a.geo + (size_t)t * GEO, &lb2)) visit(uniform_load(frames, t));
+      }
+    }
+  } else {
+    // too many super-bins as well: every occupied bin, with the same test
+    for (int t = 0; t < nocc; ++t) {
+      double lb2;
+      if (passes(a.geo + (size_t)t * GEO, &lb2)) visit(uniform_load(frames, t));
     }
   }
 #pragma unroll
@@ -1768,9 +1794,9 @@ hipError_t launch_scan_bins(const int32_t* count, int32_t nbins, int32_t* start,
     hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, count, nbins, start);
     return hipGetLastError();
   }
-  // at most SCAN_TILES tiles of a multiple of 256 counts
+  // at most SCAN_TILES tiles of a multiple of 256 counts, at least 1024
   const int64_t per = ((int64_t)nbins + SCAN_TILES - 1) / SCAN_TILES;
-  const int32_t tile = (int32_t)std::max<int64_t>(4096, (per + 255) / 256 * 256);
+  const int32_t tile = (int32_t)std::max<int64_t>(1024, (per + 255) / 256 * 256);
   const int32_t ntiles = (int32_t)(((int64_t)nbins + tile - 1) / tile);
   int32_t* sums = tmp;
   int32_t* offs = tmp + SCAN_TILES;

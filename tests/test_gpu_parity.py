@@ -133,15 +133,21 @@ def test_distance_field_union_sampled():
     assert (np.abs(got - dor) <= 4 * np.spacing(dor)).all()
 
 
-@pytest.mark.parametrize("case", ["dense", "corner", "corner2d"])
+@pytest.mark.parametrize("case", ["dense", "corner", "corner2d", "sphere_centre"])
 def test_distance_field_dense_and_far_clouds(case):
-    """Many points per bin (80k points on a small torus at 72^3) and nodes up
-    to the far corner of the grid from a cloud in one corner: the bins are
-    visited nearest first and skipped wave by wave, and every node still
-    gets its exact nearest distance."""
+    """Many points per bin (80k points on a small torus at 72^3), nodes up to
+    the far corner of the grid from a cloud in one corner, and the centre of
+    a dense sphere (150k points, about 8000 bins at 128^3), where every bin
+    lies at nearly the same distance, so that a brick's candidates overflow
+    the kernel's lists: the bins are visited nearest first and skipped wave
+    by wave, or walked without order, and every node still gets its exact
+    nearest distance."""
     if case == "dense":
         g = synth.cube_grid(3, 72)
         pts = synth.torus_cloud(80_000, 0.3, 0.1, 0.0, seed=21)
+    elif case == "sphere_centre":
+        g = synth.cube_grid(3, 128)
+        pts = synth.sphere_points(np.random.default_rng(24), 150_000, 0.8)
     elif case == "corner":
         g = synth.cube_grid(3, 96)
         pts = synth.torus_cloud(4_000, 0.15, 0.05, 0.0, seed=22) + np.array([-0.75, -0.7, -0.72])
@@ -151,6 +157,18 @@ def test_distance_field_dense_and_far_clouds(case):
     w = dict(grid=g, points=pts, phi0=("sphere", (0.0, 0.0, 0.0, 0.9)), interp="weno",
              dt=0.5 * g["h"], steps=0, gamma=6 * g["h"], beta=3 * g["h"], reinit_every=0)
     _, _, _, _, _, dgpu = gpu_run(w, steps=0)
+    if case == "sphere_centre":
+        # every node near the centre, where the lists overflow, and a random
+        # sample of the rest (the oracle's tree query is slow at the centre)
+        X = oracle.node_coords(g)
+        near = np.nonzero(np.abs(X).max(axis=1) <= 0.09)[0]
+        rest = np.random.default_rng(25).choice(dgpu.size, size=50_000, replace=False)
+        idx = np.union1d(near, rest)
+        dor = oracle.distance(w["points"], g, x=X[idx])
+        got = dgpu.ravel()[idx]
+        assert near.size > 1000
+        assert (np.abs(got - dor) <= 4 * np.spacing(dor)).all()
+        return
     dor = oracle.distance(w["points"], g)
     err = np.abs(dgpu - dor)
     assert (err <= 4 * np.spacing(dor)).all(), f"max err {err.max():.3e}"
