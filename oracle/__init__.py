@@ -56,6 +56,7 @@ def _lib():
         lib = ctypes.CDLL(_build.LIB)
         sig = {
             "orc_cutoff": (ctypes.c_double, [ctypes.c_double] * 3),
+            "orc_energy_sum": (ctypes.c_double, [_D, _D, _GP, ctypes.c_double, ctypes.c_int]),
             "orc_weno1d": (ctypes.c_double, [_D, ctypes.c_double, ctypes.c_double, _D]),
             "orc_interp": (ctypes.c_double, [_D, _GP, ctypes.c_int, _D]),
             "orc_gradient": (None, [_D, _GP, ctypes.c_int64, _D]),
@@ -245,3 +246,13 @@ def distance(points, grid, x=None):
         return dd.reshape(shape(grid))
     dd, _ = tree.query(np.asarray(x, dtype=np.float64), k=1, workers=-1)
     return dd
+
+
+def energy(phi, d, grid, p, R=5):
+    """E_p(phi) of Section 3.5 (eq. energyApprox in 2D, eq. energyApproxFiner
+    with R subcells per axis in 3D), from nodal phi and d."""
+    f = np.ascontiguousarray(phi, dtype=np.float64)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    assert f.shape == shape(grid) and dd.shape == shape(grid)
+    s = _lib().orc_energy_sum(_ptr(f), _ptr(dd), ctypes.byref(_grid(grid)), float(p), int(R))
+    return s ** (1.0 / p)

@@ -541,3 +541,133 @@ void orc_distance_brute(const double* pts, int64_t n_pts, const orc_grid* g, dou
     d[j] = sqrt(best);
   }
 }
+
+/* ------------------------------------------------------ energy functional */
+
+/* Section 3.5: E_p(phi) is approximated over the front cells, the cells of
+ * the grid whose vertices do not all lie on one side of the front (a vertex
+ * is inside when phi < 0), with |grad phi| = 1 assumed there.  This returns
+ * the sum whose p-th root is E_p, the cells visited in index order:
+ *  2D (eq. energyApprox, line form): the front crosses an edge where its two
+ *     vertices lie on different sides, at the zero of the linear interpolant
+ *     of phi along the edge; d there is the linear interpolant of d.  The
+ *     integral over the segment between two crossings is taken by the
+ *     trapezoidal rule, L (|d_1|^p + |d_2|^p) / 2.  A cell crossed on all four
+ *     edges (reading: the paper names two points) gets two segments, paired
+ *     so that the centre, where phi is the mean of the four vertex values,
+ *     lies on the side of the vertex (i, j) when the two agree.
+ *  3D (eq. energyApproxFiner): every front cell is split into R^3 subcells of
+ *     side h' = h / R; phi and d at a subcell's centre are the trilinear
+ *     interpolants of the cell's vertex values (reading: the reconstruction
+ *     the paper leaves open), and the subcell adds |d|^p h'^2 when
+ *     |phi| < (sqrt 3 / 2) h'. */
+static double orc_lerp(double a, double b, double t) { return a + t * (b - a); }
+
+static double orc_energy_2d_cell(const double* phi, const double* d, const orc_grid* g, int i,
+                                 int j, double p) {
+  /* corners in edge order: (i,j), (i+1,j), (i+1,j+1), (i,j+1) */
+  const int ci[4] = {i, i + 1, i + 1, i}, cj[4] = {j, j, j + 1, j + 1};
+  double f[4], e[4];
+  int in[4], n_in = 0;
+  for (int q = 0; q < 4; ++q) {
+    int c[3] = {ci[q], cj[q], 0};
+    int64_t k = orc_index(g, c);
+    f[q] = phi[k];
+    e[q] = d[k];
+    in[q] = f[q] < 0.0;
+    n_in += in[q];
+  }
+  if (n_in == 0 || n_in == 4) return 0.0;
+  /* crossing on edge q (corner q to corner q + 1) */
+  double px[4], py[4], pd[4];
+  int has[4];
+  for (int q = 0; q < 4; ++q) {
+    int r = (q + 1) & 3;
+    has[q] = in[q] != in[r];
+    if (!has[q]) continue;
+    double t = f[q] / (f[q] - f[r]);
+    px[q] = g->lo[0] + g->h * orc_lerp(ci[q], ci[r], t);
+    py[q] = g->lo[1] + g->h * orc_lerp(cj[q], cj[r], t);
+    pd[q] = orc_lerp(e[q], e[r], t);
+  }
+  int pairs[2][2], n_seg = 0;
+  if (has[0] && has[1] && has[2] && has[3]) {
+    double centre = 0.25 * (f[0] + f[1] + f[2] + f[3]);
+    if ((centre < 0.0) == in[0]) {
+      /* the centre joins corner 0: segments cut off corners 1 and 3 */
+      pairs[0][0] = 0; pairs[0][1] = 1;
+      pairs[1][0] = 2; pairs[1][1] = 3;
+    } else {
+      /* segments cut off corners 0 and 2 */
+      pairs[0][0] = 3; pairs[0][1] = 0;
+      pairs[1][0] = 1; pairs[1][1] = 2;
+    }
+    n_seg = 2;
+  } else {
+    int a = -1, b = -1;
+    for (int q = 0; q < 4; ++q)
+      if (has[q]) {
+        if (a < 0) a = q; else b = q;
+      }
+    pairs[0][0] = a;
+    pairs[0][1] = b;
+    n_seg = 1;
+  }
+  double s = 0.0;
+  for (int m = 0; m < n_seg; ++m) {
+    int a = pairs[m][0], b = pairs[m][1];
+    double L = hypot(px[a] - px[b], py[a] - py[b]);
+    s += L * 0.5 * (pow(fabs(pd[a]), p) + pow(fabs(pd[b]), p));
+  }
+  return s;
+}
+
+static double orc_energy_3d_cell(const double* phi, const double* d, const orc_grid* g, int i,
+                                 int j, int k, double p, int R) {
+  /* vertex values v[a][b][c] at (i + a, j + b, k + c) */
+  double f[2][2][2], e[2][2][2];
+  int n_in = 0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int c = 0; c < 2; ++c) {
+        int cc[3] = {i + a, j + b, k + c};
+        int64_t m = orc_index(g, cc);
+        f[a][b][c] = phi[m];
+        e[a][b][c] = d[m];
+        n_in += phi[m] < 0.0;
+      }
+  if (n_in == 0 || n_in == 8) return 0.0;
+  const double hs = g->h / R;
+  const double lim = 0.5 * sqrt(3.0) * hs;
+  double s = 0.0;
+  for (int u = 0; u < R; ++u)
+    for (int v = 0; v < R; ++v)
+      for (int w = 0; w < R; ++w) {
+        double tx = (u + 0.5) / R, ty = (v + 0.5) / R, tz = (w + 0.5) / R;
+        /* trilinear: along x, then y, then z */
+        double fy[2][2], ey[2][2];
+        for (int b = 0; b < 2; ++b)
+          for (int c = 0; c < 2; ++c) {
+            fy[b][c] = orc_lerp(f[0][b][c], f[1][b][c], tx);
+            ey[b][c] = orc_lerp(e[0][b][c], e[1][b][c], tx);
+          }
+        double fz0 = orc_lerp(fy[0][0], fy[1][0], ty), fz1 = orc_lerp(fy[0][1], fy[1][1], ty);
+        double ez0 = orc_lerp(ey[0][0], ey[1][0], ty), ez1 = orc_lerp(ey[0][1], ey[1][1], ty);
+        double fc = orc_lerp(fz0, fz1, tz), ec = orc_lerp(ez0, ez1, tz);
+        if (fabs(fc) < lim) s += pow(fabs(ec), p) * hs * hs;
+      }
+  return s;
+}
+
+double orc_energy_sum(const double* phi, const double* d, const orc_grid* g, double p, int R) {
+  double s = 0.0;
+  if (g->dim == 2) {
+    for (int i = 0; i + 1 < g->n[0]; ++i)
+      for (int j = 0; j + 1 < g->n[1]; ++j) s += orc_energy_2d_cell(phi, d, g, i, j, p);
+  } else {
+    for (int i = 0; i + 1 < g->n[0]; ++i)
+      for (int j = 0; j + 1 < g->n[1]; ++j)
+        for (int k = 0; k + 1 < g->n[2]; ++k) s += orc_energy_3d_cell(phi, d, g, i, j, k, p, R);
+  }
+  return s;
+}

@@ -1,0 +1,111 @@
+"""Pins of the oracle's energy functional E_p (Section 3.5, eqs.
+energyApprox and energyApproxFiner) against values that the mathematics or
+the paper fixes, independent of the oracle's own code:
+
+* 2D, unit circle and the 64-point cloud on it: E_2 of the exact circle is
+  sqrt(256 (pi/64 - sin(pi/64))) = 7.1035e-2, the paper's reference value for
+  its circle test; the discrete E_2 of the circle's signed distance
+  approaches it as h -> 0.
+* 2D, a straight line y = y0 with constant d = c: the segments tile the
+  line, so E_p = c L^(1/p) exactly.
+* 2D, one cell crossed on all four edges, worked by hand.
+* 3D, a plane z = z0 through the centres of one layer of subcells: exactly
+  that layer counts (its neighbours lie h' away, beyond (sqrt 3/2) h'), so
+  E_1 with d linear in x is the integral of d over the plane's rectangle
+  (the midpoint rule is exact for linear d).  Shifting the plane by 0.2 h'
+  brings the next layer within 0.8 h' < (sqrt 3/2) h': two layers count.
+* Homogeneity E_p(phi, lam d) = lam E_p(phi, d) and symmetry under phi -> -phi.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22205_amd import synth
+
+E2_CIRCLE = math.sqrt(256.0 * (math.pi / 64.0 - math.sin(math.pi / 64.0)))
+
+
+def circle_case(n):
+    g = synth.cube_grid(2, n, -1.5, 1.5)
+    X = oracle.node_coords(g)
+    phi = (np.linalg.norm(X, axis=1) - 1.0).reshape(g["n"])
+    th = 2.0 * np.pi * np.arange(64) / 64.0
+    pts = np.stack([np.cos(th), np.sin(th)], 1)
+    return g, phi, oracle.distance(pts, g)
+
+
+@pytest.mark.parametrize("n,tol", [(401, 2e-3), (1601, 5e-4)])
+def test_energy_circle_approaches_exact_value(n, tol):
+    assert abs(E2_CIRCLE - 7.103510780002126e-02) < 1e-15
+    g, phi, d = circle_case(n)
+    e2 = oracle.energy(phi, d, g, 2.0)
+    assert abs(e2 - E2_CIRCLE) / E2_CIRCLE < tol
+
+
+@pytest.mark.parametrize("p", [1.0, 2.0, 3.0])
+def test_energy_straight_line(p):
+    g = synth.cube_grid(2, 41, -1.0, 1.0)
+    X = oracle.node_coords(g)
+    y0 = 0.1234
+    phi = (X[:, 1] - y0).reshape(g["n"])
+    c = 0.37
+    d = np.full(g["n"], c)
+    L = (g["n"][0] - 1) * g["h"]
+    assert oracle.energy(phi, d, g, p) == pytest.approx(c * L ** (1.0 / p), rel=1e-13)
+
+
+def test_energy_four_crossing_cell():
+    # vertices (i,j)=3, (i+1,j)=-1, (i,j+1)=-1, (i+1,j+1)=1; centre mean 0.5 lies
+    # outside like vertex (i,j): crossings (0.75,0)-(1,0.5) and (0.5,1)-(0,0.75)
+    g = {"dim": 2, "n": (2, 2), "lo": (0.0, 0.0), "h": 1.0}
+    phi = np.array([[3.0, -1.0], [-1.0, 1.0]])
+    d = np.ones((2, 2))
+    seg = math.hypot(0.25, 0.5)
+    assert oracle.energy(phi, d, g, 1.0) == pytest.approx(2.0 * seg, rel=1e-14)
+    # the other pairing would give hypot(0.75, 0.75) + hypot(0.5, 0.5)
+    assert abs(2.0 * seg - (math.hypot(0.75, 0.75) + math.hypot(0.5, 0.5))) > 0.5
+
+
+def plane_case(shift, R=5):
+    g = synth.cube_grid(3, 13, -1.0, 1.0)
+    h = g["h"]
+    hs = h / R
+    k0, w0 = 5, 2
+    z0 = g["lo"][2] + (k0 + (w0 + 0.5) / R) * h + shift * hs
+    X = oracle.node_coords(g)
+    phi = (X[:, 2] - z0).reshape(g["n"])
+    a, b = 2.0, 0.5
+    d = (a + b * X[:, 0]).reshape(g["n"])
+    x0, x1 = g["lo"][0], g["lo"][0] + (g["n"][0] - 1) * h
+    y0, y1 = g["lo"][1], g["lo"][1] + (g["n"][1] - 1) * h
+    integral = (a * (x1 - x0) + 0.5 * b * (x1 ** 2 - x0 ** 2)) * (y1 - y0)
+    return g, phi, d, integral
+
+
+def test_energy_plane_one_layer():
+    g, phi, d, integral = plane_case(0.0)
+    assert oracle.energy(phi, d, g, 1.0) == pytest.approx(integral, rel=1e-12)
+
+
+def test_energy_plane_threshold():
+    # 0.2 h' off a centre: the next layer's centres are 0.8 h' away (< 0.866 h')
+    g, phi, d, integral = plane_case(0.2)
+    assert oracle.energy(phi, d, g, 1.0) == pytest.approx(2.0 * integral, rel=1e-12)
+    # 0.05 h' off: the neighbours are 0.95 h' and 1.05 h' away
+    g, phi, d, integral = plane_case(0.05)
+    assert oracle.energy(phi, d, g, 1.0) == pytest.approx(integral, rel=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_homogeneous_and_symmetric(dim):
+    g = synth.cube_grid(dim, 24 if dim == 3 else 64)
+    X = oracle.node_coords(g)
+    r = np.linalg.norm(X - 0.05, axis=1)
+    phi = (r - 0.55 + 0.03 * np.sin(7 * X[:, 0])).reshape(g["n"])
+    d = (0.1 + np.abs(np.cos(3 * X[:, 1]))).reshape(g["n"])
+    e = oracle.energy(phi, d, g, 2.0)
+    assert e > 0
+    assert oracle.energy(phi, 3.0 * d, g, 2.0) == pytest.approx(3.0 * e, rel=1e-13)
+    assert oracle.energy(-phi, d, g, 2.0) == pytest.approx(e, rel=1e-13)
