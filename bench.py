@@ -357,6 +357,16 @@ def main():
         "jobs_per_s": args.steps / wall,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
     }
+    # E_2 of the last job's final phi (Section 3.5), outside the timed
+    # region: this workload runs at p = 1 for a fixed step count, so its loop
+    # needs no energy.  Wall time per call includes the 8-byte copy back and
+    # the synchronisation; the kernels' own time is in the rocprofv3 trace.
+    e2 = job.energy(2.0)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        job.energy(2.0)
+    out["energy"] = {"p": 2, "R": 5, "E_p": e2,
+                     "wall_us_per_call": round((time.perf_counter() - t0) / 10 * 1e6, 1)}
     job.close()
     if args.batch_jobs:
         out["batched"] = run_batched(args.batch_jobs, args.batch_steps, args.precision,

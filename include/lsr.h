@@ -25,7 +25,7 @@
  *    lsr_create (a batch's on its own stream, with its second stream
  *    joined back into it within every call); only calls that return
  *    host-side values from the device (lsr_load_cloud's input check,
- *    lsr_extract with n_band, lsr_counters, lsr_profile_read,
+ *    lsr_extract with n_band, lsr_energy, lsr_counters, lsr_profile_read,
  *    lsr_batch_tune) and the switches of the graph, stream and timing
  *    hooks synchronise that stream.
  *  - Nodal arrays are in C order: 2D index i*n[1] + j, 3D index
@@ -164,6 +164,18 @@ lsr_status lsr_step(lsr_job* job, int32_t n_steps, double dt, lsr_interp interp)
 /* One reinitialisation (Section 3.7) plus cut, on the current band and its
  * face neighbours, outside the step loop. */
 lsr_status lsr_reinit(lsr_job* job);
+
+/* Energy functional E_p(phi) of Section 3.5 of the current phi with the
+ * job's distance field: over the front cells (the cells whose vertices do
+ * not all lie on one side of the front, a vertex being inside when
+ * phi < 0), in 2D the trapezoidal rule on the segment between the linear
+ * edge crossings (eq. energyApprox), in 3D the sum of |d|^p h'^2 over the R^3
+ * subcells of side h' = h / R per front cell whose trilinear phi at the
+ * centre lies within (sqrt 3 / 2) h' of zero (eq. energyApproxFiner; the
+ * paper uses R = 5).  Computed in double; *out (host) receives E_p.  p:
+ * finite, > 0; R: 1..64 (ignored in 2D); else LSR_E_INVALID.  LSR_E_STATE
+ * without phi or d, or for a job in a batch.  Synchronises the stream. */
+lsr_status lsr_energy(lsr_job* job, double p, int32_t R, double* out);
 
 /* Copy out the current phi (dev_phi: device, one value per node in the job's
  * precision) and the band

@@ -102,6 +102,7 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.max_sup = (int64_t)std::min((size_t)nsup, P);
   L.sup = take(8 * (size_t)L.max_sup);
   L.sgeo = take(8 * (size_t)GEO * (size_t)L.max_sup);
+  L.energy = take(8 * ((size_t)ENERGY_BLOCKS + 1));
   L.total = off;
   return L;
 }
@@ -487,6 +488,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->sup = (int2*)(w + L.sup);
   j->sgeo = (double*)(w + L.sgeo);
   j->max_sup = L.max_sup;
+  j->energy_buf = (double*)(w + L.energy);
   j->ncu = ncu > 0 ? ncu : 256;
   j->lanes = 1;
   j->blocks_per_cu = 8;
@@ -670,6 +672,29 @@ lsr_status lsr_reinit(lsr_job* j) {
   if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
   if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   return run_reinit(j);
+}
+
+lsr_status lsr_energy(lsr_job* j, double p, int32_t R, double* out) {
+  if (!j || !out) return fail(LSR_E_INVALID, "NULL argument");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
+  if (!(p > 0.0) || !isfinite(p)) return fail(LSR_E_INVALID, "p must be finite and > 0");
+  if (R < 1 || R > 64) return fail(LSR_E_INVALID, "R must be in 1..64");
+  if (!j->has_phi) return fail(LSR_E_STATE, "no phi: call lsr_init_phi first");
+  if (!j->has_d) return fail(LSR_E_STATE, "no distance field yet");
+  hipStream_t s = j->stream;
+  double* part = j->energy_buf;
+  double* dout = part + ENERGY_BLOCKS;
+  if (j->fp64)
+    LSR_HIP(launch_energy<double>(j->grid.dim, j->dg, phi_buf<double>(j, j->cur), j->d64, p, R,
+                                  part, dout, s));
+  else
+    LSR_HIP(launch_energy<float>(j->grid.dim, j->dg, phi_buf<float>(j, j->cur), j->d64, p, R,
+                                 part, dout, s));
+  double v = 0.0;
+  LSR_HIP(hipMemcpyAsync(&v, dout, sizeof(double), hipMemcpyDeviceToHost, s));
+  LSR_HIP(hipStreamSynchronize(s));
+  *out = v;
+  return LSR_OK;
 }
 
 lsr_status lsr_extract(lsr_job* j, void* dev_phi, uint8_t* dev_band, int64_t* n_band,

@@ -209,6 +209,13 @@ hipError_t launch_super_geo(int dim, const double* pts, const int32_t* start,
                             const uint32_t* occ, const int2* sup, const int32_t* sup_cnt,
                             double* sgeo, int64_t max_sup, hipStream_t s);
 hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s);
+// Energy functional E_p of Section 3.5 (R subcells per axis in 3D) of the
+// nodal phi and d: per-block sums into partial[ENERGY_BLOCKS], then
+// out[0] = E_p.
+constexpr unsigned ENERGY_BLOCKS = 1024;
+template <typename T>
+hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* d, double p, int R,
+                         double* partial, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,
                         hipStream_t s);

@@ -30,6 +30,7 @@ struct Layout {
   size_t blist0, blist1, bstamp;  // brick lists and stamps of the staged 3D step
   int64_t nbricks;
   size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo, sup, sgeo;
+  size_t energy;  // energy partial sums and result
   int64_t max_occ, max_sup;
   size_t total;
   int64_t nbins;  // bin ids at the finer width, super-bin padding included
@@ -72,6 +73,7 @@ struct lsr_job {
   int2* sup;        // occupied super-bins: their runs in the occupied list
   double* sgeo;     // super-bin frames
   int64_t max_sup;  // room for super-bins
+  double* energy_buf;  // ENERGY_BLOCKS partial sums, then E_p
   uint32_t* blist[2];
   uint32_t* bstamp;
   int cur_blist;       // brick list buffer holding the current brick list

@@ -1595,6 +1595,190 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   }
 }
 
+// ------------------------------------------------------------ energy
+
+// Energy functional of Section 3.5 over the front cells, the cells whose
+// vertices do not all lie on one side of the front (inside: phi < 0):
+//  2D (eq. energyApprox): the trapezoidal rule on the segment between the
+//     zeros of the linear interpolants of phi on the crossed edges, with d
+//     interpolated linearly along the edge there; a cell crossed on all four
+//     edges gets two segments, which leave the centre (phi = mean of the
+//     corners) on the side of corner (i, j) when the two agree;
+//  3D (eq. energyApproxFiner): R^3 subcells of side h' = h / R per front
+//     cell; a subcell whose trilinear phi at its centre is below
+//     (sqrt 3 / 2) h' in magnitude adds |d|^p h'^2, d trilinear as well.
+// All in double, without FMA contraction.
+__device__ __forceinline__ double lerp_d(double a, double b, double t) { return a + t * (b - a); }
+
+// |x|^p, with the common exponents exact to rounding and without pow
+__device__ __forceinline__ double pow_abs(double x, double p) {
+  const double a = fabs(x);
+  return p == 2.0 ? a * a : (p == 1.0 ? a : pow(a, p));
+}
+
+// Corners of a 2D cell in edge order: (i,j), (i+1,j), (i+1,j+1), (i,j+1).
+__device__ double energy_cell_2d(const DevGrid& g, const double f[4], const double e[4], int i,
+                                 int j, double p) {
+#pragma clang fp contract(off)
+  const int ci[4] = {i, i + 1, i + 1, i}, cj[4] = {j, j, j + 1, j + 1};
+  bool in[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) in[q] = f[q] < 0.0;
+  double px[4], py[4], pd[4];
+  bool has[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = (q + 1) & 3;
+    has[q] = in[q] != in[r];
+    px[q] = py[q] = pd[q] = 0.0;
+    if (!has[q]) continue;
+    const double t = f[q] / (f[q] - f[r]);
+    px[q] = g.lo0 + g.hd * lerp_d((double)ci[q], (double)ci[r], t);
+    py[q] = g.lo1 + g.hd * lerp_d((double)cj[q], (double)cj[r], t);
+    pd[q] = lerp_d(e[q], e[r], t);
+  }
+  int a0 = -1, b0 = -1, a1 = -1, b1 = -1;
+  if (has[0] && has[1] && has[2] && has[3]) {
+    const double centre = 0.25 * (f[0] + f[1] + f[2] + f[3]);
+    if ((centre < 0.0) == in[0]) {
+      a0 = 0; b0 = 1; a1 = 2; b1 = 3;  // segments cut off corners 1 and 3
+    } else {
+      a0 = 3; b0 = 0; a1 = 1; b1 = 2;  // segments cut off corners 0 and 2
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (has[q]) {
+        if (a0 < 0) a0 = q; else b0 = q;
+      }
+  }
+  auto seg = [&](int a, int b) {
+    const double L = hypot(px[a] - px[b], py[a] - py[b]);
+    return L * 0.5 * (pow_abs(pd[a], p) + pow_abs(pd[b], p));
+  };
+  double s = seg(a0, b0);
+  if (a1 >= 0) s += seg(a1, b1);
+  return s;
+}
+
+// Each block walks chunks of 256 cells (one lower-corner node per thread,
+// with a grid stride); the front cells of a chunk are compacted into LDS in
+// lane order, their vertex values with them, and the whole block then works
+// through their subcells (3D) or segments (2D).  The block's sum goes to
+// partial[blockIdx.x]; every sum runs in a fixed order, so a launch of the
+// same grid always gives the same result.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_energy(DevGrid g, const T* __restrict__ phi,
+                                                const double* __restrict__ d, double p, int R,
+                                                double* __restrict__ partial) {
+#pragma clang fp contract(off)
+  constexpr int NV = DIM == 3 ? 8 : 4;
+  __shared__ double fv[256][NV], ev[256][NV];
+  __shared__ int cij[256][2];
+  __shared__ int wcnt[4];
+  __shared__ double red[4];
+  const int tid = (int)threadIdx.x, wv = tid >> 6;
+  const uint32_t m0 = (uint32_t)g.n0 - 1u, m1 = (uint32_t)g.n1 - 1u;
+  const uint32_t m2 = DIM == 3 ? (uint32_t)g.n2 - 1u : 1u;
+  const uint64_t ncell = (uint64_t)m0 * m1 * m2;
+  const double hs = g.hd / R;
+  const double lim = 0.5 * sqrt(3.0) * hs;
+  const int R3 = R * R * R;
+  double s = 0.0;
+  for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < ncell;
+       base += (uint64_t)gridDim.x * 256u) {
+    const uint64_t c = base + (uint64_t)tid;
+    bool front = false;
+    int i = 0, j = 0, k = 0;
+    double f[NV];
+    uint32_t node = 0;
+    if (c < ncell) {
+      k = (int)(c % m2);
+      const uint64_t r = c / m2;
+      j = (int)(r % m1);
+      i = (int)(r / m1);
+      node = (uint32_t)i * g.s0 + (uint32_t)j * g.s1 + (uint32_t)k;
+      int n_in = 0;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        // 3D: q = 4a + 2b + c' for vertex (i+a, j+b, k+c'); 2D: edge order
+        uint32_t off;
+        if (DIM == 3)
+          off = (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 + (uint32_t)(q & 1);
+        else
+          off = (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
+        f[q] = (double)phi[node + off];
+        n_in += f[q] < 0.0 ? 1 : 0;
+      }
+      front = n_in != 0 && n_in != NV;
+    }
+    // ordered compaction of the chunk's front cells
+    const uint64_t m = __ballot(front);
+    if (lane_id() == 0) wcnt[wv] = (int)__popcll(m);
+    __syncthreads();
+    int off = 0;
+    for (int q = 0; q < wv; ++q) off += wcnt[q];
+    const int nfront = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (front) {
+      const int pos = off + (int)lanes_below(m);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        uint32_t o;
+        if (DIM == 3)
+          o = (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 + (uint32_t)(q & 1);
+        else
+          o = (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
+        fv[pos][q] = f[q];
+        ev[pos][q] = d[node + o];
+      }
+      cij[pos][0] = i;
+      cij[pos][1] = j;
+    }
+    __syncthreads();
+    if (DIM == 3) {
+      for (int it = tid; it < nfront * R3; it += 256) {
+        const int cell = it / R3, sub = it - cell * R3;
+        const int u = sub / (R * R), v = (sub / R) % R, w = sub % R;
+        const double tx = (u + 0.5) / R, ty = (v + 0.5) / R, tz = (w + 0.5) / R;
+        // trilinear: along x, then y, then z; vertex (a, b, c') at 4a + 2b + c'
+        const double* F = fv[cell];
+        const double* E = ev[cell];
+        const double fy00 = lerp_d(F[0], F[4], tx), fy01 = lerp_d(F[1], F[5], tx);
+        const double fy10 = lerp_d(F[2], F[6], tx), fy11 = lerp_d(F[3], F[7], tx);
+        const double ey00 = lerp_d(E[0], E[4], tx), ey01 = lerp_d(E[1], E[5], tx);
+        const double ey10 = lerp_d(E[2], E[6], tx), ey11 = lerp_d(E[3], E[7], tx);
+        const double fz0 = lerp_d(fy00, fy10, ty), fz1 = lerp_d(fy01, fy11, ty);
+        const double ez0 = lerp_d(ey00, ey10, ty), ez1 = lerp_d(ey01, ey11, ty);
+        const double fc = lerp_d(fz0, fz1, tz);
+        if (fabs(fc) < lim) s += pow_abs(lerp_d(ez0, ez1, tz), p) * hs * hs;
+      }
+    } else {
+      for (int it = tid; it < nfront; it += 256)
+        s += energy_cell_2d(g, fv[it], ev[it], cij[it][0], cij[it][1], p);
+    }
+    __syncthreads();
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0) red[wv] = s;
+  __syncthreads();
+  if (tid == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Sum of the n partial sums in a fixed order, and its p-th root: out[0] = E_p.
+__global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ partial, int n,
+                                                      double p, double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) s += partial[q];
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = ((red[0] + red[1]) + red[2]) + red[3];
+    out[0] = pow(t, 1.0 / p);
+  }
+}
+
 // Centred gradient of d (one-sided on the boundary), in double, packed with
 // d itself: dp = (d_x, d_y, d_z, d) in the state's precision (d_z = 0 in 2D).
 template <int DIM, typename P>
@@ -1853,6 +2037,18 @@ hipError_t launch_super_geo(int dim, const double* pts, const int32_t* start,
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* d, double p, int R,
+                         double* partial, double* out, hipStream_t s) {
+  dim3 gr(ENERGY_BLOCKS), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_energy<3, T>), gr, bl, 0, s, g, phi, d, p, R, partial);
+  else
+    hipLaunchKernelGGL((k_energy<2, T>), gr, bl, 0, s, g, phi, d, p, R, partial);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), bl, 0, s, partial, (int)ENERGY_BLOCKS, p, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s) {
   if (dim == 3)
     hipLaunchKernelGGL(k_distance<3>, dim3(bricks), dim3(256), 0, s, a);
@@ -1936,7 +2132,9 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_reinit_fix_batch<T>(int, const RArgs<T>*, int, unsigned, hipStream_t);\
   template hipError_t launch_reinit_iter_batch<T>(int, const RArgs<T>*, int, unsigned,             \
                                                   hipStream_t);                                   \
-  template hipError_t launch_reinit_final_batch<T>(const FinArgs<T>*, int, unsigned, hipStream_t);
+  template hipError_t launch_reinit_final_batch<T>(const FinArgs<T>*, int, unsigned, hipStream_t);\
+  template hipError_t launch_energy<T>(int, const DevGrid&, const T*, const double*, double, int,  \
+                                       double*, double*, hipStream_t);
 
 LSR_INSTANTIATE(float)
 LSR_INSTANTIATE(double)

@@ -26,7 +26,7 @@ COUNTER_NAMES = ["node_updates", "fallbacks", "frame0", "reinits", "gbar", "inte
 EXPORTED = [
     "lsr_params_default", "lsr_workspace_bytes", "lsr_create", "lsr_load_cloud",
     "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
-    "lsr_extract", "lsr_counters", "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
+    "lsr_extract", "lsr_energy", "lsr_counters", "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
     "lsr_batch_add", "lsr_batch_remove", "lsr_batch_step", "lsr_batch_set_launch",
     "lsr_batch_tune", "lsr_batch_destroy", "lsr_batch_set_graphs", "lsr_batch_set_streams",
     "lsr_set_launch",
@@ -79,6 +79,7 @@ def load():
             "lsr_step": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int],
             "lsr_reinit": [_P],
             "lsr_extract": [_P, _P, _P, I64P, I64P],
+            "lsr_energy": [_P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
             "lsr_counters": [_P, I64P, ctypes.c_int32],
             "lsr_destroy": [_P],
             "lsr_batch_workspace_bytes": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -185,6 +186,12 @@ def lsr_extract(job, phi_ptr, band_ptr, want_count=True):
                               _P(band_ptr) if band_ptr else None,
                               ctypes.byref(nb) if want_count else None, ctypes.byref(si)))
     return nb.value, si.value
+
+
+def lsr_energy(job, p, R=5):
+    out = ctypes.c_double(0.0)
+    _check(load().lsr_energy(job, float(p), int(R), ctypes.byref(out)))
+    return out.value
 
 
 def lsr_counters(job):
@@ -355,6 +362,10 @@ class Job:
         phi, band, nb, si = self.extract_device()
         self.stream.synchronize()
         return phi.cpu().numpy(), band.cpu().numpy(), nb, si
+
+    def energy(self, p, R=5):
+        """E_p of the current phi (Section 3.5); synchronises the stream."""
+        return lsr_energy(self.handle, p, R)
 
     def counters(self):
         return lsr_counters(self.handle)

@@ -1,0 +1,111 @@
+"""GPU parity of the energy functional E_p (Section 3.5) through the C ABI:
+lsr_energy on the device's phi and d against the oracle's E_p of the same
+nodal values.  Both sum in double over the same cells with the same
+arithmetic per cell (no FMA contraction) in different orders, and take the
+same subcell decisions; tolerance 1e-12 relative."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _job(w, precision):
+    from paper_2410_22205_amd import lsr
+    g = w["grid"]
+    prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w.get("reinit_every", 10),
+               precision=precision)
+    return lsr.Job(g, prm, max_points=len(w["points"]))
+
+
+def _evolved(name, n, steps, precision):
+    w = synth.workload(name, n=n)
+    job = _job(w, precision)
+    job.load_cloud(w["points"])
+    job.init_phi(w["phi0"][0], w["phi0"][1])
+    if steps:
+        job.step(steps, w["dt"], w["interp"])
+    return w, job
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,n,steps", [("circle2d", 128, 30), ("circle2d", 61, 5),
+                                          ("torus3d", 48, 12), ("torus3d", 37, 3)])
+@pytest.mark.parametrize("p", [1.0, 2.0])
+def test_energy_matches_oracle(name, n, steps, precision, p):
+    w, job = _evolved(name, n, steps, precision)
+    try:
+        phi, _, _, _ = job.extract()
+        d = job.distance()
+        e = job.energy(p)
+        e3 = job.energy(p, R=3) if w["grid"]["dim"] == 3 else None
+    finally:
+        job.close()
+    eo = oracle.energy(phi.astype(np.float64), d, w["grid"], p)
+    assert eo > 0
+    assert abs(e - eo) <= TOL * eo, (e, eo)
+    if e3 is not None:
+        eo3 = oracle.energy(phi.astype(np.float64), d, w["grid"], p, R=3)
+        assert abs(e3 - eo3) <= TOL * eo3, (e3, eo3)
+
+
+def test_energy_circle_of_64_points():
+    """The unit circle's signed distance and the 64-point cloud on it: E_2
+    close to the exact 7.1035e-2 and equal to the oracle's."""
+    from paper_2410_22205_amd import lsr
+    g = synth.cube_grid(2, 801, -1.5, 1.5)
+    th = 2.0 * np.pi * np.arange(64) / 64.0
+    pts = np.stack([np.cos(th), np.sin(th)], 1)
+    X = oracle.node_coords(g)
+    phi = (np.linalg.norm(X, axis=1) - 1.0).reshape(g["n"])
+    job = lsr.Job(g, dict(gamma=6 * g["h"], beta=3 * g["h"], precision="fp64"), max_points=64)
+    try:
+        job.load_cloud(pts)
+        job.init_phi(phi0=phi)
+        cut, _, _, _ = job.extract()
+        d = job.distance()
+        e = job.energy(2.0)
+    finally:
+        job.close()
+    exact = math.sqrt(256.0 * (math.pi / 64.0 - math.sin(math.pi / 64.0)))
+    assert abs(e - exact) / exact < 5e-3
+    eo = oracle.energy(cut, d, g, 2.0)
+    assert abs(e - eo) <= TOL * eo
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_without_front_is_zero(dim):
+    """phi0 a sphere that holds the whole grid: no cell is crossed."""
+    w = synth.workload("circle2d" if dim == 2 else "torus3d", n=32)
+    job = _job(w, "fp64")
+    try:
+        job.load_cloud(w["points"])
+        job.init_phi("sphere", (0.0, 0.0, 0.0, 5.0))
+        assert job.energy(2.0) == 0.0
+    finally:
+        job.close()
+
+
+def test_energy_arguments():
+    from paper_2410_22205_amd import lsr
+    w = synth.workload("circle2d", n=32)
+    job = _job(w, "fp32")
+    try:
+        with pytest.raises(RuntimeError):
+            job.energy(2.0)  # no phi, no d yet
+        job.load_cloud(w["points"])
+        job.init_phi(w["phi0"][0], w["phi0"][1])
+        for bad in (0.0, -1.0, float("nan")):
+            with pytest.raises(RuntimeError):
+                job.energy(bad)
+        with pytest.raises(RuntimeError):
+            lsr.lsr_energy(job.handle, 2.0, 0)
+        assert job.energy(1.0) > 0
+    finally:
+        job.close()
