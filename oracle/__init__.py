@@ -207,6 +207,24 @@ def run(phi0, d, grid, prm, dt, kind, n_steps, step0=0):
     return phi, counts
 
 
+def run_p(phi0, d, grid, prm, dt, kind, n_steps, step0=0, R=5):
+    """n_steps of Algorithm 1's loop with the energy step, for p != 1: at
+    every step E_p of the current phi (Section 3.5, R subcells per axis in
+    3D) enters the update's C, then the band, update and every
+    reinit_every-th step the reinitialisation and cut, as in :func:`run`.
+    Returns (phi, energies) with energies[s] = E_p(phi^s)."""
+    phi = np.array(phi0, dtype=np.float64, order="C", copy=True)
+    energies = []
+    for s in range(n_steps):
+        E = energy(phi, d, grid, prm["p"], R)
+        energies.append(E)
+        nxt, band, _ = step(phi, d, grid, dict(prm, energy=E), dt, kind)
+        if prm["reinit_every"] > 0 and (step0 + s + 1) % prm["reinit_every"] == 0:
+            nxt, _ = reinit(nxt, band, grid, prm)
+        phi = nxt
+    return phi, energies
+
+
 def band_mask(phi, prm):
     """Narrow band of eq. (subgrid), read as |phi| < gamma."""
     return (np.abs(phi) < prm["gamma"]).astype(np.uint8)

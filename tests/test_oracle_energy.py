@@ -109,3 +109,52 @@ def test_energy_homogeneous_and_symmetric(dim):
     assert e > 0
     assert oracle.energy(phi, 3.0 * d, g, 2.0) == pytest.approx(3.0 * e, rel=1e-13)
     assert oracle.energy(-phi, d, g, 2.0) == pytest.approx(e, rel=1e-13)
+
+
+# ------------------------------------------------ the p = 2 step (Section 2)
+
+def test_p2_with_constant_d_equals_p1_with_half_delta():
+    """With d = d0 everywhere and E = d0, C = c (d/E)^(p-1) equals c, and the
+    diffusion reach sqrt(C delta d dt / p) at p = 2 is that of p = 1 with
+    delta / 2: the two steps agree bit for bit."""
+    g = synth.cube_grid(3, 33)
+    h = g["h"]
+    X = oracle.node_coords(g)
+    phi = (np.linalg.norm(X - 0.03, axis=1) - 0.5).reshape(g["n"])
+    phi = np.clip(phi, -6 * h, 6 * h)
+    d0 = 0.2
+    d = np.full(g["n"], d0)
+    base = oracle.default_params(3, h)
+    p2 = dict(base, p=2.0, energy=d0, delta=1.0)
+    p1 = dict(base, p=1.0, delta=0.5)
+    a, _, _ = oracle.step(phi, d, g, p2, 0.5 * h, "weno")
+    b, _, _ = oracle.step(phi, d, g, p1, 0.5 * h, "weno")
+    np.testing.assert_array_equal(a, b)
+
+
+def test_p2_radial_closed_form():
+    """A single cloud point at the origin, phi = |x| - 0.5 near the front:
+    at p = 2, C = r / E (d = r, c = 1 inside the cut-off), the drift moves a
+    node at radius r to r + C dt and the four foot points lie a distance
+    sqrt(2) a off that point across the gradient, a^2 = C delta r dt / 2, so
+    phi^{n+1} = sqrt((r + C dt)^2 + C delta r dt) - 0.5 up to interpolation
+    error.  Misplacing the factor or the 1/p leaves an O(h) residual."""
+    g = synth.cube_grid(3, 65)
+    h = g["h"]
+    prm = dict(oracle.default_params(3, h), p=2.0, energy=0.4)
+    dt = 0.5 * h
+    d = oracle.distance_brute(np.zeros((1, 3)), g)
+    phi = d - 0.5
+    sel = np.nonzero((np.abs(phi.ravel()) <= prm["beta"]) & (d.ravel() > 0.2))[0][:200]
+    got, _ = oracle.sl_nodes(phi, d, g, prm, dt, "weno", sel)
+    r = d.ravel()[sel]
+    E = prm["energy"]
+
+    def closed(C, half):
+        return np.sqrt((r + C * dt) ** 2 + (0.5 if half else 1.0) * 2 * C * r * dt) - 0.5
+
+    right = np.abs(got - closed(r / E, True)).max()
+    assert right < 0.05 * h
+    assert right < 0.1 * np.abs(got - closed(r / E, False)).max()   # 1/p dropped
+    assert right < 0.1 * np.abs(got - closed(1.0, True)).max()      # (d/E) dropped
+    assert right < 0.1 * np.abs(got - closed(E / r, True)).max()    # inverted ratio
