@@ -75,7 +75,12 @@ typedef struct {
 
 /* Parameters (see lsr_params_default for the values the paper uses). */
 typedef struct {
-  double p;          /* energy exponent of Section 2; only p = 1 is supported */
+  double p;          /* energy exponent of Section 2: 1 or 2 (the values the
+                        paper runs; else LSR_E_UNSUPPORTED).  For p = 2 every
+                        step first computes E_2 of the current phi (Section
+                        3.5, R = 5; see lsr_energy) on the device and scales
+                        the update's C by d / E_2; E_2 = 0 (no front) stops
+                        the motion */
   double delta;      /* curvature weight, eq. (levelset:pde); >= 0 */
   double gamma;      /* narrow-band half width, eq. (subgrid); band |phi| < gamma */
   double beta;       /* cut-off inner radius, eq. (cutoff); 0 < beta < gamma */
@@ -209,7 +214,8 @@ lsr_status lsr_destroy(lsr_job* job);
  * lsr_batch_add: the job joins at the next batch step, after the work
  * already queued on its own stream (no host synchronisation); a job in a
  * batch refuses lsr_step, lsr_reinit, lsr_init_phi, lsr_load_cloud,
- * lsr_set_distance, lsr_set_launch and lsr_destroy.
+ * lsr_set_distance, lsr_set_launch and lsr_destroy.  Only jobs with p = 1
+ * join a batch (else LSR_E_UNSUPPORTED).
  * lsr_batch_remove: the job leaves at the current step boundary; its own
  * stream is ordered after the batch's queued work.
  * lsr_batch_step: n_steps steps of every member (uploads one table per group).

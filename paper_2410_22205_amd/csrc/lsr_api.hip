@@ -125,7 +125,7 @@ lsr_status check_grid(const lsr_grid* g) {
 lsr_status check_params(const lsr_grid* g, const lsr_params* p) {
   if (!p) return fail(LSR_E_INVALID, "params is NULL");
   if (!(p->p >= 1.0)) return fail(LSR_E_INVALID, "p must be >= 1");
-  if (p->p != 1.0) return fail(LSR_E_UNSUPPORTED, "p != 1 needs the energy functional");
+  if (p->p != 1.0 && p->p != 2.0) return fail(LSR_E_UNSUPPORTED, "p must be 1 or 2");
   if (!(p->delta >= 0.0) || !isfinite(p->delta)) return fail(LSR_E_INVALID, "delta must be >= 0");
   if (!(p->beta > 0.0) || !(p->gamma > p->beta) || !isfinite(p->gamma))
     return fail(LSR_E_INVALID, "need 0 < beta < gamma");
@@ -184,14 +184,24 @@ static lsr_status rebuild_bricks(lsr_job* j) {
 // n steps of the node-list kernel, each followed by the reinitialisation
 // when due, from the current plan state, which they advance.  With launch
 // false nothing is launched (the state of a replayed graph).
+// Algorithm 1, step 2, for p != 1: E_p of the current phi, left on the
+// device for the step kernel that follows.
+template <typename T>
+static hipError_t launch_step_energy(lsr_job* j) {
+  return launch_energy<T>(j->grid.dim, j->dg, phi_buf<T>(j, j->cur), j->d64, j->prm.p, ENERGY_R,
+                          j->energy_buf, j->energy_buf + ENERGY_BLOCKS, j->stream);
+}
+
 template <typename T>
 static hipError_t issue_steps(lsr_job* j, int32_t n, const StepConst<T>& c, int interp,
                               bool launch) {
   hipStream_t s = j->stream;
   hipError_t e = hipSuccess;
   for (int32_t q = 0; q < n && e == hipSuccess; ++q) {
+    if (launch && j->prm.p != 1.0) e = launch_step_energy<T>(j);
     SLArgs<T> a = plan_step<T>(j, c);
-    if (launch) e = launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s);
+    if (launch && e == hipSuccess)
+      e = launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s);
     if (reinit_due(j)) {
       ReinitPlan<T> r = plan_reinit<T>(j);
       if (launch && e == hipSuccess) e = launch_reinit_plan<T>(j, r);
@@ -252,6 +262,7 @@ static lsr_status direct_steps(lsr_job* j, int32_t n_steps, const StepConst<T>& 
       lsr_status st = rebuild_bricks(j);
       if (st != LSR_OK) return st;
     }
+    if (j->prm.p != 1.0) LSR_HIP(launch_step_energy<T>(j));
     SLArgs<T> a = plan_step<T>(j, c);
     const bool rec = j->prof_on && 2 * (size_t)j->prof_used + 1 < j->prof_ev.size();
     hipEvent_t e0 = rec ? j->prof_ev[2 * j->prof_used] : nullptr;

@@ -516,6 +516,7 @@ lsr_status lsr_batch_add(lsr_batch* b, lsr_job* j, double dt, lsr_interp interp)
   if (j->in_batch) return fail(LSR_E_STATE, "the job is already in a batch");
   if ((int)b->jobs.size() >= b->max_jobs) return fail(LSR_E_NOMEM, "the batch is full");
   if (j->prm.reinit_iters > b->max_iters) return fail(LSR_E_NOMEM, "reinit_iters above the batch's maximum");
+  if (j->prm.p != 1.0) return fail(LSR_E_UNSUPPORTED, "batches run p = 1 jobs");
   if (b->dim && (j->grid.dim != b->dim || j->fp64 != b->fp64))
     return fail(LSR_E_UNSUPPORTED, "a batch needs one dimension and one precision");
   if (!(dt > 0.0) || !isfinite(dt)) return fail(LSR_E_INVALID, "dt must be > 0");

@@ -73,6 +73,8 @@ struct StepConst {
   T diff2;                 // delta dt / (p h^2): squared diffusion reach in cells per unit C d
   T grad_thr;              // C dt^alpha of the fallback test
   T weno_e;                // h^4 (eps = h^2 with indicators scaled by h^2)
+  T pm1;                   // p - 1: 0 or 1 (p = 1 or 2)
+  T inv_E;                 // 1 / E_p(phi^n) when p = 2, read on the device per step
   T half_inv_h, inv_h;
 };
 
@@ -373,7 +375,9 @@ __device__ __forceinline__ T sl_update_src(const S& src, const DevGrid& g, const
     out = sum / cnt;
     flags |= UPD_FALLBACK;
   } else {
-    const T C = cutoff(v, c);
+    // C = c(phi) [d / E_p]^(p - 1), eqs. (SL2d)/(SL3d), p = 1 or 2
+    T C = cutoff(v, c);
+    if (c.pm1 != T(0)) C *= dp.w * c.inv_E;
     const T amp = sqrt(C * dp.w * c.diff2);  // diffusion reach in cells
     const T cd = C * c.drift;
     const T bx = cd * dp.x, by = cd * dp.y, bz = DIM == 3 ? cd * dp.z : T(0);

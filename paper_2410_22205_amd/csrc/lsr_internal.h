@@ -66,6 +66,9 @@ struct SLArgs {
   int32_t* cnt_out;
   int32_t* cnt_reset;
   unsigned long long* stats;
+  // E_p(phi^n) on the device (written by the energy kernels before the
+  // step) when p != 1, else null
+  const double* Ep;
   // brick lists of the staged 3D step (bricks of 4 x 8 x 8 nodes): the input
   // list covers every node of Lin, the output list the bricks of Lout
   const uint32_t* BLin;
@@ -213,6 +216,8 @@ hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStrea
 // nodal phi and d: per-block sums into partial[ENERGY_BLOCKS], then
 // out[0] = E_p.
 constexpr unsigned ENERGY_BLOCKS = 1024;
+// Subcells per axis of the energy that a p = 2 step computes (the paper's R)
+constexpr int ENERGY_R = 5;
 template <typename T>
 hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* d, double p, int R,
                          double* partial, double* out, hipStream_t s);

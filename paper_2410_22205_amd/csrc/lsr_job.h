@@ -115,6 +115,8 @@ StepConst<T> step_const(const lsr_job* j, double dt) {
   c.weno_e = (T)(h * h * h * h);
   c.half_inv_h = (T)(0.5 / h);
   c.inv_h = (T)(1.0 / h);
+  c.pm1 = (T)(p.p - 1.0);
+  c.inv_E = T(0);
   return c;
 }
 
@@ -138,6 +140,7 @@ SLArgs<T> plan_step(lsr_job* j, const StepConst<T>& c) {
   a.c = c;
   a.dp = (const typename Vec<T>::pack*)j->dp;
   a.stats = j->stats;
+  a.Ep = j->prm.p != 1.0 ? j->energy_buf + ENERGY_BLOCKS : nullptr;
   a.A = phi_buf<T>(j, j->cur);
   a.B = phi_buf<T>(j, 1 - j->cur);
   a.Lin = j->list[j->cur_list];

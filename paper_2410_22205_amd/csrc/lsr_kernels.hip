@@ -240,6 +240,18 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
 // single-job kernels, and follows them from job to job, so that blocks start
 // on different jobs and no block idles while another works through the jobs.
 
+// The step's constants, with 1 / E_p(phi^n) from the device when p != 1
+// (E_p = 0, no front, stops the motion: C = 0).
+template <typename T>
+__device__ __forceinline__ StepConst<T> step_consts(const SLArgs<T>& a) {
+  StepConst<T> c = a.c;
+  if (a.Ep) {
+    const double E = *a.Ep;
+    c.inv_E = E > 0.0 ? (T)(1.0 / E) : T(0);
+  }
+  return c;
+}
+
 template <int DIM, int INTERP, typename T, int LANES>
 __device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t base, int n, int* lds_app,
                                          uint32_t& nupd, uint32_t& nfb, uint32_t& nfr) {
@@ -261,7 +273,8 @@ __device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t base, int 
     T nv = v;
     if (fabs(v) < a.c.gamma) {
       act = true;
-      nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, a.c, i, j, k, idx, v, DP[idx], sub, fl);
+      nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, step_consts(a), i, j, k, idx, v, DP[idx], sub,
+                                            fl);
     }
     if (sub == 0) B[idx] = nv;
   }
@@ -458,7 +471,8 @@ __global__ __launch_bounds__(256) void k_sl_step_staged(SLArgs<T> a) {
       code = encode(g, i2, j2, k2);
       const StagedSrc<INTERP, T, H> src{tile, oi, oj, ok, tn2,
                                         GlobalSrc<3, INTERP, T>{A, g, a.c.weno_e}};
-      B[idx] = sl_update_src<3, T, 1>(src, g, a.c, i2, j2, k2, idx, tile[tn2], DP[idx], 0, fl);
+      B[idx] = sl_update_src<3, T, 1>(src, g, step_consts(a), i2, j2, k2, idx, tile[tn2], DP[idx], 0,
+                                      fl);
     }
     block_append1(act, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds_app);
     if (t == 0 && tot > 0) a.BLout[atomicAdd(a.bcnt_out, 1)] = br;

@@ -74,7 +74,7 @@ def _create(params_over):
 @pytest.mark.parametrize("over,code", [
     ({"beta": 0.7}, lsr.LSR_E_INVALID),          # beta >= gamma
     ({"delta": -1.0}, lsr.LSR_E_INVALID),
-    ({"p": 2.0}, lsr.LSR_E_UNSUPPORTED),         # needs the energy functional
+    ({"p": 3.0}, lsr.LSR_E_UNSUPPORTED),         # the paper runs p = 1 and 2
     ({"p": 0.5}, lsr.LSR_E_INVALID),
     ({"reinit_dtau": 0.1}, lsr.LSR_E_INVALID),   # beyond h/sqrt(3)
     ({"reinit_every": -1}, lsr.LSR_E_INVALID),

@@ -109,3 +109,45 @@ def test_energy_arguments():
         assert job.energy(1.0) > 0
     finally:
         job.close()
+
+
+# ------------------------------------------------ the p = 2 loop (Section 2)
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,n,steps", [("circle2d", 128, 25), ("torus3d", 40, 12)])
+def test_p2_run_matches_oracle(name, n, steps, precision):
+    """p = 2: every step computes E_2 of the current phi on the device and
+    scales C by d / E_2 (Algorithm 1, step 2); the run follows the oracle's
+    loop with the energy step within 1e-4 h, band exact away from gamma."""
+    from test_gpu_parity import check_band, check_phi, gpu_run, oracle_params
+    w = synth.workload(name, n=n)
+    extra = {"p": 2.0}
+    phi, band, _, _, cnt, _ = gpu_run(w, steps=steps, extra=extra, precision=precision)
+    g = w["grid"]
+    prm = oracle_params(w, extra)
+    d = oracle.distance(w["points"], g)
+    phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
+    ophi, energies = oracle.run_p(phi0, d, g, prm, w["dt"], w["interp"], steps)
+    assert all(e > 0 for e in energies)
+    check_phi(phi, ophi, g["h"], 1e-4)
+    check_band(band, phi, ophi, prm["gamma"], g["h"])
+    # the p = 1 run from the same start ends elsewhere: the energy factor acts
+    phi1, _, _, _, _, _ = gpu_run(w, steps=steps, precision=precision)
+    assert np.abs(phi1.astype(np.float64) - ophi).max() > 1e-3 * g["h"]
+
+
+def test_p2_jobs_stay_out_of_batches():
+    from paper_2410_22205_amd import lsr
+    w = synth.workload("circle2d", n=32)
+    job = lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"], p=2.0), max_points=len(w["points"]))
+    batch = lsr.Batch(max_jobs=2, group_steps=4)
+    try:
+        job.load_cloud(w["points"])
+        job.init_phi(w["phi0"][0], w["phi0"][1])
+        with pytest.raises(RuntimeError):
+            batch.add(job, w["dt"], w["interp"])
+        with pytest.raises(RuntimeError):
+            lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"], p=1.5), max_points=10)
+    finally:
+        batch.close()
+        job.close()

@@ -47,8 +47,8 @@ PRECISIONS = ["fp32", "fp64"]
 def gpu_run(w, steps=None, d=None, step0=0, extra=None, precision="fp64"):
     lsr = _lsr()
     oprm = oracle_params(w, extra)
-    prm = {k: oprm[k] for k in ("gamma", "beta", "reinit_every", "reinit_iters", "reinit_dtau",
-                                "delta", "grad_C", "grad_alpha", "interface_floor")}
+    prm = {k: oprm[k] for k in ("p", "gamma", "beta", "reinit_every", "reinit_iters",
+                                "reinit_dtau", "delta", "grad_C", "grad_alpha", "interface_floor")}
     prm["precision"] = precision
     job = lsr.Job(w["grid"], prm, max_points=len(w["points"]))
     if d is None:
