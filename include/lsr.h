@@ -25,7 +25,8 @@
  *    lsr_create (a batch's on its own stream, with its second stream
  *    joined back into it within every call); only calls that return
  *    host-side values from the device (lsr_load_cloud's input check,
- *    lsr_extract with n_band, lsr_energy, lsr_counters, lsr_profile_read,
+ *    lsr_extract with n_band, lsr_energy, lsr_run_to_steady, lsr_counters,
+ *    lsr_profile_read,
  *    lsr_batch_tune) and the switches of the graph, stream and timing
  *    hooks synchronise that stream.
  *  - Nodal arrays are in C order: 2D index i*n[1] + j, 3D index
@@ -181,6 +182,25 @@ lsr_status lsr_reinit(lsr_job* job);
  * finite, > 0; R: 1..64 (ignored in 2D); else LSR_E_INVALID.  LSR_E_STATE
  * without phi or d, or for a job in a batch.  Synchronises the stream. */
 lsr_status lsr_energy(lsr_job* job, double p, int32_t R, double* out);
+
+/* Stopping test of eq. (deltaEn) after iteration n.  e (host): E_2(phi^i)
+ * for i = 0..n.  With k = min(n, LSR_ENERGY_WINDOW) and e_m the mean of the
+ * k values ending at m, returns 1 when |e_(n-1) - e_m| / e_n < tol (n >=
+ * min_steps) or when n >= max_steps, else 0; -1 for e NULL or n < 0.  Both
+ * means use the same k, so the one at n - 1 reaches back to phi^0 while
+ * n <= LSR_ENERGY_WINDOW; a zero mean stops.  Host only (no device work). */
+#define LSR_ENERGY_WINDOW 10
+int32_t lsr_energy_stop(const double* e, int32_t n, int32_t min_steps, int32_t max_steps,
+                        double tol);
+
+/* Steps the job one step at a time until lsr_energy_stop says stop (the
+ * paper: min_steps 10, max_steps 100, tol 1e-4), computing E_2 (R = 5) of
+ * phi^0 and after every step; synchronises the stream once per step.
+ * *n_done: steps taken; energies (host, may be NULL): room for
+ * max_steps + 1 values, receives E_2(phi^0..phi^n_done).  Errors as
+ * lsr_step and lsr_energy, LSR_E_INVALID for bad limits. */
+lsr_status lsr_run_to_steady(lsr_job* job, double dt, lsr_interp interp, int32_t min_steps,
+                             int32_t max_steps, double tol, double* energies, int32_t* n_done);
 
 /* Copy out the current phi (dev_phi: device, one value per node in the job's
  * precision) and the band

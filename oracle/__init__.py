@@ -274,3 +274,23 @@ def energy(phi, d, grid, p, R=5):
     assert f.shape == shape(grid) and dd.shape == shape(grid)
     s = _lib().orc_energy_sum(_ptr(f), _ptr(dd), ctypes.byref(_grid(grid)), float(p), int(R))
     return s ** (1.0 / p)
+
+
+def stop_rule(energies, n, min_steps=10, max_steps=100, tol=1e-4, window=10):
+    """The stopping test of eq. (deltaEn) after iteration n, from
+    energies[i] = E_2(phi^i), i = 0..n: with k = min(n, window) and
+    e_m = mean(E_2(phi^(m-k+1)), ..., E_2(phi^m)), stop when
+    |e_(n-1) - e_n| / e_n < tol, never before min_steps iterations and
+    always at max_steps (reading: both averages use the same k, so the one
+    at n - 1 reaches back to phi^0 while n <= window; a zero average
+    stops)."""
+    if n >= max_steps:
+        return True
+    if n < min_steps or n < 1:
+        return False
+    k = min(n, window)
+    cur = sum(energies[n - k + 1: n + 1]) / k
+    prev = sum(energies[n - k: n]) / k
+    if not cur > 0.0:
+        return True
+    return abs(prev - cur) / cur < tol

@@ -708,6 +708,41 @@ lsr_status lsr_energy(lsr_job* j, double p, int32_t R, double* out) {
   return LSR_OK;
 }
 
+int32_t lsr_energy_stop(const double* e, int32_t n, int32_t min_steps, int32_t max_steps,
+                        double tol) {
+  if (!e || n < 0) return -1;
+  if (n >= max_steps) return 1;
+  if (n < min_steps || n < 1) return 0;
+  const int32_t k = n < LSR_ENERGY_WINDOW ? n : LSR_ENERGY_WINDOW;
+  double cur = 0.0, prev = 0.0;
+  for (int32_t i = n - k + 1; i <= n; ++i) cur += e[i];
+  for (int32_t i = n - k; i <= n - 1; ++i) prev += e[i];
+  cur /= k;
+  prev /= k;
+  if (!(cur > 0.0)) return 1;
+  return fabs(prev - cur) / cur < tol ? 1 : 0;
+}
+
+lsr_status lsr_run_to_steady(lsr_job* j, double dt, lsr_interp interp, int32_t min_steps,
+                             int32_t max_steps, double tol, double* energies, int32_t* n_done) {
+  if (!j || !n_done) return fail(LSR_E_INVALID, "NULL argument");
+  if (min_steps < 0 || max_steps < 1 || min_steps > max_steps)
+    return fail(LSR_E_INVALID, "need 0 <= min_steps <= max_steps and max_steps >= 1");
+  if (!(tol >= 0.0) || !isfinite(tol)) return fail(LSR_E_INVALID, "tol must be finite and >= 0");
+  std::vector<double> e((size_t)max_steps + 1, 0.0);
+  lsr_status st = lsr_energy(j, 2.0, ENERGY_R, &e[0]);
+  int32_t n = 0;
+  while (st == LSR_OK && lsr_energy_stop(e.data(), n, min_steps, max_steps, tol) == 0) {
+    st = lsr_step(j, 1, dt, interp);
+    if (st != LSR_OK) break;
+    n += 1;
+    st = lsr_energy(j, 2.0, ENERGY_R, &e[(size_t)n]);
+  }
+  *n_done = n;
+  if (energies) memcpy(energies, e.data(), sizeof(double) * ((size_t)n + 1));
+  return st;
+}
+
 lsr_status lsr_extract(lsr_job* j, void* dev_phi, uint8_t* dev_band, int64_t* n_band,
                        int64_t* step_index) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");

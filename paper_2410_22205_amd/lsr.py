@@ -26,7 +26,8 @@ COUNTER_NAMES = ["node_updates", "fallbacks", "frame0", "reinits", "gbar", "inte
 EXPORTED = [
     "lsr_params_default", "lsr_workspace_bytes", "lsr_create", "lsr_load_cloud",
     "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
-    "lsr_extract", "lsr_energy", "lsr_counters", "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
+    "lsr_extract", "lsr_energy", "lsr_energy_stop", "lsr_run_to_steady", "lsr_counters",
+    "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
     "lsr_batch_add", "lsr_batch_remove", "lsr_batch_step", "lsr_batch_set_launch",
     "lsr_batch_tune", "lsr_batch_destroy", "lsr_batch_set_graphs", "lsr_batch_set_streams",
     "lsr_set_launch",
@@ -80,6 +81,11 @@ def load():
             "lsr_reinit": [_P],
             "lsr_extract": [_P, _P, _P, I64P, I64P],
             "lsr_energy": [_P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+            "lsr_energy_stop": [ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_double],
+            "lsr_run_to_steady": [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int32)],
             "lsr_counters": [_P, I64P, ctypes.c_int32],
             "lsr_destroy": [_P],
             "lsr_batch_workspace_bytes": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -192,6 +198,19 @@ def lsr_energy(job, p, R=5):
     out = ctypes.c_double(0.0)
     _check(load().lsr_energy(job, float(p), int(R), ctypes.byref(out)))
     return out.value
+
+
+def lsr_energy_stop(energies, n, min_steps=10, max_steps=100, tol=1e-4):
+    e = (ctypes.c_double * max(len(energies), 1))(*energies)
+    return load().lsr_energy_stop(e, int(n), int(min_steps), int(max_steps), float(tol))
+
+
+def lsr_run_to_steady(job, dt, interp, min_steps=10, max_steps=100, tol=1e-4):
+    e = (ctypes.c_double * (max_steps + 1))()
+    n = ctypes.c_int32(0)
+    _check(load().lsr_run_to_steady(job, float(dt), int(interp), int(min_steps), int(max_steps),
+                                    float(tol), e, ctypes.byref(n)))
+    return n.value, list(e[: n.value + 1])
 
 
 def lsr_counters(job):
@@ -362,6 +381,12 @@ class Job:
         phi, band, nb, si = self.extract_device()
         self.stream.synchronize()
         return phi.cpu().numpy(), band.cpu().numpy(), nb, si
+
+    def run_to_steady(self, dt, interp, min_steps=10, max_steps=100, tol=1e-4):
+        """Steps until the energy test of eq. (deltaEn) stops the run; returns
+        (steps taken, [E_2(phi^0), ..., E_2(phi^n)])."""
+        code = interp_code(interp) if isinstance(interp, str) else interp
+        return lsr_run_to_steady(self.handle, dt, code, min_steps, max_steps, tol)
 
     def energy(self, p, R=5):
         """E_p of the current phi (Section 3.5); synchronises the stream."""

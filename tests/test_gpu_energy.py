@@ -151,3 +151,23 @@ def test_p2_jobs_stay_out_of_batches():
     finally:
         batch.close()
         job.close()
+
+
+@pytest.mark.parametrize("p", [1.0, 2.0])
+def test_run_to_steady_follows_the_stopping_test(p):
+    """lsr_run_to_steady stops where the oracle's test of eq. (deltaEn) does on
+    the energies it reports, and the last of them is E_2 of the final phi."""
+    from paper_2410_22205_amd import lsr
+    w = synth.workload("circle2d", n=64)
+    job = lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"], reinit_every=1, p=p,
+                                  precision="fp64"), max_points=len(w["points"]))
+    try:
+        job.load_cloud(w["points"])
+        job.init_phi(w["phi0"][0], w["phi0"][1])
+        n, e = job.run_to_steady(w["dt"], w["interp"])
+        last = job.energy(2.0)
+    finally:
+        job.close()
+    assert 10 <= n <= 100 and len(e) == n + 1
+    assert [oracle.stop_rule(e, m) for m in range(n + 1)] == [False] * n + [True]
+    assert last == e[-1]

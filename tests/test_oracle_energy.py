@@ -158,3 +158,43 @@ def test_p2_radial_closed_form():
     assert right < 0.1 * np.abs(got - closed(r / E, False)).max()   # 1/p dropped
     assert right < 0.1 * np.abs(got - closed(1.0, True)).max()      # (d/E) dropped
     assert right < 0.1 * np.abs(got - closed(E / r, True)).max()    # inverted ratio
+
+
+# ------------------------------------------------ stopping test, eq. (deltaEn)
+
+def test_stop_rule_constant_energy_stops_at_the_minimum():
+    e = [0.3] * 200
+    stops = [n for n in range(200) if oracle.stop_rule(e, n)]
+    assert stops[0] == 10
+
+
+def test_stop_rule_linear_decrease_closed_form():
+    """E_2(phi^i) = 1 - a i: consecutive k-means differ by a exactly, so
+    Delta_n = a / mean_n, with mean_n = 1 - a (n - (k - 1) / 2)."""
+    a = 2e-5
+    e = [1.0 - a * i for i in range(120)]
+    for n in (10, 30, 60):
+        k = min(n, 10)
+        mean_n = 1.0 - a * (n - (k - 1) / 2.0)
+        delta = a / mean_n
+        assert oracle.stop_rule(e, n, tol=delta * (1 + 1e-6))
+        assert not oracle.stop_rule(e, n, tol=delta * (1 - 1e-6))
+
+
+def test_stop_rule_limits():
+    e = list(np.linspace(1.0, 0.5, 150))  # Delta about 3e-3 per step: never below 1e-4
+    assert not any(oracle.stop_rule(e, n) for n in range(100))
+    assert oracle.stop_rule(e, 100)
+    assert not oracle.stop_rule([0.2] * 12, 5)  # below the minimum
+
+
+def test_stop_rule_of_the_library_matches_the_oracle():
+    """The C ABI's host-side rule (no device work) against the oracle's."""
+    from paper_2410_22205_amd import lsr
+    rng = np.random.default_rng(7)
+    for trial in range(200):
+        n_max = int(rng.integers(1, 130))
+        e = list(0.1 + np.cumsum(rng.normal(0.0, 1e-5, n_max + 1)) * rng.choice([0.0, 1.0, 10.0]))
+        tol = float(rng.choice([1e-4, 1e-5, 1e-3]))
+        for n in range(n_max + 1):
+            assert lsr.lsr_energy_stop(e, n, 10, 100, tol) == int(oracle.stop_rule(e, n, tol=tol))
