@@ -76,6 +76,38 @@ def read_traffic(workload, precision):
         return None
 
 
+def run_p2(w, precision, n_jobs, pts):
+    """Whole jobs of the workload at p = 2 (one warm-up, n_jobs timed)."""
+    import torch
+
+    from paper_2410_22205_amd import lsr
+    prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"], p=2.0,
+               precision=precision)
+    job = lsr.Job(w["grid"], prm, max_points=len(w["points"]), stream=torch.cuda.Stream())
+    kind = {"sphere": lsr.LSR_PHI_SPHERE, "torus": lsr.LSR_PHI_TORUS}[w["phi0"][0]]
+    interp = lsr.interp_code(w["interp"])
+    torch.cuda.synchronize()
+
+    def one():
+        lsr.lsr_load_cloud(job.handle, pts.data_ptr(), pts.shape[0])
+        lsr.lsr_init_phi(job.handle, None, kind, list(w["phi0"][1]), 0)
+        lsr.lsr_step(job.handle, w["steps"], w["dt"], interp)
+
+    one()
+    job.stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_jobs):
+        one()
+    job.stream.synchronize()
+    wall = time.perf_counter() - t0
+    # the counters restart with every job, and the jobs are identical
+    upd = n_jobs * lsr.lsr_counters(job.handle)["node_updates"]
+    e2 = job.energy(2.0)
+    job.close()
+    return {"jobs": n_jobs, "ms_per_job": 1e3 * wall / n_jobs, "node_updates_per_s": upd / wall,
+            "E_2_final": e2}
+
+
 def cpu_baseline(w, min_seconds=10.0):
     """The oracle on the same workload: whole jobs (distance field, phi0, all
     steps), repeated until at least min_seconds have passed."""
@@ -231,6 +263,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed jobs")
+    ap.add_argument("--p2-jobs", type=int, default=2,
+                    help="timed jobs of the same workload at p = 2 (context; 0 = skip)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus3d")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
@@ -368,6 +402,10 @@ def main():
     out["energy"] = {"p": 2, "R": 5, "E_p": e2,
                      "wall_us_per_call": round((time.perf_counter() - t0) / 10 * 1e6, 1)}
     job.close()
+    # context, not the headline: the same jobs at p = 2, where every step
+    # first computes E_2 of the current phi on the device
+    if args.p2_jobs:
+        out["p2"] = run_p2(w, args.precision, args.p2_jobs, pts)
     if args.batch_jobs:
         out["batched"] = run_batched(args.batch_jobs, args.batch_steps, args.precision,
                                      graphs=not args.no_graphs,
