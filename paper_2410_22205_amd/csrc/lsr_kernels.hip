@@ -1697,35 +1697,49 @@ __global__ __launch_bounds__(256) void k_energy(DevGrid g, const T* __restrict__
   const uint64_t ncell = (uint64_t)m0 * m1 * m2;
   const double hs = g.hd / R;
   const double lim = 0.5 * sqrt(3.0) * hs;
-  const int R3 = R * R * R;
-  double s = 0.0;
-  for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < ncell;
-       base += (uint64_t)gridDim.x * 256u) {
+  const int R2 = R * R;
+  // offset of vertex q from the cell's lower corner (3D: q = 4a + 2b + c'
+  // for (i+a, j+b, k+c'); 2D: edge order)
+  auto voff = [&](int q) -> uint32_t {
+    if (DIM == 3)
+      return (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 + (uint32_t)(q & 1);
+    return (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
+  };
+  // the cell of this thread in the chunk at `base`, and its vertex values
+  struct Cell {
+    bool ok;
+    int i, j;
+    uint32_t node;
+    T f[NV];
+  };
+  auto fetch = [&](uint64_t base) {
+    Cell x;
     const uint64_t c = base + (uint64_t)tid;
-    bool front = false;
-    int i = 0, j = 0, k = 0;
-    double f[NV];
-    uint32_t node = 0;
-    if (c < ncell) {
-      k = (int)(c % m2);
+    x.ok = c < ncell;
+    x.i = x.j = 0;
+    x.node = 0;
+    if (x.ok) {
+      const int k = (int)(c % m2);
       const uint64_t r = c / m2;
-      j = (int)(r % m1);
-      i = (int)(r / m1);
-      node = (uint32_t)i * g.s0 + (uint32_t)j * g.s1 + (uint32_t)k;
-      int n_in = 0;
+      x.j = (int)(r % m1);
+      x.i = (int)(r / m1);
+      x.node = (uint32_t)x.i * g.s0 + (uint32_t)x.j * g.s1 + (uint32_t)k;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        // 3D: q = 4a + 2b + c' for vertex (i+a, j+b, k+c'); 2D: edge order
-        uint32_t off;
-        if (DIM == 3)
-          off = (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 + (uint32_t)(q & 1);
-        else
-          off = (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
-        f[q] = (double)phi[node + off];
-        n_in += f[q] < 0.0 ? 1 : 0;
-      }
-      front = n_in != 0 && n_in != NV;
+      for (int q = 0; q < NV; ++q) x.f[q] = phi[x.node + voff(q)];
     }
+    return x;
+  };
+  double s = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  uint64_t base = (uint64_t)blockIdx.x * 256u;
+  Cell cur = fetch(base);
+  for (; base < ncell; base += stride) {
+    // the next chunk's values are in flight while this one is processed
+    const Cell nxt = fetch(base + stride);
+    int n_in = 0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) n_in += (double)cur.f[q] < 0.0 ? 1 : 0;
+    const bool front = cur.ok && n_in != 0 && n_in != NV;
     // ordered compaction of the chunk's front cells
     const uint64_t m = __ballot(front);
     if (lane_id() == 0) wcnt[wv] = (int)__popcll(m);
@@ -1737,40 +1751,37 @@ __global__ __launch_bounds__(256) void k_energy(DevGrid g, const T* __restrict__
       const int pos = off + (int)lanes_below(m);
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        uint32_t o;
-        if (DIM == 3)
-          o = (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 + (uint32_t)(q & 1);
-        else
-          o = (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
-        fv[pos][q] = f[q];
-        ev[pos][q] = d[node + o];
+        fv[pos][q] = (double)cur.f[q];
+        ev[pos][q] = d[cur.node + voff(q)];
       }
-      cij[pos][0] = i;
-      cij[pos][1] = j;
+      cij[pos][0] = cur.i;
+      cij[pos][1] = cur.j;
     }
     __syncthreads();
     if (DIM == 3) {
-      for (int it = tid; it < nfront * R3; it += 256) {
-        const int cell = it / R3, sub = it - cell * R3;
-        const int u = sub / (R * R), v = (sub / R) % R, w = sub % R;
-        const double tx = (u + 0.5) / R, ty = (v + 0.5) / R, tz = (w + 0.5) / R;
+      // one item per (cell, u, v): the z line of R subcells at (u, v)
+      for (int it = tid; it < nfront * R2; it += 256) {
+        const int cell = it / R2, uv = it - cell * R2;
+        const int u = uv / R, v = uv - u * R;
+        const double tx = (u + 0.5) / R, ty = (v + 0.5) / R;
         // trilinear: along x, then y, then z; vertex (a, b, c') at 4a + 2b + c'
         const double* F = fv[cell];
         const double* E = ev[cell];
-        const double fy00 = lerp_d(F[0], F[4], tx), fy01 = lerp_d(F[1], F[5], tx);
-        const double fy10 = lerp_d(F[2], F[6], tx), fy11 = lerp_d(F[3], F[7], tx);
-        const double ey00 = lerp_d(E[0], E[4], tx), ey01 = lerp_d(E[1], E[5], tx);
-        const double ey10 = lerp_d(E[2], E[6], tx), ey11 = lerp_d(E[3], E[7], tx);
-        const double fz0 = lerp_d(fy00, fy10, ty), fz1 = lerp_d(fy01, fy11, ty);
-        const double ez0 = lerp_d(ey00, ey10, ty), ez1 = lerp_d(ey01, ey11, ty);
-        const double fc = lerp_d(fz0, fz1, tz);
-        if (fabs(fc) < lim) s += pow_abs(lerp_d(ez0, ez1, tz), p) * hs * hs;
+        const double fz0 = lerp_d(lerp_d(F[0], F[4], tx), lerp_d(F[2], F[6], tx), ty);
+        const double fz1 = lerp_d(lerp_d(F[1], F[5], tx), lerp_d(F[3], F[7], tx), ty);
+        const double ez0 = lerp_d(lerp_d(E[0], E[4], tx), lerp_d(E[2], E[6], tx), ty);
+        const double ez1 = lerp_d(lerp_d(E[1], E[5], tx), lerp_d(E[3], E[7], tx), ty);
+        for (int w = 0; w < R; ++w) {
+          const double tz = (w + 0.5) / R;
+          if (fabs(lerp_d(fz0, fz1, tz)) < lim) s += pow_abs(lerp_d(ez0, ez1, tz), p) * hs * hs;
+        }
       }
     } else {
       for (int it = tid; it < nfront; it += 256)
         s += energy_cell_2d(g, fv[it], ev[it], cij[it][0], cij[it][1], p);
     }
     __syncthreads();
+    cur = nxt;
   }
   s = wave_sum(s);
   if (lane_id() == 0) red[wv] = s;
