@@ -234,8 +234,8 @@ lsr_status lsr_destroy(lsr_job* job);
  * lsr_batch_add: the job joins at the next batch step, after the work
  * already queued on its own stream (no host synchronisation); a job in a
  * batch refuses lsr_step, lsr_reinit, lsr_init_phi, lsr_load_cloud,
- * lsr_set_distance, lsr_set_launch and lsr_destroy.  Only jobs with p = 1
- * join a batch (else LSR_E_UNSUPPORTED).
+ * lsr_set_distance, lsr_set_launch and lsr_destroy.  A p = 2 member gets
+ * its own energy launch before each batched step.
  * lsr_batch_remove: the job leaves at the current step boundary; its own
  * stream is ordered after the batch's queued work.
  * lsr_batch_step: n_steps steps of every member (uploads one table per group).

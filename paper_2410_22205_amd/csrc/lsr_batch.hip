@@ -22,11 +22,13 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Launch {
-  int kind;  // 0 step, 1 Gbar scan, 2 fix, 3 iteration, 4 final
+  int kind;  // 0 step, 1 Gbar scan, 2 fix, 3 iteration, 4 final, 5 energy of one p = 2 job
   size_t off;
   int n;
   int interp;    // kind 0 only
   int group;     // cache group (see cache_groups)
+  lsr_job* job = nullptr;  // kind 5: the job, and the phi buffer its next step reads
+  int phi = 0;
 };
 
 }  // namespace
@@ -115,6 +117,17 @@ struct Builder {
 template <typename T>
 lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
   for (int s = 0; s < steps; ++s) {
+    // p = 2 members: E_2 of the phi this step reads, left on the device for
+    // the step kernel (Algorithm 1, step 2)
+    for (int q = q0; q < q1; ++q) {
+      lsr_job* j = b->jobs[q];
+      if (j->prm.p != 1.0) {
+        Launch L{5, 0, 1, 0, B.group};
+        L.job = j;
+        L.phi = j->cur;
+        B.launches.push_back(L);
+      }
+    }
     // one step table and launch per interpolator
     for (int itp = 0; itp < 2; ++itp) {
       int m = 0;
@@ -201,6 +214,12 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
       case 4:
         e = launch_reinit_final_batch<T>((const FinArgs<T>*)(dev + L.off), L.n, b->blocks, s);
         break;
+      case 5: {
+        lsr_job* j = L.job;
+        e = launch_energy<T>(b->dim, j->dg, (const T*)j->phi[L.phi], j->d64, j->prm.p, ENERGY_R,
+                             j->energy_buf, j->energy_buf + ENERGY_BLOCKS, s);
+        break;
+      }
     }
   }
   for (int q = 1; q < ns; ++q) {
@@ -226,6 +245,10 @@ std::vector<int64_t> group_key(const lsr_batch* b, const Builder<T>& B) {
     k.push_back(L.n);
     k.push_back(L.interp);
     k.push_back(L.group);
+    if (L.kind == 5) {
+      k.push_back((int64_t)(intptr_t)L.job);
+      k.push_back(L.phi);
+    }
   }
   return k;
 }
@@ -354,6 +377,11 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
   hipStream_t s = b->stream;
   char* dev = b->ws + b->table_off;
   LSR_HIP(hipMemcpyAsync(dev, b->host, top, hipMemcpyHostToDevice, s));
+  // p = 2 members: the energy their next step will read
+  for (lsr_job* j : b->jobs)
+    if (j->prm.p != 1.0)
+      LSR_HIP(launch_energy<T>(b->dim, j->dg, (const T*)j->phi[j->cur], j->d64, j->prm.p, ENERGY_R,
+                               j->energy_buf, j->energy_buf + ENERGY_BLOCKS, s));
   hipEvent_t e0, e1;
   LSR_HIP(hipEventCreate(&e0));
   LSR_HIP(hipEventCreate(&e1));
@@ -516,7 +544,6 @@ lsr_status lsr_batch_add(lsr_batch* b, lsr_job* j, double dt, lsr_interp interp)
   if (j->in_batch) return fail(LSR_E_STATE, "the job is already in a batch");
   if ((int)b->jobs.size() >= b->max_jobs) return fail(LSR_E_NOMEM, "the batch is full");
   if (j->prm.reinit_iters > b->max_iters) return fail(LSR_E_NOMEM, "reinit_iters above the batch's maximum");
-  if (j->prm.p != 1.0) return fail(LSR_E_UNSUPPORTED, "batches run p = 1 jobs");
   if (b->dim && (j->grid.dim != b->dim || j->fp64 != b->fp64))
     return fail(LSR_E_UNSUPPORTED, "a batch needs one dimension and one precision");
   if (!(dt > 0.0) || !isfinite(dt)) return fail(LSR_E_INVALID, "dt must be > 0");

@@ -31,7 +31,7 @@ def _jobs(precision, n=5, seed=4000, small=True):
 def _make(lsr, w, step0=0, lanes=None):
     h = w["grid"]["h"]
     prm = dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
-               precision=w["precision"])
+               precision=w["precision"], p=w.get("p", 1.0))
     job = lsr.Job(w["grid"], prm, max_points=len(w["points"]))
     if lanes:
         job.set_launch(lanes)
@@ -67,6 +67,31 @@ def test_batch_equals_solo_bitwise(precision):
         np.testing.assert_array_equal(band, band0)
         assert nb == nb0 and si == si0 == steps
         assert j.counters() == cnt0
+    batch.close()
+    for j in jobs:
+        j.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_with_p2_members_equals_solo_bitwise(precision):
+    """p = 2 members get their own energy launch before each batched step;
+    mixed with p = 1 members they still match their solo runs bit for bit."""
+    lsr = _lsr()
+    ws = _jobs(precision, n=4, seed=4200)
+    for k, w in enumerate(ws):
+        w["p"] = 2.0 if k % 2 == 0 else 1.0
+    steps = 13  # crosses a reinitialisation
+    solo = [_solo(w, steps) for w in ws]
+    batch = lsr.Batch(max_jobs=len(ws), group_steps=5)
+    jobs = [_make(lsr, w) for w in ws]
+    for w, j in zip(ws, jobs):
+        batch.add(j, w["dt"], w["interp"])
+    batch.step(steps)
+    for (phi0, band0, nb0, si0, cnt0), j in zip(solo, jobs):
+        phi, band, nb, si = j.extract()
+        np.testing.assert_array_equal(phi, phi0)
+        np.testing.assert_array_equal(band, band0)
+        assert nb == nb0 and si == si0 == steps
     batch.close()
     for j in jobs:
         j.close()

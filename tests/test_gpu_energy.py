@@ -136,21 +136,11 @@ def test_p2_run_matches_oracle(name, n, steps, precision):
     assert np.abs(phi1.astype(np.float64) - ophi).max() > 1e-3 * g["h"]
 
 
-def test_p2_jobs_stay_out_of_batches():
+def test_p_other_than_1_or_2_is_refused():
     from paper_2410_22205_amd import lsr
     w = synth.workload("circle2d", n=32)
-    job = lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"], p=2.0), max_points=len(w["points"]))
-    batch = lsr.Batch(max_jobs=2, group_steps=4)
-    try:
-        job.load_cloud(w["points"])
-        job.init_phi(w["phi0"][0], w["phi0"][1])
-        with pytest.raises(RuntimeError):
-            batch.add(job, w["dt"], w["interp"])
-        with pytest.raises(RuntimeError):
-            lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"], p=1.5), max_points=10)
-    finally:
-        batch.close()
-        job.close()
+    with pytest.raises(RuntimeError):
+        lsr.Job(w["grid"], dict(gamma=w["gamma"], beta=w["beta"], p=1.5), max_points=10)
 
 
 @pytest.mark.parametrize("p", [1.0, 2.0])
