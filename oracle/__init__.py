@@ -294,3 +294,16 @@ def stop_rule(energies, n, min_steps=10, max_steps=100, tol=1e-4, window=10):
     if not cur > 0.0:
         return True
     return abs(prev - cur) / cur < tol
+
+
+def cloud_spacing(points, sample):
+    """h_S of Section 4 (the text after eq. dxdt): the mean over the sampled
+    points (indices into points) of the distance to their nearest neighbour
+    in the cloud, i.e. the second smallest distance to the cloud counting the
+    point itself (an exact duplicate is a neighbour at distance 0).  Uses
+    SciPy's exact k-d tree query for the two nearest points."""
+    from scipy.spatial import cKDTree
+    pts = np.asarray(points, dtype=np.float64)
+    tree = cKDTree(pts)
+    dd, _ = tree.query(pts[np.asarray(sample, dtype=np.int64)], k=2)
+    return float(np.mean(dd[:, 1]))
