@@ -25,7 +25,8 @@
  *    lsr_create (a batch's on its own stream, with its second stream
  *    joined back into it within every call); only calls that return
  *    host-side values from the device (lsr_load_cloud's input check,
- *    lsr_extract with n_band, lsr_energy, lsr_run_to_steady, lsr_counters,
+ *    lsr_extract with n_band, lsr_energy, lsr_run_to_steady,
+ *    lsr_cloud_spacing, lsr_counters,
  *    lsr_profile_read,
  *    lsr_batch_tune) and the switches of the graph, stream and timing
  *    hooks synchronise that stream.
@@ -182,6 +183,18 @@ lsr_status lsr_reinit(lsr_job* job);
  * finite, > 0; R: 1..64 (ignored in 2D); else LSR_E_INVALID.  LSR_E_STATE
  * without phi or d, or for a job in a batch.  Synchronises the stream. */
 lsr_status lsr_energy(lsr_job* job, double p, int32_t R, double* out);
+
+/* Cloud resolution h_S (Section 4, the text after eq. dxdt): the mean over
+ * the sampled points of the distance to their nearest neighbour in the
+ * cloud loaded by lsr_load_cloud (the second smallest distance counting the
+ * point itself; an exact duplicate is a neighbour at distance 0).
+ * dev_sample: device, n_sample indices into the cloud as it was given (the
+ * paper draws a random 10 %; the caller draws them), 1 <= n_sample <=
+ * max_points.  *out (host) receives h_S.  LSR_E_STATE without a loaded
+ * cloud of at least two points or for a job in a batch; LSR_E_INVALID for
+ * an index outside the cloud.  Synchronises the stream. */
+lsr_status lsr_cloud_spacing(lsr_job* job, const int64_t* dev_sample, int64_t n_sample,
+                             double* out);
 
 /* Stopping test of eq. (deltaEn) after iteration n.  e (host): E_2(phi^i)
  * for i = 0..n.  With k = min(n, LSR_ENERGY_WINDOW) and e_m the mean of the

@@ -103,6 +103,7 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.sup = take(8 * (size_t)L.max_sup);
   L.sgeo = take(8 * (size_t)GEO * (size_t)L.max_sup);
   L.energy = take(8 * ((size_t)ENERGY_BLOCKS + 1));
+  L.nn = take(8 * (P + 1));  // nearest-neighbour distances of a sample, and their mean
   L.total = off;
   return L;
 }
@@ -500,6 +501,8 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->sgeo = (double*)(w + L.sgeo);
   j->max_sup = L.max_sup;
   j->energy_buf = (double*)(w + L.energy);
+  j->nn = (double*)(w + L.nn);
+  j->n_cloud = 0;
   j->ncu = ncu > 0 ? ncu : 256;
   j->lanes = 1;
   j->blocks_per_cu = 8;
@@ -591,6 +594,8 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
     da.mu2 = 1e-12 * diag * diag;
   }
   da.d64 = j->d64;
+  j->bg_load = bg;
+  j->n_cloud = n;
   const int BS = dim == 3 ? 8 : 16;
   unsigned bricks = (unsigned)(((j->dg.n0 + BS - 1) / BS) * ((j->dg.n1 + BS - 1) / BS) *
                                (dim == 3 ? (j->dg.n2 + BS - 1) / BS : 1));
@@ -606,6 +611,7 @@ lsr_status lsr_set_distance(lsr_job* j, const double* dev_d) {
   if (!dev_d) return fail(LSR_E_INVALID, "distance is NULL");
   LSR_HIP(hipMemcpyAsync(j->d64, dev_d, sizeof(double) * j->dg.N, hipMemcpyDeviceToDevice,
                          j->stream));
+  j->n_cloud = 0;  // a given field, no cloud
   LSR_HIP(dpack(j));
   j->has_d = true;
   return LSR_OK;
@@ -704,6 +710,29 @@ lsr_status lsr_energy(lsr_job* j, double p, int32_t R, double* out) {
   double v = 0.0;
   LSR_HIP(hipMemcpyAsync(&v, dout, sizeof(double), hipMemcpyDeviceToHost, s));
   LSR_HIP(hipStreamSynchronize(s));
+  *out = v;
+  return LSR_OK;
+}
+
+lsr_status lsr_cloud_spacing(lsr_job* j, const int64_t* dev_sample, int64_t n_sample,
+                             double* out) {
+  if (!j || !dev_sample || !out) return fail(LSR_E_INVALID, "NULL argument");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
+  if (j->n_cloud < 2) return fail(LSR_E_STATE, "needs a cloud of two or more points (lsr_load_cloud)");
+  if (n_sample < 1 || n_sample > j->max_points)
+    return fail(LSR_E_INVALID, "n_sample must be in 1..max_points");
+  hipStream_t s = j->stream;
+  int32_t* flag = j->cnt + 11;
+  LSR_HIP(launch_fill_u32((uint32_t*)flag, 0u, 1, s));
+  LSR_HIP(launch_cloud_spacing(j->grid.dim, j->bg_load, j->pts, j->bin_start, j->pts_raw,
+                               j->n_cloud, dev_sample, n_sample, j->nn, flag,
+                               j->nn + j->max_points, s));
+  double v = 0.0;
+  int32_t bad = 0;
+  LSR_HIP(hipMemcpyAsync(&v, j->nn + j->max_points, sizeof(double), hipMemcpyDeviceToHost, s));
+  LSR_HIP(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LSR_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(LSR_E_INVALID, "a sample index lies outside the cloud");
   *out = v;
   return LSR_OK;
 }

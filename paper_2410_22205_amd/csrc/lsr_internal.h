@@ -212,6 +212,14 @@ hipError_t launch_super_geo(int dim, const double* pts, const int32_t* start,
                             const uint32_t* occ, const int2* sup, const int32_t* sup_cnt,
                             double* sgeo, int64_t max_sup, hipStream_t s);
 hipError_t launch_distance(int dim, const DistArgs& a, unsigned bricks, hipStream_t s);
+// Cloud resolution h_S: nearest-neighbour distances of the ns sampled points
+// (indices into raw, the cloud in its given order) into nn[0 .. ns-1], their
+// mean into out[0]; *flag |= 1 for an index outside [0, n_pts).  sorted and
+// start: the cloud sorted by the bins of bg (lsr_cloud.hip).
+hipError_t launch_cloud_spacing(int dim, const BinGeom& bg, const double* sorted,
+                                const int32_t* start, const double* raw, int64_t n_pts,
+                                const int64_t* sample, int64_t ns, double* nn, int32_t* flag,
+                                double* out, hipStream_t s);
 // Energy functional E_p of Section 3.5 (R subcells per axis in 3D) of the
 // nodal phi and d: per-block sums into partial[ENERGY_BLOCKS], then
 // out[0] = E_p.

@@ -31,6 +31,7 @@ struct Layout {
   int64_t nbricks;
   size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo, sup, sgeo;
   size_t energy;  // energy partial sums and result
+  size_t nn;      // nearest-neighbour distances of a cloud sample
   int64_t max_occ, max_sup;
   size_t total;
   int64_t nbins;  // bin ids at the finer width, super-bin padding included
@@ -57,8 +58,8 @@ struct lsr_job {
   uint8_t* mflags;
   int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins,
                  // [6] bins a cloud's points occupy (density check), [7] occupied
-                 // super-bins, [8..10] brick-count
-                 // ring (staged 3D step)
+                 // super-bins, [8..10] brick-count ring (staged 3D step), [11]
+                 // sample-index flag of lsr_cloud_spacing
   unsigned long long* stats;
   double* pts_raw;
   double* pts;
@@ -74,6 +75,9 @@ struct lsr_job {
   double* sgeo;     // super-bin frames
   int64_t max_sup;  // room for super-bins
   double* energy_buf;  // ENERGY_BLOCKS partial sums, then E_p
+  double* nn;          // max_points nearest-neighbour distances, then their mean
+  int64_t n_cloud;     // points of the loaded cloud (0: none, or a given d)
+  lsr::BinGeom bg_load;  // the bins the loaded cloud is sorted by
   uint32_t* blist[2];
   uint32_t* bstamp;
   int cur_blist;       // brick list buffer holding the current brick list

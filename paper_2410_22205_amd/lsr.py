@@ -26,7 +26,8 @@ COUNTER_NAMES = ["node_updates", "fallbacks", "frame0", "reinits", "gbar", "inte
 EXPORTED = [
     "lsr_params_default", "lsr_workspace_bytes", "lsr_create", "lsr_load_cloud",
     "lsr_set_distance", "lsr_get_distance", "lsr_init_phi", "lsr_step", "lsr_reinit",
-    "lsr_extract", "lsr_energy", "lsr_energy_stop", "lsr_run_to_steady", "lsr_counters",
+    "lsr_extract", "lsr_energy", "lsr_energy_stop", "lsr_run_to_steady", "lsr_cloud_spacing",
+    "lsr_counters",
     "lsr_destroy", "lsr_batch_workspace_bytes", "lsr_batch_create",
     "lsr_batch_add", "lsr_batch_remove", "lsr_batch_step", "lsr_batch_set_launch",
     "lsr_batch_tune", "lsr_batch_destroy", "lsr_batch_set_graphs", "lsr_batch_set_streams",
@@ -81,6 +82,7 @@ def load():
             "lsr_reinit": [_P],
             "lsr_extract": [_P, _P, _P, I64P, I64P],
             "lsr_energy": [_P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+            "lsr_cloud_spacing": [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)],
             "lsr_energy_stop": [ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_int32, ctypes.c_double],
             "lsr_run_to_steady": [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
@@ -197,6 +199,12 @@ def lsr_extract(job, phi_ptr, band_ptr, want_count=True):
 def lsr_energy(job, p, R=5):
     out = ctypes.c_double(0.0)
     _check(load().lsr_energy(job, float(p), int(R), ctypes.byref(out)))
+    return out.value
+
+
+def lsr_cloud_spacing(job, sample_ptr, n_sample):
+    out = ctypes.c_double(0.0)
+    _check(load().lsr_cloud_spacing(job, _P(sample_ptr), int(n_sample), ctypes.byref(out)))
     return out.value
 
 
@@ -387,6 +395,13 @@ class Job:
         (steps taken, [E_2(phi^0), ..., E_2(phi^n)])."""
         code = interp_code(interp) if isinstance(interp, str) else interp
         return lsr_run_to_steady(self.handle, dt, code, min_steps, max_steps, tol)
+
+    def cloud_spacing(self, sample):
+        """h_S of the loaded cloud over the sampled point indices (Section 4);
+        synchronises the stream."""
+        t = self._dev(np.asarray(sample, dtype=np.int64), self.torch.int64)
+        self.torch.cuda.current_stream().synchronize()  # the copy, before the job's stream reads it
+        return lsr_cloud_spacing(self.handle, t.data_ptr(), t.numel())
 
     def energy(self, p, R=5):
         """E_p of the current phi (Section 3.5); synchronises the stream."""
