@@ -401,6 +401,16 @@ def main():
         job.energy(2.0)
     out["energy"] = {"p": 2, "R": 5, "E_p": e2,
                      "wall_us_per_call": round((time.perf_counter() - t0) / 10 * 1e6, 1)}
+    # the cloud resolution h_S over a seeded 10 % sample (Section 4), also
+    # outside the timed region: preprocessing, not part of the loop
+    sample = np.random.default_rng(11).choice(len(w["points"]), size=len(w["points"]) // 10,
+                                               replace=False)
+    h_s = job.cloud_spacing(sample)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        job.cloud_spacing(sample)
+    out["cloud_spacing"] = {"h_S": h_s, "sample": int(len(sample)),
+                            "wall_us_per_call": round((time.perf_counter() - t0) / 10 * 1e6, 1)}
     job.close()
     # context, not the headline: the same jobs at p = 2, where every step
     # first computes E_2 of the current phi on the device
