@@ -538,6 +538,7 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   if (n > j->max_points) return fail(LSR_E_NOMEM, "cloud larger than the workspace allows");
   hipStream_t s = j->stream;
   const int dim = j->grid.dim;
+  j->n_cloud = 0;  // set again once the new cloud is binned and sorted
   LSR_HIP(hipMemcpyAsync(j->pts_raw, dev_xyz, sizeof(double) * dim * (size_t)n,
                          hipMemcpyDeviceToDevice, s));
   // bin at the standard width; validate the points and count occupied bins

@@ -66,5 +66,11 @@ def test_duplicates_and_arguments():
         with pytest.raises(RuntimeError):
             job.cloud_spacing([0, len(pts)])  # an index outside the cloud
         assert job.cloud_spacing([1, 2, 3]) > 0  # usable after the refusal
+        bad = pts.copy()
+        bad[0, 0] = 5.0  # outside the grid's box: the load fails ...
+        with pytest.raises(RuntimeError):
+            job.load_cloud(bad)
+        with pytest.raises(RuntimeError):
+            job.cloud_spacing([1, 2, 3])  # ... and leaves no cloud to sample
     finally:
         job.close()
