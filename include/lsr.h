@@ -198,7 +198,7 @@ lsr_status lsr_cloud_spacing(lsr_job* job, const int64_t* dev_sample, int64_t n_
 
 /* Stopping test of eq. (deltaEn) after iteration n.  e (host): E_2(phi^i)
  * for i = 0..n.  With k = min(n, LSR_ENERGY_WINDOW) and e_m the mean of the
- * k values ending at m, returns 1 when |e_(n-1) - e_m| / e_n < tol (n >=
+ * k values ending at m, returns 1 when |e_(n-1) - e_n| / e_n < tol (n >=
  * min_steps) or when n >= max_steps, else 0; -1 for e NULL or n < 0.  Both
  * means use the same k, so the one at n - 1 reaches back to phi^0 while
  * n <= LSR_ENERGY_WINDOW; a zero mean stops.  Host only (no device work). */
