@@ -57,6 +57,8 @@ def _lib():
         sig = {
             "orc_cutoff": (ctypes.c_double, [ctypes.c_double] * 3),
             "orc_energy_sum": (ctypes.c_double, [_D, _D, _GP, ctypes.c_double, ctypes.c_int]),
+            "orc_phi0_from_cloud": (ctypes.c_int, [_D, _GP, ctypes.c_double, ctypes.c_int, _D,
+                                                   _U8]),
             "orc_weno1d": (ctypes.c_double, [_D, ctypes.c_double, ctypes.c_double, _D]),
             "orc_interp": (ctypes.c_double, [_D, _GP, ctypes.c_int, _D]),
             "orc_gradient": (None, [_D, _GP, ctypes.c_int64, _D]),
@@ -307,3 +309,17 @@ def cloud_spacing(points, sample):
     tree = cKDTree(pts)
     dd, _ = tree.query(pts[np.asarray(sample, dtype=np.int64)], k=2)
     return float(np.mean(dd[:, 1]))
+
+
+def phi0_from_cloud(d, grid, gamma_s, max_cycles=100):
+    """phi0 of Section 3.6 from the distance field d and the threshold
+    gamma_S: external marking from the grid's boundary, d - gamma_S there,
+    fast sweeping inside, sign reversed inside.  Returns (phi0, external,
+    sweep cycles used)."""
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    assert dd.shape == shape(grid)
+    phi = np.empty_like(dd)
+    ext = np.empty(dd.shape, dtype=np.uint8)
+    cycles = _lib().orc_phi0_from_cloud(_ptr(dd), ctypes.byref(_grid(grid)), float(gamma_s),
+                                        int(max_cycles), _ptr(phi), _ptr(ext, _U8))
+    return phi, ext, cycles

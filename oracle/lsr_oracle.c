@@ -671,3 +671,123 @@ double orc_energy_sum(const double* phi, const double* d, const orc_grid* g, dou
   }
   return s;
 }
+
+/* ------------------------------------------------ initial data from the cloud */
+
+/* Section 3.6: phi0 from the distance field d and a threshold gamma_S.
+ *  1. External marking: the nodes on the boundary of the grid with
+ *     d >= gamma_S are external; the marking then moves inwards through face
+ *     neighbours, repeating sweeps along every Cartesian direction until no
+ *     node changes (reading: the printed "move inwards in all directions
+ *     until d < gamma_S" iterated to convergence, the serial result the
+ *     paper's parallel marking reproduces), never entering a node with
+ *     d < gamma_S.
+ *  2. phi0 = d - gamma_S on external nodes, a large value elsewhere.
+ *  3. Fast sweeping (Zhao 2005): Gauss-Seidel sweeps in the 2^dim
+ *     alternating orders of the first-order Godunov upwind discretisation
+ *     of |grad u| = 1 recompute the internal values (external values
+ *     fixed), until a full cycle changes nothing or max_cycles.
+ *  4. The sign is reversed on internal nodes.
+ * external[j] receives 1 for external nodes.  Returns the cycles used. */
+static double orc_eik_update(const double* u, const orc_grid* g, const int c[3]) {
+  double m[3];
+  int n = 0;
+  for (int a = 0; a < g->dim; ++a) {
+    double best = INFINITY;
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      int cn[3] = {c[0], c[1], c[2]};
+      cn[a] += sgn;
+      if (cn[a] < 0 || cn[a] > g->n[a] - 1) continue;
+      double v = u[orc_index(g, cn)];
+      if (v < best) best = v;
+    }
+    if (best < INFINITY) m[n++] = best;
+  }
+  /* sort ascending */
+  for (int i = 0; i < n; ++i)
+    for (int k = i + 1; k < n; ++k)
+      if (m[k] < m[i]) {
+        double t = m[i];
+        m[i] = m[k];
+        m[k] = t;
+      }
+  const double h = g->h;
+  if (n == 0) return INFINITY;
+  double x = m[0] + h;
+  if (n >= 2 && x > m[1]) {
+    x = 0.5 * (m[0] + m[1] + sqrt(2.0 * h * h - (m[0] - m[1]) * (m[0] - m[1])));
+    if (n >= 3 && x > m[2]) {
+      double s = m[0] + m[1] + m[2];
+      double q = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+      x = (s + sqrt(s * s - 3.0 * (q - h * h))) / 3.0;
+    }
+  }
+  return x;
+}
+
+int orc_phi0_from_cloud(const double* d, const orc_grid* g, double gamma_s, int max_cycles,
+                        double* phi, uint8_t* external) {
+  const int64_t N = orc_nodes(g);
+  const int dim = g->dim;
+  const int n2 = dim == 3 ? g->n[2] : 1;
+  memset(external, 0, (size_t)N);
+  for (int64_t j = 0; j < N; ++j) {
+    int c[3];
+    orc_coords(g, j, c);
+    int on_boundary = 0;
+    for (int a = 0; a < dim; ++a) on_boundary |= c[a] == 0 || c[a] == g->n[a] - 1;
+    if (on_boundary && d[j] >= gamma_s) external[j] = 1;
+  }
+  /* directional sweeps until no node changes */
+  for (int changed = 1; changed;) {
+    changed = 0;
+    for (int a = 0; a < dim; ++a)
+      for (int dir = -1; dir <= 1; dir += 2) {
+        for (int i = 0; i < g->n[0]; ++i)
+          for (int jj = 0; jj < g->n[1]; ++jj)
+            for (int k = 0; k < n2; ++k) {
+              int c[3] = {i, jj, k};
+              /* visit along axis a in direction dir */
+              if (dir < 0) c[a] = g->n[a] - 1 - c[a];
+              int64_t idx = orc_index(g, c);
+              if (external[idx] || d[idx] < gamma_s) continue;
+              int cp[3] = {c[0], c[1], c[2]};
+              cp[a] -= dir;
+              if (cp[a] < 0 || cp[a] > g->n[a] - 1) continue;
+              if (external[orc_index(g, cp)]) {
+                external[idx] = 1;
+                changed = 1;
+              }
+            }
+      }
+  }
+  const double big = 1e30;
+  for (int64_t j = 0; j < N; ++j) phi[j] = external[j] ? d[j] - gamma_s : big;
+  /* fast sweeping over the internal nodes */
+  int cycles = 0;
+  for (; cycles < max_cycles; ++cycles) {
+    int changed = 0;
+    for (int o = 0; o < (1 << dim); ++o) {
+      for (int i0 = 0; i0 < g->n[0]; ++i0)
+        for (int j0 = 0; j0 < g->n[1]; ++j0)
+          for (int k0 = 0; k0 < n2; ++k0) {
+            int c[3] = {(o & 1) ? g->n[0] - 1 - i0 : i0, (o & 2) ? g->n[1] - 1 - j0 : j0,
+                        dim == 3 ? ((o & 4) ? n2 - 1 - k0 : k0) : 0};
+            int64_t idx = orc_index(g, c);
+            if (external[idx]) continue;
+            double x = orc_eik_update(phi, g, c);
+            if (x < phi[idx]) {
+              phi[idx] = x;
+              changed = 1;
+            }
+          }
+    }
+    if (!changed) {
+      ++cycles;
+      break;
+    }
+  }
+  for (int64_t j = 0; j < N; ++j)
+    if (!external[j]) phi[j] = -phi[j];
+  return cycles;
+}
