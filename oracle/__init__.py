@@ -59,6 +59,8 @@ def _lib():
             "orc_energy_sum": (ctypes.c_double, [_D, _D, _GP, ctypes.c_double, ctypes.c_int]),
             "orc_phi0_from_cloud": (ctypes.c_int, [_D, _GP, ctypes.c_double, ctypes.c_int, _D,
                                                    _U8]),
+            "orc_distance_approx": (ctypes.c_int, [_D, ctypes.c_int64, _D, _GP, ctypes.c_int, _D,
+                                                   _U8]),
             "orc_weno1d": (ctypes.c_double, [_D, ctypes.c_double, ctypes.c_double, _D]),
             "orc_interp": (ctypes.c_double, [_D, _GP, ctypes.c_int, _D]),
             "orc_gradient": (None, [_D, _GP, ctypes.c_int64, _D]),
@@ -323,3 +325,16 @@ def phi0_from_cloud(d, grid, gamma_s, max_cycles=100):
     cycles = _lib().orc_phi0_from_cloud(_ptr(dd), ctypes.byref(_grid(grid)), float(gamma_s),
                                         int(max_cycles), _ptr(phi), _ptr(ext, _U8))
     return phi, ext, cycles
+
+
+def distance_approx(points, grid, max_cycles=100):
+    """The paper's approximate distance field (Section 3.4): exact at the
+    nodes of a 4^dim box around each cloud point, fast sweeping elsewhere.
+    Returns (d, fixed mask, sweep cycles used)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    exact = distance(pts, grid)
+    d = np.empty_like(exact)
+    fixed = np.empty(exact.shape, dtype=np.uint8)
+    cycles = _lib().orc_distance_approx(_ptr(pts), len(pts), _ptr(exact), ctypes.byref(_grid(grid)),
+                                        int(max_cycles), _ptr(d), _ptr(fixed, _U8))
+    return d, fixed, cycles

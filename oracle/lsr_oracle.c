@@ -791,3 +791,57 @@ int orc_phi0_from_cloud(const double* d, const orc_grid* g, double gamma_s, int 
     if (!external[j]) phi[j] = -phi[j];
   return cycles;
 }
+
+/* ------------------------------------------------ the paper's approximate d */
+
+/* Section 3.4: d is set to its exact value (d_exact, the minimum over the
+ * whole cloud) at every node of the box of 4 nodes per axis around each
+ * cloud point (the two nodes on each side of the cell holding the point,
+ * clamped to the grid), then the fast sweeping of orc_phi0_from_cloud's
+ * step 3 (Zhao 2005) computes every other node from those.  Returns the
+ * sweep cycles used. */
+int orc_distance_approx(const double* pts, int64_t n_pts, const double* d_exact,
+                        const orc_grid* g, int max_cycles, double* d, uint8_t* fixed) {
+  const int64_t N = orc_nodes(g);
+  const int dim = g->dim;
+  const int n2 = dim == 3 ? g->n[2] : 1;
+  memset(fixed, 0, (size_t)N);
+  for (int64_t q = 0; q < n_pts; ++q) {
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+      int c = (int)floor((pts[q * dim + a] - g->lo[a]) / g->h);
+      lo[a] = c - 1 < 0 ? 0 : c - 1;
+      hi[a] = c + 2 > g->n[a] - 1 ? g->n[a] - 1 : c + 2;
+    }
+    for (int i = lo[0]; i <= hi[0]; ++i)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int k = lo[2]; k <= hi[2]; ++k) {
+          int c[3] = {i, j, k};
+          fixed[orc_index(g, c)] = 1;
+        }
+  }
+  for (int64_t j = 0; j < N; ++j) d[j] = fixed[j] ? d_exact[j] : 1e30;
+  int cycles = 0;
+  for (; cycles < max_cycles; ++cycles) {
+    int changed = 0;
+    for (int o = 0; o < (1 << dim); ++o)
+      for (int i0 = 0; i0 < g->n[0]; ++i0)
+        for (int j0 = 0; j0 < g->n[1]; ++j0)
+          for (int k0 = 0; k0 < n2; ++k0) {
+            int c[3] = {(o & 1) ? g->n[0] - 1 - i0 : i0, (o & 2) ? g->n[1] - 1 - j0 : j0,
+                        dim == 3 ? ((o & 4) ? n2 - 1 - k0 : k0) : 0};
+            int64_t idx = orc_index(g, c);
+            if (fixed[idx]) continue;
+            double x = orc_eik_update(d, g, c);
+            if (x < d[idx]) {
+              d[idx] = x;
+              changed = 1;
+            }
+          }
+    if (!changed) {
+      ++cycles;
+      break;
+    }
+  }
+  return cycles;
+}
