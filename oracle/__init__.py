@@ -72,6 +72,8 @@ def _lib():
                                ctypes.c_int32, _I64]),
             "orc_init_phi": (None, [_D, _GP, ctypes.c_int, _D, ctypes.c_double]),
             "orc_distance_brute": (None, [_D, ctypes.c_int64, _GP, _D]),
+            "orc_resample": (None, [_D, _GP, ctypes.c_int, _GP, _D]),
+            "orc_threads": (ctypes.c_int, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -338,3 +340,118 @@ def distance_approx(points, grid, max_cycles=100):
     cycles = _lib().orc_distance_approx(_ptr(pts), len(pts), _ptr(exact), ctypes.byref(_grid(grid)),
                                         int(max_cycles), _ptr(d), _ptr(fixed, _U8))
     return d, fixed, cycles
+
+
+def threads(n=0):
+    """Worker threads of the oracle's per-node loops (n < 1: leave as is);
+    returns the count in effect."""
+    return int(_lib().orc_threads(int(n)))
+
+
+# ------------------------------------------------ the multi-run schedule
+
+def run_params(r):
+    """(p, delta) of run r >= 1 of Algorithm 1 (Section 4, Table param):
+    (1, 0), then (2, 0), then (2, 1) for every later run."""
+    if r < 1:
+        raise ValueError("runs are numbered from 1")
+    return (1.0, 0.0) if r == 1 else ((2.0, 0.0) if r == 2 else (2.0, 1.0))
+
+
+def run_spacing(h_s, r):
+    """(dx, dt) of run r, eq. (dxdt): dx = h_S / 2^(r-1), dt = dx / 4."""
+    dx = h_s / 2.0 ** (r - 1)
+    return dx, dx / 4.0
+
+
+def run_margin(dim, h_s, r, K_S=2.0):
+    """Nodes added on each side of the cloud's bounding box on the grid of
+    run r.  The paper says only that the grid encompasses the cloud
+    (Algorithm 1, step 1).  Reading, fitted to every grid size the paper
+    prints (the circle and square tables and the 3D grid table, with K_S = 2
+    and, for the scans with larger K_S, 5 or 10): the band half width in
+    cells (4 in 2D, 6 in 3D) plus 4, and in the first run also the
+    threshold gamma_S = K_S h_S in cells, rounded up."""
+    dx, _ = run_spacing(h_s, r)
+    m = (4 if dim == 2 else 6) + 4
+    if r == 1:
+        m += int(math.ceil(K_S * h_s / dx - 1e-9))
+    return m
+
+
+def run_grid(points, h_s, r, K_S=2.0):
+    """Grid of run r: spacing dx of eq. (dxdt); per axis the cloud's
+    extent L in whole cells, ceil(L / dx), plus one node and the margin
+    of run_margin on each side; node 0 sits the margin below the cloud's
+    smallest coordinate."""
+    pts = np.asarray(points, dtype=np.float64)
+    dim = pts.shape[1]
+    dx, _ = run_spacing(h_s, r)
+    m = run_margin(dim, h_s, r, K_S)
+    lo = pts.min(axis=0)
+    ext = pts.max(axis=0) - lo
+    n = tuple(int(math.ceil(ext[a] / dx)) + 1 + 2 * m for a in range(dim))
+    return {"dim": dim, "n": n, "lo": tuple(float(lo[a] - m * dx) for a in range(dim)), "h": dx}
+
+
+def resample(f, grid_from, grid, kind):
+    """Warm start of a finer run (Section 4, after eq. dxdt): the nodal field
+    f of grid_from interpolated at every node of grid with the interpolator
+    kind ('q1' or 'weno', Section 3.2)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert f.shape == shape(grid_from)
+    out = np.empty(shape(grid), dtype=np.float64)
+    _lib().orc_resample(_ptr(f), ctypes.byref(_grid(grid_from)), 0 if kind == "q1" else 1,
+                        ctypes.byref(_grid(grid)), _ptr(out))
+    return out
+
+
+def run_to_steady(phi0, d, grid, prm, dt, kind, R=5, min_steps=10, max_steps=100, tol=1e-4):
+    """One run of Algorithm 1 until the stopping test of eq. (deltaEn):
+    E_2 of phi^0 and of every new phi (R subcells per axis in 3D); each
+    step takes E_p(phi^n) (= E_2 when p = 2; unused at p = 1), the band,
+    the update and every reinit_every-th step the reinitialisation and cut.
+    Returns (phi, energies, steps)."""
+    phi = np.array(phi0, dtype=np.float64, order="C", copy=True)
+    energies = [energy(phi, d, grid, 2.0, R)]
+    n = 0
+    while True:
+        E = energies[-1] if prm["p"] == 2.0 else energy(phi, d, grid, prm["p"], R)
+        nxt, band, _ = step(phi, d, grid, dict(prm, energy=E), dt, kind)
+        if prm["reinit_every"] > 0 and (n + 1) % prm["reinit_every"] == 0:
+            nxt, _ = reinit(nxt, band, grid, prm)
+        phi = nxt
+        n += 1
+        energies.append(energy(phi, d, grid, 2.0, R))
+        if stop_rule(energies, n, min_steps, max_steps, tol):
+            return phi, energies, n
+
+
+def reconstruct(points, sample, kind, runs=3, K_S=2.0, R=5, min_steps=10, max_steps=100,
+                tol=1e-4):
+    """Algorithm 1 run `runs` times from coarse to fine (Section 4): h_S from
+    the sampled points; run r on the grid of run_grid with (p, delta) of
+    Table param and (dx, dt) of eq. (dxdt); the exact distance field on each
+    grid; phi^0 of the first run from the cloud with gamma_S = K_S h_S
+    (Section 3.6), of every later run the previous result resampled; each
+    phi^0 cut to [-gamma, gamma]; each run stepped to steady state.  Returns
+    (h_S, a list of per-run dicts: grid, params, dt, phi, energies,
+    steps)."""
+    pts = np.asarray(points, dtype=np.float64)
+    h_s = cloud_spacing(pts, sample)
+    out = []
+    for r in range(1, runs + 1):
+        g = run_grid(pts, h_s, r, K_S)
+        p, delta = run_params(r)
+        dx, dt = run_spacing(h_s, r)
+        prm = default_params(g["dim"], dx, p=p, delta=delta)
+        d = distance(pts, g)
+        if r == 1:
+            phi0, _, _ = phi0_from_cloud(d, g, K_S * h_s)
+        else:
+            phi0 = resample(out[-1]["phi"], out[-1]["grid"], g, kind)
+        phi0 = np.clip(phi0, -prm["gamma"], prm["gamma"])
+        phi, energies, n = run_to_steady(phi0, d, g, prm, dt, kind, R, min_steps, max_steps, tol)
+        out.append({"grid": g, "params": prm, "dt": dt, "phi0": phi0, "phi": phi,
+                    "energies": energies, "steps": n, "d": d})
+    return h_s, out

@@ -845,3 +845,32 @@ int orc_distance_approx(const double* pts, int64_t n_pts, const double* d_exact,
   }
   return cycles;
 }
+
+/* ------------------------------------------------ warm start of a finer run */
+
+/* Section 4, after eq. (dxdt): every run after the first starts from the
+ * steady state of the previous run, interpolated onto the run's own grid.
+ * out[j] = I[f](x_j) at every node x_j of grid g, where f holds nodal values
+ * on the coarser grid gf and I is the interpolator of Section 3.2 (kind 0:
+ * IQ1, 1: tensor WENO); a node outside gf's box is moved onto it, as every
+ * interpolation point is (orc_locate). */
+void orc_resample(const double* f, const orc_grid* gf, int kind, const orc_grid* g, double* out) {
+  const int64_t N = orc_nodes(g);
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < N; ++j) {
+    int c[3];
+    orc_coords(g, j, c);
+    double x[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < g->dim; ++a) x[a] = g->lo[a] + c[a] * g->h;
+    out[j] = orc_interp(f, gf, kind, x);
+  }
+}
+
+/* Worker threads of the OpenMP loops (n < 1: the runtime's default).  Used to
+ * time the oracle on one core and on all of them. */
+extern int omp_get_max_threads(void);
+extern void omp_set_num_threads(int);
+int orc_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
