@@ -269,8 +269,8 @@ def main():
     ap.add_argument("--workload", default="torus3d")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--lanes", type=int, default=-1,
-                    help="step kernel: 0 brick-staged (3D), 1 one lane per node, 4 (2 in 2D) one "
-                         "lane per foot point; -1 the library default")
+                    help="step kernel: 1 one lane per node, 4 (2 in 2D) one lane per foot point; "
+                         "-1 the library default")
     ap.add_argument("--blocks-per-cu", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="least wall time of the oracle sample")
@@ -304,10 +304,10 @@ def main():
                precision=args.precision)
     # a stream of its own (the null stream cannot be captured into graphs)
     job = lsr.Job(g, prm, max_points=len(w["points"]), stream=torch.cuda.Stream())
-    if args.lanes >= 0 or args.blocks_per_cu != 8:
-        lsr.lsr_set_launch(job.handle, args.lanes if args.lanes >= 0 else DEFAULT_LANES[dim],
+    if args.lanes > 0 or args.blocks_per_cu != 8:
+        lsr.lsr_set_launch(job.handle, args.lanes if args.lanes > 0 else DEFAULT_LANES[dim],
                            args.blocks_per_cu)
-    lanes = args.lanes if args.lanes >= 0 else DEFAULT_LANES[dim]
+    lanes = args.lanes if args.lanes > 0 else DEFAULT_LANES[dim]
     if args.no_graphs:
         job.set_graphs(False)
     stream = job.stream
@@ -357,11 +357,11 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / peak, 4),
                 "traffic": traffic,
-                "kernel": f"k_sl_step{'_staged' if lanes == 0 else ''}<{dim},{w['interp']},{'double' if args.precision == 'fp64' else 'float'}>",
+                "kernel": f"k_sl_step<{dim},{w['interp']},{'double' if args.precision == 'fp64' else 'float'}>",
                 "flops_per_node_update": flops,
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
                 "node_updates_per_launch": round(upd_per_launch, 1),
-                "lanes": lanes, "staged": lanes == 0, "blocks_per_cu": args.blocks_per_cu}
+                "lanes": lanes, "blocks_per_cu": args.blocks_per_cu}
     hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in lat)
     out = {

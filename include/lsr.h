@@ -4,11 +4,12 @@
  *
  * Method: S. Preda and M. Semplice, "Surface reconstruction from point cloud
  * using a semi-Lagrangian scheme with local interpolator", arXiv:2410.22205.
- * The library runs Algorithm 1's steps 2 and 4 (the energy step omitted, as
- * it only matters for p > 1): the distance field to the cloud (Section 2 and
- * 3.4, computed exactly), the narrow band (3.8), the semi-Lagrangian update
- * with Q1 or tensor WENO interpolation (3.1, 3.2) and the reinitialisation
- * plus cut (3.7, 3.8).
+ * The library runs Algorithm 1: the distance field to the cloud (Sections 2
+ * and 3.4, exact, or the paper's approximation), the initial data (3.6, from
+ * the cloud or in closed form), the narrow band (3.8), the energy functional
+ * and its p = 2 regime (3.5), the semi-Lagrangian update with Q1 or tensor
+ * WENO interpolation (3.1, 3.2), the reinitialisation plus cut (3.7, 3.8), the
+ * stopping test and the multi-run coarse-to-fine schedule (Section 4).
  *
  * General rules
  *  - Every function returns an lsr_status; none throws.  On failure the job is
@@ -24,12 +25,12 @@
  *  - All device work is enqueued on the caller's HIP stream given to
  *    lsr_create (a batch's on its own stream, with its second stream
  *    joined back into it within every call); only calls that return
- *    host-side values from the device (lsr_load_cloud's input check,
+ *    host-side values from the device (the loads' input checks, the
+ *    convergence tests of lsr_load_cloud_approx and lsr_init_phi_cloud,
  *    lsr_extract with n_band, lsr_energy, lsr_run_to_steady,
- *    lsr_cloud_spacing, lsr_counters,
- *    lsr_profile_read,
- *    lsr_batch_tune) and the switches of the graph, stream and timing
- *    hooks synchronise that stream.
+ *    lsr_cloud_spacing, lsr_counters, lsr_profile_read, lsr_batch_tune)
+ *    and the switches of the graph, stream and timing hooks synchronise
+ *    that stream.
  *  - Nodal arrays are in C order: 2D index i*n[1] + j, 3D index
  *    (i*n[1] + j)*n[2] + k, axis 0 <-> x.  Node (i,j,k) sits at
  *    lo + (i,j,k)*h.
@@ -51,7 +52,8 @@ typedef enum {
   LSR_E_NOMEM = -2,       /* workspace too small */
   LSR_E_DEVICE = -3,      /* HIP error; text in lsr_last_error() */
   LSR_E_STATE = -4,       /* call out of order (e.g. step before init_phi) */
-  LSR_E_UNSUPPORTED = -5  /* valid but not implemented (e.g. p != 1) */
+  LSR_E_UNSUPPORTED = -5  /* valid but not implemented (p other than 1 or 2; a batch
+                             mixing dimensions or precisions) */
 } lsr_status;
 
 /* Interpolation operator I[phi] of Section 3.2. */
@@ -129,7 +131,7 @@ lsr_status lsr_workspace_bytes(const lsr_grid* grid, const lsr_params* params, i
  * and untouched by other work while the job lives.  hip_stream: a
  * hipStream_t (NULL = default stream).  Enqueues the clearing of the
  * workspace.  LSR_E_INVALID on a bad grid or parameters, LSR_E_NOMEM if the
- * workspace is too small, LSR_E_UNSUPPORTED for p != 1. */
+ * workspace is too small, LSR_E_UNSUPPORTED for p other than 1 or 2. */
 lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_workspace,
                       size_t ws_bytes, void* hip_stream, lsr_job** out);
 
@@ -137,9 +139,22 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
  * every node from the cloud.  dev_xyz: device, n x dim doubles, row major;
  * it is copied into the workspace and may be freed afterwards.  Every point
  * must be finite and inside the grid's box (Algorithm 1, step 1: the grid
- * encompasses the cloud); otherwise LSR_E_INVALID.  Synchronises the stream
- * once to check the points.  The current phi and band are kept. */
+ * encompasses the cloud); otherwise LSR_E_INVALID, and the stored cloud and
+ * distance field are left as they were (the points are checked before
+ * anything is written).  Synchronises the stream twice: to check the points
+ * and to choose the bin width.  The current phi and band are kept. */
 lsr_status lsr_load_cloud(lsr_job* job, const double* dev_xyz, int64_t n);
+
+/* The paper's approximate distance field (Section 3.4): the exact distance
+ * to the cloud at the nodes of the box of 4 nodes per axis around each point
+ * (the two nodes on either side of the cell holding it, clamped to the
+ * grid), and elsewhere the solution of the first-order Godunov
+ * discretisation of |grad d| = 1 that Zhao's fast sweeping computes from
+ * those nodes (reached here by tiled passes to the same fixed point).
+ * Arguments, checks and synchronisations as lsr_load_cloud, plus one
+ * synchronisation per four passes of the solve; LSR_E_DEVICE if the solve
+ * does not settle within about eight passes per node along the axes. */
+lsr_status lsr_load_cloud_approx(lsr_job* job, const double* dev_xyz, int64_t n);
 
 /* Test and restart hook: use the given distance field instead of a cloud.
  * dev_d: device, one double per node, C order, finite and >= 0 (not
@@ -159,6 +174,45 @@ lsr_status lsr_get_distance(lsr_job* job, double* dev_out);
  * step, which fixes the reinitialisation phase after a restart. */
 lsr_status lsr_init_phi(lsr_job* job, const void* dev_phi0, int32_t kind, const double* args,
                         int64_t step0);
+
+/* Initial data from the cloud (Section 3.6) from the job's distance field d
+ * and the threshold gamma_s > 0 (the paper: gamma_S = K_S h_S, K_S = 2 by
+ * default, Section 4): nodes on the grid's boundary with d >= gamma_s are
+ * external, and so is every node with d >= gamma_s reachable from them
+ * through face neighbours that are; phi0 = d - gamma_s there; on the other
+ * nodes phi0 = -u with u the fast-sweeping solution of |grad u| = 1 from the
+ * external values (first-order Godunov, the external nodes held fixed;
+ * 1e30 where no external node leads); cut to [-gamma, gamma] as in
+ * lsr_init_phi, with the first band.  step0 as in lsr_init_phi.  LSR_E_STATE
+ * without a distance field; one synchronisation per four passes of the
+ * marking and of the solve; LSR_E_DEVICE if either does not settle (see
+ * lsr_load_cloud_approx). */
+lsr_status lsr_init_phi_cloud(lsr_job* job, double gamma_s, int64_t step0);
+
+/* Warm start of a finer run (Section 4, after eq. dxdt): phi0 at every node
+ * x of the job's grid is I[phi](x) with phi the current phi of `coarse` (a
+ * job of the same dimension and precision on another grid) and I the
+ * interpolator `interp` (Section 3.2; a node outside coarse's box is moved
+ * onto it), cut to [-gamma, gamma], with the first band.  The job's stream
+ * is ordered after the work queued on coarse's, and coarse's after the
+ * read.  step0 as in lsr_init_phi. */
+lsr_status lsr_init_phi_resample(lsr_job* job, const lsr_job* coarse, lsr_interp interp,
+                                 int64_t step0);
+
+/* Grid, parameters and time step of run r >= 1 of the coarse-to-fine
+ * schedule (Section 4) for a cloud with bounding box [box_lo, box_hi] (host,
+ * dim values each) and resolution h_s (see lsr_cloud_spacing): dx = h_s /
+ * 2^(r-1) and dt = dx / 4 (eq. dxdt); p = 1, delta = 0 in run 1, p = 2,
+ * delta = 0 in run 2 and p = 2, delta = 1 after (Table param); the other
+ * parameters as lsr_params_default(dim, dx).  The grid (the paper says only
+ * that it encompasses the cloud; these sizes reproduce every grid the paper
+ * lists): per axis ceil(extent / dx) + 1 nodes plus m on each side, node 0
+ * at box_lo - m dx, with m the band half width in cells plus 4, and in run 1
+ * also ceil(k_s h_s / dx) (the threshold gamma_S = k_s h_s of the initial
+ * data).  Host only. */
+lsr_status lsr_schedule_run(int32_t r, int32_t dim, const double* box_lo, const double* box_hi,
+                            double h_s, double k_s, lsr_grid* grid, lsr_params* params,
+                            double* dt);
 
 /* n_steps iterations of Algorithm 1's loop: band (eq. subgrid, read as
  * |phi| < gamma), the update of eqs. (SL2d)/(SL3d) with the cut-off factor of
@@ -290,13 +344,10 @@ lsr_status lsr_batch_tune(lsr_batch* batch, int32_t* lanes, int32_t* blocks_per_
 lsr_status lsr_batch_destroy(lsr_batch* batch);
 
 /* Launch shape of the list kernels (results are bitwise the same for every
- * shape): lanes = 1 (one lane per band node), the number of foot points per
- * node (2 in 2D, 4 in 3D: one lane per foot point), or, in 3D only, 0: the
- * step kernel works brick by brick (4 x 8 x 8 nodes) with the brick and a
- * halo of phi staged in LDS, and falls back to device-memory reads for foot
- * points beyond the halo.  blocks_per_cu in 1..64 bounds the persistent grid,
- * which never exceeds the blocks of the kernel that fit on the device at
- * once.  Defaults: 1 lane, 8. */
+ * shape): lanes = 1 (one lane per band node) or the number of foot points
+ * per node (2 in 2D, 4 in 3D: one lane per foot point).  blocks_per_cu in
+ * 1..64 bounds the persistent grid, which never exceeds the blocks of the
+ * kernel that fit on the device at once.  Defaults: 1 lane, 8. */
 lsr_status lsr_set_launch(lsr_job* job, int32_t lanes, int32_t blocks_per_cu);
 
 /* Step loops as HIP graphs.  With enable = 1 (the default) lsr_step runs
@@ -304,9 +355,8 @@ lsr_status lsr_set_launch(lsr_job* job, int32_t lanes, int32_t blocks_per_cu);
  * through recorded graphs: a chunk is recorded the second time the job
  * starts one in the same state (buffer roles, counter slots, phase in the
  * reinitialisation period, dt, interpolator, launch shape) and replayed after
- * that; the remaining steps, the staged kernel (lanes = 0), jobs on the null
- * stream and step loops while kernel timing is on (lsr_profile_enable)
- * launch directly.  Results are the same either way.
+ * that; the remaining steps, jobs on the null stream and step loops while
+ * kernel timing is on (lsr_profile_enable) launch directly.  Results are the same either way.
  * Synchronises the stream and drops the recorded graphs. */
 lsr_status lsr_set_graphs(lsr_job* job, int32_t enable);
 
@@ -317,8 +367,7 @@ lsr_status lsr_graph_counts(lsr_job* job, lsr_batch* batch, int64_t* captured, i
 /* Measurement hook.  While enabled, lsr_step launches directly and every
  * semi-Lagrangian step kernel of the job carries a pair of HIP events tied
  * to its dispatch (hipExtLaunchKernel), whose elapsed time is the kernel's
- * execution time (the staged kernel, lanes = 0: events recorded on the
- * stream around the launch); at most max_launches pairs, later launches are
+ * execution time; at most max_launches pairs, later launches are
  * not timed.  Enabling or disabling clears earlier records.
  * lsr_profile_read synchronises the stream and returns the summed kernel
  * time in milliseconds and the number of timed launches. */

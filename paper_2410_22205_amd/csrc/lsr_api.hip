@@ -75,17 +75,26 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.phi1 = take(es * N);
   L.dp = take(4 * es * N);
   L.d64 = take(8 * N);
-  L.list0 = take(4 * N);
-  L.list1 = take(4 * N);
+  // band lists: whole chunks, and room for the slot lists of a grid scan
+  const uint32_t slots = gbar_slots(g.dim, g.n[0], g.n[1], g.dim == 3 ? g.n[2] : 1);
+  const size_t nch = (N + LCHUNK - 1) / LCHUNK;
+  L.list_cap = (int64_t)std::max(nch * LCHUNK, (size_t)slots * GBAR_CHUNK);
+  L.list0 = take(4 * (size_t)L.list_cap);
+  L.list1 = take(4 * (size_t)L.list_cap);
+  L.ccnt0 = take(4 * nch);
+  L.ccnt1 = take(4 * nch);
+  L.scnt = take(4 * (size_t)slots);
+  L.soff = take(4 * ((size_t)slots + 1));
   L.listM = take(4 * N);
   L.mflags = take(N);
-  // bricks of the staged 3D step: 4 x 8 x 8 nodes
-  L.nbricks = g.dim == 3 ? (int64_t)((g.n[0] + BRICK_I - 1) / BRICK_I) *
-                               ((g.n[1] + BRICK_J - 1) / BRICK_J) * ((g.n[2] + BRICK_K - 1) / BRICK_K)
-                         : 1;
-  L.blist0 = take(4 * (size_t)L.nbricks);
-  L.blist1 = take(4 * (size_t)L.nbricks);
-  L.bstamp = take(4 * (size_t)L.nbricks);
+  {
+    // bricks of the distance kernel (8^3, 16^2 in 2D), marked for the
+    // approximate distance
+    const int BS = g.dim == 3 ? 8 : 16;
+    const size_t nb = (size_t)((g.n[0] + BS - 1) / BS) * ((g.n[1] + BS - 1) / BS) *
+                      (g.dim == 3 ? (g.n[2] + BS - 1) / BS : 1);
+    L.dmark = take(nb);
+  }
   L.cnt = take(4 * 16);
   L.stats = take(8 * STAT_WORDS);
   L.pts_raw = take(8 * (size_t)g.dim * P);
@@ -150,7 +159,7 @@ template <typename T>
 static hipError_t launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
   hipStream_t s = j->stream;
   const int dim = j->grid.dim;
-  hipError_t e = launch_gbar_scan<T>(dim, r.gb, j->list_blocks, s);
+  hipError_t e = launch_grid_list<T>(dim, r.gb, j->list_blocks, s);
   if (e == hipSuccess) e = launch_reinit_fix<T>(dim, r.fix, j->list_blocks, s);
   for (int it = 0; it < r.iters && e == hipSuccess; ++it)
     e = launch_reinit_iter<T>(dim, r.iter[it % 2], j->list_blocks, s);
@@ -161,24 +170,7 @@ static hipError_t launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
 template <typename T>
 static lsr_status run_reinit_t(lsr_job* j) {
   ReinitPlan<T> r = plan_reinit<T>(j);
-  j->bricks_valid = false;
   LSR_HIP(launch_reinit_plan<T>(j, r));
-  return LSR_OK;
-}
-
-// Brick list of the current node list (before a staged step that follows a
-// step of another kind, the initial data or a reinitialisation).
-static lsr_status rebuild_bricks(lsr_job* j) {
-  hipStream_t s = j->stream;
-  if (j->bepoch == 0xFFFFFFFFu) {
-    LSR_HIP(launch_fill_u32(j->bstamp, 0u, (uint64_t)j->L.nbricks, s));
-    j->bepoch = 0;
-  }
-  j->bepoch += 1;
-  LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 8), 0u, 3, s));
-  LSR_HIP(launch_nodes_to_bricks(j->dg, j->list[j->cur_list], ring_slot(j, 0), j->bstamp, j->bepoch,
-                                 j->blist[j->cur_blist], bring_slot(j, 0), j->list_blocks, s));
-  j->bricks_valid = true;
   return LSR_OK;
 }
 
@@ -208,30 +200,25 @@ static hipError_t issue_steps(lsr_job* j, int32_t n, const StepConst<T>& c, int 
       if (launch && e == hipSuccess) e = launch_reinit_plan<T>(j, r);
     }
   }
-  j->bricks_valid = false;
   return e;
 }
 
 struct PlanState {
-  int cur, cur_list, cur_blist, ring;
+  int cur, cur_list, ring;
   int64_t step_index, n_reinits, n_steps;
-  bool bricks_valid;
 };
 
 static PlanState save_plan(const lsr_job* j) {
-  return {j->cur, j->cur_list, j->cur_blist, j->ring, j->step_index, j->n_reinits, j->n_steps,
-          j->bricks_valid};
+  return {j->cur, j->cur_list, j->ring, j->step_index, j->n_reinits, j->n_steps};
 }
 
 static void restore_plan(lsr_job* j, const PlanState& p) {
   j->cur = p.cur;
   j->cur_list = p.cur_list;
-  j->cur_blist = p.cur_blist;
   j->ring = p.ring;
   j->step_index = p.step_index;
   j->n_reinits = p.n_reinits;
   j->n_steps = p.n_steps;
-  j->bricks_valid = p.bricks_valid;
 }
 
 // Steps between two graph keys: twice the reinitialisation period, after
@@ -248,7 +235,7 @@ static std::vector<int64_t> graph_key(const lsr_job* j, int32_t n, double dt, in
   int64_t dtb;
   memcpy(&dtb, &dt, sizeof dtb);
   const int64_t K = j->prm.reinit_every;
-  return {(int64_t)sizeof(T), j->cur, j->cur_list, j->cur_blist, j->ring,
+  return {(int64_t)sizeof(T), j->cur, j->cur_list, j->ring,
           K > 0 ? j->step_index % K : 0, n, dtb, interp, j->lanes, (int64_t)j->list_blocks};
 }
 
@@ -257,25 +244,13 @@ static std::vector<int64_t> graph_key(const lsr_job* j, int32_t n, double dt, in
 template <typename T>
 static lsr_status direct_steps(lsr_job* j, int32_t n_steps, const StepConst<T>& c, int interp) {
   hipStream_t s = j->stream;
-  const bool staged = j->lanes == 0;
   for (int32_t q = 0; q < n_steps; ++q) {
-    if (staged && !j->bricks_valid) {
-      lsr_status st = rebuild_bricks(j);
-      if (st != LSR_OK) return st;
-    }
     if (j->prm.p != 1.0) LSR_HIP(launch_step_energy<T>(j));
     SLArgs<T> a = plan_step<T>(j, c);
     const bool rec = j->prof_on && 2 * (size_t)j->prof_used + 1 < j->prof_ev.size();
     hipEvent_t e0 = rec ? j->prof_ev[2 * j->prof_used] : nullptr;
     hipEvent_t e1 = rec ? j->prof_ev[2 * j->prof_used + 1] : nullptr;
-    if (staged) {
-      if (rec) LSR_HIP(hipEventRecord(e0, s));
-      LSR_HIP(launch_sl_step_staged<T>(interp, a, j->list_blocks, s));
-      if (rec) LSR_HIP(hipEventRecord(e1, s));
-    } else {
-      LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s, e0, e1));
-      j->bricks_valid = false;
-    }
+    LSR_HIP(launch_sl_step<T>(j->grid.dim, interp, j->lanes, a, j->list_blocks, s, e0, e1));
     if (rec) j->prof_used += 1;
     if (reinit_due(j)) {
       lsr_status st = run_reinit_t<T>(j);
@@ -289,11 +264,11 @@ template <typename T>
 static lsr_status run_steps_t(lsr_job* j, int32_t n_steps, double dt, int interp) {
   hipStream_t s = j->stream;
   const StepConst<T> c = step_const<T>(j, dt);
-  // whole chunks through recorded graphs (node-list kernel only, not while
-  // kernel timing is on, never on the null stream, which cannot be captured)
+  // whole chunks through recorded graphs (not while kernel timing is on,
+  // never on the null stream, which cannot be captured)
   const int32_t chunk = graph_chunk(j);
   GraphCache& G = j->graphs;
-  while (j->lanes != 0 && !j->prof_on && G.enabled && s != nullptr && n_steps >= chunk) {
+  while (!j->prof_on && G.enabled && s != nullptr && n_steps >= chunk) {
     const std::vector<int64_t> key = graph_key<T>(j, chunk, dt, interp);
     GraphCache::Entry* g = G.find(key);
     bool direct = false;
@@ -353,6 +328,66 @@ hipError_t dpack(lsr_job* j) {
                                        (typename Vec<float>::pack*)j->dp, j->stream);
 }
 
+// Passes of an iteration to its fixed point: groups of four passes, each
+// flagging a change in its own counter slot, until the last pass of a group
+// changes nothing (one synchronisation per group); at most about eight
+// passes per node along the grid's axes.
+template <typename F>
+lsr_status until_still(lsr_job* j, const char* what, F pass) {
+  hipStream_t s = j->stream;
+  int32_t* fl = j->cnt + 12;
+  constexpr int G = 4;
+  const int64_t max_passes = 8 * ((int64_t)j->dg.n0 + j->dg.n1 + j->dg.n2) + 64;
+  for (int64_t done = 0; done < max_passes; done += G) {
+    LSR_HIP(launch_fill_u32((uint32_t*)fl, 0u, G, s));
+    for (int q = 0; q < G; ++q) LSR_HIP(pass(fl + q));
+    int32_t last = 1;
+    LSR_HIP(hipMemcpyAsync(&last, fl + G - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSR_HIP(hipStreamSynchronize(s));
+    if (!last) return LSR_OK;
+  }
+  return fail(LSR_E_DEVICE, std::string(what) + " did not reach its fixed point");
+}
+
+// Arguments of the grid scan that builds the first band (|phi| < gamma) of
+// freshly initialised data into list 0, chunked; list 1 holds the slots.
+template <typename T>
+GbarArgs<T> first_band(lsr_job* j) {
+  GbarArgs<T> a;
+  a.g = j->dg;
+  a.gamma = (T)j->prm.gamma;
+  a.nbr = 0;
+  a.P = phi_buf<T>(j, 0);
+  a.S = j->list[1];
+  a.scnt = j->scnt;
+  a.soff = j->soff;
+  a.M = j->list[0];
+  a.cnt_out = j->cnt;  // ring slot 0
+  a.ccnt = j->ccnt[0];
+  return a;
+}
+
+// After new initial data: counters and statistics cleared, the first band
+// built (in the order of a brick-by-brick scan of the grid), the step index
+// set.
+lsr_status start_loop(lsr_job* j, int64_t step0) {
+  hipStream_t s = j->stream;
+  LSR_HIP(launch_fill_u32((uint32_t*)j->cnt, 0u, 3, s));
+  LSR_HIP(launch_fill_u32((uint32_t*)j->stats, 0u, 2 * STAT_WORDS, s));
+  if (j->fp64)
+    LSR_HIP(launch_grid_list<double>(j->grid.dim, first_band<double>(j), j->list_blocks, s));
+  else
+    LSR_HIP(launch_grid_list<float>(j->grid.dim, first_band<float>(j), j->list_blocks, s));
+  j->cur = 0;
+  j->cur_list = 0;
+  j->ring = 0;
+  j->step_index = step0;
+  j->n_reinits = 0;
+  j->n_steps = 0;
+  j->has_phi = true;
+  return LSR_OK;
+}
+
 // Initial data into both phi buffers, or (write = false) only the check of
 // the caller's array.
 hipError_t init_phi(lsr_job* j, int kind, const double* a, const void* src, bool write) {
@@ -389,6 +424,49 @@ lsr_status lsr_params_default(int32_t dim, double h, lsr_params* out) {
   p.interface_floor = 1e-3;
   p.precision = LSR_FP32;
   *out = p;
+  return LSR_OK;
+}
+
+lsr_status lsr_schedule_run(int32_t r, int32_t dim, const double* box_lo, const double* box_hi,
+                            double h_s, double k_s, lsr_grid* grid, lsr_params* params,
+                            double* dt) {
+  if (!box_lo || !box_hi || !grid || !params || !dt) return fail(LSR_E_INVALID, "NULL argument");
+  if (r < 1 || r > 30) return fail(LSR_E_INVALID, "runs are numbered 1 .. 30");
+  if (dim != 2 && dim != 3) return fail(LSR_E_INVALID, "dim must be 2 or 3");
+  if (!(h_s > 0.0) || !isfinite(h_s)) return fail(LSR_E_INVALID, "h_s must be finite and > 0");
+  if (!(k_s >= 0.0) || !isfinite(k_s)) return fail(LSR_E_INVALID, "k_s must be finite and >= 0");
+  for (int a = 0; a < dim; ++a)
+    if (!isfinite(box_lo[a]) || !isfinite(box_hi[a]) || box_hi[a] < box_lo[a])
+      return fail(LSR_E_INVALID, "the cloud's box must be finite with hi >= lo");
+  // eq. (dxdt)
+  const double dx = h_s / pow(2.0, (double)(r - 1));
+  // margin: the band half width in cells plus 4, and gamma_S in the first run
+  int m = (dim == 2 ? 4 : 6) + 4;
+  if (r == 1) m += (int)ceil(k_s * h_s / dx - 1e-9);
+  lsr_grid g;
+  memset(&g, 0, sizeof g);
+  g.dim = dim;
+  g.h = dx;
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      const double cells = ceil((box_hi[a] - box_lo[a]) / dx);
+      if (cells + 1.0 + 2.0 * m > 2147483647.0) return fail(LSR_E_INVALID, "grid too large");
+      g.n[a] = (int32_t)cells + 1 + 2 * m;
+      g.lo[a] = box_lo[a] - m * dx;
+    } else {
+      g.n[a] = 1;
+      g.lo[a] = 0.0;
+    }
+  }
+  lsr_params p;
+  lsr_status st = lsr_params_default(dim, dx, &p);
+  if (st != LSR_OK) return st;
+  // Table param
+  p.p = r == 1 ? 1.0 : 2.0;
+  p.delta = r <= 2 ? 0.0 : 1.0;
+  *grid = g;
+  *params = p;
+  *dt = dx / 4.0;
   return LSR_OK;
 }
 
@@ -477,14 +555,13 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->d64 = (double*)(w + L.d64);
   j->list[0] = (uint32_t*)(w + L.list0);
   j->list[1] = (uint32_t*)(w + L.list1);
+  j->ccnt[0] = (int32_t*)(w + L.ccnt0);
+  j->ccnt[1] = (int32_t*)(w + L.ccnt1);
+  j->scnt = (int32_t*)(w + L.scnt);
+  j->soff = (int32_t*)(w + L.soff);
   j->listM = (uint32_t*)(w + L.listM);
   j->mflags = (uint8_t*)(w + L.mflags);
-  j->blist[0] = (uint32_t*)(w + L.blist0);
-  j->blist[1] = (uint32_t*)(w + L.blist1);
-  j->bstamp = (uint32_t*)(w + L.bstamp);
-  j->cur_blist = 0;
-  j->bepoch = 0;
-  j->bricks_valid = false;
+  j->dmark = (uint8_t*)(w + L.dmark);
   j->cnt = (int32_t*)(w + L.cnt);
   j->stats = (unsigned long long*)(w + L.stats);
   j->pts_raw = (double*)(w + L.pts_raw);
@@ -519,8 +596,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->prof_used = 0;
 
   hipStream_t s = j->stream;
-  hipError_t e = launch_fill_u32(j->bstamp, 0u, (uint64_t)L.nbricks, s);
-  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->cnt, 0u, 16, s);
+  hipError_t e = launch_fill_u32((uint32_t*)j->cnt, 0u, 16, s);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->stats, 0u, 2 * STAT_WORDS, s);
   if (e != hipSuccess) {
     delete j;
@@ -530,7 +606,13 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   return LSR_OK;
 }
 
-lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
+}  // extern "C"
+
+namespace lsr {
+
+// The cloud into the workspace, binned and sorted, and the distance field:
+// exact at every node, or (approx) the paper's approximation of Section 3.4.
+static lsr_status load_cloud(lsr_job* j, const double* dev_xyz, int64_t n, bool approx) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
   if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   if (!dev_xyz) return fail(LSR_E_INVALID, "points are NULL");
@@ -538,6 +620,15 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
   if (n > j->max_points) return fail(LSR_E_NOMEM, "cloud larger than the workspace allows");
   hipStream_t s = j->stream;
   const int dim = j->grid.dim;
+  {
+    // check the points before touching the stored cloud
+    int32_t bad = 0;
+    LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s));
+    LSR_HIP(launch_check_points(dim, j->bg, dev_xyz, n, j->cnt + 3, s));
+    LSR_HIP(hipMemcpyAsync(&bad, j->cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSR_HIP(hipStreamSynchronize(s));
+    if (bad) return fail(LSR_E_INVALID, "cloud has a non-finite point or one outside the grid box");
+  }
   j->n_cloud = 0;  // set again once the new cloud is binned and sorted
   LSR_HIP(hipMemcpyAsync(j->pts_raw, dev_xyz, sizeof(double) * dim * (size_t)n,
                          hipMemcpyDeviceToDevice, s));
@@ -595,15 +686,44 @@ lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
     da.mu2 = 1e-12 * diag * diag;
   }
   da.d64 = j->d64;
+  da.bmark = nullptr;
   j->bg_load = bg;
   j->n_cloud = n;
   const int BS = dim == 3 ? 8 : 16;
   unsigned bricks = (unsigned)(((j->dg.n0 + BS - 1) / BS) * ((j->dg.n1 + BS - 1) / BS) *
                                (dim == 3 ? (j->dg.n2 + BS - 1) / BS : 1));
+  if (approx) {
+    // exact values only on the bricks holding a point's 4^dim box, then the
+    // fast-sweeping fixed point from the box nodes outwards
+    LSR_HIP(launch_fill_u8(j->mflags, 0, j->dg.N, s));
+    LSR_HIP(launch_fill_u8(j->dmark, 0, bricks, s));
+    LSR_HIP(launch_box_mark(dim, j->dg, j->pts_raw, n, j->mflags, j->dmark, s));
+    da.bmark = j->dmark;
+  }
   LSR_HIP(launch_distance(dim, da, bricks, s));
+  j->has_d = false;
+  if (approx) {
+    LSR_HIP(launch_eik_init(j->dg, j->d64, j->mflags, j->d64, s));
+    lsr_status st = until_still(j, "the approximate distance", [&](int32_t* fl) {
+      return launch_eik_pass(dim, j->dg, j->d64, j->mflags, fl, s);
+    });
+    if (st != LSR_OK) return st;
+  }
   LSR_HIP(dpack(j));
   j->has_d = true;
   return LSR_OK;
+}
+
+}  // namespace lsr
+
+extern "C" {
+
+lsr_status lsr_load_cloud(lsr_job* j, const double* dev_xyz, int64_t n) {
+  return load_cloud(j, dev_xyz, n, false);
+}
+
+lsr_status lsr_load_cloud_approx(lsr_job* j, const double* dev_xyz, int64_t n) {
+  return load_cloud(j, dev_xyz, n, true);
 }
 
 lsr_status lsr_set_distance(lsr_job* j, const double* dev_d) {
@@ -645,7 +765,6 @@ lsr_status lsr_init_phi(lsr_job* j, const void* dev_phi0, int32_t kind, const do
     if (j->grid.dim == 2) a[2] = 0.0;
   }
   hipStream_t s = j->stream;
-  const int dim = j->grid.dim;
   if (kind == LSR_PHI_ARRAY) {
     // check the input before touching the state (no output buffers: check only)
     LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 3), 0u, 1, s));
@@ -656,22 +775,68 @@ lsr_status lsr_init_phi(lsr_job* j, const void* dev_phi0, int32_t kind, const do
     if (flag) return fail(LSR_E_INVALID, "phi0 has a non-finite value");
   }
   LSR_HIP(init_phi(j, kind, a, dev_phi0, true));
-  LSR_HIP(launch_fill_u32((uint32_t*)j->cnt, 0u, 3, s));
-  LSR_HIP(launch_fill_u32((uint32_t*)j->stats, 0u, 2 * STAT_WORDS, s));
-  LSR_HIP(j->fp64 ? launch_band_scan<double>(dim, j->dg, j->prm.gamma, phi_buf<double>(j, 0),
-                                             j->list[0], j->cnt, s)
-                  : launch_band_scan<float>(dim, j->dg, (float)j->prm.gamma, phi_buf<float>(j, 0),
-                                            j->list[0], j->cnt, s));
-  j->cur = 0;
-  j->cur_list = 0;
-  j->cur_blist = 0;
-  j->ring = 0;
-  j->step_index = step0;
-  j->n_reinits = 0;
-  j->n_steps = 0;
-  j->has_phi = true;
-  j->bricks_valid = false;
-  return LSR_OK;
+  return start_loop(j, step0);
+}
+
+lsr_status lsr_init_phi_cloud(lsr_job* j, double gamma_s, int64_t step0) {
+  if (!j) return fail(LSR_E_INVALID, "job is NULL");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
+  if (!(gamma_s > 0.0) || !isfinite(gamma_s)) return fail(LSR_E_INVALID, "gamma_s must be > 0");
+  if (step0 < 0) return fail(LSR_E_INVALID, "step0 must be >= 0");
+  if (!j->has_d) return fail(LSR_E_STATE, "no distance field: call lsr_load_cloud first");
+  hipStream_t s = j->stream;
+  const int dim = j->grid.dim;
+  uint8_t* ext = j->mflags;
+  double* u = (double*)j->dp;  // the packed gradient is rebuilt from d afterwards
+  LSR_HIP(launch_mark_init(dim, j->dg, j->d64, gamma_s, ext, s));
+  lsr_status st = until_still(j, "the external marking", [&](int32_t* fl) {
+    return launch_mark_pass(dim, j->dg, j->d64, gamma_s, ext, fl, s);
+  });
+  if (st == LSR_OK) {
+    LSR_HIP(launch_eik_init_ext(j->dg, j->d64, gamma_s, ext, u, s));
+    st = until_still(j, "the fast sweeping", [&](int32_t* fl) {
+      return launch_eik_pass(dim, j->dg, u, ext, fl, s);
+    });
+  }
+  if (st == LSR_OK) {
+    if (j->fp64)
+      LSR_HIP(launch_phi0_cloud<double>(j->dg, j->d64, u, ext, gamma_s, j->prm.gamma,
+                                        phi_buf<double>(j, 0), phi_buf<double>(j, 1), s));
+    else
+      LSR_HIP(launch_phi0_cloud<float>(j->dg, j->d64, u, ext, gamma_s, (float)j->prm.gamma,
+                                       phi_buf<float>(j, 0), phi_buf<float>(j, 1), s));
+  }
+  LSR_HIP(dpack(j));
+  if (st != LSR_OK) return st;
+  return start_loop(j, step0);
+}
+
+lsr_status lsr_init_phi_resample(lsr_job* j, const lsr_job* coarse, lsr_interp interp,
+                                 int64_t step0) {
+  if (!j || !coarse) return fail(LSR_E_INVALID, "job is NULL");
+  if (j == coarse) return fail(LSR_E_INVALID, "the coarser job must be another job");
+  if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
+  if (interp != LSR_Q1 && interp != LSR_WENO) return fail(LSR_E_INVALID, "unknown interpolator");
+  if (step0 < 0) return fail(LSR_E_INVALID, "step0 must be >= 0");
+  if (coarse->grid.dim != j->grid.dim || coarse->fp64 != j->fp64)
+    return fail(LSR_E_INVALID, "both jobs need the same dimension and precision");
+  if (!coarse->has_phi) return fail(LSR_E_STATE, "the coarser job has no phi");
+  hipStream_t s = j->stream;
+  LSR_HIP(order_after(s, coarse->stream));
+  const double hc = coarse->grid.h;
+  if (j->fp64)
+    LSR_HIP(launch_resample<double>(j->grid.dim, (int)interp, j->dg, coarse->dg,
+                                    (const double*)coarse->phi[coarse->cur], j->prm.gamma,
+                                    hc * hc * hc * hc, phi_buf<double>(j, 0),
+                                    phi_buf<double>(j, 1), s));
+  else
+    LSR_HIP(launch_resample<float>(j->grid.dim, (int)interp, j->dg, coarse->dg,
+                                   (const float*)coarse->phi[coarse->cur], (float)j->prm.gamma,
+                                   (float)(hc * hc * hc * hc), phi_buf<float>(j, 0),
+                                   phi_buf<float>(j, 1), s));
+  // the coarser job's stream waits for the read before it may change phi
+  LSR_HIP(order_after(coarse->stream, s));
+  return start_loop(j, step0);
 }
 
 lsr_status lsr_step(lsr_job* j, int32_t n_steps, double dt, lsr_interp interp) {
@@ -786,12 +951,12 @@ lsr_status lsr_extract(lsr_job* j, void* dev_phi, uint8_t* dev_band, int64_t* n_
     LSR_HIP(launch_fill_u32((uint32_t*)(j->cnt + 4), 0u, 1, s));
     if (j->fp64)
       LSR_HIP(launch_band_mask<double>(j->dg, j->prm.gamma, phi_buf<double>(j, j->cur),
-                                       j->list[j->cur_list], ring_slot(j, 0), dev_band, j->cnt + 4,
-                                       j->list_blocks, s));
+                                       j->list[j->cur_list], j->ccnt[j->cur_list], ring_slot(j, 0),
+                                       dev_band, j->cnt + 4, j->list_blocks, s));
     else
       LSR_HIP(launch_band_mask<float>(j->dg, (float)j->prm.gamma, phi_buf<float>(j, j->cur),
-                                      j->list[j->cur_list], ring_slot(j, 0), dev_band, j->cnt + 4,
-                                      j->list_blocks, s));
+                                      j->list[j->cur_list], j->ccnt[j->cur_list], ring_slot(j, 0),
+                                      dev_band, j->cnt + 4, j->list_blocks, s));
   }
   if (n_band) {
     int32_t c = 0;
@@ -829,8 +994,8 @@ lsr_status lsr_set_launch(lsr_job* j, int32_t lanes, int32_t blocks_per_cu) {
   if (!j) return fail(LSR_E_INVALID, "job is NULL");
   if (j->in_batch) return fail(LSR_E_STATE, "job belongs to a batch");
   const int fp = j->grid.dim == 3 ? 4 : 2;
-  if (lanes != 1 && lanes != fp && !(lanes == 0 && j->grid.dim == 3))
-    return fail(LSR_E_INVALID, "lanes must be 1, the foot points per node, or 0 (staged, 3D)");
+  if (lanes != 1 && lanes != fp)
+    return fail(LSR_E_INVALID, "lanes must be 1 or the foot points per node");
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LSR_E_INVALID, "blocks_per_cu must be in 1..64");
   j->lanes = lanes;
   j->blocks_per_cu = blocks_per_cu;

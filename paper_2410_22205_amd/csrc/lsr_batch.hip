@@ -139,7 +139,6 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
       for (int q = q0; q < q1; ++q) {
         if (b->interp[q] != itp) continue;
         lsr_job* j = b->jobs[q];
-        j->bricks_valid = false;  // stepped here through the node list
         tab[m++] = plan_step<T>(j, step_const<T>(j, b->dt[q]));
       }
       B.launches.push_back({0, o, m, itp, B.group});
@@ -202,7 +201,7 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
                                     b->blocks, s);
         break;
       case 1:
-        e = launch_gbar_scan_batch<T>(b->dim, (const GbarArgs<T>*)(dev + L.off), L.n, b->blocks, s);
+        e = launch_grid_list_batch<T>(b->dim, (const GbarArgs<T>*)(dev + L.off), L.n, b->blocks, s);
         break;
       case 2:
         e = launch_reinit_fix_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n, b->blocks, s);
@@ -246,8 +245,18 @@ std::vector<int64_t> group_key(const lsr_batch* b, const Builder<T>& B) {
     k.push_back(L.interp);
     k.push_back(L.group);
     if (L.kind == 5) {
-      k.push_back((int64_t)(intptr_t)L.job);
-      k.push_back(L.phi);
+      // the energy launch bakes in the job's buffers and sizes, not the job
+      // object (a job created where a destroyed one lived may reuse its
+      // address with another workspace)
+      const lsr_job* j = L.job;
+      int64_t pb;
+      memcpy(&pb, &j->prm.p, sizeof pb);
+      k.push_back((int64_t)(intptr_t)j->phi[L.phi]);
+      k.push_back((int64_t)(intptr_t)j->d64);
+      k.push_back((int64_t)(intptr_t)j->energy_buf);
+      k.push_back((int64_t)j->dg.N);
+      k.push_back((int64_t)j->dg.n0 << 40 | (int64_t)j->dg.n1 << 20 | (int64_t)j->dg.n2);
+      k.push_back(pb);
     }
   }
   return k;
@@ -366,7 +375,6 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
         SLArgs<T> a = plan_step<T>(j, step_const<T>(j, b->dt[q]));
         restore(j, sv);
         a.cnt_out = b->scratch_cnt + 2 * q;
-        a.cnt_reset = b->scratch_cnt + 2 * q + 1;
         a.stats = b->scratch_stats;
         tab[m++] = a;
       }
@@ -552,7 +560,7 @@ lsr_status lsr_batch_add(lsr_batch* b, lsr_job* j, double dt, lsr_interp interp)
   if (!b->dim) {
     b->dim = j->grid.dim;
     b->fp64 = j->fp64;
-    if (!b->lanes) b->lanes = j->lanes ? j->lanes : 1;  // batches step through node lists
+    if (!b->lanes) b->lanes = j->lanes;
   }
   j->in_batch = true;
   j->own_stream = j->stream;

@@ -53,6 +53,15 @@ __host__ __device__ inline int bin_id(const BinGeom& bg, const int b[3]) {
 // Number of bin ids, super-bin padding included.
 inline int32_t bin_ids(const BinGeom& bg) { return bg.ns[0] * bg.ns[1] * bg.ns[2] * bg.ksup; }
 
+// Band lists are chunked: chunk c of a list holds its entries at
+// [c * LCHUNK, c * LCHUNK + ccnt[c]) of the list buffer, and the list's
+// counter slot holds its number of chunks.  A list is built in the order of
+// a scan of the grid brick by brick (ordered compaction, no atomics); each
+// step keeps the chunks of its input list and compacts every chunk in place
+// into the output list, so the order, and with it the locality of the nodes
+// a block or an XCD works on, lasts from one reinitialisation to the next.
+constexpr uint32_t LCHUNK = 256;
+
 template <typename T>
 struct SLArgs {
   DevGrid g;
@@ -60,38 +69,54 @@ struct SLArgs {
   const T* A;                       // phi^n (read only)
   T* B;                             // phi^{n+1} (written on the list)
   const typename Vec<T>::pack* dp;  // (grad d, d)
-  const uint32_t* Lin;
-  uint32_t* Lout;
-  const int32_t* cnt_in;
-  int32_t* cnt_out;
-  int32_t* cnt_reset;
+  const uint32_t* Lin;              // band list of this step (chunked)
+  uint32_t* Lout;                   // the entries updated here, chunk by chunk
+  const int32_t* ccnt_in;           // entries per chunk of Lin
+  int32_t* ccnt_out;                // entries per chunk of Lout
+  const int32_t* cnt_in;            // chunks of Lin
+  int32_t* cnt_out;                 // chunks of Lout (the same number)
   unsigned long long* stats;
   // E_p(phi^n) on the device (written by the energy kernels before the
   // step) when p != 1, else null
   const double* Ep;
-  // brick lists of the staged 3D step (bricks of 4 x 8 x 8 nodes): the input
-  // list covers every node of Lin, the output list the bricks of Lout
-  const uint32_t* BLin;
-  uint32_t* BLout;
-  const int32_t* bcnt_in;
-  int32_t* bcnt_out;
-  int32_t* bcnt_reset;
 };
 
-// Bricks of the staged 3D step.
-constexpr int BRICK_I = 4, BRICK_J = 8, BRICK_K = 8;
+// Grid scans in slots of GBAR_CHUNK nodes: in 3D a slot is GBAR_SUB bricks
+// of 4 x 8 x 8 nodes, bricks numbered in C order of their coordinates and
+// nodes in C order inside a brick; in 2D GBAR_CHUNK consecutive nodes.
+constexpr uint32_t GBAR_SUB = 8, GBAR_CHUNK = 256 * GBAR_SUB;
 
-// Gbar (the band of the step and its face neighbours) found by a scan of
-// the grid: node x belongs to it iff |P| < gamma at x or at a face neighbour,
-// with P = phi^n, the field whose band the step updated.
+__host__ __device__ inline uint32_t gbar_slots(int dim, int n0, int n1, int n2) {
+  if (dim == 3) {
+    const uint32_t nb = (uint32_t)((n0 + 3) / 4) * (uint32_t)((n1 + 7) / 8) * (uint32_t)((n2 + 7) / 8);
+    return (nb + GBAR_SUB - 1) / GBAR_SUB;
+  }
+  return ((uint32_t)n0 * (uint32_t)n1 + GBAR_CHUNK - 1) / GBAR_CHUNK;
+}
+__host__ __device__ inline uint32_t gbar_slots(const DevGrid& g) {
+  return gbar_slots(g.n2 > 1 ? 3 : 2, g.n0, g.n1, g.n2);
+}
+
+// A list from a scan of the grid: node x belongs to it iff |P| < gamma at x
+// (nbr = 0: the band) or at x or a face neighbour (nbr = 1: Gbar, the band
+// of the step and its face neighbours, with P = phi^n, the field whose band
+// the step updated).  Three launches: each slot's members in node order into
+// S at s * GBAR_CHUNK with their number in scnt[s]; the exclusive prefix of
+// the counts into soff[0 .. slots] (one block per job); every slot's members
+// copied to M at soff[s].  *cnt_out receives the length of M, or, when ccnt
+// is given, M's number of LCHUNK chunks with their entries in ccnt.
 template <typename T>
 struct GbarArgs {
   DevGrid g;
   T gamma;
+  int nbr;
   const T* P;
+  uint32_t* S;
+  int32_t* scnt;
+  int32_t* soff;
   uint32_t* M;
   int32_t* cnt_out;
-  int32_t* cnt_reset;
+  int32_t* ccnt;
 };
 
 template <typename T>
@@ -108,6 +133,8 @@ struct RArgs {
   unsigned long long* stats;
 };
 
+// Cut on Gbar (a compacted list of *cnt_in entries) and the new band list,
+// chunked: Gbar's LCHUNK-entry chunk c gives chunk c of Lout.
 template <typename T>
 struct FinArgs {
   DevGrid g;
@@ -117,8 +144,8 @@ struct FinArgs {
   T* cur;
   T* other;
   uint32_t* Lout;
+  int32_t* ccnt_out;
   int32_t* cnt_out;
-  int32_t* cnt_reset;
 };
 
 // Bounding frame of the points of one occupied bin, GEO doubles per bin at
@@ -151,6 +178,7 @@ struct DistArgs {
   double mu;              // distance margin that covers rounding (1e-12 x box diagonal)
   double mu2;             // the same for squared distances (1e-12 x diagonal^2)
   double* d64;
+  const uint8_t* bmark;   // null: every brick; else only the bricks marked 1
 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
@@ -158,28 +186,19 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* args, T gamma,
                            const T* src, T* A, T* B, int32_t* flag, hipStream_t s);
+// The first band of a job (a.nbr = 0) or Gbar (a.nbr = 1), see GbarArgs.
 template <typename T>
-hipError_t launch_band_scan(int dim, const DevGrid& g, T gamma, const T* A, uint32_t* L,
-                            int32_t* cnt, hipStream_t s);
+hipError_t launch_grid_list(int dim, const GbarArgs<T>& a, unsigned blocks, hipStream_t s);
+// mask[idx] = 1 on the nodes of the chunked list L with |A| < gamma, *count
+// += their number (mask may be null).
 template <typename T>
 hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_t* L,
-                            const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
-                            hipStream_t s);
+                            const int32_t* ccnt, const int32_t* cnt, uint8_t* mask,
+                            int32_t* count, unsigned blocks, hipStream_t s);
 // lanes: 1, or the number of foot points per node (2 in 2D, 4 in 3D).
 template <typename T>
 hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
                           hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
-// The 3D step over a brick list with phi staged in LDS (same results as
-// launch_sl_step).
-template <typename T>
-hipError_t launch_sl_step_staged(int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s);
-// Brick list (bricks holding a node of L, deduplicated through per-brick
-// stamps at `epoch`) appended to BL / bcnt.
-hipError_t launch_nodes_to_bricks(const DevGrid& g, const uint32_t* L, const int32_t* cnt,
-                                  uint32_t* bstamp, uint32_t epoch, uint32_t* BL, int32_t* bcnt,
-                                  unsigned blocks, hipStream_t s);
-template <typename T>
-hipError_t launch_gbar_scan(int dim, const GbarArgs<T>& a, unsigned blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_fix(int dim, const RArgs<T>& a, unsigned blocks, hipStream_t s);
 template <typename T>
@@ -233,12 +252,38 @@ template <typename T>
 hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,
                         hipStream_t s);
 
+// Initial data from the cloud (Section 3.6) and the approximate distance
+// (Section 3.4), lsr_init.hip.  Passes set *changed = 1 when they change a
+// node; a pass that changes nothing has reached the fixed point.
+hipError_t launch_check_points(int dim, const BinGeom& bg, const double* pts, int64_t n,
+                               int32_t* flag, hipStream_t s);
+hipError_t launch_mark_init(int dim, const DevGrid& g, const double* d, double gs, uint8_t* ext,
+                            hipStream_t s);
+hipError_t launch_mark_pass(int dim, const DevGrid& g, const double* d, double gs, uint8_t* ext,
+                            int32_t* changed, hipStream_t s);
+hipError_t launch_eik_init(const DevGrid& g, const double* v, const uint8_t* fixed, double* u,
+                           hipStream_t s);
+hipError_t launch_eik_init_ext(const DevGrid& g, const double* d, double gs, const uint8_t* ext,
+                               double* u, hipStream_t s);
+hipError_t launch_eik_pass(int dim, const DevGrid& g, double* u, const uint8_t* fixed,
+                           int32_t* changed, hipStream_t s);
+template <typename T>
+hipError_t launch_phi0_cloud(const DevGrid& g, const double* d, const double* u, const uint8_t* ext,
+                             double gs, T gamma, T* A, T* B, hipStream_t s);
+hipError_t launch_box_mark(int dim, const DevGrid& g, const double* pts, int64_t n, uint8_t* fixed,
+                           uint8_t* bmark, hipStream_t s);
+// Warm start (Section 4): src (phi on the coarser grid gc) interpolated at
+// the nodes of g (interp 0: Q1, 1: WENO), cut to [-gamma, gamma], into A, B.
+template <typename T>
+hipError_t launch_resample(int dim, int interp, const DevGrid& g, const DevGrid& gc, const T* src,
+                           T gamma, T weno_e, T* A, T* B, hipStream_t s);
+
 // Batched forms: one launch over a packed table of per-job arguments.
 template <typename T>
 hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>* tab, int n,
                                 unsigned blocks, hipStream_t s);
 template <typename T>
-hipError_t launch_gbar_scan_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
+hipError_t launch_grid_list_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
                                   hipStream_t s);
 template <typename T>
 hipError_t launch_reinit_fix_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,

@@ -27,8 +27,10 @@ lsr_status fail(lsr_status st, const std::string& msg);
 
 struct Layout {
   size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, cnt, stats;
-  size_t blist0, blist1, bstamp;  // brick lists and stamps of the staged 3D step
-  int64_t nbricks;
+  size_t ccnt0, ccnt1;  // entries per chunk of the two band lists
+  size_t scnt, soff;    // members per grid slot and their prefix (list builds)
+  size_t dmark;         // distance-kernel bricks marked for the approximate distance
+  int64_t list_cap;     // entries of a band-list buffer: chunks and grid slots
   size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo, sup, sgeo;
   size_t energy;  // energy partial sums and result
   size_t nn;      // nearest-neighbour distances of a cloud sample
@@ -53,13 +55,17 @@ struct lsr_job {
   void* phi[2];
   void* dp;
   double* d64;
-  uint32_t* list[2];
+  uint32_t* list[2];     // band lists, chunked (LCHUNK entries per chunk)
+  int32_t* ccnt[2];      // their entries per chunk
+  int32_t* scnt;         // members per grid slot of a list build
+  int32_t* soff;         // and their exclusive prefix
   uint32_t* listM;
-  uint8_t* mflags;
-  int32_t* cnt;  // [0..2] list-count ring, [3] flag, [4] extract count, [5] occupied bins,
-                 // [6] bins a cloud's points occupy (density check), [7] occupied
-                 // super-bins, [8..10] brick-count ring (staged 3D step), [11]
-                 // sample-index flag of lsr_cloud_spacing
+  uint8_t* mflags;  // reinitialisation flags; scratch of the initial-data passes
+  uint8_t* dmark;
+  int32_t* cnt;  // [0..2] list-count ring (chunks of a band list, entries of Gbar),
+                 // [3] flag, [4] extract count, [5] occupied bins, [6] bins a
+                 // cloud's points occupy (density check), [7] occupied
+                 // super-bins, [11] sample-index flag of lsr_cloud_spacing
   unsigned long long* stats;
   double* pts_raw;
   double* pts;
@@ -78,13 +84,8 @@ struct lsr_job {
   double* nn;          // max_points nearest-neighbour distances, then their mean
   int64_t n_cloud;     // points of the loaded cloud (0: none, or a given d)
   lsr::BinGeom bg_load;  // the bins the loaded cloud is sorted by
-  uint32_t* blist[2];
-  uint32_t* bstamp;
-  int cur_blist;       // brick list buffer holding the current brick list
-  uint32_t bepoch;     // stamp epoch of the last brick-list rebuild
-  bool bricks_valid;   // the current brick list covers the current node list
   unsigned list_blocks;
-  int lanes;         // step kernel: 0 staged bricks (3D), 1 one lane per node, or foot points
+  int lanes;         // step kernel: 1 one lane per node, or one per foot point
   int blocks_per_cu; // persistent grid of the list kernels: blocks_per_cu x CUs (multiple of 8)
   int ncu;
   int cur;       // phi buffer holding the current phi
@@ -125,7 +126,6 @@ StepConst<T> step_const(const lsr_job* j, double dt) {
 }
 
 inline int32_t* ring_slot(lsr_job* j, int k) { return j->cnt + ((j->ring + k) % 3); }
-inline int32_t* bring_slot(lsr_job* j, int k) { return j->cnt + 8 + ((j->ring + k) % 3); }
 
 template <typename T>
 inline T* phi_buf(lsr_job* j, int b) {
@@ -149,17 +149,12 @@ SLArgs<T> plan_step(lsr_job* j, const StepConst<T>& c) {
   a.B = phi_buf<T>(j, 1 - j->cur);
   a.Lin = j->list[j->cur_list];
   a.Lout = j->list[1 - j->cur_list];
+  a.ccnt_in = j->ccnt[j->cur_list];
+  a.ccnt_out = j->ccnt[1 - j->cur_list];
   a.cnt_in = ring_slot(j, 0);
   a.cnt_out = ring_slot(j, 1);
-  a.cnt_reset = ring_slot(j, 2);
-  a.BLin = j->blist[j->cur_blist];
-  a.BLout = j->blist[1 - j->cur_blist];
-  a.bcnt_in = bring_slot(j, 0);
-  a.bcnt_out = bring_slot(j, 1);
-  a.bcnt_reset = bring_slot(j, 2);
   j->cur = 1 - j->cur;
   j->cur_list = 1 - j->cur_list;
-  j->cur_blist = 1 - j->cur_blist;
   j->ring = (j->ring + 1) % 3;
   j->step_index += 1;
   j->n_steps += 1;
@@ -182,10 +177,14 @@ ReinitPlan<T> plan_reinit(lsr_job* j) {
   ReinitPlan<T> r;
   r.gb.g = j->dg;
   r.gb.gamma = (T)j->prm.gamma;
+  r.gb.nbr = 1;
   r.gb.P = phi_buf<T>(j, 1 - j->cur);  // phi^n: the step just taken read it
+  r.gb.S = j->list[1 - j->cur_list];   // the step's input list, no longer needed
+  r.gb.scnt = j->scnt;
+  r.gb.soff = j->soff;
   r.gb.M = j->listM;
   r.gb.cnt_out = ring_slot(j, 1);
-  r.gb.cnt_reset = ring_slot(j, 2);
+  r.gb.ccnt = nullptr;
   j->ring = (j->ring + 1) % 3;
 
   RArgs<T> ra;
@@ -216,8 +215,8 @@ ReinitPlan<T> plan_reinit(lsr_job* j) {
   r.fin.cur = phi_buf<T>(j, wf);
   r.fin.other = phi_buf<T>(j, 1 - wf);
   r.fin.Lout = j->list[j->cur_list];
+  r.fin.ccnt_out = j->ccnt[j->cur_list];
   r.fin.cnt_out = ring_slot(j, 1);
-  r.fin.cnt_reset = ring_slot(j, 2);
   j->ring = (j->ring + 1) % 3;
   j->cur = wf;
   j->n_reinits += 1;
@@ -225,6 +224,14 @@ ReinitPlan<T> plan_reinit(lsr_job* j) {
 }
 
 lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp);
+lsr_status start_loop(lsr_job* j, int64_t step0);
+
+}  // namespace lsr
+
+// Make `waiter` wait for the work queued on `signaller` so far (no host sync).
+hipError_t order_after(hipStream_t waiter, hipStream_t signaller);
+
+namespace lsr {
 lsr_status run_reinit(lsr_job* j);
 
 }  // namespace lsr

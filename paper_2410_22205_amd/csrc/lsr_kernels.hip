@@ -3,10 +3,10 @@
 //
 // Every list kernel is a grid-stride loop over a device-resident list whose
 // length it reads from device memory, so launches have a fixed shape and need
-// no host round trip.  Blocks are remapped so that each of the 8 XCDs walks a
-// contiguous stretch of the list (its own L2 then sees neighbouring nodes).
-// Lists are compacted with a wave-wide ballot, a popcount and one atomic per
-// wave.
+// no host round trip.  Each of the 8 XCDs walks a contiguous stretch of the
+// list (xcd_share), so its own L2 sees neighbouring nodes.  Lists are built
+// in the order of a brick-by-brick scan of the grid and compacted per block
+// in that order (block_compact), without atomics.
 #include <hip/hip_ext.h>
 
 #include <mutex>
@@ -17,17 +17,6 @@
 namespace lsr {
 
 // ------------------------------------------------------------------ helpers
-
-// Work distribution over a persistent grid (a multiple of 8 blocks): a list
-// is cut into chunks; chunk c is handled on XCD (c / STRIPE) % 8, where the
-// dispatcher places workgroup b on XCD b % 8, and the blocks of one XCD take
-// that XCD's chunks in turn.  Neighbouring chunks (neighbouring nodes) share
-// an L2, and every XCD gets work whatever the list length.
-constexpr uint32_t STRIPE = 4;
-
-__device__ __forceinline__ uint32_t chunk_of(uint32_t q, uint32_t xcd) {
-  return ((q / STRIPE) * 8u + xcd) * STRIPE + (q % STRIPE);
-}
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
@@ -104,6 +93,55 @@ __device__ __forceinline__ void block_add3(uint32_t a, uint32_t b, uint32_t c,
   }
 }
 
+
+// Items [0, n) shared out in contiguous stretches, one per XCD: the blocks
+// of XCD x (the dispatcher places workgroup b on XCD b mod 8) take the items
+// [x * per, min(x * per + per, n)), per = ceil(n / 8), in increasing order,
+// so that an XCD works through one stretch of a list at a time and its L2
+// holds that stretch's neighbourhood.  Sets the block's first item and the
+// stretch's end and returns the stride between the block's items.  The grid
+// is a multiple of 8 blocks.
+__device__ __forceinline__ uint32_t xcd_share(uint32_t n, uint32_t& first, uint32_t& end) {
+  const uint32_t per = (n + 7u) / 8u, beg = (blockIdx.x % 8u) * per;
+  end = min(beg + per, n);
+  first = beg + blockIdx.x / 8u;
+  return gridDim.x / 8u;
+}
+
+// Block-wide ordered compaction (256 threads, called by all of them): the
+// values of the lanes with pred set go to out[0 ..) ordered by (q, wave,
+// lane), q the index of the value in the thread; returns their number.  No
+// atomics: the order is the order of the block's nodes.  lds holds at least
+// 4 K + 1 ints.
+template <int K>
+__device__ __forceinline__ int block_compact(const bool (&pred)[K], const uint32_t (&val)[K],
+                                             gwptr<uint32_t> out, int* lds) {
+  uint64_t m[K];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    m[q] = __ballot(pred[q]);
+    if (lane_id() == 0) lds[q * 4 + w] = (int)__popcll(m[q]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int e = 0; e < 4 * K; ++e) {
+      const int c = lds[e];
+      lds[e] = run;
+      run += c;
+    }
+    lds[4 * K] = run;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < K; ++q)
+    if (pred[q]) out[lds[q * 4 + w] + (int)lanes_below(m[q])] = val[q];
+  const int tot = lds[4 * K];
+  __syncthreads();
+  return tot;
+}
+
 // ------------------------------------------------------------------ fills
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
@@ -165,143 +203,6 @@ __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2,
   }
 }
 
-// First band {|phi| < gamma} from a scan of the whole grid.
-template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_band_scan(DevGrid g, T gamma, const T* __restrict__ A,
-                                                   uint32_t* __restrict__ L, int32_t* cnt) {
-  __shared__ int lds[8];
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * 256u;
-    if (base >= g.N) break;
-    const uint32_t idx = base + threadIdx.x;
-    bool in = false;
-    uint32_t code = 0;
-    if (idx < g.N) {
-      in = fabs(A[idx]) < gamma;
-      uint32_t r = idx;
-      int k = 0;
-      if (DIM == 3) {
-        k = (int)(r % (uint32_t)g.n2);
-        r /= (uint32_t)g.n2;
-      }
-      code = encode(g, (int)(r / (uint32_t)g.n1), (int)(r % (uint32_t)g.n1), k);
-    }
-    block_append1(in, code, (gwptr<uint32_t>)L, cnt, lds);
-  }
-}
-
-// Band mask of the current list: mask[idx] = 1 iff |phi| < gamma.
-template <typename T>
-__global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* __restrict__ A,
-                                                   const uint32_t* __restrict__ L,
-                                                   const int32_t* cnt, uint8_t* __restrict__ mask,
-                                                   int32_t* count) {
-  __shared__ uint32_t lds[12];
-  const int n = *cnt;
-  uint32_t tot = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * 256u;
-    if (base >= (uint32_t)n) break;
-    const uint32_t e = base + threadIdx.x;
-    bool in = false;
-    if (e < (uint32_t)n) {
-      int i, j, k;
-      decode(g, L[e], i, j, k);
-      const uint32_t idx = lin(g, i, j, k);
-      in = fabs(A[idx]) < gamma;
-      if (in && mask) mask[idx] = 1;
-    }
-    tot += wave_count(in);
-  }
-  __syncthreads();
-  if (lane_id() == 0) lds[threadIdx.x >> 6] = tot;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t t = lds[0] + lds[1] + lds[2] + lds[3];
-    if (t) atomicAdd(count, (int)t);
-  }
-}
-
-// ---------------------------------------------------------- the SL step
-
-// One time step over the current list: entries with |phi^n| < gamma get the
-// update of eqs. (SL2d)/(SL3d) written to B; entries that left the band in
-// the previous step get their value copied, so that A and B agree off the
-// new list.  The new list is the set of entries updated here (the band of
-// this step).  cnt_reset is the list counter the next step will write.
-// LANES lanes share one entry (see sl_update).
-//
-// Each kernel below is a per-chunk body (one block, CH consecutive list
-// entries) driven either over one job's list or, in the batched kernels, over
-// the chunks of all jobs of the table numbered one after the other: every
-// block takes global chunk numbers in increasing order, XCD-striped as in the
-// single-job kernels, and follows them from job to job, so that blocks start
-// on different jobs and no block idles while another works through the jobs.
-
-// The step's constants, with 1 / E_p(phi^n) from the device when p != 1
-// (E_p = 0, no front, stops the motion: C = 0).
-template <typename T>
-__device__ __forceinline__ StepConst<T> step_consts(const SLArgs<T>& a) {
-  StepConst<T> c = a.c;
-  if (a.Ep) {
-    const double E = *a.Ep;
-    c.inv_E = E > 0.0 ? (T)(1.0 / E) : T(0);
-  }
-  return c;
-}
-
-template <int DIM, int INTERP, typename T, int LANES>
-__device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t base, int n, int* lds_app,
-                                         uint32_t& nupd, uint32_t& nfb, uint32_t& nfr) {
-  const gptr<T> A = (gptr<T>)a.A;
-  const gwptr<T> B = (gwptr<T>)a.B;
-  const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
-  const gptr<uint32_t> Lin = (gptr<uint32_t>)a.Lin;
-  const int sub = (int)(threadIdx.x % LANES);
-  const uint32_t e = base + threadIdx.x / LANES;
-  bool act = false;
-  int fl = 0;
-  uint32_t code = 0;
-  if (e < (uint32_t)n) {
-    code = Lin[e];
-    int i, j, k;
-    decode(a.g, code, i, j, k);
-    const uint32_t idx = lin(a.g, i, j, k);
-    const T v = A[idx];
-    T nv = v;
-    if (fabs(v) < a.c.gamma) {
-      act = true;
-      nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, step_consts(a), i, j, k, idx, v, DP[idx], sub,
-                                            fl);
-    }
-    if (sub == 0) B[idx] = nv;
-  }
-  const bool lead = act && sub == 0;
-  block_append1(lead, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds_app);
-  nupd += wave_count(lead);
-  nfb += wave_count(sub == 0 && (fl & UPD_FALLBACK));
-  nfr += wave_count(sub == 0 && (fl & UPD_FRAME0));
-}
-
-template <int DIM, int INTERP, typename T, int LANES>
-__global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
-  constexpr uint32_t CH = 256 / LANES;  // entries per block and chunk
-  __shared__ int lds_app[8];
-  __shared__ uint32_t lds_st[12];
-  const int n = *a.cnt_in;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
-  uint32_t nupd = 0, nfb = 0, nfr = 0;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * CH;
-    if (base >= (uint32_t)n) break;
-    sl_chunk<DIM, INTERP, T, LANES>(a, base, n, lds_app, nupd, nfb, nfr);
-  }
-  block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
-}
-
 // A table entry read with scalar loads into scalar registers, as kernel
 // arguments are: the table is read through the constant address space (the
 // host writes it before the launch and nothing writes it during one) at a
@@ -320,300 +221,94 @@ __device__ __forceinline__ A uniform_load(const A* tab, int index) {
   return out;
 }
 
-// ---------------------------------------------- the staged 3D step (bricks)
-
-#ifndef LSR_GBAR_BRICK_ORDER
-#define LSR_GBAR_BRICK_ORDER 1
-#endif
-#ifndef LSR_STAGE_HALO_F32
-#define LSR_STAGE_HALO_F32 6
-#endif
-#ifndef LSR_STAGE_HALO_F64
-#define LSR_STAGE_HALO_F64 5
-#endif
-
-// Rows of phi^n from a tile staged in LDS: the box of virtual node indices
-// [oi, oi + RI) x [oj, oj + RJ) x [ok, ok + RK), each entry holding phi at the
-// index clamped to the grid (the boundary node repeated), so reading the tile
-// gives exactly what the clamped reads of device memory give.
-template <typename T, int RJ, int RK>
-struct TileRows {
-  const T* tile;
-  int oi, oj, ok;
-  __device__ __forceinline__ typename Vec<T>::v4 w4(int ii, int jj, int k0) const {
-    const T* p = tile + ((ii - oi) * RJ + (jj - oj)) * RK + (k0 - 1 - ok);
-    typename Vec<T>::v4 r;
-    r.x = p[0];
-    r.y = p[1];
-    r.z = p[2];
-    r.w = p[3];
-    return r;
-  }
-  __device__ __forceinline__ typename Vec<T>::v2 w2(int ii, int jj, int k0) const {
-    const T* p = tile + ((ii - oi) * RJ + (jj - oj)) * RK + (k0 - ok);
-    typename Vec<T>::v2 r;
-    r.x = p[0];
-    r.y = p[1];
-    return r;
-  }
-};
-
-// phi^n for the node update of one node of a staged brick: neighbours from
-// the tile; a foot point whose whole stencil lies in the tile is interpolated
-// from it, any other from device memory.
-template <int INTERP, typename T, int H>
-struct StagedSrc {
-  static constexpr int RI = BRICK_I + 2 * H, RJ = BRICK_J + 2 * H, RK = BRICK_K + 2 * H;
-  const T* tile;
-  int oi, oj, ok;
-  int tn;  // tile index of the node
-  GlobalSrc<3, INTERP, T> glob;
-  // the tile holds the clamped values: off the grid it reads the node itself
-  __device__ __forceinline__ T nb(uint32_t, bool, int di, int dj, int dk) const {
-    return tile[tn + (di * RJ + dj) * RK + dk];
-  }
-  __device__ __forceinline__ T foot3(const Loc<T>& lx, const Loc<T>& ly, const Loc<T>& lz) const {
-    constexpr int lo = INTERP == 0 ? 0 : 1, hi = INTERP == 0 ? 1 : 2;  // stencil reach
-    const bool in = lx.i0 - lo >= oi && lx.i0 + hi < oi + RI && ly.i0 - lo >= oj &&
-                    ly.i0 + hi < oj + RJ && lz.i0 - lo >= ok && lz.i0 + hi < ok + RK;
-    if (in) {
-      const TileRows<T, RJ, RK> r{tile, oi, oj, ok};
-      return INTERP == 0 ? interp_q1_3(r, lx, ly, lz) : interp_weno3(r, lx, ly, lz, glob.e);
-    }
-    return glob.foot3(lx, ly, lz);
-  }
-  __device__ __forceinline__ T foot2(const Loc<T>& lx, const Loc<T>& ly) const {
-    return glob.foot2(lx, ly);
-  }
-};
-
-// One time step over a list of bricks (4 x 8 x 8 nodes, one thread per node):
-// phi^n on the brick and a halo of H nodes is staged in LDS with coalesced
-// reads, then every node of the brick with |phi^n| < gamma gets the update of
-// k_sl_step (the same arithmetic on the same values) and every other node of
-// the brick is copied to B.  The next node list holds the updated nodes, the
-// next brick list the bricks that had one.
-template <int INTERP, typename T, int H>
-__global__ __launch_bounds__(256) void k_sl_step_staged(SLArgs<T> a) {
-  constexpr int RI = BRICK_I + 2 * H, RJ = BRICK_J + 2 * H, RK = BRICK_K + 2 * H;
-  constexpr int RJK = RJ * RK, RN = RI * RJK;
-  // index steps of the staging loop (r += 256)
-  constexpr int DI = 256 / RJK, DJ = (256 % RJK) / RK, DK = 256 % RK;
-  __shared__ T tile[RN];
-  __shared__ int lds_app[8];
-  __shared__ uint32_t lds_st[12];
-  __shared__ int wave_act[4];
-  __shared__ uint16_t act_ids[256];
-  const DevGrid& g = a.g;
-  const gptr<T> A = (gptr<T>)a.A;
-  const gwptr<T> B = (gwptr<T>)a.B;
-  const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
-  const gptr<uint32_t> BLin = (gptr<uint32_t>)a.BLin;
-  const int nbr = *a.bcnt_in;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *a.cnt_reset = 0;
-    *a.bcnt_reset = 0;
-  }
-  const uint32_t nbj = ((uint32_t)g.n1 + BRICK_J - 1) / BRICK_J;
-  const uint32_t nbk = ((uint32_t)g.n2 + BRICK_K - 1) / BRICK_K;
-  const int t = (int)threadIdx.x, w = t >> 6;
-  const int ri0 = t / RJK, rj0 = (t % RJK) / RK, rk0 = t % RK;
-  uint32_t nupd = 0, nfb = 0, nfr = 0;
-  for (int q = blockIdx.x; q < nbr; q += gridDim.x) {
-    const uint32_t br = BLin[q];
-    const int bi = (int)(br / (nbj * nbk)), bj = (int)((br / nbk) % nbj), bk = (int)(br % nbk);
-    const int oi = bi * BRICK_I - H, oj = bj * BRICK_J - H, ok = bk * BRICK_K - H;
-    __syncthreads();  // the previous brick's tile and ids are no longer read
-    {
-      int ri = ri0, rj = rj0, rk = rk0;
-      for (int r = t; r < RN; r += 256) {
-        tile[r] = A[lin(g, clampi(oi + ri, g.n0), clampi(oj + rj, g.n1), clampi(ok + rk, g.n2))];
-        rk += DK;
-        const int ck = rk >= RK;
-        rk -= ck * RK;
-        rj += DJ + ck;
-        const int cj = rj >= RJ;
-        rj -= cj * RJ;
-        ri += DI + cj;
-      }
-    }
-    __syncthreads();
-    // the brick's node t: copied to B unless it is in the band; band nodes
-    // are packed into the first lanes of the block for the update
-    const int li = t / (BRICK_J * BRICK_K), lj = (t / BRICK_K) % BRICK_J, lk = t % BRICK_K;
-    const int i = bi * BRICK_I + li, j = bj * BRICK_J + lj, k = bk * BRICK_K + lk;
-    const bool valid = i < g.n0 && j < g.n1 && k < g.n2;
-    const int tn = ((i - oi) * RJ + (j - oj)) * RK + (k - ok);
-    const T v = valid ? tile[tn] : T(0);
-    const bool band = valid && fabs(v) < a.c.gamma;
-    if (valid && !band) B[lin(g, i, j, k)] = v;
-    const uint64_t m = __ballot(band);
-    if ((t & 63) == 0) wave_act[w] = (int)__popcll(m);
-    __syncthreads();
-    int off = 0, tot = 0;
+// One field (at byte offset off) of table entry `index`, read the same way.
+template <typename F, typename A>
+__device__ __forceinline__ F uniform_field(const A* tab, int index, size_t off) {
+  static_assert(sizeof(F) % 4 == 0, "fields are whole words");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  const int q = __builtin_amdgcn_readfirstlane(index);
+  cword* src = (cword*)((const char*)(tab + q) + off);
+  F out;
+  uint32_t* dst = (uint32_t*)&out;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      off += u < w ? wave_act[u] : 0;
-      tot += wave_act[u];
-    }
-    if (band) act_ids[off + (int)lanes_below(m)] = (uint16_t)t;
-    __syncthreads();
-    bool act = false;
-    int fl = 0;
-    uint32_t code = 0;
-    if (t < tot) {
-      const int u = act_ids[t];
-      const int ui = u / (BRICK_J * BRICK_K), uj = (u / BRICK_K) % BRICK_J, uk = u % BRICK_K;
-      const int i2 = bi * BRICK_I + ui, j2 = bj * BRICK_J + uj, k2 = bk * BRICK_K + uk;
-      const int tn2 = ((i2 - oi) * RJ + (j2 - oj)) * RK + (k2 - ok);
-      const uint32_t idx = lin(g, i2, j2, k2);
-      act = true;
-      code = encode(g, i2, j2, k2);
-      const StagedSrc<INTERP, T, H> src{tile, oi, oj, ok, tn2,
-                                        GlobalSrc<3, INTERP, T>{A, g, a.c.weno_e}};
-      B[idx] = sl_update_src<3, T, 1>(src, g, step_consts(a), i2, j2, k2, idx, tile[tn2], DP[idx], 0,
-                                      fl);
-    }
-    block_append1(act, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds_app);
-    if (t == 0 && tot > 0) a.BLout[atomicAdd(a.bcnt_out, 1)] = br;
-    nupd += wave_count(act);
-    nfb += wave_count(fl & UPD_FALLBACK);
-    nfr += wave_count(fl & UPD_FRAME0);
-  }
-  block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
+  for (unsigned w = 0; w < sizeof(F) / 4; ++w) dst[w] = src[w];
+  return out;
+}
+#define LSR_FIELD(tab, jb, Type, field) \
+  uniform_field<decltype(Type::field)>(tab, jb, offsetof(Type, field))
+
+// Chunks of one job in a launch: band-list chunks (step), grid slots (list
+// builds), LCHUNK-entry chunks of Gbar (reinitialisation).
+template <typename T>
+__device__ __forceinline__ uint32_t job_chunks(const SLArgs<T>* tab, int jb) {
+  return (uint32_t)*LSR_FIELD(tab, jb, SLArgs<T>, cnt_in);
+}
+template <typename T>
+__device__ __forceinline__ uint32_t job_chunks(const GbarArgs<T>* tab, int jb) {
+  return gbar_slots(LSR_FIELD(tab, jb, GbarArgs<T>, g));
+}
+template <typename T>
+__device__ __forceinline__ uint32_t job_chunks(const RArgs<T>* tab, int jb) {
+  return ((uint32_t)*LSR_FIELD(tab, jb, RArgs<T>, cnt) + LCHUNK - 1) / LCHUNK;
+}
+template <typename T>
+__device__ __forceinline__ uint32_t job_chunks(const FinArgs<T>* tab, int jb) {
+  return ((uint32_t)*LSR_FIELD(tab, jb, FinArgs<T>, cnt_in) + LCHUNK - 1) / LCHUNK;
 }
 
-// Bricks holding a node of the list L (each once: per-brick stamps).
-__global__ __launch_bounds__(256) void k_nodes_to_bricks(DevGrid g, const uint32_t* __restrict__ L,
-                                                         const int32_t* cnt, uint32_t* bstamp,
-                                                         uint32_t epoch, uint32_t* BL,
-                                                         int32_t* bcnt) {
-  __shared__ int lds[8];
-  const int n = *cnt;
-  const uint32_t nbj = ((uint32_t)g.n1 + BRICK_J - 1) / BRICK_J;
-  const uint32_t nbk = ((uint32_t)g.n2 + BRICK_K - 1) / BRICK_K;
-  for (uint32_t base = blockIdx.x * 256u; base < (uint32_t)n; base += gridDim.x * 256u) {
-    const uint32_t e = base + threadIdx.x;
-    bool fresh = false;
-    uint32_t br = 0;
-    if (e < (uint32_t)n) {
-      int i, j, k;
-      decode(g, L[e], i, j, k);
-      br = ((uint32_t)(i / BRICK_I) * nbj + (uint32_t)(j / BRICK_J)) * nbk + (uint32_t)(k / BRICK_K);
-      fresh = atomicMax(&bstamp[br], epoch) < epoch;
-    }
-    block_append1(fresh, br, (gwptr<uint32_t>)BL, bcnt, lds);
-  }
+template <typename A>
+__device__ __forceinline__ uint32_t total_chunks(const A* tab, int n) {
+  uint32_t t = 0;
+  for (int jb = 0; jb < n; ++jb) t += job_chunks(tab, jb);
+  return t;
 }
 
-// Grid nodes covered by the chunks of the Gbar scan.
-template <int DIM>
-__device__ __forceinline__ uint32_t gbar_extent(const DevGrid& g) {
-#if LSR_GBAR_BRICK_ORDER
-  if (DIM == 3)
-    return ((uint32_t)g.n0 + 3u) / 4u * (((uint32_t)g.n1 + 7u) / 8u) * (((uint32_t)g.n2 + 7u) / 8u) *
-           256u;
-#endif
-  return g.N;
-}
-
-// Cursor of a block over the jobs of a batched launch: job jb holds the
-// global chunks [beg, end) and nl list entries.  advance() moves to the job
-// holding chunk gch and returns false once gch lies past the last job; on
-// every job change it calls leave(jb) for the job being left (uniform across
-// the block).  Only these integers are carried from chunk to chunk; the
-// job's arguments are read again for every chunk (into scalar registers).
+// Cursor of a block over the jobs of a batched launch, whose chunks are
+// numbered one job after the other: job jb holds the global chunks
+// [beg, end).  advance() moves to the job holding chunk gch (gch never
+// decreases) and returns false once gch lies past the last job; on every job
+// change it calls leave(jb) for the job being left (uniform across the
+// block).
 struct JobCursor {
-  int n, jb = -1, nl = 0;
+  int n, jb = -1;
   uint32_t beg = 0, end = 0;
   template <typename A, typename Leave>
-  __device__ __forceinline__ bool advance(const A* tab, uint32_t gch, uint32_t ch, Leave leave) {
+  __device__ __forceinline__ bool advance(const A* tab, uint32_t gch, Leave leave) {
     while (gch >= end) {
       if (jb >= 0) leave(jb);
       if (++jb >= n) return false;
-      nl = __builtin_amdgcn_readfirstlane(count(uniform_load(tab, jb)));
       beg = end;
-      end = beg + ((uint32_t)nl + ch - 1) / ch;
+      end = beg + job_chunks(tab, jb);
     }
     return true;
   }
-  // list entries of a job, or grid nodes for the Gbar scan
-  static __device__ __forceinline__ int count(const SLArgs<float>& x) { return *x.cnt_in; }
-  static __device__ __forceinline__ int count(const SLArgs<double>& x) { return *x.cnt_in; }
-  static __device__ __forceinline__ int count(const GbarArgs<float>& x) {
-    return (int)(x.g.n2 > 1 ? gbar_extent<3>(x.g) : gbar_extent<2>(x.g));
-  }
-  static __device__ __forceinline__ int count(const GbarArgs<double>& x) {
-    return (int)(x.g.n2 > 1 ? gbar_extent<3>(x.g) : gbar_extent<2>(x.g));
-  }
-  static __device__ __forceinline__ int count(const RArgs<float>& x) { return *x.cnt; }
-  static __device__ __forceinline__ int count(const RArgs<double>& x) { return *x.cnt; }
-  static __device__ __forceinline__ int count(const FinArgs<float>& x) { return *x.cnt_in; }
-  static __device__ __forceinline__ int count(const FinArgs<double>& x) { return *x.cnt_in; }
 };
 
-// Batched step for the jobs of one interpolator (one launch per interpolator,
-// so that each kernel keeps its own register count and resident grid).
-template <int DIM, int INTERP, typename T, int LANES>
-__global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab, int n) {
-  constexpr uint32_t CH = 256 / LANES;
-  __shared__ int lds_app[8];
-  __shared__ uint32_t lds_st[12];
-  if (blockIdx.x == 0)
-    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
-  uint32_t nupd = 0, nfb = 0, nfr = 0;
-  JobCursor cur{n};
-  auto leave = [&](int jb) {
-    const SLArgs<T> a = uniform_load(tab, jb);
-    block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
-    nupd = nfb = nfr = 0;
-  };
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t gch = chunk_of(q, xcd);
-    if (!cur.advance(tab, gch, CH, leave)) break;
-    sl_chunk<DIM, INTERP, T, LANES>(uniform_load(tab, cur.jb), (gch - cur.beg) * CH, cur.nl,
-                                    lds_app, nupd, nfb, nfr);
-  }
-}
-
-// ------------------------------------------------------- reinitialisation
-
-// Gbar = band + face neighbours, by a scan of 256 consecutive grid nodes per
-// chunk (the band of the step is {|phi^n| < gamma}).
-// One chunk of the Gbar scan: 4 sub-chunks of 256 nodes (in 3D, 4 bricks of
-// 4 x 8 x 8 nodes in local order), one node of each per thread, the values
-// read together and the members appended in node order with one atomic.
-#ifndef LSR_GBAR_SUB
-#define LSR_GBAR_SUB 8
-#endif
-constexpr uint32_t GBAR_SUB = LSR_GBAR_SUB, GBAR_CHUNK = 256 * GBAR_SUB;
-
+// Grid nodes of one slot of a grid scan (GBAR_CHUNK nodes; see GbarArgs):
+// thread t's node of sub-slot u (in 3D brick sub = slot * GBAR_SUB + u, a
+// wave per 8 x 8 plane of the brick).  False past the grid.
 template <int DIM>
-__device__ __forceinline__ bool gbar_node(const DevGrid& g, uint32_t sub, int& i, int& j, int& k) {
-#if LSR_GBAR_BRICK_ORDER
+__device__ __forceinline__ bool slot_node(const DevGrid& g, uint32_t slot, uint32_t u, int& i,
+                                          int& j, int& k) {
   if (DIM == 3) {
+    const uint32_t sub = slot * GBAR_SUB + u;
     const uint32_t nbj = ((uint32_t)g.n1 + 7u) / 8u, nbk = ((uint32_t)g.n2 + 7u) / 8u;
     i = (int)((sub / (nbj * nbk)) * 4u + threadIdx.x / 64u);
     j = (int)(((sub / nbk) % nbj) * 8u + (threadIdx.x / 8u) % 8u);
     k = (int)((sub % nbk) * 8u + threadIdx.x % 8u);
     return i < g.n0 && j < g.n1 && k < g.n2;
   }
-#endif
-  const uint32_t idx = sub * 256u + threadIdx.x;
-  uint32_t r = idx;
+  const uint32_t idx = slot * GBAR_CHUNK + u * 256u + threadIdx.x;
   k = 0;
-  if (DIM == 3) {
-    k = (int)(r % (uint32_t)g.n2);
-    r /= (uint32_t)g.n2;
-  }
-  i = (int)(r / (uint32_t)g.n1);
-  j = (int)(r % (uint32_t)g.n1);
+  i = (int)(idx / (uint32_t)g.n1);
+  j = (int)(idx % (uint32_t)g.n1);
   return idx < g.N;
 }
 
+// Members of one slot, in node order, to S at slot * GBAR_CHUNK; their
+// number to scnt[slot].
 template <int DIM, typename T>
-__device__ __forceinline__ void gbar_chunk(const GbarArgs<T>& a, uint32_t base, int* lds) {
+__device__ __forceinline__ void grid_slot(const GbarArgs<T>& a, uint32_t slot, int* lds) {
   const gptr<T> P = (gptr<T>)a.P;
   bool in[GBAR_SUB];
   uint32_t code[GBAR_SUB];
@@ -622,52 +317,271 @@ __device__ __forceinline__ void gbar_chunk(const GbarArgs<T>& a, uint32_t base, 
     int i, j, k;
     in[u] = false;
     code[u] = 0;
-    if (gbar_node<DIM>(a.g, base / 256u + u, i, j, k)) {
+    if (slot_node<DIM>(a.g, slot, u, i, j, k)) {
       const uint32_t idx = lin(a.g, i, j, k);
-      // all seven values (a neighbour off the grid reads the node itself)
-      const T v0 = P[idx];
-      const T xm = P[i > 0 ? idx - a.g.s0 : idx], xp = P[i < a.g.n0 - 1 ? idx + a.g.s0 : idx];
-      const T ym = P[j > 0 ? idx - a.g.s1 : idx], yp = P[j < a.g.n1 - 1 ? idx + a.g.s1 : idx];
-      T m = fmin(fmin(fabs(v0), fmin(fabs(xm), fabs(xp))), fmin(fabs(ym), fabs(yp)));
-      if (DIM == 3) {
-        const T zm = P[k > 0 ? idx - 1 : idx], zp = P[k < a.g.n2 - 1 ? idx + 1 : idx];
-        m = fmin(m, fmin(fabs(zm), fabs(zp)));
+      T m = fabs(P[idx]);
+      if (a.nbr) {
+        // the six neighbours (a neighbour off the grid reads the node itself)
+        const T xm = P[i > 0 ? idx - a.g.s0 : idx], xp = P[i < a.g.n0 - 1 ? idx + a.g.s0 : idx];
+        const T ym = P[j > 0 ? idx - a.g.s1 : idx], yp = P[j < a.g.n1 - 1 ? idx + a.g.s1 : idx];
+        m = fmin(fmin(m, fmin(fabs(xm), fabs(xp))), fmin(fabs(ym), fabs(yp)));
+        if (DIM == 3) {
+          const T zm = P[k > 0 ? idx - 1 : idx], zp = P[k < a.g.n2 - 1 ? idx + 1 : idx];
+          m = fmin(m, fmin(fabs(zm), fabs(zp)));
+        }
       }
       in[u] = m < a.gamma;
       code[u] = encode(a.g, i, j, k);
     }
   }
-  block_append<GBAR_SUB>(in, code, (gwptr<uint32_t>)a.M, a.cnt_out, lds);
+  const int tot = block_compact<GBAR_SUB>(in, code, (gwptr<uint32_t>)a.S + slot * GBAR_CHUNK, lds);
+  if (threadIdx.x == 0) a.scnt[slot] = tot;
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_gbar_scan(GbarArgs<T> a) {
-  __shared__ int lds[8];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
-  const uint32_t ext = gbar_extent<DIM>(a.g);
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * GBAR_CHUNK;
-    if (base >= ext) break;
-    gbar_chunk<DIM, T>(a, base, lds);
-  }
+__global__ __launch_bounds__(256) void k_grid_scan(GbarArgs<T> a) {
+  __shared__ int lds[4 * GBAR_SUB + 1];
+  uint32_t c, end;
+  const uint32_t step = xcd_share(gbar_slots(a.g), c, end);
+  for (; c < end; c += step) grid_slot<DIM, T>(a, c, lds);
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_gbar_scan_batch(const GbarArgs<T>* __restrict__ tab,
+__global__ __launch_bounds__(256) void k_grid_scan_batch(const GbarArgs<T>* __restrict__ tab,
                                                          int n) {
-  __shared__ int lds[8];
-  if (blockIdx.x == 0)
-    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+  __shared__ int lds[4 * GBAR_SUB + 1];
   JobCursor cur{n};
   auto leave = [](int) {};
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t gch = chunk_of(q, xcd);
-    if (!cur.advance(tab, gch, GBAR_CHUNK, leave)) break;
-    gbar_chunk<DIM, T>(uniform_load(tab, cur.jb), (gch - cur.beg) * GBAR_CHUNK, lds);
+  uint32_t c, end;
+  const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
+  for (; c < end; c += step) {
+    if (!cur.advance(tab, c, leave)) break;
+    grid_slot<DIM, T>(uniform_load(tab, cur.jb), c - cur.beg, lds);
   }
 }
+
+// Exclusive prefix of the slot counts (one block of 1024 threads per job):
+// thread t sums a run of consecutive slots, the block scans the 1024 sums.
+template <typename T>
+__device__ __forceinline__ void slot_prefix(const GbarArgs<T>& a, int* lds) {
+  const uint32_t G = gbar_slots(a.g);
+  const uint32_t per = (G + 1023u) / 1024u;
+  const uint32_t t = threadIdx.x, b0 = min(t * per, G), b1 = min(b0 + per, G);
+  int s = 0;
+  for (uint32_t u = b0; u < b1; ++u) s += a.scnt[u];
+  // inclusive scan within the wave, then over the 16 wave totals
+  const int lane = (int)lane_id(), w = (int)(t >> 6);
+  int x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int q = 0; q < 16; ++q) {
+      const int c = lds[q];
+      lds[q] = run;
+      run += c;
+    }
+    lds[16] = run;
+  }
+  __syncthreads();
+  int run = lds[w] + x - s;
+  for (uint32_t u = b0; u < b1; ++u) {
+    a.soff[u] = run;
+    run += a.scnt[u];
+  }
+  const int total = lds[16];
+  if (t == 0) {
+    a.soff[G] = total;
+    *a.cnt_out = a.ccnt ? (int)((total + (int)LCHUNK - 1) / (int)LCHUNK) : total;
+  }
+  if (a.ccnt) {
+    const int nc = (total + (int)LCHUNK - 1) / (int)LCHUNK;
+    for (int c = (int)t; c < nc; c += 1024) a.ccnt[c] = min((int)LCHUNK, total - c * (int)LCHUNK);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_slot_prefix(GbarArgs<T> a) {
+  __shared__ int lds[17];
+  slot_prefix<T>(a, lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_slot_prefix_batch(const GbarArgs<T>* __restrict__ tab) {
+  __shared__ int lds[17];
+  slot_prefix<T>(uniform_load(tab, (int)blockIdx.x), lds);
+}
+
+// Every slot's members to their place in M.
+template <typename T>
+__device__ __forceinline__ void slot_pack(const GbarArgs<T>& a, uint32_t slot) {
+  const int n = a.scnt[slot], o = a.soff[slot];
+  const gptr<uint32_t> S = (gptr<uint32_t>)a.S + slot * GBAR_CHUNK;
+  const gwptr<uint32_t> M = (gwptr<uint32_t>)a.M + o;
+  for (int r = (int)threadIdx.x; r < n; r += 256) M[r] = S[r];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_slot_pack(GbarArgs<T> a) {
+  uint32_t c, end;
+  const uint32_t step = xcd_share(gbar_slots(a.g), c, end);
+  for (; c < end; c += step) slot_pack<T>(a, c);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_slot_pack_batch(const GbarArgs<T>* __restrict__ tab,
+                                                         int n) {
+  JobCursor cur{n};
+  auto leave = [](int) {};
+  uint32_t c, end;
+  const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
+  for (; c < end; c += step) {
+    if (!cur.advance(tab, c, leave)) break;
+    slot_pack<T>(uniform_load(tab, cur.jb), c - cur.beg);
+  }
+}
+
+// Band mask of the current list: mask[idx] = 1 iff |phi| < gamma.
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* __restrict__ A,
+                                                   const uint32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ ccnt,
+                                                   const int32_t* cnt, uint8_t* __restrict__ mask,
+                                                   int32_t* count) {
+  __shared__ uint32_t lds[12];
+  uint32_t tot = 0;
+  uint32_t c, end;
+  const uint32_t step = xcd_share((uint32_t)*cnt, c, end);
+  for (; c < end; c += step) {
+    bool in = false;
+    if ((int)threadIdx.x < ccnt[c]) {
+      int i, j, k;
+      decode(g, L[c * LCHUNK + threadIdx.x], i, j, k);
+      const uint32_t idx = lin(g, i, j, k);
+      in = fabs(A[idx]) < gamma;
+      if (in && mask) mask[idx] = 1;
+    }
+    tot += wave_count(in);
+  }
+  __syncthreads();
+  if (lane_id() == 0) lds[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = lds[0] + lds[1] + lds[2] + lds[3];
+    if (t) atomicAdd(count, (int)t);
+  }
+}
+
+// ---------------------------------------------------------- the SL step
+
+// One time step over the current band list: entries with |phi^n| < gamma get
+// the update of eqs. (SL2d)/(SL3d) written to B; entries that left the band
+// in the previous step get their value copied, so that A and B agree off
+// the new list.  The new list is the set of entries updated here (the band
+// of this step), chunk c of Lin compacted into chunk c of Lout.  LANES lanes
+// share one entry (see sl_update).
+//
+// Each kernel below is a per-chunk body (one block, one chunk) driven either
+// over one job's list or, in the batched kernels, over the chunks of all
+// jobs of the table numbered one after the other; in both the chunks are
+// shared out in contiguous stretches, one per XCD (xcd_share).
+
+// The step's constants, with 1 / E_p(phi^n) from the device when p != 1
+// (E_p = 0, no front, stops the motion: C = 0).
+template <typename T>
+__device__ __forceinline__ StepConst<T> step_consts(const SLArgs<T>& a) {
+  StepConst<T> c = a.c;
+  if (a.Ep) {
+    const double E = *a.Ep;
+    c.inv_E = E > 0.0 ? (T)(1.0 / E) : T(0);
+  }
+  return c;
+}
+
+template <int DIM, int INTERP, typename T, int LANES>
+__device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t c, int* lds,
+                                         uint32_t& nupd, uint32_t& nfb, uint32_t& nfr) {
+  constexpr int CH = (int)LCHUNK / LANES;  // entries per round of the block
+  const gptr<T> A = (gptr<T>)a.A;
+  const gwptr<T> B = (gwptr<T>)a.B;
+  const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
+  const gptr<uint32_t> Lin = (gptr<uint32_t>)a.Lin + c * LCHUNK;
+  const gwptr<uint32_t> Lout = (gwptr<uint32_t>)a.Lout + c * LCHUNK;
+  const int nc = a.ccnt_in[c];
+  const int sub = (int)(threadIdx.x % LANES);
+  int kept = 0;
+  for (int r = 0; r < LANES && r * CH < nc; ++r) {
+    const int le = r * CH + (int)(threadIdx.x / LANES);
+    bool act = false;
+    int fl = 0;
+    uint32_t code = 0;
+    if (le < nc) {
+      code = Lin[le];
+      int i, j, k;
+      decode(a.g, code, i, j, k);
+      const uint32_t idx = lin(a.g, i, j, k);
+      const T v = A[idx];
+      T nv = v;
+      if (fabs(v) < a.c.gamma) {
+        act = true;
+        nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, step_consts(a), i, j, k, idx, v, DP[idx],
+                                              sub, fl);
+      }
+      if (sub == 0) B[idx] = nv;
+    }
+    const bool lead = act && sub == 0;
+    const bool p1[1] = {lead};
+    const uint32_t v1[1] = {code};
+    kept += block_compact<1>(p1, v1, Lout + kept, lds);
+    nupd += wave_count(lead);
+    nfb += wave_count(sub == 0 && (fl & UPD_FALLBACK));
+    nfr += wave_count(sub == 0 && (fl & UPD_FRAME0));
+  }
+  if (threadIdx.x == 0) a.ccnt_out[c] = kept;
+}
+
+template <int DIM, int INTERP, typename T, int LANES>
+__global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
+  __shared__ int lds[5];
+  __shared__ uint32_t lds_st[12];
+  const uint32_t nch = (uint32_t)*a.cnt_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_out = (int32_t)nch;
+  uint32_t nupd = 0, nfb = 0, nfr = 0;
+  uint32_t c, end;
+  const uint32_t step = xcd_share(nch, c, end);
+  for (; c < end; c += step) sl_chunk<DIM, INTERP, T, LANES>(a, c, lds, nupd, nfb, nfr);
+  block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
+}
+
+// Batched step for the jobs of one interpolator (one launch per interpolator,
+// so that each kernel keeps its own register count and resident grid).
+template <int DIM, int INTERP, typename T, int LANES>
+__global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab, int n) {
+  __shared__ int lds[5];
+  __shared__ uint32_t lds_st[12];
+  if (blockIdx.x == 0)
+    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_out = *tab[t].cnt_in;
+  uint32_t nupd = 0, nfb = 0, nfr = 0;
+  JobCursor cur{n};
+  auto leave = [&](int jb) {
+    block_add3(nupd, nfb, nfr, LSR_FIELD(tab, jb, SLArgs<T>, stats), 0, 1, 2, lds_st);
+    nupd = nfb = nfr = 0;
+  };
+  uint32_t c, end;
+  const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
+  for (; c < end; c += step) {
+    if (!cur.advance(tab, c, leave)) break;
+    sl_chunk<DIM, INTERP, T, LANES>(uniform_load(tab, cur.jb), c - cur.beg, lds, nupd, nfb, nfr);
+  }
+  if (cur.jb >= 0 && cur.jb < n) leave(cur.jb);
+}
+
+// ------------------------------------------------------- reinitialisation
 
 // Interface set and one-step fix on Gbar.  Reads phi~ from src, writes the
 // working copy dst: dst = phi~ / max(|grad_c phi~|, floor) on interface nodes
@@ -719,37 +633,35 @@ template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_fix(RArgs<T> a) {
   __shared__ uint32_t lds_st[12];
   const int n = *a.cnt;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   uint32_t nif = 0, ng = 0;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * 256u;
-    if (base >= (uint32_t)n) break;
-    fix_chunk<DIM, T>(a, base, n, ng, nif);
-  }
+  uint32_t c, end;
+  const uint32_t step = xcd_share(((uint32_t)n + LCHUNK - 1) / LCHUNK, c, end);
+  for (; c < end; c += step) fix_chunk<DIM, T>(a, c * LCHUNK, n, ng, nif);
   block_add3(ng, nif, 0, a.stats, 4, 5, -1, lds_st);
 }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_fix_batch(const RArgs<T>* __restrict__ tab, int n) {
   __shared__ uint32_t lds_st[12];
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   uint32_t nif = 0, ng = 0;
   JobCursor cur{n};
   auto leave = [&](int jb) {
-    const RArgs<T> a = uniform_load(tab, jb);
-    block_add3(ng, nif, 0, a.stats, 4, 5, -1, lds_st);
+    block_add3(ng, nif, 0, LSR_FIELD(tab, jb, RArgs<T>, stats), 4, 5, -1, lds_st);
     ng = nif = 0;
   };
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t gch = chunk_of(q, xcd);
-    if (!cur.advance(tab, gch, 256u, leave)) break;
-    fix_chunk<DIM, T>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl, ng, nif);
+  uint32_t c, end;
+  const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
+  for (; c < end; c += step) {
+    if (!cur.advance(tab, c, leave)) break;
+    const RArgs<T> a = uniform_load(tab, cur.jb);
+    fix_chunk<DIM, T>(a, (c - cur.beg) * LCHUNK, *a.cnt, ng, nif);
   }
+  if (cur.jb >= 0 && cur.jb < n) leave(cur.jb);
 }
 
 // One forward-Euler pseudo-time step of phi_tau + S (|grad phi| - 1) = 0 on
 // Gbar minus the interface set, first-order upwind (Godunov) gradient; a
-// missing neighbour contributes no difference.  src -> dst on Gbar.
+// neighbour off the grid contributes no difference.  src -> dst on Gbar.
 template <int DIM, typename T>
 __device__ __forceinline__ void iter_chunk(const RArgs<T>& a, uint32_t base, int n) {
   const gptr<T> src = (gptr<T>)a.src;
@@ -795,89 +707,77 @@ __device__ __forceinline__ void iter_chunk(const RArgs<T>& a, uint32_t base, int
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_iter(RArgs<T> a) {
   const int n = *a.cnt;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * 256u;
-    if (base >= (uint32_t)n) break;
-    iter_chunk<DIM, T>(a, base, n);
-  }
+  uint32_t c, end;
+  const uint32_t step = xcd_share(((uint32_t)n + LCHUNK - 1) / LCHUNK, c, end);
+  for (; c < end; c += step) iter_chunk<DIM, T>(a, c * LCHUNK, n);
 }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_reinit_iter_batch(const RArgs<T>* __restrict__ tab, int n) {
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
   JobCursor cur{n};
   auto leave = [](int) {};
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t gch = chunk_of(q, xcd);
-    if (!cur.advance(tab, gch, 256u, leave)) break;
-    iter_chunk<DIM, T>(uniform_load(tab, cur.jb), (gch - cur.beg) * 256u, cur.nl);
+  uint32_t c, end;
+  const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
+  for (; c < end; c += step) {
+    if (!cur.advance(tab, c, leave)) break;
+    const RArgs<T> a = uniform_load(tab, cur.jb);
+    iter_chunk<DIM, T>(a, (c - cur.beg) * LCHUNK, *a.cnt);
   }
 }
 
-// Cut of eq. (cut) on Gbar, both buffers made equal there, new band list.
-// A block takes FIN_SUB sub-chunks of 256 entries per list append: this
-// kernel is short and its blocks finish together, so one atomic on the list
-// counter per 256 entries would queue up at the end of the launch.
-#ifndef LSR_FIN_SUB
-#define LSR_FIN_SUB 4
-#endif
-constexpr uint32_t FIN_SUB = LSR_FIN_SUB, FIN_CHUNK = 256 * FIN_SUB;
-
+// Cut of eq. (cut) on Gbar, both buffers made equal there, and the new band
+// list: Gbar's chunk c compacted into chunk c of Lout.
 template <typename T>
-__device__ __forceinline__ void final_chunk(const FinArgs<T>& a, uint32_t base, int n, int* lds) {
+__device__ __forceinline__ void final_chunk(const FinArgs<T>& a, uint32_t c, int n, int* lds) {
   const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
   const gwptr<T> cur = (gwptr<T>)a.cur;
   const gwptr<T> other = (gwptr<T>)a.other;
-  bool in[FIN_SUB];
-  uint32_t code[FIN_SUB];
-#pragma unroll
-  for (uint32_t u = 0; u < FIN_SUB; ++u) {
-    const uint32_t e = base + u * 256u + threadIdx.x;
-    in[u] = false;
-    code[u] = 0;
-    if (e < (uint32_t)n) {
-      code[u] = M[e];
-      int i, j, k;
-      decode(a.g, code[u], i, j, k);
-      const uint32_t idx = lin(a.g, i, j, k);
-      const T v = fmin(fmax(cur[idx], -a.gamma), a.gamma);
-      cur[idx] = v;
-      other[idx] = v;
-      in[u] = fabs(v) < a.gamma;
-    }
+  const uint32_t e = c * LCHUNK + threadIdx.x;
+  bool in[1] = {false};
+  uint32_t code[1] = {0};
+  if (e < (uint32_t)n) {
+    code[0] = M[e];
+    int i, j, k;
+    decode(a.g, code[0], i, j, k);
+    const uint32_t idx = lin(a.g, i, j, k);
+    const T v = fmin(fmax(cur[idx], -a.gamma), a.gamma);
+    cur[idx] = v;
+    other[idx] = v;
+    in[0] = fabs(v) < a.gamma;
   }
-  block_append<FIN_SUB>(in, code, (gwptr<uint32_t>)a.Lout, a.cnt_out, lds);
+  const int kept = block_compact<1>(in, code, (gwptr<uint32_t>)a.Lout + c * LCHUNK, lds);
+  if (threadIdx.x == 0) a.ccnt_out[c] = kept;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_reinit_final(FinArgs<T> a) {
-  __shared__ int lds[8];
+  __shared__ int lds[5];
   const int n = *a.cnt_in;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t base = chunk_of(q, xcd) * FIN_CHUNK;
-    if (base >= (uint32_t)n) break;
-    final_chunk<T>(a, base, n, lds);
-  }
+  const uint32_t nch = ((uint32_t)n + LCHUNK - 1) / LCHUNK;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_out = (int32_t)nch;
+  uint32_t c, end;
+  const uint32_t step = xcd_share(nch, c, end);
+  for (; c < end; c += step) final_chunk<T>(a, c, n, lds);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_reinit_final_batch(const FinArgs<T>* __restrict__ tab,
                                                             int n) {
-  __shared__ int lds[8];
+  __shared__ int lds[5];
   if (blockIdx.x == 0)
-    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_reset = 0;
-  const uint32_t xcd = blockIdx.x % 8u, nper = gridDim.x / 8u;
+    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x)
+      *tab[t].cnt_out = (int32_t)(((uint32_t)*tab[t].cnt_in + LCHUNK - 1) / LCHUNK);
   JobCursor cur{n};
   auto leave = [](int) {};
-  for (uint32_t q = blockIdx.x / 8u;; q += nper) {
-    const uint32_t gch = chunk_of(q, xcd);
-    if (!cur.advance(tab, gch, FIN_CHUNK, leave)) break;
-    final_chunk<T>(uniform_load(tab, cur.jb), (gch - cur.beg) * FIN_CHUNK, cur.nl, lds);
+  uint32_t c, end;
+  const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
+  for (; c < end; c += step) {
+    if (!cur.advance(tab, c, leave)) break;
+    const FinArgs<T> a = uniform_load(tab, cur.jb);
+    final_chunk<T>(a, c - cur.beg, *a.cnt_in, lds);
   }
 }
+
 
 // ------------------------------------------------------------ distance
 
@@ -1312,6 +1212,7 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   __shared__ int ncand, nsl, ndc, pstar, ubest;
   __shared__ int shell_n[NSH], shell_at[NSH];
   const DevGrid& g = a.g;
+  if (a.bmark && !a.bmark[blockIdx.x]) return;  // a brick the caller left out
   const int nbx = (g.n0 + BS - 1) / BS, nby = (g.n1 + BS - 1) / BS;
   const int nbz = DIM == 3 ? (g.n2 + BS - 1) / BS : 1;
   int b = blockIdx.x;
@@ -1917,23 +1818,22 @@ hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* ar
   return hipGetLastError();
 }
 
+// The three launches of a list from a grid scan (see GbarArgs).
 template <typename T>
-hipError_t launch_band_scan(int dim, const DevGrid& g, T gamma, const T* A, uint32_t* L,
-                            int32_t* cnt, hipStream_t s) {
-  // the chunk loop needs a multiple of 8 blocks (equal shares per XCD)
-  dim3 gr((grid_for(g.N, 256, 8192) + 7) / 8 * 8), bl(256);
-  if (dim == 3)
-    hipLaunchKernelGGL((k_band_scan<3, T>), gr, bl, 0, s, g, gamma, A, L, cnt);
-  else
-    hipLaunchKernelGGL((k_band_scan<2, T>), gr, bl, 0, s, g, gamma, A, L, cnt);
-  return hipGetLastError();
+hipError_t launch_grid_list(int dim, const GbarArgs<T>& a, unsigned blocks, hipStream_t s) {
+  hipError_t e = persistent_launch(dim == 3 ? k_grid_scan<3, T> : k_grid_scan<2, T>, blocks, s, a);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slot_prefix<T>, dim3(1), dim3(1024), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return persistent_launch(k_slot_pack<T>, blocks, s, a);
 }
 
 template <typename T>
 hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_t* L,
-                            const int32_t* cnt, uint8_t* mask, int32_t* count, unsigned blocks,
-                            hipStream_t s) {
-  return persistent_launch(k_band_mask<T>, blocks, s, g, gamma, A, L, cnt, mask, count);
+                            const int32_t* ccnt, const int32_t* cnt, uint8_t* mask,
+                            int32_t* count, unsigned blocks, hipStream_t s) {
+  return persistent_launch(k_band_mask<T>, blocks, s, g, gamma, A, L, ccnt, cnt, mask, count);
 }
 
 template <typename T>
@@ -1948,25 +1848,6 @@ hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, un
                    : (interp == 0 ? k_sl_step<2, 0, T, 2> : k_sl_step<2, 1, T, 2>);
   if (start) return persistent_launch_timed(k, blocks, s, start, stop, a);
   return persistent_launch(k, blocks, s, a);
-}
-
-template <typename T>
-hipError_t launch_sl_step_staged(int interp, const SLArgs<T>& a, unsigned blocks, hipStream_t s) {
-  // halo of the staged tile (nodes): LSR_STAGE_HALO_F32 / _F64
-  constexpr int H = sizeof(T) == 4 ? LSR_STAGE_HALO_F32 : LSR_STAGE_HALO_F64;
-  return persistent_launch(interp == 0 ? k_sl_step_staged<0, T, H> : k_sl_step_staged<1, T, H>,
-                           blocks, s, a);
-}
-
-hipError_t launch_nodes_to_bricks(const DevGrid& g, const uint32_t* L, const int32_t* cnt,
-                                  uint32_t* bstamp, uint32_t epoch, uint32_t* BL, int32_t* bcnt,
-                                  unsigned blocks, hipStream_t s) {
-  return persistent_launch(k_nodes_to_bricks, blocks, s, g, L, cnt, bstamp, epoch, BL, bcnt);
-}
-
-template <typename T>
-hipError_t launch_gbar_scan(int dim, const GbarArgs<T>& a, unsigned blocks, hipStream_t s) {
-  return persistent_launch(dim == 3 ? k_gbar_scan<3, T> : k_gbar_scan<2, T>, blocks, s, a);
 }
 
 template <typename T>
@@ -2108,10 +1989,15 @@ hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>*
 }
 
 template <typename T>
-hipError_t launch_gbar_scan_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
+hipError_t launch_grid_list_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
                                   hipStream_t s) {
-  return persistent_launch(dim == 3 ? k_gbar_scan_batch<3, T> : k_gbar_scan_batch<2, T>, blocks, s,
-                           tab, n);
+  hipError_t e = persistent_launch(dim == 3 ? k_grid_scan_batch<3, T> : k_grid_scan_batch<2, T>,
+                                   blocks, s, tab, n);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slot_prefix_batch<T>, dim3(n), dim3(1024), 0, s, tab);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return persistent_launch(k_slot_pack_batch<T>, blocks, s, tab, n);
 }
 
 template <typename T>
@@ -2136,11 +2022,10 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
 #define LSR_INSTANTIATE(T)                                                                        \
   template hipError_t launch_init_phi<T>(int, const DevGrid&, int, const double*, T, const T*, T*, \
                                          T*, int32_t*, hipStream_t);                              \
-  template hipError_t launch_band_scan<T>(int, const DevGrid&, T, const T*, uint32_t*, int32_t*,   \
-                                          hipStream_t);                                           \
+  template hipError_t launch_grid_list<T>(int, const GbarArgs<T>&, unsigned, hipStream_t);        \
   template hipError_t launch_band_mask<T>(const DevGrid&, T, const T*, const uint32_t*,           \
-                                          const int32_t*, uint8_t*, int32_t*, unsigned,           \
-                                          hipStream_t);                                           \
+                                          const int32_t*, const int32_t*, uint8_t*, int32_t*,     \
+                                          unsigned, hipStream_t);                                 \
   template hipError_t launch_sl_step<T>(int, int, int, const SLArgs<T>&, unsigned, hipStream_t,    \
                                         hipEvent_t, hipEvent_t);                                  \
   template hipError_t launch_reinit_fix<T>(int, const RArgs<T>&, unsigned, hipStream_t);          \
@@ -2148,9 +2033,7 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \
   template hipError_t launch_dpack<T>(int, const DevGrid&, const double*, typename Vec<T>::pack*, \
                                       hipStream_t);                                               \
-  template hipError_t launch_sl_step_staged<T>(int, const SLArgs<T>&, unsigned, hipStream_t);     \
-  template hipError_t launch_gbar_scan<T>(int, const GbarArgs<T>&, unsigned, hipStream_t);        \
-  template hipError_t launch_gbar_scan_batch<T>(int, const GbarArgs<T>*, int, unsigned,           \
+  template hipError_t launch_grid_list_batch<T>(int, const GbarArgs<T>*, int, unsigned,           \
                                                 hipStream_t);                                     \
   template hipError_t launch_sl_step_batch<T>(int, int, int, const SLArgs<T>*, int,               \
                                               unsigned, hipStream_t);                             \

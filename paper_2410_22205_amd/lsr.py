@@ -33,7 +33,8 @@ EXPORTED = [
     "lsr_batch_tune", "lsr_batch_destroy", "lsr_batch_set_graphs", "lsr_batch_set_streams",
     "lsr_set_launch",
     "lsr_set_graphs", "lsr_graph_counts", "lsr_profile_enable",
-    "lsr_profile_read", "lsr_last_error",
+    "lsr_profile_read", "lsr_last_error", "lsr_load_cloud_approx", "lsr_init_phi_cloud",
+    "lsr_init_phi_resample", "lsr_schedule_run",
 ]
 
 
@@ -75,6 +76,12 @@ def load():
             "lsr_workspace_bytes": [GP, PP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
             "lsr_create": [GP, PP, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
             "lsr_load_cloud": [_P, _P, ctypes.c_int64],
+            "lsr_load_cloud_approx": [_P, _P, ctypes.c_int64],
+            "lsr_init_phi_cloud": [_P, ctypes.c_double, ctypes.c_int64],
+            "lsr_init_phi_resample": [_P, _P, ctypes.c_int, ctypes.c_int64],
+            "lsr_schedule_run": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double,
+                                 GP, PP, ctypes.POINTER(ctypes.c_double)],
             "lsr_set_distance": [_P, _P],
             "lsr_get_distance": [_P, _P],
             "lsr_init_phi": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int64],
@@ -164,6 +171,28 @@ def lsr_create(grid, params, ws_ptr, ws_bytes, stream_ptr):
 
 def lsr_load_cloud(job, xyz_ptr, n):
     _check(load().lsr_load_cloud(job, _P(xyz_ptr), int(n)))
+
+
+def lsr_load_cloud_approx(job, xyz_ptr, n):
+    _check(load().lsr_load_cloud_approx(job, _P(xyz_ptr), int(n)))
+
+
+def lsr_init_phi_cloud(job, gamma_s, step0=0):
+    _check(load().lsr_init_phi_cloud(job, float(gamma_s), int(step0)))
+
+
+def lsr_init_phi_resample(job, coarse, interp, step0=0):
+    _check(load().lsr_init_phi_resample(job, coarse, int(interp), int(step0)))
+
+
+def lsr_schedule_run(r, dim, box_lo, box_hi, h_s, k_s=2.0):
+    """(grid, params, dt) of run r of the coarse-to-fine schedule."""
+    lo = (ctypes.c_double * 3)(*(list(box_lo) + [0.0] * (3 - len(box_lo))))
+    hi = (ctypes.c_double * 3)(*(list(box_hi) + [0.0] * (3 - len(box_hi))))
+    g, p, dt = LsrGrid(), LsrParams(), ctypes.c_double()
+    _check(load().lsr_schedule_run(int(r), int(dim), lo, hi, float(h_s), float(k_s),
+                                   ctypes.byref(g), ctypes.byref(p), ctypes.byref(dt)))
+    return g, p, dt.value
 
 
 def lsr_set_distance(job, d_ptr):
@@ -348,10 +377,22 @@ class Job:
         t = self.torch.as_tensor(np.ascontiguousarray(x) if isinstance(x, np.ndarray) else x)
         return t.to(device=self.stream.device, dtype=dtype).contiguous()
 
-    def load_cloud(self, points):
+    def load_cloud(self, points, approx=False):
+        """The cloud and its distance field: exact, or (approx) the paper's
+        approximation of Section 3.4."""
         pts = self._dev(points, self.torch.float64)
-        with self.torch.cuda.stream(self.stream):
-            lsr_load_cloud(self.handle, pts.data_ptr(), pts.shape[0])
+        self.torch.cuda.current_stream().synchronize()  # the copy, before the job's stream reads it
+        (lsr_load_cloud_approx if approx else lsr_load_cloud)(self.handle, pts.data_ptr(),
+                                                             pts.shape[0])
+
+    def init_phi_cloud(self, gamma_s, step0=0):
+        """phi0 from the loaded distance field (Section 3.6)."""
+        lsr_init_phi_cloud(self.handle, gamma_s, step0)
+
+    def init_phi_resample(self, coarse, interp, step0=0):
+        """phi0 = the coarser job's phi interpolated onto this grid (Section 4)."""
+        lsr_init_phi_resample(self.handle, coarse.handle,
+                              interp_code(interp) if isinstance(interp, str) else interp, step0)
 
     def set_distance(self, d):
         dd = self._dev(d, self.torch.float64)

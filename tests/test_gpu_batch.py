@@ -191,25 +191,6 @@ def test_batch_rules():
     j2.close()
 
 
-def test_staged_job_through_a_batch():
-    """A job stepped by the brick-staged kernel, then in a batch (node lists),
-    then staged again gives bitwise the result of the node kernel alone."""
-    lsr = _lsr()
-    w = _jobs("fp32", n=1, seed=4500)[0]
-    ref = _solo(w, 20, lanes=1)[0]
-    job = _make(lsr, w)
-    job.set_launch(0, 8)
-    job.step(5, w["dt"], w["interp"])
-    batch = lsr.Batch(max_jobs=1, group_steps=4)
-    batch.add(job, w["dt"], w["interp"])
-    batch.step(7)
-    batch.remove(job)
-    job.step(8, w["dt"], w["interp"])
-    np.testing.assert_array_equal(job.extract()[0], ref)
-    batch.close()
-    job.close()
-
-
 def test_tuned_shape_is_kept_for_the_same_signature():
     """A second batch of the same dimension, precision, interpolator mix and
     size gets the first one's tuned shape without timing again (the same

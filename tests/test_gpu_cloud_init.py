@@ -1,0 +1,192 @@
+"""GPU parity of the initial data from the cloud (Section 3.6), of the
+paper's approximate distance field (Section 3.4) and of the multi-run
+coarse-to-fine schedule (Section 4) against the oracle, through the C ABI.
+
+The marking is integer work: any disagreement shows up as a sign change of
+phi0.  The fast-sweeping solution is the fixed point of one discrete system,
+which the oracle reaches by Gauss-Seidel sweeps and the device by tiled
+Jacobi passes; both evaluate the same Godunov update in double without
+contraction, so in FP64 they agree to rounding (measured: bitwise).  An
+FP32 state stores the same values rounded once.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22205_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _lsr():
+    from paper_2410_22205_amd import lsr
+    return lsr
+
+
+def circle64():
+    th = np.arange(64) * (2.0 * np.pi / 64)
+    return np.stack([np.cos(th), np.sin(th)], axis=1)
+
+
+def shell_with_cavity(seed=12):
+    """Two concentric spheres: the cavity between them holds no point and is
+    sealed from the boundary, so the marking must leave it internal."""
+    rng = np.random.default_rng(seed)
+    return np.concatenate([synth.sphere_points(rng, 3000, 0.6, (0.02, -0.01, 0.03)),
+                           synth.sphere_points(rng, 1500, 0.3, (0.02, -0.01, 0.03))])
+
+
+def _case(name):
+    """(points, grid, gamma_S) on the first run's grid of the schedule."""
+    if name == "circle64":
+        pts = circle64()
+        hs = oracle.cloud_spacing(pts, np.arange(64))
+    elif name == "circle2d":
+        pts = synth.workload("circle2d")["points"]
+        hs = oracle.cloud_spacing(pts, np.arange(0, len(pts), 3))
+    elif name == "torus":
+        pts = synth.torus_cloud(4000, 0.5, 0.2, 0.0, seed=21)
+        hs = oracle.cloud_spacing(pts, np.arange(0, len(pts), 10))
+    elif name == "union":
+        pts = synth.union_cloud(20000, seed=3)
+        hs = oracle.cloud_spacing(pts, np.arange(0, len(pts), 10))
+    else:  # the shell with a sealed cavity, on a finer grid
+        pts = shell_with_cavity()
+        hs = 0.5 * oracle.cloud_spacing(pts, np.arange(0, len(pts), 10))
+    grid = oracle.run_grid(pts, hs, 1)
+    return pts, grid, 2.0 * hs
+
+
+CASES = ["circle64", "circle2d", "torus", "union", "cavity"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", CASES)
+def test_phi0_from_cloud_matches_oracle(name, precision):
+    lsr = _lsr()
+    pts, grid, gs = _case(name)
+    h = grid["h"]
+    prm = oracle.default_params(grid["dim"], h)
+    job = lsr.Job(grid, {"precision": precision}, max_points=len(pts))
+    job.load_cloud(pts)
+    job.init_phi_cloud(gs)
+    phi, band, nb, si = job.extract()
+    job.close()
+    d = oracle.distance(pts, grid)
+    ophi, ext, cycles = oracle.phi0_from_cloud(d, grid, gs)
+    want = np.clip(ophi, -prm["gamma"], prm["gamma"])
+    err = float(np.abs(phi.astype(np.float64) - want).max())
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert err <= tol * h, (err / h, cycles)
+    # the marking decides the sign: external nodes are >= 0, internal < 0
+    np.testing.assert_array_equal(phi >= 0, want >= 0)
+    assert nb == int((np.abs(phi) < phi.dtype.type(prm["gamma"])).sum()) and si == 0
+    if name == "cavity":
+        assert (ext == 0).sum() > (ext == 1).sum() // 50  # the cavity stays internal
+    print(f"{name} {precision}: max |dphi0| {err / h:.2e} h, oracle sweep cycles {cycles}")
+
+
+@pytest.mark.parametrize("name", ["circle2d", "torus", "union", "one_point", "corner"])
+def test_approximate_distance_matches_oracle(name):
+    lsr = _lsr()
+    if name == "one_point":
+        grid = synth.cube_grid(3, 40)
+        pts = np.array([[0.1234, -0.2345, 0.3456]])
+    elif name == "corner":
+        grid = synth.cube_grid(3, 48)
+        rng = np.random.default_rng(8)
+        pts = -0.95 + 0.2 * rng.random((500, 3))
+    else:
+        pts, grid, _ = _case(name)
+    job = lsr.Job(grid, {"precision": "fp64"}, max_points=len(pts))
+    job.load_cloud(pts, approx=True)
+    d = job.distance()
+    job.close()
+    od, fixed, cycles = oracle.distance_approx(pts, grid)
+    err = np.abs(d - od)
+    rel = float((err / np.maximum(od, grid["h"])).max())
+    assert rel <= 1e-12, (rel, cycles)
+    # the box nodes hold the exact distance
+    exact = oracle.distance(pts, grid)
+    assert np.array_equal(d[fixed == 1], exact[fixed == 1])
+    print(f"{name}: max relative |dd| {rel:.2e}, oracle sweep cycles {cycles}")
+
+
+def test_approximate_distance_drives_a_run():
+    """A job on the approximate field steps like the oracle on the oracle's
+    approximate field (the torus at 48^3, WENO, 20 steps, FP64)."""
+    lsr = _lsr()
+    w = synth.workload("torus3d", n=48, steps=20)
+    g = w["grid"]
+    prm = oracle.default_params(3, g["h"], gamma=w["gamma"], beta=w["beta"],
+                                reinit_every=w["reinit_every"])
+    job = lsr.Job(g, dict(gamma=w["gamma"], beta=w["beta"], reinit_every=w["reinit_every"],
+                          precision="fp64"), max_points=len(w["points"]))
+    job.load_cloud(w["points"], approx=True)
+    job.init_phi(w["phi0"][0], w["phi0"][1])
+    job.step(w["steps"], w["dt"], w["interp"])
+    phi = job.extract()[0]
+    job.close()
+    od, _, _ = oracle.distance_approx(w["points"], g)
+    phi0 = oracle.init_phi(g, w["phi0"][0], w["phi0"][1], prm["gamma"])
+    ophi, _ = oracle.run(phi0, od, g, prm, w["dt"], w["interp"], w["steps"])
+    assert np.abs(phi - ophi).max() <= 1e-4 * g["h"]
+
+
+def _compare_schedule(pts, sample, kind, runs, max_steps, tol_phi):
+    from paper_2410_22205_amd import schedule
+    hs, got = schedule.reconstruct(pts, sample, kind, runs=runs, precision="fp64",
+                                   max_steps=max_steps)
+    ohs, want = oracle.reconstruct(pts, sample, kind, runs=runs, max_steps=max_steps)
+    assert abs(hs - ohs) <= 1e-12 * ohs
+    worst = 0.0
+    for r, (a, b) in enumerate(zip(got, want), 1):
+        assert a["grid"]["n"] == b["grid"]["n"], (r, a["grid"], b["grid"])
+        np.testing.assert_allclose(a["grid"]["lo"], b["grid"]["lo"], rtol=0, atol=1e-12)
+        assert a["grid"]["h"] == pytest.approx(b["grid"]["h"], rel=1e-15)
+        assert (a["p"], a["delta"]) == oracle.run_params(r)
+        assert a["steps"] == b["steps"], (r, a["steps"], b["steps"])
+        np.testing.assert_allclose(a["energies"], b["energies"], rtol=1e-9)
+        err = float(np.abs(a["phi"] - b["phi"]).max()) / a["grid"]["h"]
+        worst = max(worst, err)
+        assert err <= tol_phi, (r, err)
+    return got, worst
+
+
+@pytest.mark.parametrize("kind", ["q1", "weno"])
+def test_schedule_circle64(kind):
+    """The paper's circle test, three runs (grids 42, 58, 99), FP64."""
+    got, worst = _compare_schedule(circle64(), np.arange(64), kind, 3, 100, 1e-8)
+    print(f"circle64 {kind}: steps {[g['steps'] for g in got]}, max |dphi| {worst:.2e} h")
+
+
+def test_schedule_torus3d():
+    """A 3D cloud through three runs (phi0 from the cloud, then two warm
+    starts, p = 1 then 2, delta = 0 then 1), at most 15 steps each, FP64."""
+    pts = synth.torus_cloud(1500, 0.5, 0.2, 0.0, seed=31)
+    got, worst = _compare_schedule(pts, np.arange(0, len(pts), 10), "weno", 3, 15, 1e-6)
+    print(f"torus schedule: grids {[g['grid']['n'] for g in got]}, max |dphi| {worst:.2e} h")
+
+
+@pytest.mark.parametrize("kind", ["q1", "weno"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_resample_matches_oracle(dim, kind):
+    """The warm start alone: a coarse job's phi interpolated onto a finer,
+    shifted grid (nodes outside the coarse box are moved onto it)."""
+    lsr = _lsr()
+    coarse = synth.cube_grid(dim, 33)
+    fine = {"dim": dim, "n": (61,) * dim, "lo": (-1.07,) * dim, "h": 2.1 / 60}
+    X = oracle.node_coords(coarse)
+    phi_c = (np.linalg.norm(X - 0.05, axis=1) - 0.6 + 0.05 * np.sin(7 * X[:, 0])).reshape(
+        coarse["n"])
+    gam_c, gam_f = 6 * coarse["h"], 6 * fine["h"]
+    a = lsr.Job(coarse, {"precision": "fp64", "gamma": gam_c, "beta": gam_c / 2}, max_points=1)
+    a.init_phi(phi0=np.clip(phi_c, -gam_c, gam_c))
+    b = lsr.Job(fine, {"precision": "fp64", "gamma": gam_f, "beta": gam_f / 2}, max_points=1)
+    b.init_phi_resample(a, kind)
+    got = b.extract()[0]
+    a.close()
+    b.close()
+    want = np.clip(oracle.resample(np.clip(phi_c, -gam_c, gam_c), coarse, fine, kind), -gam_f,
+                   gam_f)
+    assert np.abs(got - want).max() <= 1e-12

@@ -550,17 +550,15 @@ def test_errors_leave_the_job_usable():
 @pytest.mark.parametrize("name,interp", [("torus3d", "weno"), ("torus3d", "q1"),
                                          ("circle2d", "weno")])
 def test_launch_shape_does_not_change_results(name, interp, precision):
-    """One lane per node, one lane per foot point and (3D) the brick-staged
-    kernel read the same values and add the foot values in the same order:
-    bitwise equal results, whatever the persistent grid.  12 steps cross a
-    reinitialisation (the staged kernel then rebuilds its brick list)."""
+    """One lane per node and one lane per foot point read the same values and
+    add the foot values in the same order: bitwise equal results, whatever
+    the persistent grid (1 block per CU leaves most chunks of the band to a
+    second round of the blocks).  12 steps cross a reinitialisation."""
     lsr = _lsr()
     w = synth.workload(name, n=40 if name == "torus3d" else 96, steps=12)
     w["interp"] = interp
     fp = 4 if w["grid"]["dim"] == 3 else 2
-    shapes = [(1, 8), (fp, 8), (1, 2)]
-    if w["grid"]["dim"] == 3:
-        shapes += [(0, 8), (0, 1)]
+    shapes = [(1, 8), (fp, 8), (1, 2), (fp, 1)]
     out = []
     for lanes, bpc in shapes:
         oprm = oracle_params(w)
@@ -578,23 +576,24 @@ def test_launch_shape_does_not_change_results(name, interp, precision):
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
-def test_staged_step_near_the_grid_boundary(precision):
-    """Bricks on the boundary of a ragged grid: the staged tile holds the
-    clamped values, foot stencils reaching past it fall back to device memory;
-    same result as the node kernel."""
+def test_launch_shapes_on_a_ragged_grid(precision):
+    """Ragged extents (no axis a multiple of a brick): the list builds scan
+    partial bricks and slots, the chunked band lists end in partial chunks;
+    every launch shape gives the same result and the same work counts."""
     lsr = _lsr()
     g = {"dim": 3, "n": (23, 41, 30), "lo": (-0.6, -1.0, -0.75), "h": 0.05}
     pts = synth.torus_cloud(3000, 0.45, 0.18, 0.0, seed=9)
     pts = pts[np.all(np.abs(pts) < [0.5, 0.9, 0.7], axis=1)]
     out = []
-    for lanes in (1, 0):
+    for lanes, bpc in ((1, 8), (4, 8), (1, 1)):
         job = lsr.Job(g, dict(gamma=0.3, beta=0.15, reinit_every=4, precision=precision),
                       max_points=len(pts))
-        job.set_launch(lanes, 8)
+        job.set_launch(lanes, bpc)
         job.load_cloud(pts)
         job.init_phi("sphere", (0.0123, 0.0571, -0.0087, 0.55))
         job.step(9, 0.025, "weno")
         out.append((job.extract()[0], job.counters()))
         job.close()
-    np.testing.assert_array_equal(out[0][0], out[1][0])
-    assert out[0][1] == out[1][1]
+    for o in out[1:]:
+        np.testing.assert_array_equal(out[0][0], o[0])
+        assert out[0][1] == o[1]
