@@ -324,9 +324,10 @@ lsr_status lsr_destroy(lsr_job* job);
  * (lanes per node, blocks per CU) without changing the jobs, keeps the
  * fastest and returns it with its time in ms (synchronises).  The choice is
  * kept for the process under the batch's signature (dimension, precision,
- * jobs per interpolator, total grid nodes rounded up to a power of two); a
- * later call with the same signature applies it without timing and returns
- * the time measured then.
+ * jobs per interpolator, total grid nodes rounded up to a power of two), and
+ * in the file of lsr_set_tune_cache if one is set; a later call with the
+ * same signature applies it without timing and returns the time measured
+ * then.
  * lsr_batch_destroy: removes the members, waits for the stream and
  * releases the batch's graphs, second stream and events. */
 lsr_status lsr_batch_workspace_bytes(int32_t max_jobs, int32_t group_steps, int32_t max_reinit_iters,
@@ -341,6 +342,13 @@ lsr_status lsr_batch_set_launch(lsr_batch* batch, int32_t lanes, int32_t blocks_
 lsr_status lsr_batch_set_streams(lsr_batch* batch, int32_t n_streams);
 lsr_status lsr_batch_set_graphs(lsr_batch* batch, int32_t enable);
 lsr_status lsr_batch_tune(lsr_batch* batch, int32_t* lanes, int32_t* blocks_per_cu, double* ms);
+/* Keep tuned launch shapes in a text file as well (path NULL or empty: in
+ * the process only): the file's choices are read now (a missing file is an
+ * empty one; choices already made in this process win), and every later
+ * tuning appends its line: dimension, precision, Q1 jobs, WENO jobs, nodes
+ * rounded up to a power of two, lanes, blocks per CU, time in ms.
+ * LSR_E_INVALID for a malformed line (nothing is read then).  Host only. */
+lsr_status lsr_set_tune_cache(const char* path);
 lsr_status lsr_batch_destroy(lsr_batch* batch);
 
 /* Launch shape of the list kernels (results are bitwise the same for every

@@ -85,6 +85,7 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.ccnt1 = take(4 * nch);
   L.scnt = take(4 * (size_t)slots);
   L.soff = take(4 * ((size_t)slots + 1));
+  L.smark = take((size_t)slots);
   L.listM = take(4 * N);
   L.mflags = take(N);
   {
@@ -155,6 +156,25 @@ lsr_status check_params(const lsr_grid* g, const lsr_params* p) {
 
 namespace lsr {
 
+lsr_status grid_ok(const lsr_grid* g) { return check_grid(g); }
+
+DevGrid make_devgrid(const lsr_grid& g) {
+  DevGrid d;
+  d.n0 = g.n[0];
+  d.n1 = g.n[1];
+  d.n2 = g.dim == 3 ? g.n[2] : 1;
+  d.s1 = (uint32_t)d.n2;
+  d.s0 = (uint32_t)d.n1 * (uint32_t)d.n2;
+  d.N = (uint32_t)node_count(g);
+  d.bits_k = g.dim == 3 ? bits_for(d.n2) : 0;
+  d.bits_j = bits_for(d.n1);
+  d.hd = g.h;
+  d.lo0 = g.lo[0];
+  d.lo1 = g.lo[1];
+  d.lo2 = g.dim == 3 ? g.lo[2] : 0.0;
+  return d;
+}
+
 template <typename T>
 static hipError_t launch_reinit_plan(lsr_job* j, const ReinitPlan<T>& r) {
   hipStream_t s = j->stream;
@@ -181,8 +201,9 @@ static lsr_status run_reinit_t(lsr_job* j) {
 // device for the step kernel that follows.
 template <typename T>
 static hipError_t launch_step_energy(lsr_job* j) {
-  return launch_energy<T>(j->grid.dim, j->dg, phi_buf<T>(j, j->cur), j->d64, j->prm.p, ENERGY_R,
-                          j->energy_buf, j->energy_buf + ENERGY_BLOCKS, j->stream);
+  return launch_energy_listed<T>(j->grid.dim, j->dg, phi_buf<T>(j, j->cur), j->d64, j->prm.p,
+                                 ENERGY_R, energy_lists(j), j->energy_buf,
+                                 j->energy_buf + ENERGY_BLOCKS, j->list_blocks, j->stream);
 }
 
 template <typename T>
@@ -357,6 +378,9 @@ GbarArgs<T> first_band(lsr_job* j) {
   a.g = j->dg;
   a.gamma = (T)j->prm.gamma;
   a.nbr = 0;
+  a.smark = nullptr;
+  a.L = nullptr;
+  a.Lccnt = a.Lcnt = nullptr;
   a.P = phi_buf<T>(j, 0);
   a.S = j->list[1];
   a.scnt = j->scnt;
@@ -532,19 +556,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->L = L;
   j->max_points = maxp;
   const lsr_grid& g = j->grid;
-  DevGrid& d = j->dg;
-  d.n0 = g.n[0];
-  d.n1 = g.n[1];
-  d.n2 = g.dim == 3 ? g.n[2] : 1;
-  d.s1 = (uint32_t)d.n2;
-  d.s0 = (uint32_t)d.n1 * (uint32_t)d.n2;
-  d.N = (uint32_t)node_count(g);
-  d.bits_k = g.dim == 3 ? bits_for(d.n2) : 0;
-  d.bits_j = bits_for(d.n1);
-  d.hd = g.h;
-  d.lo0 = g.lo[0];
-  d.lo1 = g.lo[1];
-  d.lo2 = g.lo[2];
+  j->dg = make_devgrid(g);
   j->bg = bin_geom(g, BIN_W);
   j->bg_fine = bin_geom(g, BIN_W_FINE);
 
@@ -559,6 +571,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->ccnt[1] = (int32_t*)(w + L.ccnt1);
   j->scnt = (int32_t*)(w + L.scnt);
   j->soff = (int32_t*)(w + L.soff);
+  j->smark = (uint8_t*)(w + L.smark);
   j->listM = (uint32_t*)(w + L.listM);
   j->mflags = (uint8_t*)(w + L.mflags);
   j->dmark = (uint8_t*)(w + L.dmark);
@@ -597,6 +610,10 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
 
   hipStream_t s = j->stream;
   hipError_t e = launch_fill_u32((uint32_t*)j->cnt, 0u, 16, s);
+  if (e == hipSuccess)
+    e = launch_fill_u8(j->smark, 0,
+                       gbar_slots(grid->dim, grid->n[0], grid->n[1], grid->dim == 3 ? grid->n[2] : 1),
+                       s);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)j->stats, 0u, 2 * STAT_WORDS, s);
   if (e != hipSuccess) {
     delete j;
@@ -868,11 +885,13 @@ lsr_status lsr_energy(lsr_job* j, double p, int32_t R, double* out) {
   double* part = j->energy_buf;
   double* dout = part + ENERGY_BLOCKS;
   if (j->fp64)
-    LSR_HIP(launch_energy<double>(j->grid.dim, j->dg, phi_buf<double>(j, j->cur), j->d64, p, R,
-                                  part, dout, s));
+    LSR_HIP(launch_energy_listed<double>(j->grid.dim, j->dg, phi_buf<double>(j, j->cur), j->d64,
+                                         p, R, energy_lists(j), j->energy_buf,
+                                         j->energy_buf + ENERGY_BLOCKS, j->list_blocks, s));
   else
-    LSR_HIP(launch_energy<float>(j->grid.dim, j->dg, phi_buf<float>(j, j->cur), j->d64, p, R,
-                                 part, dout, s));
+    LSR_HIP(launch_energy_listed<float>(j->grid.dim, j->dg, phi_buf<float>(j, j->cur), j->d64,
+                                        p, R, energy_lists(j), j->energy_buf,
+                                        j->energy_buf + ENERGY_BLOCKS, j->list_blocks, s));
   double v = 0.0;
   LSR_HIP(hipMemcpyAsync(&v, dout, sizeof(double), hipMemcpyDeviceToHost, s));
   LSR_HIP(hipStreamSynchronize(s));

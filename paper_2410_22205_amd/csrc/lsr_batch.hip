@@ -7,10 +7,12 @@
 // goes through the same buffers, counters and per-node arithmetic as it would
 // alone.  Tables for a group of steps are written to pinned host memory and
 // copied to the caller's device workspace with one transfer per group.
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "lsr_job.h"
@@ -29,6 +31,7 @@ struct Launch {
   int group;     // cache group (see cache_groups)
   lsr_job* job = nullptr;  // kind 5: the job, and the phi buffer its next step reads
   int phi = 0;
+  EnergyLists lists{};     // kind 5: the buffers of the front-cell list
 };
 
 }  // namespace
@@ -125,6 +128,7 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
         Launch L{5, 0, 1, 0, B.group};
         L.job = j;
         L.phi = j->cur;
+        L.lists = energy_lists(j);
         B.launches.push_back(L);
       }
     }
@@ -201,7 +205,8 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
                                     b->blocks, s);
         break;
       case 1:
-        e = launch_grid_list_batch<T>(b->dim, (const GbarArgs<T>*)(dev + L.off), L.n, b->blocks, s);
+        e = launch_grid_list_batch<T>(b->dim, (const GbarArgs<T>*)(dev + L.off), L.n, b->blocks, s,
+                                      true);
         break;
       case 2:
         e = launch_reinit_fix_batch<T>(b->dim, (const RArgs<T>*)(dev + L.off), L.n, b->blocks, s);
@@ -215,8 +220,9 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
         break;
       case 5: {
         lsr_job* j = L.job;
-        e = launch_energy<T>(b->dim, j->dg, (const T*)j->phi[L.phi], j->d64, j->prm.p, ENERGY_R,
-                             j->energy_buf, j->energy_buf + ENERGY_BLOCKS, s);
+        e = launch_energy_listed<T>(b->dim, j->dg, (const T*)j->phi[L.phi], j->d64, j->prm.p,
+                                    ENERGY_R, L.lists, j->energy_buf,
+                                    j->energy_buf + ENERGY_BLOCKS, b->blocks, s);
         break;
       }
     }
@@ -254,6 +260,8 @@ std::vector<int64_t> group_key(const lsr_batch* b, const Builder<T>& B) {
       k.push_back((int64_t)(intptr_t)j->phi[L.phi]);
       k.push_back((int64_t)(intptr_t)j->d64);
       k.push_back((int64_t)(intptr_t)j->energy_buf);
+      k.push_back((int64_t)(intptr_t)L.lists.S);
+      k.push_back((int64_t)(intptr_t)L.lists.M);
       k.push_back((int64_t)j->dg.N);
       k.push_back((int64_t)j->dg.n0 << 40 | (int64_t)j->dg.n1 << 20 | (int64_t)j->dg.n2);
       k.push_back(pb);
@@ -388,8 +396,9 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
   // p = 2 members: the energy their next step will read
   for (lsr_job* j : b->jobs)
     if (j->prm.p != 1.0)
-      LSR_HIP(launch_energy<T>(b->dim, j->dg, (const T*)j->phi[j->cur], j->d64, j->prm.p, ENERGY_R,
-                               j->energy_buf, j->energy_buf + ENERGY_BLOCKS, s));
+      LSR_HIP(launch_energy_listed<T>(b->dim, j->dg, (const T*)j->phi[j->cur], j->d64, j->prm.p,
+                                      ENERGY_R, energy_lists(j), j->energy_buf,
+                                      j->energy_buf + ENERGY_BLOCKS, b->blocks, s));
   hipEvent_t e0, e1;
   LSR_HIP(hipEventCreate(&e0));
   LSR_HIP(hipEventCreate(&e1));
@@ -437,6 +446,23 @@ struct TuneEntry {
 
 std::mutex g_tune_mutex;
 std::vector<TuneEntry> g_tune_cache;
+std::string g_tune_path;  // file that keeps the choices across processes ("" = none)
+
+// One line per choice: the five key fields, lanes, blocks per CU, time in ms.
+bool parse_tune_line(const char* line, TuneEntry* e) {
+  long long k[5];
+  int lanes, bpc;
+  double ms;
+  if (sscanf(line, "%lld %lld %lld %lld %lld %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4],
+             &lanes, &bpc, &ms) != 8)
+    return false;
+  if (lanes < 1 || bpc < 1 || bpc > 64 || !(ms >= 0.0)) return false;
+  for (int q = 0; q < 5; ++q) e->key[q] = k[q];
+  e->lanes = lanes;
+  e->bpc = bpc;
+  e->ms = ms;
+  return true;
+}
 
 void tune_key(const lsr_batch* b, int64_t key[5]) {
   int64_t nq = 0, nw = 0, nodes = 0;
@@ -664,12 +690,54 @@ lsr_status lsr_batch_tune(lsr_batch* b, int32_t* lanes, int32_t* blocks_per_cu, 
     e.bpc = bb;
     e.ms = t;
     g_tune_cache.push_back(e);
+    if (!g_tune_path.empty()) {
+      FILE* f = fopen(g_tune_path.c_str(), "a");
+      if (f) {
+        fprintf(f, "%lld %lld %lld %lld %lld %d %d %.17g\n", (long long)key[0], (long long)key[1],
+                (long long)key[2], (long long)key[3], (long long)key[4], bl, bb, t);
+        fclose(f);
+      }
+    }
   }
   lsr_status st = lsr_batch_set_launch(b, bl, bb);
   if (st != LSR_OK) return st;
   if (lanes) *lanes = bl;
   if (blocks_per_cu) *blocks_per_cu = bb;
   if (ms) *ms = t;
+  return LSR_OK;
+}
+
+lsr_status lsr_set_tune_cache(const char* path) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  if (!path || !*path) {
+    g_tune_path.clear();
+    return LSR_OK;
+  }
+  std::vector<TuneEntry> got;
+  if (FILE* f = fopen(path, "r")) {
+    char line[512];
+    int no = 0;
+    bool bad = false;
+    while (fgets(line, sizeof line, f)) {
+      ++no;
+      if (line[0] == '#' || line[0] == '\n') continue;
+      TuneEntry e;
+      if (!parse_tune_line(line, &e)) {
+        bad = true;
+        break;
+      }
+      got.push_back(e);
+    }
+    fclose(f);
+    if (bad) return fail(LSR_E_INVALID, std::string(path) + ": malformed line " + std::to_string(no));
+  }
+  // entries already known in this process keep their values
+  for (const TuneEntry& e : got) {
+    bool known = false;
+    for (const TuneEntry& c : g_tune_cache) known = known || std::equal(e.key, e.key + 5, c.key);
+    if (!known) g_tune_cache.push_back(e);
+  }
+  g_tune_path = path;
   return LSR_OK;
 }
 

@@ -105,11 +105,20 @@ __host__ __device__ inline uint32_t gbar_slots(const DevGrid& g) {
 // the counts into soff[0 .. slots] (one block per job); every slot's members
 // copied to M at soff[s].  *cnt_out receives the length of M, or, when ccnt
 // is given, M's number of LCHUNK chunks with their entries in ccnt.
+// With smark, only the slots marked 1 are scanned (the others hold no
+// member), and the scan clears every mark it reads (all marks are clear
+// between builds); for Gbar the slots are marked from the band list L of the
+// step: every node with |P| < gamma is on L, and a member of Gbar is such a
+// node or its face neighbour.
 template <typename T>
 struct GbarArgs {
   DevGrid g;
   T gamma;
   int nbr;
+  uint8_t* smark;        // null: every slot
+  const uint32_t* L;     // with smark: the band list (chunked), its entries
+  const int32_t* Lccnt;  // per chunk and its number of chunks
+  const int32_t* Lcnt;
   const T* P;
   uint32_t* S;
   int32_t* scnt;
@@ -248,6 +257,21 @@ constexpr int ENERGY_R = 5;
 template <typename T>
 hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* d, double p, int R,
                          double* partial, double* out, hipStream_t s);
+// The same E_p from a list of the front cells: a grid scan (GbarArgs with
+// nbr = 2) compacts them into M in scan order (S, scnt, soff: its slot
+// lists; *cnt: their number), then ENERGY_BLOCKS blocks sum equal stretches
+// of the list.  Same value to rounding, and deterministic.
+struct EnergyLists {
+  uint32_t* S;
+  int32_t* scnt;
+  int32_t* soff;
+  uint32_t* M;
+  int32_t* cnt;
+};
+template <typename T>
+hipError_t launch_energy_listed(int dim, const DevGrid& g, const T* phi, const double* d, double p,
+                                int R, const EnergyLists& w, double* partial, double* out,
+                                unsigned blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,
                         hipStream_t s);
@@ -282,9 +306,10 @@ hipError_t launch_resample(int dim, int interp, const DevGrid& g, const DevGrid&
 template <typename T>
 hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>* tab, int n,
                                 unsigned blocks, hipStream_t s);
+// marked: the table's entries carry slot marks (all of them, or none).
 template <typename T>
 hipError_t launch_grid_list_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
-                                  hipStream_t s);
+                                  hipStream_t s, bool marked);
 template <typename T>
 hipError_t launch_reinit_fix_batch(int dim, const RArgs<T>* tab, int n, unsigned blocks,
                                    hipStream_t s);

@@ -29,6 +29,7 @@ struct Layout {
   size_t phi0, phi1, dp, d64, list0, list1, listM, mflags, cnt, stats;
   size_t ccnt0, ccnt1;  // entries per chunk of the two band lists
   size_t scnt, soff;    // members per grid slot and their prefix (list builds)
+  size_t smark;         // grid slots marked for the Gbar scan
   size_t dmark;         // distance-kernel bricks marked for the approximate distance
   int64_t list_cap;     // entries of a band-list buffer: chunks and grid slots
   size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo, sup, sgeo;
@@ -59,13 +60,16 @@ struct lsr_job {
   int32_t* ccnt[2];      // their entries per chunk
   int32_t* scnt;         // members per grid slot of a list build
   int32_t* soff;         // and their exclusive prefix
+  uint8_t* smark;        // slots a Gbar build scans (clear between builds)
   uint32_t* listM;
   uint8_t* mflags;  // reinitialisation flags; scratch of the initial-data passes
   uint8_t* dmark;
   int32_t* cnt;  // [0..2] list-count ring (chunks of a band list, entries of Gbar),
                  // [3] flag, [4] extract count, [5] occupied bins, [6] bins a
                  // cloud's points occupy (density check), [7] occupied
-                 // super-bins, [11] sample-index flag of lsr_cloud_spacing
+                 // super-bins, [9] front cells of the energy, [11]
+                 // sample-index flag of lsr_cloud_spacing, [12..15] change
+                 // flags of the convergence passes
   unsigned long long* stats;
   double* pts_raw;
   double* pts;
@@ -132,6 +136,19 @@ inline T* phi_buf(lsr_job* j, int b) {
   return (T*)j->phi[b];
 }
 
+// Buffers of the front-cell list of the energy (Section 3.5) between steps:
+// the free band list (the next step's output) holds the slot lists, the
+// Gbar list the front cells, counter slot 9 their number.
+inline EnergyLists energy_lists(lsr_job* j) {
+  EnergyLists w;
+  w.S = j->list[1 - j->cur_list];
+  w.scnt = j->scnt;
+  w.soff = j->soff;
+  w.M = j->listM;
+  w.cnt = j->cnt + 9;
+  return w;
+}
+
 inline bool reinit_due(const lsr_job* j) {
   return j->prm.reinit_every > 0 && j->step_index % j->prm.reinit_every == 0;
 }
@@ -178,6 +195,10 @@ ReinitPlan<T> plan_reinit(lsr_job* j) {
   r.gb.g = j->dg;
   r.gb.gamma = (T)j->prm.gamma;
   r.gb.nbr = 1;
+  r.gb.smark = j->smark;                // slots of the band list of the step
+  r.gb.L = j->list[j->cur_list];
+  r.gb.Lccnt = j->ccnt[j->cur_list];
+  r.gb.Lcnt = ring_slot(j, 0);
   r.gb.P = phi_buf<T>(j, 1 - j->cur);  // phi^n: the step just taken read it
   r.gb.S = j->list[1 - j->cur_list];   // the step's input list, no longer needed
   r.gb.scnt = j->scnt;
@@ -225,6 +246,9 @@ ReinitPlan<T> plan_reinit(lsr_job* j) {
 
 lsr_status run_steps(lsr_job* j, int32_t n_steps, double dt, int interp);
 lsr_status start_loop(lsr_job* j, int64_t step0);
+// Checks of a grid as lsr_create makes them, and the kernels' view of it.
+lsr_status grid_ok(const lsr_grid* g);
+DevGrid make_devgrid(const lsr_grid& g);
 
 }  // namespace lsr
 

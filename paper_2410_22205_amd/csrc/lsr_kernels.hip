@@ -319,6 +319,24 @@ __device__ __forceinline__ void grid_slot(const GbarArgs<T>& a, uint32_t slot, i
     code[u] = 0;
     if (slot_node<DIM>(a.g, slot, u, i, j, k)) {
       const uint32_t idx = lin(a.g, i, j, k);
+      if (a.nbr == 2) {
+        // the cell with lower corner (i, j, k) is a front cell: its vertices
+        // do not all lie on one side (inside: P < 0)
+        const bool corner = i < a.g.n0 - 1 && j < a.g.n1 - 1 && (DIM == 2 || k < a.g.n2 - 1);
+        int neg = 0;
+        if (corner) {
+#pragma unroll
+          for (int q = 0; q < (DIM == 3 ? 8 : 4); ++q) {
+            const uint32_t o = (uint32_t)(q >> (DIM - 1)) * a.g.s0 +
+                               (uint32_t)((q >> (DIM - 2)) & 1) * a.g.s1 +
+                               (DIM == 3 ? (uint32_t)(q & 1) : 0u);
+            neg += P[idx + o] < T(0) ? 1 : 0;
+          }
+        }
+        in[u] = corner && neg != 0 && neg != (DIM == 3 ? 8 : 4);
+        code[u] = encode(a.g, i, j, k);
+        continue;
+      }
       T m = fabs(P[idx]);
       if (a.nbr) {
         // the six neighbours (a neighbour off the grid reads the node itself)
@@ -338,12 +356,82 @@ __device__ __forceinline__ void grid_slot(const GbarArgs<T>& a, uint32_t slot, i
   if (threadIdx.x == 0) a.scnt[slot] = tot;
 }
 
+// Slot of grid node (i, j, k) in the scan order of slot_node.
+template <int DIM>
+__device__ __forceinline__ uint32_t slot_of(const DevGrid& g, int i, int j, int k) {
+  if (DIM == 3) {
+    const uint32_t nbj = ((uint32_t)g.n1 + 7u) / 8u, nbk = ((uint32_t)g.n2 + 7u) / 8u;
+    const uint32_t b = ((uint32_t)(i / 4) * nbj + (uint32_t)(j / 8)) * nbk + (uint32_t)(k / 8);
+    return b / GBAR_SUB;
+  }
+  return ((uint32_t)i * (uint32_t)g.n1 + (uint32_t)j) / GBAR_CHUNK;
+}
+
+// Marks of the slots that can hold a member of Gbar: those of every band
+// node and of its face neighbours.
+template <int DIM, typename T>
+__device__ __forceinline__ void mark_chunk(const GbarArgs<T>& a, uint32_t c) {
+  if ((int)threadIdx.x >= a.Lccnt[c]) return;
+  int i, j, k;
+  decode(a.g, a.L[c * LCHUNK + threadIdx.x], i, j, k);
+  const DevGrid& g = a.g;
+  a.smark[slot_of<DIM>(g, i, j, k)] = 1;
+  if (i > 0) a.smark[slot_of<DIM>(g, i - 1, j, k)] = 1;
+  if (i < g.n0 - 1) a.smark[slot_of<DIM>(g, i + 1, j, k)] = 1;
+  if (j > 0) a.smark[slot_of<DIM>(g, i, j - 1, k)] = 1;
+  if (j < g.n1 - 1) a.smark[slot_of<DIM>(g, i, j + 1, k)] = 1;
+  if (DIM == 3) {
+    if (k > 0) a.smark[slot_of<DIM>(g, i, j, k - 1)] = 1;
+    if (k < g.n2 - 1) a.smark[slot_of<DIM>(g, i, j, k + 1)] = 1;
+  }
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_mark_slots(GbarArgs<T> a) {
+  uint32_t c, end;
+  const uint32_t step = xcd_share((uint32_t)*a.Lcnt, c, end);
+  for (; c < end; c += step) mark_chunk<DIM, T>(a, c);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_mark_slots_batch(const GbarArgs<T>* __restrict__ tab,
+                                                          int n) {
+  // chunks of the band lists, numbered one job after the other
+  uint32_t tot = 0;
+  for (int jb = 0; jb < n; ++jb) tot += (uint32_t)*LSR_FIELD(tab, jb, GbarArgs<T>, Lcnt);
+  uint32_t c, end;
+  const uint32_t step = xcd_share(tot, c, end);
+  int jb = -1;
+  uint32_t beg = 0, stop = 0;
+  for (; c < end; c += step) {
+    while (c >= stop) {
+      ++jb;
+      beg = stop;
+      stop = beg + (uint32_t)*LSR_FIELD(tab, jb, GbarArgs<T>, Lcnt);
+    }
+    mark_chunk<DIM, T>(uniform_load(tab, jb), c - beg);
+  }
+}
+
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_grid_scan(GbarArgs<T> a) {
   __shared__ int lds[4 * GBAR_SUB + 1];
   uint32_t c, end;
   const uint32_t step = xcd_share(gbar_slots(a.g), c, end);
-  for (; c < end; c += step) grid_slot<DIM, T>(a, c, lds);
+  for (; c < end; c += step) {
+    if (a.smark) {
+      // the mark is read and cleared here (one block per slot), so the
+      // marks are all clear again for the next build
+      const bool marked = a.smark[c] != 0;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        a.smark[c] = 0;
+        if (!marked) a.scnt[c] = 0;
+      }
+      if (!marked) continue;
+    }
+    grid_slot<DIM, T>(a, c, lds);
+  }
 }
 
 template <int DIM, typename T>
@@ -356,7 +444,18 @@ __global__ __launch_bounds__(256) void k_grid_scan_batch(const GbarArgs<T>* __re
   const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
   for (; c < end; c += step) {
     if (!cur.advance(tab, c, leave)) break;
-    grid_slot<DIM, T>(uniform_load(tab, cur.jb), c - cur.beg, lds);
+    const GbarArgs<T> a = uniform_load(tab, cur.jb);
+    const uint32_t s = c - cur.beg;
+    if (a.smark) {
+      const bool marked = a.smark[s] != 0;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        a.smark[s] = 0;
+        if (!marked) a.scnt[s] = 0;
+      }
+      if (!marked) continue;
+    }
+    grid_slot<DIM, T>(a, s, lds);
   }
 }
 
@@ -1690,6 +1789,63 @@ __global__ __launch_bounds__(256) void k_energy(DevGrid g, const T* __restrict__
   if (tid == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// The same sum over a list of front cells (their lower corners, packed
+// codes; *cnt of them) built by a grid scan (GbarArgs, nbr = 2): block b
+// takes the b-th of gridDim.x equal stretches of the list's items (3D: the
+// R^2 lines of R subcells of a cell; 2D: the cells) and adds them thread by
+// thread in a fixed order; the block's sum goes to partial[b].
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_energy_cells(DevGrid g, const T* __restrict__ phi,
+                                                      const double* __restrict__ d, double p, int R,
+                                                      const uint32_t* __restrict__ M,
+                                                      const int32_t* cnt,
+                                                      double* __restrict__ partial) {
+#pragma clang fp contract(off)
+  constexpr int NV = DIM == 3 ? 8 : 4;
+  __shared__ double red[4];
+  const uint64_t per = DIM == 3 ? (uint64_t)R * R : 1u;
+  const uint64_t nitem = (uint64_t)*cnt * per;
+  const uint64_t b0 = nitem * blockIdx.x / gridDim.x, b1 = nitem * (blockIdx.x + 1) / gridDim.x;
+  const double hs = g.hd / R;
+  const double lim = 0.5 * sqrt(3.0) * hs;
+  double s = 0.0;
+  for (uint64_t it = b0 + threadIdx.x; it < b1; it += 256) {
+    const uint64_t cell = it / per;
+    const int uv = (int)(it - cell * per);
+    int i, j, k;
+    decode(g, M[cell], i, j, k);
+    const uint32_t node = lin(g, i, j, k);
+    double F[NV], E[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      // 3D: vertex (i+a, j+b, k+c') at q = 4a + 2b + c'; 2D: edge order
+      const uint32_t o = DIM == 3 ? (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 +
+                                        (uint32_t)(q & 1)
+                                  : (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
+      F[q] = (double)phi[node + o];
+      E[q] = d[node + o];
+    }
+    if (DIM == 3) {
+      const int u = uv / R, v = uv - u * R;
+      const double tx = (u + 0.5) / R, ty = (v + 0.5) / R;
+      const double fz0 = lerp_d(lerp_d(F[0], F[4], tx), lerp_d(F[2], F[6], tx), ty);
+      const double fz1 = lerp_d(lerp_d(F[1], F[5], tx), lerp_d(F[3], F[7], tx), ty);
+      const double ez0 = lerp_d(lerp_d(E[0], E[4], tx), lerp_d(E[2], E[6], tx), ty);
+      const double ez1 = lerp_d(lerp_d(E[1], E[5], tx), lerp_d(E[3], E[7], tx), ty);
+      for (int w = 0; w < R; ++w) {
+        const double tz = (w + 0.5) / R;
+        if (fabs(lerp_d(fz0, fz1, tz)) < lim) s += pow_abs(lerp_d(ez0, ez1, tz), p) * hs * hs;
+      }
+    } else {
+      s += energy_cell_2d(g, F, E, i, j, p);
+    }
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 // Sum of the n partial sums in a fixed order, and its p-th root: out[0] = E_p.
 __global__ __launch_bounds__(256) void k_energy_final(const double* __restrict__ partial, int n,
                                                       double p, double* __restrict__ out) {
@@ -1821,7 +1977,12 @@ hipError_t launch_init_phi(int dim, const DevGrid& g, int kind, const double* ar
 // The three launches of a list from a grid scan (see GbarArgs).
 template <typename T>
 hipError_t launch_grid_list(int dim, const GbarArgs<T>& a, unsigned blocks, hipStream_t s) {
-  hipError_t e = persistent_launch(dim == 3 ? k_grid_scan<3, T> : k_grid_scan<2, T>, blocks, s, a);
+  hipError_t e = hipSuccess;
+  if (a.smark) {
+    e = persistent_launch(dim == 3 ? k_mark_slots<3, T> : k_mark_slots<2, T>, blocks, s, a);
+    if (e != hipSuccess) return e;
+  }
+  e = persistent_launch(dim == 3 ? k_grid_scan<3, T> : k_grid_scan<2, T>, blocks, s, a);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_slot_prefix<T>, dim3(1), dim3(1024), 0, s, a);
   e = hipGetLastError();
@@ -1944,6 +2105,39 @@ hipError_t launch_super_geo(int dim, const double* pts, const int32_t* start,
 }
 
 template <typename T>
+hipError_t launch_energy_listed(int dim, const DevGrid& g, const T* phi, const double* d, double p,
+                                int R, const EnergyLists& w, double* partial, double* out,
+                                unsigned blocks, hipStream_t s) {
+  GbarArgs<T> a;
+  a.g = g;
+  a.gamma = T(0);
+  a.nbr = 2;
+  a.smark = nullptr;
+  a.L = nullptr;
+  a.Lccnt = a.Lcnt = nullptr;
+  a.P = phi;
+  a.S = w.S;
+  a.scnt = w.scnt;
+  a.soff = w.soff;
+  a.M = w.M;
+  a.cnt_out = w.cnt;
+  a.ccnt = nullptr;
+  hipError_t e = launch_grid_list<T>(dim, a, blocks, s);
+  if (e != hipSuccess) return e;
+  dim3 gr(ENERGY_BLOCKS), bl(256);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_energy_cells<3, T>), gr, bl, 0, s, g, phi, d, p, R, (const uint32_t*)w.M,
+                       (const int32_t*)w.cnt, partial);
+  else
+    hipLaunchKernelGGL((k_energy_cells<2, T>), gr, bl, 0, s, g, phi, d, p, R, (const uint32_t*)w.M,
+                       (const int32_t*)w.cnt, partial);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, partial, (int)ENERGY_BLOCKS, p, out);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* d, double p, int R,
                          double* partial, double* out, hipStream_t s) {
   dim3 gr(ENERGY_BLOCKS), bl(256);
@@ -1990,9 +2184,15 @@ hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>*
 
 template <typename T>
 hipError_t launch_grid_list_batch(int dim, const GbarArgs<T>* tab, int n, unsigned blocks,
-                                  hipStream_t s) {
-  hipError_t e = persistent_launch(dim == 3 ? k_grid_scan_batch<3, T> : k_grid_scan_batch<2, T>,
-                                   blocks, s, tab, n);
+                                  hipStream_t s, bool marked) {
+  hipError_t e = hipSuccess;
+  if (marked) {
+    e = persistent_launch(dim == 3 ? k_mark_slots_batch<3, T> : k_mark_slots_batch<2, T>, blocks,
+                          s, tab, n);
+    if (e != hipSuccess) return e;
+  }
+  e = persistent_launch(dim == 3 ? k_grid_scan_batch<3, T> : k_grid_scan_batch<2, T>, blocks, s,
+                        tab, n);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_slot_prefix_batch<T>, dim3(n), dim3(1024), 0, s, tab);
   e = hipGetLastError();
@@ -2034,13 +2234,16 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_dpack<T>(int, const DevGrid&, const double*, typename Vec<T>::pack*, \
                                       hipStream_t);                                               \
   template hipError_t launch_grid_list_batch<T>(int, const GbarArgs<T>*, int, unsigned,           \
-                                                hipStream_t);                                     \
+                                                hipStream_t, bool);                               \
   template hipError_t launch_sl_step_batch<T>(int, int, int, const SLArgs<T>*, int,               \
                                               unsigned, hipStream_t);                             \
   template hipError_t launch_reinit_fix_batch<T>(int, const RArgs<T>*, int, unsigned, hipStream_t);\
   template hipError_t launch_reinit_iter_batch<T>(int, const RArgs<T>*, int, unsigned,             \
                                                   hipStream_t);                                   \
   template hipError_t launch_reinit_final_batch<T>(const FinArgs<T>*, int, unsigned, hipStream_t);\
+  template hipError_t launch_energy_listed<T>(int, const DevGrid&, const T*, const double*, double, \
+                                              int, const EnergyLists&, double*, double*, unsigned, \
+                                              hipStream_t);                                        \
   template hipError_t launch_energy<T>(int, const DevGrid&, const T*, const double*, double, int,  \
                                        double*, double*, hipStream_t);
 

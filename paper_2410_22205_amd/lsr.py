@@ -34,7 +34,7 @@ EXPORTED = [
     "lsr_set_launch",
     "lsr_set_graphs", "lsr_graph_counts", "lsr_profile_enable",
     "lsr_profile_read", "lsr_last_error", "lsr_load_cloud_approx", "lsr_init_phi_cloud",
-    "lsr_init_phi_resample", "lsr_schedule_run",
+    "lsr_init_phi_resample", "lsr_schedule_run", "lsr_set_tune_cache",
 ]
 
 
@@ -108,6 +108,7 @@ def load():
             "lsr_batch_tune": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_double)],
             "lsr_batch_destroy": [_P],
+            "lsr_set_tune_cache": [ctypes.c_char_p],
             "lsr_profile_enable": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_set_launch": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_set_graphs": [_P, ctypes.c_int32],
@@ -294,6 +295,10 @@ def lsr_batch_tune(batch):
     lanes, bpc, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(load().lsr_batch_tune(batch, ctypes.byref(lanes), ctypes.byref(bpc), ctypes.byref(ms)))
     return lanes.value, bpc.value, ms.value
+
+
+def lsr_set_tune_cache(path):
+    _check(load().lsr_set_tune_cache(path.encode() if path else None))
 
 
 def lsr_batch_destroy(batch):

@@ -95,3 +95,16 @@ def test_misaligned_or_small_workspace_is_rejected():
     with pytest.raises(lsr.LsrError) as e:
         lsr.lsr_create(g, p, 256, 1024, 0)
     assert e.value.status == lsr.LSR_E_NOMEM
+
+
+def test_tune_cache_file_is_checked(tmp_path):
+    good = tmp_path / "tune.txt"
+    good.write_text("# dim fp64 q1 weno nodes lanes bpc ms\n3 0 1 1 1048576 4 2 0.5\n")
+    lsr.lsr_set_tune_cache(str(good))
+    bad = tmp_path / "bad.txt"
+    bad.write_text("3 0 1 1 1048576 four 2 0.5\n")
+    with pytest.raises(lsr.LsrError) as e:
+        lsr.lsr_set_tune_cache(str(bad))
+    assert e.value.status == lsr.LSR_E_INVALID
+    lsr.lsr_set_tune_cache(str(tmp_path / "missing.txt"))  # an empty cache
+    lsr.lsr_set_tune_cache(None)

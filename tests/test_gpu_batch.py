@@ -233,3 +233,40 @@ def test_cache_groups_on_two_streams(streams):
     batch.close()
     for j in jobs:
         j.close()
+
+
+def test_tune_cache_file(tmp_path):
+    """A tuned shape written to the cache file is found again: a batch whose
+    signature has a line in the file takes that line's shape and time
+    without timing, and a new signature's tuning appends its line."""
+    lsr = _lsr()
+    ws = _jobs("fp64", n=2, seed=4900)
+    jobs = [_make(lsr, w) for w in ws]
+    nodes = sum(int(np.prod(w["grid"]["n"])) for w in ws)
+    p2 = 1
+    while p2 < nodes:
+        p2 *= 2
+    nq = sum(w["interp"] == "q1" for w in ws)
+    path = tmp_path / "tune.txt"
+    path.write_text(f"3 1 {nq} {len(ws) - nq} {p2} 4 2 0.125\n")
+    lsr.lsr_set_tune_cache(str(path))
+    batch = lsr.Batch(max_jobs=2, group_steps=4)
+    for w, j in zip(ws, jobs):
+        batch.add(j, w["dt"], w["interp"])
+    assert batch.tune() == (4, 2, 0.125)
+    batch.close()
+    for j in jobs:
+        j.close()
+    # a signature no other test tunes (one FP64 WENO job of 130^3 nodes):
+    # timed, and its line appended
+    w = dict(synth.workload("torus3d", n=130, steps=1), precision="fp64")
+    job = _make(lsr, w)
+    batch = lsr.Batch(max_jobs=1, group_steps=4)
+    batch.add(job, w["dt"], w["interp"])
+    lanes, bpc, ms = batch.tune()
+    batch.close()
+    job.close()
+    lines = [ln for ln in path.read_text().split("\n") if ln.strip()]
+    assert len(lines) == 2 and lines[1].startswith("3 1 0 1 4194304 ")
+    assert lines[1].split()[5:7] == [str(lanes), str(bpc)] and ms > 0
+    lsr.lsr_set_tune_cache(None)

@@ -99,12 +99,16 @@ def check_phi(phi_gpu, phi_orc, h, tol):
     return worst / h
 
 
-def check_band(band_gpu, phi_gpu, phi_orc, gamma, h):
-    # the device's own band list is exactly {|phi_gpu| < gamma} in its precision
+def check_band(band_gpu, phi_gpu, phi_orc, gamma, h, margin=1e-6):
+    """The device's own band list is exactly {|phi_gpu| < gamma} in its
+    precision, and agrees with the oracle's band at every node whose oracle
+    value lies farther than margin * h from gamma (1e-6 h; for an FP32 state
+    compared step by step, the value bar of that comparison, since the
+    values themselves differ by up to that)."""
     g = phi_gpu.dtype.type(gamma)
     np.testing.assert_array_equal(band_gpu, (np.abs(phi_gpu) < g).astype(np.uint8))
     want = np.abs(phi_orc) < gamma
-    sure = np.abs(np.abs(phi_orc) - gamma) > 1e-6 * h
+    sure = np.abs(np.abs(phi_orc) - gamma) > margin * h
     bad = (band_gpu.astype(bool) != want) & sure
     assert not bad.any(), f"{int(bad.sum())} band nodes differ away from the threshold"
 
@@ -347,28 +351,17 @@ def test_full_run_torus3d_full_size_fp64():
           f"Err_S {eg / h:.4f} h vs {eo / h:.4f} h")
 
 
-def test_union3d_first_steps():
-    """The 256^3 non-uniform workload, FP64 state: within 1e-4 h from phi0
-    over the first 12 steps (one reinitialisation); each of the first 20
-    steps (two reinitialisations) within 1e-10 h of the oracle's step from
-    the device's state."""
-    w = synth.workload("union3d", steps=12)
-    h = w["grid"]["h"]
-    d = oracle.distance(w["points"], w["grid"])
-    phi, band, nb, si, cnt, _ = gpu_run(w, d=d, precision="fp64")
-    ophi, counts, _, prm = oracle_run(w, d=d)
-    check_phi(phi, ophi, h, 1e-4)
-    check_band(band, phi, ophi, prm["gamma"], h)
-    step_err, where = stepwise_errors(w, 20, d)
-    assert step_err <= 1e-10, (step_err, where)
-
-
 def test_fp32_torus3d_full_size():
     """FP32 state on the 128^3 workload: the first steps within 1e-4 h of the
-    oracle; each of the 300 steps within 1e-4 h of the oracle's FP64 step
-    from the device's FP32 state (band-exact away from the threshold); after
-    the 300 steps the reconstruction attaches to the cloud as the oracle's
-    does (cloud error within 0.02 h) and the band work agrees within 1 %."""
+    oracle; each of the 300 steps within 2e-5 h of the oracle's FP64 step
+    from the device's FP32 state (band-exact away from the threshold): one
+    FP32 update rounds its ~2,700 operations on values up to gamma = 6h, and
+    the largest error over the run's 6e7 updates is about 19 FP32 ulps of
+    gamma (1.3e-5 h), where the small-grid one-step tests see 1e-5 h; after
+    the 300 steps the mean deviation from the oracle over the band is at most
+    twice what a 2^-24 relative perturbation of phi0 (the FP32 state's
+    resolution) makes the oracle's own run deviate, with the same attachment
+    to the cloud (Err_S within 0.02 h) and band work within 1 %."""
     w = synth.workload("torus3d", steps=5)
     h = w["grid"]["h"]
     phi, band, _, _, _, _ = gpu_run(w, precision="fp32")
@@ -376,17 +369,239 @@ def test_fp32_torus3d_full_size():
     ophi, _, _, prm = oracle_run(w, d=d)
     check_phi(phi, ophi, h, 1e-4)
     step_err, where = stepwise_errors(synth.workload("torus3d"), 300, d, precision="fp32")
-    assert step_err <= 1e-4, (step_err, where)
+    assert step_err <= 2e-5, (step_err, where)
     print(f"fp32 torus3d stepwise max {step_err:.2e} h at {where}")
     w = synth.workload("torus3d")
     phi, band, nb, si, cnt, _ = gpu_run(w, precision="fp32")
     ophi, counts, _, prm = oracle_run(w, d=d)
-    eg = _err_cloud(phi.astype(np.float64), w["grid"], w["points"])
+    pphi = _perturbed_oracle(w, d, w["steps"], rel=2.0 ** -24)
+    phi = phi.astype(np.float64)
+    sel = (np.abs(ophi) < prm["gamma"]) | (np.abs(phi) < prm["gamma"])
+    gpu_mean = np.abs(phi - ophi)[sel].mean()
+    env_mean = np.abs(pphi - ophi)[sel].mean()
+    assert gpu_mean <= 2 * env_mean, (gpu_mean / h, env_mean / h)
+    eg = _err_cloud(phi, w["grid"], w["points"])
     eo = _err_cloud(ophi, w["grid"], w["points"])
     assert abs(eg - eo) < 0.02 * h, (eg / h, eo / h)
     assert abs(cnt["node_updates"] - counts[0]) < 0.01 * counts[0]
-    print(f"fp32 torus3d: Err_S gpu {eg / h:.4f} h oracle {eo / h:.4f} h, "
-          f"max |dphi| {np.abs(phi - ophi).max() / h:.2e} h")
+    print(f"fp32 torus3d: Err_S gpu {eg / h:.4f} h oracle {eo / h:.4f} h, mean |dphi| "
+          f"{gpu_mean / h:.2e} h vs envelope {env_mean / h:.2e} h, max "
+          f"{np.abs(phi - ophi).max() / h:.2e} h")
+
+
+def sampled_stepwise(w, steps, d, precision, n_sample=20000, full_every=5, seed=7):
+    """Stepwise parity at full size on sampled nodes, in the launch shape the
+    bench times.  After every step the device's values at n_sample nodes of
+    the previous band (a fresh seeded sample each step) must equal the
+    oracle's update of those nodes from the device's previous state, and a
+    sample of the other nodes must have kept their values exactly; the
+    device's band mask must be exactly {|phi| < gamma} of its own state.  At
+    every full_every-th reinitialisation the whole state is compared with the
+    oracle's step plus reinitialisation from the device's previous state,
+    band membership included.  Returns (worst sampled error, worst full-check
+    error) in units of h and where the worst sampled one was."""
+    lsr = _lsr()
+    g = w["grid"]
+    h = g["h"]
+    oprm = oracle_params(w)
+    prm = {k: oprm[k] for k in ("gamma", "beta", "reinit_every", "reinit_iters", "reinit_dtau")}
+    prm["precision"] = precision
+    if precision == "fp32":
+        oprm = dict(oprm, gamma=float(np.float32(oprm["gamma"])))
+    gam = oprm["gamma"]
+    band_margin = 1e-6 if precision == "fp64" else 2e-5
+    job = lsr.Job(g, prm)
+    job.set_distance(d)
+    job.init_phi(w["phi0"][0], w["phi0"][1])
+    prev = job.extract()[0].astype(np.float64).ravel()
+    rng = np.random.default_rng(seed)
+    K = oprm["reinit_every"]
+    worst, worst_full, where, reinits = 0.0, 0.0, None, 0
+    for s in range(steps):
+        job.step(1, w["dt"], w["interp"])
+        cur, band, nb, si = job.extract()
+        assert si == s + 1
+        flat = cur.ravel()
+        np.testing.assert_array_equal(band.ravel(),
+                                      (np.abs(flat) < flat.dtype.type(gam)).astype(np.uint8))
+        cur64 = flat.astype(np.float64)
+        if K > 0 and (s + 1) % K == 0:
+            reinits += 1
+            if reinits % full_every == 0:
+                if precision == "fp64":
+                    ref, _ = oracle.run(prev.reshape(cur.shape), d, g, oprm, w["dt"],
+                                        w["interp"], 1, step0=s)
+                else:
+                    ref = _reinit_from_device_step(lsr, g, prm, d, prev, cur, s, w, oprm, h)
+                err = np.abs(cur64 - ref.ravel())
+                worst_full = max(worst_full, float(err.max()) / h)
+                want = np.abs(ref.ravel()) < gam
+                sure = np.abs(np.abs(ref.ravel()) - gam) > band_margin * h
+                bad = ((np.abs(cur64) < gam) != want) & sure
+                if bad.any():
+                    print(f"  step {s + 1}: {int(bad.sum())} band nodes differ, their values by up "
+                          f"to {err[bad].max() / h:.2e} h, the state by {err.max() / h:.2e} h",
+                          flush=True)
+                assert not bad.any(), (s + 1, int(bad.sum()), float(err[bad].max()) / h)
+        else:
+            inside = np.flatnonzero(np.abs(prev) < gam)
+            if len(inside):
+                idx = rng.choice(inside, size=min(n_sample, len(inside)), replace=False)
+                vals, _ = oracle.sl_nodes(prev.reshape(cur.shape), d, g, oprm, w["dt"],
+                                          w["interp"], idx)
+                e = np.abs(cur64[idx] - vals)
+                if e.max() / h > worst:
+                    worst = float(e.max()) / h
+                    where = (s + 1, int(idx[int(e.argmax())]))
+                # band membership at the sample, away from the threshold
+                sure = np.abs(np.abs(vals) - gam) > band_margin * h
+                assert not (((np.abs(cur64[idx]) < gam) != (np.abs(vals) < gam)) & sure).any()
+            rest = rng.integers(0, len(prev), size=n_sample)
+            rest = rest[np.abs(prev[rest]) >= gam]
+            np.testing.assert_array_equal(cur64[rest], prev[rest])
+        prev = cur64
+        if (s + 1) % 100 == 0:
+            print(f"  step {s + 1}: sampled max {worst:.2e} h, full checks max {worst_full:.2e} h",
+                  flush=True)
+    job.close()
+    return worst, worst_full, where
+
+
+def _reinit_from_device_step(lsr, g, prm, d, prev, cur, s, w, oprm, h):
+    """For an FP32 state at a reinitialisation step: the oracle's
+    reinitialisation of the device's own post-step state.  The interface
+    set of the reinitialisation is decided by the signs of values near
+    zero, which an FP64 step and an FP32 step may round to either side; so
+    the step and the reinitialisation are checked separately, each from the
+    device's own input: a twin job without reinitialisation takes the same
+    step from the same state (bitwise the same post-step state), its values
+    are checked against the oracle's update on the band, and the oracle
+    reinitialises them on the pre-update band."""
+    twin = lsr.Job(g, dict(prm, reinit_every=0))
+    twin.set_distance(d)
+    twin.init_phi(phi0=prev.reshape(cur.shape).astype(np.float32), step0=s)
+    twin.step(1, w["dt"], w["interp"])
+    post = twin.extract()[0].astype(np.float64)
+    twin.close()
+    prev3 = prev.reshape(cur.shape)
+    band = (np.abs(prev3) < oprm["gamma"]).astype(np.uint8)
+    idx = np.flatnonzero(band.ravel())[::50]
+    vals, _ = oracle.sl_nodes(prev3, d, g, oprm, w["dt"], w["interp"], idx)
+    assert np.abs(post.ravel()[idx] - vals).max() <= 2e-5 * h
+    ref, _ = oracle.reinit(post, band, g, oprm)
+    return ref
+
+
+_UNION_D = {}
+
+
+def union_distance():
+    """The oracle's exact distance field of the 256^3 union workload, kept
+    for the tests of this module."""
+    if "d" not in _UNION_D:
+        import time
+        w = synth.workload("union3d")
+        t0 = time.perf_counter()
+        _UNION_D["d"] = oracle.distance(w["points"], w["grid"])
+        print(f"oracle distance field of the 256^3 union: {time.perf_counter() - t0:.1f} s",
+              flush=True)
+    return _UNION_D["d"]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_union3d_full_size(precision):
+    """The 256^3 non-uniform workload (200k points, density ramp, two holes,
+    WENO, dt = h/2, reinit every 10 steps), in the launch shape the bench
+    times.  Every one of the 400 steps is checked against the oracle's step
+    from the device's previous state on 20k sampled band nodes (1e-10 h in
+    FP64; 2e-5 h in FP32, the FP32 state's own rounding, see
+    test_fp32_torus3d_full_size), with every fifth reinitialisation checked
+    on the whole grid.  From phi0, the scheme amplifies rounding near the
+    poles of the initial sphere (tests/test_oracle_sensitivity.py): the FP64
+    state stays within 1e-4 h of the oracle (band-exact away from the
+    threshold) over the first 12 steps, one reinitialisation included; the
+    FP32 state within 1e-4 h over the first 2 steps, and over 12 steps within
+    twice the deviation that a 2^-24 relative perturbation of phi0 (the FP32
+    state's resolution) makes in the oracle's own run, in the mean over the
+    band and at the worst node."""
+    d = union_distance()
+    w = synth.workload("union3d")
+    h = w["grid"]["h"]
+    bar = 1e-10 if precision == "fp64" else 2e-5
+    worst, worst_full, where = sampled_stepwise(w, w["steps"], d, precision)
+    assert worst <= bar, (worst, where)
+    assert worst_full <= bar, worst_full
+    w = synth.workload("union3d", steps=12 if precision == "fp64" else 2)
+    phi, band, nb, si, cnt, _ = gpu_run(w, d=d, precision=precision)
+    ophi, counts, _, prm = oracle_run(w, d=d)
+    e0 = check_phi(phi, ophi, h, 1e-4)
+    gam = float(np.float32(prm["gamma"])) if precision == "fp32" else prm["gamma"]
+    check_band(band, phi, ophi, gam, h)
+    msg = (f"union3d {precision}: 400 steps sampled max {worst:.2e} h at {where}, full "
+           f"reinitialisation checks max {worst_full:.2e} h; {w['steps']} steps from phi0 max "
+           f"|dphi| {e0:.2e} h")
+    if precision == "fp32":
+        w = synth.workload("union3d", steps=12)
+        phi, band, nb, si, cnt, _ = gpu_run(w, d=d, precision=precision)
+        ophi, counts, _, prm = oracle_run(w, d=d)
+        pphi = _perturbed_oracle(w, d, w["steps"], rel=2.0 ** -24)
+        phi = phi.astype(np.float64)
+        sel = (np.abs(ophi) < prm["gamma"]) | (np.abs(phi) < prm["gamma"])
+        dev, env = np.abs(phi - ophi), np.abs(pphi - ophi)
+        assert dev[sel].mean() <= 2 * env[sel].mean(), (dev[sel].mean() / h, env[sel].mean() / h)
+        assert dev.max() <= max(2 * env.max(), 1e-4 * h), (dev.max() / h, env.max() / h)
+        msg += (f"; 12 steps mean {dev[sel].mean() / h:.2e} h (envelope "
+                f"{env[sel].mean() / h:.2e} h), max {dev.max() / h:.2e} h (envelope "
+                f"{env.max() / h:.2e} h)")
+    print(msg)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_union3d_96_whole_run(precision):
+    """The union workload at 96^3 through all 400 steps: at this size the
+    run does not amplify rounding (a relative 2^-24 perturbation of phi0
+    leaves the oracle's end state within 1e-16 h in the mean), so the whole
+    run is held to 1e-4 h of the oracle, band-exact away from the threshold,
+    with the same attachment to the cloud (Err_S within 0.02 h)."""
+    w = synth.workload("union3d", n=96)
+    h = w["grid"]["h"]
+    d = oracle.distance(w["points"], w["grid"])
+    phi, band, nb, si, cnt, _ = gpu_run(w, d=d, precision=precision)
+    ophi, counts, _, prm = oracle_run(w, d=d)
+    e = check_phi(phi, ophi, h, 1e-4)
+    gam = float(np.float32(prm["gamma"])) if precision == "fp32" else prm["gamma"]
+    check_band(band, phi, ophi, gam, h)
+    # nodes whose value sits at gamma to rounding stay there (c(gamma) = 0)
+    # and are counted in the band or not by the last bit, step after step
+    assert abs(cnt["node_updates"] - counts[0]) <= 1e-4 * counts[0]
+    eg = _err_cloud(phi.astype(np.float64), w["grid"], w["points"])
+    eo = _err_cloud(ophi, w["grid"], w["points"])
+    assert abs(eg - eo) < 0.02 * h, (eg / h, eo / h)
+    print(f"union3d 96^3 {precision}: 400 steps max |dphi| {e:.2e} h; Err_S {eg / h:.4f} h "
+          f"vs {eo / h:.4f} h")
+
+
+def test_torus_reaches_the_cloud():
+    """Sanity of the method on the 128^3 torus workload (not parity; the
+    steps are checked against the oracle above): run on to 600 steps, the
+    zero level set attaches to the cloud, Err_S of eq. (errCloud) below
+    0.5 h, and lies within O(h) of the closed-form torus, the mean
+    |phi - SDF| over the nodes within gamma of the torus below h.  At the
+    workload's 300 steps the front is still closing the torus's hole: the
+    oracle's Err_S is 1.34 h there, 0.62 h at 400, 0.30 h at 500 and 0.25 h
+    from 600 steps on, with delta = 0 as with delta = 1."""
+    w = synth.workload("torus3d", steps=600)
+    g = w["grid"]
+    h = g["h"]
+    phi = gpu_run(w, precision="fp32")[0].astype(np.float64)
+    X = oracle.node_coords(g)
+    rho = np.sqrt(X[:, 0] ** 2 + X[:, 1] ** 2) - 0.5
+    sdf = (np.sqrt(rho ** 2 + X[:, 2] ** 2) - 0.2).reshape(g["n"])
+    near = np.abs(sdf) < w["gamma"]
+    l1 = float(np.abs(phi - sdf)[near].mean())
+    es = _err_cloud(phi, g, w["points"])
+    assert es < 0.5 * h and l1 < h, (es / h, l1 / h)
+    print(f"torus at 600 steps: Err_S {es / h:.3f} h, mean |phi - SDF| near the surface {l1 / h:.3f} h")
 
 
 # ------------------------------------------------------- reinitialisation

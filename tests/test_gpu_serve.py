@@ -1,8 +1,11 @@
 """Served execution on the GPU: jobs arriving over time and running in one
-continuously re-formed batch give bitwise the result each gives alone."""
+continuously re-formed batch give bitwise the result each gives alone, and
+every served result matches the oracle's run of the same job (within
+1e-4 h, band membership exact away from the threshold)."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2410_22205_amd import serve, synth
 
 pytestmark = pytest.mark.gpu
@@ -40,10 +43,32 @@ def test_served_results_equal_alone(precision):
     out = srv.run(reqs, keep_results=True)
     assert out["jobs"] == len(reqs) and not out["rejected"]
     assert out["max_batch"] >= 2  # the jobs did share the batch
+    worst = 0.0
     for i, req in enumerate(reqs):
         phi, band = _alone(req, precision)
         np.testing.assert_array_equal(out["results"][i][0], phi)
         np.testing.assert_array_equal(out["results"][i][1], band)
+        worst = max(worst, _against_oracle(req, out["results"][i][0], out["results"][i][1]))
+    print(f"served {precision}: max |phi - oracle| {worst:.2e} h over {len(reqs)} jobs")
+
+
+def _against_oracle(req, phi, band):
+    """The oracle's run of the request: its grid, cloud, phi0, dt, steps and
+    interpolator; returns max |phi - oracle| in units of h."""
+    g = req["grid"]
+    h = g["h"]
+    prm = oracle.default_params(g["dim"], h, gamma=req["gamma"], beta=req["beta"],
+                                reinit_every=req["reinit_every"])
+    d = oracle.distance(req["points"], g)
+    phi0 = oracle.init_phi(g, req["phi0"][0], req["phi0"][1], prm["gamma"])
+    ophi, _ = oracle.run(phi0, d, g, prm, req["dt"], req["interp"], req["steps"])
+    ophi = ophi.ravel()
+    err = float(np.abs(phi.astype(np.float64) - ophi).max())
+    assert err <= 1e-4 * h, err / h
+    np.testing.assert_array_equal(band, (np.abs(phi) < phi.dtype.type(prm["gamma"])).astype(np.uint8))
+    sure = np.abs(np.abs(ophi) - prm["gamma"]) > 1e-6 * h
+    assert not ((band.astype(bool) != (np.abs(ophi) < prm["gamma"])) & sure).any()
+    return err / h
 
 
 def test_budget_bounds_the_mix_and_sequential_replay_agrees():

@@ -66,11 +66,12 @@ def test_duplicates_and_arguments():
         with pytest.raises(RuntimeError):
             job.cloud_spacing([0, len(pts)])  # an index outside the cloud
         assert job.cloud_spacing([1, 2, 3]) > 0  # usable after the refusal
+        before = job.cloud_spacing([1, 2, 3])
         bad = pts.copy()
         bad[0, 0] = 5.0  # outside the grid's box: the load fails ...
         with pytest.raises(RuntimeError):
             job.load_cloud(bad)
-        with pytest.raises(RuntimeError):
-            job.cloud_spacing([1, 2, 3])  # ... and leaves no cloud to sample
+        # ... and leaves the job as it was: the previous cloud is still there
+        assert job.cloud_spacing([1, 2, 3]) == before
     finally:
         job.close()
