@@ -382,6 +382,26 @@ lsr_status lsr_graph_counts(lsr_job* job, lsr_batch* batch, int64_t* captured, i
 lsr_status lsr_profile_enable(lsr_job* job, int32_t enable, int32_t max_launches);
 lsr_status lsr_profile_read(lsr_job* job, double* total_ms, int64_t* launches);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * energy functional of lsr_energy (Section 3.5, same kernels up to the order
+ * of summation) of nodal fields the caller holds, without a job or a
+ * workspace.  grid: as for lsr_create (nodes < 2^32); dev_phi: device, one
+ * value per node in `precision` (LSR_FP32 or LSR_FP64), C order; dev_d:
+ * device, one double per node; p finite > 0; R in 1..64; dev_out: device,
+ * one double, receives E_p.  The kernels' per-block partial sums live in a
+ * file-scope device array of this library (1024 doubles, 8 KiB, one copy per
+ * device, held until the process ends; every block writes its own slot on
+ * every call, so nothing needs clearing); its address is taken once per
+ * device, with that device current, on the first call.  Calls that overlap
+ * on one device race on that array; calls on different devices do not.
+ * Enqueued on hip_stream (NULL = default stream), no synchronisation, no
+ * allocation.  LSR_E_INVALID for bad arguments, LSR_E_UNSUPPORTED for a
+ * grid of 2^32 nodes or more or a device index above 63. */
+lsr_status lsr_energy_noalloc(const lsr_grid* grid, int32_t precision, const void* dev_phi,
+                              const double* dev_d, double p, int32_t R, double* dev_out,
+                              void* hip_stream);
+
 /* Text of the last error on this host thread; valid until the next call. */
 const char* lsr_last_error(void);
 

@@ -34,7 +34,7 @@ EXPORTED = [
     "lsr_set_launch",
     "lsr_set_graphs", "lsr_graph_counts", "lsr_profile_enable",
     "lsr_profile_read", "lsr_last_error", "lsr_load_cloud_approx", "lsr_init_phi_cloud",
-    "lsr_init_phi_resample", "lsr_schedule_run", "lsr_set_tune_cache",
+    "lsr_init_phi_resample", "lsr_schedule_run", "lsr_set_tune_cache", "lsr_energy_noalloc",
 ]
 
 
@@ -109,6 +109,8 @@ def load():
                                ctypes.POINTER(ctypes.c_double)],
             "lsr_batch_destroy": [_P],
             "lsr_set_tune_cache": [ctypes.c_char_p],
+            "lsr_energy_noalloc": [GP, ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_int32, _P,
+                                   _P],
             "lsr_profile_enable": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_set_launch": [_P, ctypes.c_int32, ctypes.c_int32],
             "lsr_set_graphs": [_P, ctypes.c_int32],
@@ -295,6 +297,13 @@ def lsr_batch_tune(batch):
     lanes, bpc, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(load().lsr_batch_tune(batch, ctypes.byref(lanes), ctypes.byref(bpc), ctypes.byref(ms)))
     return lanes.value, bpc.value, ms.value
+
+
+def lsr_energy_noalloc(grid, precision, phi_ptr, d_ptr, p, R, out_ptr, stream_ptr):
+    """E_p of device fields into the device double at out_ptr, with no job,
+    workspace or allocation (see lsr.h)."""
+    return load().lsr_energy_noalloc(ctypes.byref(grid), int(precision), _P(phi_ptr), _P(d_ptr),
+                                     float(p), int(R), _P(out_ptr), _P(stream_ptr))
 
 
 def lsr_set_tune_cache(path):
