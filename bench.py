@@ -43,7 +43,8 @@ BYTES_PER_UPDATE = {"fp32": 4 + 4 + 16 + 4 + 4, "fp64": 4 + 8 + 32 + 8 + 4}
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
 DEFAULT_LANES = {2: 1, 3: 1}  # the library's default launch shape (lsr_create)
-KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kernels.hip"]
+KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kern.h",
+                  "paper_2410_22205_amd/csrc/lsr_step.hip"]
 
 
 def kernel_source_hash():

@@ -233,7 +233,9 @@ lsr_status lsr_reinit(lsr_job* job);
  * edge crossings (eq. energyApprox), in 3D the sum of |d|^p h'^2 over the R^3
  * subcells of side h' = h / R per front cell whose trilinear phi at the
  * centre lies within (sqrt 3 / 2) h' of zero (eq. energyApproxFiner; the
- * paper uses R = 5).  Computed in double; *out (host) receives E_p.  p:
+ * paper uses R = 5).  Computed in double over every cell of the grid (the
+ * job keeps one sign bit per node, which shows the front cells 32 at a
+ * time).  *out (host) receives E_p.  p:
  * finite, > 0; R: 1..64 (ignored in 2D); else LSR_E_INVALID.  LSR_E_STATE
  * without phi or d, or for a job in a batch.  Synchronises the stream. */
 lsr_status lsr_energy(lsr_job* job, double p, int32_t R, double* out);

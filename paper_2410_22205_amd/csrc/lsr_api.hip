@@ -96,6 +96,10 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
                       (g.dim == 3 ? (g.n[2] + BS - 1) / BS : 1);
     L.dmark = take(nb);
   }
+  {
+    const size_t rows = g.dim == 3 ? (size_t)g.n[0] * g.n[1] : (size_t)g.n[0];
+    L.sgn = take(4 * rows * sign_row_words(g.dim == 3 ? g.n[2] : g.n[1]));
+  }
   L.cnt = take(4 * 16);
   L.stats = take(8 * STAT_WORDS);
   L.pts_raw = take(8 * (size_t)g.dim * P);
@@ -201,9 +205,8 @@ static lsr_status run_reinit_t(lsr_job* j) {
 // device for the step kernel that follows.
 template <typename T>
 static hipError_t launch_step_energy(lsr_job* j) {
-  return launch_energy_listed<T>(j->grid.dim, j->dg, phi_buf<T>(j, j->cur), j->d64, j->prm.p,
-                                 ENERGY_R, energy_lists(j), j->energy_buf,
-                                 j->energy_buf + ENERGY_BLOCKS, j->list_blocks, j->stream);
+  return energy_now<T>(j, j->prm.p, ENERGY_R, j->energy_buf, j->energy_buf + ENERGY_BLOCKS,
+                       j->stream);
 }
 
 template <typename T>
@@ -398,10 +401,13 @@ lsr_status start_loop(lsr_job* j, int64_t step0) {
   hipStream_t s = j->stream;
   LSR_HIP(launch_fill_u32((uint32_t*)j->cnt, 0u, 3, s));
   LSR_HIP(launch_fill_u32((uint32_t*)j->stats, 0u, 2 * STAT_WORDS, s));
-  if (j->fp64)
+  if (j->fp64) {
     LSR_HIP(launch_grid_list<double>(j->grid.dim, first_band<double>(j), j->list_blocks, s));
-  else
+    LSR_HIP(launch_sign_build<double>(j->dg, phi_buf<double>(j, 0), j->sgn, s));
+  } else {
     LSR_HIP(launch_grid_list<float>(j->grid.dim, first_band<float>(j), j->list_blocks, s));
+    LSR_HIP(launch_sign_build<float>(j->dg, phi_buf<float>(j, 0), j->sgn, s));
+  }
   j->cur = 0;
   j->cur_list = 0;
   j->ring = 0;
@@ -575,6 +581,7 @@ lsr_status lsr_create(const lsr_grid* grid, const lsr_params* params, void* dev_
   j->listM = (uint32_t*)(w + L.listM);
   j->mflags = (uint8_t*)(w + L.mflags);
   j->dmark = (uint8_t*)(w + L.dmark);
+  j->sgn = (uint32_t*)(w + L.sgn);
   j->cnt = (int32_t*)(w + L.cnt);
   j->stats = (unsigned long long*)(w + L.stats);
   j->pts_raw = (double*)(w + L.pts_raw);
@@ -885,13 +892,9 @@ lsr_status lsr_energy(lsr_job* j, double p, int32_t R, double* out) {
   double* part = j->energy_buf;
   double* dout = part + ENERGY_BLOCKS;
   if (j->fp64)
-    LSR_HIP(launch_energy_listed<double>(j->grid.dim, j->dg, phi_buf<double>(j, j->cur), j->d64,
-                                         p, R, energy_lists(j), j->energy_buf,
-                                         j->energy_buf + ENERGY_BLOCKS, j->list_blocks, s));
+    LSR_HIP(energy_now<double>(j, p, R, part, dout, s));
   else
-    LSR_HIP(launch_energy_listed<float>(j->grid.dim, j->dg, phi_buf<float>(j, j->cur), j->d64,
-                                        p, R, energy_lists(j), j->energy_buf,
-                                        j->energy_buf + ENERGY_BLOCKS, j->list_blocks, s));
+    LSR_HIP(energy_now<float>(j, p, R, part, dout, s));
   double v = 0.0;
   LSR_HIP(hipMemcpyAsync(&v, dout, sizeof(double), hipMemcpyDeviceToHost, s));
   LSR_HIP(hipStreamSynchronize(s));

@@ -31,7 +31,6 @@ struct Launch {
   int group;     // cache group (see cache_groups)
   lsr_job* job = nullptr;  // kind 5: the job, and the phi buffer its next step reads
   int phi = 0;
-  EnergyLists lists{};     // kind 5: the buffers of the front-cell list
 };
 
 }  // namespace
@@ -128,7 +127,6 @@ lsr_status build_group(lsr_batch* b, int q0, int q1, int steps, Builder<T>& B) {
         Launch L{5, 0, 1, 0, B.group};
         L.job = j;
         L.phi = j->cur;
-        L.lists = energy_lists(j);
         B.launches.push_back(L);
       }
     }
@@ -220,9 +218,9 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
         break;
       case 5: {
         lsr_job* j = L.job;
-        e = launch_energy_listed<T>(b->dim, j->dg, (const T*)j->phi[L.phi], j->d64, j->prm.p,
-                                    ENERGY_R, L.lists, j->energy_buf,
-                                    j->energy_buf + ENERGY_BLOCKS, b->blocks, s);
+        e = launch_energy_front<T>(b->dim, j->dg, (const T*)j->phi[L.phi], j->d64, j->prm.p,
+                                   ENERGY_R, j->sgn, j->energy_buf, j->energy_buf + ENERGY_BLOCKS,
+                                   s);
         break;
       }
     }
@@ -260,8 +258,7 @@ std::vector<int64_t> group_key(const lsr_batch* b, const Builder<T>& B) {
       k.push_back((int64_t)(intptr_t)j->phi[L.phi]);
       k.push_back((int64_t)(intptr_t)j->d64);
       k.push_back((int64_t)(intptr_t)j->energy_buf);
-      k.push_back((int64_t)(intptr_t)L.lists.S);
-      k.push_back((int64_t)(intptr_t)L.lists.M);
+      k.push_back((int64_t)(intptr_t)j->sgn);
       k.push_back((int64_t)j->dg.N);
       k.push_back((int64_t)j->dg.n0 << 40 | (int64_t)j->dg.n1 << 20 | (int64_t)j->dg.n2);
       k.push_back(pb);
@@ -384,6 +381,7 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
         restore(j, sv);
         a.cnt_out = b->scratch_cnt + 2 * q;
         a.stats = b->scratch_stats;
+        a.sgn = nullptr;  // a trial: the sign words stay those of phi^n
         tab[m++] = a;
       }
       if (m) tabs.push_back({top, m, itp});
@@ -396,9 +394,8 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
   // p = 2 members: the energy their next step will read
   for (lsr_job* j : b->jobs)
     if (j->prm.p != 1.0)
-      LSR_HIP(launch_energy_listed<T>(b->dim, j->dg, (const T*)j->phi[j->cur], j->d64, j->prm.p,
-                                      ENERGY_R, energy_lists(j), j->energy_buf,
-                                      j->energy_buf + ENERGY_BLOCKS, b->blocks, s));
+      LSR_HIP(energy_now<T>(j, j->prm.p, ENERGY_R, j->energy_buf, j->energy_buf + ENERGY_BLOCKS,
+                            s));
   hipEvent_t e0, e1;
   LSR_HIP(hipEventCreate(&e0));
   LSR_HIP(hipEventCreate(&e1));

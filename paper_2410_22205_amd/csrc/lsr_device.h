@@ -92,6 +92,30 @@ __device__ __forceinline__ uint32_t lin(const DevGrid& g, int i, int j, int k) {
   return (uint32_t)i * g.s0 + (uint32_t)j * g.s1 + (uint32_t)k;
 }
 
+// Sign words of phi: one bit per node, 1 where phi < 0, packed 32 to a word
+// along rows of the last axis (3D: rows (i, j) along k; 2D: rows i along j),
+// each row starting a new word; bits past a row's end are 0.
+__host__ __device__ inline uint32_t sign_row_words(int n_last) { return ((uint32_t)n_last + 31u) / 32u; }
+
+__device__ __forceinline__ void sign_word_of(const DevGrid& g, int i, int j, int k, uint32_t& w,
+                                             uint32_t& bit) {
+  if (g.n2 > 1) {
+    w = ((uint32_t)i * (uint32_t)g.n1 + (uint32_t)j) * sign_row_words(g.n2) + (uint32_t)k / 32u;
+    bit = 1u << (k & 31);
+  } else {
+    w = (uint32_t)i * sign_row_words(g.n1) + (uint32_t)j / 32u;
+    bit = 1u << (j & 31);
+  }
+}
+
+// The node's bit set to its new side (idempotent: repeating it changes nothing).
+__device__ __forceinline__ void sign_set(uint32_t* sgn, uint32_t w, uint32_t bit, bool neg) {
+  if (neg)
+    atomicOr(sgn + w, bit);
+  else
+    atomicAnd(sgn + w, ~bit);
+}
+
 // Reciprocal: the hardware approximation in single precision (1 ulp); in
 // double, the approximation refined by one Newton step.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }

@@ -79,6 +79,9 @@ struct SLArgs {
   // E_p(phi^n) on the device (written by the energy kernels before the
   // step) when p != 1, else null
   const double* Ep;
+  // sign words of phi (lsr_device.h), moved to phi^{n+1} where a node
+  // changes side; null: left alone (a trial step)
+  uint32_t* sgn;
 };
 
 // Grid scans in slots of GBAR_CHUNK nodes: in 3D a slot is GBAR_SUB bricks
@@ -155,6 +158,7 @@ struct FinArgs {
   uint32_t* Lout;
   int32_t* ccnt_out;
   int32_t* cnt_out;
+  uint32_t* sgn;  // sign words of phi, moved to the cut phi on Gbar
 };
 
 // Bounding frame of the points of one occupied bin, GEO doubles per bin at
@@ -257,21 +261,16 @@ constexpr int ENERGY_R = 5;
 template <typename T>
 hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* d, double p, int R,
                          double* partial, double* out, hipStream_t s);
-// The same E_p from a list of the front cells: a grid scan (GbarArgs with
-// nbr = 2) compacts them into M in scan order (S, scnt, soff: its slot
-// lists; *cnt: their number), then ENERGY_BLOCKS blocks sum equal stretches
-// of the list.  Same value to rounding, and deterministic.
-struct EnergyLists {
-  uint32_t* S;
-  int32_t* scnt;
-  int32_t* soff;
-  uint32_t* M;
-  int32_t* cnt;
-};
+// The same E_p from the sign words of phi (sgn, see lsr_device.h), which
+// show every front cell of the grid 32 at a time; the front cells are
+// shared out over ENERGY_BLOCKS blocks word by word.  Deterministic.
 template <typename T>
-hipError_t launch_energy_listed(int dim, const DevGrid& g, const T* phi, const double* d, double p,
-                                int R, const EnergyLists& w, double* partial, double* out,
-                                unsigned blocks, hipStream_t s);
+hipError_t launch_energy_front(int dim, const DevGrid& g, const T* phi, const double* d, double p,
+                               int R, const uint32_t* sgn, double* partial, double* out,
+                               hipStream_t s);
+// The sign words of phi, built from scratch (fresh initial data).
+template <typename T>
+hipError_t launch_sign_build(const DevGrid& g, const T* phi, uint32_t* sgn, hipStream_t s);
 template <typename T>
 hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec<T>::pack* dp,
                         hipStream_t s);

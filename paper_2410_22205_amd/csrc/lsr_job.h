@@ -31,6 +31,7 @@ struct Layout {
   size_t scnt, soff;    // members per grid slot and their prefix (list builds)
   size_t smark;         // grid slots marked for the Gbar scan
   size_t dmark;         // distance-kernel bricks marked for the approximate distance
+  size_t sgn;           // sign words of phi
   int64_t list_cap;     // entries of a band-list buffer: chunks and grid slots
   size_t pts_raw, pts, pt_bin, bin_count, bin_start, bin_fill, occ, scan_tmp, geo, sup, sgeo;
   size_t energy;  // energy partial sums and result
@@ -64,10 +65,11 @@ struct lsr_job {
   uint32_t* listM;
   uint8_t* mflags;  // reinitialisation flags; scratch of the initial-data passes
   uint8_t* dmark;
+  uint32_t* sgn;    // sign words of the current phi (lsr_device.h)
   int32_t* cnt;  // [0..2] list-count ring (chunks of a band list, entries of Gbar),
                  // [3] flag, [4] extract count, [5] occupied bins, [6] bins a
                  // cloud's points occupy (density check), [7] occupied
-                 // super-bins, [9] front cells of the energy, [11]
+                 // super-bins, [11]
                  // sample-index flag of lsr_cloud_spacing, [12..15] change
                  // flags of the convergence passes
   unsigned long long* stats;
@@ -136,17 +138,12 @@ inline T* phi_buf(lsr_job* j, int b) {
   return (T*)j->phi[b];
 }
 
-// Buffers of the front-cell list of the energy (Section 3.5) between steps:
-// the free band list (the next step's output) holds the slot lists, the
-// Gbar list the front cells, counter slot 9 their number.
-inline EnergyLists energy_lists(lsr_job* j) {
-  EnergyLists w;
-  w.S = j->list[1 - j->cur_list];
-  w.scnt = j->scnt;
-  w.soff = j->soff;
-  w.M = j->listM;
-  w.cnt = j->cnt + 9;
-  return w;
+// E_p of the current phi (Section 3.5) from the sign words, into the
+// partial sums and out.
+template <typename T>
+hipError_t energy_now(lsr_job* j, double p, int R, double* partial, double* out, hipStream_t s) {
+  return launch_energy_front<T>(j->grid.dim, j->dg, phi_buf<T>(j, j->cur), j->d64, p, R, j->sgn,
+                                partial, out, s);
 }
 
 inline bool reinit_due(const lsr_job* j) {
@@ -162,6 +159,7 @@ SLArgs<T> plan_step(lsr_job* j, const StepConst<T>& c) {
   a.dp = (const typename Vec<T>::pack*)j->dp;
   a.stats = j->stats;
   a.Ep = j->prm.p != 1.0 ? j->energy_buf + ENERGY_BLOCKS : nullptr;
+  a.sgn = j->sgn;
   a.A = phi_buf<T>(j, j->cur);
   a.B = phi_buf<T>(j, 1 - j->cur);
   a.Lin = j->list[j->cur_list];
@@ -238,6 +236,7 @@ ReinitPlan<T> plan_reinit(lsr_job* j) {
   r.fin.Lout = j->list[j->cur_list];
   r.fin.ccnt_out = j->ccnt[j->cur_list];
   r.fin.cnt_out = ring_slot(j, 1);
+  r.fin.sgn = j->sgn;
   j->ring = (j->ring + 1) % 3;
   j->cur = wf;
   j->n_reinits += 1;

@@ -12,135 +12,9 @@
 #include <mutex>
 #include <unordered_map>
 
-#include "lsr_internal.h"
+#include "lsr_kern.h"
 
 namespace lsr {
-
-// ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ __forceinline__ uint32_t wave_count(bool pred) { return (uint32_t)__popcll(__ballot(pred)); }
-
-// Block-wide append (256 threads, called by all of them): the values of the
-// lanes with pred set go to out[] in lane order within the block, behind one
-// atomic on the list counter per block.  lds holds at least 5 ints.
-template <int K>
-__device__ __forceinline__ void block_append(const bool (&pred)[K], const uint32_t (&val)[K],
-                                             gwptr<uint32_t> out, int32_t* counter, int* lds) {
-  uint64_t m[K];
-  int tot = 0;
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    m[q] = __ballot(pred[q]);
-    tot += (int)__popcll(m[q]);
-  }
-  const int w = threadIdx.x >> 6;
-  if (lane_id() == 0) lds[w] = tot;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int q = 0; q < 4; ++q) {
-      const int cq = lds[q];
-      lds[q] = run;
-      run += cq;
-    }
-    lds[4] = run ? atomicAdd(counter, run) : 0;
-  }
-  __syncthreads();
-  int off = lds[4] + lds[w];
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    if (pred[q]) out[off + (int)lanes_below(m[q])] = val[q];
-    off += (int)__popcll(m[q]);
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ void block_append1(bool pred, uint32_t val, gwptr<uint32_t> out,
-                                              int32_t* counter, int* lds) {
-  const bool p[1] = {pred};
-  const uint32_t v[1] = {val};
-  block_append<1>(p, v, out, counter, lds);
-}
-
-// Block-wide sum of up to three wave-uniform counts added to work counters
-// ca, cb, cc (-1: none) of the statistics array, one atomic per nonzero total,
-// in this block's slot.  lds holds at least 12 uints.
-__device__ __forceinline__ void block_add3(uint32_t a, uint32_t b, uint32_t c,
-                                           unsigned long long* stats, int ca, int cb, int cc,
-                                           uint32_t* lds) {
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane_id() == 0) {
-    lds[3 * w] = a;
-    lds[3 * w + 1] = b;
-    lds[3 * w + 2] = c;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t[3] = {0, 0, 0};
-    for (int q = 0; q < 4; ++q)
-      for (int r = 0; r < 3; ++r) t[r] += lds[3 * q + r];
-    const int slot = (int)(blockIdx.x % STAT_SLOTS);
-    const int cs[3] = {ca, cb, cc};
-    for (int r = 0; r < 3; ++r)
-      if (t[r] && cs[r] >= 0) atomicAdd(&stats[stat_index(cs[r], slot)], (unsigned long long)t[r]);
-  }
-}
-
-
-// Items [0, n) shared out in contiguous stretches, one per XCD: the blocks
-// of XCD x (the dispatcher places workgroup b on XCD b mod 8) take the items
-// [x * per, min(x * per + per, n)), per = ceil(n / 8), in increasing order,
-// so that an XCD works through one stretch of a list at a time and its L2
-// holds that stretch's neighbourhood.  Sets the block's first item and the
-// stretch's end and returns the stride between the block's items.  The grid
-// is a multiple of 8 blocks.
-__device__ __forceinline__ uint32_t xcd_share(uint32_t n, uint32_t& first, uint32_t& end) {
-  const uint32_t per = (n + 7u) / 8u, beg = (blockIdx.x % 8u) * per;
-  end = min(beg + per, n);
-  first = beg + blockIdx.x / 8u;
-  return gridDim.x / 8u;
-}
-
-// Block-wide ordered compaction (256 threads, called by all of them): the
-// values of the lanes with pred set go to out[0 ..) ordered by (q, wave,
-// lane), q the index of the value in the thread; returns their number.  No
-// atomics: the order is the order of the block's nodes.  lds holds at least
-// 4 K + 1 ints.
-template <int K>
-__device__ __forceinline__ int block_compact(const bool (&pred)[K], const uint32_t (&val)[K],
-                                             gwptr<uint32_t> out, int* lds) {
-  uint64_t m[K];
-  const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    m[q] = __ballot(pred[q]);
-    if (lane_id() == 0) lds[q * 4 + w] = (int)__popcll(m[q]);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int e = 0; e < 4 * K; ++e) {
-      const int c = lds[e];
-      lds[e] = run;
-      run += c;
-    }
-    lds[4 * K] = run;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < K; ++q)
-    if (pred[q]) out[lds[q * 4 + w] + (int)lanes_below(m[q])] = val[q];
-  const int tot = lds[4 * K];
-  __syncthreads();
-  return tot;
-}
 
 // ------------------------------------------------------------------ fills
 
@@ -203,87 +77,6 @@ __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2,
   }
 }
 
-// A table entry read with scalar loads into scalar registers, as kernel
-// arguments are: the table is read through the constant address space (the
-// host writes it before the launch and nothing writes it during one) at a
-// wave-uniform index, so the per-job arguments neither cost vector memory
-// instructions nor occupy vector registers.
-template <typename A>
-__device__ __forceinline__ A uniform_load(const A* tab, int index) {
-  static_assert(sizeof(A) % 4 == 0, "table entries are whole words");
-  typedef const __attribute__((address_space(4))) uint32_t cword;
-  const int q = __builtin_amdgcn_readfirstlane(index);
-  cword* src = (cword*)(tab + q);
-  A out;
-  uint32_t* dst = (uint32_t*)&out;
-#pragma unroll
-  for (unsigned w = 0; w < sizeof(A) / 4; ++w) dst[w] = src[w];
-  return out;
-}
-
-// One field (at byte offset off) of table entry `index`, read the same way.
-template <typename F, typename A>
-__device__ __forceinline__ F uniform_field(const A* tab, int index, size_t off) {
-  static_assert(sizeof(F) % 4 == 0, "fields are whole words");
-  typedef const __attribute__((address_space(4))) uint32_t cword;
-  const int q = __builtin_amdgcn_readfirstlane(index);
-  cword* src = (cword*)((const char*)(tab + q) + off);
-  F out;
-  uint32_t* dst = (uint32_t*)&out;
-#pragma unroll
-  for (unsigned w = 0; w < sizeof(F) / 4; ++w) dst[w] = src[w];
-  return out;
-}
-#define LSR_FIELD(tab, jb, Type, field) \
-  uniform_field<decltype(Type::field)>(tab, jb, offsetof(Type, field))
-
-// Chunks of one job in a launch: band-list chunks (step), grid slots (list
-// builds), LCHUNK-entry chunks of Gbar (reinitialisation).
-template <typename T>
-__device__ __forceinline__ uint32_t job_chunks(const SLArgs<T>* tab, int jb) {
-  return (uint32_t)*LSR_FIELD(tab, jb, SLArgs<T>, cnt_in);
-}
-template <typename T>
-__device__ __forceinline__ uint32_t job_chunks(const GbarArgs<T>* tab, int jb) {
-  return gbar_slots(LSR_FIELD(tab, jb, GbarArgs<T>, g));
-}
-template <typename T>
-__device__ __forceinline__ uint32_t job_chunks(const RArgs<T>* tab, int jb) {
-  return ((uint32_t)*LSR_FIELD(tab, jb, RArgs<T>, cnt) + LCHUNK - 1) / LCHUNK;
-}
-template <typename T>
-__device__ __forceinline__ uint32_t job_chunks(const FinArgs<T>* tab, int jb) {
-  return ((uint32_t)*LSR_FIELD(tab, jb, FinArgs<T>, cnt_in) + LCHUNK - 1) / LCHUNK;
-}
-
-template <typename A>
-__device__ __forceinline__ uint32_t total_chunks(const A* tab, int n) {
-  uint32_t t = 0;
-  for (int jb = 0; jb < n; ++jb) t += job_chunks(tab, jb);
-  return t;
-}
-
-// Cursor of a block over the jobs of a batched launch, whose chunks are
-// numbered one job after the other: job jb holds the global chunks
-// [beg, end).  advance() moves to the job holding chunk gch (gch never
-// decreases) and returns false once gch lies past the last job; on every job
-// change it calls leave(jb) for the job being left (uniform across the
-// block).
-struct JobCursor {
-  int n, jb = -1;
-  uint32_t beg = 0, end = 0;
-  template <typename A, typename Leave>
-  __device__ __forceinline__ bool advance(const A* tab, uint32_t gch, Leave leave) {
-    while (gch >= end) {
-      if (jb >= 0) leave(jb);
-      if (++jb >= n) return false;
-      beg = end;
-      end = beg + job_chunks(tab, jb);
-    }
-    return true;
-  }
-};
-
 // Grid nodes of one slot of a grid scan (GBAR_CHUNK nodes; see GbarArgs):
 // thread t's node of sub-slot u (in 3D brick sub = slot * GBAR_SUB + u, a
 // wave per 8 x 8 plane of the brick).  False past the grid.
@@ -319,24 +112,6 @@ __device__ __forceinline__ void grid_slot(const GbarArgs<T>& a, uint32_t slot, i
     code[u] = 0;
     if (slot_node<DIM>(a.g, slot, u, i, j, k)) {
       const uint32_t idx = lin(a.g, i, j, k);
-      if (a.nbr == 2) {
-        // the cell with lower corner (i, j, k) is a front cell: its vertices
-        // do not all lie on one side (inside: P < 0)
-        const bool corner = i < a.g.n0 - 1 && j < a.g.n1 - 1 && (DIM == 2 || k < a.g.n2 - 1);
-        int neg = 0;
-        if (corner) {
-#pragma unroll
-          for (int q = 0; q < (DIM == 3 ? 8 : 4); ++q) {
-            const uint32_t o = (uint32_t)(q >> (DIM - 1)) * a.g.s0 +
-                               (uint32_t)((q >> (DIM - 2)) & 1) * a.g.s1 +
-                               (DIM == 3 ? (uint32_t)(q & 1) : 0u);
-            neg += P[idx + o] < T(0) ? 1 : 0;
-          }
-        }
-        in[u] = corner && neg != 0 && neg != (DIM == 3 ? 8 : 4);
-        code[u] = encode(a.g, i, j, k);
-        continue;
-      }
       T m = fabs(P[idx]);
       if (a.nbr) {
         // the six neighbours (a neighbour off the grid reads the node itself)
@@ -576,110 +351,6 @@ __global__ __launch_bounds__(256) void k_band_mask(DevGrid g, T gamma, const T* 
   }
 }
 
-// ---------------------------------------------------------- the SL step
-
-// One time step over the current band list: entries with |phi^n| < gamma get
-// the update of eqs. (SL2d)/(SL3d) written to B; entries that left the band
-// in the previous step get their value copied, so that A and B agree off
-// the new list.  The new list is the set of entries updated here (the band
-// of this step), chunk c of Lin compacted into chunk c of Lout.  LANES lanes
-// share one entry (see sl_update).
-//
-// Each kernel below is a per-chunk body (one block, one chunk) driven either
-// over one job's list or, in the batched kernels, over the chunks of all
-// jobs of the table numbered one after the other; in both the chunks are
-// shared out in contiguous stretches, one per XCD (xcd_share).
-
-// The step's constants, with 1 / E_p(phi^n) from the device when p != 1
-// (E_p = 0, no front, stops the motion: C = 0).
-template <typename T>
-__device__ __forceinline__ StepConst<T> step_consts(const SLArgs<T>& a) {
-  StepConst<T> c = a.c;
-  if (a.Ep) {
-    const double E = *a.Ep;
-    c.inv_E = E > 0.0 ? (T)(1.0 / E) : T(0);
-  }
-  return c;
-}
-
-template <int DIM, int INTERP, typename T, int LANES>
-__device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t c, int* lds,
-                                         uint32_t& nupd, uint32_t& nfb, uint32_t& nfr) {
-  constexpr int CH = (int)LCHUNK / LANES;  // entries per round of the block
-  const gptr<T> A = (gptr<T>)a.A;
-  const gwptr<T> B = (gwptr<T>)a.B;
-  const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
-  const gptr<uint32_t> Lin = (gptr<uint32_t>)a.Lin + c * LCHUNK;
-  const gwptr<uint32_t> Lout = (gwptr<uint32_t>)a.Lout + c * LCHUNK;
-  const int nc = a.ccnt_in[c];
-  const int sub = (int)(threadIdx.x % LANES);
-  int kept = 0;
-  for (int r = 0; r < LANES && r * CH < nc; ++r) {
-    const int le = r * CH + (int)(threadIdx.x / LANES);
-    bool act = false;
-    int fl = 0;
-    uint32_t code = 0;
-    if (le < nc) {
-      code = Lin[le];
-      int i, j, k;
-      decode(a.g, code, i, j, k);
-      const uint32_t idx = lin(a.g, i, j, k);
-      const T v = A[idx];
-      T nv = v;
-      if (fabs(v) < a.c.gamma) {
-        act = true;
-        nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, step_consts(a), i, j, k, idx, v, DP[idx],
-                                              sub, fl);
-      }
-      if (sub == 0) B[idx] = nv;
-    }
-    const bool lead = act && sub == 0;
-    const bool p1[1] = {lead};
-    const uint32_t v1[1] = {code};
-    kept += block_compact<1>(p1, v1, Lout + kept, lds);
-    nupd += wave_count(lead);
-    nfb += wave_count(sub == 0 && (fl & UPD_FALLBACK));
-    nfr += wave_count(sub == 0 && (fl & UPD_FRAME0));
-  }
-  if (threadIdx.x == 0) a.ccnt_out[c] = kept;
-}
-
-template <int DIM, int INTERP, typename T, int LANES>
-__global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
-  __shared__ int lds[5];
-  __shared__ uint32_t lds_st[12];
-  const uint32_t nch = (uint32_t)*a.cnt_in;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_out = (int32_t)nch;
-  uint32_t nupd = 0, nfb = 0, nfr = 0;
-  uint32_t c, end;
-  const uint32_t step = xcd_share(nch, c, end);
-  for (; c < end; c += step) sl_chunk<DIM, INTERP, T, LANES>(a, c, lds, nupd, nfb, nfr);
-  block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
-}
-
-// Batched step for the jobs of one interpolator (one launch per interpolator,
-// so that each kernel keeps its own register count and resident grid).
-template <int DIM, int INTERP, typename T, int LANES>
-__global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab, int n) {
-  __shared__ int lds[5];
-  __shared__ uint32_t lds_st[12];
-  if (blockIdx.x == 0)
-    for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_out = *tab[t].cnt_in;
-  uint32_t nupd = 0, nfb = 0, nfr = 0;
-  JobCursor cur{n};
-  auto leave = [&](int jb) {
-    block_add3(nupd, nfb, nfr, LSR_FIELD(tab, jb, SLArgs<T>, stats), 0, 1, 2, lds_st);
-    nupd = nfb = nfr = 0;
-  };
-  uint32_t c, end;
-  const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
-  for (; c < end; c += step) {
-    if (!cur.advance(tab, c, leave)) break;
-    sl_chunk<DIM, INTERP, T, LANES>(uniform_load(tab, cur.jb), c - cur.beg, lds, nupd, nfb, nfr);
-  }
-  if (cur.jb >= 0 && cur.jb < n) leave(cur.jb);
-}
-
 // ------------------------------------------------------- reinitialisation
 
 // Interface set and one-step fix on Gbar.  Reads phi~ from src, writes the
@@ -824,8 +495,9 @@ __global__ __launch_bounds__(256) void k_reinit_iter_batch(const RArgs<T>* __res
   }
 }
 
-// Cut of eq. (cut) on Gbar, both buffers made equal there, and the new band
-// list: Gbar's chunk c compacted into chunk c of Lout.
+// Cut of eq. (cut) on Gbar, both buffers made equal there, the sign words
+// moved to the cut phi, and the new band list: Gbar's chunk c compacted into
+// chunk c of Lout.
 template <typename T>
 __device__ __forceinline__ void final_chunk(const FinArgs<T>& a, uint32_t c, int n, int* lds) {
   const gptr<uint32_t> M = (gptr<uint32_t>)a.M;
@@ -843,6 +515,12 @@ __device__ __forceinline__ void final_chunk(const FinArgs<T>& a, uint32_t c, int
     cur[idx] = v;
     other[idx] = v;
     in[0] = fabs(v) < a.gamma;
+    // this node's bit is written by this thread alone (other bits of the
+    // word may change meanwhile)
+    uint32_t w, bit;
+    sign_word_of(a.g, i, j, k, w, bit);
+    const bool neg = v < T(0);
+    if (((a.sgn[w] & bit) != 0) != neg) sign_set(a.sgn, w, bit, neg);
   }
   const int kept = block_compact<1>(in, code, (gwptr<uint32_t>)a.Lout + c * LCHUNK, lds);
   if (threadIdx.x == 0) a.ccnt_out[c] = kept;
@@ -1675,72 +1353,96 @@ __device__ double energy_cell_2d(const DevGrid& g, const double f[4], const doub
   return s;
 }
 
-// Each block walks chunks of 256 cells (one lower-corner node per thread,
-// with a grid stride); the front cells of a chunk are compacted into LDS in
-// lane order, their vertex values with them, and the whole block then works
-// through their subcells (3D) or segments (2D).  The block's sum goes to
-// partial[blockIdx.x]; every sum runs in a fixed order, so a launch of the
-// same grid always gives the same result.
-template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_energy(DevGrid g, const T* __restrict__ phi,
-                                                const double* __restrict__ d, double p, int R,
-                                                double* __restrict__ partial) {
+// Sum over the subcells (3D) or segments (2D) of the cells whose vertex
+// values are staged in F, E (and lower corners in IJ), n of them, one thread
+// per (cell, subcell row u) in 3D, per cell in 2D; tt: the R subcell centres
+// (w + 1/2) / R.  Added to s in a fixed order; in 3D the |d|^p of each line
+// of R subcells are summed first and scaled by h'^2 once.
+template <int DIM, int NV, int CAP>
+__device__ __forceinline__ void energy_staged(const DevGrid& g, const double (&F)[CAP][NV],
+                                              const double (&E)[CAP][NV], const int (&IJ)[CAP][2],
+                                              int n, const double* tt, double p, int R, double& s) {
 #pragma clang fp contract(off)
+  const double hs = g.hd / R;
+  const double lim = 0.5 * sqrt(3.0) * hs;
+  const double hs2 = hs * hs;  // each subcell adds |d|^p h'^2
+  if (DIM == 3) {
+    for (int it = (int)threadIdx.x; it < n * R; it += 256) {
+      const int cell = it / R, u = it - cell * R;
+      const double* f = F[cell];
+      const double* e = E[cell];
+      // trilinear: along x, then y, then z; vertex (a, b, c') at 4a + 2b + c'
+      const double tx = tt[u];
+      const double f0 = lerp_d(f[0], f[4], tx), f2 = lerp_d(f[2], f[6], tx);
+      const double f1 = lerp_d(f[1], f[5], tx), f3 = lerp_d(f[3], f[7], tx);
+      const double e0 = lerp_d(e[0], e[4], tx), e2 = lerp_d(e[2], e[6], tx);
+      const double e1 = lerp_d(e[1], e[5], tx), e3 = lerp_d(e[3], e[7], tx);
+      for (int v = 0; v < R; ++v) {
+        const double ty = tt[v];
+        const double fz0 = lerp_d(f0, f2, ty), fz1 = lerp_d(f1, f3, ty);
+        const double ez0 = lerp_d(e0, e2, ty), ez1 = lerp_d(e1, e3, ty);
+        // lerp_d(a, b, t) = a + t (b - a), with b - a taken once per line
+        const double fd = fz1 - fz0, ed = ez1 - ez0;
+        double line = 0.0;
+        for (int w = 0; w < R; ++w) {
+          const double tz = tt[w];
+          if (fabs(fz0 + tz * fd) < lim) line += pow_abs(ez0 + tz * ed, p);
+        }
+        s += line * hs2;
+      }
+    }
+  } else {
+    for (int it = (int)threadIdx.x; it < n; it += 256)
+      s += energy_cell_2d(g, F[it], E[it], IJ[it][0], IJ[it][1], p);
+  }
+}
+
+// Offset of vertex q of the cell with lower corner at node idx: 3D vertex
+// (i+a, j+b, k+c') at q = 4a + 2b + c'; 2D edge order.
+template <int DIM>
+__device__ __forceinline__ uint32_t vertex_offset(const DevGrid& g, int q) {
+  return DIM == 3 ? (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 + (uint32_t)(q & 1)
+                  : (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
+}
+
+// Block b of nb (256 threads, called by all of them) sums the front cells of
+// the whole grid: chunks of CAP cells, one lower-corner node per thread, with
+// a stride of nb chunks; the front cells of a chunk are compacted into the
+// caller's LDS arrays in lane order with their vertex values.  Returns the
+// block's sum (in every thread), in a fixed order.
+template <int DIM, typename T, int CAP>
+__device__ double energy_grid_block(const DevGrid& g, const T* __restrict__ phi,
+                                    const double* __restrict__ d, double p, int R, uint32_t b,
+                                    uint32_t nb, double (&fv)[CAP][DIM == 3 ? 8 : 4],
+                                    double (&ev)[CAP][DIM == 3 ? 8 : 4], int (&cij)[CAP][2],
+                                    double* tt, int* wcnt, double* red) {
   constexpr int NV = DIM == 3 ? 8 : 4;
-  __shared__ double fv[256][NV], ev[256][NV];
-  __shared__ int cij[256][2];
-  __shared__ int wcnt[4];
-  __shared__ double red[4];
   const int tid = (int)threadIdx.x, wv = tid >> 6;
+  if (tid < R) tt[tid] = (tid + 0.5) / R;
   const uint32_t m0 = (uint32_t)g.n0 - 1u, m1 = (uint32_t)g.n1 - 1u;
   const uint32_t m2 = DIM == 3 ? (uint32_t)g.n2 - 1u : 1u;
   const uint64_t ncell = (uint64_t)m0 * m1 * m2;
-  const double hs = g.hd / R;
-  const double lim = 0.5 * sqrt(3.0) * hs;
-  const int R2 = R * R;
-  // offset of vertex q from the cell's lower corner (3D: q = 4a + 2b + c'
-  // for (i+a, j+b, k+c'); 2D: edge order)
-  auto voff = [&](int q) -> uint32_t {
-    if (DIM == 3)
-      return (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 + (uint32_t)(q & 1);
-    return (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
-  };
-  // the cell of this thread in the chunk at `base`, and its vertex values
-  struct Cell {
-    bool ok;
-    int i, j;
-    uint32_t node;
-    T f[NV];
-  };
-  auto fetch = [&](uint64_t base) {
-    Cell x;
+  double s = 0.0;
+  for (uint64_t base = (uint64_t)b * CAP; base < ncell; base += (uint64_t)nb * CAP) {
     const uint64_t c = base + (uint64_t)tid;
-    x.ok = c < ncell;
-    x.i = x.j = 0;
-    x.node = 0;
-    if (x.ok) {
+    bool front = false;
+    int i = 0, j = 0;
+    uint32_t node = 0;
+    T f[NV];
+    if (tid < CAP && c < ncell) {
       const int k = (int)(c % m2);
       const uint64_t r = c / m2;
-      x.j = (int)(r % m1);
-      x.i = (int)(r / m1);
-      x.node = (uint32_t)x.i * g.s0 + (uint32_t)x.j * g.s1 + (uint32_t)k;
+      j = (int)(r % m1);
+      i = (int)(r / m1);
+      node = (uint32_t)i * g.s0 + (uint32_t)j * g.s1 + (uint32_t)k;
+      int n_in = 0;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) x.f[q] = phi[x.node + voff(q)];
+      for (int q = 0; q < NV; ++q) {
+        f[q] = phi[node + vertex_offset<DIM>(g, q)];
+        n_in += (double)f[q] < 0.0 ? 1 : 0;
+      }
+      front = n_in != 0 && n_in != NV;
     }
-    return x;
-  };
-  double s = 0.0;
-  const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  uint64_t base = (uint64_t)blockIdx.x * 256u;
-  Cell cur = fetch(base);
-  for (; base < ncell; base += stride) {
-    // the next chunk's values are in flight while this one is processed
-    const Cell nxt = fetch(base + stride);
-    int n_in = 0;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) n_in += (double)cur.f[q] < 0.0 ? 1 : 0;
-    const bool front = cur.ok && n_in != 0 && n_in != NV;
-    // ordered compaction of the chunk's front cells
     const uint64_t m = __ballot(front);
     if (lane_id() == 0) wcnt[wv] = (int)__popcll(m);
     __syncthreads();
@@ -1751,99 +1453,187 @@ __global__ __launch_bounds__(256) void k_energy(DevGrid g, const T* __restrict__
       const int pos = off + (int)lanes_below(m);
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        fv[pos][q] = (double)cur.f[q];
-        ev[pos][q] = d[cur.node + voff(q)];
+        fv[pos][q] = (double)f[q];
+        ev[pos][q] = d[node + vertex_offset<DIM>(g, q)];
       }
-      cij[pos][0] = cur.i;
-      cij[pos][1] = cur.j;
+      cij[pos][0] = i;
+      cij[pos][1] = j;
     }
     __syncthreads();
-    if (DIM == 3) {
-      // one item per (cell, u, v): the z line of R subcells at (u, v)
-      for (int it = tid; it < nfront * R2; it += 256) {
-        const int cell = it / R2, uv = it - cell * R2;
-        const int u = uv / R, v = uv - u * R;
-        const double tx = (u + 0.5) / R, ty = (v + 0.5) / R;
-        // trilinear: along x, then y, then z; vertex (a, b, c') at 4a + 2b + c'
-        const double* F = fv[cell];
-        const double* E = ev[cell];
-        const double fz0 = lerp_d(lerp_d(F[0], F[4], tx), lerp_d(F[2], F[6], tx), ty);
-        const double fz1 = lerp_d(lerp_d(F[1], F[5], tx), lerp_d(F[3], F[7], tx), ty);
-        const double ez0 = lerp_d(lerp_d(E[0], E[4], tx), lerp_d(E[2], E[6], tx), ty);
-        const double ez1 = lerp_d(lerp_d(E[1], E[5], tx), lerp_d(E[3], E[7], tx), ty);
-        for (int w = 0; w < R; ++w) {
-          const double tz = (w + 0.5) / R;
-          if (fabs(lerp_d(fz0, fz1, tz)) < lim) s += pow_abs(lerp_d(ez0, ez1, tz), p) * hs * hs;
-        }
-      }
-    } else {
-      for (int it = tid; it < nfront; it += 256)
-        s += energy_cell_2d(g, fv[it], ev[it], cij[it][0], cij[it][1], p);
-    }
+    energy_staged<DIM, NV, CAP>(g, fv, ev, cij, nfront, tt, p, R, s);
     __syncthreads();
-    cur = nxt;
   }
   s = wave_sum(s);
   if (lane_id() == 0) red[wv] = s;
   __syncthreads();
-  if (tid == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  const double t = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return t;
 }
 
-// The same sum over a list of front cells (their lower corners, packed
-// codes; *cnt of them) built by a grid scan (GbarArgs, nbr = 2): block b
-// takes the b-th of gridDim.x equal stretches of the list's items (3D: the
-// R^2 lines of R subcells of a cell; 2D: the cells) and adds them thread by
-// thread in a fixed order; the block's sum goes to partial[b].
+// Energy functional over the whole grid: block b's sum to partial[b].
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_energy_cells(DevGrid g, const T* __restrict__ phi,
-                                                      const double* __restrict__ d, double p, int R,
-                                                      const uint32_t* __restrict__ M,
-                                                      const int32_t* cnt,
-                                                      double* __restrict__ partial) {
-#pragma clang fp contract(off)
+__global__ __launch_bounds__(256) void k_energy(DevGrid g, const T* __restrict__ phi,
+                                                const double* __restrict__ d, double p, int R,
+                                                double* __restrict__ partial) {
   constexpr int NV = DIM == 3 ? 8 : 4;
+  __shared__ double fv[256][NV], ev[256][NV];
+  __shared__ int cij[256][2];
+  __shared__ double tt[64];
+  __shared__ int wcnt[4];
   __shared__ double red[4];
-  const uint64_t per = DIM == 3 ? (uint64_t)R * R : 1u;
-  const uint64_t nitem = (uint64_t)*cnt * per;
-  const uint64_t b0 = nitem * blockIdx.x / gridDim.x, b1 = nitem * (blockIdx.x + 1) / gridDim.x;
-  const double hs = g.hd / R;
-  const double lim = 0.5 * sqrt(3.0) * hs;
-  double s = 0.0;
-  for (uint64_t it = b0 + threadIdx.x; it < b1; it += 256) {
-    const uint64_t cell = it / per;
-    const int uv = (int)(it - cell * per);
-    int i, j, k;
-    decode(g, M[cell], i, j, k);
-    const uint32_t node = lin(g, i, j, k);
-    double F[NV], E[NV];
+  const double t = energy_grid_block<DIM, T, 256>(g, phi, d, p, R, blockIdx.x, gridDim.x, fv, ev,
+                                                  cij, tt, wcnt, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// Front cells of one word of a row of lower corners (see the sign words in
+// lsr_device.h): unit = row * W + w, rows (i, j) with i < n0 - 1, j < n1 - 1
+// in 3D (cells at k = 32 w + t), rows i < n0 - 1 in 2D (cells at j = 32 w +
+// t).  Bit t is set where the cell's vertex bits are neither all 1 nor all 0;
+// (i, j) and the first k (2D: j) of the word are returned.
+template <int DIM>
+__device__ __forceinline__ uint32_t front_word(const DevGrid& g, const uint32_t* __restrict__ sgn,
+                                               uint32_t unit, int& i, int& j, int& kb) {
+  const int nl = DIM == 3 ? g.n2 : g.n1;  // nodes along the rows
+  const uint32_t W = sign_row_words(nl);
+  const uint32_t row = unit / W, w = unit - row * W;
+  uint32_t r[4];  // the words of the rows of the cells' vertices
+  if (DIM == 3) {
+    j = (int)(row % (uint32_t)(g.n1 - 1));
+    i = (int)(row / (uint32_t)(g.n1 - 1));
+    r[0] = ((uint32_t)i * (uint32_t)g.n1 + (uint32_t)j) * W + w;
+    r[1] = r[0] + W;                       // (i, j + 1)
+    r[2] = r[0] + (uint32_t)g.n1 * W;      // (i + 1, j)
+    r[3] = r[2] + W;                       // (i + 1, j + 1)
+  } else {
+    i = (int)row;
+    j = 0;
+    r[0] = row * W + w;
+    r[1] = r[0] + W;  // row i + 1
+  }
+  kb = (int)(32u * w);
+  uint32_t all = ~0u, any = 0u;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      // 3D: vertex (i+a, j+b, k+c') at q = 4a + 2b + c'; 2D: edge order
-      const uint32_t o = DIM == 3 ? (uint32_t)(q >> 2) * g.s0 + (uint32_t)((q >> 1) & 1) * g.s1 +
-                                        (uint32_t)(q & 1)
-                                  : (uint32_t)(q == 1 || q == 2) * g.s0 + (uint32_t)(q >= 2) * g.s1;
-      F[q] = (double)phi[node + o];
-      E[q] = d[node + o];
+  for (int q = 0; q < (DIM == 3 ? 4 : 2); ++q) {
+    const uint32_t x = sgn[r[q]];
+    const uint32_t nx = w + 1u < W ? sgn[r[q] + 1] : 0u;
+    const uint32_t x1 = (x >> 1) | (nx << 31);  // bit t: the node one further along
+    all &= x & x1;
+    any |= x | x1;
+  }
+  const int nc = nl - 1 - kb;  // cells left in the row from kb on
+  const uint32_t valid = nc >= 32 ? ~0u : (1u << nc) - 1u;
+  return any & ~all & valid;
+}
+
+// The energy functional over every front cell of the grid, found from the
+// sign words.  Word units are dealt out in groups of 8 consecutive units
+// (thread t of block b takes unit r0 + ((t / 8) gridDim.x + b) 8 + t mod 8
+// in round r0), so that neighbouring threads read neighbouring words and
+// every block gets a share of every part of the front; per round the
+// block's front cells are numbered in (thread, bit) order, listed in LDS
+// and staged with their vertex values STAGE at a time, and summed.  The
+// block's sum goes to partial[b] in a fixed order.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_energy_front(DevGrid g, const T* __restrict__ phi,
+                                                      const double* __restrict__ d, double p, int R,
+                                                      const uint32_t* __restrict__ sgn,
+                                                      double* __restrict__ partial) {
+  constexpr int NV = DIM == 3 ? 8 : 4;
+  constexpr int STAGE = 256;
+  __shared__ double fv[STAGE][NV], ev[STAGE][NV];
+  __shared__ int cij[STAGE][2];
+  __shared__ uint32_t lst[STAGE];
+  __shared__ double tt[64];
+  __shared__ int wsum[4];
+  __shared__ double red[4];
+  const int tid = (int)threadIdx.x, wv = tid >> 6, lane = (int)lane_id();
+  if (tid < R) tt[tid] = (tid + 0.5) / R;
+  const uint32_t W = sign_row_words(DIM == 3 ? g.n2 : g.n1);
+  const uint64_t units =
+      (uint64_t)(DIM == 3 ? (uint32_t)(g.n0 - 1) * (uint32_t)(g.n1 - 1) : (uint32_t)(g.n0 - 1)) * W;
+  const uint64_t G = gridDim.x;
+  double s = 0.0;
+  for (uint64_t r0 = 0; r0 < units; r0 += 256u * G) {
+    const uint64_t u = r0 + ((uint64_t)(tid >> 3) * G + blockIdx.x) * 8u + (uint64_t)(tid & 7);
+    uint32_t f = 0;
+    int i = 0, j = 0, kb = 0;
+    if (u < units) f = front_word<DIM>(g, sgn, (uint32_t)u, i, j, kb);
+    // exclusive prefix of the counts over the block
+    const int c = __popc(f);
+    int x = c;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+      const int y = __shfl_up(x, dd, 64);
+      if (lane >= dd) x += y;
     }
-    if (DIM == 3) {
-      const int u = uv / R, v = uv - u * R;
-      const double tx = (u + 0.5) / R, ty = (v + 0.5) / R;
-      const double fz0 = lerp_d(lerp_d(F[0], F[4], tx), lerp_d(F[2], F[6], tx), ty);
-      const double fz1 = lerp_d(lerp_d(F[1], F[5], tx), lerp_d(F[3], F[7], tx), ty);
-      const double ez0 = lerp_d(lerp_d(E[0], E[4], tx), lerp_d(E[2], E[6], tx), ty);
-      const double ez1 = lerp_d(lerp_d(E[1], E[5], tx), lerp_d(E[3], E[7], tx), ty);
-      for (int w = 0; w < R; ++w) {
-        const double tz = (w + 0.5) / R;
-        if (fabs(lerp_d(fz0, fz1, tz)) < lim) s += pow_abs(lerp_d(ez0, ez1, tz), p) * hs * hs;
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int off = x - c, total = 0;
+    for (int q = 0; q < 4; ++q) {
+      off += q < wv ? wsum[q] : 0;
+      total += wsum[q];
+    }
+    for (int base = 0; base < total; base += STAGE) {
+      // this thread's cells with numbers in [base, base + STAGE) to the list
+      if (c && off < base + STAGE && off + c > base) {
+        uint32_t bits = f;
+        for (int pos = off - base; bits; ++pos) {
+          const int t = __ffs(bits) - 1;
+          bits &= bits - 1u;
+          if (pos >= 0 && pos < STAGE)
+            lst[pos] = DIM == 3 ? encode(g, i, j, kb + t) : encode(g, i, kb + t, 0);
+        }
       }
-    } else {
-      s += energy_cell_2d(g, F, E, i, j, p);
+      __syncthreads();
+      const int nr = min(STAGE, total - base);
+      if (tid < nr) {
+        int ci, cj, ck;
+        decode(g, lst[tid], ci, cj, ck);
+        const uint32_t idx = lin(g, ci, cj, ck);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const uint32_t o = vertex_offset<DIM>(g, q);
+          fv[tid][q] = (double)phi[idx + o];
+          ev[tid][q] = d[idx + o];
+        }
+        cij[tid][0] = ci;
+        cij[tid][1] = cj;
+      }
+      __syncthreads();
+      energy_staged<DIM, NV, STAGE>(g, fv, ev, cij, nr, tt, p, R, s);
+      __syncthreads();
     }
   }
   s = wave_sum(s);
-  if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+  if (lane == 0) red[wv] = s;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (tid == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Sign words from scratch: one wave per 64 nodes of a row (two words), the
+// bits from a ballot.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sign_build(DevGrid g, const T* __restrict__ phi,
+                                                    uint32_t* __restrict__ sgn) {
+  const bool d3 = g.n2 > 1;
+  const int nl = d3 ? g.n2 : g.n1;
+  const uint32_t W = sign_row_words(nl);
+  const uint32_t segs = ((uint32_t)nl + 63u) / 64u;
+  const uint32_t rows = d3 ? (uint32_t)g.n0 * (uint32_t)g.n1 : (uint32_t)g.n0;
+  const uint64_t total = (uint64_t)rows * segs;
+  const uint32_t lane = lane_id();
+  for (uint64_t q = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6); q < total;
+       q += (uint64_t)gridDim.x * 4u) {
+    const uint32_t row = (uint32_t)(q / segs), m = (uint32_t)(q - (uint64_t)row * segs);
+    const uint32_t t = 64u * m + lane;  // position along the row
+    // rows are contiguous in memory
+    const bool neg = t < (uint32_t)nl && phi[row * (uint32_t)nl + t] < T(0);
+    const uint64_t bits = __ballot(neg);
+    const uint32_t w = 2u * m + lane;
+    if (lane < 2 && w < W) sgn[(uint64_t)row * W + w] = (uint32_t)(bits >> (32u * lane));
+  }
 }
 
 // Sum of the n partial sums in a fixed order, and its p-th root: out[0] = E_p.
@@ -1901,49 +1691,6 @@ __global__ void k_dpack(DevGrid g, const double* __restrict__ d, P* __restrict__
 
 // ------------------------------------------------------------ launchers
 
-// Blocks of a persistent launch: `blocks` (a multiple of 8) is an upper
-// bound, and the launch takes no more blocks than fit on the device at once
-// (this kernel's occupancy at 256 threads times the CU count), rounded down
-// to a multiple of 8.  The chunks of a list are striped over the blocks up
-// front, so a block that had to wait for a second round would finish its
-// share late and hold up the whole launch.  Computed once per kernel (one
-// device type per process).
-static unsigned resident_blocks(const void* kern) {
-  static std::mutex m;
-  static std::unordered_map<const void*, unsigned> cache;
-  std::lock_guard<std::mutex> lock(m);
-  auto it = cache.find(kern);
-  if (it != cache.end()) return it->second;
-  int dev = 0, ncu = 0, nb = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess)
-    return 1u << 30;  // unknown: no clamp
-  unsigned r = (unsigned)(ncu * (nb > 0 ? nb : 1)) / 8u * 8u;
-  if (r < 8) r = 8;
-  cache[kern] = r;
-  return r;
-}
-
-template <typename... P, typename... A>
-static hipError_t persistent_launch(void (*kern)(P...), unsigned blocks, hipStream_t s, A... args) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  const unsigned b = std::min(blocks, resident_blocks((const void*)kern));
-  hipLaunchKernelGGL(kern, dim3(b), dim3(256), 0, s, args...);
-  return hipGetLastError();
-}
-
-// The same launch with start and stop events tied to the dispatch itself, so
-// that their elapsed time is the kernel's execution time.
-template <typename... P, typename... A>
-static hipError_t persistent_launch_timed(void (*kern)(P...), unsigned blocks, hipStream_t s,
-                                          hipEvent_t start, hipEvent_t stop, A... args) {
-  if (blocks == 0 || blocks % 8) return hipErrorInvalidConfiguration;
-  const unsigned b = std::min(blocks, resident_blocks((const void*)kern));
-  hipExtLaunchKernelGGL(kern, dim3(b), dim3(256), 0, s, start, stop, 0, args...);
-  return hipGetLastError();
-}
-
 static inline unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
   uint64_t b = (n + block - 1) / block;
   if (b < 1) b = 1;
@@ -1995,20 +1742,6 @@ hipError_t launch_band_mask(const DevGrid& g, T gamma, const T* A, const uint32_
                             const int32_t* ccnt, const int32_t* cnt, uint8_t* mask,
                             int32_t* count, unsigned blocks, hipStream_t s) {
   return persistent_launch(k_band_mask<T>, blocks, s, g, gamma, A, L, ccnt, cnt, mask, count);
-}
-
-template <typename T>
-hipError_t launch_sl_step(int dim, int interp, int lanes, const SLArgs<T>& a, unsigned blocks,
-                          hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-  void (*k)(SLArgs<T>);
-  if (dim == 3)
-    k = lanes == 1 ? (interp == 0 ? k_sl_step<3, 0, T, 1> : k_sl_step<3, 1, T, 1>)
-                   : (interp == 0 ? k_sl_step<3, 0, T, 4> : k_sl_step<3, 1, T, 4>);
-  else
-    k = lanes == 1 ? (interp == 0 ? k_sl_step<2, 0, T, 1> : k_sl_step<2, 1, T, 1>)
-                   : (interp == 0 ? k_sl_step<2, 0, T, 2> : k_sl_step<2, 1, T, 2>);
-  if (start) return persistent_launch_timed(k, blocks, s, start, stop, a);
-  return persistent_launch(k, blocks, s, a);
 }
 
 template <typename T>
@@ -2105,35 +1838,26 @@ hipError_t launch_super_geo(int dim, const double* pts, const int32_t* start,
 }
 
 template <typename T>
-hipError_t launch_energy_listed(int dim, const DevGrid& g, const T* phi, const double* d, double p,
-                                int R, const EnergyLists& w, double* partial, double* out,
-                                unsigned blocks, hipStream_t s) {
-  GbarArgs<T> a;
-  a.g = g;
-  a.gamma = T(0);
-  a.nbr = 2;
-  a.smark = nullptr;
-  a.L = nullptr;
-  a.Lccnt = a.Lcnt = nullptr;
-  a.P = phi;
-  a.S = w.S;
-  a.scnt = w.scnt;
-  a.soff = w.soff;
-  a.M = w.M;
-  a.cnt_out = w.cnt;
-  a.ccnt = nullptr;
-  hipError_t e = launch_grid_list<T>(dim, a, blocks, s);
-  if (e != hipSuccess) return e;
+hipError_t launch_energy_front(int dim, const DevGrid& g, const T* phi, const double* d, double p,
+                               int R, const uint32_t* sgn, double* partial, double* out,
+                               hipStream_t s) {
   dim3 gr(ENERGY_BLOCKS), bl(256);
   if (dim == 3)
-    hipLaunchKernelGGL((k_energy_cells<3, T>), gr, bl, 0, s, g, phi, d, p, R, (const uint32_t*)w.M,
-                       (const int32_t*)w.cnt, partial);
+    hipLaunchKernelGGL((k_energy_front<3, T>), gr, bl, 0, s, g, phi, d, p, R, sgn, partial);
   else
-    hipLaunchKernelGGL((k_energy_cells<2, T>), gr, bl, 0, s, g, phi, d, p, R, (const uint32_t*)w.M,
-                       (const int32_t*)w.cnt, partial);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, partial, (int)ENERGY_BLOCKS, p, out);
+    hipLaunchKernelGGL((k_energy_front<2, T>), gr, bl, 0, s, g, phi, d, p, R, sgn, partial);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), bl, 0, s, (const double*)partial, (int)ENERGY_BLOCKS,
+                     p, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sign_build(const DevGrid& g, const T* phi, uint32_t* sgn, hipStream_t s) {
+  const bool d3 = g.n2 > 1;
+  const int nl = d3 ? g.n2 : g.n1;
+  const uint64_t waves = (uint64_t)(d3 ? (uint64_t)g.n0 * g.n1 : (uint64_t)g.n0) * ((nl + 63) / 64);
+  const unsigned blocks = (unsigned)std::min<uint64_t>((waves + 3) / 4, 16384);
+  hipLaunchKernelGGL((k_sign_build<T>), dim3(blocks), dim3(256), 0, s, g, phi, sgn);
   return hipGetLastError();
 }
 
@@ -2145,7 +1869,8 @@ hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* 
     hipLaunchKernelGGL((k_energy<3, T>), gr, bl, 0, s, g, phi, d, p, R, partial);
   else
     hipLaunchKernelGGL((k_energy<2, T>), gr, bl, 0, s, g, phi, d, p, R, partial);
-  hipLaunchKernelGGL(k_energy_final, dim3(1), bl, 0, s, partial, (int)ENERGY_BLOCKS, p, out);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), bl, 0, s, (const double*)partial, (int)ENERGY_BLOCKS,
+                     p, out);
   return hipGetLastError();
 }
 
@@ -2167,19 +1892,6 @@ hipError_t launch_dpack(int dim, const DevGrid& g, const double* d, typename Vec
   else
     hipLaunchKernelGGL((k_dpack<2, P>), gr, bl, 0, s, g, d, dp);
   return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_sl_step_batch(int dim, int interp, int lanes, const SLArgs<T>* tab, int n,
-                                unsigned blocks, hipStream_t s) {
-  void (*k)(const SLArgs<T>*, int);
-  if (dim == 3)
-    k = lanes == 1 ? (interp == 0 ? k_sl_step_batch<3, 0, T, 1> : k_sl_step_batch<3, 1, T, 1>)
-                   : (interp == 0 ? k_sl_step_batch<3, 0, T, 4> : k_sl_step_batch<3, 1, T, 4>);
-  else
-    k = lanes == 1 ? (interp == 0 ? k_sl_step_batch<2, 0, T, 1> : k_sl_step_batch<2, 1, T, 1>)
-                   : (interp == 0 ? k_sl_step_batch<2, 0, T, 2> : k_sl_step_batch<2, 1, T, 2>);
-  return persistent_launch(k, blocks, s, tab, n);
 }
 
 template <typename T>
@@ -2226,8 +1938,6 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
   template hipError_t launch_band_mask<T>(const DevGrid&, T, const T*, const uint32_t*,           \
                                           const int32_t*, const int32_t*, uint8_t*, int32_t*,     \
                                           unsigned, hipStream_t);                                 \
-  template hipError_t launch_sl_step<T>(int, int, int, const SLArgs<T>&, unsigned, hipStream_t,    \
-                                        hipEvent_t, hipEvent_t);                                  \
   template hipError_t launch_reinit_fix<T>(int, const RArgs<T>&, unsigned, hipStream_t);          \
   template hipError_t launch_reinit_iter<T>(int, const RArgs<T>&, unsigned, hipStream_t);         \
   template hipError_t launch_reinit_final<T>(const FinArgs<T>&, unsigned, hipStream_t);           \
@@ -2235,15 +1945,13 @@ hipError_t launch_reinit_final_batch(const FinArgs<T>* tab, int n, unsigned bloc
                                       hipStream_t);                                               \
   template hipError_t launch_grid_list_batch<T>(int, const GbarArgs<T>*, int, unsigned,           \
                                                 hipStream_t, bool);                               \
-  template hipError_t launch_sl_step_batch<T>(int, int, int, const SLArgs<T>*, int,               \
-                                              unsigned, hipStream_t);                             \
   template hipError_t launch_reinit_fix_batch<T>(int, const RArgs<T>*, int, unsigned, hipStream_t);\
   template hipError_t launch_reinit_iter_batch<T>(int, const RArgs<T>*, int, unsigned,             \
                                                   hipStream_t);                                   \
   template hipError_t launch_reinit_final_batch<T>(const FinArgs<T>*, int, unsigned, hipStream_t);\
-  template hipError_t launch_energy_listed<T>(int, const DevGrid&, const T*, const double*, double, \
-                                              int, const EnergyLists&, double*, double*, unsigned, \
-                                              hipStream_t);                                        \
+  template hipError_t launch_energy_front<T>(int, const DevGrid&, const T*, const double*, double,  \
+                                             int, const uint32_t*, double*, double*, hipStream_t); \
+  template hipError_t launch_sign_build<T>(const DevGrid&, const T*, uint32_t*, hipStream_t);      \
   template hipError_t launch_energy<T>(int, const DevGrid&, const T*, const double*, double, int,  \
                                        double*, double*, hipStream_t);
 

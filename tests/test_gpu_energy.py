@@ -79,6 +79,56 @@ def test_energy_circle_of_64_points():
     assert abs(e - eo) <= TOL * eo
 
 
+def _planted(dim, plant):
+    """A sphere's (circle's) signed distance with a planted second front far
+    from it, where the cut holds phi at +gamma:
+      split - a 2^dim block of nodes at -gamma: front cells none of whose
+              vertices is on the band;
+      mate  - one node at -gamma whose 3^dim neighbourhood is at +gamma/2, on
+              the band: front cells whose lower corner is off the band."""
+    from paper_2410_22205_amd import lsr
+    n = 40 if dim == 3 else 81
+    g = synth.cube_grid(dim, n, -1.5, 1.5)
+    h = g["h"]
+    gamma = 6 * h
+    rng = np.random.default_rng(11)
+    m = 400 if dim == 3 else 64
+    v = rng.normal(size=(m, dim))
+    pts = 0.6 * v / np.linalg.norm(v, axis=1, keepdims=True)
+    X = oracle.node_coords(g)
+    phi = (np.linalg.norm(X, axis=1) - 0.6).reshape(g["n"])
+    clean = phi.copy()
+    c = (5,) * dim
+    if plant == "split":
+        phi[tuple(slice(q, q + 2) for q in c)] = -1.0
+    else:
+        phi[tuple(slice(q - 1, q + 2) for q in c)] = 0.5 * gamma
+        phi[c] = -1.0
+    job = lsr.Job(g, dict(gamma=gamma, beta=3 * h, precision="fp64"), max_points=m)
+    job.load_cloud(pts)
+    job.init_phi(phi0=phi)
+    return g, gamma, clean, job
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("plant", ["split", "mate"])
+def test_energy_front_off_the_band(dim, plant):
+    """Every front cell of the grid counts, also those away from the band:
+    equal to the oracle's sum, which without the planted cells would be
+    another one."""
+    g, gamma, clean, job = _planted(dim, plant)
+    try:
+        cut, _, _, _ = job.extract()
+        d = job.distance()
+        e = job.energy(2.0)
+    finally:
+        job.close()
+    eo = oracle.energy(cut, d, g, 2.0)
+    assert abs(e - eo) <= TOL * eo, (e, eo)
+    e_clean = oracle.energy(np.clip(clean, -gamma, gamma), d, g, 2.0)
+    assert abs(eo - e_clean) > 1e-6 * eo
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_energy_without_front_is_zero(dim):
     """phi0 a sphere that holds the whole grid: no cell is crossed."""
