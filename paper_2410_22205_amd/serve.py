@@ -133,7 +133,7 @@ class Server:
     batch_streams: streams the batch runs its cache groups on (1 or 2)."""
 
     def __init__(self, budget_bytes=None, max_active=64, group_steps=10, precision="fp32",
-                 load_streams=2, max_reinit_iters=32, work_budget=3_000_000, prefetch=3,
+                 load_streams=2, max_reinit_iters=32, work_budget=8_000_000, prefetch=3,
                  graphs=True, batch_streams=2):
         import torch
         self.torch = torch
