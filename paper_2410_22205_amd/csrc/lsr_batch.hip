@@ -191,10 +191,14 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
   char* dev = b->ws + b->table_off;
   hipError_t e = hipSuccess;
   const int ns = std::min(b->n_streams, B.group);
+  // side[] and join_ev[] hold kMaxStreams - 1 entries; every index below is
+  // q - 1 or sq - 1 with q, sq < ns
+  if (ns > lsr_batch::kMaxStreams) return hipErrorInvalidValue;
   if (ns > 1) e = hipEventRecord(b->fork_ev, b->stream);
   for (int q = 1; q < ns && e == hipSuccess; ++q) e = hipStreamWaitEvent(b->side[q - 1], b->fork_ev, 0);
   for (const Launch& L : B.launches) {
     if (e != hipSuccess) break;
+    if (L.group < 0) return hipErrorInvalidValue;
     const int sq = ns > 1 ? L.group % ns : 0;
     hipStream_t s = sq ? b->side[sq - 1] : b->stream;
     switch (L.kind) {
