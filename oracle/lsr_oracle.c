@@ -678,10 +678,9 @@ double orc_energy_sum(const double* phi, const double* d, const orc_grid* g, dou
  *  1. External marking: the nodes on the boundary of the grid with
  *     d >= gamma_S are external; the marking then moves inwards through face
  *     neighbours, repeating sweeps along every Cartesian direction until no
- *     node changes (reading: the printed "move inwards in all directions
- *     until d < gamma_S" iterated to convergence, the serial result the
- *     paper's parallel marking reproduces), never entering a node with
- *     d < gamma_S.
+ *     node changes, never entering a node with d < gamma_S (reading: the
+ *     inward marking of Section 3.6 iterated to convergence, the serial
+ *     result that the paper's parallel marking reproduces).
  *  2. phi0 = d - gamma_S on external nodes, a large value elsewhere.
  *  3. Fast sweeping (Zhao 2005): Gauss-Seidel sweeps in the 2^dim
  *     alternating orders of the first-order Godunov upwind discretisation

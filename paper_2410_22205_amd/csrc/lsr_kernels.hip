@@ -558,6 +558,12 @@ __global__ __launch_bounds__(256) void k_reinit_final_batch(const FinArgs<T>* __
 
 // ------------------------------------------------------------ distance
 
+// Points of a candidate bin read per trip through the scalar unit (all of a
+// trip's loads are in flight before the first is used).
+#ifndef LSR_DIST_PTS
+#define LSR_DIST_PTS 8
+#endif
+
 // Validate and bin the cloud (bin ids grouped by super-bin, see SUP); flag
 // |= 1 for a non-finite point or one outside the grid's box.
 template <int DIM>
@@ -1216,8 +1222,8 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
       need = need || (valid[u] && frame_lb2<DIM>(F.w, x[u], mu) <= bn[u] * slack);
     if (!__any(need)) return;
     const int2 rng = *(const int2*)(F.w + 13);
-    // the same point for the whole block, read through the scalar unit; two
-    // points per trip, both loads in flight before either is used
+    // the same point for the whole block, read through the scalar unit,
+    // LSR_DIST_PTS points per trip
     auto fold = [&](const double* Q) {
 #pragma unroll
       for (int u = 0; u < NPT; ++u) {
@@ -1230,18 +1236,18 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
         bn[u] = fmin(bn[u], s2);
       }
     };
+    constexpr int PT = LSR_DIST_PTS;  // points per trip
     int p = rng.x;
-    for (; p + 1 < rng.y; p += 2) {
-      double Q0[3], Q1[3];
+    for (; p + PT - 1 < rng.y; p += PT) {
+      double Q[PT][3];
 #pragma unroll
-      for (int ax = 0; ax < DIM; ++ax) {
-        Q0[ax] = pts4[(int64_t)p * DIM + ax];
-        Q1[ax] = pts4[(int64_t)(p + 1) * DIM + ax];
-      }
-      fold(Q0);
-      fold(Q1);
+      for (int r = 0; r < PT; ++r)
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) Q[r][ax] = pts4[(int64_t)(p + r) * DIM + ax];
+#pragma unroll
+      for (int r = 0; r < PT; ++r) fold(Q[r]);
     }
-    if (p < rng.y) {
+    for (; p < rng.y; ++p) {
       double Q0[3];
 #pragma unroll
       for (int ax = 0; ax < DIM; ++ax) Q0[ax] = pts4[(int64_t)p * DIM + ax];

@@ -97,6 +97,46 @@ def test_batch_with_p2_members_equals_solo_bitwise(precision):
         j.close()
 
 
+def test_p2_member_replaced_while_graphs_replay():
+    """A p = 2 member leaves after the batch has recorded and replayed its
+    groups, is destroyed, and a new p = 2 job of the same shape (whose
+    workspace may reuse the old one's memory) joins: the energy launches key
+    on the buffers they read, and every job still ends bitwise where it ends
+    alone."""
+    lsr = _lsr()
+    ws = _jobs("fp32", n=2, seed=4300)
+    for w in ws:
+        w["p"] = 2.0
+    solo_c = _solo(ws[0], 40)
+    solo_b = _solo(ws[1], 100)
+    # groups of 10 steps, one reinitialisation each: two alternating launch
+    # sequences, recorded at their second sight and replayed from the fifth
+    # group on
+    import torch
+    # a stream of its own: the null stream cannot be captured into graphs
+    batch = lsr.Batch(max_jobs=2, group_steps=10, stream=torch.cuda.Stream())
+    a, b = _make(lsr, ws[0]), _make(lsr, ws[1])
+    batch.add(a, ws[0]["dt"], ws[0]["interp"])
+    batch.add(b, ws[1]["dt"], ws[1]["interp"])
+    batch.step(60)
+    captured, replayed = batch.graph_counts()
+    assert captured >= 2 and replayed >= 2, (captured, replayed)
+    batch.remove(a)
+    a.close()
+    del a
+    c = _make(lsr, ws[0])
+    batch.add(c, ws[0]["dt"], ws[0]["interp"])
+    batch.step(40)
+    for (phi0, band0, nb0, si0, _), j in ((solo_c, c), (solo_b, b)):
+        phi, band, nb, si = j.extract()
+        np.testing.assert_array_equal(phi, phi0)
+        np.testing.assert_array_equal(band, band0)
+        assert nb == nb0 and si == si0
+    batch.close()
+    b.close()
+    c.close()
+
+
 def test_batch_with_mixed_phases_and_membership():
     lsr = _lsr()
     ws = _jobs("fp32", n=4, seed=4100)
