@@ -201,12 +201,11 @@ static lsr_status run_reinit_t(lsr_job* j) {
 // n steps of the node-list kernel, each followed by the reinitialisation
 // when due, from the current plan state, which they advance.  With launch
 // false nothing is launched (the state of a replayed graph).
-// Algorithm 1, step 2, for p != 1: E_p of the current phi, left on the
-// device for the step kernel that follows.
+// Algorithm 1, step 2, for p != 1: the partial sums of E_p(phi^n)^p,
+// left on the device for the step kernel that follows, which adds them.
 template <typename T>
 static hipError_t launch_step_energy(lsr_job* j) {
-  return energy_now<T>(j, j->prm.p, ENERGY_R, j->energy_buf, j->energy_buf + ENERGY_BLOCKS,
-                       j->stream);
+  return energy_now<T>(j, j->prm.p, ENERGY_R, j->energy_buf, nullptr, j->stream);
 }
 
 template <typename T>

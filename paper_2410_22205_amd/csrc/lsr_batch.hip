@@ -223,8 +223,7 @@ hipError_t issue(lsr_batch* b, const Builder<T>& B) {
       case 5: {
         lsr_job* j = L.job;
         e = launch_energy_front<T>(b->dim, j->dg, (const T*)j->phi[L.phi], j->d64, j->prm.p,
-                                   ENERGY_R, j->sgn, j->energy_buf, j->energy_buf + ENERGY_BLOCKS,
-                                   s);
+                                   ENERGY_R, j->sgn, j->energy_buf, nullptr, s);
         break;
       }
     }
@@ -398,8 +397,7 @@ lsr_status tune(lsr_batch* b, int* best_lanes, int* best_bpc, double* best_ms) {
   // p = 2 members: the energy their next step will read
   for (lsr_job* j : b->jobs)
     if (j->prm.p != 1.0)
-      LSR_HIP(energy_now<T>(j, j->prm.p, ENERGY_R, j->energy_buf, j->energy_buf + ENERGY_BLOCKS,
-                            s));
+      LSR_HIP(energy_now<T>(j, j->prm.p, ENERGY_R, j->energy_buf, nullptr, s));
   hipEvent_t e0, e1;
   LSR_HIP(hipEventCreate(&e0));
   LSR_HIP(hipEventCreate(&e1));

@@ -74,7 +74,7 @@ struct StepConst {
   T grad_thr;              // C dt^alpha of the fallback test
   T weno_e;                // h^4 (eps = h^2 with indicators scaled by h^2)
   T pm1;                   // p - 1: 0 or 1 (p = 1 or 2)
-  T inv_E;                 // 1 / E_p(phi^n) when p = 2, read on the device per step
+  T inv_E;                 // 1 / E_p(phi^n) when p = 2, reduced on the device per step
   T half_inv_h, inv_h;
 };
 

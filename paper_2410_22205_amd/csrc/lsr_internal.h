@@ -76,9 +76,9 @@ struct SLArgs {
   const int32_t* cnt_in;            // chunks of Lin
   int32_t* cnt_out;                 // chunks of Lout (the same number)
   unsigned long long* stats;
-  // E_p(phi^n) on the device (written by the energy kernels before the
-  // step) when p != 1, else null
-  const double* Ep;
+  // when p = 2, the ENERGY_BLOCKS partial sums of E_2(phi^n)^2 that the
+  // energy kernel leaves on the device before the step; p = 1: null
+  const double* Epart;
   // sign words of phi (lsr_device.h), moved to phi^{n+1} where a node
   // changes side; null: left alone (a trial step)
   uint32_t* sgn;
@@ -263,7 +263,8 @@ hipError_t launch_energy(int dim, const DevGrid& g, const T* phi, const double* 
                          double* partial, double* out, hipStream_t s);
 // The same E_p from the sign words of phi (sgn, see lsr_device.h), which
 // show every front cell of the grid 32 at a time; the front cells are
-// shared out over ENERGY_BLOCKS blocks word by word.  Deterministic.
+// shared out over ENERGY_BLOCKS blocks word by word.  Deterministic.  With
+// out null only the partial sums are left (the p = 2 step reduces them).
 template <typename T>
 hipError_t launch_energy_front(int dim, const DevGrid& g, const T* phi, const double* d, double p,
                                int R, const uint32_t* sgn, double* partial, double* out,

@@ -86,7 +86,7 @@ struct lsr_job {
   int2* sup;        // occupied super-bins: their runs in the occupied list
   double* sgeo;     // super-bin frames
   int64_t max_sup;  // room for super-bins
-  double* energy_buf;  // ENERGY_BLOCKS partial sums, then E_p
+  double* energy_buf;  // ENERGY_BLOCKS partial sums, then E_p (lsr_energy)
   double* nn;          // max_points nearest-neighbour distances, then their mean
   int64_t n_cloud;     // points of the loaded cloud (0: none, or a given d)
   lsr::BinGeom bg_load;  // the bins the loaded cloud is sorted by
@@ -158,7 +158,7 @@ SLArgs<T> plan_step(lsr_job* j, const StepConst<T>& c) {
   a.c = c;
   a.dp = (const typename Vec<T>::pack*)j->dp;
   a.stats = j->stats;
-  a.Ep = j->prm.p != 1.0 ? j->energy_buf + ENERGY_BLOCKS : nullptr;
+  a.Epart = j->prm.p != 1.0 ? j->energy_buf : nullptr;
   a.sgn = j->sgn;
   a.A = phi_buf<T>(j, j->cur);
   a.B = phi_buf<T>(j, 1 - j->cur);

@@ -158,6 +158,19 @@ __device__ __forceinline__ A uniform_load(const A* tab, int index) {
   return out;
 }
 
+// A value that every lane of the wave holds alike, moved into scalar
+// registers (lane 0's copy), so that keeping it costs no vector register.
+template <typename V>
+__device__ __forceinline__ V uniform_value(V x) {
+  static_assert(sizeof(V) % 4 == 0, "whole words");
+  uint32_t w[sizeof(V) / 4];
+  __builtin_memcpy(w, &x, sizeof(V));
+#pragma unroll
+  for (unsigned q = 0; q < sizeof(V) / 4; ++q) w[q] = __builtin_amdgcn_readfirstlane(w[q]);
+  __builtin_memcpy(&x, w, sizeof(V));
+  return x;
+}
+
 // One field (at byte offset off) of table entry `index`, read the same way.
 template <typename F, typename A>
 __device__ __forceinline__ F uniform_field(const A* tab, int index, size_t off) {

@@ -1852,8 +1852,9 @@ hipError_t launch_energy_front(int dim, const DevGrid& g, const T* phi, const do
     hipLaunchKernelGGL((k_energy_front<3, T>), gr, bl, 0, s, g, phi, d, p, R, sgn, partial);
   else
     hipLaunchKernelGGL((k_energy_front<2, T>), gr, bl, 0, s, g, phi, d, p, R, sgn, partial);
-  hipLaunchKernelGGL(k_energy_final, dim3(1), bl, 0, s, (const double*)partial, (int)ENERGY_BLOCKS,
-                     p, out);
+  if (out)
+    hipLaunchKernelGGL(k_energy_final, dim3(1), bl, 0, s, (const double*)partial,
+                       (int)ENERGY_BLOCKS, p, out);
   return hipGetLastError();
 }
 

@@ -20,22 +20,33 @@ namespace lsr {
 // jobs of the table numbered one after the other; in both the chunks are
 // shared out in contiguous stretches, one per XCD (xcd_share).
 
-// The step's constants, with 1 / E_p(phi^n) from the device when p != 1
-// (E_p = 0, no front, stops the motion: C = 0).
+// 1 / E_2(phi^n) of a p = 2 step (the only p != 1 a step takes): every
+// block adds the energy kernel's partial sums of E_2^2 in the same fixed
+// order (so that every block, in the single-job and the batched kernels
+// alike, takes the same value) and takes the square root; E_2 = 0 (no
+// front) stops the motion (C = 0).  Called by all threads of the block with
+// the field Epart of the step's arguments (null: p = 1, inv_E unused); red:
+// 4 doubles of LDS.
 template <typename T>
-__device__ __forceinline__ StepConst<T> step_consts(const SLArgs<T>& a) {
-  StepConst<T> c = a.c;
-  if (a.Ep) {
-    const double E = *a.Ep;
-    c.inv_E = E > 0.0 ? (T)(1.0 / E) : T(0);
-  }
-  return c;
+__device__ __forceinline__ T step_inv_energy(const double* Epart, double* red) {
+  if (!Epart) return T(0);
+  double s = 0.0;
+  for (int q = (int)threadIdx.x; q < (int)ENERGY_BLOCKS; q += 256) s += Epart[q];
+  // butterfly: the two lanes of every pair add the same two values
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __syncthreads();  // red may still be read from the previous call
+  if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double E = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
+  return uniform_value(E > 0.0 ? (T)(1.0 / E) : T(0));
 }
 
 template <int DIM, int INTERP, typename T, int LANES>
-__device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t c, int* lds,
+__device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, T inv_E, uint32_t c, int* lds,
                                          uint32_t& nupd, uint32_t& nfb, uint32_t& nfr) {
   constexpr int CH = (int)LCHUNK / LANES;  // entries per round of the block
+  StepConst<T> sc = a.c;
+  sc.inv_E = inv_E;
   const gptr<T> A = (gptr<T>)a.A;
   const gwptr<T> B = (gwptr<T>)a.B;
   const gptr<typename Vec<T>::p4> DP = (gptr<typename Vec<T>::p4>)a.dp;
@@ -58,8 +69,7 @@ __device__ __forceinline__ void sl_chunk(const SLArgs<T>& a, uint32_t c, int* ld
       T nv = v;
       if (fabs(v) < a.c.gamma) {
         act = true;
-        nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, step_consts(a), i, j, k, idx, v, DP[idx],
-                                              sub, fl);
+        nv = sl_update<DIM, INTERP, T, LANES>(A, a.g, sc, i, j, k, idx, v, DP[idx], sub, fl);
         if (sub == 0 && a.sgn && (nv < T(0)) != (v < T(0))) {
           uint32_t w, bit;
           sign_word_of(a.g, i, j, k, w, bit);
@@ -83,12 +93,14 @@ template <int DIM, int INTERP, typename T, int LANES>
 __global__ __launch_bounds__(256) void k_sl_step(SLArgs<T> a) {
   __shared__ int lds[5];
   __shared__ uint32_t lds_st[12];
+  __shared__ double red[4];
+  const T inv_E = step_inv_energy<T>(a.Epart, red);
   const uint32_t nch = (uint32_t)*a.cnt_in;
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.cnt_out = (int32_t)nch;
   uint32_t nupd = 0, nfb = 0, nfr = 0;
   uint32_t c, end;
   const uint32_t step = xcd_share(nch, c, end);
-  for (; c < end; c += step) sl_chunk<DIM, INTERP, T, LANES>(a, c, lds, nupd, nfb, nfr);
+  for (; c < end; c += step) sl_chunk<DIM, INTERP, T, LANES>(a, inv_E, c, lds, nupd, nfb, nfr);
   block_add3(nupd, nfb, nfr, a.stats, 0, 1, 2, lds_st);
 }
 
@@ -98,10 +110,13 @@ template <int DIM, int INTERP, typename T, int LANES>
 __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restrict__ tab, int n) {
   __shared__ int lds[5];
   __shared__ uint32_t lds_st[12];
+  __shared__ double red[4];
   if (blockIdx.x == 0)
     for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) *tab[t].cnt_out = *tab[t].cnt_in;
   uint32_t nupd = 0, nfb = 0, nfr = 0;
   JobCursor cur{n};
+  int cjob = -1;  // the job whose 1 / E_p inv_E holds
+  T inv_E = T(0);
   auto leave = [&](int jb) {
     block_add3(nupd, nfb, nfr, LSR_FIELD(tab, jb, SLArgs<T>, stats), 0, 1, 2, lds_st);
     nupd = nfb = nfr = 0;
@@ -110,7 +125,12 @@ __global__ __launch_bounds__(256) void k_sl_step_batch(const SLArgs<T>* __restri
   const uint32_t step = xcd_share(total_chunks(tab, n), c, end);
   for (; c < end; c += step) {
     if (!cur.advance(tab, c, leave)) break;
-    sl_chunk<DIM, INTERP, T, LANES>(uniform_load(tab, cur.jb), c - cur.beg, lds, nupd, nfb, nfr);
+    if (cur.jb != cjob) {
+      inv_E = step_inv_energy<T>(LSR_FIELD(tab, cur.jb, SLArgs<T>, Epart), red);
+      cjob = cur.jb;
+    }
+    sl_chunk<DIM, INTERP, T, LANES>(uniform_load(tab, cur.jb), inv_E, c - cur.beg, lds, nupd, nfb,
+                                    nfr);
   }
   if (cur.jb >= 0 && cur.jb < n) leave(cur.jb);
 }
