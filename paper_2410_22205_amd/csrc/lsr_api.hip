@@ -89,12 +89,8 @@ Layout make_layout(const lsr_grid& g, int64_t max_points, bool fp64) {
   L.listM = take(4 * N);
   L.mflags = take(N);
   {
-    // bricks of the distance kernel (8^3, 16^2 in 2D), marked for the
-    // approximate distance
-    const int BS = g.dim == 3 ? 8 : 16;
-    const size_t nb = (size_t)((g.n[0] + BS - 1) / BS) * ((g.n[1] + BS - 1) / BS) *
-                      (g.dim == 3 ? (g.n[2] + BS - 1) / BS : 1);
-    L.dmark = take(nb);
+    // bricks of the distance kernel, marked for the approximate distance
+    L.dmark = take(dist_bricks(g.dim, g.n[0], g.n[1], g.dim == 3 ? g.n[2] : 1));
   }
   {
     const size_t rows = g.dim == 3 ? (size_t)g.n[0] * g.n[1] : (size_t)g.n[0];
@@ -712,9 +708,7 @@ static lsr_status load_cloud(lsr_job* j, const double* dev_xyz, int64_t n, bool 
   da.bmark = nullptr;
   j->bg_load = bg;
   j->n_cloud = n;
-  const int BS = dim == 3 ? 8 : 16;
-  unsigned bricks = (unsigned)(((j->dg.n0 + BS - 1) / BS) * ((j->dg.n1 + BS - 1) / BS) *
-                               (dim == 3 ? (j->dg.n2 + BS - 1) / BS : 1));
+  const unsigned bricks = (unsigned)dist_bricks(dim, j->dg.n0, j->dg.n1, j->dg.n2);
   if (approx) {
     // exact values only on the bricks holding a point's 4^dim box, then the
     // fast-sweeping fixed point from the box nodes outwards

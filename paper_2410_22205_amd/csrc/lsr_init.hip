@@ -240,14 +240,15 @@ __global__ void k_phi0_cloud(uint32_t N, const double* __restrict__ d, const dou
 
 // Section 3.4: fixed = 1 at the nodes of the box of 4 nodes per axis around
 // each point (the two nodes on either side of the cell holding it, clamped
-// to the grid); bmark = 1 on the distance kernel's bricks (8^3, 16^2 in 2D)
-// that hold such nodes.
+// to the grid); bmark = 1 on the distance kernel's bricks that hold such
+// nodes.
 template <int DIM>
 __global__ void k_box_mark(DevGrid g, const double* __restrict__ pts, int64_t n,
                            uint8_t* __restrict__ fixed, uint8_t* __restrict__ bmark) {
 #pragma clang fp contract(off)
-  constexpr int BS = DIM == 3 ? 8 : 16;
-  const int nby = (g.n1 + BS - 1) / BS, nbz = DIM == 3 ? (g.n2 + BS - 1) / BS : 1;
+  const int B0 = dist_brick_extent(DIM, 0), B1 = dist_brick_extent(DIM, 1),
+            B2 = dist_brick_extent(DIM, 2);
+  const int nby = dist_bricks_along(DIM, 1, g.n1), nbz = dist_bricks_along(DIM, 2, g.n2);
   const int nn[3] = {g.n0, g.n1, g.n2};
   const double lo[3] = {g.lo0, g.lo1, g.lo2};
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
@@ -261,9 +262,9 @@ __global__ void k_box_mark(DevGrid g, const double* __restrict__ pts, int64_t n,
     for (int i = a0[0]; i <= a1[0]; ++i)
       for (int j = a0[1]; j <= a1[1]; ++j)
         for (int k = a0[2]; k <= a1[2]; ++k) fixed[lin(g, i, j, k)] = 1;
-    for (int bi = a0[0] / BS; bi <= a1[0] / BS; ++bi)
-      for (int bj = a0[1] / BS; bj <= a1[1] / BS; ++bj)
-        for (int bk = a0[2] / BS; bk <= a1[2] / BS; ++bk) bmark[(bi * nby + bj) * nbz + bk] = 1;
+    for (int bi = a0[0] / B0; bi <= a1[0] / B0; ++bi)
+      for (int bj = a0[1] / B1; bj <= a1[1] / B1; ++bj)
+        for (int bk = a0[2] / B2; bk <= a1[2] / B2; ++bk) bmark[(bi * nby + bj) * nbz + bk] = 1;
   }
 }
 

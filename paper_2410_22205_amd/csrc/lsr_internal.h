@@ -178,6 +178,22 @@ struct FinArgs {
 //   |x - p|^2 >= gap(a, [tmin, tmax])^2 + max(tau - rt, 0)^2.
 constexpr int GEO = 16;
 
+// Bricks of the distance kernel, one workgroup each: 8^3 nodes in 3D (four
+// waves, each a 4 x 4 x 8 box of two nodes per lane), 16 x 16 in 2D (one
+// node per thread).  Bricks are numbered in C order.
+__host__ __device__ constexpr int dist_brick_extent(int dim, int ax) {
+  return dim == 3 ? 8 : (ax < 2 ? 16 : 1);
+}
+// Number of bricks per axis and in all.
+__host__ __device__ constexpr int dist_bricks_along(int dim, int ax, int n) {
+  const int b = dist_brick_extent(dim, ax);
+  return ax < dim ? (n + b - 1) / b : 1;
+}
+inline size_t dist_bricks(int dim, int n0, int n1, int n2) {
+  return (size_t)dist_bricks_along(dim, 0, n0) * dist_bricks_along(dim, 1, n1) *
+         dist_bricks_along(dim, 2, n2);
+}
+
 struct DistArgs {
   DevGrid g;
   BinGeom bg;

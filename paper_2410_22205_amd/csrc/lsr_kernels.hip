@@ -984,7 +984,6 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   // no FMA contraction: node coordinates lo + i h and the sums of squares are
   // rounded exactly as the plain definition states them
 #pragma clang fp contract(off)
-  constexpr int BS = DIM == 3 ? 8 : 16;
   constexpr int NPT = DIM == 3 ? 2 : 1;
   // LDS: CAP + SCAP ints and a few words, about 21 KB (7 blocks of 4 waves
   // per CU, as many as the registers allow)
@@ -996,16 +995,18 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   __shared__ int shell_n[NSH], shell_at[NSH];
   const DevGrid& g = a.g;
   if (a.bmark && !a.bmark[blockIdx.x]) return;  // a brick the caller left out
-  const int nbx = (g.n0 + BS - 1) / BS, nby = (g.n1 + BS - 1) / BS;
-  const int nbz = DIM == 3 ? (g.n2 + BS - 1) / BS : 1;
+  const int nbx = dist_bricks_along(DIM, 0, g.n0), nby = dist_bricks_along(DIM, 1, g.n1);
+  const int nbz = dist_bricks_along(DIM, 2, g.n2);
   int b = blockIdx.x;
   const int bz = b % nbz;
   b /= nbz;
   const int by = b % nby, bx = b / nby;
   if (bx >= nbx) return;
-  const int f[3] = {bx * BS, by * BS, DIM == 3 ? bz * BS : 0};
-  const int l[3] = {min(f[0] + BS, g.n0) - 1, min(f[1] + BS, g.n1) - 1,
-                    DIM == 3 ? min(f[2] + BS, g.n2) - 1 : 0};
+  const int f[3] = {bx * dist_brick_extent(DIM, 0), by * dist_brick_extent(DIM, 1),
+                    DIM == 3 ? bz * dist_brick_extent(DIM, 2) : 0};
+  const int l[3] = {min(f[0] + dist_brick_extent(DIM, 0), g.n0) - 1,
+                    min(f[1] + dist_brick_extent(DIM, 1), g.n1) - 1,
+                    DIM == 3 ? min(f[2] + dist_brick_extent(DIM, 2), g.n2) - 1 : 0};
   const double glo[3] = {g.lo0, g.lo1, g.lo2};
   double c[3], e[3], rho2 = 0.0;
 #pragma unroll
