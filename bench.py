@@ -45,7 +45,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
 DEFAULT_LANES = {2: 1, 3: 1}  # the library's default launch shape (lsr_create)
 KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kern.h",
-                  "paper_2410_22205_amd/csrc/lsr_step.hip"]
+                  "paper_2410_22205_amd/csrc/lsr_step.hip", "paper_2410_22205_amd/csrc/lsr_internal.h"]
 
 
 def kernel_source_hash():

@@ -78,17 +78,17 @@ __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2,
 }
 
 // Grid nodes of one slot of a grid scan (GBAR_CHUNK nodes; see GbarArgs):
-// thread t's node of sub-slot u (in 3D brick sub = slot * GBAR_SUB + u, a
-// wave per 8 x 8 plane of the brick).  False past the grid.
+// thread t's node of sub-slot u (in 3D brick sub = slot * GBAR_SUB + u, the
+// brick's nodes in C order over the block's threads).  False past the grid.
 template <int DIM>
 __device__ __forceinline__ bool slot_node(const DevGrid& g, uint32_t slot, uint32_t u, int& i,
                                           int& j, int& k) {
   if (DIM == 3) {
     const uint32_t sub = slot * GBAR_SUB + u;
-    const uint32_t nbj = ((uint32_t)g.n1 + 7u) / 8u, nbk = ((uint32_t)g.n2 + 7u) / 8u;
-    i = (int)((sub / (nbj * nbk)) * 4u + threadIdx.x / 64u);
-    j = (int)(((sub / nbk) % nbj) * 8u + (threadIdx.x / 8u) % 8u);
-    k = (int)((sub % nbk) * 8u + threadIdx.x % 8u);
+    const uint32_t nbj = ((uint32_t)g.n1 + SB1 - 1) / SB1, nbk = ((uint32_t)g.n2 + SB2 - 1) / SB2;
+    i = (int)((sub / (nbj * nbk)) * SB0 + threadIdx.x / (SB1 * SB2));
+    j = (int)(((sub / nbk) % nbj) * SB1 + (threadIdx.x / SB2) % SB1);
+    k = (int)((sub % nbk) * SB2 + threadIdx.x % SB2);
     return i < g.n0 && j < g.n1 && k < g.n2;
   }
   const uint32_t idx = slot * GBAR_CHUNK + u * 256u + threadIdx.x;
@@ -135,8 +135,9 @@ __device__ __forceinline__ void grid_slot(const GbarArgs<T>& a, uint32_t slot, i
 template <int DIM>
 __device__ __forceinline__ uint32_t slot_of(const DevGrid& g, int i, int j, int k) {
   if (DIM == 3) {
-    const uint32_t nbj = ((uint32_t)g.n1 + 7u) / 8u, nbk = ((uint32_t)g.n2 + 7u) / 8u;
-    const uint32_t b = ((uint32_t)(i / 4) * nbj + (uint32_t)(j / 8)) * nbk + (uint32_t)(k / 8);
+    const uint32_t nbj = ((uint32_t)g.n1 + SB1 - 1) / SB1, nbk = ((uint32_t)g.n2 + SB2 - 1) / SB2;
+    const uint32_t b =
+        ((uint32_t)i / SB0 * nbj + (uint32_t)j / SB1) * nbk + (uint32_t)k / SB2;
     return b / GBAR_SUB;
   }
   return ((uint32_t)i * (uint32_t)g.n1 + (uint32_t)j) / GBAR_CHUNK;
