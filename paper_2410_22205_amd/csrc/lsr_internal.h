@@ -84,11 +84,12 @@ struct SLArgs {
   uint32_t* sgn;
 };
 
-// Grid scans in slots of GBAR_CHUNK nodes: in 3D a slot is GBAR_SUB bricks
-// of SB0 x SB1 x SB2 = 256 nodes, bricks numbered in C order of their
-// coordinates and nodes in C order inside a brick; in 2D GBAR_CHUNK
-// consecutive nodes.  Every band list follows this order, so a wave's 64
-// consecutive list entries are neighbours in the grid.
+// Grid scans in slots of GBAR_CHUNK nodes: in 3D a slot is 2 x 2 x 2 =
+// GBAR_SUB bricks of SB0 x SB1 x SB2 = 256 nodes, slots numbered in C order
+// of their coordinates, bricks in C order inside a slot and nodes in C
+// order inside a brick; in 2D GBAR_CHUNK consecutive nodes.  Every band
+// list follows this order, so a wave's 64 consecutive list entries are
+// neighbours in the grid.
 constexpr uint32_t GBAR_SUB = 8, GBAR_CHUNK = 256 * GBAR_SUB;
 #ifndef LSR_SCAN_BRICK
 #define LSR_SCAN_BRICK 2, 4, 32
@@ -97,12 +98,15 @@ constexpr uint32_t SCAN_BRICK[3] = {LSR_SCAN_BRICK};
 constexpr uint32_t SB0 = SCAN_BRICK[0], SB1 = SCAN_BRICK[1], SB2 = SCAN_BRICK[2];
 static_assert(SB0 * SB1 * SB2 == 256, "a scan brick is one workgroup's 256 nodes");
 
+// Slots along an axis of n nodes with bricks b nodes long (3D).
+__host__ __device__ inline uint32_t slots_along(uint32_t n, uint32_t b) {
+  return ((n + b - 1) / b + 1) / 2;
+}
+
 __host__ __device__ inline uint32_t gbar_slots(int dim, int n0, int n1, int n2) {
-  if (dim == 3) {
-    const uint32_t nb = (((uint32_t)n0 + SB0 - 1) / SB0) * (((uint32_t)n1 + SB1 - 1) / SB1) *
-                        (((uint32_t)n2 + SB2 - 1) / SB2);
-    return (nb + GBAR_SUB - 1) / GBAR_SUB;
-  }
+  if (dim == 3)
+    return slots_along((uint32_t)n0, SB0) * slots_along((uint32_t)n1, SB1) *
+           slots_along((uint32_t)n2, SB2);
   return ((uint32_t)n0 * (uint32_t)n1 + GBAR_CHUNK - 1) / GBAR_CHUNK;
 }
 __host__ __device__ inline uint32_t gbar_slots(const DevGrid& g) {

@@ -78,17 +78,19 @@ __global__ void k_init_phi(DevGrid g, int kind, double a0, double a1, double a2,
 }
 
 // Grid nodes of one slot of a grid scan (GBAR_CHUNK nodes; see GbarArgs):
-// thread t's node of sub-slot u (in 3D brick sub = slot * GBAR_SUB + u, the
+// thread t's node of sub-slot u (in 3D brick u of the slot's 2 x 2 x 2, the
 // brick's nodes in C order over the block's threads).  False past the grid.
 template <int DIM>
 __device__ __forceinline__ bool slot_node(const DevGrid& g, uint32_t slot, uint32_t u, int& i,
                                           int& j, int& k) {
   if (DIM == 3) {
-    const uint32_t sub = slot * GBAR_SUB + u;
-    const uint32_t nbj = ((uint32_t)g.n1 + SB1 - 1) / SB1, nbk = ((uint32_t)g.n2 + SB2 - 1) / SB2;
-    i = (int)((sub / (nbj * nbk)) * SB0 + threadIdx.x / (SB1 * SB2));
-    j = (int)(((sub / nbk) % nbj) * SB1 + (threadIdx.x / SB2) % SB1);
-    k = (int)((sub % nbk) * SB2 + threadIdx.x % SB2);
+    const uint32_t nsj = slots_along((uint32_t)g.n1, SB1), nsk = slots_along((uint32_t)g.n2, SB2);
+    const uint32_t bi = 2 * (slot / (nsj * nsk)) + (u >> 2);
+    const uint32_t bj = 2 * ((slot / nsk) % nsj) + ((u >> 1) & 1);
+    const uint32_t bk = 2 * (slot % nsk) + (u & 1);
+    i = (int)(bi * SB0 + threadIdx.x / (SB1 * SB2));
+    j = (int)(bj * SB1 + (threadIdx.x / SB2) % SB1);
+    k = (int)(bk * SB2 + threadIdx.x % SB2);
     return i < g.n0 && j < g.n1 && k < g.n2;
   }
   const uint32_t idx = slot * GBAR_CHUNK + u * 256u + threadIdx.x;
@@ -135,10 +137,8 @@ __device__ __forceinline__ void grid_slot(const GbarArgs<T>& a, uint32_t slot, i
 template <int DIM>
 __device__ __forceinline__ uint32_t slot_of(const DevGrid& g, int i, int j, int k) {
   if (DIM == 3) {
-    const uint32_t nbj = ((uint32_t)g.n1 + SB1 - 1) / SB1, nbk = ((uint32_t)g.n2 + SB2 - 1) / SB2;
-    const uint32_t b =
-        ((uint32_t)i / SB0 * nbj + (uint32_t)j / SB1) * nbk + (uint32_t)k / SB2;
-    return b / GBAR_SUB;
+    const uint32_t nsj = slots_along((uint32_t)g.n1, SB1), nsk = slots_along((uint32_t)g.n2, SB2);
+    return ((uint32_t)i / SB0 / 2 * nsj + (uint32_t)j / SB1 / 2) * nsk + (uint32_t)k / SB2 / 2;
   }
   return ((uint32_t)i * (uint32_t)g.n1 + (uint32_t)j) / GBAR_CHUNK;
 }
