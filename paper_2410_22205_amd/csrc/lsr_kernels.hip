@@ -981,13 +981,16 @@ __device__ __forceinline__ void dist_node(int u, int& li, int& lj, int& lk) {
 // The minimum is taken over all pairs that can attain it, so the result
 // does not depend on the order.  All distance arithmetic in double.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_distance(DistArgs a) {
+// Registers held to 7 waves per SIMD (71 VGPRs, a few scalar values kept in
+// vector lanes), the occupancy the LDS allows: the kernel is latency-bound.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_distance(
+    DistArgs a) {
   // no FMA contraction: node coordinates lo + i h and the sums of squares are
   // rounded exactly as the plain definition states them
 #pragma clang fp contract(off)
   constexpr int NPT = DIM == 3 ? 2 : 1;
   // LDS: CAP + SCAP ints and a few words, about 21 KB (7 blocks of 4 waves
-  // per CU, as many as the registers allow)
+  // per CU)
   constexpr int CAP = 4608, SCAP = 512, NSH = 32;
   __shared__ double red[4];
   __shared__ uint32_t cand[CAP];
@@ -1114,7 +1117,8 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   }
   const double bmin = block_min(best, red);  // synchronises the block
   if (bidx >= 0 && best == bmin) atomicMin(&pstar, bidx);
-  best = bmin;
+  // the values of the whole block from here on sit in scalar registers
+  best = uniform_value(bmin);
   const double R = sqrt(best) + 2.0 * rho;
   const double R2 = R * R * slack;
   if (tid < NSH) shell_n[tid] = 0;
@@ -1125,11 +1129,12 @@ __global__ __launch_bounds__(256) void k_distance(DistArgs a) {
   __syncthreads();
 
   // 2. candidates
-  const bool havep = pstar != INT_MAX;
+  const int ps = uniform_value(pstar);
+  const bool havep = ps != INT_MAX;
   double P[3] = {0.0, 0.0, 0.0};
   if (havep)
 #pragma unroll
-    for (int ax = 0; ax < DIM; ++ax) P[ax] = a.pts[(int64_t)pstar * DIM + ax];
+    for (int ax = 0; ax < DIM; ++ax) P[ax] = uniform_value(a.pts[(int64_t)ps * DIM + ax]);
   // every candidate frame lies at least d(c) - (bin diagonal) from c
   const double s0 = fmax(sqrt(best) - a.bg.bw * sqrt((double)DIM), 0.0);
   const double shell_scale = NSH / fmax(R - s0, 1e-300);
