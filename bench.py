@@ -283,10 +283,11 @@ def run_batched(n_jobs, steps, precision, graphs=True, batch_streams=2, phases=(
 
 def run_served(n_jobs, precision, graphs=True, streams=2):
     """The served workload: a stream of jobs with grids 64^3-320^3, 5k-1M
-    points, 200-400 WENO steps, served with continuous batching and as plain
-    solves one at a time, each way twice: with every request queued at once
-    (the capacity in jobs/s), and arriving as a Poisson stream at 20
-    requests/s (latency = completion - arrival, p50/p99)."""
+    points, 200-400 WENO steps, served with continuous batching (the
+    server's default policy: least work left first) and as plain solves one
+    at a time, each way twice: with every request queued at once (the
+    capacity in jobs/s), and arriving as a Poisson stream at 20 requests/s
+    (latency = completion - arrival, p50/p99)."""
     from paper_2410_22205_amd import serve, synth
     reqs = serve.materialise(synth.served_jobs(n_jobs=n_jobs))
     srv = serve.Server(precision=precision, graphs=graphs, batch_streams=streams)

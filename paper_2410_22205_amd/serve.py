@@ -5,16 +5,19 @@ Life of a request:
   queued    arrived, waiting for memory (first come, first served)
   loading   workspace taken; cloud upload, distance field and phi0 enqueued on
             a side stream while the running jobs keep stepping
-  ready     loaded, waiting for room in the per-step work budget
+  ready     loaded, waiting for room in the per-step work budget (or set
+            aside for jobs with less work left)
   running   member of the shared batch; stepped together with the others
   finishing left the batch at a step boundary; phi and the band copied out
   done      copy-out complete; latency = completion - arrival; memory freed
 
 Two budgets: device bytes decide which requests may hold a workspace (and so
 start loading early), and the band nodes updated per step decide which loaded
-jobs step together.  Small jobs pack into one launch; a job that fills the GPU
-by itself steps alone (a shared launch would only stretch every member's
-latency).
+jobs step together.  By default the jobs with the least work left step first
+(up to 1M band nodes per step while few requests wait, up to 8M when many
+do): a short job does not wait at a long job's pace, and the long job, set
+aside with its state on the device, resumes when the short ones are done or
+when it has waited too long.
 
 Every job's phi, d and band stay in its own device workspace for its whole
 life; nothing goes to the host between steps.  The batch steps all members
@@ -130,11 +133,25 @@ class Server:
     may be loading or loaded ahead of joining;
     precision: "fp32" | "fp64" (one per server: a batch has one precision);
     graphs: replay recorded HIP graphs for repeated groups of batch steps;
-    batch_streams: streams the batch runs its cache groups on (1 or 2)."""
+    batch_streams: streams the batch runs its cache groups on (1 or 2);
+    policy: "arrival" (loaded jobs join in arrival order while the work
+    budget allows) or "shortest" (at every boundary the jobs with the least
+    remaining work run, up to short_budget band nodes per step, or up to
+    work_budget while at least busy_backlog requests wait; a running job
+    with more left is parked, kept on the device, until the shorter ones
+    are done; a job that has waited max_wait_s joins and stays until it is
+    done)."""
 
     def __init__(self, budget_bytes=None, max_active=64, group_steps=10, precision="fp32",
                  load_streams=2, max_reinit_iters=32, work_budget=8_000_000, prefetch=3,
-                 graphs=True, batch_streams=2):
+                 graphs=True, batch_streams=2, policy="shortest", short_budget=1_000_000,
+                 max_wait_s=0.5, busy_backlog=8):
+        if policy not in ("arrival", "shortest"):
+            raise ValueError(f"unknown policy {policy!r}")
+        self.policy = policy
+        self.short_budget = short_budget
+        self.max_wait_s = max_wait_s
+        self.busy_backlog = busy_backlog
         import torch
         self.torch = torch
         self.precision = precision
@@ -210,6 +227,11 @@ class Server:
         done_at = {}
         started_at = {}
         in_flight = collections.deque()  # events of issued batch calls
+        waiting_since = {}  # loaded jobs not in the batch: since when
+        sticky = set()      # jobs that waited too long: they run until done
+        parked = set()      # jobs that ran and were set aside for shorter ones
+        keep_set = set()
+        n_parked = 0
         n_done = 0
         max_running = 0
         t0 = time.perf_counter()
@@ -228,7 +250,7 @@ class Server:
                 adm.offer(i, footprint_bytes(requests[i], self.precision))
                 work[i] = band_estimate(requests[i])
             # admission: start loading on a side stream
-            for i in adm.admit(limit=max(0, self.prefetch - len(loading) - len(ready))):
+            for i in adm.admit(limit=max(0, self.prefetch - len(loading) - len(ready) + len(parked))):
                 live = _Live()
                 live.req = requests[i]
                 lives[i] = live
@@ -241,12 +263,49 @@ class Server:
                 loading.remove(i)
                 lives[i].state = "ready"
                 ready.append(i)
+                waiting_since[i] = now()
+            if self.policy == "shortest" and ready:
+                # the jobs with the least work left run, up to the short
+                # budget; a job that has waited max_wait_s joins them and
+                # stays until it is done
+                t_now = now()
+                for i in ready:
+                    if t_now - waiting_since[i] > self.max_wait_s:
+                        sticky.add(i)
+                keep = [i for i in running + list(ready) if i in sticky]
+                backlog = len(adm.queue) + len(loading) + len(ready)  # arrived, waiting
+                budget = self.work_budget if backlog >= self.busy_backlog else self.short_budget
+                w_sum = 0
+                for i in sorted((i for i in running + list(ready) if i not in sticky),
+                                key=lambda i: (lives[i].left * work[i], i)):
+                    if w_sum and w_sum + work[i] > budget:
+                        break
+                    keep.append(i)
+                    w_sum += work[i]
+                for i in [i for i in running if i not in keep]:
+                    batch.remove(lives[i].job)  # parked: its state stays on the device
+                    running.remove(i)
+                    running_work -= work[i]
+                    lives[i].state = "ready"
+                    ready.append(i)
+                    waiting_since[i] = t_now
+                    parked.add(i)
+                    n_parked += 1
+                ready = collections.deque([i for i in keep if i not in running] +
+                                          [i for i in ready if i not in keep])
+                keep_set = set(keep)
             while ready:
                 i = ready[0]
                 w = work[i]
-                if running and running_work + w > self.work_budget:
+                if self.policy == "shortest":
+                    # the order above decided; stop at the first one left out
+                    if i not in keep_set:
+                        break
+                elif running and running_work + w > self.work_budget:
                     break
                 ready.popleft()
+                waiting_since.pop(i, None)
+                parked.discard(i)
                 live = lives[i]
                 batch.add(live.job, live.req["dt"], live.req["interp"])
                 live.state = "running"
@@ -297,7 +356,7 @@ class Server:
         lat = [1e3 * latency[i] for i in sorted(latency)]
         out = {"jobs": n_done, "rejected": list(adm.rejected), "wall_s": wall,
                "jobs_per_s": n_done / wall if wall > 0 else None,
-               "latency_ms": _percentiles(lat), "max_batch": max_running,
+               "latency_ms": _percentiles(lat), "max_batch": max_running, "parked": n_parked,
                "latency_ms_each": {i: 1e3 * latency[i] for i in latency}}
         if keep_results:
             out["results"] = results

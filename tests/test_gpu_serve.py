@@ -52,6 +52,25 @@ def test_served_results_equal_alone(precision):
     print(f"served {precision}: max |phi - oracle| {worst:.2e} h over {len(reqs)} jobs")
 
 
+def test_shortest_first_parks_and_results_equal_alone():
+    """The shortest-remaining-work policy sets running jobs aside for shorter
+    arrivals and later resumes them (their state stays on the device): every
+    result is still bitwise the job's result alone."""
+    reqs = _requests(5, 4600, steps_range=(20, 25))
+    reqs[0]["steps"] = 1000  # a long job first, shorter ones arriving while it runs
+    for k, r in enumerate(reqs):
+        r["arrival"] = 0.0 if k == 0 else 0.002 + 0.001 * k
+    srv = serve.Server(max_active=8, group_steps=5, precision="fp32", policy="shortest",
+                       short_budget=1, max_wait_s=0.03)
+    out = srv.run(reqs, keep_results=True)
+    assert out["jobs"] == len(reqs) and not out["rejected"]
+    assert out["parked"] >= 1, out["parked"]
+    for i, req in enumerate(reqs):
+        phi, band = _alone(req, "fp32")
+        np.testing.assert_array_equal(out["results"][i][0], phi)
+        np.testing.assert_array_equal(out["results"][i][1], band)
+
+
 def _against_oracle(req, phi, band):
     """The oracle's run of the request: its grid, cloud, phi0, dt, steps and
     interpolator; returns max |phi - oracle| in units of h."""
