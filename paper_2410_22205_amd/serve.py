@@ -112,6 +112,21 @@ class Admission:
         self.used -= self.holding.pop(key)
 
 
+def least_work_first(cands, remaining, work, sticky, budget):
+    """The jobs that run next under the "shortest" policy: every job in
+    sticky, then the others in order of remaining work (ties by key) while
+    their per-step work adds up to at most budget (the first always).
+    Pure host logic."""
+    keep = [i for i in cands if i in sticky]
+    w_sum = 0
+    for i in sorted((i for i in cands if i not in sticky), key=lambda i: (remaining[i], i)):
+        if w_sum and w_sum + work[i] > budget:
+            break
+        keep.append(i)
+        w_sum += work[i]
+    return keep
+
+
 class _Live:
     __slots__ = ("req", "job", "ev", "left", "phi", "band", "pts", "state")
 
@@ -272,16 +287,11 @@ class Server:
                 for i in ready:
                     if t_now - waiting_since[i] > self.max_wait_s:
                         sticky.add(i)
-                keep = [i for i in running + list(ready) if i in sticky]
                 backlog = len(adm.queue) + len(loading) + len(ready)  # arrived, waiting
                 budget = self.work_budget if backlog >= self.busy_backlog else self.short_budget
-                w_sum = 0
-                for i in sorted((i for i in running + list(ready) if i not in sticky),
-                                key=lambda i: (lives[i].left * work[i], i)):
-                    if w_sum and w_sum + work[i] > budget:
-                        break
-                    keep.append(i)
-                    w_sum += work[i]
+                cands = running + list(ready)
+                keep = least_work_first(cands, {i: lives[i].left * work[i] for i in cands}, work,
+                                        sticky, budget)
                 for i in [i for i in running if i not in keep]:
                     batch.remove(lives[i].job)  # parked: its state stays on the device
                     running.remove(i)

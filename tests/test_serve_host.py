@@ -67,3 +67,23 @@ def test_admission_limit_and_band_estimate():
     r = np.linalg.norm(node_coords(g), axis=1)
     exact = int((np.abs(r - 0.5) < 6 * g["h"]).sum())
     assert abs(est - exact) < 0.02 * exact
+
+
+def test_least_work_first_orders_by_remaining_work_within_the_budget():
+    rem = {0: 900, 1: 30, 2: 50, 3: 10}
+    work = {0: 300, 1: 10, 2: 20, 3: 5}
+    # the three shortest fit 40 node updates per step; the long job waits
+    assert serve.least_work_first([0, 1, 2, 3], rem, work, set(), 40) == [3, 1, 2]
+    # a budget smaller than any job still runs the shortest one
+    assert serve.least_work_first([0, 1, 2, 3], rem, work, set(), 1) == [3]
+    # equal remaining work: the lower key first
+    assert serve.least_work_first([5, 4], {4: 7, 5: 7}, {4: 1, 5: 1}, set(), 1) == [4]
+
+
+def test_least_work_first_keeps_jobs_that_waited_too_long():
+    rem = {0: 900, 1: 30, 2: 50}
+    work = {0: 300, 1: 10, 2: 20}
+    # the long job has waited too long: it runs, and the budget still admits
+    # the shortest of the others
+    assert serve.least_work_first([0, 1, 2], rem, work, {0}, 15) == [0, 1]
+    assert serve.least_work_first([], {}, {}, set(), 10) == []
