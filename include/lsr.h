@@ -306,7 +306,9 @@ lsr_status lsr_destroy(lsr_job* job);
  * lsr_set_distance, lsr_set_launch and lsr_destroy.  A p = 2 member gets
  * its own energy launch before each batched step.
  * lsr_batch_remove: the job leaves at the current step boundary; its own
- * stream is ordered after the batch's queued work.
+ * stream is ordered after the batch's queued work.  Its state (phi, lists,
+ * step index, reinitialisation phase) stays in its workspace, so it can be
+ * stepped alone or added to a batch again and continues where it left.
  * lsr_batch_step: n_steps steps of every member (uploads one table per group).
  * lsr_batch_set_launch: launch shape as in lsr_set_launch.
  * lsr_batch_set_streams: members whose state does not fit the device's
