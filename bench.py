@@ -43,6 +43,7 @@ FLOPS_PER_UPDATE = {(3, "weno"): 84 * 30 + 4 * 42 + 60, (3, "q1"): 4 * (7 * 3 + 
 BYTES_PER_UPDATE = {"fp32": 4 + 4 + 16 + 4 + 4, "fp64": 4 + 8 + 32 + 8 + 4}
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
+N_CU, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 DEFAULT_LANES = {2: 1, 3: 1}  # the library's default launch shape (lsr_create)
 KERNEL_SOURCES = ["paper_2410_22205_amd/csrc/lsr_device.h", "paper_2410_22205_amd/csrc/lsr_kern.h",
                   "paper_2410_22205_amd/csrc/lsr_step.hip", "paper_2410_22205_amd/csrc/lsr_internal.h"]
@@ -60,24 +61,32 @@ def traffic_path(workload, precision):
     return os.path.join(ROOT, "profiles", f"sl_step_weno3_{workload}_{precision}_traffic.txt")
 
 
-def read_traffic(workload, precision):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources."""
+def read_profile(workload, precision):
+    """The step kernel's committed rocprofv3 counter summary as key: value
+    pairs, if it was taken on the current kernel sources, else {}."""
     path = traffic_path(workload, precision)
     if not os.path.exists(path):
-        return None
+        return {}
     kv = {}
     with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash():
-        return None
+    return kv if kv.get("kernel_source_hash") == kernel_source_hash() else {}
+
+
+def profile_value(kv, key):
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(workload, precision):
+    """HBM bytes per launch of the step kernel (FETCH_SIZE and WRITE_SIZE with
+    the copy calibration) from the committed summary, or None."""
+    return profile_value(read_profile(workload, precision), "hbm_bytes_per_launch")
 
 
 def run_p2(w, precision, n_jobs, pts):
@@ -467,6 +476,15 @@ def main():
                 "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
                 "node_updates_per_launch": round(upd_per_launch, 1),
                 "lanes": lanes, "blocks_per_cu": args.blocks_per_cu}
+    # the vector L1's tag lookups (one 128-byte line per cycle per CU) that
+    # the step kernel's gathers take, against the launch time measured here
+    tags = profile_value(read_profile(args.workload, args.precision),
+                         "l1_tag_lookups_per_launch")
+    launch_cycles = kernel_ms * 1e-3 / launches * CLOCK_HZ
+    l1 = None if tags is None else {
+        "tag_lookups_per_launch": tags, "per_cu_cycle": round(tags / N_CU / launch_cycles, 4),
+        "peak": 1.0, "unit": "tag lookups per CU per cycle",
+        "source": "TCP_TOTAL_CACHE_ACCESSES_sum of the committed counter summary; launch time live"}
     hbm_gbs = BYTES_PER_UPDATE[args.precision] * total_updates / kernel_s / 1e9
     lat_ms = sorted(1e3 * x for x in r["lat"])
     out = {
@@ -484,6 +502,7 @@ def main():
         "data": "synthetic",
         "config": workload_config(args.workload, w),
         "roofline": roofline,
+        "l1": l1,
         "hbm": {"algorithmic_bytes_per_update": BYTES_PER_UPDATE[args.precision],
                 "achieved_gbs": round(hbm_gbs, 1),
                 "peak_gbs": PEAK_HBM_GBS, "frac": round(hbm_gbs / PEAK_HBM_GBS, 4)},
